@@ -1,0 +1,232 @@
+"""FP64 CPU oracle for monopole borehole acoustic FWI -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product path (the HIP library and
+its Python binding) never does, and shares no code with it.
+
+The arithmetic lives in ``orc.c`` (plain serial C, double precision); this
+module only marshals numpy arrays through ctypes.  Each function names the
+passage of the paper it follows.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "orc.c")
+_SO = os.path.join(_HERE, "liborc.so")
+
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile liborc.so with gcc (plain -O2, no fast-math, serial)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fno-fast-math",
+             "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+class _Geom(C.Structure):
+    _fields_ = [
+        ("nr", C.c_int32), ("nz", C.c_int32), ("pr", C.c_int32), ("pz", C.c_int32),
+        ("dr", C.c_double), ("dz", C.c_double), ("dt", C.c_double),
+        ("nt", C.c_int32),
+        ("f0", C.c_double), ("vmax", C.c_double),
+        ("src_k", C.c_int32), ("nrec", C.c_int32),
+        ("rec_k", C.POINTER(C.c_int32)),
+    ]
+
+
+_D = C.POINTER(C.c_double)
+_U8 = C.POINTER(C.c_uint8)
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = C.CDLL(_SO)
+        G = C.POINTER(_Geom)
+        lib.orc_moduli.argtypes = [C.c_int64, _D, _D, _D, _D, _D]
+        lib.orc_velocities.argtypes = [C.c_int64, _D, _D, _D, _D, _D]
+        lib.orc_forward.argtypes = [G, _D, _D, _D, _D, _D, _D]
+        lib.orc_forward.restype = C.c_int
+        lib.orc_misfit.argtypes = [C.c_int64, _D, _D, _D]
+        lib.orc_misfit.restype = C.c_double
+        lib.orc_gradient.argtypes = [G, _D, _D, _D, _D, _D, C.c_int32, _D, _D, _D]
+        lib.orc_gradient.restype = C.c_int
+        lib.orc_source_adjoint.argtypes = [G, _D, _D, _D, _D, _D]
+        lib.orc_source_adjoint.restype = C.c_int
+        lib.orc_state_len.argtypes = [G]
+        lib.orc_state_len.restype = C.c_int64
+        lib.orc_propagate.argtypes = [G, _D, _D, _D, _D, C.c_int32]
+        lib.orc_propagate.restype = C.c_int
+        lib.orc_propagate_adjoint.argtypes = [G, _D, _D, _D, _D, C.c_int32]
+        lib.orc_propagate_adjoint.restype = C.c_int
+        lib.orc_precondition.argtypes = [C.c_int64, _D, _U8, C.c_double, _D, _D]
+        lib.orc_update.argtypes = [C.c_int64, _D, _D, _D, _D, _D, _U8, C.c_double,
+                                   C.c_double, C.c_double, C.c_double, C.c_double,
+                                   C.c_double]
+        lib.orc_update.restype = C.c_double
+        _lib = lib
+    return _lib
+
+
+@dataclass
+class Geom:
+    """One shot: physical grid nr x nz, PML widths, spacing, time axis, PML
+    constants, on-axis source row and receiver rows (padded-grid C rows)."""
+    nr: int
+    nz: int
+    pr: int
+    pz: int
+    dr: float
+    dz: float
+    dt: float
+    nt: int
+    f0: float
+    vmax: float
+    src_k: int
+    rec_k: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
+
+    @property
+    def NR(self) -> int:
+        return self.nr + self.pr
+
+    @property
+    def NZ(self) -> int:
+        return self.nz + 2 * self.pz
+
+    def _c(self):
+        rk = np.ascontiguousarray(self.rec_k, dtype=np.int32)
+        g = _Geom(self.nr, self.nz, self.pr, self.pz, self.dr, self.dz, self.dt,
+                  self.nt, self.f0, self.vmax, self.src_k, len(rk),
+                  rk.ctypes.data_as(C.POINTER(C.c_int32)))
+        return g, rk  # keep rk alive
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None and a.shape != tuple(shape):
+        a = a.reshape(shape)
+    return a
+
+
+def _p(a):
+    return a.ctypes.data_as(_D)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError("oracle %s rejected its input" % what)
+
+
+def moduli(vp, vs, rho):
+    """Eq. 3-4."""
+    vp, vs, rho = _f64(vp), _f64(vs), _f64(rho)
+    lam, mu = np.empty_like(vp), np.empty_like(vp)
+    _load().orc_moduli(vp.size, _p(vp), _p(vs), _p(rho), _p(lam), _p(mu))
+    return lam, mu
+
+
+def velocities(lam, mu, rho):
+    """Eq. 11-12."""
+    lam, mu, rho = _f64(lam), _f64(mu), _f64(rho)
+    vp, vs = np.empty_like(lam), np.empty_like(lam)
+    _load().orc_velocities(lam.size, _p(lam), _p(mu), _p(rho), _p(vp), _p(vs))
+    return vp, vs
+
+
+def forward(g: Geom, lam, mu, rho, wavelet, return_state=False):
+    """Eq. 2 forward modelling; returns traces [nrec, nt] (and the final state,
+    14 x NR x NZ, when asked)."""
+    shp = (g.NR, g.NZ)
+    lam, mu, rho = _f64(lam, shp), _f64(mu, shp), _f64(rho, shp)
+    w = _f64(wavelet)
+    assert w.size >= g.nt
+    gc, rk = g._c()
+    tr = np.zeros((len(rk), g.nt))
+    st = np.zeros((14,) + shp) if return_state else None
+    rc = _load().orc_forward(C.byref(gc), _p(lam), _p(mu), _p(rho), _p(w), _p(tr),
+                             _p(st) if st is not None else None)
+    _check(rc, "forward")
+    return (tr, st) if return_state else tr
+
+
+def misfit(d, dobs):
+    """Eq. 1 and 5: returns (J, resid)."""
+    d, dobs = _f64(d), _f64(dobs)
+    r = np.empty_like(d)
+    J = _load().orc_misfit(d.size, _p(d), _p(dobs), _p(r))
+    return J, r
+
+
+def gradient(g: Geom, lam, mu, rho, wavelet, resid, seg=200):
+    """Eq. 6-8 via the exact discrete transpose; returns (glam, gmu, illum)."""
+    shp = (g.NR, g.NZ)
+    lam, mu, rho = _f64(lam, shp), _f64(mu, shp), _f64(rho, shp)
+    w, r = _f64(wavelet), _f64(resid)
+    gc, rk = g._c()
+    assert r.size == len(rk) * g.nt
+    gl, gm, il = np.zeros(shp), np.zeros(shp), np.zeros(shp)
+    rc = _load().orc_gradient(C.byref(gc), _p(lam), _p(mu), _p(rho), _p(w), _p(r),
+                              int(seg), _p(gl), _p(gm), _p(il))
+    _check(rc, "gradient")
+    return gl, gm, il
+
+
+def source_adjoint(g: Geom, lam, mu, rho, resid):
+    """Transpose of wavelet -> traces (dot-product test)."""
+    shp = (g.NR, g.NZ)
+    lam, mu, rho = _f64(lam, shp), _f64(mu, shp), _f64(rho, shp)
+    r = _f64(resid)
+    gc, rk = g._c()
+    out = np.zeros(g.nt)
+    rc = _load().orc_source_adjoint(C.byref(gc), _p(lam), _p(mu), _p(rho), _p(r), _p(out))
+    _check(rc, "source_adjoint")
+    return out
+
+
+def propagate(g: Geom, lam, mu, rho, state, nsteps, adjoint=False):
+    """nsteps source-free steps (or their exact transpose) on a full state."""
+    shp = (g.NR, g.NZ)
+    lam, mu, rho = _f64(lam, shp), _f64(mu, shp), _f64(rho, shp)
+    st = np.array(state, dtype=np.float64, order="C", copy=True)
+    gc, rk = g._c()
+    lib = _load()
+    assert st.size == lib.orc_state_len(C.byref(gc))
+    fn = lib.orc_propagate_adjoint if adjoint else lib.orc_propagate
+    _check(fn(C.byref(gc), _p(lam), _p(mu), _p(rho), _p(st), int(nsteps)), "propagate")
+    return st
+
+
+def precondition(illum, mask, eps, g_lam, g_mu):
+    """Diagonal preconditioner P = 1/(E + eps max E) applied to both gradients."""
+    il = _f64(illum)
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    gl, gm = np.array(g_lam, np.float64, order="C"), np.array(g_mu, np.float64, order="C")
+    _load().orc_precondition(il.size, _p(il), m.ctypes.data_as(_U8), float(eps),
+                             _p(gl), _p(gm))
+    return gl, gm
+
+
+def update(lam, mu, rho, g_lam, g_mu, mask, eta, alpha_override=0.0,
+           vp_bounds=(0.0, 1e30), vs_bounds=(0.0, 1e30)):
+    """Eq. 9-10 with the max-change rule for alpha; returns (lam, mu, alpha)."""
+    l, m = np.array(lam, np.float64, order="C"), np.array(mu, np.float64, order="C")
+    r, gl, gm = _f64(rho), _f64(g_lam), _f64(g_mu)
+    mk = np.ascontiguousarray(mask, dtype=np.uint8)
+    a = _load().orc_update(l.size, _p(l), _p(m), _p(r), _p(gl), _p(gm),
+                           mk.ctypes.data_as(_U8), float(eta), float(alpha_override),
+                           float(vp_bounds[0]), float(vp_bounds[1]),
+                           float(vs_bounds[0]), float(vs_bounds[1]))
+    return l, m, a

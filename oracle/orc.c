@@ -1,0 +1,682 @@
+/*
+ * orc.c -- FP64 CPU oracle for monopole borehole acoustic FWI.
+ *
+ * TEST INFRASTRUCTURE ONLY (see orc.h).  Serial plain C, double precision.
+ *
+ * What is computed, and from which passage of the paper:
+ *   - Eq. 2 (Method): velocity-stress monopole equations in (r, z) with the
+ *     1/r terms, discretised on a staggered grid with second-order differences
+ *     in space and leapfrog in time.  The radial divergence is taken in the
+ *     conservative form (1/r) d(r v_r)/dr, which is what the averaged 1/r terms
+ *     below give.  PML on the outer radius and both axial ends (complex
+ *     frequency-shifted, auxiliary-variable form); symmetry on the axis
+ *     (v_r = tau_rz = 0 at r = 0).
+ *   - Source f added to the three normal stresses of the on-axis source cell.
+ *   - Recorded pressure: the mean normal stress at on-axis receiver cells.
+ *   - Eq. 1, 5: misfit and residual.
+ *   - Eq. 6: adjoint equations, here the exact transpose of the discrete
+ *     forward map (scatter form: every forward read becomes an adjoint write).
+ *   - Eq. 7-8: zero-lag correlation of forward strain rates with adjoint stresses.
+ *   - Eq. 3-4, 9-12: moduli, update, velocities.
+ * Where the paper is silent (order, averaging, PML constants, source and
+ * receiver conventions) the readings stated in the design notes are used.
+ */
+#include "orc.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_PI 3.14159265358979323846
+#define ORC_RC 1.0e-4 /* PML theoretical reflection coefficient */
+
+/* ---------------------------------------------------------------------------
+ * Grid, coefficients and state
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int NR, NZ, nr, nz, pr, pz;
+    double dr, dz, dt;
+    /* PML profiles.  r at integer positions (R, S nodes) and half positions
+     * (C, Z nodes); z at integer positions (C, R nodes) and half positions
+     * (Z, S nodes).  on = 1 where the node lies inside the layer (x > 0). */
+    double *ar_i, *br_i, *ar_h, *br_h;
+    double *az_i, *bz_i, *az_h, *bz_h;
+    char *onr_i, *onr_h, *onz_i, *onz_h;
+    const double *lam, *mu, *rho;
+} grid;
+
+/* State: 14 arrays of NR*NZ. psi[] are the PML memory variables:
+ *   A: R node, d/dr tau_rr      B: R node, d/dz tau_rz
+ *   C: Z node, d/dr tau_rz      D: Z node, d/dz tau_zz
+ *   E: C node, d/dr v_r         F: C node, d/dz v_z
+ *   G: S node, d/dz v_r         H: S node, d/dr v_z                        */
+typedef struct {
+    double *vr, *vz, *trr, *ttt, *tzz, *trz;
+    double *psi[8];
+} state;
+
+static void state_bind(state *s, double *mem, size_t n)
+{
+    s->vr = mem;
+    s->vz = mem + n;
+    s->trr = mem + 2 * n;
+    s->ttt = mem + 3 * n;
+    s->tzz = mem + 4 * n;
+    s->trz = mem + 5 * n;
+    for (int q = 0; q < 8; ++q) s->psi[q] = mem + (6 + q) * n;
+}
+
+/* CFS-PML coefficients for penetration x in (0,1]:
+ *   d(x) = d0 x^2, alpha(x) = pi f0 (1 - x), kappa = 1,
+ *   b = exp(-(d + alpha) dt), a = d (b - 1) / (d + alpha);
+ * memory update psi <- b psi + a D, the difference D is then replaced by D + psi. */
+static void pml_ab(double x, double d0, double f0, double dt, double *a, double *b, char *on)
+{
+    if (!(x > 0.0)) {
+        *a = 0.0;
+        *b = 1.0;
+        *on = 0;
+        return;
+    }
+    double d = d0 * x * x;
+    double al = ORC_PI * f0 * (1.0 - x);
+    *b = exp(-(d + al) * dt);
+    *a = d * (*b - 1.0) / (d + al);
+    *on = 1;
+}
+
+static int grid_init(grid *G, const orc_geom *g, const double *lam, const double *mu,
+                     const double *rho)
+{
+    if (g->nr <= 1 || g->nz <= 1 || g->pr < 0 || g->pz < 0 || g->nt < 0) return -1;
+    if (!(g->dr > 0) || !(g->dz > 0) || !(g->dt > 0)) return -1;
+    G->nr = g->nr;
+    G->nz = g->nz;
+    G->pr = g->pr;
+    G->pz = g->pz;
+    G->NR = g->nr + g->pr;
+    G->NZ = g->nz + 2 * g->pz;
+    G->dr = g->dr;
+    G->dz = g->dz;
+    G->dt = g->dt;
+    G->lam = lam;
+    G->mu = mu;
+    G->rho = rho;
+    int NR = G->NR, NZ = G->NZ;
+    G->ar_i = calloc(NR, sizeof(double));
+    G->br_i = calloc(NR, sizeof(double));
+    G->ar_h = calloc(NR, sizeof(double));
+    G->br_h = calloc(NR, sizeof(double));
+    G->az_i = calloc(NZ, sizeof(double));
+    G->bz_i = calloc(NZ, sizeof(double));
+    G->az_h = calloc(NZ, sizeof(double));
+    G->bz_h = calloc(NZ, sizeof(double));
+    G->onr_i = calloc(NR, 1);
+    G->onr_h = calloc(NR, 1);
+    G->onz_i = calloc(NZ, 1);
+    G->onz_h = calloc(NZ, 1);
+    double lnR = log(ORC_RC);
+    double d0r = g->pr > 0 ? -3.0 * g->vmax * lnR / (2.0 * g->pr * g->dr) : 0.0;
+    double d0z = g->pz > 0 ? -3.0 * g->vmax * lnR / (2.0 * g->pz * g->dz) : 0.0;
+    for (int i = 0; i < NR; ++i) {
+        double xi = 0.0, xh = 0.0;
+        if (g->pr > 0) {
+            xi = ((double)i - g->nr) / g->pr;
+            xh = ((double)i + 0.5 - g->nr) / g->pr;
+        }
+        pml_ab(xi, d0r, g->f0, g->dt, &G->ar_i[i], &G->br_i[i], &G->onr_i[i]);
+        pml_ab(xh, d0r, g->f0, g->dt, &G->ar_h[i], &G->br_h[i], &G->onr_h[i]);
+    }
+    for (int k = 0; k < NZ; ++k) {
+        double xi = 0.0, xh = 0.0;
+        if (g->pz > 0) {
+            /* physical C rows are k in [pz, pz+nz); their cell faces span
+             * [pz - 1/2, pz + nz - 1/2] in index units */
+            double lo = g->pz - 0.5, hi = g->pz + g->nz - 0.5;
+            double ui = k, uh = k + 0.5;
+            if (ui < lo) xi = (lo - ui) / g->pz;
+            if (ui > hi) xi = (ui - hi) / g->pz;
+            if (uh < lo) xh = (lo - uh) / g->pz;
+            if (uh > hi) xh = (uh - hi) / g->pz;
+        }
+        pml_ab(xi, d0z, g->f0, g->dt, &G->az_i[k], &G->bz_i[k], &G->onz_i[k]);
+        pml_ab(xh, d0z, g->f0, g->dt, &G->az_h[k], &G->bz_h[k], &G->onz_h[k]);
+    }
+    return 0;
+}
+
+static void grid_free(grid *G)
+{
+    free(G->ar_i); free(G->br_i); free(G->ar_h); free(G->br_h);
+    free(G->az_i); free(G->bz_i); free(G->az_h); free(G->bz_h);
+    free(G->onr_i); free(G->onr_h); free(G->onz_i); free(G->onz_h);
+}
+
+#define IX(i, k) ((size_t)(i) * (size_t)NZ + (size_t)(k))
+
+/* Medium averaging (reading: arithmetic density at velocity nodes, harmonic
+ * rigidity at tau_rz nodes, zero if any neighbour is fluid). */
+static double buoy_R(const grid *G, int i, int k)
+{
+    int NZ = G->NZ;
+    return 2.0 / (G->rho[IX(i - 1, k)] + G->rho[IX(i, k)]);
+}
+static double buoy_Z(const grid *G, int i, int k)
+{
+    int NZ = G->NZ;
+    int k1 = k + 1 < NZ ? k + 1 : NZ - 1;
+    return 2.0 / (G->rho[IX(i, k)] + G->rho[IX(i, k1)]);
+}
+static double mu_S(const grid *G, int i, int k)
+{
+    int NZ = G->NZ;
+    int k1 = k + 1 < NZ ? k + 1 : NZ - 1;
+    double m1 = G->mu[IX(i - 1, k)], m2 = G->mu[IX(i, k)];
+    double m3 = G->mu[IX(i - 1, k1)], m4 = G->mu[IX(i, k1)];
+    if (!(m1 > 0 && m2 > 0 && m3 > 0 && m4 > 0)) return 0.0;
+    return 4.0 / (1.0 / m1 + 1.0 / m2 + 1.0 / m3 + 1.0 / m4);
+}
+
+/* ---------------------------------------------------------------------------
+ * One forward step (Eq. 2).  srcval is added to the three normal stresses of
+ * C(0, src_k).  If eps != NULL the strain rates used for the stress update are
+ * stored: eps[0..3] planes = e_rr', e_tt, e_zz' (C nodes), e_rz' (S nodes),
+ * where ' marks the PML-modified difference.
+ * ------------------------------------------------------------------------- */
+static void fwd_step(const grid *G, state *s, int src_k, double srcval, double *eps)
+{
+    const int NR = G->NR, NZ = G->NZ;
+    const double dr = G->dr, dz = G->dz, dt = G->dt;
+    double *vr = s->vr, *vz = s->vz, *trr = s->trr, *ttt = s->ttt, *tzz = s->tzz, *trz = s->trz;
+    double *pA = s->psi[0], *pB = s->psi[1], *pC = s->psi[2], *pD = s->psi[3];
+    double *pE = s->psi[4], *pF = s->psi[5], *pG = s->psi[6], *pH = s->psi[7];
+    size_t N = (size_t)NR * NZ;
+
+    /* velocity: R nodes, i >= 1 */
+    for (int i = 1; i < NR; ++i) {
+        double ri = i * dr;
+        for (int k = 0; k < NZ; ++k) {
+            size_t c = IX(i, k), cm = IX(i - 1, k);
+            double Dr = (trr[c] - trr[cm]) / dr;
+            if (G->onr_i[i]) {
+                pA[c] = G->br_i[i] * pA[c] + G->ar_i[i] * Dr;
+                Dr += pA[c];
+            }
+            double trz_km = k > 0 ? trz[IX(i, k - 1)] : 0.0;
+            double Dz = (trz[c] - trz_km) / dz;
+            if (G->onz_i[k]) {
+                pB[c] = G->bz_i[k] * pB[c] + G->az_i[k] * Dz;
+                Dz += pB[c];
+            }
+            double hoop = ((trr[c] - ttt[c]) + (trr[cm] - ttt[cm])) / (2.0 * ri);
+            vr[c] += dt * buoy_R(G, i, k) * (Dr + Dz + hoop);
+        }
+    }
+    /* velocity: Z nodes */
+    for (int i = 0; i < NR; ++i) {
+        double rh = (i + 0.5) * dr;
+        for (int k = 0; k < NZ; ++k) {
+            size_t c = IX(i, k);
+            double trz_ip = i + 1 < NR ? trz[IX(i + 1, k)] : 0.0;
+            double Dr = (trz_ip - trz[c]) / dr;
+            if (G->onr_h[i]) {
+                pC[c] = G->br_h[i] * pC[c] + G->ar_h[i] * Dr;
+                Dr += pC[c];
+            }
+            double tzz_kp = k + 1 < NZ ? tzz[IX(i, k + 1)] : 0.0;
+            double Dz = (tzz_kp - tzz[c]) / dz;
+            if (G->onz_h[k]) {
+                pD[c] = G->bz_h[k] * pD[c] + G->az_h[k] * Dz;
+                Dz += pD[c];
+            }
+            double hoop = (trz_ip + trz[c]) / (2.0 * rh);
+            vz[c] += dt * buoy_Z(G, i, k) * (Dr + Dz + hoop);
+        }
+    }
+    /* stress: C nodes */
+    for (int i = 0; i < NR; ++i) {
+        double rh = (i + 0.5) * dr;
+        for (int k = 0; k < NZ; ++k) {
+            size_t c = IX(i, k);
+            double vr_ip = i + 1 < NR ? vr[IX(i + 1, k)] : 0.0;
+            double err = (vr_ip - vr[c]) / dr;
+            if (G->onr_h[i]) {
+                pE[c] = G->br_h[i] * pE[c] + G->ar_h[i] * err;
+                err += pE[c];
+            }
+            double ett = (vr_ip + vr[c]) / (2.0 * rh);
+            double vz_km = k > 0 ? vz[IX(i, k - 1)] : 0.0;
+            double ezz = (vz[c] - vz_km) / dz;
+            if (G->onz_i[k]) {
+                pF[c] = G->bz_i[k] * pF[c] + G->az_i[k] * ezz;
+                ezz += pF[c];
+            }
+            double l = G->lam[c], m = G->mu[c];
+            trr[c] += dt * ((l + 2.0 * m) * err + l * (ett + ezz));
+            ttt[c] += dt * ((l + 2.0 * m) * ett + l * (err + ezz));
+            tzz[c] += dt * ((l + 2.0 * m) * ezz + l * (err + ett));
+            if (eps) {
+                eps[c] = err;
+                eps[N + c] = ett;
+                eps[2 * N + c] = ezz;
+            }
+        }
+    }
+    /* source: f of Eq. 2 in the three normal stresses */
+    {
+        size_t c = IX(0, src_k);
+        trr[c] += srcval;
+        ttt[c] += srcval;
+        tzz[c] += srcval;
+    }
+    /* stress: S nodes, i >= 1 */
+    if (eps)
+        for (int k = 0; k < NZ; ++k) eps[3 * N + IX(0, k)] = 0.0;
+    for (int i = 1; i < NR; ++i) {
+        for (int k = 0; k < NZ; ++k) {
+            size_t c = IX(i, k);
+            double vr_kp = k + 1 < NZ ? vr[IX(i, k + 1)] : 0.0;
+            double ez = (vr_kp - vr[c]) / dz;
+            if (G->onz_h[k]) {
+                pG[c] = G->bz_h[k] * pG[c] + G->az_h[k] * ez;
+                ez += pG[c];
+            }
+            double er = (vz[c] - vz[IX(i - 1, k)]) / dr;
+            if (G->onr_i[i]) {
+                pH[c] = G->br_i[i] * pH[c] + G->ar_i[i] * er;
+                er += pH[c];
+            }
+            trz[c] += dt * mu_S(G, i, k) * (ez + er);
+            if (eps) eps[3 * N + c] = ez + er;
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Exact transpose of fwd_step (without source), applied to the adjoint state a.
+ * Order is the reverse of the forward: stress phase first, then velocity.
+ * ------------------------------------------------------------------------- */
+static void adj_step(const grid *G, state *a)
+{
+    const int NR = G->NR, NZ = G->NZ;
+    const double dr = G->dr, dz = G->dz, dt = G->dt;
+    double *avr = a->vr, *avz = a->vz, *atrr = a->trr, *attt = a->ttt, *atzz = a->tzz,
+           *atrz = a->trz;
+    double *qA = a->psi[0], *qB = a->psi[1], *qC = a->psi[2], *qD = a->psi[3];
+    double *qE = a->psi[4], *qF = a->psi[5], *qG = a->psi[6], *qH = a->psi[7];
+
+    /* transpose of the stress phase: C nodes */
+    for (int i = 0; i < NR; ++i) {
+        double rh = (i + 0.5) * dr;
+        for (int k = 0; k < NZ; ++k) {
+            size_t c = IX(i, k);
+            double l = G->lam[c], m = G->mu[c];
+            double srr = (l + 2.0 * m) * atrr[c] + l * attt[c] + l * atzz[c];
+            double stt = l * atrr[c] + (l + 2.0 * m) * attt[c] + l * atzz[c];
+            double szz = l * atrr[c] + l * attt[c] + (l + 2.0 * m) * atzz[c];
+            double g_err = dt * srr, g_ett = dt * stt, g_ezz = dt * szz;
+            if (G->onr_h[i]) {
+                double q = qE[c] + g_err;
+                qE[c] = G->br_h[i] * q;
+                g_err += G->ar_h[i] * q;
+            }
+            if (G->onz_i[k]) {
+                double q = qF[c] + g_ezz;
+                qF[c] = G->bz_i[k] * q;
+                g_ezz += G->az_i[k] * q;
+            }
+            if (i + 1 < NR) avr[IX(i + 1, k)] += g_err / dr + g_ett / (2.0 * rh);
+            avr[c] += -g_err / dr + g_ett / (2.0 * rh);
+            avz[c] += g_ezz / dz;
+            if (k > 0) avz[IX(i, k - 1)] -= g_ezz / dz;
+        }
+    }
+    /* transpose of the stress phase: S nodes */
+    for (int i = 1; i < NR; ++i) {
+        for (int k = 0; k < NZ; ++k) {
+            size_t c = IX(i, k);
+            double g = dt * mu_S(G, i, k) * atrz[c];
+            double g_ez = g, g_er = g;
+            if (G->onz_h[k]) {
+                double q = qG[c] + g;
+                qG[c] = G->bz_h[k] * q;
+                g_ez += G->az_h[k] * q;
+            }
+            if (G->onr_i[i]) {
+                double q = qH[c] + g;
+                qH[c] = G->br_i[i] * q;
+                g_er += G->ar_i[i] * q;
+            }
+            if (k + 1 < NZ) avr[IX(i, k + 1)] += g_ez / dz;
+            avr[c] -= g_ez / dz;
+            avz[c] += g_er / dr;
+            avz[IX(i - 1, k)] -= g_er / dr;
+        }
+    }
+    /* transpose of the velocity phase: R nodes, i >= 1 */
+    for (int i = 1; i < NR; ++i) {
+        double ri = i * dr;
+        for (int k = 0; k < NZ; ++k) {
+            size_t c = IX(i, k), cm = IX(i - 1, k);
+            double w = dt * buoy_R(G, i, k) * avr[c];
+            double g_Dr = w, g_Dz = w;
+            if (G->onr_i[i]) {
+                double q = qA[c] + w;
+                qA[c] = G->br_i[i] * q;
+                g_Dr += G->ar_i[i] * q;
+            }
+            if (G->onz_i[k]) {
+                double q = qB[c] + w;
+                qB[c] = G->bz_i[k] * q;
+                g_Dz += G->az_i[k] * q;
+            }
+            atrr[c] += g_Dr / dr;
+            atrr[cm] -= g_Dr / dr;
+            atrz[c] += g_Dz / dz;
+            if (k > 0) atrz[IX(i, k - 1)] -= g_Dz / dz;
+            double h = w / (2.0 * ri);
+            atrr[c] += h;
+            attt[c] -= h;
+            atrr[cm] += h;
+            attt[cm] -= h;
+        }
+    }
+    /* transpose of the velocity phase: Z nodes */
+    for (int i = 0; i < NR; ++i) {
+        double rh = (i + 0.5) * dr;
+        for (int k = 0; k < NZ; ++k) {
+            size_t c = IX(i, k);
+            double w = dt * buoy_Z(G, i, k) * avz[c];
+            double g_Dr = w, g_Dz = w;
+            if (G->onr_h[i]) {
+                double q = qC[c] + w;
+                qC[c] = G->br_h[i] * q;
+                g_Dr += G->ar_h[i] * q;
+            }
+            if (G->onz_h[k]) {
+                double q = qD[c] + w;
+                qD[c] = G->bz_h[k] * q;
+                g_Dz += G->az_h[k] * q;
+            }
+            if (i + 1 < NR) atrz[IX(i + 1, k)] += g_Dr / dr + w / (2.0 * rh);
+            atrz[c] += -g_Dr / dr + w / (2.0 * rh);
+            if (k + 1 < NZ) atzz[IX(i, k + 1)] += g_Dz / dz;
+            atzz[c] -= g_Dz / dz;
+        }
+    }
+}
+
+static double src_scale(const grid *G)
+{
+    /* point source spread over the on-axis cell, volume pi dr^2 dz */
+    return G->dt / (ORC_PI * G->dr * G->dr * G->dz);
+}
+
+static int geom_ok(const orc_geom *g)
+{
+    int NZ = g->nz + 2 * g->pz;
+    if (g->src_k < 0 || g->src_k >= NZ) return 0;
+    for (int j = 0; j < g->nrec; ++j)
+        if (g->rec_k[j] < 0 || g->rec_k[j] >= NZ) return 0;
+    return 1;
+}
+
+/* ---------------------------------------------------------------------------
+ * Public entry points
+ * ------------------------------------------------------------------------- */
+void orc_moduli(int64_t n, const double *vp, const double *vs, const double *rho, double *lam,
+                double *mu)
+{
+    for (int64_t c = 0; c < n; ++c) {
+        lam[c] = rho[c] * vp[c] * vp[c] - 2.0 * rho[c] * vs[c] * vs[c];
+        mu[c] = rho[c] * vs[c] * vs[c];
+    }
+}
+
+void orc_velocities(int64_t n, const double *lam, const double *mu, const double *rho,
+                    double *vp, double *vs)
+{
+    for (int64_t c = 0; c < n; ++c) {
+        vp[c] = sqrt((lam[c] + 2.0 * mu[c]) / rho[c]);
+        vs[c] = sqrt(mu[c] / rho[c]);
+    }
+}
+
+int64_t orc_state_len(const orc_geom *g)
+{
+    return (int64_t)14 * (g->nr + g->pr) * (g->nz + 2 * g->pz);
+}
+
+int orc_forward(const orc_geom *g, const double *lam, const double *mu, const double *rho,
+                const double *wavelet, double *traces, double *final_state)
+{
+    grid G;
+    if (grid_init(&G, g, lam, mu, rho) || !geom_ok(g)) return -1;
+    int NZ = G.NZ;
+    size_t N = (size_t)G.NR * G.NZ;
+    double *mem = calloc(14 * N, sizeof(double));
+    if (!mem) {
+        grid_free(&G);
+        return -1;
+    }
+    state s;
+    state_bind(&s, mem, N);
+    double sc = src_scale(&G);
+    for (int n = 0; n < g->nt; ++n) {
+        fwd_step(&G, &s, g->src_k, sc * wavelet[n], NULL);
+        for (int j = 0; j < g->nrec; ++j) {
+            size_t c = IX(0, g->rec_k[j]);
+            traces[(size_t)j * g->nt + n] = (s.trr[c] + s.ttt[c] + s.tzz[c]) / 3.0;
+        }
+    }
+    if (final_state) memcpy(final_state, mem, 14 * N * sizeof(double));
+    free(mem);
+    grid_free(&G);
+    return 0;
+}
+
+double orc_misfit(int64_t n, const double *d, const double *dobs, double *resid)
+{
+    double J = 0.0;
+    for (int64_t c = 0; c < n; ++c) {
+        double r = d[c] - dobs[c];
+        if (resid) resid[c] = r;
+        J += 0.5 * r * r;
+    }
+    return J;
+}
+
+static void inject_residual(const orc_geom *g, int NZ, state *a, const double *resid, int n)
+{
+    for (int j = 0; j < g->nrec; ++j) {
+        size_t c = IX(0, g->rec_k[j]);
+        double r3 = resid[(size_t)j * g->nt + n] / 3.0;
+        a->trr[c] += r3;
+        a->ttt[c] += r3;
+        a->tzz[c] += r3;
+    }
+}
+
+int orc_gradient(const orc_geom *g, const double *lam, const double *mu, const double *rho,
+                 const double *wavelet, const double *resid, int32_t seg, double *glam,
+                 double *gmu, double *illum)
+{
+    grid G;
+    if (seg <= 0 || grid_init(&G, g, lam, mu, rho) || !geom_ok(g)) return -1;
+    const int NR = G.NR, NZ = G.NZ, nt = g->nt;
+    const double dt = G.dt;
+    size_t N = (size_t)NR * NZ, SL = 14 * N;
+    int nseg = (nt + seg - 1) / seg;
+    double *ckpt = malloc((size_t)(nseg > 0 ? nseg : 1) * SL * sizeof(double));
+    double *fmem = calloc(SL, sizeof(double));
+    double *amem = calloc(SL, sizeof(double));
+    double *eps = malloc((size_t)seg * 4 * N * sizeof(double));
+    double *gmuS = calloc(N, sizeof(double));
+    if (!ckpt || !fmem || !amem || !eps || !gmuS) {
+        free(ckpt); free(fmem); free(amem); free(eps); free(gmuS);
+        grid_free(&G);
+        return -1;
+    }
+    state s, a;
+    state_bind(&s, fmem, N);
+    state_bind(&a, amem, N);
+    double sc = src_scale(&G);
+    memset(glam, 0, N * sizeof(double));
+    memset(gmu, 0, N * sizeof(double));
+    memset(illum, 0, N * sizeof(double));
+
+    /* forward pass: checkpoints every seg steps, illumination from v^{n+1/2} */
+    for (int n = 0; n < nt; ++n) {
+        if (n % seg == 0) memcpy(ckpt + (size_t)(n / seg) * SL, fmem, SL * sizeof(double));
+        fwd_step(&G, &s, g->src_k, sc * wavelet[n], NULL);
+        for (int i = 0; i < NR; ++i)
+            for (int k = 0; k < NZ; ++k) {
+                size_t c = IX(i, k);
+                double vr_ip = i + 1 < NR ? s.vr[IX(i + 1, k)] : 0.0;
+                double vz_km = k > 0 ? s.vz[IX(i, k - 1)] : 0.0;
+                double ur = 0.5 * (s.vr[c] + vr_ip), uz = 0.5 * (vz_km + s.vz[c]);
+                illum[c] += dt * (ur * ur + uz * uz);
+            }
+    }
+
+    /* reverse pass, one segment at a time */
+    for (int j = nseg - 1; j >= 0; --j) {
+        int n0 = j * seg, n1 = n0 + seg < nt ? n0 + seg : nt;
+        memcpy(fmem, ckpt + (size_t)j * SL, SL * sizeof(double));
+        for (int n = n0; n < n1; ++n)
+            fwd_step(&G, &s, g->src_k, sc * wavelet[n], eps + (size_t)(n - n0) * 4 * N);
+        for (int n = n1 - 1; n >= n0; --n) {
+            inject_residual(g, NZ, &a, resid, n);
+            const double *e = eps + (size_t)(n - n0) * 4 * N;
+            /* Eq. 7 and Eq. 8, the adjoint stress being dJ/dtau^{n+1} */
+            for (size_t c = 0; c < N; ++c) {
+                double err = e[c], ett = e[N + c], ezz = e[2 * N + c];
+                double sa = a.trr[c] + a.ttt[c] + a.tzz[c];
+                glam[c] += dt * (err + ett + ezz) * sa;
+                gmu[c] += dt * 2.0 * (err * a.trr[c] + ett * a.ttt[c] + ezz * a.tzz[c]);
+                gmuS[c] += dt * e[3 * N + c] * a.trz[c];
+            }
+            adj_step(&G, &a);
+        }
+    }
+    /* rigidity at tau_rz nodes is the harmonic mean of the four adjacent C cells:
+     * d muS / d mu_c = muS^2 / (4 mu_c^2) per occurrence of c among the four */
+    for (int i = 1; i < NR; ++i)
+        for (int k = 0; k < NZ; ++k) {
+            double ms = mu_S(&G, i, k);
+            if (!(ms > 0)) continue;
+            int k1 = k + 1 < NZ ? k + 1 : NZ - 1;
+            size_t nb[4] = {IX(i - 1, k), IX(i, k), IX(i - 1, k1), IX(i, k1)};
+            for (int q = 0; q < 4; ++q) {
+                double mc = mu[nb[q]];
+                gmu[nb[q]] += gmuS[IX(i, k)] * ms * ms / (4.0 * mc * mc);
+            }
+        }
+    free(ckpt); free(fmem); free(amem); free(eps); free(gmuS);
+    grid_free(&G);
+    return 0;
+}
+
+int orc_source_adjoint(const orc_geom *g, const double *lam, const double *mu,
+                       const double *rho, const double *resid, double *wadj)
+{
+    grid G;
+    if (grid_init(&G, g, lam, mu, rho) || !geom_ok(g)) return -1;
+    int NZ = G.NZ;
+    size_t N = (size_t)G.NR * G.NZ;
+    double *amem = calloc(14 * N, sizeof(double));
+    if (!amem) {
+        grid_free(&G);
+        return -1;
+    }
+    state a;
+    state_bind(&a, amem, N);
+    double sc = src_scale(&G);
+    size_t cs = IX(0, g->src_k);
+    for (int n = g->nt - 1; n >= 0; --n) {
+        inject_residual(g, NZ, &a, resid, n);
+        wadj[n] = sc * (a.trr[cs] + a.ttt[cs] + a.tzz[cs]);
+        adj_step(&G, &a);
+    }
+    free(amem);
+    grid_free(&G);
+    return 0;
+}
+
+int orc_propagate(const orc_geom *g, const double *lam, const double *mu, const double *rho,
+                  double *st, int32_t nsteps)
+{
+    grid G;
+    if (grid_init(&G, g, lam, mu, rho) || !geom_ok(g)) return -1;
+    size_t N = (size_t)G.NR * G.NZ;
+    state s;
+    state_bind(&s, st, N);
+    for (int n = 0; n < nsteps; ++n) fwd_step(&G, &s, g->src_k, 0.0, NULL);
+    grid_free(&G);
+    return 0;
+}
+
+int orc_propagate_adjoint(const orc_geom *g, const double *lam, const double *mu,
+                          const double *rho, double *ast, int32_t nsteps)
+{
+    grid G;
+    if (grid_init(&G, g, lam, mu, rho) || !geom_ok(g)) return -1;
+    size_t N = (size_t)G.NR * G.NZ;
+    state a;
+    state_bind(&a, ast, N);
+    for (int n = 0; n < nsteps; ++n) adj_step(&G, &a);
+    grid_free(&G);
+    return 0;
+}
+
+void orc_precondition(int64_t n, const double *illum, const uint8_t *mask, double eps,
+                      double *g_lam, double *g_mu)
+{
+    double emax = 0.0;
+    for (int64_t c = 0; c < n; ++c)
+        if (mask[c] && illum[c] > emax) emax = illum[c];
+    for (int64_t c = 0; c < n; ++c) {
+        if (!mask[c]) {
+            g_lam[c] = 0.0;
+            g_mu[c] = 0.0;
+            continue;
+        }
+        double p = 1.0 / (illum[c] + eps * emax);
+        g_lam[c] *= p;
+        g_mu[c] *= p;
+    }
+}
+
+double orc_update(int64_t n, double *lam, double *mu, const double *rho, const double *g_lam,
+                  const double *g_mu, const uint8_t *mask, double eta, double alpha_override,
+                  double vp_min, double vp_max, double vs_min, double vs_max)
+{
+    double alpha = alpha_override;
+    if (!(alpha > 0)) {
+        double gl = 0, gm = 0, lm = 0, mm = 0;
+        for (int64_t c = 0; c < n; ++c) {
+            if (!mask[c]) continue;
+            if (fabs(g_lam[c]) > gl) gl = fabs(g_lam[c]);
+            if (fabs(g_mu[c]) > gm) gm = fabs(g_mu[c]);
+            if (fabs(lam[c]) > lm) lm = fabs(lam[c]);
+            if (fabs(mu[c]) > mm) mm = fabs(mu[c]);
+        }
+        double rl = lm > 0 ? gl / lm : 0, rm = mm > 0 ? gm / mm : 0;
+        double r = rl > rm ? rl : rm;
+        alpha = r > 0 ? eta / r : 0.0;
+    }
+    for (int64_t c = 0; c < n; ++c) {
+        if (!mask[c]) continue;
+        double l = lam[c] - alpha * g_lam[c];
+        double m = mu[c] - alpha * g_mu[c];
+        double r = rho[c];
+        if (m < r * vs_min * vs_min) m = r * vs_min * vs_min;
+        if (m > r * vs_max * vs_max) m = r * vs_max * vs_max;
+        double p = l + 2.0 * m;
+        if (p < r * vp_min * vp_min) p = r * vp_min * vp_min;
+        if (p > r * vp_max * vp_max) p = r * vp_max * vp_max;
+        lam[c] = p - 2.0 * m;
+        mu[c] = m;
+    }
+    return alpha;
+}

@@ -1,0 +1,94 @@
+/*
+ * orc.h -- FP64 CPU oracle for monopole borehole acoustic FWI
+ *          (Tang, Cheng, Li & Fang, "Borehole acoustic full-waveform inversion").
+ *
+ * TEST INFRASTRUCTURE.  This library exists only to check the HIP path.  It is
+ * loaded by the tests, by the smoke check and by the CPU-baseline leg of the
+ * benchmark, never by the product path.  It shares no code, header, table or
+ * constant with the HIP library: everything here is written from the paper's
+ * equations and from the discretisation readings listed in the design notes.
+ *
+ * Plain, serial, double precision.  No blocking, no fusion, no reordering
+ * beyond what the equations state.
+ *
+ * Grid (one shot).  NR = nr + pr radial rows i, NZ = nz + 2*pz axial columns k,
+ * k contiguous in memory, index i*NZ + k.  Node families (staggered, Method
+ * section, Eq. 2):
+ *   C (i,k) at (r = (i+1/2)dr, z = k dz)      tau_rr, tau_tt, tau_zz, lambda, mu, rho
+ *   R (i,k) at (r = i dr,      z = k dz)      v_r        (v_r = 0 on the axis, i = 0)
+ *   Z (i,k) at (r = (i+1/2)dr, z = (k+1/2)dz) v_z
+ *   S (i,k) at (r = i dr,      z = (k+1/2)dz) tau_rz     (tau_rz = 0 on the axis)
+ * Every field read outside [0,NR) x [0,NZ) is zero.
+ *
+ * Parity status of each entry point is stated in its comment.
+ */
+#ifndef ORC_H
+#define ORC_H
+#include <stdint.h>
+
+typedef struct {
+    int32_t nr, nz, pr, pz;   /* physical cells, PML widths (outer r, both z ends) */
+    double dr, dz, dt;        /* metres, seconds */
+    int32_t nt;               /* time steps */
+    double f0;                /* Hz: PML frequency shift alpha_max = pi*f0 */
+    double vmax;              /* m/s: PML damping reference velocity (fixed per shot) */
+    int32_t src_k;            /* C row of the on-axis source, padded-grid index */
+    int32_t nrec;             /* on-axis receivers */
+    const int32_t *rec_k;     /* their C rows, padded-grid index */
+} orc_geom;
+
+/* Eq. 3-4: lambda = rho Vp^2 - 2 rho Vs^2, mu = rho Vs^2.  Pinned by closed form. */
+void orc_moduli(int64_t n, const double *vp, const double *vs, const double *rho,
+                double *lam, double *mu);
+/* Eq. 11-12: Vp = sqrt((lambda+2mu)/rho), Vs = sqrt(mu/rho). */
+void orc_velocities(int64_t n, const double *lam, const double *mu, const double *rho,
+                    double *vp, double *vs);
+
+/* Eq. 2 forward modelling; traces[j*nt + n] = mean normal stress at receiver j
+ * after step n (time (n+1) dt).  final_state (nullable) receives the full state
+ * (orc_state_len doubles) after the last step.  Returns 0 or -1 on bad input. */
+int orc_forward(const orc_geom *g, const double *lam, const double *mu, const double *rho,
+                const double *wavelet, double *traces, double *final_state);
+
+/* Eq. 1 and 5: resid = d - dobs, returns J = 0.5 * sum(resid^2). */
+double orc_misfit(int64_t n, const double *d, const double *dobs, double *resid);
+
+/* Eq. 6-8 by the exact transpose of the discrete forward, driven by resid
+ * (= dJ/dtraces, [nrec][nt]).  Checkpoints every `seg` steps, recomputes each
+ * segment storing the strain rates it used, correlates them with the adjoint
+ * stresses.  Outputs (NR*NZ each, overwritten): glam = dJ/dlambda,
+ * gmu = dJ/dmu (the tau_rz-node harmonic-mean chain rule included; cells with
+ * mu <= 0 get only their own-node term), illum = sum_n dt |v|^2 at C nodes.
+ * Pinned by brute-force central differences and by dot-product tests. */
+int orc_gradient(const orc_geom *g, const double *lam, const double *mu, const double *rho,
+                 const double *wavelet, const double *resid, int32_t seg,
+                 double *glam, double *gmu, double *illum);
+
+/* Transpose of the map wavelet -> traces for a fixed model: wadj[n] =
+ * d<traces, resid>/d wavelet[n].  Used by the source-to-trace dot-product test. */
+int orc_source_adjoint(const orc_geom *g, const double *lam, const double *mu,
+                       const double *rho, const double *resid, double *wadj);
+
+/* Full state vector: 14 arrays of NR*NZ doubles in this order:
+ * vr vz trr ttt tzz trz psiA..psiH (memory variables of the PML, see orc.c).
+ * propagate: nsteps source-free forward steps in place.
+ * propagate_adjoint: the exact transpose of propagate, in place.          */
+int64_t orc_state_len(const orc_geom *g);
+int orc_propagate(const orc_geom *g, const double *lam, const double *mu, const double *rho,
+                  double *state, int32_t nsteps);
+int orc_propagate_adjoint(const orc_geom *g, const double *lam, const double *mu,
+                          const double *rho, double *astate, int32_t nsteps);
+
+/* Diagonal preconditioner (reading of the Numerical Examples section and
+ * Fig. 6): P = 1 / (E + eps * max_{mask} E); g <- P*g on mask cells, 0 elsewhere. */
+void orc_precondition(int64_t n, const double *illum, const uint8_t *mask, double eps,
+                      double *g_lam, double *g_mu);
+
+/* Eq. 9-10 with one alpha chosen so that the largest change relative to the
+ * largest modulus is eta (alpha_override > 0 uses that alpha instead), then a
+ * velocity box clip.  Only mask cells change.  Returns alpha. */
+double orc_update(int64_t n, double *lam, double *mu, const double *rho,
+                  const double *g_lam, const double *g_mu, const uint8_t *mask,
+                  double eta, double alpha_override,
+                  double vp_min, double vp_max, double vs_min, double vs_max);
+#endif
