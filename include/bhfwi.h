@@ -1,0 +1,179 @@
+/*
+ * bhfwi.h -- C-ABI of the MI355X (gfx950) hot path of gradient-descent
+ * borehole acoustic full-waveform inversion
+ * (Tang, Cheng, Li & Fang, "Borehole acoustic full-waveform inversion").
+ *
+ * The library advances the monopole velocity-stress equations in cylindrical
+ * (r, z) coordinates (Method section, Eq. 2) forward and adjoint (Eq. 6),
+ * correlates the two wavefields into lambda/mu gradients (Eq. 7-8), applies
+ * the diagonal preconditioner and updates the model (Eq. 9-12).
+ *
+ * Conventions for every entry point
+ *  - Return 0 on success or a negative BHFWI_E* code; bhfwi_last_error()
+ *    gives the text of the last failure on that context.  Nothing throws.
+ *  - Every pointer marked "device" is a HIP device pointer owned by the
+ *    caller; the library never frees or retains it past the call.  Host
+ *    pointers are read during the call only.
+ *  - Calls are asynchronous on the given stream (hipStream_t passed as void*;
+ *    NULL is the default stream).  Argument errors are reported
+ *    synchronously; nothing is launched when a call fails validation.
+ *  - Arrays are FP32, structure of arrays, z (k) contiguous.  A shot's padded
+ *    grid has NR = nr + npml_r radial rows i and NZ = nz + 2*npml_z axial rows
+ *    k; cell (i,k) of shot s reads the global model at
+ *    model_off + i*model_ld + k.
+ *  - Traces are packed shot after shot, each [nrec][nt]; wavelets are packed
+ *    shot after shot, each [nt] sampled at t = (n + 1/2) dt.
+ *
+ * Staggered grid (reading of the paper's finite-difference solver): normal
+ * stresses and the model at C (r=(i+1/2)dr, z=k dz), v_r at (i dr, k dz),
+ * v_z at ((i+1/2)dr, (k+1/2)dz), tau_rz at (i dr, (k+1/2)dz); v_r = tau_rz = 0
+ * on the axis; second order in space and time; complex-frequency-shifted PML
+ * on the outer radius and both axial ends.
+ */
+#ifndef BHFWI_H
+#define BHFWI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BHFWI_OK 0
+#define BHFWI_EINVAL (-1)      /* bad shape, null pointer, geometry */
+#define BHFWI_ECFL (-2)        /* time step above the stability limit */
+#define BHFWI_ENOMEM (-3)      /* a workspace smaller than bhfwi_sizes() asks */
+#define BHFWI_EHIP (-4)        /* HIP runtime error (text in bhfwi_last_error) */
+#define BHFWI_ENONFINITE (-5)  /* non-finite values detected */
+#define BHFWI_EUNSUPPORTED (-6)
+
+typedef struct bhfwi_ctx bhfwi_ctx;
+
+/* One shot (tool position), host struct. */
+typedef struct {
+    int32_t nr, nz;           /* physical cells, radial and axial */
+    int32_t npml_r, npml_z;   /* PML cells: outer radius, each axial end */
+    float dr, dz, dt;         /* m, m, s */
+    int32_t nt;               /* time steps */
+    float f0;                 /* Hz; PML frequency shift alpha_max = pi f0 */
+    float pml_vmax;           /* m/s; PML damping d0 = -3 vmax ln(1e-4) / (2 L) */
+    int32_t src_k;            /* padded-grid row of the on-axis source cell */
+    int32_t nrec;             /* on-axis receivers of this shot */
+    int32_t rec_off;          /* their rows are rec_k[rec_off .. rec_off+nrec) */
+    int32_t pad_;             /* keep the struct 8-byte aligned; set to 0 */
+    int64_t model_off;        /* global-model element of cell (0,0) */
+    int64_t model_ld;         /* global-model elements between radial rows */
+} bhfwi_shot;
+
+/* Workspace sizes in bytes and packed lengths in elements for a context. */
+typedef struct {
+    int64_t fwd_ws_bytes;     /* forward state, double-buffered */
+    int64_t ckpt_bytes;       /* forward checkpoints (one every ckpt_every steps) */
+    int64_t adj_ws_bytes;     /* adjoint state, double-buffered, plus the
+                                 velocity history of one checkpoint segment */
+    int64_t acc_elems;        /* per-shot accumulators: 4 planes of sum(NR*NZ) */
+    int64_t trace_elems;      /* sum over shots of nrec*nt */
+    int64_t wavelet_elems;    /* sum over shots of nt */
+    int64_t cells;            /* sum over shots of NR*NZ */
+    int64_t cell_steps;       /* sum over shots of NR*NZ*nt */
+    int32_t nt_max;
+    int32_t ckpt_every;
+    int32_t nseg;             /* checkpoint segments of the longest shot */
+    int32_t work_items;       /* wave work items per time step */
+} bhfwi_sizes_t;
+
+/* Tunables of the wave-march kernels (all shapes valid; see bhfwi_autotune). */
+typedef struct {
+    int32_t rows_per_wave;    /* radial rows one wave marches per launch, >= 1 */
+    int32_t waves_per_block;  /* 1, 2, 4 or 8 wave64 per workgroup */
+} bhfwi_tune;
+
+/* Create a context for a survey: a set of shots over one global model of
+ * model_len elements.  rec_k (host, nrec_total entries) holds the receiver
+ * rows of every shot.
+ * ckpt_every > 0 is the forward checkpoint interval in steps.  Validates the
+ * geometry (receiver and source rows inside the grid, windows inside the
+ * model) and the CFL condition vmax dt sqrt(1/dr^2 + 1/dz^2) < 1 with vmax =
+ * pml_vmax.  Uploads the shot table, receiver rows and PML profiles to the
+ * device selected by hip_device. */
+int bhfwi_create(bhfwi_ctx **out, int32_t hip_device, const bhfwi_shot *shots, int32_t nshot,
+                 const int32_t *rec_k, int32_t nrec_total, int64_t model_len,
+                 int32_t ckpt_every);
+void bhfwi_destroy(bhfwi_ctx *ctx);
+/* Text of the last failure on ctx; with ctx == NULL, of the last failed
+ * bhfwi_create on this thread. */
+const char *bhfwi_last_error(const bhfwi_ctx *ctx);
+int bhfwi_sizes(const bhfwi_ctx *ctx, bhfwi_sizes_t *out);
+int bhfwi_set_tune(bhfwi_ctx *ctx, const bhfwi_tune *tune);
+int bhfwi_get_tune(const bhfwi_ctx *ctx, bhfwi_tune *out);
+
+/* Eq. 3-4 (Method section): lam = rho vp^2 - 2 rho vs^2, mu = rho vs^2,
+ * n elements, device arrays. */
+int bhfwi_moduli(void *stream, int64_t n, const float *vp, const float *vs, const float *rho,
+                 float *lam, float *mu);
+/* Eq. 11-12: vp = sqrt((lam + 2 mu)/rho), vs = sqrt(mu/rho). */
+int bhfwi_velocities(void *stream, int64_t n, const float *lam, const float *mu,
+                     const float *rho, float *vp, float *vs);
+
+#define BHFWI_STORE_CKPT 1
+
+/* Forward modelling (Eq. 2) of every shot.  Device inputs: lam, mu, rho
+ * (global model), wavelet (packed).  Device output: traces (packed), the mean
+ * normal stress at each receiver after each step (Method section: pressure
+ * recorded in the fluid).  fwd_ws (>= fwd_ws_bytes) is scratch for the state.
+ * With BHFWI_STORE_CKPT, ckpt (>= ckpt_bytes) receives the state every
+ * ckpt_every steps for bhfwi_adjoint_model. */
+int bhfwi_fwd_model(bhfwi_ctx *ctx, void *stream, const float *lam, const float *mu,
+                    const float *rho, const float *wavelet, float *traces, void *fwd_ws,
+                    int64_t fwd_ws_bytes, void *ckpt, int64_t ckpt_bytes, int32_t flags);
+
+/* Eq. 1 and 5: resid = traces - observed (packed), and J = 0.5 sum resid^2
+ * accumulated in double into *J_dev (device, overwritten). */
+int bhfwi_misfit(bhfwi_ctx *ctx, void *stream, const float *traces, const float *observed,
+                 float *resid, double *J_dev);
+
+/* Adjoint modelling (Eq. 6, as the exact transpose of the discrete forward)
+ * driven by resid = dJ/dtraces (packed), fused with the zero-lag correlation
+ * of Eq. 7-8.  Each checkpoint segment is recomputed from ckpt (written by
+ * bhfwi_fwd_model with BHFWI_STORE_CKPT and the same model) storing v, then
+ * run backwards.  acc (device, acc_elems floats, overwritten) receives per
+ * shot, on the shot's padded grid: plane 0 dJ/dlambda, plane 1 the C-node
+ * part of dJ/dmu, plane 2 dJ/dmu_S at tau_rz nodes, plane 3 the illumination
+ * sum_n dt |v|^2.  adj_ws (>= adj_ws_bytes) is scratch. */
+int bhfwi_adjoint_model(bhfwi_ctx *ctx, void *stream, const float *lam, const float *mu,
+                        const float *rho, const float *wavelet, const float *resid,
+                        void *fwd_ws, int64_t fwd_ws_bytes, const void *ckpt,
+                        int64_t ckpt_bytes, void *adj_ws, int64_t adj_ws_bytes, float *acc);
+
+/* Gradient finalize: folds the tau_rz-node rigidity gradient into the C cells
+ * (harmonic-mean chain rule), and sums every shot's window into the global
+ * model grid in shot order (no atomics; deterministic).  Outputs (device,
+ * model_len each, overwritten): g_lam, g_mu, illum. */
+int bhfwi_gradient(bhfwi_ctx *ctx, void *stream, const float *mu, const float *acc,
+                   float *g_lam, float *g_mu, float *illum);
+
+/* Diagonal preconditioner (Numerical Examples section, Fig. 6): with
+ * E = illum and Emax its maximum over mask cells, g <- g / (E + eps Emax) for
+ * lam and mu on mask cells, 0 elsewhere.  n elements, device arrays;
+ * mask is uint8 (1 = invert this cell). */
+int bhfwi_precondition(bhfwi_ctx *ctx, void *stream, int64_t n, const float *illum,
+                       const uint8_t *mask, float eps, float *g_lam, float *g_mu);
+
+/* Velocity box applied after the update. */
+typedef struct {
+    float vp_min, vp_max, vs_min, vs_max;
+} bhfwi_bounds;
+
+/* Eq. 9-10 on mask cells: lam -= alpha g_lam, mu -= alpha g_mu, with one
+ * alpha = eta / max(max|g_lam|/max|lam|, max|g_mu|/max|mu|) over mask cells
+ * (the step controls the greatest change), or alpha = alpha_override when it
+ * is > 0; then mu is clipped to rho [vs_min^2, vs_max^2] and lam + 2 mu to
+ * rho [vp_min^2, vp_max^2].  alpha_out (device float, nullable) receives alpha. */
+int bhfwi_update(bhfwi_ctx *ctx, void *stream, int64_t n, float *lam, float *mu,
+                 const float *rho, const float *g_lam, const float *g_mu, const uint8_t *mask,
+                 float eta, float alpha_override, const bhfwi_bounds *bounds, float *alpha_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,10 @@
+"""MI355X-native hot path of gradient-descent borehole acoustic FWI
+(Tang, Cheng, Li & Fang, "Borehole acoustic full-waveform inversion").
+
+The compute runs in libbhfwi.so (hand-written HIP for gfx950, C-ABI in
+include/bhfwi.h).  This package is the Python binding: ``Survey`` wraps the
+C-ABI, ``BoreholeFWI`` is the torch.autograd.Function around the forward and
+adjoint kernels, ``fwi`` holds the iteration driver.
+"""
+from ._lib import BhfwiError, Survey, load, moduli, velocities  # noqa: F401
+from .autograd import BoreholeFWI  # noqa: F401

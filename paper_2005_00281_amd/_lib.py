@@ -1,0 +1,309 @@
+"""ctypes binding of libbhfwi (include/bhfwi.h).  Argument marshalling only:
+every step of the path runs in the library's HIP kernels; torch supplies
+device memory and the current stream.  Raises if the library is missing --
+there is no fallback."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbhfwi.so")
+
+BHFWI_STORE_CKPT = 1
+_ERRORS = {-1: "EINVAL", -2: "ECFL", -3: "ENOMEM", -4: "EHIP", -5: "ENONFINITE",
+           -6: "EUNSUPPORTED"}
+
+
+class BhfwiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("bhfwi %s (%d): %s" % (_ERRORS.get(code, "?"), code, msg))
+        self.code = code
+        self.name = _ERRORS.get(code, "?")
+
+
+class Shot(C.Structure):
+    _fields_ = [("nr", C.c_int32), ("nz", C.c_int32), ("npml_r", C.c_int32),
+                ("npml_z", C.c_int32), ("dr", C.c_float), ("dz", C.c_float),
+                ("dt", C.c_float), ("nt", C.c_int32), ("f0", C.c_float),
+                ("pml_vmax", C.c_float), ("src_k", C.c_int32), ("nrec", C.c_int32),
+                ("rec_off", C.c_int32), ("pad_", C.c_int32), ("model_off", C.c_int64),
+                ("model_ld", C.c_int64)]
+
+
+class Sizes(C.Structure):
+    _fields_ = [("fwd_ws_bytes", C.c_int64), ("ckpt_bytes", C.c_int64),
+                ("adj_ws_bytes", C.c_int64), ("acc_elems", C.c_int64),
+                ("trace_elems", C.c_int64), ("wavelet_elems", C.c_int64),
+                ("cells", C.c_int64), ("cell_steps", C.c_int64), ("nt_max", C.c_int32),
+                ("ckpt_every", C.c_int32), ("nseg", C.c_int32), ("work_items", C.c_int32)]
+
+
+class Tune(C.Structure):
+    _fields_ = [("rows_per_wave", C.c_int32), ("waves_per_block", C.c_int32)]
+
+
+class Bounds(C.Structure):
+    _fields_ = [("vp_min", C.c_float), ("vp_max", C.c_float), ("vs_min", C.c_float),
+                ("vs_max", C.c_float)]
+
+
+EXPORTS = ["bhfwi_create", "bhfwi_destroy", "bhfwi_last_error", "bhfwi_sizes",
+           "bhfwi_set_tune", "bhfwi_get_tune", "bhfwi_moduli", "bhfwi_velocities",
+           "bhfwi_fwd_model", "bhfwi_misfit", "bhfwi_adjoint_model", "bhfwi_gradient",
+           "bhfwi_precondition", "bhfwi_update"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libbhfwi.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libbhfwi.so is not built (%s); run __graft_entry__.build()" % path)
+    L = C.CDLL(path)
+    P, V, I64, I32, F = C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_float
+    L.bhfwi_create.argtypes = [C.POINTER(C.c_void_p), I32, C.POINTER(Shot), I32,
+                               C.POINTER(C.c_int32), I32, I64, I32]
+    L.bhfwi_destroy.argtypes = [P]
+    L.bhfwi_destroy.restype = None
+    L.bhfwi_last_error.argtypes = [P]
+    L.bhfwi_last_error.restype = C.c_char_p
+    L.bhfwi_sizes.argtypes = [P, C.POINTER(Sizes)]
+    L.bhfwi_set_tune.argtypes = [P, C.POINTER(Tune)]
+    L.bhfwi_get_tune.argtypes = [P, C.POINTER(Tune)]
+    L.bhfwi_moduli.argtypes = [V, I64, P, P, P, P, P]
+    L.bhfwi_velocities.argtypes = [V, I64, P, P, P, P, P]
+    L.bhfwi_fwd_model.argtypes = [P, V, P, P, P, P, P, P, I64, P, I64, I32]
+    L.bhfwi_misfit.argtypes = [P, V, P, P, P, P]
+    L.bhfwi_adjoint_model.argtypes = [P, V, P, P, P, P, P, P, I64, P, I64, P, I64, P]
+    L.bhfwi_gradient.argtypes = [P, V, P, P, P, P, P]
+    L.bhfwi_precondition.argtypes = [P, V, I64, P, P, F, P, P]
+    L.bhfwi_update.argtypes = [P, V, I64, P, P, P, P, P, P, F, F, C.POINTER(Bounds), P]
+    for name in EXPORTS:
+        if name not in ("bhfwi_destroy", "bhfwi_last_error"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _f32(t, n=None):
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous float32 device tensor")
+    if n is not None and t.numel() < n:
+        raise ValueError("tensor has %d elements, %d needed" % (t.numel(), n))
+    return C.c_void_p(t.data_ptr())
+
+
+def _check(rc, ctx=None):
+    if rc != 0:
+        msg = load().bhfwi_last_error(ctx)
+        raise BhfwiError(rc, msg.decode() if msg else "")
+
+
+def moduli(vp, vs, rho):
+    """Eq. 3-4 on device tensors."""
+    lam, mu = torch.empty_like(vp), torch.empty_like(vp)
+    _check(load().bhfwi_moduli(_stream(), vp.numel(), _f32(vp), _f32(vs), _f32(rho),
+                               _f32(lam), _f32(mu)))
+    return lam, mu
+
+
+def velocities(lam, mu, rho):
+    """Eq. 11-12 on device tensors."""
+    vp, vs = torch.empty_like(lam), torch.empty_like(lam)
+    _check(load().bhfwi_velocities(_stream(), lam.numel(), _f32(lam), _f32(mu), _f32(rho),
+                                   _f32(vp), _f32(vs)))
+    return vp, vs
+
+
+class Survey:
+    """A set of shots over one global model, bound to one HIP device.
+
+    shots: objects with nr, nz, pr, pz, dr, dz, dt, nt, f0, vmax, src_k,
+    rec_k (int array) and win_k0 (first global row of the shot's window);
+    model_shape: (NRg, NZg) of the global model."""
+
+    def __init__(self, shots, model_shape, ckpt_every=250, device=0):
+        L = load()
+        self.model_shape = tuple(int(x) for x in model_shape)
+        NRg, NZg = self.model_shape
+        arr = (Shot * len(shots))()
+        recs = []
+        for s, sh in enumerate(shots):
+            rk = np.asarray(sh.rec_k, np.int32)
+            NR, NZ = sh.nr + sh.pr, sh.nz + 2 * sh.pz
+            if NR > NRg:
+                raise ValueError("shot %d has more radial rows than the model" % s)
+            arr[s] = Shot(sh.nr, sh.nz, sh.pr, sh.pz, sh.dr, sh.dz, sh.dt, sh.nt, sh.f0,
+                          sh.vmax, sh.src_k, len(rk), len(recs), 0, int(sh.win_k0), NZg)
+            recs.extend(int(x) for x in rk)
+        rec_arr = (C.c_int32 * max(1, len(recs)))(*recs)
+        h = C.c_void_p()
+        rc = L.bhfwi_create(C.byref(h), int(device), arr, len(shots), rec_arr, len(recs),
+                            NRg * NZg, int(ckpt_every))
+        _check(rc, None)
+        self._h = h
+        self.device = torch.device("cuda", device)
+        self.nshot = len(shots)
+        self.shots = list(shots)
+        self.sizes = Sizes()
+        _check(L.bhfwi_sizes(h, C.byref(self.sizes)), h)
+        self._ws = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.bhfwi_destroy(h)
+            self._h = None
+
+    # ---------------------------------------------------------------- tuning
+    def set_tune(self, rows_per_wave, waves_per_block=4):
+        t = Tune(int(rows_per_wave), int(waves_per_block))
+        _check(load().bhfwi_set_tune(self._h, C.byref(t)), self._h)
+        _check(load().bhfwi_sizes(self._h, C.byref(self.sizes)), self._h)
+
+    def get_tune(self):
+        t = Tune()
+        _check(load().bhfwi_get_tune(self._h, C.byref(t)), self._h)
+        return t.rows_per_wave, t.waves_per_block
+
+    # ------------------------------------------------------------ workspaces
+    def workspace(self, name):
+        """Device scratch owned by this survey (torch allocations, reused)."""
+        nbytes = {"fwd": self.sizes.fwd_ws_bytes, "ckpt": self.sizes.ckpt_bytes,
+                  "adj": self.sizes.adj_ws_bytes}[name]
+        t = self._ws.get(name)
+        if t is None or t.numel() < nbytes:
+            t = torch.empty(max(1, nbytes), dtype=torch.uint8, device=self.device)
+            self._ws[name] = t
+        return t
+
+    def free_workspaces(self):
+        self._ws.clear()
+
+    # ---------------------------------------------------------------- steps
+    def fwd_model(self, lam, mu, rho, wavelet, store_ckpt=False, ckpt=None, traces=None):
+        """Eq. 2 for every shot; returns packed traces (and writes checkpoints)."""
+        z = self.sizes
+        if traces is None:
+            traces = torch.empty(z.trace_elems, dtype=torch.float32, device=self.device)
+        fw = self.workspace("fwd")
+        if store_ckpt and ckpt is None:
+            ckpt = self.workspace("ckpt")
+        n = self.model_shape[0] * self.model_shape[1]
+        rc = load().bhfwi_fwd_model(
+            self._h, _stream(), _f32(lam, n), _f32(mu, n), _f32(rho, n),
+            _f32(wavelet, z.wavelet_elems), _f32(traces, z.trace_elems), _ptr(fw), fw.numel(),
+            _ptr(ckpt) if store_ckpt else None, ckpt.numel() if store_ckpt else 0,
+            BHFWI_STORE_CKPT if store_ckpt else 0)
+        _check(rc, self._h)
+        return traces
+
+    def misfit(self, traces, observed, resid=None):
+        """Eq. 1 and 5: returns (resid, J as a 0-d float64 device tensor)."""
+        z = self.sizes
+        if resid is None:
+            resid = torch.empty(z.trace_elems, dtype=torch.float32, device=self.device)
+        J = torch.empty((), dtype=torch.float64, device=self.device)
+        _check(load().bhfwi_misfit(self._h, _stream(), _f32(traces, z.trace_elems),
+                                   _f32(observed, z.trace_elems), _f32(resid, z.trace_elems),
+                                   _ptr(J)), self._h)
+        return resid, J
+
+    def adjoint_model(self, lam, mu, rho, wavelet, resid, ckpt=None, acc=None):
+        """Eq. 6-8 with checkpoint recompute; returns the per-shot accumulators
+        [4, cells] (dJ/dlam, C part of dJ/dmu, dJ/dmu_S, illumination)."""
+        z = self.sizes
+        if acc is None:
+            acc = torch.empty(z.acc_elems, dtype=torch.float32, device=self.device)
+        if ckpt is None:
+            ckpt = self.workspace("ckpt")
+        fw, aw = self.workspace("fwd"), self.workspace("adj")
+        n = self.model_shape[0] * self.model_shape[1]
+        rc = load().bhfwi_adjoint_model(
+            self._h, _stream(), _f32(lam, n), _f32(mu, n), _f32(rho, n),
+            _f32(wavelet, z.wavelet_elems), _f32(resid, z.trace_elems), _ptr(fw), fw.numel(),
+            _ptr(ckpt), ckpt.numel(), _ptr(aw), aw.numel(), _f32(acc, z.acc_elems))
+        _check(rc, self._h)
+        return acc
+
+    def gradient(self, mu, acc, out=None):
+        """Gradient finalize: returns (g_lam, g_mu, illum) on the global grid."""
+        shp = self.model_shape
+        if out is None:
+            out = tuple(torch.empty(shp, dtype=torch.float32, device=self.device)
+                        for _ in range(3))
+        g_lam, g_mu, illum = out
+        _check(load().bhfwi_gradient(self._h, _stream(), _f32(mu), _f32(acc), _f32(g_lam),
+                                     _f32(g_mu), _f32(illum)), self._h)
+        return g_lam, g_mu, illum
+
+    def precondition(self, illum, mask, eps, g_lam, g_mu):
+        """Diagonal preconditioner, in place on g_lam and g_mu."""
+        if mask.dtype != torch.uint8:
+            raise ValueError("mask must be uint8")
+        _check(load().bhfwi_precondition(self._h, _stream(), illum.numel(), _f32(illum),
+                                         _ptr(mask), float(eps), _f32(g_lam), _f32(g_mu)),
+               self._h)
+        return g_lam, g_mu
+
+    def update(self, lam, mu, rho, g_lam, g_mu, mask, eta, alpha_override=0.0,
+               bounds=(0.0, 1e30, 0.0, 1e30)):
+        """Eq. 9-10 in place on lam, mu; returns alpha as a device tensor."""
+        alpha = torch.empty((), dtype=torch.float32, device=self.device)
+        b = Bounds(*[float(x) for x in bounds])
+        _check(load().bhfwi_update(self._h, _stream(), lam.numel(), _f32(lam), _f32(mu),
+                                   _f32(rho), _f32(g_lam), _f32(g_mu), _ptr(mask), float(eta),
+                                   float(alpha_override), C.byref(b), _ptr(alpha)), self._h)
+        return alpha
+
+    # ---------------------------------------------------------------- layout
+    def trace_slices(self):
+        """(offset, nrec, nt) of each shot in the packed trace arrays."""
+        out, off = [], 0
+        for sh in self.shots:
+            nrec = len(sh.rec_k)
+            out.append((off, nrec, sh.nt))
+            off += nrec * sh.nt
+        return out
+
+    def pack_wavelets(self, wavelets):
+        return torch.as_tensor(np.concatenate([np.asarray(w[: sh.nt], np.float32)
+                                               for w, sh in zip(wavelets, self.shots)]),
+                               device=self.device)
+
+    def unpack_traces(self, traces):
+        t = traces.detach().cpu().numpy()
+        return [t[o: o + r * nt].reshape(r, nt) for (o, r, nt) in self.trace_slices()]
+
+    def acc_views(self, acc):
+        """Per-shot [4, NR, NZ] views of the accumulators (cells are packed
+        with 64-float alignment)."""
+        z = self.sizes
+        a = acc.view(4, z.cells)
+        out, off = [], 0
+        for sh in self.shots:
+            NR, NZ = sh.nr + sh.pr, sh.nz + 2 * sh.pz
+            out.append(a[:, off: off + NR * NZ].view(4, NR, NZ))
+            off += (NR * NZ + 63) // 64 * 64
+        return out

@@ -1,0 +1,37 @@
+"""torch.autograd.Function around the HIP forward and adjoint kernels.
+
+forward: Eq. 2 for every shot of the survey, storing checkpoints (a fresh
+device allocation per call, kept on the autograd context).
+backward: grad_traces is dJ/dtraces for whatever loss the caller built (for
+Eq. 1 it is the residual of Eq. 5); the adjoint kernels recompute each
+checkpoint segment and correlate (Eq. 6-8); the finalize kernel returns
+dJ/dlambda and dJ/dmu on the global model grid.  The illumination of the
+same pass is left on the survey as ``last_illum`` for the preconditioner.
+"""
+from __future__ import annotations
+
+import torch
+
+
+class BoreholeFWI(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, lam, mu, survey, rho, wavelet):
+        z = survey.sizes
+        ckpt = torch.empty(max(1, z.ckpt_bytes), dtype=torch.uint8, device=lam.device)
+        traces = survey.fwd_model(lam.detach(), mu.detach(), rho, wavelet, store_ckpt=True,
+                                  ckpt=ckpt)
+        ctx.survey = survey
+        ctx.ckpt = ckpt
+        ctx.save_for_backward(lam.detach(), mu.detach(), rho, wavelet)
+        return traces
+
+    @staticmethod
+    def backward(ctx, grad_traces):
+        lam, mu, rho, wavelet = ctx.saved_tensors
+        survey = ctx.survey
+        acc = survey.adjoint_model(lam, mu, rho, wavelet, grad_traces.contiguous().float(),
+                                   ckpt=ctx.ckpt)
+        g_lam, g_mu, illum = survey.gradient(mu, acc)
+        survey.last_illum = illum
+        ctx.ckpt = None
+        return g_lam, g_mu, None, None, None

@@ -1,0 +1,558 @@
+// bhfwi_host.hip -- C-ABI of libbhfwi: validation, layout planning, PML
+// profiles and the launch sequences of the forward, adjoint and update steps.
+#include "bhfwi.h"
+#include "bhfwi_kernels.hip"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using bhfwi::ShotDev;
+
+namespace {
+
+constexpr int kPartBlocks = 1024;  // blocks of the two-level reductions
+constexpr int64_t kAlign = 64;     // floats (256 bytes) between packed blocks
+
+int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+thread_local std::string g_create_err;  // message of the last failed bhfwi_create
+
+}  // namespace
+
+struct bhfwi_ctx {
+    int device = 0;
+    int nshot = 0;
+    int64_t model_len = 0;
+    int ckpt_every = 0;
+    std::vector<bhfwi_shot> shots;
+    std::vector<int32_t> rec;
+    std::vector<ShotDev> sd;
+    int64_t cells = 0, fst_len = 0, ast_len = 0, trace_len = 0, wave_len = 0, cell_steps = 0;
+    int nt_max = 0, nseg = 0;
+    bhfwi_tune tune{16, 4};
+    std::vector<int4> work;
+    std::vector<int> work_nt;  // nt of each work item's shot, non-increasing
+    ShotDev* d_shots = nullptr;
+    int* d_rec = nullptr;
+    float* d_pml_r = nullptr;
+    float* d_pml_z = nullptr;
+    int4* d_work = nullptr;
+    void* d_scratch = nullptr;
+    std::string err;
+};
+
+namespace {
+
+int fail(bhfwi_ctx* c, int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+#define HIPOK(ctx, call)                                                              \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail((ctx), BHFWI_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+int grid1d(int64_t n, int cap = 4096)
+{
+    int64_t g = (n + 255) / 256;
+    if (g < 1) g = 1;
+    return (int)std::min<int64_t>(g, cap);
+}
+
+// Complex-frequency-shifted PML (reading of the paper's PML citation):
+// penetration x in (0, 1], d = d0 x^2, alpha = pi f0 (1 - x), kappa = 1,
+// b = exp(-(d + alpha) dt), a = d (b - 1) / (d + alpha); a = 0, b = 1 outside.
+void pml_coef(double x, double d0, double f0, double dt, float* a, float* b)
+{
+    if (!(x > 0.0)) {
+        *a = 0.0f;
+        *b = 1.0f;
+        return;
+    }
+    const double d = d0 * x * x;
+    const double al = M_PI * f0 * (1.0 - x);
+    const double bb = std::exp(-(d + al) * dt);
+    *b = (float)bb;
+    *a = (float)(d * (bb - 1.0) / (d + al));
+}
+
+void rebuild_work(bhfwi_ctx* c)
+{
+    c->work.clear();
+    c->work_nt.clear();
+    std::vector<int> order(c->nshot);
+    for (int s = 0; s < c->nshot; ++s) order[s] = s;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return c->sd[a].nt > c->sd[b].nt; });
+    const int R = std::max(1, c->tune.rows_per_wave);
+    for (int s : order) {
+        const ShotDev& S = c->sd[s];
+        const int strips = (S.NZ + bhfwi::kOwn - 1) / bhfwi::kOwn;
+        for (int i0 = 0; i0 < S.NR; i0 += R)
+            for (int j = 0; j < strips; ++j) {
+                c->work.push_back(make_int4(s, j * bhfwi::kOwn, i0, std::min(i0 + R, S.NR)));
+                c->work_nt.push_back(S.nt);
+            }
+    }
+}
+
+int upload_work(bhfwi_ctx* c)
+{
+    if (c->d_work) {
+        HIPOK(c, hipFree(c->d_work));
+        c->d_work = nullptr;
+    }
+    HIPOK(c, hipMalloc(&c->d_work, sizeof(int4) * c->work.size()));
+    HIPOK(c, hipMemcpy(c->d_work, c->work.data(), sizeof(int4) * c->work.size(),
+                       hipMemcpyHostToDevice));
+    return BHFWI_OK;
+}
+
+int default_rows(const bhfwi_ctx* c)
+{
+    // aim for >= 8192 waves per step (32 per CU) before lengthening the march
+    int64_t strip_rows = 0;
+    for (const ShotDev& S : c->sd)
+        strip_rows += (int64_t)((S.NZ + bhfwi::kOwn - 1) / bhfwi::kOwn) * S.NR;
+    int64_t r = strip_rows / 8192;
+    return (int)std::max<int64_t>(4, std::min<int64_t>(64, r));
+}
+
+int active_items(const bhfwi_ctx* c, int n)
+{
+    // work_nt is non-increasing: count items whose shot still runs at step n
+    auto it = std::partition_point(c->work_nt.begin(), c->work_nt.end(),
+                                   [n](int nt) { return nt > n; });
+    return (int)(it - c->work_nt.begin());
+}
+
+int check_ctx(bhfwi_ctx* c)
+{
+    if (!c) return BHFWI_EINVAL;
+    HIPOK(c, hipSetDevice(c->device));
+    return BHFWI_OK;
+}
+
+void launch_fill(hipStream_t st, float* p, int64_t n, float v)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(bhfwi::k_fill, dim3(grid1d(n)), dim3(256), 0, st, p, (long long)n, v);
+}
+
+int fwd_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const float* mu,
+               const float* rho, const float* wav, const float* in, float* out, float* traces,
+               float* hist)
+{
+    const int nact = active_items(c, n);
+    if (nact <= 0) return BHFWI_OK;
+    const int wpb = c->tune.waves_per_block;
+    hipLaunchKernelGGL(bhfwi::k_fwd_step, dim3((nact + wpb - 1) / wpb), dim3(64 * wpb), 0, st,
+                       c->d_shots, c->d_work, nact, n, lam, mu, rho, wav, c->d_rec, c->d_pml_r,
+                       c->d_pml_z, in, out, traces, hist, (long long)c->cells);
+    return BHFWI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bhfwi_create(bhfwi_ctx** out, int32_t hip_device, const bhfwi_shot* shots, int32_t nshot,
+                 const int32_t* rec_k, int32_t nrec_total, int64_t model_len, int32_t ckpt_every)
+{
+    if (!out) return BHFWI_EINVAL;
+    *out = nullptr;
+    bhfwi_ctx* c = new (std::nothrow) bhfwi_ctx;
+    if (!c) return BHFWI_ENOMEM;
+    auto bail = [&](int code) {
+        g_create_err = c->err;  // readable through bhfwi_last_error(NULL)
+        bhfwi_destroy(c);
+        return code;
+    };
+    if (nshot < 1 || !shots || model_len <= 0 || ckpt_every < 1 || nrec_total < 0 ||
+        (nrec_total > 0 && !rec_k))
+        return bail(fail(c, BHFWI_EINVAL, "bad survey arguments"));
+    c->device = hip_device;
+    c->nshot = nshot;
+    c->model_len = model_len;
+    c->ckpt_every = ckpt_every;
+    c->shots.assign(shots, shots + nshot);
+    c->rec.assign(rec_k, rec_k + nrec_total);
+    int64_t cell_off = 0, fst = 0, ast = 0, tr = 0, wv = 0;
+    int pr_off = 0, pz_off = 0;
+    std::vector<float> pmr, pmz;
+    for (int s = 0; s < nshot; ++s) {
+        const bhfwi_shot& h = shots[s];
+        const int64_t NR = (int64_t)h.nr + h.npml_r, NZ = (int64_t)h.nz + 2 * (int64_t)h.npml_z;
+        if (h.nr < 2 || h.nz < 2 || h.npml_r < 0 || h.npml_z < 0 || h.nt < 1)
+            return bail(fail(c, BHFWI_EINVAL, "shot %d: bad grid sizes", s));
+        if (NR * NZ >= (int64_t)1 << 31)
+            return bail(fail(c, BHFWI_EINVAL, "shot %d: more than 2^31 cells", s));
+        if (!(h.dr > 0) || !(h.dz > 0) || !(h.dt > 0) || !std::isfinite(h.dr) ||
+            !std::isfinite(h.dz) || !std::isfinite(h.dt) || !(h.pml_vmax > 0) || !(h.f0 >= 0))
+            return bail(fail(c, BHFWI_EINVAL, "shot %d: bad spacing, dt, f0 or vmax", s));
+        const double cfl =
+            (double)h.pml_vmax * h.dt * std::sqrt(1.0 / ((double)h.dr * h.dr) + 1.0 / ((double)h.dz * h.dz));
+        if (!(cfl < 1.0))
+            return bail(fail(c, BHFWI_ECFL, "shot %d: vmax dt sqrt(1/dr^2+1/dz^2) = %.4f >= 1", s, cfl));
+        if (h.src_k < 0 || h.src_k >= NZ)
+            return bail(fail(c, BHFWI_EINVAL, "shot %d: source row %d outside [0,%lld)", s, h.src_k,
+                             (long long)NZ));
+        if (h.nrec < 0 || h.rec_off < 0 || (int64_t)h.rec_off + h.nrec > nrec_total)
+            return bail(fail(c, BHFWI_EINVAL, "shot %d: receiver range outside rec_k", s));
+        for (int j = 0; j < h.nrec; ++j)
+            if (rec_k[h.rec_off + j] < 0 || rec_k[h.rec_off + j] >= NZ)
+                return bail(fail(c, BHFWI_EINVAL, "shot %d: receiver row %d outside grid", s,
+                                 rec_k[h.rec_off + j]));
+        if (h.model_off < 0 || h.model_ld < NZ ||
+            h.model_off + (NR - 1) * h.model_ld + NZ > model_len)
+            return bail(fail(c, BHFWI_EINVAL, "shot %d: model window outside the model", s));
+        ShotDev S{};
+        S.NR = (int)NR;
+        S.NZ = (int)NZ;
+        S.nr = h.nr;
+        S.nz = h.nz;
+        S.pr = h.npml_r;
+        S.pz = h.npml_z;
+        S.nt = h.nt;
+        S.src_k = h.src_k;
+        S.nrec = h.nrec;
+        S.rec_off = h.rec_off;
+        S.dr = h.dr;
+        S.dz = h.dz;
+        S.dt = h.dt;
+        S.inv_dr = (float)(1.0 / h.dr);
+        S.inv_dz = (float)(1.0 / h.dz);
+        // point source spread over the on-axis cell of volume pi dr^2 dz
+        S.src_scale = (float)((double)h.dt / (M_PI * (double)h.dr * h.dr * h.dz));
+        S.model_off = h.model_off;
+        S.model_ld = h.model_ld;
+        S.psir_len = (int64_t)h.npml_r * NZ;
+        S.psiz_len = NR * 2 * h.npml_z;
+        S.cell_off = cell_off;
+        cell_off += align_up(NR * NZ);
+        S.fst_off = fst;
+        fst += align_up(6 * NR * NZ + 4 * S.psir_len + 4 * S.psiz_len);
+        S.ast_off = ast;
+        ast += align_up(6 * NR * NZ + 5 * S.psir_len + 5 * S.psiz_len);
+        S.trace_off = tr;
+        tr += (int64_t)h.nrec * h.nt;
+        S.wave_off = wv;
+        wv += h.nt;
+        S.pml_r_off = pr_off;
+        S.pml_z_off = pz_off;
+        pr_off += 4 * (int)NR;
+        pz_off += 4 * (int)NZ;
+        // PML tables: [a_int | b_int | a_half | b_half]
+        const double lnR = std::log(1e-4);
+        const double d0r = h.npml_r > 0 ? -3.0 * h.pml_vmax * lnR / (2.0 * h.npml_r * h.dr) : 0.0;
+        const double d0z = h.npml_z > 0 ? -3.0 * h.pml_vmax * lnR / (2.0 * h.npml_z * h.dz) : 0.0;
+        std::vector<float> tr_(4 * NR), tz_(4 * NZ);
+        for (int i = 0; i < NR; ++i) {
+            double xi = 0, xh = 0;
+            if (h.npml_r > 0) {
+                xi = ((double)i - h.nr) / h.npml_r;
+                xh = ((double)i + 0.5 - h.nr) / h.npml_r;
+            }
+            pml_coef(xi, d0r, h.f0, h.dt, &tr_[i], &tr_[NR + i]);
+            pml_coef(xh, d0r, h.f0, h.dt, &tr_[2 * NR + i], &tr_[3 * NR + i]);
+        }
+        const double lo = h.npml_z - 0.5, hi = h.npml_z + h.nz - 0.5;
+        for (int k = 0; k < NZ; ++k) {
+            double xi = 0, xh = 0;
+            if (h.npml_z > 0) {
+                const double ui = k, uh = k + 0.5;
+                xi = ui < lo ? (lo - ui) / h.npml_z : (ui > hi ? (ui - hi) / h.npml_z : 0.0);
+                xh = uh < lo ? (lo - uh) / h.npml_z : (uh > hi ? (uh - hi) / h.npml_z : 0.0);
+            }
+            pml_coef(xi, d0z, h.f0, h.dt, &tz_[k], &tz_[NZ + k]);
+            pml_coef(xh, d0z, h.f0, h.dt, &tz_[2 * NZ + k], &tz_[3 * NZ + k]);
+        }
+        pmr.insert(pmr.end(), tr_.begin(), tr_.end());
+        pmz.insert(pmz.end(), tz_.begin(), tz_.end());
+        c->sd.push_back(S);
+        c->nt_max = std::max(c->nt_max, h.nt);
+        c->cell_steps += NR * NZ * h.nt;
+    }
+    c->cells = cell_off;
+    c->fst_len = fst;
+    c->ast_len = ast;
+    c->trace_len = tr;
+    c->wave_len = wv;
+    c->nseg = (c->nt_max + ckpt_every - 1) / ckpt_every;
+    c->tune.rows_per_wave = default_rows(c);
+    c->tune.waves_per_block = 4;
+    rebuild_work(c);
+
+    hipError_t e = hipSetDevice(hip_device);
+    if (e != hipSuccess) return bail(fail(c, BHFWI_EHIP, "hipSetDevice: %s", hipGetErrorString(e)));
+#define CREATE_HIP(call)                                                                \
+    do {                                                                                \
+        hipError_t e2 = (call);                                                         \
+        if (e2 != hipSuccess)                                                           \
+            return bail(fail(c, BHFWI_EHIP, "%s: %s", #call, hipGetErrorString(e2)));   \
+    } while (0)
+    CREATE_HIP(hipMalloc(&c->d_shots, sizeof(ShotDev) * nshot));
+    CREATE_HIP(hipMemcpy(c->d_shots, c->sd.data(), sizeof(ShotDev) * nshot, hipMemcpyHostToDevice));
+    CREATE_HIP(hipMalloc(&c->d_rec, sizeof(int) * std::max(1, nrec_total)));
+    if (nrec_total > 0)
+        CREATE_HIP(hipMemcpy(c->d_rec, rec_k, sizeof(int) * nrec_total, hipMemcpyHostToDevice));
+    CREATE_HIP(hipMalloc(&c->d_pml_r, sizeof(float) * pmr.size()));
+    CREATE_HIP(hipMemcpy(c->d_pml_r, pmr.data(), sizeof(float) * pmr.size(), hipMemcpyHostToDevice));
+    CREATE_HIP(hipMalloc(&c->d_pml_z, sizeof(float) * pmz.size()));
+    CREATE_HIP(hipMemcpy(c->d_pml_z, pmz.data(), sizeof(float) * pmz.size(), hipMemcpyHostToDevice));
+    CREATE_HIP(hipMalloc(&c->d_scratch, 4 * sizeof(float) * kPartBlocks + sizeof(double) * kPartBlocks));
+#undef CREATE_HIP
+    if (int rc = upload_work(c)) return bail(rc);
+    *out = c;
+    return BHFWI_OK;
+}
+
+void bhfwi_destroy(bhfwi_ctx* c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->d_shots) (void)hipFree(c->d_shots);
+    if (c->d_rec) (void)hipFree(c->d_rec);
+    if (c->d_pml_r) (void)hipFree(c->d_pml_r);
+    if (c->d_pml_z) (void)hipFree(c->d_pml_z);
+    if (c->d_work) (void)hipFree(c->d_work);
+    if (c->d_scratch) (void)hipFree(c->d_scratch);
+    delete c;
+}
+
+const char* bhfwi_last_error(const bhfwi_ctx* c)
+{
+    return c ? c->err.c_str() : g_create_err.c_str();
+}
+
+int bhfwi_sizes(const bhfwi_ctx* c, bhfwi_sizes_t* o)
+{
+    if (!c || !o) return BHFWI_EINVAL;
+    o->fwd_ws_bytes = 2 * c->fst_len * (int64_t)sizeof(float);
+    o->ckpt_bytes = (int64_t)std::max(0, c->nseg - 1) * c->fst_len * (int64_t)sizeof(float);
+    o->adj_ws_bytes =
+        (2 * c->ast_len + 2 * (int64_t)c->ckpt_every * c->cells) * (int64_t)sizeof(float);
+    o->acc_elems = 4 * c->cells;
+    o->trace_elems = c->trace_len;
+    o->wavelet_elems = c->wave_len;
+    o->cells = c->cells;
+    o->cell_steps = c->cell_steps;
+    o->nt_max = c->nt_max;
+    o->ckpt_every = c->ckpt_every;
+    o->nseg = c->nseg;
+    o->work_items = (int32_t)c->work.size();
+    return BHFWI_OK;
+}
+
+int bhfwi_set_tune(bhfwi_ctx* c, const bhfwi_tune* t)
+{
+    if (!c || !t) return BHFWI_EINVAL;
+    if (t->rows_per_wave < 1 ||
+        !(t->waves_per_block == 1 || t->waves_per_block == 2 || t->waves_per_block == 4 ||
+          t->waves_per_block == 8))
+        return fail(c, BHFWI_EINVAL, "bad tune (rows %d, waves/block %d)", t->rows_per_wave,
+                    t->waves_per_block);
+    if (int rc = check_ctx(c)) return rc;
+    c->tune = *t;
+    rebuild_work(c);
+    return upload_work(c);
+}
+
+int bhfwi_get_tune(const bhfwi_ctx* c, bhfwi_tune* o)
+{
+    if (!c || !o) return BHFWI_EINVAL;
+    *o = c->tune;
+    return BHFWI_OK;
+}
+
+int bhfwi_moduli(void* stream, int64_t n, const float* vp, const float* vs, const float* rho,
+                 float* lam, float* mu)
+{
+    if (n < 0 || (n > 0 && (!vp || !vs || !rho || !lam || !mu))) return BHFWI_EINVAL;
+    if (n == 0) return BHFWI_OK;
+    hipLaunchKernelGGL(bhfwi::k_moduli, dim3(grid1d(n)), dim3(256), 0, (hipStream_t)stream,
+                       (long long)n, vp, vs, rho, lam, mu);
+    return hipGetLastError() == hipSuccess ? BHFWI_OK : BHFWI_EHIP;
+}
+
+int bhfwi_velocities(void* stream, int64_t n, const float* lam, const float* mu,
+                     const float* rho, float* vp, float* vs)
+{
+    if (n < 0 || (n > 0 && (!vp || !vs || !rho || !lam || !mu))) return BHFWI_EINVAL;
+    if (n == 0) return BHFWI_OK;
+    hipLaunchKernelGGL(bhfwi::k_velocities, dim3(grid1d(n)), dim3(256), 0, (hipStream_t)stream,
+                       (long long)n, lam, mu, rho, vp, vs);
+    return hipGetLastError() == hipSuccess ? BHFWI_OK : BHFWI_EHIP;
+}
+
+int bhfwi_fwd_model(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
+                    const float* rho, const float* wavelet, float* traces, void* fwd_ws,
+                    int64_t fwd_ws_bytes, void* ckpt, int64_t ckpt_bytes, int32_t flags)
+{
+    if (int rc = check_ctx(c)) return rc;
+    bhfwi_sizes_t z;
+    bhfwi_sizes(c, &z);
+    if (!lam || !mu || !rho || !wavelet || !traces || !fwd_ws)
+        return fail(c, BHFWI_EINVAL, "fwd_model: null pointer");
+    if (fwd_ws_bytes < z.fwd_ws_bytes)
+        return fail(c, BHFWI_ENOMEM, "fwd_model: fwd_ws %lld < %lld bytes",
+                    (long long)fwd_ws_bytes, (long long)z.fwd_ws_bytes);
+    const bool store = (flags & BHFWI_STORE_CKPT) != 0;
+    if (store && z.ckpt_bytes > 0 && (!ckpt || ckpt_bytes < z.ckpt_bytes))
+        return fail(c, BHFWI_ENOMEM, "fwd_model: ckpt %lld < %lld bytes", (long long)ckpt_bytes,
+                    (long long)z.ckpt_bytes);
+    hipStream_t st = (hipStream_t)stream;
+    float* b[2] = {(float*)fwd_ws, (float*)fwd_ws + c->fst_len};
+    launch_fill(st, b[0], 2 * c->fst_len, 0.0f);
+    const int K = c->ckpt_every;
+    for (int n = 0; n < c->nt_max; ++n) {
+        fwd_launch(c, st, n, lam, mu, rho, wavelet, b[n & 1], b[(n + 1) & 1], traces, nullptr);
+        if (store && (n + 1) % K == 0 && n + 1 < c->nt_max) {
+            float* dst = (float*)ckpt + (int64_t)((n + 1) / K - 1) * c->fst_len;
+            HIPOK(c, hipMemcpyAsync(dst, b[(n + 1) & 1], sizeof(float) * c->fst_len,
+                                    hipMemcpyDeviceToDevice, st));
+        }
+    }
+    HIPOK(c, hipGetLastError());
+    return BHFWI_OK;
+}
+
+int bhfwi_misfit(bhfwi_ctx* c, void* stream, const float* traces, const float* observed,
+                 float* resid, double* J_dev)
+{
+    if (int rc = check_ctx(c)) return rc;
+    if (!traces || !observed || !resid || !J_dev)
+        return fail(c, BHFWI_EINVAL, "misfit: null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    const int nb = grid1d(c->trace_len, kPartBlocks);
+    double* part = (double*)((float*)c->d_scratch + 4 * kPartBlocks);
+    hipLaunchKernelGGL(bhfwi::k_misfit_partial, dim3(nb), dim3(256), 0, st,
+                       (long long)c->trace_len, traces, observed, resid, part);
+    hipLaunchKernelGGL(bhfwi::k_sum_partials, dim3(1), dim3(256), 0, st, nb, part, J_dev);
+    HIPOK(c, hipGetLastError());
+    return BHFWI_OK;
+}
+
+int bhfwi_adjoint_model(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
+                        const float* rho, const float* wavelet, const float* resid,
+                        void* fwd_ws, int64_t fwd_ws_bytes, const void* ckpt,
+                        int64_t ckpt_bytes, void* adj_ws, int64_t adj_ws_bytes, float* acc)
+{
+    if (int rc = check_ctx(c)) return rc;
+    bhfwi_sizes_t z;
+    bhfwi_sizes(c, &z);
+    if (!lam || !mu || !rho || !wavelet || !resid || !fwd_ws || !adj_ws || !acc)
+        return fail(c, BHFWI_EINVAL, "adjoint_model: null pointer");
+    if (fwd_ws_bytes < z.fwd_ws_bytes || adj_ws_bytes < z.adj_ws_bytes)
+        return fail(c, BHFWI_ENOMEM, "adjoint_model: workspace too small (fwd %lld/%lld, adj %lld/%lld)",
+                    (long long)fwd_ws_bytes, (long long)z.fwd_ws_bytes, (long long)adj_ws_bytes,
+                    (long long)z.adj_ws_bytes);
+    if (z.ckpt_bytes > 0 && (!ckpt || ckpt_bytes < z.ckpt_bytes))
+        return fail(c, BHFWI_ENOMEM, "adjoint_model: ckpt %lld < %lld bytes", (long long)ckpt_bytes,
+                    (long long)z.ckpt_bytes);
+    hipStream_t st = (hipStream_t)stream;
+    float* fb[2] = {(float*)fwd_ws, (float*)fwd_ws + c->fst_len};
+    float* ab[2] = {(float*)adj_ws, (float*)adj_ws + c->ast_len};
+    float* hist = (float*)adj_ws + 2 * c->ast_len;
+    const int64_t hslot = 2 * c->cells;
+    launch_fill(st, fb[0], 2 * c->fst_len, 0.0f);
+    launch_fill(st, ab[0], 2 * c->ast_len, 0.0f);
+    launch_fill(st, acc, 4 * c->cells, 0.0f);
+    const int K = c->ckpt_every;
+    const int wpb = c->tune.waves_per_block;
+    int m = 0;
+    for (int j = c->nseg - 1; j >= 0; --j) {
+        const int n0 = j * K, n1 = std::min(n0 + K, c->nt_max);
+        if (j == 0)
+            launch_fill(st, fb[0], c->fst_len, 0.0f);
+        else
+            HIPOK(c, hipMemcpyAsync(fb[0], (const float*)ckpt + (int64_t)(j - 1) * c->fst_len,
+                                    sizeof(float) * c->fst_len, hipMemcpyDeviceToDevice, st));
+        for (int n = n0; n < n1; ++n)
+            fwd_launch(c, st, n, lam, mu, rho, wavelet, fb[(n - n0) & 1], fb[(n - n0 + 1) & 1],
+                       nullptr, hist + (int64_t)(n - n0) * hslot);
+        for (int n = n1 - 1; n >= n0; --n, ++m) {
+            const int nact = active_items(c, n);
+            if (nact <= 0) continue;
+            hipLaunchKernelGGL(bhfwi::k_adj_step, dim3((nact + wpb - 1) / wpb), dim3(64 * wpb), 0,
+                               st, c->d_shots, c->d_work, nact, n, lam, mu, rho, c->d_rec, resid,
+                               c->d_pml_r, c->d_pml_z, ab[m & 1], ab[(m + 1) & 1],
+                               hist + (int64_t)(n - n0) * hslot, acc, (long long)c->cells);
+        }
+    }
+    HIPOK(c, hipGetLastError());
+    return BHFWI_OK;
+}
+
+int bhfwi_gradient(bhfwi_ctx* c, void* stream, const float* mu, const float* acc, float* g_lam,
+                   float* g_mu, float* illum)
+{
+    if (int rc = check_ctx(c)) return rc;
+    if (!mu || !acc || !g_lam || !g_mu || !illum)
+        return fail(c, BHFWI_EINVAL, "gradient: null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    launch_fill(st, g_lam, c->model_len, 0.0f);
+    launch_fill(st, g_mu, c->model_len, 0.0f);
+    launch_fill(st, illum, c->model_len, 0.0f);
+    for (int s = 0; s < c->nshot; ++s) {
+        const int64_t cells = (int64_t)c->sd[s].NR * c->sd[s].NZ;
+        hipLaunchKernelGGL(bhfwi::k_finalize_shot, dim3(grid1d(cells)), dim3(256), 0, st,
+                           c->d_shots, s, mu, acc, (long long)c->cells, g_lam, g_mu, illum);
+    }
+    HIPOK(c, hipGetLastError());
+    return BHFWI_OK;
+}
+
+int bhfwi_precondition(bhfwi_ctx* c, void* stream, int64_t n, const float* illum,
+                       const uint8_t* mask, float eps, float* g_lam, float* g_mu)
+{
+    if (int rc = check_ctx(c)) return rc;
+    if (n < 1 || !illum || !mask || !g_lam || !g_mu || !(eps >= 0))
+        return fail(c, BHFWI_EINVAL, "precondition: bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    const int nb = grid1d(n, kPartBlocks);
+    float* part = (float*)c->d_scratch;
+    hipLaunchKernelGGL(bhfwi::k_absmax_partial, dim3(nb), dim3(256), 0, st, (long long)n, mask,
+                       illum, (const float*)nullptr, (const float*)nullptr,
+                       (const float*)nullptr, part);
+    hipLaunchKernelGGL(bhfwi::k_precond_apply, dim3(grid1d(n)), dim3(256), 0, st, (long long)n,
+                       mask, illum, eps, part, nb, g_lam, g_mu);
+    HIPOK(c, hipGetLastError());
+    return BHFWI_OK;
+}
+
+int bhfwi_update(bhfwi_ctx* c, void* stream, int64_t n, float* lam, float* mu, const float* rho,
+                 const float* g_lam, const float* g_mu, const uint8_t* mask, float eta,
+                 float alpha_override, const bhfwi_bounds* b, float* alpha_out)
+{
+    if (int rc = check_ctx(c)) return rc;
+    if (n < 1 || !lam || !mu || !rho || !g_lam || !g_mu || !mask || !b)
+        return fail(c, BHFWI_EINVAL, "update: bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    const int nb = grid1d(n, kPartBlocks);
+    float* part = (float*)c->d_scratch;
+    hipLaunchKernelGGL(bhfwi::k_absmax_partial, dim3(nb), dim3(256), 0, st, (long long)n, mask,
+                       g_lam, g_mu, (const float*)lam, (const float*)mu, part);
+    hipLaunchKernelGGL(bhfwi::k_update_apply, dim3(grid1d(n)), dim3(256), 0, st, (long long)n,
+                       mask, lam, mu, rho, g_lam, g_mu, (const float*)part, nb, eta,
+                       alpha_override, b->vp_min, b->vp_max, b->vs_min, b->vs_max, alpha_out);
+    HIPOK(c, hipGetLastError());
+    return BHFWI_OK;
+}
+
+}  // extern "C"

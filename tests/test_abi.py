@@ -1,0 +1,59 @@
+"""The C-ABI library loads and exports every entry point its header declares
+(no compute calls: this runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bhfwi.h")
+LIB = os.path.join(ROOT, "paper_2005_00281_amd", "libbhfwi.so")
+
+
+def declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(bhfwi_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_path_entry_points():
+    names = declared()
+    for verb in ("bhfwi_fwd_model", "bhfwi_adjoint_model", "bhfwi_gradient",
+                 "bhfwi_precondition", "bhfwi_update", "bhfwi_misfit", "bhfwi_moduli"):
+        assert verb in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libbhfwi.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libbhfwi.so not built")
+def test_binding_lists_every_declared_symbol():
+    from paper_2005_00281_amd import _lib
+    assert sorted(_lib.EXPORTS) == declared()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libbhfwi.so not built")
+def test_create_rejects_bad_geometry_without_gpu_work():
+    """Validation happens before any device call: a receiver outside the
+    grid and a CFL violation are refused with their codes."""
+    from paper_2005_00281_amd import _lib
+    L = _lib.load()
+    sh = (_lib.Shot * 1)()
+    sh[0] = _lib.Shot(16, 32, 4, 4, 5e-3, 5e-3, 0.5e-6, 10, 1e4, 4000.0, 10, 1, 0, 0, 0, 40)
+    rec = (ctypes.c_int32 * 1)(999)
+    h = ctypes.c_void_p()
+    rc = L.bhfwi_create(ctypes.byref(h), 0, sh, 1, rec, 1, 20 * 40, 10)
+    assert rc == -1 and b"receiver" in L.bhfwi_last_error(None)
+    rec[0] = 12
+    sh[0].dt = 1e-6  # 4000 * 1e-6 * sqrt(2) / 5e-3 = 1.13
+    rc = L.bhfwi_create(ctypes.byref(h), 0, sh, 1, rec, 1, 20 * 40, 10)
+    assert rc == -2 and b"vmax" in L.bhfwi_last_error(None)
+    sh[0].dt = 0.5e-6
+    sh[0].model_off = 5  # window runs past the model
+    rc = L.bhfwi_create(ctypes.byref(h), 0, sh, 1, rec, 1, 20 * 40, 10)
+    assert rc == -1 and b"model window" in L.bhfwi_last_error(None)

@@ -1,0 +1,301 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Tolerances: traces relative L2 <= 1e-4, gradients <= 1e-3 (FP32 GPU vs FP64
+oracle), exact equality where the same FP32 arithmetic is repeated (batched vs
+single shot, checkpoint interval).  Every case prints its name and shape
+before touching the GPU.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from util import geom, oracle_models, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def f32(a):
+    return torch.as_tensor(np.ascontiguousarray(a, np.float32), device=_dev())
+
+
+def gpu_models(w, which="start"):
+    import paper_2005_00281_amd as P
+    rho = f32(w.rho)
+    vp = w.vp_start if which == "start" else w.vp_true
+    vs = w.vs_start if which == "start" else w.vs_true
+    lam, mu = P.moduli(f32(vp), f32(vs), rho)
+    return lam, mu, rho
+
+
+def survey(w, ckpt=250, tune=None):
+    import paper_2005_00281_amd as P
+    sv = P.Survey(w.shots, (w.NRg, w.NZg), ckpt_every=ckpt)
+    if tune:
+        sv.set_tune(*tune)
+    return sv
+
+
+def oracle_traces(w, s=0, which="start"):
+    lam, mu, rho = oracle_models(w, s, which)
+    return oracle.forward(geom(w.shots[s]), lam, mu, rho, w.shots[s].wavelet)
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("tune", [(1, 1), (3, 2), (4, 4), (16, 4), (64, 8)])
+def test_forward_parity_tiny_ragged(tune):
+    """NZ = 162 spans three 62-row strips with a ragged tail; NR = 46 is not
+    a multiple of the radial chunk."""
+    w = workloads.tiny(nr=40, nz=150, p=6, nt=300)
+    _say("fwd tiny", tune, w.shots[0].NR, w.shots[0].NZ)
+    d_o = oracle_traces(w)
+    sv = survey(w, tune=tune)
+    lam, mu, rho = gpu_models(w)
+    tr = sv.fwd_model(lam, mu, rho, sv.pack_wavelets([w.shots[0].wavelet]))
+    torch.cuda.synchronize()
+    d_g = sv.unpack_traces(tr)[0]
+    assert rel_l2(d_g, d_o) <= 1e-4, rel_l2(d_g, d_o)
+
+
+def test_forward_parity_single_shot_128x512():
+    """The 128 x 512 workload (4000 steps, 10 kHz, water-filled hole),
+    true model: every trace within 1e-4 relative L2 of the oracle."""
+    w = workloads.make("c1")
+    _say("fwd c1", w.shots[0].NR, w.shots[0].NZ, w.shots[0].nt)
+    d_o = oracle_traces(w, which="true")
+    sv = survey(w)
+    lam, mu, rho = gpu_models(w, "true")
+    tr = sv.fwd_model(lam, mu, rho, sv.pack_wavelets([w.shots[0].wavelet]))
+    torch.cuda.synchronize()
+    d_g = sv.unpack_traces(tr)[0]
+    for j in range(d_o.shape[0]):
+        assert rel_l2(d_g[j], d_o[j]) <= 1e-4, (j, rel_l2(d_g[j], d_o[j]))
+
+
+def _gradient_case(w, ckpt, seg_oracle, tune=None):
+    """Oracle residual drives both adjoints, so the comparison isolates the
+    adjoint and correlation kernels (plus the recomputed forward)."""
+    sh = w.shots[0]
+    lam_o, mu_o, rho_o = oracle_models(w, 0, "start")
+    lt, mt, _ = oracle_models(w, 0, "true")
+    d_obs = oracle.forward(geom(sh), lt, mt, rho_o, sh.wavelet)
+    d_o = oracle.forward(geom(sh), lam_o, mu_o, rho_o, sh.wavelet)
+    _, r = oracle.misfit(d_o, d_obs)
+    gl_o, gm_o, il_o = oracle.gradient(geom(sh), lam_o, mu_o, rho_o, sh.wavelet, r,
+                                       seg=seg_oracle)
+    sv = survey(w, ckpt=ckpt, tune=tune)
+    lam, mu, rho = gpu_models(w)
+    wav = sv.pack_wavelets([sh.wavelet])
+    sv.fwd_model(lam, mu, rho, wav, store_ckpt=True)
+    acc = sv.adjoint_model(lam, mu, rho, wav, f32(r.ravel()))
+    g_lam, g_mu, illum = sv.gradient(mu, acc)
+    torch.cuda.synchronize()
+    return (g_lam.cpu().numpy(), g_mu.cpu().numpy(), illum.cpu().numpy()), (gl_o, gm_o, il_o)
+
+
+def _regions(sh, shape):
+    r = np.zeros(shape, bool)
+    r[sh.nr:, :] = True
+    z = np.zeros(shape, bool)
+    z[:, : sh.pz] = True
+    z[:, -sh.pz:] = True
+    return {"all": np.ones(shape, bool), "interior": ~(r | z), "pml_r": r, "pml_z": z}
+
+
+@pytest.mark.parametrize("tune", [(1, 1), (5, 4), (64, 8)])
+def test_gradient_parity_tiny(tune):
+    w = workloads.tiny(nr=40, nz=150, p=6, nt=300)
+    _say("grad tiny", tune)
+    (gl, gm, il), (gl_o, gm_o, il_o) = _gradient_case(w, ckpt=37, seg_oracle=50, tune=tune)
+    reg = _regions(w.shots[0], gl.shape)
+    errs = {k: (rel_l2(gl[m], gl_o[m]), rel_l2(gm[m], gm_o[m]),
+                np.linalg.norm(gl_o[m]) / np.linalg.norm(gl_o)) for k, m in reg.items()}
+    print("rel-L2 (g_lam, g_mu, |g_lam region|/|g_lam|):", errs, "illum", rel_l2(il, il_o))
+    assert errs["all"][0] <= 1e-3 and errs["all"][1] <= 1e-3
+    assert errs["interior"][0] <= 1e-3 and errs["interior"][1] <= 1e-3
+    assert rel_l2(il, il_o) <= 1e-4
+    # PML cells alone (the exact-in-PML correlation); their gradient is 2-3
+    # orders below the interior's, so FP32 rounding of the shared wavefields
+    # weighs more there
+    for k in ("pml_r", "pml_z"):
+        assert errs[k][0] <= 1e-2 and errs[k][1] <= 1e-2, (k, errs[k])
+
+
+def test_gradient_parity_single_shot_128x512():
+    w = workloads.make("c1")
+    _say("grad c1")
+    (gl, gm, il), (gl_o, gm_o, il_o) = _gradient_case(w, ckpt=250, seg_oracle=200)
+    form = w.mask.astype(bool)
+    assert rel_l2(gl[form], gl_o[form]) <= 1e-3, rel_l2(gl[form], gl_o[form])
+    assert rel_l2(gm[form], gm_o[form]) <= 1e-3, rel_l2(gm[form], gm_o[form])
+    assert rel_l2(gl, gl_o) <= 1e-3 and rel_l2(gm, gm_o) <= 1e-3
+    assert rel_l2(il, il_o) <= 1e-4
+
+
+def test_checkpoint_interval_is_exact():
+    """Recompute from checkpoints repeats the same FP32 arithmetic: any
+    checkpoint interval gives the bitwise-same gradient."""
+    w = workloads.tiny(nt=200)
+    _say("ckpt interval")
+    outs = []
+    r = np.random.default_rng(0).standard_normal(len(w.shots[0].rec_k) * 200)
+    for K in (7, 64, 200):
+        sv = survey(w, ckpt=K)
+        lam, mu, rho = gpu_models(w)
+        wav = sv.pack_wavelets([w.shots[0].wavelet])
+        sv.fwd_model(lam, mu, rho, wav, store_ckpt=True)
+        acc = sv.adjoint_model(lam, mu, rho, wav, f32(r))
+        outs.append([t.cpu().numpy() for t in sv.gradient(mu, acc)])
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+
+
+def _multi_shot_workload():
+    """Three shots over one layered global model: overlapping windows,
+    different record lengths (ragged nt) and receiver counts."""
+    base = workloads.batched_layered(nshot=3, nr=24, nz=90, h=5e-3, p=6, dt=0.5e-6, nt=260,
+                                     f0=40e3, nrec=3, step_m=0.05, cfg_id=77)
+    base.shots[1].nt = 200
+    base.shots[1].wavelet = base.shots[1].wavelet[:200]
+    base.shots[2].rec_k = base.shots[2].rec_k[:2]
+    for sh in base.shots:
+        sh.src_k = sh.pz + 10
+        sh.rec_k = np.array([sh.pz + 40 + 12 * j for j in range(len(sh.rec_k))], np.int32)
+    return base
+
+
+def test_batched_equals_single_and_oracle():
+    w = _multi_shot_workload()
+    _say("batched 3 shots", [(s.NR, s.NZ, s.nt) for s in w.shots])
+    import copy
+    lam, mu, rho = gpu_models(w)
+    sv = survey(w, ckpt=50)
+    wav = sv.pack_wavelets([s.wavelet for s in w.shots])
+    tr = sv.fwd_model(lam, mu, rho, wav, store_ckpt=True)
+    torch.manual_seed(0)
+    r = torch.randn(sv.sizes.trace_elems, device=_dev())
+    acc = sv.adjoint_model(lam, mu, rho, wav, r)
+    g_b = [t.cpu().numpy() for t in sv.gradient(mu, acc)]
+    tr_b = sv.unpack_traces(tr)
+    r_np = r.cpu().numpy()
+    sums = [np.zeros((w.NRg, w.NZg), np.float32) for _ in range(3)]
+    for s, (off, nrec, nt) in enumerate(sv.trace_slices()):
+        w1 = copy.copy(w)
+        w1.shots = [w.shots[s]]
+        sv1 = survey(w1, ckpt=50)
+        wav1 = sv1.pack_wavelets([w.shots[s].wavelet])
+        tr1 = sv1.fwd_model(lam, mu, rho, wav1, store_ckpt=True)
+        assert np.array_equal(sv1.unpack_traces(tr1)[0], tr_b[s])
+        acc1 = sv1.adjoint_model(lam, mu, rho, wav1, f32(r_np[off: off + nrec * nt]))
+        g1 = [t.cpu().numpy() for t in sv1.gradient(mu, acc1)]
+        for q in range(3):
+            sums[q] += g1[q]
+        # each shot against the oracle
+        lo, mo, ro = oracle_models(w, s, "start")
+        d_o = oracle.forward(geom(w.shots[s]), lo, mo, ro, w.shots[s].wavelet)
+        assert rel_l2(tr_b[s], d_o) <= 1e-4
+    for q in range(3):
+        assert np.array_equal(sums[q], g_b[q]), q
+
+
+def test_misfit_precondition_update_moduli_parity():
+    import paper_2005_00281_amd as P
+    _say("elementwise steps")
+    rng = np.random.default_rng(1)
+    w = workloads.tiny()
+    sv = survey(w)
+    n = sv.sizes.trace_elems
+    d, o = rng.standard_normal(n), rng.standard_normal(n)
+    resid, J = sv.misfit(f32(d), f32(o))
+    J_o, r_o = oracle.misfit(d.astype(np.float32), o.astype(np.float32))
+    assert abs(J.item() - J_o) <= 1e-6 * J_o
+    assert np.array_equal(resid.cpu().numpy(), (d.astype(np.float32) - o.astype(np.float32)))
+    # moduli / velocities
+    lam, mu, rho = gpu_models(w, "true")
+    lo, mo = oracle.moduli(w.vp_true, w.vs_true, w.rho)
+    assert rel_l2(lam.cpu().numpy(), lo) < 1e-6 and rel_l2(mu.cpu().numpy(), mo) < 1e-6
+    vp, vs = P.velocities(lam, mu, rho)
+    assert rel_l2(vp.cpu().numpy(), w.vp_true) < 1e-6
+    # preconditioner and update
+    shp = (w.NRg, w.NZg)
+    il = rng.uniform(0, 5, shp)
+    gl, gm = rng.standard_normal(shp), rng.standard_normal(shp)
+    mask = w.mask
+    tgl, tgm = f32(gl), f32(gm)
+    sv.precondition(f32(il), torch.as_tensor(mask, device=_dev()), 1e-3, tgl, tgm)
+    gl_o, gm_o = oracle.precondition(il.astype(np.float32), mask, 1e-3, gl.astype(np.float32),
+                                     gm.astype(np.float32))
+    assert rel_l2(tgl.cpu().numpy(), gl_o) < 1e-6 and rel_l2(tgm.cpu().numpy(), gm_o) < 1e-6
+    lam2, mu2 = lam.clone(), mu.clone()
+    bounds = (1000.0, 6000.0, 500.0, 3500.0)
+    a = sv.update(lam2, mu2, rho, tgl, tgm, torch.as_tensor(mask, device=_dev()), 0.02,
+                  bounds=bounds)
+    l_o, m_o, a_o = oracle.update(lam.cpu().numpy(), mu.cpu().numpy(), w.rho.astype(np.float32),
+                                  tgl.cpu().numpy(), tgm.cpu().numpy(), mask, 0.02,
+                                  vp_bounds=bounds[:2], vs_bounds=bounds[2:])
+    assert abs(a.item() - a_o) <= 1e-6 * a_o
+    assert rel_l2(lam2.cpu().numpy(), l_o) < 1e-6 and rel_l2(mu2.cpu().numpy(), m_o) < 1e-6
+
+
+def test_autograd_end_to_end_and_central_differences():
+    """BoreholeFWI: loss = 0.5 |d - d_obs|^2 with the GPU's own residual; the
+    gradient matches the oracle's (<= 1e-3) and central differences of the
+    GPU loss on illuminated cells (<= 1e-2)."""
+    import paper_2005_00281_amd as P
+    w = workloads.tiny(nr=30, nz=100, p=6, nt=300)
+    sh = w.shots[0]
+    _say("autograd tiny")
+    lam_o, mu_o, rho_o = oracle_models(w, 0, "start")
+    lt, mt, _ = oracle_models(w, 0, "true")
+    d_obs = oracle.forward(geom(sh), lt, mt, rho_o, sh.wavelet)
+    d_o = oracle.forward(geom(sh), lam_o, mu_o, rho_o, sh.wavelet)
+    _, r_o = oracle.misfit(d_o, d_obs)
+    gl_o, gm_o, _ = oracle.gradient(geom(sh), lam_o, mu_o, rho_o, sh.wavelet, r_o, seg=64)
+    sv = survey(w, ckpt=64)
+    lam, mu, rho = gpu_models(w)
+    wav = sv.pack_wavelets([sh.wavelet])
+    obs = f32(d_obs.ravel())
+    lam.requires_grad_(True)
+    mu.requires_grad_(True)
+    tr = P.BoreholeFWI.apply(lam, mu, sv, rho, wav)
+    loss = 0.5 * ((tr - obs).double() ** 2).sum()
+    loss.backward()
+    gl, gm = lam.grad.cpu().numpy(), mu.grad.cpu().numpy()
+    assert rel_l2(gl, gl_o) <= 1e-3 and rel_l2(gm, gm_o) <= 1e-3
+
+    def J(l, m):
+        with torch.no_grad():
+            t = sv.fwd_model(l, m, rho, wav)
+            return 0.5 * ((t - obs).double() ** 2).sum().item()
+
+    # 16 cells of largest |g| among formation cells: well illuminated
+    form = w.mask.astype(bool)
+    score = np.where(form, np.abs(gl) / np.abs(gl[form]).max() + np.abs(gm) / np.abs(gm[form]).max(), 0)
+    cells = np.argsort(score.ravel())[-16:]
+    L0, M0 = lam.detach(), mu.detach()
+    for c in cells:
+        i, k = np.unravel_index(c, gl.shape)
+        for name, base, G in (("lam", L0, gl), ("mu", M0, gm)):
+            h = 1e-2 * base[i, k].item()
+            p, q = base.clone(), base.clone()
+            p[i, k] += h
+            q[i, k] -= h
+            if name == "lam":
+                fd = (J(p, M0) - J(q, M0)) / (2 * h)
+            else:
+                fd = (J(L0, p) - J(L0, q)) / (2 * h)
+            assert abs(fd - G[i, k]) <= 1e-2 * abs(G[i, k]) + 1e-3 * np.abs(G).max(), \
+                (name, i, k, fd, G[i, k])
