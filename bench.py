@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Benchmark of the borehole FWI hot path on one MI355X.
+
+A step is one full gradient-descent FWI iteration over the workload: moduli,
+forward modelling with checkpoints, misfit, adjoint recompute + adjoint with
+the fused correlation, gradient finalize, preconditioner, update and the
+conversion back to velocities -- every step in the HIP library.  Inputs are
+seeded synthetic models already resident in HBM.
+
+Default workload: one shot of 320 x 2048 cells (2.5 mm, 20-cell PML), 8000
+steps of 0.25 us, 12 kHz Ricker, 13 receivers, checkpoints every 250 steps.
+
+Prints one JSON line.  value = Gcell-updates/s of the whole iteration
+(2 x cell-steps per iteration / wall time: one forward and one adjoint sweep).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("Gcell-updates/s fwd+adj+grad and % HBM roofline; "
+          "shots·FWI-iters/s batched vs plain")
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per cell and step (FP32): adjoint step with the fused
+# correlation reads/writes 6 adjoint fields, reads lambda, mu, rho and the
+# stored v_r, v_z, and reads/writes g_lambda, g_mu and the illumination
+ADJ_BYTES_PER_CELL_STEP = 92
+FWD_BYTES_PER_CELL_STEP = 60
+REC_BYTES_PER_CELL_STEP = 68
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, nt_sample):
+    """The FP64 oracle, as it is, on the first nt_sample steps of shot 0:
+    one forward (observed data), one forward (start model) and one gradient
+    evaluation.  Rate reported per cell-step of the gradient evaluation."""
+    import numpy as np
+    import oracle
+    sh = w.shots[0]
+    g = oracle.Geom(sh.nr, sh.nz, sh.pr, sh.pz, sh.dr, sh.dz, sh.dt, nt_sample, sh.f0, sh.vmax,
+                    sh.src_k, sh.rec_k)
+    win = lambda a: np.ascontiguousarray(w.window(a, 0))
+    rho = win(w.rho)
+    lt, mt = oracle.moduli(win(w.vp_true), win(w.vs_true), rho)
+    lam, mu = oracle.moduli(win(w.vp_start), win(w.vs_start), rho)
+    dobs = oracle.forward(g, lt, mt, rho, sh.wavelet)
+    t0 = time.time()
+    d = oracle.forward(g, lam, mu, rho, sh.wavelet)
+    _, r = oracle.misfit(d, dobs)
+    oracle.gradient(g, lam, mu, rho, sh.wavelet, r, seg=50)
+    dt = time.time() - t0
+    cs = sh.cells * nt_sample
+    return {"value": round(2 * cs / dt / 1e9, 5), "unit": "Gcell-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "shot 0, first %d of %d steps (%.3g cell-steps), forward + misfit + "
+                      "checkpointed gradient, %.1f s" % (nt_sample, sh.nt, cs, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--rows", type=int, default=0, help="rows per wave (0: library default)")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=120)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU; this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads
+    import paper_2005_00281_amd as P
+    from paper_2005_00281_amd.fwi import Inversion
+
+    dev = torch.device("cuda", 0)
+    w = workloads.make(args.workload)
+    f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=dev)
+    log("workload", args.workload, "shots", len(w.shots), "grid", w.shots[0].NR, w.shots[0].NZ,
+        "nt", w.shots[0].nt)
+    sv = P.Survey(w.shots, (w.NRg, w.NZg), ckpt_every=w.meta.get("ckpt", 250))
+    if args.rows:
+        sv.set_tune(args.rows, 4, 0 if args.no_graph else 1)
+    elif args.no_graph:
+        r, wpb, _, _ = sv.get_tune()
+        sv.set_tune(r, wpb, 0)
+    tune = sv.get_tune()
+    rho = f32(w.rho)
+    wav = sv.pack_wavelets([s.wavelet for s in w.shots])
+    lam_t, mu_t = P.moduli(f32(w.vp_true), f32(w.vs_true), rho)
+    observed = sv.fwd_model(lam_t, mu_t, rho, wav).clone()
+    del lam_t, mu_t
+    mask = torch.as_tensor(w.mask, device=dev)
+    inv = Inversion(sv, f32(w.vp_start), f32(w.vs_start), rho, wav, observed, mask)
+    z = sv.sizes
+
+    for _ in range(args.warmup):
+        inv.iterate()
+    torch.cuda.synchronize()
+    log("warmup done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Js = []
+    for _ in range(args.steps):
+        J, a = inv.iterate()
+        Js.append(J)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / max(1, args.steps)
+    value = 2 * z.cell_steps / (ms * 1e-3) / 1e9
+    log("ms/iteration %.2f, J %s" % (ms, [round(float(j), 6) for j in Js]))
+
+    # per-kernel durations: one more (untimed) iteration with every time-step
+    # kernel bracketed by HIP events on the stream it runs on
+    r, wpb, ug, _ = tune
+    sv.set_tune(r, wpb, 0, 1)
+    sv.kernel_times(reset=True)
+    inv.iterate()
+    kt = sv.kernel_times(reset=True)
+    sv.set_tune(r, wpb, ug, 0)
+    cells = z.cells
+    adj_ms, adj_n = kt["adj"]
+    fwd_ms, fwd_n = kt["fwd"]
+    rec_ms, rec_n = kt["rec"]
+    cells_active = sum(s.cells for s in w.shots)
+    adj_avg = adj_ms / max(1, adj_n)
+    # algorithmic bytes per launch: every active cell once (shots share launches)
+    adj_bytes = ADJ_BYTES_PER_CELL_STEP * z.cell_steps / z.nt_max
+    achieved = adj_bytes / (adj_avg * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_adj_step", "avg_launch_us": round(adj_avg * 1e3, 3),
+                "bytes_per_launch": int(adj_bytes)}
+    kernels = {k: {"avg_us": round(v[0] * 1e3 / max(1, v[1]), 3), "launches": v[1]}
+               for k, v in kt.items()}
+    # iteration-level roofline: 220 B per cell-step over one gradient evaluation
+    it_frac = (220 * z.cell_steps / (ms * 1e-3)) / (HBM_PEAK_GBS * 1e9)
+
+    base = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        base = cpu_baseline(w, args.cpu_sample_steps)
+
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gcell-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload + ": " + (w.__class__.__name__ and
+                   "%d shot(s), %dx%d padded cells, %d steps, dt %.3g s, f0 %.3g Hz, "
+                   "%d receivers, checkpoints every %d steps" % (
+                       len(w.shots), w.shots[0].NR, w.shots[0].NZ, w.shots[0].nt,
+                       w.shots[0].dt, w.shots[0].f0, len(w.shots[0].rec_k),
+                       z.ckpt_every)),
+                   "cell_steps_per_iteration": int(z.cell_steps),
+                   "tune": {"rows_per_wave": r, "waves_per_block": wpb, "graph": ug}},
+        "roofline": roofline,
+        "iteration_hbm_frac_at_220B": round(it_frac, 4),
+        "shots_iters_per_s": round(len(w.shots) / (ms * 1e-3), 4),
+        "kernels": kernels,
+        "cpu_baseline": base,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

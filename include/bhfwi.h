@@ -82,11 +82,27 @@ typedef struct {
     int32_t work_items;       /* wave work items per time step */
 } bhfwi_sizes_t;
 
-/* Tunables of the wave-march kernels (all shapes valid; see bhfwi_autotune). */
+/* Tunables of the wave-march kernels (every value in range is correct; only
+ * speed changes).  rows_per_wave <= 4 selects kernels that issue all loads of
+ * a wave before computing. */
 typedef struct {
     int32_t rows_per_wave;    /* radial rows one wave marches per launch, >= 1 */
     int32_t waves_per_block;  /* 1, 2, 4 or 8 wave64 per workgroup */
+    int32_t use_graph;        /* 1: capture each call's launch sequence once per
+                                 set of pointers as a HIP graph and replay it;
+                                 0: launch step by step from the host */
+    int32_t time_kernels;     /* 1 (with use_graph 0): bracket every time-step
+                                 kernel with a pair of HIP events on its stream;
+                                 read the sums with bhfwi_kernel_times */
 } bhfwi_tune;
+
+/* Per-kernel time sums collected while tune.time_kernels is on: the forward
+ * step of bhfwi_fwd_model, the recompute step (forward step storing v) and
+ * the adjoint step of bhfwi_adjoint_model.  Synchronises the device. */
+typedef struct {
+    double fwd_ms, rec_ms, adj_ms;
+    int64_t fwd_launches, rec_launches, adj_launches;
+} bhfwi_kernel_times_t;
 
 /* Create a context for a survey: a set of shots over one global model of
  * model_len elements.  rec_k (host, nrec_total entries) holds the receiver
@@ -106,6 +122,8 @@ const char *bhfwi_last_error(const bhfwi_ctx *ctx);
 int bhfwi_sizes(const bhfwi_ctx *ctx, bhfwi_sizes_t *out);
 int bhfwi_set_tune(bhfwi_ctx *ctx, const bhfwi_tune *tune);
 int bhfwi_get_tune(const bhfwi_ctx *ctx, bhfwi_tune *out);
+/* Read (and with reset != 0 clear) the sums of bhfwi_kernel_times_t. */
+int bhfwi_kernel_times(bhfwi_ctx *ctx, bhfwi_kernel_times_t *out, int32_t reset);
 
 /* Eq. 3-4 (Method section): lam = rho vp^2 - 2 rho vs^2, mu = rho vs^2,
  * n elements, device arrays. */

@@ -43,7 +43,14 @@ class Sizes(C.Structure):
 
 
 class Tune(C.Structure):
-    _fields_ = [("rows_per_wave", C.c_int32), ("waves_per_block", C.c_int32)]
+    _fields_ = [("rows_per_wave", C.c_int32), ("waves_per_block", C.c_int32),
+                ("use_graph", C.c_int32), ("time_kernels", C.c_int32)]
+
+
+class KernelTimes(C.Structure):
+    _fields_ = [("fwd_ms", C.c_double), ("rec_ms", C.c_double), ("adj_ms", C.c_double),
+                ("fwd_launches", C.c_int64), ("rec_launches", C.c_int64),
+                ("adj_launches", C.c_int64)]
 
 
 class Bounds(C.Structure):
@@ -52,7 +59,7 @@ class Bounds(C.Structure):
 
 
 EXPORTS = ["bhfwi_create", "bhfwi_destroy", "bhfwi_last_error", "bhfwi_sizes",
-           "bhfwi_set_tune", "bhfwi_get_tune", "bhfwi_moduli", "bhfwi_velocities",
+           "bhfwi_set_tune", "bhfwi_get_tune", "bhfwi_kernel_times", "bhfwi_moduli", "bhfwi_velocities",
            "bhfwi_fwd_model", "bhfwi_misfit", "bhfwi_adjoint_model", "bhfwi_gradient",
            "bhfwi_precondition", "bhfwi_update"]
 
@@ -77,6 +84,7 @@ def load(path: str = LIB_PATH):
     L.bhfwi_sizes.argtypes = [P, C.POINTER(Sizes)]
     L.bhfwi_set_tune.argtypes = [P, C.POINTER(Tune)]
     L.bhfwi_get_tune.argtypes = [P, C.POINTER(Tune)]
+    L.bhfwi_kernel_times.argtypes = [P, C.POINTER(KernelTimes), I32]
     L.bhfwi_moduli.argtypes = [V, I64, P, P, P, P, P]
     L.bhfwi_velocities.argtypes = [V, I64, P, P, P, P, P]
     L.bhfwi_fwd_model.argtypes = [P, V, P, P, P, P, P, P, I64, P, I64, I32]
@@ -120,17 +128,17 @@ def _check(rc, ctx=None):
         raise BhfwiError(rc, msg.decode() if msg else "")
 
 
-def moduli(vp, vs, rho):
+def moduli(vp, vs, rho, out=None):
     """Eq. 3-4 on device tensors."""
-    lam, mu = torch.empty_like(vp), torch.empty_like(vp)
+    lam, mu = out if out is not None else (torch.empty_like(vp), torch.empty_like(vp))
     _check(load().bhfwi_moduli(_stream(), vp.numel(), _f32(vp), _f32(vs), _f32(rho),
                                _f32(lam), _f32(mu)))
     return lam, mu
 
 
-def velocities(lam, mu, rho):
+def velocities(lam, mu, rho, out=None):
     """Eq. 11-12 on device tensors."""
-    vp, vs = torch.empty_like(lam), torch.empty_like(lam)
+    vp, vs = out if out is not None else (torch.empty_like(lam), torch.empty_like(lam))
     _check(load().bhfwi_velocities(_stream(), lam.numel(), _f32(lam), _f32(mu), _f32(rho),
                                    _f32(vp), _f32(vs)))
     return vp, vs
@@ -177,15 +185,22 @@ class Survey:
             self._h = None
 
     # ---------------------------------------------------------------- tuning
-    def set_tune(self, rows_per_wave, waves_per_block=4):
-        t = Tune(int(rows_per_wave), int(waves_per_block))
+    def set_tune(self, rows_per_wave, waves_per_block=4, use_graph=1, time_kernels=0):
+        t = Tune(int(rows_per_wave), int(waves_per_block), int(use_graph), int(time_kernels))
         _check(load().bhfwi_set_tune(self._h, C.byref(t)), self._h)
         _check(load().bhfwi_sizes(self._h, C.byref(self.sizes)), self._h)
 
     def get_tune(self):
         t = Tune()
         _check(load().bhfwi_get_tune(self._h, C.byref(t)), self._h)
-        return t.rows_per_wave, t.waves_per_block
+        return t.rows_per_wave, t.waves_per_block, t.use_graph, t.time_kernels
+
+    def kernel_times(self, reset=True):
+        """Sums of the per-launch event timings of the instrumented mode."""
+        o = KernelTimes()
+        _check(load().bhfwi_kernel_times(self._h, C.byref(o), int(reset)), self._h)
+        return {"fwd": (o.fwd_ms, o.fwd_launches), "rec": (o.rec_ms, o.rec_launches),
+                "adj": (o.adj_ms, o.adj_launches)}
 
     # ------------------------------------------------------------ workspaces
     def workspace(self, name):

@@ -35,7 +35,7 @@ struct bhfwi_ctx {
     std::vector<ShotDev> sd;
     int64_t cells = 0, fst_len = 0, ast_len = 0, trace_len = 0, wave_len = 0, cell_steps = 0;
     int nt_max = 0, nseg = 0;
-    bhfwi_tune tune{16, 4};
+    bhfwi_tune tune{16, 4, 1, 0};
     std::vector<int4> work;
     std::vector<int> work_nt;  // nt of each work item's shot, non-increasing
     ShotDev* d_shots = nullptr;
@@ -44,6 +44,15 @@ struct bhfwi_ctx {
     float* d_pml_z = nullptr;
     int4* d_work = nullptr;
     void* d_scratch = nullptr;
+    hipStream_t cap_stream = nullptr;  // private stream that graphs are captured on
+    struct Graph {
+        std::vector<uintptr_t> key;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;  // small cache, most recent last
+    // per-launch event pairs of the instrumented mode: kind 0 fwd, 1 rec, 2 adj
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, int>> ev_used;  // (kind, index of the start event)
     std::string err;
 };
 
@@ -154,16 +163,110 @@ void launch_fill(hipStream_t st, float* p, int64_t n, float v)
     hipLaunchKernelGGL(bhfwi::k_fill, dim3(grid1d(n)), dim3(256), 0, st, p, (long long)n, v);
 }
 
-int fwd_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const float* mu,
-               const float* rho, const float* wav, const float* in, float* out, float* traces,
-               float* hist)
+// Chunks of up to 4 rows use the kernels that issue every load up front.
+#define BHFWI_DISPATCH(R, KER, ...)                                                         \
+    do {                                                                                    \
+        switch (R) {                                                                        \
+        case 1: hipLaunchKernelGGL(KER<1>, __VA_ARGS__); break;                             \
+        case 2: hipLaunchKernelGGL(KER<2>, __VA_ARGS__); break;                             \
+        case 3: hipLaunchKernelGGL(KER<3>, __VA_ARGS__); break;                             \
+        case 4: hipLaunchKernelGGL(KER<4>, __VA_ARGS__); break;                             \
+        default: hipLaunchKernelGGL(KER<0>, __VA_ARGS__); break;                            \
+        }                                                                                   \
+    } while (0)
+
+// Instrumented mode: an event pair around one launch (events are pooled).
+struct EvScope {
+    bhfwi_ctx* c;
+    hipStream_t st;
+    int idx = -1;
+    EvScope(bhfwi_ctx* c_, hipStream_t st_, int kind) : c(c_), st(st_)
+    {
+        if (!c->tune.time_kernels || c->tune.use_graph) return;
+        idx = (int)(2 * c->ev_used.size());
+        while ((int)c->ev_pool.size() < idx + 2) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) {
+                idx = -1;
+                return;
+            }
+            c->ev_pool.push_back(e);
+        }
+        c->ev_used.push_back({kind, idx});
+        (void)hipEventRecord(c->ev_pool[idx], st);
+    }
+    ~EvScope()
+    {
+        if (idx >= 0) (void)hipEventRecord(c->ev_pool[idx + 1], st);
+    }
+};
+
+void fwd_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const float* mu,
+                const float* rho, const float* wav, const float* in, float* out, float* traces,
+                float* hist)
 {
     const int nact = active_items(c, n);
-    if (nact <= 0) return BHFWI_OK;
+    if (nact <= 0) return;
     const int wpb = c->tune.waves_per_block;
-    hipLaunchKernelGGL(bhfwi::k_fwd_step, dim3((nact + wpb - 1) / wpb), dim3(64 * wpb), 0, st,
-                       c->d_shots, c->d_work, nact, n, lam, mu, rho, wav, c->d_rec, c->d_pml_r,
-                       c->d_pml_z, in, out, traces, hist, (long long)c->cells);
+    EvScope ev(c, st, hist ? 1 : 0);
+    BHFWI_DISPATCH(c->tune.rows_per_wave, bhfwi::k_fwd_step, dim3((nact + wpb - 1) / wpb),
+                   dim3(64 * wpb), 0, st, c->d_shots, c->d_work, nact, n, lam, mu, rho, wav,
+                   c->d_rec, c->d_pml_r, c->d_pml_z, in, out, traces, hist, (long long)c->cells);
+}
+
+void adj_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const float* mu,
+                const float* rho, const float* resid, const float* in, float* out,
+                const float* hist, float* acc)
+{
+    const int nact = active_items(c, n);
+    if (nact <= 0) return;
+    const int wpb = c->tune.waves_per_block;
+    EvScope ev(c, st, 2);
+    BHFWI_DISPATCH(c->tune.rows_per_wave, bhfwi::k_adj_step, dim3((nact + wpb - 1) / wpb),
+                   dim3(64 * wpb), 0, st, c->d_shots, c->d_work, nact, n, lam, mu, rho, c->d_rec,
+                   resid, c->d_pml_r, c->d_pml_z, in, out, hist, acc, (long long)c->cells);
+}
+
+void clear_graphs(bhfwi_ctx* c)
+{
+    for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+}
+
+// Run `record(stream)` directly, or -- with graphs on -- capture it once per
+// key on the context's private stream and replay the instantiated graph on st.
+template <class F>
+int run_sequence(bhfwi_ctx* c, hipStream_t st, std::vector<uintptr_t> key, F&& record)
+{
+    if (!c->tune.use_graph) {
+        record(st);
+        HIPOK(c, hipGetLastError());
+        return BHFWI_OK;
+    }
+    key.push_back((uintptr_t)c->tune.rows_per_wave);
+    key.push_back((uintptr_t)c->tune.waves_per_block);
+    for (size_t g = 0; g < c->graphs.size(); ++g)
+        if (c->graphs[g].key == key) {
+            HIPOK(c, hipGraphLaunch(c->graphs[g].exec, st));
+            return BHFWI_OK;
+        }
+    if (!c->cap_stream) HIPOK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIPOK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+    record(c->cap_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+    if (e != hipSuccess || !graph)
+        return fail(c, BHFWI_EHIP, "graph capture: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(c, BHFWI_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+    if (c->graphs.size() >= 6) {
+        (void)hipGraphExecDestroy(c->graphs.front().exec);
+        c->graphs.erase(c->graphs.begin());
+    }
+    c->graphs.push_back({std::move(key), exec});
+    HIPOK(c, hipGraphLaunch(exec, st));
     return BHFWI_OK;
 }
 
@@ -296,6 +399,7 @@ int bhfwi_create(bhfwi_ctx** out, int32_t hip_device, const bhfwi_shot* shots, i
     c->nseg = (c->nt_max + ckpt_every - 1) / ckpt_every;
     c->tune.rows_per_wave = default_rows(c);
     c->tune.waves_per_block = 4;
+    c->tune.use_graph = 1;
     rebuild_work(c);
 
     hipError_t e = hipSetDevice(hip_device);
@@ -326,6 +430,9 @@ void bhfwi_destroy(bhfwi_ctx* c)
 {
     if (!c) return;
     (void)hipSetDevice(c->device);
+    clear_graphs(c);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->d_shots) (void)hipFree(c->d_shots);
     if (c->d_rec) (void)hipFree(c->d_rec);
     if (c->d_pml_r) (void)hipFree(c->d_pml_r);
@@ -362,15 +469,41 @@ int bhfwi_sizes(const bhfwi_ctx* c, bhfwi_sizes_t* o)
 int bhfwi_set_tune(bhfwi_ctx* c, const bhfwi_tune* t)
 {
     if (!c || !t) return BHFWI_EINVAL;
-    if (t->rows_per_wave < 1 ||
+    if (t->rows_per_wave < 1 || t->use_graph < 0 || t->use_graph > 1 || t->time_kernels < 0 ||
+        t->time_kernels > 1 ||
         !(t->waves_per_block == 1 || t->waves_per_block == 2 || t->waves_per_block == 4 ||
           t->waves_per_block == 8))
         return fail(c, BHFWI_EINVAL, "bad tune (rows %d, waves/block %d)", t->rows_per_wave,
                     t->waves_per_block);
     if (int rc = check_ctx(c)) return rc;
+    HIPOK(c, hipDeviceSynchronize());  // no replay may still read the old work table
+    clear_graphs(c);
     c->tune = *t;
     rebuild_work(c);
     return upload_work(c);
+}
+
+int bhfwi_kernel_times(bhfwi_ctx* c, bhfwi_kernel_times_t* o, int32_t reset)
+{
+    if (int rc = check_ctx(c)) return rc;
+    if (!o) return fail(c, BHFWI_EINVAL, "kernel_times: null output");
+    HIPOK(c, hipDeviceSynchronize());
+    double ms[3] = {0, 0, 0};
+    int64_t cnt[3] = {0, 0, 0};
+    for (auto& u : c->ev_used) {
+        float t = 0.f;
+        HIPOK(c, hipEventElapsedTime(&t, c->ev_pool[u.second], c->ev_pool[u.second + 1]));
+        ms[u.first] += t;
+        cnt[u.first] += 1;
+    }
+    o->fwd_ms = ms[0];
+    o->rec_ms = ms[1];
+    o->adj_ms = ms[2];
+    o->fwd_launches = cnt[0];
+    o->rec_launches = cnt[1];
+    o->adj_launches = cnt[2];
+    if (reset) c->ev_used.clear();
+    return BHFWI_OK;
 }
 
 int bhfwi_get_tune(const bhfwi_ctx* c, bhfwi_tune* o)
@@ -418,18 +551,22 @@ int bhfwi_fwd_model(bhfwi_ctx* c, void* stream, const float* lam, const float* m
                     (long long)z.ckpt_bytes);
     hipStream_t st = (hipStream_t)stream;
     float* b[2] = {(float*)fwd_ws, (float*)fwd_ws + c->fst_len};
-    launch_fill(st, b[0], 2 * c->fst_len, 0.0f);
     const int K = c->ckpt_every;
-    for (int n = 0; n < c->nt_max; ++n) {
-        fwd_launch(c, st, n, lam, mu, rho, wavelet, b[n & 1], b[(n + 1) & 1], traces, nullptr);
-        if (store && (n + 1) % K == 0 && n + 1 < c->nt_max) {
-            float* dst = (float*)ckpt + (int64_t)((n + 1) / K - 1) * c->fst_len;
-            HIPOK(c, hipMemcpyAsync(dst, b[(n + 1) & 1], sizeof(float) * c->fst_len,
-                                    hipMemcpyDeviceToDevice, st));
+    auto record = [&](hipStream_t s) {
+        launch_fill(s, b[0], 2 * c->fst_len, 0.0f);
+        for (int n = 0; n < c->nt_max; ++n) {
+            fwd_launch(c, s, n, lam, mu, rho, wavelet, b[n & 1], b[(n + 1) & 1], traces, nullptr);
+            if (store && (n + 1) % K == 0 && n + 1 < c->nt_max) {
+                float* dst = (float*)ckpt + (int64_t)((n + 1) / K - 1) * c->fst_len;
+                (void)hipMemcpyAsync(dst, b[(n + 1) & 1], sizeof(float) * c->fst_len,
+                                     hipMemcpyDeviceToDevice, s);
+            }
         }
-    }
-    HIPOK(c, hipGetLastError());
-    return BHFWI_OK;
+    };
+    return run_sequence(c, st,
+                        {1, (uintptr_t)lam, (uintptr_t)mu, (uintptr_t)rho, (uintptr_t)wavelet,
+                         (uintptr_t)traces, (uintptr_t)fwd_ws, (uintptr_t)(store ? ckpt : nullptr)},
+                        record);
 }
 
 int bhfwi_misfit(bhfwi_ctx* c, void* stream, const float* traces, const float* observed,
@@ -470,33 +607,32 @@ int bhfwi_adjoint_model(bhfwi_ctx* c, void* stream, const float* lam, const floa
     float* ab[2] = {(float*)adj_ws, (float*)adj_ws + c->ast_len};
     float* hist = (float*)adj_ws + 2 * c->ast_len;
     const int64_t hslot = 2 * c->cells;
-    launch_fill(st, fb[0], 2 * c->fst_len, 0.0f);
-    launch_fill(st, ab[0], 2 * c->ast_len, 0.0f);
-    launch_fill(st, acc, 4 * c->cells, 0.0f);
     const int K = c->ckpt_every;
-    const int wpb = c->tune.waves_per_block;
-    int m = 0;
-    for (int j = c->nseg - 1; j >= 0; --j) {
-        const int n0 = j * K, n1 = std::min(n0 + K, c->nt_max);
-        if (j == 0)
-            launch_fill(st, fb[0], c->fst_len, 0.0f);
-        else
-            HIPOK(c, hipMemcpyAsync(fb[0], (const float*)ckpt + (int64_t)(j - 1) * c->fst_len,
-                                    sizeof(float) * c->fst_len, hipMemcpyDeviceToDevice, st));
-        for (int n = n0; n < n1; ++n)
-            fwd_launch(c, st, n, lam, mu, rho, wavelet, fb[(n - n0) & 1], fb[(n - n0 + 1) & 1],
-                       nullptr, hist + (int64_t)(n - n0) * hslot);
-        for (int n = n1 - 1; n >= n0; --n, ++m) {
-            const int nact = active_items(c, n);
-            if (nact <= 0) continue;
-            hipLaunchKernelGGL(bhfwi::k_adj_step, dim3((nact + wpb - 1) / wpb), dim3(64 * wpb), 0,
-                               st, c->d_shots, c->d_work, nact, n, lam, mu, rho, c->d_rec, resid,
-                               c->d_pml_r, c->d_pml_z, ab[m & 1], ab[(m + 1) & 1],
-                               hist + (int64_t)(n - n0) * hslot, acc, (long long)c->cells);
+    auto record = [&](hipStream_t s) {
+        launch_fill(s, fb[0], 2 * c->fst_len, 0.0f);
+        launch_fill(s, ab[0], 2 * c->ast_len, 0.0f);
+        launch_fill(s, acc, 4 * c->cells, 0.0f);
+        int m = 0;
+        for (int j = c->nseg - 1; j >= 0; --j) {
+            const int n0 = j * K, n1 = std::min(n0 + K, c->nt_max);
+            if (j == 0)
+                launch_fill(s, fb[0], c->fst_len, 0.0f);
+            else
+                (void)hipMemcpyAsync(fb[0], (const float*)ckpt + (int64_t)(j - 1) * c->fst_len,
+                                     sizeof(float) * c->fst_len, hipMemcpyDeviceToDevice, s);
+            for (int n = n0; n < n1; ++n)
+                fwd_launch(c, s, n, lam, mu, rho, wavelet, fb[(n - n0) & 1],
+                           fb[(n - n0 + 1) & 1], nullptr, hist + (int64_t)(n - n0) * hslot);
+            for (int n = n1 - 1; n >= n0; --n, ++m)
+                adj_launch(c, s, n, lam, mu, rho, resid, ab[m & 1], ab[(m + 1) & 1],
+                           hist + (int64_t)(n - n0) * hslot, acc);
         }
-    }
-    HIPOK(c, hipGetLastError());
-    return BHFWI_OK;
+    };
+    return run_sequence(c, st,
+                        {2, (uintptr_t)lam, (uintptr_t)mu, (uintptr_t)rho, (uintptr_t)wavelet,
+                         (uintptr_t)resid, (uintptr_t)fwd_ws, (uintptr_t)ckpt, (uintptr_t)adj_ws,
+                         (uintptr_t)acc},
+                        record);
 }
 
 int bhfwi_gradient(bhfwi_ctx* c, void* stream, const float* mu, const float* acc, float* g_lam,

@@ -46,7 +46,20 @@ __device__ __forceinline__ float mu_harm(float a, float b, float c, float d)
 //   pr*NZ [A: d/dr trr at R, C: d/dr trz at Z, E: d/dr vr at C, H: d/dr vz at S],
 //   then 4 axial PML strips of NR*2pz [B: d/dz trz at R, D: d/dz tzz at Z,
 //   F: d/dz vz at C, G: d/dz vr at S].
+//
+// RU > 0: the wave's chunk has at most RU rows and every load of the chunk
+// (RU + 2 rows) is issued before any arithmetic, so a wave waits for memory
+// once per step instead of once per row -- the form for small grids, where
+// there are too few waves to hide latency.  RU == 0: rows are loaded as the
+// march reaches them (long chunks; latency hidden by occupancy).
 // ---------------------------------------------------------------------------
+struct FRow {
+    float trr, ttt, tzz, trz, lam, mu, rho, vr, vz;
+    float pA, pC, pE, pH;  // radial PML memories at this row (0 outside the layer)
+    float pB, pD, pF, pG;  // axial PML memories at this row (0 outside the layer)
+};
+
+template <int RU>
 __global__ void __launch_bounds__(512)
 k_fwd_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int nwork, int n,
            const float* __restrict__ lam, const float* __restrict__ mu,
@@ -80,8 +93,9 @@ k_fwd_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
     float* __restrict__ Fo = sout + S.fst_off;
     const long long oVR = 0, oVZ = cells, oTRR = 2 * cells, oTTT = 3 * cells, oTZZ = 4 * cells,
                     oTRZ = 5 * cells;
-    const long long oPR = 6 * cells;                       // radial strips
-    const long long oPZ = oPR + 4LL * S.psir_len;          // axial strips
+    const long long LR = S.psir_len, LZ = S.psiz_len;
+    const long long oPR = 6 * cells;     // radial strips
+    const long long oPZ = oPR + 4 * LR;  // axial strips
     const long long mbase = S.model_off + kc;
     const float* __restrict__ prt = pml_r + S.pml_r_off;  // [a_ri | b_ri | a_rh | b_rh] x NR
     const float* __restrict__ pzt = pml_z + S.pml_z_off;  // [a_zi | b_zi | a_zh | b_zh] x NZ
@@ -92,97 +106,95 @@ k_fwd_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
         a_zh = pzt[2 * NZ + k];
         b_zh = pzt[3 * NZ + k];
     }
-    auto ir = [&](int i) { return (long long)(i - nr) * NZ + kc; };      // radial strip index
-    auto iz = [&](int i) { return (long long)i * (2 * pz) + kk; };       // axial strip index
+    auto ir = [&](int i) { return (long long)(i - nr) * NZ + kc; };  // radial strip index
+    auto iz = [&](int i) { return (long long)i * (2 * pz) + kk; };   // axial strip index
 
-    // registers of row i (old state and model) and of the velocities already updated
-    float trr0 = 0.f, ttt0 = 0.f, tzz0 = 0.f, trz0 = 0.f, lam0 = 0.f, mu0 = 0.f, rho0 = 0.f;
-    float vrn0 = 0.f;            // v_r new at R(i)
-    float vznm = 0.f;            // v_z new at Z(i-1)
+    auto load = [&](int i) -> FRow {
+        FRow X;
+        X.trr = X.ttt = X.tzz = X.trz = X.lam = X.mu = X.rho = X.vr = X.vz = 0.f;
+        X.pA = X.pC = X.pE = X.pH = X.pB = X.pD = X.pF = X.pG = 0.f;
+        if (i < 0 || i >= NR) return X;
+        const long long c = (long long)i * NZ + kc;
+        X.trr = ld(Fi, oTRR + c, kin);
+        X.ttt = ld(Fi, oTTT + c, kin);
+        X.tzz = ld(Fi, oTZZ + c, kin);
+        X.trz = ld(Fi, oTRZ + c, kin);
+        X.vr = ld(Fi, oVR + c, kin);
+        X.vz = ld(Fi, oVZ + c, kin);
+        const long long m = mbase + (long long)i * S.model_ld;
+        X.lam = ld(lam, m, kin);
+        X.mu = ld(mu, m, kin);
+        X.rho = ld(rho, m, kin);
+        if (i >= nr) {
+            const long long q = oPR + ir(i);
+            X.pA = ld(Fi, q, kin);
+            X.pC = ld(Fi, q + LR, kin);
+            X.pE = ld(Fi, q + 2 * LR, kin);
+            X.pH = ld(Fi, q + 3 * LR, kin);
+        }
+        if (zp) {
+            const long long q = oPZ + iz(i);
+            X.pB = Fi[q];
+            X.pD = Fi[q + LZ];
+            X.pF = Fi[q + 2 * LZ];
+            X.pG = Fi[q + 3 * LZ];
+        }
+        return X;
+    };
+
+    float vrn0 = 0.f;               // v_r new at R(i)
+    float vznm = 0.f;               // v_z new at Z(i-1)
     float mum = 0.f, mum_kp = 0.f;  // mu at row i-1, columns k and k+1
 
-    if (i0 >= 1) {
-        const int i = i0 - 1;
-        const long long c = (long long)i * NZ + kc;
-        trr0 = ld(Fi, oTRR + c, kin);
-        ttt0 = ld(Fi, oTTT + c, kin);
-        tzz0 = ld(Fi, oTZZ + c, kin);
-        trz0 = ld(Fi, oTRZ + c, kin);
-        const long long m = mbase + (long long)i * S.model_ld;
-        lam0 = ld(lam, m, kin);
-        mu0 = ld(mu, m, kin);
-        rho0 = ld(rho, m, kin);
-    }
-
-    for (int i = i0 - 1; i < i1; ++i) {
+    // One march step: rows i (A) and i+1 (B) of the old state are in registers.
+    auto body = [&](int i, const FRow& A, const FRow& B) {
         const int ip = i + 1;
-        // ---- load row ip
-        float trr1 = 0.f, ttt1 = 0.f, tzz1 = 0.f, trz1 = 0.f, lam1 = 0.f, mu1 = 0.f, rho1 = 0.f,
-              vro1 = 0.f;
-        if (ip < NR) {
-            const long long c = (long long)ip * NZ + kc;
-            trr1 = ld(Fi, oTRR + c, kin);
-            ttt1 = ld(Fi, oTTT + c, kin);
-            tzz1 = ld(Fi, oTZZ + c, kin);
-            trz1 = ld(Fi, oTRZ + c, kin);
-            vro1 = ld(Fi, oVR + c, kin);
-            const long long m = mbase + (long long)ip * S.model_ld;
-            lam1 = ld(lam, m, kin);
-            mu1 = ld(mu, m, kin);
-            rho1 = ld(rho, m, kin);
-        }
         // ---- v_r at R(ip), ip >= 1
         float vrn1 = 0.f;
+        const float trz1_km = sh_up(B.trz);
         if (ip >= 1 && ip < NR) {
-            const float trz1_km = sh_up(trz1);
-            float Dr = (trr1 - trr0) * idr;
-            float Dz = (trz1 - trz1_km) * idz;
+            float Dr = (B.trr - A.trr) * idr;
+            float Dz = (B.trz - trz1_km) * idz;
             const bool st = own && ip < i1;
-            if (ip >= nr) {  // PML memory A (radial, integer position)
-                const long long q = oPR + 0LL * S.psir_len + ir(ip);
-                const float psi = prt[NR + ip] * ld(Fi, q, kin) + prt[ip] * Dr;
-                if (st) Fo[q] = psi;
+            if (ip >= nr) {  // A (radial, integer position)
+                const float psi = prt[NR + ip] * B.pA + prt[ip] * Dr;
+                if (st) Fo[oPR + ir(ip)] = psi;
                 Dr += psi;
             }
-            if (zp) {  // PML memory B (axial, integer position)
-                const long long q = oPZ + 0LL * S.psiz_len + iz(ip);
-                const float psi = b_zi * Fi[q] + a_zi * Dz;
-                if (st) Fo[q] = psi;
+            if (zp) {  // B (axial, integer position)
+                const float psi = b_zi * B.pB + a_zi * Dz;
+                if (st) Fo[oPZ + iz(ip)] = psi;
                 Dz += psi;
             }
-            const float hoop = ((trr1 - ttt1) + (trr0 - ttt0)) * (0.5f / (ip * dr));
-            const float bR = 2.0f / (rho0 + rho1);
-            vrn1 = kin ? vro1 + dt * bR * (Dr + Dz + hoop) : 0.f;
+            const float hoop = ((B.trr - B.ttt) + (A.trr - A.ttt)) * (0.5f / (ip * dr));
+            const float bR = 2.0f / (A.rho + B.rho);
+            vrn1 = kin ? B.vr + dt * bR * (Dr + Dz + hoop) : 0.f;
         }
         // ---- v_z at Z(i), i >= 0
         float vzn0 = 0.f;
-        const float tzz0_kp = sh_dn(tzz0);
-        float rho0_kp = sh_dn(rho0);
-        if (top) rho0_kp = rho0;
+        const float tzz0_kp = sh_dn(A.tzz);
+        float rho0_kp = sh_dn(A.rho);
+        if (top) rho0_kp = A.rho;
         if (i >= 0) {
-            const long long c = (long long)i * NZ + kc;
-            const float vzo = ld(Fi, oVZ + c, kin);
-            float Dr = (trz1 - trz0) * idr;
-            float Dz = (tzz0_kp - tzz0) * idz;
+            float Dr = (B.trz - A.trz) * idr;
+            float Dz = (tzz0_kp - A.tzz) * idz;
             const bool st = own && i >= i0;
             if (i >= nr) {  // C (radial, half position)
-                const long long q = oPR + 1LL * S.psir_len + ir(i);
-                const float psi = prt[3 * NR + i] * ld(Fi, q, kin) + prt[2 * NR + i] * Dr;
-                if (st) Fo[q] = psi;
+                const float psi = prt[3 * NR + i] * A.pC + prt[2 * NR + i] * Dr;
+                if (st) Fo[oPR + LR + ir(i)] = psi;
                 Dr += psi;
             }
             if (zp) {  // D (axial, half position)
-                const long long q = oPZ + 1LL * S.psiz_len + iz(i);
-                const float psi = b_zh * Fi[q] + a_zh * Dz;
-                if (st) Fo[q] = psi;
+                const float psi = b_zh * A.pD + a_zh * Dz;
+                if (st) Fo[oPZ + LZ + iz(i)] = psi;
                 Dz += psi;
             }
-            const float hoop = (trz1 + trz0) * (0.5f / ((i + 0.5f) * dr));
-            const float bZ = 2.0f / (rho0 + rho0_kp);
-            vzn0 = kin ? vzo + dt * bZ * (Dr + Dz + hoop) : 0.f;
+            const float hoop = (B.trz + A.trz) * (0.5f / ((i + 0.5f) * dr));
+            const float bZ = 2.0f / (A.rho + rho0_kp);
+            vzn0 = kin ? A.vz + dt * bZ * (Dr + Dz + hoop) : 0.f;
         }
-        float mu0_kp = sh_dn(mu0);
-        if (top) mu0_kp = mu0;
+        float mu0_kp = sh_dn(A.mu);
+        if (top) mu0_kp = A.mu;
         const float vzn0_km = sh_up(vzn0);
         const float vrn0_kp = sh_dn(vrn0);
         if (i >= i0) {
@@ -192,21 +204,19 @@ k_fwd_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
             const float ett = (vrn1 + vrn0) * (0.5f / ((i + 0.5f) * dr));
             float ezz = (vzn0 - vzn0_km) * idz;
             if (i >= nr) {  // E
-                const long long q = oPR + 2LL * S.psir_len + ir(i);
-                const float psi = prt[3 * NR + i] * ld(Fi, q, kin) + prt[2 * NR + i] * err;
-                if (own) Fo[q] = psi;
+                const float psi = prt[3 * NR + i] * A.pE + prt[2 * NR + i] * err;
+                if (own) Fo[oPR + 2 * LR + ir(i)] = psi;
                 err += psi;
             }
             if (zp) {  // F
-                const long long q = oPZ + 2LL * S.psiz_len + iz(i);
-                const float psi = b_zi * Fi[q] + a_zi * ezz;
-                if (own) Fo[q] = psi;
+                const float psi = b_zi * A.pF + a_zi * ezz;
+                if (own) Fo[oPZ + 2 * LZ + iz(i)] = psi;
                 ezz += psi;
             }
             const float tr = err + ett + ezz;
-            float nrr = trr0 + dt * (lam0 * tr + 2.0f * mu0 * err);
-            float ntt = ttt0 + dt * (lam0 * tr + 2.0f * mu0 * ett);
-            float nzz = tzz0 + dt * (lam0 * tr + 2.0f * mu0 * ezz);
+            float nrr = A.trr + dt * (A.lam * tr + 2.0f * A.mu * err);
+            float ntt = A.ttt + dt * (A.lam * tr + 2.0f * A.mu * ett);
+            float nzz = A.tzz + dt * (A.lam * tr + 2.0f * A.mu * ezz);
             if (i == 0 && k == S.src_k) {
                 const float s = S.src_scale * wavelet[S.wave_off + n];
                 nrr += s;
@@ -219,18 +229,16 @@ k_fwd_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
                 float ez = (vrn0_kp - vrn0) * idz;
                 float er = (vzn0 - vznm) * idr;
                 if (zp) {  // G
-                    const long long q = oPZ + 3LL * S.psiz_len + iz(i);
-                    const float psi = b_zh * Fi[q] + a_zh * ez;
-                    if (own) Fo[q] = psi;
+                    const float psi = b_zh * A.pG + a_zh * ez;
+                    if (own) Fo[oPZ + 3 * LZ + iz(i)] = psi;
                     ez += psi;
                 }
                 if (i >= nr) {  // H
-                    const long long q = oPR + 3LL * S.psir_len + ir(i);
-                    const float psi = prt[NR + i] * ld(Fi, q, kin) + prt[i] * er;
-                    if (own) Fo[q] = psi;
+                    const float psi = prt[NR + i] * A.pH + prt[i] * er;
+                    if (own) Fo[oPR + 3 * LR + ir(i)] = psi;
                     er += psi;
                 }
-                nrz = trz0 + dt * mu_harm(mum, mu0, mum_kp, mu0_kp) * (ez + er);
+                nrz = A.trz + dt * mu_harm(mum, A.mu, mum_kp, mu0_kp) * (ez + er);
             }
             if (own) {
                 if (i >= 1) {
@@ -253,18 +261,26 @@ k_fwd_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
                 }
             }
         }
-        // ---- rotate
-        mum = mu0;
+        mum = A.mu;
         mum_kp = mu0_kp;
-        trr0 = trr1;
-        ttt0 = ttt1;
-        tzz0 = tzz1;
-        trz0 = trz1;
-        lam0 = lam1;
-        mu0 = mu1;
-        rho0 = rho1;
         vrn0 = vrn1;
         vznm = vzn0;
+    };
+
+    if constexpr (RU > 0) {
+        FRow rows[RU + 2];
+#pragma unroll
+        for (int q = 0; q < RU + 2; ++q) rows[q] = load(i0 - 1 + q <= i1 ? i0 - 1 + q : -1);
+#pragma unroll
+        for (int q = 0; q < RU + 1; ++q)
+            if (i0 - 1 + q < i1) body(i0 - 1 + q, rows[q], rows[q + 1]);
+    } else {
+        FRow A = load(i0 - 1);
+        for (int i = i0 - 1; i < i1; ++i) {
+            const FRow B = load(i + 1);
+            body(i, A, B);
+            A = B;
+        }
     }
 }
 
@@ -280,13 +296,20 @@ k_fwd_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
 // part of the correlation, so the gradient is exact in the PML too while only
 // the velocities are stored from the forward pass.
 // ---------------------------------------------------------------------------
-struct ARow {
-    float trr, ttt, tzz, trz;     // adjoint stresses (residual injected)
-    float lam, mu, rho, mu_kp;    // model at this row (mu_kp: column k+1, clamped)
-    float Err, Ett, Ezz, Ez, Er;  // drivers of the transposed stress update
+struct ARaw {  // everything read from memory for one row
+    float trr, ttt, tzz, trz, lam, mu, rho, avr, avz, vrh, vzh;
+    float qA, qC, qTr, qRr, qH;  // radial strips (old)
+    float qB, qD, qTz, qZz, qG;  // axial strips (old)
+    float gl, gm, gs, ge;        // accumulators (rows of the chunk only)
+};
+struct ARow {  // derived from ARaw and the previous row's rigidity
+    float trr, ttt, tzz, trz;          // adjoint stresses (residual injected)
+    float rho, mu, mu_kp;              // model (mu_kp: column k+1, clamped)
+    float Err, Ett, Ezz, Ez, Er;       // drivers of the transposed stress update
     float pTr, pRr, pTz, pZz, pG, pH;  // new Phi values (0 outside the PML)
 };
 
+template <int RU>
 __global__ void __launch_bounds__(512)
 k_adj_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int nwork, int n,
            const float* __restrict__ lam, const float* __restrict__ mu,
@@ -320,8 +343,9 @@ k_adj_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
     float* __restrict__ Ao = aout + S.ast_off;
     const long long oVR = 0, oVZ = cells, oTRR = 2 * cells, oTTT = 3 * cells, oTZZ = 4 * cells,
                     oTRZ = 5 * cells;
+    const long long LR = S.psir_len, LZ = S.psiz_len;
     const long long oPR = 6 * cells;
-    const long long oPZ = oPR + 5LL * S.psir_len;
+    const long long oPZ = oPR + 5 * LR;
     const long long mbase = S.model_off + kc;
     const float* __restrict__ prt = pml_r + S.pml_r_off;
     const float* __restrict__ pzt = pml_z + S.pml_z_off;
@@ -348,126 +372,142 @@ k_adj_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
     float* __restrict__ g_s = acc + 2 * cells_total + S.cell_off;
     float* __restrict__ g_e = acc + 3 * cells_total + S.cell_off;
 
-    // Load row ip of the adjoint state and model, compute the drivers of the
-    // transposed stress update and the new Phi values.  mu_prev/_kp: row ip-1.
-    auto load_row = [&](int ip, float mu_prev, float mu_prev_kp, bool store) -> ARow {
-        ARow X{};
-        X.pTr = X.pRr = X.pTz = X.pZz = X.pG = X.pH = 0.f;
-        if (ip < 0 || ip >= NR) {
-            X.mu_kp = 0.f;
-            return X;
-        }
-        const long long c = (long long)ip * NZ + kc;
+    auto load = [&](int i) -> ARaw {
+        ARaw X;
+        X.trr = X.ttt = X.tzz = X.trz = X.lam = X.mu = X.rho = X.avr = X.avz = X.vrh = X.vzh = 0.f;
+        X.qA = X.qC = X.qTr = X.qRr = X.qH = X.qB = X.qD = X.qTz = X.qZz = X.qG = 0.f;
+        X.gl = X.gm = X.gs = X.ge = 0.f;
+        if (i < 0 || i >= NR) return X;
+        const long long c = (long long)i * NZ + kc;
         X.trr = ld(Ai, oTRR + c, kin);
         X.ttt = ld(Ai, oTTT + c, kin);
         X.tzz = ld(Ai, oTZZ + c, kin);
-        X.trz = (ip >= 1) ? ld(Ai, oTRZ + c, kin) : 0.f;
+        if (i >= 1) X.trz = ld(Ai, oTRZ + c, kin);
+        X.avr = ld(Ai, oVR + c, kin);
+        X.avz = ld(Ai, oVZ + c, kin);
+        const long long m = mbase + (long long)i * S.model_ld;
+        X.lam = ld(lam, m, kin);
+        X.mu = ld(mu, m, kin);
+        X.rho = ld(rho, m, kin);
+        X.vrh = ld(vrh, c, kin);
+        X.vzh = ld(vzh, c, kin);
+        if (i >= nr) {
+            const long long q = oPR + ir(i);
+            X.qA = ld(Ai, q, kin);
+            X.qC = ld(Ai, q + LR, kin);
+            X.qTr = ld(Ai, q + 2 * LR, kin);
+            X.qRr = ld(Ai, q + 3 * LR, kin);
+            X.qH = ld(Ai, q + 4 * LR, kin);
+        }
+        if (zp) {
+            const long long q = oPZ + iz(i);
+            X.qB = Ai[q];
+            X.qD = Ai[q + LZ];
+            X.qTz = Ai[q + 2 * LZ];
+            X.qZz = Ai[q + 3 * LZ];
+            X.qG = Ai[q + 4 * LZ];
+        }
+        if (i >= i0 && i < i1) {
+            X.gl = ld(g_l, c, own);
+            X.gm = ld(g_m, c, own);
+            X.gs = ld(g_s, c, own);
+            X.ge = ld(g_e, c, own);
+        }
+        return X;
+    };
+
+    // Drivers of the transposed stress update at row ip and the new Phi values.
+    // mu_prev/_kp: rigidity of row ip-1.
+    auto derive = [&](int ip, const ARaw& R, float mu_prev, float mu_prev_kp,
+                      bool store) -> ARow {
+        ARow X;
+        X.trr = R.trr;
+        X.ttt = R.ttt;
+        X.tzz = R.tzz;
+        X.trz = R.trz;
+        X.rho = R.rho;
+        X.mu = R.mu;
+        X.pTr = X.pRr = X.pTz = X.pZz = X.pG = X.pH = 0.f;
+        X.mu_kp = sh_dn(R.mu);
+        if (top) X.mu_kp = R.mu;
+        X.Err = X.Ett = X.Ezz = X.Ez = X.Er = 0.f;
+        if (ip < 0 || ip >= NR) return X;
         if (ip == 0) {
             X.trr += inj;
             X.ttt += inj;
             X.tzz += inj;
         }
-        const long long m = mbase + (long long)ip * S.model_ld;
-        X.lam = ld(lam, m, kin);
-        X.mu = ld(mu, m, kin);
-        X.rho = ld(rho, m, kin);
-        X.mu_kp = sh_dn(X.mu);
-        if (top) X.mu_kp = X.mu;
         const float sa = X.trr + X.ttt + X.tzz;
-        const float l = X.lam, mm2 = 2.0f * X.mu;
+        const float l = R.lam, mm2 = 2.0f * R.mu;
         X.Err = dt * (l * sa + mm2 * X.trr);
         X.Ett = dt * (l * sa + mm2 * X.ttt);
         X.Ezz = dt * (l * sa + mm2 * X.tzz);
         if (ip >= nr) {  // PhiT_r, PhiR_r at C (radial, half position)
             const float b = prt[3 * NR + ip], a = prt[2 * NR + ip];
-            const long long qT = oPR + 2LL * S.psir_len + ir(ip);
-            const long long qR = oPR + 3LL * S.psir_len + ir(ip);
-            X.pTr = dt * sa + b * ld(Ai, qT, kin);
-            X.pRr = dt * X.trr + b * ld(Ai, qR, kin);
+            X.pTr = dt * sa + b * R.qTr;
+            X.pRr = dt * X.trr + b * R.qRr;
             if (store) {
-                Ao[qT] = X.pTr;
-                Ao[qR] = X.pRr;
+                Ao[oPR + 2 * LR + ir(ip)] = X.pTr;
+                Ao[oPR + 3 * LR + ir(ip)] = X.pRr;
             }
             X.Err += a * (l * X.pTr + mm2 * X.pRr);
         }
         if (zp) {  // PhiT_z, PhiZ_z at C (axial, integer position)
-            const long long qT = oPZ + 2LL * S.psiz_len + iz(ip);
-            const long long qZ = oPZ + 3LL * S.psiz_len + iz(ip);
-            X.pTz = dt * sa + b_zi * Ai[qT];
-            X.pZz = dt * X.tzz + b_zi * Ai[qZ];
+            X.pTz = dt * sa + b_zi * R.qTz;
+            X.pZz = dt * X.tzz + b_zi * R.qZz;
             if (store) {
-                Ao[qT] = X.pTz;
-                Ao[qZ] = X.pZz;
+                Ao[oPZ + 2 * LZ + iz(ip)] = X.pTz;
+                Ao[oPZ + 3 * LZ + iz(ip)] = X.pZz;
             }
             X.Ezz += a_zi * (l * X.pTz + mm2 * X.pZz);
         }
-        X.Ez = 0.f;
-        X.Er = 0.f;
         if (ip >= 1) {
-            const float muS = mu_harm(mu_prev, X.mu, mu_prev_kp, X.mu_kp);
+            const float muS = mu_harm(mu_prev, R.mu, mu_prev_kp, X.mu_kp);
             const float s = dt * muS * X.trz;
             X.Ez = s;
             X.Er = s;
             if (zp) {  // PhiG at S (axial, half position)
-                const long long q = oPZ + 4LL * S.psiz_len + iz(ip);
-                X.pG = dt * X.trz + b_zh * Ai[q];
-                if (store) Ao[q] = X.pG;
+                X.pG = dt * X.trz + b_zh * R.qG;
+                if (store) Ao[oPZ + 4 * LZ + iz(ip)] = X.pG;
                 X.Ez += a_zh * muS * X.pG;
             }
             if (ip >= nr) {  // PhiH at S (radial, integer position)
-                const long long q = oPR + 4LL * S.psir_len + ir(ip);
-                X.pH = dt * X.trz + prt[NR + ip] * ld(Ai, q, kin);
-                if (store) Ao[q] = X.pH;
+                X.pH = dt * X.trz + prt[NR + ip] * R.qH;
+                if (store) Ao[oPR + 4 * LR + ir(ip)] = X.pH;
                 X.Er += prt[ip] * muS * X.pH;
             }
         }
-        if (!kin) {
-            X.Err = X.Ett = X.Ezz = X.Ez = X.Er = 0.f;
-        }
+        if (!kin) X.Err = X.Ett = X.Ezz = X.Ez = X.Er = 0.f;
         return X;
     };
 
-    ARow X0{};
-    X0.pTr = X0.pRr = X0.pTz = X0.pZz = X0.pG = X0.pH = 0.f;
-    if (i0 >= 1) {
-        float mpp = 0.f, mpp_kp = 0.f;
-        if (i0 >= 2) {
-            mpp = ld(mu, mbase + (long long)(i0 - 2) * S.model_ld, kin);
-            mpp_kp = sh_dn(mpp);
-            if (top) mpp_kp = mpp;
-        }
-        X0 = load_row(i0 - 1, mpp, mpp_kp, false);
-    }
-    // R(i): [aDr, aDzR, hR]; Z(i-1) contribution to atrz(i): zm
-    float R0_aDr = 0.f, R0_aDzR = 0.f, R0_hR = 0.f, zm = 0.f;
-    float vrh0 = 0.f, vzhm = 0.f;
-    if (i0 >= 1) vrh0 = ld(vrh, (long long)(i0 - 1) * NZ + kc, kin);
+    // carried between rows: R(i) [aDr, aDzR, hR], Z(i-1) contribution zm,
+    // v_z history of row i-1
+    float R0_aDr = 0.f, R0_aDzR = 0.f, R0_hR = 0.f, zm = 0.f, vzhm = 0.f;
 
-    for (int i = i0 - 1; i < i1; ++i) {
+    // One march step: raw rows i (P) and i+1 (Q), derived rows X0 (i), X1 (i+1).
+    auto body = [&](int i, const ARaw& P, const ARaw& Q, const ARow& X0, const ARow& X1) {
         const int ip = i + 1;
         const bool own_ip = own && ip >= i0 && ip < i1;
         const bool own_i = own && i >= i0;
-        const ARow X1 = load_row(ip, X0.mu, X0.mu_kp, own_ip);
         // ---- R(ip): transposed stress update into avr, then transposed velocity update
         float R1_aDr = 0.f, R1_aDzR = 0.f, R1_hR = 0.f;
         const float Ez1_km = sh_up(X1.Ez);
         if (ip >= 1 && ip < NR) {
             const long long c = (long long)ip * NZ + kc;
-            const float avr = ld(Ai, oVR + c, kin) + (X0.Err - X1.Err) * idr +
+            const float avr = Q.avr + (X0.Err - X1.Err) * idr +
                               X0.Ett * (0.5f / ((ip - 0.5f) * dr)) +
                               X1.Ett * (0.5f / ((ip + 0.5f) * dr)) + (Ez1_km - X1.Ez) * idz;
             const float W = kin ? dt * (2.0f / (X0.rho + X1.rho)) * avr : 0.f;
             float aDr = W, aDz = W;
             if (ip >= nr) {  // A-bar
-                const long long q = oPR + 0LL * S.psir_len + ir(ip);
-                const float qv = ld(Ai, q, kin) + W;
-                if (own_ip) Ao[q] = prt[NR + ip] * qv;
+                const float qv = Q.qA + W;
+                if (own_ip) Ao[oPR + ir(ip)] = prt[NR + ip] * qv;
                 aDr += prt[ip] * qv;
             }
             if (zp) {  // B-bar
-                const long long q = oPZ + 0LL * S.psiz_len + iz(ip);
-                const float qv = Ai[q] + W;
-                if (own_ip) Ao[q] = b_zi * qv;
+                const float qv = Q.qB + W;
+                if (own_ip) Ao[oPZ + iz(ip)] = b_zi * qv;
                 aDz += a_zi * qv;
             }
             if (own_ip) Ao[oVR + c] = avr;
@@ -482,20 +522,17 @@ k_adj_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
         if (top) rho0_kp = X0.rho;
         if (i >= 0) {
             const long long c = (long long)i * NZ + kc;
-            const float avz = ld(Ai, oVZ + c, kin) + (X0.Ezz - Ezz0_kp) * idz +
-                              (X0.Er - X1.Er) * idr;
+            const float avz = P.avz + (X0.Ezz - Ezz0_kp) * idz + (X0.Er - X1.Er) * idr;
             const float W = kin ? dt * (2.0f / (X0.rho + rho0_kp)) * avz : 0.f;
             float aDr = W, aDz = W;
             if (i >= nr) {  // C-bar (radial, half position)
-                const long long q = oPR + 1LL * S.psir_len + ir(i);
-                const float qv = ld(Ai, q, kin) + W;
-                if (own_i) Ao[q] = prt[3 * NR + i] * qv;
+                const float qv = P.qC + W;
+                if (own_i) Ao[oPR + LR + ir(i)] = prt[3 * NR + i] * qv;
                 aDr += prt[2 * NR + i] * qv;
             }
             if (zp) {  // D-bar (axial, half position)
-                const long long q = oPZ + 1LL * S.psiz_len + iz(i);
-                const float qv = Ai[q] + W;
-                if (own_i) Ao[q] = b_zh * qv;
+                const float qv = P.qD + W;
+                if (own_i) Ao[oPZ + LZ + iz(i)] = b_zh * qv;
                 aDz += a_zh * qv;
             }
             if (own_i) Ao[oVZ + c] = avz;
@@ -505,9 +542,7 @@ k_adj_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
         }
         const float aDzZ_km = sh_up(Z_aDzZ);
         const float aDzR_kp = sh_dn(R0_aDzR);
-        // ---- velocity history for the correlation at row i
-        const float vrh1 = (ip < NR) ? ld(vrh, (long long)ip * NZ + kc, kin) : 0.f;
-        const float vzh0 = (i >= 0) ? ld(vzh, (long long)i * NZ + kc, kin) : 0.f;
+        const float vrh0 = P.vrh, vrh1 = Q.vrh, vzh0 = P.vzh;
         const float vzh0_km = sh_up(vzh0);
         const float vrh0_kp = sh_dn(vrh0);
         if (i >= i0) {
@@ -551,21 +586,51 @@ k_adj_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
                 Ao[oTZZ + c] = nzz;
                 if (i >= 1) {
                     Ao[oTRZ + c] = nrz;
-                    g_s[c] += dgs;
+                    g_s[c] = P.gs + dgs;
                 }
-                g_l[c] += dgl;
-                g_m[c] += dgm;
-                g_e[c] += dge;
+                g_l[c] = P.gl + dgl;
+                g_m[c] = P.gm + dgm;
+                g_e[c] = P.ge + dge;
             }
         }
-        // ---- rotate
         zm = (i >= 0) ? Z_aDrZ * idr + Z_WZ * (0.5f / ((i + 0.5f) * dr)) : 0.f;
-        X0 = X1;
         R0_aDr = R1_aDr;
         R0_aDzR = R1_aDzR;
         R0_hR = R1_hR;
-        vrh0 = vrh1;
         vzhm = vzh0;
+    };
+
+    // rigidity of row i0-2, needed for the shear drivers of row i0-1
+    float mpp = 0.f, mpp_kp = 0.f;
+    if (i0 >= 2) mpp = ld(mu, mbase + (long long)(i0 - 2) * S.model_ld, kin);
+    mpp_kp = sh_dn(mpp);
+    if (top) mpp_kp = mpp;
+
+    if constexpr (RU > 0) {
+        ARaw raw[RU + 2];
+#pragma unroll
+        for (int q = 0; q < RU + 2; ++q) raw[q] = load(i0 - 1 + q <= i1 ? i0 - 1 + q : -1);
+        ARow X0 = derive(i0 - 1, raw[0], mpp, mpp_kp, false);
+#pragma unroll
+        for (int q = 0; q < RU + 1; ++q) {
+            const int i = i0 - 1 + q;
+            if (i < i1) {
+                const ARow X1 = derive(i + 1, raw[q + 1], X0.mu, X0.mu_kp,
+                                       own && i + 1 >= i0 && i + 1 < i1);
+                body(i, raw[q], raw[q + 1], X0, X1);
+                X0 = X1;
+            }
+        }
+    } else {
+        ARaw P = load(i0 - 1);
+        ARow X0 = derive(i0 - 1, P, mpp, mpp_kp, false);
+        for (int i = i0 - 1; i < i1; ++i) {
+            const ARaw Q = load(i + 1);
+            const ARow X1 = derive(i + 1, Q, X0.mu, X0.mu_kp, own && i + 1 >= i0 && i + 1 < i1);
+            body(i, P, Q, X0, X1);
+            P = Q;
+            X0 = X1;
+        }
     }
 }
 

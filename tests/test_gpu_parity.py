@@ -54,7 +54,7 @@ def oracle_traces(w, s=0, which="start"):
 
 
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("tune", [(1, 1), (3, 2), (4, 4), (16, 4), (64, 8)])
+@pytest.mark.parametrize("tune", [(1, 1, 0), (2, 4, 1), (3, 2, 1), (4, 4, 0), (16, 4, 1), (64, 8, 0)])
 def test_forward_parity_tiny_ragged(tune):
     """NZ = 162 spans three 62-row strips with a ragged tail; NR = 46 is not
     a multiple of the radial chunk."""
@@ -114,7 +114,7 @@ def _regions(sh, shape):
     return {"all": np.ones(shape, bool), "interior": ~(r | z), "pml_r": r, "pml_z": z}
 
 
-@pytest.mark.parametrize("tune", [(1, 1), (5, 4), (64, 8)])
+@pytest.mark.parametrize("tune", [(1, 1, 1), (2, 4, 0), (4, 4, 1), (5, 4, 1), (64, 8, 0)])
 def test_gradient_parity_tiny(tune):
     w = workloads.tiny(nr=40, nz=150, p=6, nt=300)
     _say("grad tiny", tune)
