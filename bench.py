@@ -70,6 +70,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--rows", type=int, default=0, help="rows per wave (0: library default)")
+    ap.add_argument("--tb", type=int, default=-1,
+                    help="forward steps per launch in the LDS-tiled kernels (-1: default)")
+    ap.add_argument("--tb-rows", type=int, default=0)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=120)
@@ -91,11 +94,8 @@ def main():
     log("workload", args.workload, "shots", len(w.shots), "grid", w.shots[0].NR, w.shots[0].NZ,
         "nt", w.shots[0].nt)
     sv = P.Survey(w.shots, (w.NRg, w.NZg), ckpt_every=w.meta.get("ckpt", 250))
-    if args.rows:
-        sv.set_tune(args.rows, 4, 0 if args.no_graph else 1)
-    elif args.no_graph:
-        r, wpb, _, _ = sv.get_tune()
-        sv.set_tune(r, wpb, 0)
+    sv.set_tune(rows_per_wave=args.rows or None, use_graph=0 if args.no_graph else None,
+                tb_steps=args.tb if args.tb >= 0 else None, tb_rows=args.tb_rows or None)
     tune = sv.get_tune()
     rho = f32(w.rho)
     wav = sv.pack_wavelets([s.wavelet for s in w.shots])
@@ -124,12 +124,11 @@ def main():
 
     # per-kernel durations: one more (untimed) iteration with every time-step
     # kernel bracketed by HIP events on the stream it runs on
-    r, wpb, ug, _ = tune
-    sv.set_tune(r, wpb, 0, 1)
+    sv.set_tune(use_graph=0, time_kernels=1)
     sv.kernel_times(reset=True)
     inv.iterate()
     kt = sv.kernel_times(reset=True)
-    sv.set_tune(r, wpb, ug, 0)
+    sv.set_tune(use_graph=tune["use_graph"], time_kernels=0)
     cells = z.cells
     adj_ms, adj_n = kt["adj"]
     fwd_ms, fwd_n = kt["fwd"]
@@ -165,7 +164,7 @@ def main():
                        w.shots[0].dt, w.shots[0].f0, len(w.shots[0].rec_k),
                        z.ckpt_every)),
                    "cell_steps_per_iteration": int(z.cell_steps),
-                   "tune": {"rows_per_wave": r, "waves_per_block": wpb, "graph": ug}},
+                   "tune": tune},
         "roofline": roofline,
         "iteration_hbm_frac_at_220B": round(it_frac, 4),
         "shots_iters_per_s": round(len(w.shots) / (ms * 1e-3), 4),

@@ -94,6 +94,14 @@ typedef struct {
     int32_t time_kernels;     /* 1 (with use_graph 0): bracket every time-step
                                  kernel with a pair of HIP events on its stream;
                                  read the sums with bhfwi_kernel_times */
+    int32_t tb_steps;         /* >= 2: forward, recompute and adjoint steps run
+                                 T = tb_steps at a time in LDS-tiled kernels;
+                                 0 or 1: one step per launch (wave march) */
+    int32_t tb_rows;          /* radial rows of a tile including its halo */
+    int32_t tb_waves;         /* wave64 per tile workgroup (4 or 8).  Supported
+                                 (tb_steps, tb_rows, tb_waves): (2|3|4, 16, 4),
+                                 (2|3|4, 16, 8), (2|3|4|6, 24, 8),
+                                 (4|6|8, 32, 8) */
 } bhfwi_tune;
 
 /* Per-kernel time sums collected while tune.time_kernels is on: the forward

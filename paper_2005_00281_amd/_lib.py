@@ -44,7 +44,8 @@ class Sizes(C.Structure):
 
 class Tune(C.Structure):
     _fields_ = [("rows_per_wave", C.c_int32), ("waves_per_block", C.c_int32),
-                ("use_graph", C.c_int32), ("time_kernels", C.c_int32)]
+                ("use_graph", C.c_int32), ("time_kernels", C.c_int32),
+                ("tb_steps", C.c_int32), ("tb_rows", C.c_int32), ("tb_waves", C.c_int32)]
 
 
 class KernelTimes(C.Structure):
@@ -185,15 +186,24 @@ class Survey:
             self._h = None
 
     # ---------------------------------------------------------------- tuning
-    def set_tune(self, rows_per_wave, waves_per_block=4, use_graph=1, time_kernels=0):
-        t = Tune(int(rows_per_wave), int(waves_per_block), int(use_graph), int(time_kernels))
+    def set_tune(self, rows_per_wave=None, waves_per_block=None, use_graph=None,
+                 time_kernels=None, tb_steps=None, tb_rows=None, tb_waves=None):
+        """Change any subset of the tunables (None keeps the current value)."""
+        cur = Tune()
+        _check(load().bhfwi_get_tune(self._h, C.byref(cur)), self._h)
+        new = {}
+        for name, v in (("rows_per_wave", rows_per_wave), ("waves_per_block", waves_per_block),
+                        ("use_graph", use_graph), ("time_kernels", time_kernels),
+                        ("tb_steps", tb_steps), ("tb_rows", tb_rows), ("tb_waves", tb_waves)):
+            new[name] = int(getattr(cur, name) if v is None else v)
+        t = Tune(**new)
         _check(load().bhfwi_set_tune(self._h, C.byref(t)), self._h)
         _check(load().bhfwi_sizes(self._h, C.byref(self.sizes)), self._h)
 
     def get_tune(self):
         t = Tune()
         _check(load().bhfwi_get_tune(self._h, C.byref(t)), self._h)
-        return t.rows_per_wave, t.waves_per_block, t.use_graph, t.time_kernels
+        return {name: getattr(t, name) for name, _ in Tune._fields_}
 
     def kernel_times(self, reset=True):
         """Sums of the per-launch event timings of the instrumented mode."""

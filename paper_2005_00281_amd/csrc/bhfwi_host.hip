@@ -2,6 +2,8 @@
 // profiles and the launch sequences of the forward, adjoint and update steps.
 #include "bhfwi.h"
 #include "bhfwi_kernels.hip"
+#include "bhfwi_tb_fwd.hip"
+#include "bhfwi_tb_adj.hip"
 
 #include <algorithm>
 #include <cmath>
@@ -35,14 +37,17 @@ struct bhfwi_ctx {
     std::vector<ShotDev> sd;
     int64_t cells = 0, fst_len = 0, ast_len = 0, trace_len = 0, wave_len = 0, cell_steps = 0;
     int nt_max = 0, nseg = 0;
-    bhfwi_tune tune{16, 4, 1, 0};
+    bhfwi_tune tune{16, 4, 1, 0, 0, 16, 4};
     std::vector<int4> work;
     std::vector<int> work_nt;  // nt of each work item's shot, non-increasing
+    std::vector<int4> tiles;   // temporally blocked tiles (shot, k0, i0, i1)
+    std::vector<int> tiles_nt;
     ShotDev* d_shots = nullptr;
     int* d_rec = nullptr;
     float* d_pml_r = nullptr;
     float* d_pml_z = nullptr;
     int4* d_work = nullptr;
+    int4* d_tiles = nullptr;
     void* d_scratch = nullptr;
     hipStream_t cap_stream = nullptr;  // private stream that graphs are captured on
     struct Graph {
@@ -118,6 +123,19 @@ void rebuild_work(bhfwi_ctx* c)
                 c->work_nt.push_back(S.nt);
             }
     }
+    c->tiles.clear();
+    c->tiles_nt.clear();
+    if (c->tune.tb_steps >= 2) {
+        const int T = c->tune.tb_steps, TR = c->tune.tb_rows - 2 * T, TZ = 64 - 2 * T;
+        for (int s : order) {
+            const ShotDev& S = c->sd[s];
+            for (int i0 = 0; i0 < S.NR; i0 += TR)
+                for (int k0 = 0; k0 < S.NZ; k0 += TZ) {
+                    c->tiles.push_back(make_int4(s, k0, i0, std::min(i0 + TR, S.NR)));
+                    c->tiles_nt.push_back(S.nt);
+                }
+        }
+    }
 }
 
 int upload_work(bhfwi_ctx* c)
@@ -126,9 +144,18 @@ int upload_work(bhfwi_ctx* c)
         HIPOK(c, hipFree(c->d_work));
         c->d_work = nullptr;
     }
+    if (c->d_tiles) {
+        HIPOK(c, hipFree(c->d_tiles));
+        c->d_tiles = nullptr;
+    }
     HIPOK(c, hipMalloc(&c->d_work, sizeof(int4) * c->work.size()));
     HIPOK(c, hipMemcpy(c->d_work, c->work.data(), sizeof(int4) * c->work.size(),
                        hipMemcpyHostToDevice));
+    if (!c->tiles.empty()) {
+        HIPOK(c, hipMalloc(&c->d_tiles, sizeof(int4) * c->tiles.size()));
+        HIPOK(c, hipMemcpy(c->d_tiles, c->tiles.data(), sizeof(int4) * c->tiles.size(),
+                           hipMemcpyHostToDevice));
+    }
     return BHFWI_OK;
 }
 
@@ -148,6 +175,13 @@ int active_items(const bhfwi_ctx* c, int n)
     auto it = std::partition_point(c->work_nt.begin(), c->work_nt.end(),
                                    [n](int nt) { return nt > n; });
     return (int)(it - c->work_nt.begin());
+}
+
+int active_tiles(const bhfwi_ctx* c, int n)
+{
+    auto it = std::partition_point(c->tiles_nt.begin(), c->tiles_nt.end(),
+                                   [n](int nt) { return nt > n; });
+    return (int)(it - c->tiles_nt.begin());
 }
 
 int check_ctx(bhfwi_ctx* c)
@@ -227,6 +261,86 @@ void adj_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const flo
                    resid, c->d_pml_r, c->d_pml_z, in, out, hist, acc, (long long)c->cells);
 }
 
+// Supported temporally blocked shapes: (steps T, tile rows incl. halo, waves).
+#define BHFWI_TB_SHAPES(X) \
+    X(2, 16, 4) X(3, 16, 4) X(4, 16, 4) X(2, 16, 8) X(3, 16, 8) X(4, 16, 8) X(2, 24, 8) \
+    X(3, 24, 8) X(4, 24, 8) X(6, 24, 8) X(4, 32, 8) X(6, 32, 8) X(8, 32, 8)
+
+#define BHFWI_TB(TT, RR, WW)                                                                 \
+    if (T == TT && TRE == RR && W == WW) {                                                   \
+        hipLaunchKernelGGL((bhfwi::k_fwd_tb<TT, RR, WW>), dim3(nact), dim3(64 * WW), 0, st,  \
+                           c->d_shots, c->d_tiles, nact, n0, nsteps, lam, mu, rho, wav,      \
+                           c->d_rec, c->d_pml_r, c->d_pml_z, in, out, traces, hist,          \
+                           (long long)(2 * c->cells), (long long)c->cells);                  \
+        return;                                                                              \
+    }
+
+// nsteps (<= tb_steps) forward steps from step n0 in LDS-tiled kernels.
+void fwd_tb_launch(bhfwi_ctx* c, hipStream_t st, int n0, int nsteps, const float* lam,
+                   const float* mu, const float* rho, const float* wav, const float* in,
+                   float* out, float* traces, float* hist)
+{
+    const int nact = active_tiles(c, n0);
+    if (nact <= 0) return;
+    const int T = c->tune.tb_steps, TRE = c->tune.tb_rows, W = c->tune.tb_waves;
+    EvScope ev(c, st, hist ? 1 : 0);
+    BHFWI_TB_SHAPES(BHFWI_TB)
+}
+#undef BHFWI_TB
+
+#define BHFWI_TBA(TT, RR, WW)                                                                \
+    if (T == TT && TRE == RR && W == WW) {                                                   \
+        hipLaunchKernelGGL((bhfwi::k_adj_tb<TT, RR, WW>), dim3(nact), dim3(64 * WW), 0, st,  \
+                           c->d_shots, c->d_tiles, nact, n_hi, nsteps, lam, mu, rho,         \
+                           c->d_rec, resid, c->d_pml_r, c->d_pml_z, in, out, hist_hi,        \
+                           (long long)(2 * c->cells), acc, (long long)c->cells);             \
+        return;                                                                              \
+    }
+
+// nsteps (<= tb_steps) adjoint steps n_hi, n_hi - 1, ... in LDS-tiled kernels;
+// hist_hi is the history slot of step n_hi.
+void adj_tb_launch(bhfwi_ctx* c, hipStream_t st, int n_hi, int nsteps, const float* lam,
+                   const float* mu, const float* rho, const float* resid, const float* in,
+                   float* out, const float* hist_hi, float* acc)
+{
+    const int nact = active_tiles(c, n_hi - nsteps + 1);
+    if (nact <= 0) return;
+    const int T = c->tune.tb_steps, TRE = c->tune.tb_rows, W = c->tune.tb_waves;
+    EvScope ev(c, st, 2);
+    BHFWI_TB_SHAPES(BHFWI_TBA)
+}
+#undef BHFWI_TBA
+
+bool tb_supported(int T, int TRE, int W)
+{
+#define BHFWI_TBS(TT, RR, WW) \
+    if (T == TT && TRE == RR && W == WW) return true;
+    BHFWI_TB_SHAPES(BHFWI_TBS)
+#undef BHFWI_TBS
+    return false;
+}
+
+// Forward steps [n0, n1) from buffer b[*parity] (ping-pong), one launch per
+// step or tb_steps per launch; hist (nullable) receives v of step n at slot
+// n - hist_base.
+void fwd_range(bhfwi_ctx* c, hipStream_t st, int n0, int n1, const float* lam, const float* mu,
+               const float* rho, const float* wav, float* const b[2], int* parity,
+               float* traces, float* hist, int hist_base)
+{
+    const int64_t hslot = 2 * c->cells;
+    const int T = c->tune.tb_steps >= 2 ? c->tune.tb_steps : 1;
+    for (int n = n0; n < n1;) {
+        const int nb = std::min(T, n1 - n);
+        float* h = hist ? hist + (int64_t)(n - hist_base) * hslot : nullptr;
+        if (T >= 2)
+            fwd_tb_launch(c, st, n, nb, lam, mu, rho, wav, b[*parity], b[*parity ^ 1], traces, h);
+        else
+            fwd_launch(c, st, n, lam, mu, rho, wav, b[*parity], b[*parity ^ 1], traces, h);
+        *parity ^= 1;
+        n += nb;
+    }
+}
+
 void clear_graphs(bhfwi_ctx* c)
 {
     for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
@@ -245,6 +359,9 @@ int run_sequence(bhfwi_ctx* c, hipStream_t st, std::vector<uintptr_t> key, F&& r
     }
     key.push_back((uintptr_t)c->tune.rows_per_wave);
     key.push_back((uintptr_t)c->tune.waves_per_block);
+    key.push_back((uintptr_t)c->tune.tb_steps);
+    key.push_back((uintptr_t)c->tune.tb_rows);
+    key.push_back((uintptr_t)c->tune.tb_waves);
     for (size_t g = 0; g < c->graphs.size(); ++g)
         if (c->graphs[g].key == key) {
             HIPOK(c, hipGraphLaunch(c->graphs[g].exec, st));
@@ -438,6 +555,7 @@ void bhfwi_destroy(bhfwi_ctx* c)
     if (c->d_pml_r) (void)hipFree(c->d_pml_r);
     if (c->d_pml_z) (void)hipFree(c->d_pml_z);
     if (c->d_work) (void)hipFree(c->d_work);
+    if (c->d_tiles) (void)hipFree(c->d_tiles);
     if (c->d_scratch) (void)hipFree(c->d_scratch);
     delete c;
 }
@@ -470,7 +588,8 @@ int bhfwi_set_tune(bhfwi_ctx* c, const bhfwi_tune* t)
 {
     if (!c || !t) return BHFWI_EINVAL;
     if (t->rows_per_wave < 1 || t->use_graph < 0 || t->use_graph > 1 || t->time_kernels < 0 ||
-        t->time_kernels > 1 ||
+        t->time_kernels > 1 || t->tb_steps < 0 ||
+        (t->tb_steps >= 2 && !tb_supported(t->tb_steps, t->tb_rows, t->tb_waves)) ||
         !(t->waves_per_block == 1 || t->waves_per_block == 2 || t->waves_per_block == 4 ||
           t->waves_per_block == 8))
         return fail(c, BHFWI_EINVAL, "bad tune (rows %d, waves/block %d)", t->rows_per_wave,
@@ -554,11 +673,13 @@ int bhfwi_fwd_model(bhfwi_ctx* c, void* stream, const float* lam, const float* m
     const int K = c->ckpt_every;
     auto record = [&](hipStream_t s) {
         launch_fill(s, b[0], 2 * c->fst_len, 0.0f);
-        for (int n = 0; n < c->nt_max; ++n) {
-            fwd_launch(c, s, n, lam, mu, rho, wavelet, b[n & 1], b[(n + 1) & 1], traces, nullptr);
-            if (store && (n + 1) % K == 0 && n + 1 < c->nt_max) {
-                float* dst = (float*)ckpt + (int64_t)((n + 1) / K - 1) * c->fst_len;
-                (void)hipMemcpyAsync(dst, b[(n + 1) & 1], sizeof(float) * c->fst_len,
+        int parity = 0;
+        for (int n = 0; n < c->nt_max; n += K) {
+            const int n1 = std::min(n + K, c->nt_max);
+            fwd_range(c, s, n, n1, lam, mu, rho, wavelet, b, &parity, traces, nullptr, 0);
+            if (store && n1 < c->nt_max) {
+                float* dst = (float*)ckpt + (int64_t)(n1 / K - 1) * c->fst_len;
+                (void)hipMemcpyAsync(dst, b[parity], sizeof(float) * c->fst_len,
                                      hipMemcpyDeviceToDevice, s);
             }
         }
@@ -608,6 +729,7 @@ int bhfwi_adjoint_model(bhfwi_ctx* c, void* stream, const float* lam, const floa
     float* hist = (float*)adj_ws + 2 * c->ast_len;
     const int64_t hslot = 2 * c->cells;
     const int K = c->ckpt_every;
+    float* const fbc[2] = {fb[0], fb[1]};
     auto record = [&](hipStream_t s) {
         launch_fill(s, fb[0], 2 * c->fst_len, 0.0f);
         launch_fill(s, ab[0], 2 * c->ast_len, 0.0f);
@@ -620,12 +742,21 @@ int bhfwi_adjoint_model(bhfwi_ctx* c, void* stream, const float* lam, const floa
             else
                 (void)hipMemcpyAsync(fb[0], (const float*)ckpt + (int64_t)(j - 1) * c->fst_len,
                                      sizeof(float) * c->fst_len, hipMemcpyDeviceToDevice, s);
-            for (int n = n0; n < n1; ++n)
-                fwd_launch(c, s, n, lam, mu, rho, wavelet, fb[(n - n0) & 1],
-                           fb[(n - n0 + 1) & 1], nullptr, hist + (int64_t)(n - n0) * hslot);
-            for (int n = n1 - 1; n >= n0; --n, ++m)
-                adj_launch(c, s, n, lam, mu, rho, resid, ab[m & 1], ab[(m + 1) & 1],
-                           hist + (int64_t)(n - n0) * hslot, acc);
+            int parity = 0;
+            fwd_range(c, s, n0, n1, lam, mu, rho, wavelet, fbc, &parity, nullptr, hist, n0);
+            if (c->tune.tb_steps >= 2) {
+                for (int n = n1 - 1; n >= n0;) {
+                    const int nb = std::min(c->tune.tb_steps, n - n0 + 1);
+                    adj_tb_launch(c, s, n, nb, lam, mu, rho, resid, ab[m & 1], ab[(m + 1) & 1],
+                                  hist + (int64_t)(n - n0) * hslot, acc);
+                    ++m;
+                    n -= nb;
+                }
+            } else {
+                for (int n = n1 - 1; n >= n0; --n, ++m)
+                    adj_launch(c, s, n, lam, mu, rho, resid, ab[m & 1], ab[(m + 1) & 1],
+                               hist + (int64_t)(n - n0) * hslot, acc);
+            }
         }
     };
     return run_sequence(c, st,

@@ -44,8 +44,20 @@ def survey(w, ckpt=250, tune=None):
     import paper_2005_00281_amd as P
     sv = P.Survey(w.shots, (w.NRg, w.NZg), ckpt_every=ckpt)
     if tune:
-        sv.set_tune(*tune)
+        sv.set_tune(**tune)
     return sv
+
+
+def T(rows=4, wpb=4, graph=1, tb=0, tbr=16, tbw=4):
+    return dict(rows_per_wave=rows, waves_per_block=wpb, use_graph=graph, tb_steps=tb,
+                tb_rows=tbr, tb_waves=tbw)
+
+
+FWD_TUNES = [T(1, 1, 0), T(2, 4, 1), T(3, 2, 1), T(4, 4, 0), T(16, 4, 1), T(64, 8, 0),
+             T(tb=2), T(tb=3, graph=0), T(tb=4), T(tb=4, tbw=8), T(tb=6, tbr=24, tbw=8, graph=0),
+             T(tb=8, tbr=32, tbw=8), T(tb=3, tbr=24, tbw=8)]
+GRAD_TUNES = [T(1, 1, 1), T(2, 4, 0), T(4, 4, 1), T(5, 4, 1), T(64, 8, 0), T(tb=4),
+              T(tb=3, graph=0), T(tb=4, tbw=8), T(tb=6, tbr=24, tbw=8), T(tb=8, tbr=32, tbw=8)]
 
 
 def oracle_traces(w, s=0, which="start"):
@@ -54,7 +66,7 @@ def oracle_traces(w, s=0, which="start"):
 
 
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("tune", [(1, 1, 0), (2, 4, 1), (3, 2, 1), (4, 4, 0), (16, 4, 1), (64, 8, 0)])
+@pytest.mark.parametrize("tune", FWD_TUNES)
 def test_forward_parity_tiny_ragged(tune):
     """NZ = 162 spans three 62-row strips with a ragged tail; NR = 46 is not
     a multiple of the radial chunk."""
@@ -114,7 +126,7 @@ def _regions(sh, shape):
     return {"all": np.ones(shape, bool), "interior": ~(r | z), "pml_r": r, "pml_z": z}
 
 
-@pytest.mark.parametrize("tune", [(1, 1, 1), (2, 4, 0), (4, 4, 1), (5, 4, 1), (64, 8, 0)])
+@pytest.mark.parametrize("tune", GRAD_TUNES)
 def test_gradient_parity_tiny(tune):
     w = workloads.tiny(nr=40, nz=150, p=6, nt=300)
     _say("grad tiny", tune)
@@ -144,15 +156,19 @@ def test_gradient_parity_single_shot_128x512():
     assert rel_l2(il, il_o) <= 1e-4
 
 
-def test_checkpoint_interval_is_exact():
-    """Recompute from checkpoints repeats the same FP32 arithmetic: any
-    checkpoint interval gives the bitwise-same gradient."""
+@pytest.mark.parametrize("tune", [T(4, 4, 1), T(tb=4)])
+def test_checkpoint_interval_is_exact(tune):
+    """Recompute from checkpoints repeats the same FP32 arithmetic: with one
+    step per launch any checkpoint interval gives the bitwise-same gradient.
+    Temporally blocked launches keep per-block partial sums of the
+    correlation and blocks stop at checkpoint boundaries, so the interval
+    regroups FP32 additions: equal to FP32 rounding (rel-L2 <= 1e-6)."""
     w = workloads.tiny(nt=200)
-    _say("ckpt interval")
+    _say("ckpt interval", tune)
     outs = []
     r = np.random.default_rng(0).standard_normal(len(w.shots[0].rec_k) * 200)
     for K in (7, 64, 200):
-        sv = survey(w, ckpt=K)
+        sv = survey(w, ckpt=K, tune=tune)
         lam, mu, rho = gpu_models(w)
         wav = sv.pack_wavelets([w.shots[0].wavelet])
         sv.fwd_model(lam, mu, rho, wav, store_ckpt=True)
@@ -160,7 +176,10 @@ def test_checkpoint_interval_is_exact():
         outs.append([t.cpu().numpy() for t in sv.gradient(mu, acc)])
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
-            assert np.array_equal(a, b)
+            if tune["tb_steps"] >= 2:
+                assert rel_l2(b, a) <= 1e-6, rel_l2(b, a)
+            else:
+                assert np.array_equal(a, b)
 
 
 def _multi_shot_workload():
@@ -177,12 +196,13 @@ def _multi_shot_workload():
     return base
 
 
-def test_batched_equals_single_and_oracle():
+@pytest.mark.parametrize("tune", [T(4, 4, 1), T(tb=3), T(tb=4, tbr=32, tbw=8, graph=0)])
+def test_batched_equals_single_and_oracle(tune):
     w = _multi_shot_workload()
-    _say("batched 3 shots", [(s.NR, s.NZ, s.nt) for s in w.shots])
+    _say("batched 3 shots", [(s.NR, s.NZ, s.nt) for s in w.shots], tune)
     import copy
     lam, mu, rho = gpu_models(w)
-    sv = survey(w, ckpt=50)
+    sv = survey(w, ckpt=50, tune=tune)
     wav = sv.pack_wavelets([s.wavelet for s in w.shots])
     tr = sv.fwd_model(lam, mu, rho, wav, store_ckpt=True)
     torch.manual_seed(0)
@@ -195,7 +215,7 @@ def test_batched_equals_single_and_oracle():
     for s, (off, nrec, nt) in enumerate(sv.trace_slices()):
         w1 = copy.copy(w)
         w1.shots = [w.shots[s]]
-        sv1 = survey(w1, ckpt=50)
+        sv1 = survey(w1, ckpt=50, tune=tune)
         wav1 = sv1.pack_wavelets([w.shots[s].wavelet])
         tr1 = sv1.fwd_model(lam, mu, rho, wav1, store_ckpt=True)
         assert np.array_equal(sv1.unpack_traces(tr1)[0], tr_b[s])
