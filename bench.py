@@ -74,6 +74,7 @@ def main():
                     help="forward steps per launch in the LDS-tiled kernels (-1: default)")
     ap.add_argument("--tb-rows", type=int, default=0)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=120)
     args = ap.parse_args()
@@ -94,11 +95,20 @@ def main():
     log("workload", args.workload, "shots", len(w.shots), "grid", w.shots[0].NR, w.shots[0].NZ,
         "nt", w.shots[0].nt)
     sv = P.Survey(w.shots, (w.NRg, w.NZg), ckpt_every=w.meta.get("ckpt", 250))
-    sv.set_tune(rows_per_wave=args.rows or None, use_graph=0 if args.no_graph else None,
-                tb_steps=args.tb if args.tb >= 0 else None, tb_rows=args.tb_rows or None)
-    tune = sv.get_tune()
     rho = f32(w.rho)
     wav = sv.pack_wavelets([s.wavelet for s in w.shots])
+    if args.tb >= 0 or args.rows or args.no_autotune:
+        sv.set_tune(rows_per_wave=args.rows or None, tb_steps=args.tb if args.tb >= 0 else None,
+                    tb_rows=args.tb_rows or None)
+    else:
+        lam_s, mu_s = P.moduli(f32(w.vp_start), f32(w.vs_start), rho)
+        t_at = time.perf_counter()
+        entry = sv.autotune(lam_s, mu_s, rho, wav)
+        log("autotune %.1f s -> %s" % (time.perf_counter() - t_at, entry["tune"]))
+        del lam_s, mu_s
+    if args.no_graph:
+        sv.set_tune(use_graph=0)
+    tune = sv.get_tune()
     lam_t, mu_t = P.moduli(f32(w.vp_true), f32(w.vs_true), rho)
     observed = sv.fwd_model(lam_t, mu_t, rho, wav).clone()
     del lam_t, mu_t
@@ -129,21 +139,28 @@ def main():
     inv.iterate()
     kt = sv.kernel_times(reset=True)
     sv.set_tune(use_graph=tune["use_graph"], time_kernels=0)
-    cells = z.cells
     adj_ms, adj_n = kt["adj"]
-    fwd_ms, fwd_n = kt["fwd"]
-    rec_ms, rec_n = kt["rec"]
-    cells_active = sum(s.cells for s in w.shots)
+    # every adjoint step of the iteration ran once: nt cell-steps of every shot
+    steps_per_launch = z.nt_max / max(1, adj_n)
     adj_avg = adj_ms / max(1, adj_n)
-    # algorithmic bytes per launch: every active cell once (shots share launches)
-    adj_bytes = ADJ_BYTES_PER_CELL_STEP * z.cell_steps / z.nt_max
+    adj_bytes = ADJ_BYTES_PER_CELL_STEP * z.cell_steps / max(1, adj_n)  # per launch
     achieved = adj_bytes / (adj_avg * 1e-3) / 1e9
+    T = tune["tb_steps"]
+    kname = ("k_adj_tb<%d, %d, %d>" % (T, tune["tb_rows"], tune["tb_waves"]) if T >= 2
+             else "k_adj_step<%d>" % (tune["rows_per_wave"] if tune["rows_per_wave"] <= 4 else 0))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_adj_step", "avg_launch_us": round(adj_avg * 1e3, 3),
-                "bytes_per_launch": int(adj_bytes)}
-    kernels = {k: {"avg_us": round(v[0] * 1e3 / max(1, v[1]), 3), "launches": v[1]}
-               for k, v in kt.items()}
+                "kernel": kname, "avg_launch_us": round(adj_avg * 1e3, 3),
+                "steps_per_launch": round(steps_per_launch, 3),
+                "bytes_per_launch": int(adj_bytes),
+                "bytes_per_cell_step": ADJ_BYTES_PER_CELL_STEP}
+    per_cs = {"fwd": FWD_BYTES_PER_CELL_STEP, "rec": REC_BYTES_PER_CELL_STEP,
+              "adj": ADJ_BYTES_PER_CELL_STEP}
+    kernels = {}
+    for k, (kms, kn) in kt.items():
+        if kn:
+            kernels[k] = {"avg_us": round(kms * 1e3 / kn, 3), "launches": kn,
+                          "achieved_GBs": round(per_cs[k] * z.cell_steps / (kms * 1e-3) / 1e9, 1)}
     # iteration-level roofline: 220 B per cell-step over one gradient evaluation
     it_frac = (220 * z.cell_steps / (ms * 1e-3)) / (HBM_PEAK_GBS * 1e9)
 

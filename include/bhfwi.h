@@ -130,6 +130,19 @@ const char *bhfwi_last_error(const bhfwi_ctx *ctx);
 int bhfwi_sizes(const bhfwi_ctx *ctx, bhfwi_sizes_t *out);
 int bhfwi_set_tune(bhfwi_ctx *ctx, const bhfwi_tune *tune);
 int bhfwi_get_tune(const bhfwi_ctx *ctx, bhfwi_tune *out);
+/* Autotuner: times every supported kernel shape (one-step wave marches of 1,
+ * 2 and 4 rows per wave and every temporally blocked shape) on this survey --
+ * probe_steps forward steps storing the velocity history from a zero state,
+ * then the adjoint over the same steps driven by a zero residual -- keeps the
+ * fastest as the context's tune, copies it to *best (host) and its time to
+ * *best_ms (host).  probe_steps is clamped to [1, min(ckpt_every, nt)].
+ * traces (trace_elems floats), fwd_ws, adj_ws and acc are scratch; their
+ * contents are overwritten.  Synchronises the stream. */
+int bhfwi_autotune(bhfwi_ctx *ctx, void *stream, const float *lam, const float *mu,
+                   const float *rho, const float *wavelet, float *traces, void *fwd_ws,
+                   int64_t fwd_ws_bytes, void *adj_ws, int64_t adj_ws_bytes, float *acc,
+                   int32_t probe_steps, bhfwi_tune *best, float *best_ms);
+
 /* Read (and with reset != 0 clear) the sums of bhfwi_kernel_times_t. */
 int bhfwi_kernel_times(bhfwi_ctx *ctx, bhfwi_kernel_times_t *out, int32_t reset);
 

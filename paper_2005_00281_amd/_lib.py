@@ -60,7 +60,8 @@ class Bounds(C.Structure):
 
 
 EXPORTS = ["bhfwi_create", "bhfwi_destroy", "bhfwi_last_error", "bhfwi_sizes",
-           "bhfwi_set_tune", "bhfwi_get_tune", "bhfwi_kernel_times", "bhfwi_moduli", "bhfwi_velocities",
+           "bhfwi_set_tune", "bhfwi_get_tune", "bhfwi_autotune", "bhfwi_kernel_times",
+           "bhfwi_moduli", "bhfwi_velocities",
            "bhfwi_fwd_model", "bhfwi_misfit", "bhfwi_adjoint_model", "bhfwi_gradient",
            "bhfwi_precondition", "bhfwi_update"]
 
@@ -86,6 +87,8 @@ def load(path: str = LIB_PATH):
     L.bhfwi_set_tune.argtypes = [P, C.POINTER(Tune)]
     L.bhfwi_get_tune.argtypes = [P, C.POINTER(Tune)]
     L.bhfwi_kernel_times.argtypes = [P, C.POINTER(KernelTimes), I32]
+    L.bhfwi_autotune.argtypes = [P, V, P, P, P, P, P, P, I64, P, I64, P, I32, C.POINTER(Tune),
+                                 C.POINTER(C.c_float)]
     L.bhfwi_moduli.argtypes = [V, I64, P, P, P, P, P]
     L.bhfwi_velocities.argtypes = [V, I64, P, P, P, P, P]
     L.bhfwi_fwd_model.argtypes = [P, V, P, P, P, P, P, P, I64, P, I64, I32]
@@ -204,6 +207,51 @@ class Survey:
         t = Tune()
         _check(load().bhfwi_get_tune(self._h, C.byref(t)), self._h)
         return {name: getattr(t, name) for name, _ in Tune._fields_}
+
+    def shape_key(self):
+        """Key of the autotune cache: device name and the multiset of shot shapes."""
+        shapes = sorted((sh.nr + sh.pr, sh.nz + 2 * sh.pz, sh.nt) for sh in self.shots)
+        hist = {}
+        for s in shapes:
+            hist[s] = hist.get(s, 0) + 1
+        return "%s|K%d|%s" % (torch.cuda.get_device_name(self.device), self.sizes.ckpt_every,
+                              ";".join("%dx%dx%d*%d" % (a, b, c, n)
+                                       for (a, b, c), n in sorted(hist.items())))
+
+    def autotune(self, lam, mu, rho, wavelet, probe_steps=None, cache=None):
+        """Pick the fastest kernel shape for this survey (bhfwi_autotune) and
+        install it; with cache (a JSON path) reuse and record the choice."""
+        import json
+        key = self.shape_key()
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+        if key in table:
+            self.set_tune(**table[key]["tune"])
+            return table[key]
+        z = self.sizes
+        if probe_steps is None:
+            probe_steps = min(z.ckpt_every, z.nt_max, 96)
+        tr = torch.empty(z.trace_elems, dtype=torch.float32, device=self.device)
+        acc = torch.empty(z.acc_elems, dtype=torch.float32, device=self.device)
+        fw, aw = self.workspace("fwd"), self.workspace("adj")
+        best, ms = Tune(), C.c_float()
+        n = self.model_shape[0] * self.model_shape[1]
+        _check(load().bhfwi_autotune(self._h, _stream(), _f32(lam, n), _f32(mu, n),
+                                     _f32(rho, n), _f32(wavelet, z.wavelet_elems), _f32(tr),
+                                     _ptr(fw), fw.numel(), _ptr(aw), aw.numel(), _f32(acc),
+                                     int(probe_steps), C.byref(best), C.byref(ms)), self._h)
+        _check(load().bhfwi_sizes(self._h, C.byref(self.sizes)), self._h)
+        entry = {"tune": {name: getattr(best, name) for name, _ in Tune._fields_},
+                 "probe_ms": ms.value, "probe_steps": int(probe_steps)}
+        if cache:
+            table[key] = entry
+            tmp = cache + ".tmp%d" % os.getpid()
+            with open(tmp, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return entry
 
     def kernel_times(self, reset=True):
         """Sums of the per-launch event timings of the instrumented mode."""

@@ -517,6 +517,10 @@ int bhfwi_create(bhfwi_ctx** out, int32_t hip_device, const bhfwi_shot* shots, i
     c->tune.rows_per_wave = default_rows(c);
     c->tune.waves_per_block = 4;
     c->tune.use_graph = 1;
+    c->tune.time_kernels = 0;
+    c->tune.tb_steps = 4;  // measured best on single shots; bhfwi_autotune refines
+    c->tune.tb_rows = 16;
+    c->tune.tb_waves = 8;
     rebuild_work(c);
 
     hipError_t e = hipSetDevice(hip_device);
@@ -600,6 +604,101 @@ int bhfwi_set_tune(bhfwi_ctx* c, const bhfwi_tune* t)
     c->tune = *t;
     rebuild_work(c);
     return upload_work(c);
+}
+
+int bhfwi_autotune(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
+                   const float* rho, const float* wavelet, float* traces, void* fwd_ws,
+                   int64_t fwd_ws_bytes, void* adj_ws, int64_t adj_ws_bytes, float* acc,
+                   int32_t probe_steps, bhfwi_tune* best, float* best_ms)
+{
+    if (int rc = check_ctx(c)) return rc;
+    bhfwi_sizes_t z;
+    bhfwi_sizes(c, &z);
+    if (!lam || !mu || !rho || !wavelet || !traces || !fwd_ws || !adj_ws || !acc || !best)
+        return fail(c, BHFWI_EINVAL, "autotune: null pointer");
+    if (fwd_ws_bytes < z.fwd_ws_bytes || adj_ws_bytes < z.adj_ws_bytes)
+        return fail(c, BHFWI_ENOMEM, "autotune: workspace too small");
+    hipStream_t st = (hipStream_t)stream;
+    const int P = std::max(1, std::min<int>(probe_steps, std::min(c->ckpt_every, c->nt_max)));
+    std::vector<bhfwi_tune> cand;
+    const bhfwi_tune base = c->tune;
+    for (int r : {1, 2, 4}) {
+        bhfwi_tune t = base;
+        t.rows_per_wave = r;
+        t.tb_steps = 0;
+        cand.push_back(t);
+    }
+#define BHFWI_TBC(TT, RR, WW)      \
+    {                              \
+        bhfwi_tune t = base;       \
+        t.tb_steps = TT;           \
+        t.tb_rows = RR;            \
+        t.tb_waves = WW;           \
+        cand.push_back(t);         \
+    }
+    BHFWI_TB_SHAPES(BHFWI_TBC)
+#undef BHFWI_TBC
+    float* fb[2] = {(float*)fwd_ws, (float*)fwd_ws + c->fst_len};
+    float* ab[2] = {(float*)adj_ws, (float*)adj_ws + c->ast_len};
+    float* hist = (float*)adj_ws + 2 * c->ast_len;
+    const int64_t hslot = 2 * c->cells;
+    hipEvent_t e0, e1;
+    HIPOK(c, hipEventCreate(&e0));
+    HIPOK(c, hipEventCreate(&e1));
+    float best_t = 1e30f;
+    bhfwi_tune best_tune = base;
+    for (const bhfwi_tune& t : cand) {
+        HIPOK(c, hipStreamSynchronize(st));
+        clear_graphs(c);
+        c->tune = t;
+        c->tune.use_graph = 0;
+        c->tune.time_kernels = 0;
+        rebuild_work(c);
+        if (int rc = upload_work(c)) return rc;
+        float tmin = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            launch_fill(st, fb[0], 2 * c->fst_len, 0.0f);
+            launch_fill(st, ab[0], 2 * c->ast_len, 0.0f);
+            launch_fill(st, traces, c->trace_len, 0.0f);
+            HIPOK(c, hipEventRecord(e0, st));
+            int parity = 0;
+            fwd_range(c, st, 0, P, lam, mu, rho, wavelet, fb, &parity, nullptr, hist, 0);
+            int m = 0;
+            if (c->tune.tb_steps >= 2) {
+                for (int n = P - 1; n >= 0;) {
+                    const int nb = std::min(c->tune.tb_steps, n + 1);
+                    adj_tb_launch(c, st, n, nb, lam, mu, rho, traces, ab[m & 1],
+                                  ab[(m + 1) & 1], hist + (int64_t)n * hslot, acc);
+                    ++m;
+                    n -= nb;
+                }
+            } else {
+                for (int n = P - 1; n >= 0; --n, ++m)
+                    adj_launch(c, st, n, lam, mu, rho, traces, ab[m & 1], ab[(m + 1) & 1],
+                               hist + (int64_t)n * hslot, acc);
+            }
+            HIPOK(c, hipEventRecord(e1, st));
+            HIPOK(c, hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPOK(c, hipEventElapsedTime(&ms, e0, e1));
+            if (rep > 0) tmin = std::min(tmin, ms);  // first repetition warms up
+        }
+        if (tmin < best_t) {
+            best_t = tmin;
+            best_tune = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    clear_graphs(c);
+    best_tune.use_graph = base.use_graph;
+    best_tune.time_kernels = base.time_kernels;
+    c->tune = best_tune;
+    rebuild_work(c);
+    if (int rc = upload_work(c)) return rc;
+    *best = best_tune;
+    if (best_ms) *best_ms = best_t;
+    return BHFWI_OK;
 }
 
 int bhfwi_kernel_times(bhfwi_ctx* c, bhfwi_kernel_times_t* o, int32_t reset)

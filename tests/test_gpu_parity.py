@@ -319,3 +319,24 @@ def test_autograd_end_to_end_and_central_differences():
                 fd = (J(L0, p) - J(L0, q)) / (2 * h)
             assert abs(fd - G[i, k]) <= 1e-2 * abs(G[i, k]) + 1e-3 * np.abs(G).max(), \
                 (name, i, k, fd, G[i, k])
+
+
+def test_autotune_picks_a_valid_shape_and_stays_correct(tmp_path):
+    """The autotuner times every shape on the survey, installs the fastest,
+    records it in the cache, and the chosen shape still matches the oracle."""
+    w = workloads.tiny(nr=40, nz=150, p=6, nt=300)
+    _say("autotune tiny")
+    d_o = oracle_traces(w)
+    sv = survey(w, ckpt=64)
+    lam, mu, rho = gpu_models(w)
+    wav = sv.pack_wavelets([w.shots[0].wavelet])
+    cache = str(tmp_path / "tune.json")
+    entry = sv.autotune(lam, mu, rho, wav, cache=cache)
+    assert entry["probe_ms"] > 0
+    t = sv.get_tune()
+    assert t == {**t, **entry["tune"]}
+    tr = sv.fwd_model(lam, mu, rho, wav)
+    assert rel_l2(sv.unpack_traces(tr)[0], d_o) <= 1e-4
+    sv2 = survey(w, ckpt=64)
+    again = sv2.autotune(lam, mu, rho, wav, cache=cache)  # served from the cache
+    assert again["tune"] == entry["tune"]
