@@ -63,6 +63,21 @@ def cpu_baseline(w, nt_sample):
                       "checkpointed gradient, %.1f s" % (nt_sample, sh.nt, cs, dt)}
 
 
+def copy_calibration():
+    """One device copy of 1 GiB from memory that is not in any cache, for
+    scaling the FETCH_SIZE / WRITE_SIZE counters (bytes known exactly)."""
+    import torch
+    n = 1 << 28  # floats
+    src = torch.ones(n, device="cuda")
+    dst = torch.empty(n, device="cuda")
+    evict = torch.empty(1 << 28, device="cuda")
+    evict.fill_(2.0)  # pushes src out of L2 and the infinity cache
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": 4 * n, "copy_kib": 4 * n / 1024}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,7 +92,15 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=120)
+    ap.add_argument("--plain-shots", type=int, default=2,
+                    help="shots timed in the plain one-shot, one-step-per-launch form")
+    ap.add_argument("--budget-gb", type=float, default=0.0,
+                    help="HBM budget for the planner (0: 80%% of the device)")
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU; this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -89,32 +112,53 @@ def main():
     import paper_2005_00281_amd as P
     from paper_2005_00281_amd.fwi import Inversion
 
+    from paper_2005_00281_amd import plan as planner
+
     dev = torch.device("cuda", 0)
     w = workloads.make(args.workload)
     f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=dev)
     log("workload", args.workload, "shots", len(w.shots), "grid", w.shots[0].NR, w.shots[0].NZ,
         "nt", w.shots[0].nt)
-    sv = P.Survey(w.shots, (w.NRg, w.NZg), ckpt_every=w.meta.get("ckpt", 250))
+    budget = (args.budget_gb * 1e9 if args.budget_gb > 0
+              else 0.8 * torch.cuda.get_device_properties(0).total_memory)
+    pl = planner.plan(w.shots, budget, ckpt_every=w.meta.get("ckpt"))
+    log("plan: %d group(s) of %s shots, checkpoint every %s steps, %.1f GB workspaces" % (
+        len(pl.groups), [len(g) for g in pl.groups], pl.ckpt_every, pl.bytes_workspace / 1e9))
     rho = f32(w.rho)
-    wav = sv.pack_wavelets([s.wavelet for s in w.shots])
+    surveys, wavs = [], []
+    for g, K in zip(pl.groups, pl.ckpt_every):
+        sv = P.Survey([w.shots[s] for s in g], (w.NRg, w.NZg), ckpt_every=K)
+        surveys.append(sv)
+        wavs.append(sv.pack_wavelets([w.shots[s].wavelet for s in g]))
+    lam_t, mu_t = P.moduli(f32(w.vp_true), f32(w.vs_true), rho)
+    observed = []
+    for sv, wav in zip(surveys, wavs):
+        observed.append(sv.fwd_model(lam_t, mu_t, rho, wav).clone())
+        sv.free_workspaces()
+    del lam_t, mu_t
+    mask = torch.as_tensor(w.mask, device=dev)
+    inv = Inversion(surveys, f32(w.vp_start), f32(w.vs_start), rho, wavs, observed, mask)
     if args.tb >= 0 or args.rows or args.no_autotune:
-        sv.set_tune(rows_per_wave=args.rows or None, tb_steps=args.tb if args.tb >= 0 else None,
-                    tb_rows=args.tb_rows or None)
+        for sv in surveys:
+            sv.set_tune(rows_per_wave=args.rows or None,
+                        tb_steps=args.tb if args.tb >= 0 else None,
+                        tb_rows=args.tb_rows or None)
     else:
         lam_s, mu_s = P.moduli(f32(w.vp_start), f32(w.vs_start), rho)
         t_at = time.perf_counter()
-        entry = sv.autotune(lam_s, mu_s, rho, wav)
+        for sv, wav in zip(surveys, wavs):
+            entry = sv.autotune(lam_s, mu_s, rho, wav)
         log("autotune %.1f s -> %s" % (time.perf_counter() - t_at, entry["tune"]))
         del lam_s, mu_s
     if args.no_graph:
-        sv.set_tune(use_graph=0)
+        for sv in surveys:
+            sv.set_tune(use_graph=0)
+    sv = surveys[0]
     tune = sv.get_tune()
-    lam_t, mu_t = P.moduli(f32(w.vp_true), f32(w.vs_true), rho)
-    observed = sv.fwd_model(lam_t, mu_t, rho, wav).clone()
-    del lam_t, mu_t
-    mask = torch.as_tensor(w.mask, device=dev)
-    inv = Inversion(sv, f32(w.vp_start), f32(w.vs_start), rho, wav, observed, mask)
-    z = sv.sizes
+
+    from types import SimpleNamespace
+    z = SimpleNamespace(cell_steps=sum(x.sizes.cell_steps for x in surveys),
+                        nt_max=max(x.sizes.nt_max for x in surveys))
 
     for _ in range(args.warmup):
         inv.iterate()
@@ -134,14 +178,21 @@ def main():
 
     # per-kernel durations: one more (untimed) iteration with every time-step
     # kernel bracketed by HIP events on the stream it runs on
-    sv.set_tune(use_graph=0, time_kernels=1)
-    sv.kernel_times(reset=True)
+    for x in surveys:
+        x.set_tune(use_graph=0, time_kernels=1)
+        x.kernel_times(reset=True)
     inv.iterate()
-    kt = sv.kernel_times(reset=True)
-    sv.set_tune(use_graph=tune["use_graph"], time_kernels=0)
+    kt = {"fwd": [0.0, 0], "rec": [0.0, 0], "adj": [0.0, 0]}
+    for x in surveys:
+        for k, (ms_, n_) in x.kernel_times(reset=True).items():
+            kt[k][0] += ms_
+            kt[k][1] += n_
+        x.set_tune(use_graph=tune["use_graph"], time_kernels=0)
+    # the adjoint launches of different groups cover different shots
+    adj_launch_sets = len(surveys)
     adj_ms, adj_n = kt["adj"]
     # every adjoint step of the iteration ran once: nt cell-steps of every shot
-    steps_per_launch = z.nt_max / max(1, adj_n)
+    steps_per_launch = adj_launch_sets * z.nt_max / max(1, adj_n)
     adj_avg = adj_ms / max(1, adj_n)
     adj_bytes = ADJ_BYTES_PER_CELL_STEP * z.cell_steps / max(1, adj_n)  # per launch
     achieved = adj_bytes / (adj_avg * 1e-3) / 1e9
@@ -164,6 +215,39 @@ def main():
     # iteration-level roofline: 220 B per cell-step over one gradient evaluation
     it_frac = (220 * z.cell_steps / (ms * 1e-3)) / (HBM_PEAK_GBS * 1e9)
 
+    # plain form: one shot per survey, one step per launch, no graph, same
+    # checkpoint interval; per-shot gradient-evaluation times, extrapolated
+    # over all shots by cell-steps
+    plain = None
+    if args.plain_shots > 0:
+        del inv
+        torch.cuda.empty_cache()
+        per_cs = []
+        for s_ in range(min(args.plain_shots, len(w.shots))):
+            sh = w.shots[s_]
+            g_ = [i for i, g in enumerate(pl.groups) if s_ in g][0]
+            sv1 = P.Survey([sh], (w.NRg, w.NZg), ckpt_every=pl.ckpt_every[g_])
+            sv1.set_tune(rows_per_wave=2, tb_steps=0, use_graph=0)
+            wav1 = sv1.pack_wavelets([sh.wavelet])
+            off = sum(len(w.shots[q].rec_k) * w.shots[q].nt for q in pl.groups[g_] if q < s_)
+            obs1 = observed[g_][off: off + len(sh.rec_k) * sh.nt].clone()
+            inv1 = Inversion(sv1, f32(w.vp_start), f32(w.vs_start), rho, wav1, obs1, mask)
+            inv1.gradient()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            inv1.gradient()
+            torch.cuda.synchronize()
+            per_cs.append((time.perf_counter() - t0) / (sh.cells * sh.nt))
+            del inv1, sv1
+            torch.cuda.empty_cache()
+        rate = sum(per_cs) / len(per_cs)
+        t_plain = rate * sum(sh.cells * sh.nt for sh in w.shots)
+        plain = {"shots_iters_per_s": round(len(w.shots) / t_plain, 4),
+                 "ms_per_iteration": round(t_plain * 1e3, 1),
+                 "measured_shots": len(per_cs), "extrapolated": len(per_cs) < len(w.shots),
+                 "form": "one shot per launch sequence, one step per launch (wave march, "
+                         "2 rows per wave), no HIP graph, same checkpoint interval"}
+
     base = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -174,17 +258,22 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": args.workload + ": " + (w.__class__.__name__ and
-                   "%d shot(s), %dx%d padded cells, %d steps, dt %.3g s, f0 %.3g Hz, "
-                   "%d receivers, checkpoints every %d steps" % (
+        "config": {"workload": args.workload + ": " + (
+                   "%d shot(s), %dx%d padded cells (shot 0), %d steps (shot 0), dt %.3g s, "
+                   "f0 %.3g Hz, %d receivers, checkpoints every %s steps" % (
                        len(w.shots), w.shots[0].NR, w.shots[0].NZ, w.shots[0].nt,
                        w.shots[0].dt, w.shots[0].f0, len(w.shots[0].rec_k),
-                       z.ckpt_every)),
+                       pl.ckpt_every)),
                    "cell_steps_per_iteration": int(z.cell_steps),
                    "tune": tune},
         "roofline": roofline,
         "iteration_hbm_frac_at_220B": round(it_frac, 4),
         "shots_iters_per_s": round(len(w.shots) / (ms * 1e-3), 4),
+        "plain": plain,
+        "batched_vs_plain": (round(len(w.shots) / (ms * 1e-3) / plain["shots_iters_per_s"], 3)
+                             if plain else None),
+        "plan": {"groups": [len(g) for g in pl.groups], "ckpt_every": pl.ckpt_every,
+                 "workspace_gb": round(pl.bytes_workspace / 1e9, 2)},
         "kernels": kernels,
         "cpu_baseline": base,
     }

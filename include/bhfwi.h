@@ -150,6 +150,11 @@ int bhfwi_kernel_times(bhfwi_ctx *ctx, bhfwi_kernel_times_t *out, int32_t reset)
  * n elements, device arrays. */
 int bhfwi_moduli(void *stream, int64_t n, const float *vp, const float *vs, const float *rho,
                  float *lam, float *mu);
+/* Chain rule of Eq. 3-4 for a velocity parameterisation:
+ * g_vp = 2 rho vp g_lam, g_vs = 2 rho vs (g_mu - 2 g_lam); n elements, device. */
+int bhfwi_moduli_grad(void *stream, int64_t n, const float *vp, const float *vs,
+                      const float *rho, const float *g_lam, const float *g_mu, float *g_vp,
+                      float *g_vs);
 /* Eq. 11-12: vp = sqrt((lam + 2 mu)/rho), vs = sqrt(mu/rho). */
 int bhfwi_velocities(void *stream, int64_t n, const float *lam, const float *mu,
                      const float *rho, float *vp, float *vs);
@@ -167,9 +172,10 @@ int bhfwi_fwd_model(bhfwi_ctx *ctx, void *stream, const float *lam, const float 
                     int64_t fwd_ws_bytes, void *ckpt, int64_t ckpt_bytes, int32_t flags);
 
 /* Eq. 1 and 5: resid = traces - observed (packed), and J = 0.5 sum resid^2
- * accumulated in double into *J_dev (device, overwritten). */
+ * summed in double (deterministic two-level reduction) into *J_dev (device):
+ * overwritten, or added to when accumulate != 0 (several shot groups). */
 int bhfwi_misfit(bhfwi_ctx *ctx, void *stream, const float *traces, const float *observed,
-                 float *resid, double *J_dev);
+                 float *resid, double *J_dev, int32_t accumulate);
 
 /* Adjoint modelling (Eq. 6, as the exact transpose of the discrete forward)
  * driven by resid = dJ/dtraces (packed), fused with the zero-lag correlation
@@ -187,9 +193,10 @@ int bhfwi_adjoint_model(bhfwi_ctx *ctx, void *stream, const float *lam, const fl
 /* Gradient finalize: folds the tau_rz-node rigidity gradient into the C cells
  * (harmonic-mean chain rule), and sums every shot's window into the global
  * model grid in shot order (no atomics; deterministic).  Outputs (device,
- * model_len each, overwritten): g_lam, g_mu, illum. */
+ * model_len each): g_lam, g_mu, illum -- overwritten, or added to when
+ * accumulate != 0 (contexts holding further groups of shots of one model). */
 int bhfwi_gradient(bhfwi_ctx *ctx, void *stream, const float *mu, const float *acc,
-                   float *g_lam, float *g_mu, float *illum);
+                   float *g_lam, float *g_mu, float *illum, int32_t accumulate);
 
 /* Diagonal preconditioner (Numerical Examples section, Fig. 6): with
  * E = illum and Emax its maximum over mask cells, g <- g / (E + eps Emax) for

@@ -58,6 +58,7 @@ def _load():
         G = C.POINTER(_Geom)
         lib.orc_moduli.argtypes = [C.c_int64, _D, _D, _D, _D, _D]
         lib.orc_velocities.argtypes = [C.c_int64, _D, _D, _D, _D, _D]
+        lib.orc_moduli_grad.argtypes = [C.c_int64, _D, _D, _D, _D, _D, _D, _D]
         lib.orc_forward.argtypes = [G, _D, _D, _D, _D, _D, _D]
         lib.orc_forward.restype = C.c_int
         lib.orc_misfit.argtypes = [C.c_int64, _D, _D, _D]
@@ -136,6 +137,14 @@ def moduli(vp, vs, rho):
     lam, mu = np.empty_like(vp), np.empty_like(vp)
     _load().orc_moduli(vp.size, _p(vp), _p(vs), _p(rho), _p(lam), _p(mu))
     return lam, mu
+
+
+def moduli_grad(vp, vs, rho, glam, gmu):
+    """Chain rule of Eq. 3-4: (dJ/dVp, dJ/dVs) from (dJ/dlambda, dJ/dmu)."""
+    vp, vs, rho, gl, gm = (_f64(a) for a in (vp, vs, rho, glam, gmu))
+    gvp, gvs = np.empty_like(vp), np.empty_like(vp)
+    _load().orc_moduli_grad(vp.size, _p(vp), _p(vs), _p(rho), _p(gl), _p(gm), _p(gvp), _p(gvs))
+    return gvp, gvs
 
 
 def velocities(lam, mu, rho):

@@ -433,6 +433,19 @@ void orc_moduli(int64_t n, const double *vp, const double *vs, const double *rho
     }
 }
 
+void orc_moduli_grad(int64_t n, const double *vp, const double *vs, const double *rho,
+                     const double *glam, const double *gmu, double *gvp, double *gvs)
+{
+    for (int64_t c = 0; c < n; ++c) {
+        /* lambda = rho vp^2 - 2 rho vs^2, mu = rho vs^2 */
+        double dl_dvp = 2.0 * rho[c] * vp[c];
+        double dl_dvs = -4.0 * rho[c] * vs[c];
+        double dm_dvs = 2.0 * rho[c] * vs[c];
+        gvp[c] = dl_dvp * glam[c];
+        gvs[c] = dl_dvs * glam[c] + dm_dvs * gmu[c];
+    }
+}
+
 void orc_velocities(int64_t n, const double *lam, const double *mu, const double *rho,
                     double *vp, double *vs)
 {

@@ -40,6 +40,11 @@ typedef struct {
 /* Eq. 3-4: lambda = rho Vp^2 - 2 rho Vs^2, mu = rho Vs^2.  Pinned by closed form. */
 void orc_moduli(int64_t n, const double *vp, const double *vs, const double *rho,
                 double *lam, double *mu);
+/* Chain rule of Eq. 3-4: dJ/dVp = 2 rho Vp dJ/dlambda,
+ * dJ/dVs = -4 rho Vs dJ/dlambda + 2 rho Vs dJ/dmu.  Pinned by central
+ * differences of the misfit in velocity space. */
+void orc_moduli_grad(int64_t n, const double *vp, const double *vs, const double *rho,
+                     const double *glam, const double *gmu, double *gvp, double *gvs);
 /* Eq. 11-12: Vp = sqrt((lambda+2mu)/rho), Vs = sqrt(mu/rho). */
 void orc_velocities(int64_t n, const double *lam, const double *mu, const double *rho,
                     double *vp, double *vs);

@@ -61,7 +61,7 @@ class Bounds(C.Structure):
 
 EXPORTS = ["bhfwi_create", "bhfwi_destroy", "bhfwi_last_error", "bhfwi_sizes",
            "bhfwi_set_tune", "bhfwi_get_tune", "bhfwi_autotune", "bhfwi_kernel_times",
-           "bhfwi_moduli", "bhfwi_velocities",
+           "bhfwi_moduli", "bhfwi_moduli_grad", "bhfwi_velocities",
            "bhfwi_fwd_model", "bhfwi_misfit", "bhfwi_adjoint_model", "bhfwi_gradient",
            "bhfwi_precondition", "bhfwi_update"]
 
@@ -91,10 +91,11 @@ def load(path: str = LIB_PATH):
                                  C.POINTER(C.c_float)]
     L.bhfwi_moduli.argtypes = [V, I64, P, P, P, P, P]
     L.bhfwi_velocities.argtypes = [V, I64, P, P, P, P, P]
+    L.bhfwi_moduli_grad.argtypes = [V, I64, P, P, P, P, P, P, P]
     L.bhfwi_fwd_model.argtypes = [P, V, P, P, P, P, P, P, I64, P, I64, I32]
-    L.bhfwi_misfit.argtypes = [P, V, P, P, P, P]
+    L.bhfwi_misfit.argtypes = [P, V, P, P, P, P, I32]
     L.bhfwi_adjoint_model.argtypes = [P, V, P, P, P, P, P, P, I64, P, I64, P, I64, P]
-    L.bhfwi_gradient.argtypes = [P, V, P, P, P, P, P]
+    L.bhfwi_gradient.argtypes = [P, V, P, P, P, P, P, I32]
     L.bhfwi_precondition.argtypes = [P, V, I64, P, P, F, P, P]
     L.bhfwi_update.argtypes = [P, V, I64, P, P, P, P, P, P, F, F, C.POINTER(Bounds), P]
     for name in EXPORTS:
@@ -138,6 +139,14 @@ def moduli(vp, vs, rho, out=None):
     _check(load().bhfwi_moduli(_stream(), vp.numel(), _f32(vp), _f32(vs), _f32(rho),
                                _f32(lam), _f32(mu)))
     return lam, mu
+
+
+def moduli_grad(vp, vs, rho, g_lam, g_mu):
+    """Chain rule of Eq. 3-4: (g_vp, g_vs) from (g_lam, g_mu)."""
+    g_vp, g_vs = torch.empty_like(vp), torch.empty_like(vp)
+    _check(load().bhfwi_moduli_grad(_stream(), vp.numel(), _f32(vp), _f32(vs), _f32(rho),
+                                    _f32(g_lam), _f32(g_mu), _f32(g_vp), _f32(g_vs)))
+    return g_vp, g_vs
 
 
 def velocities(lam, mu, rho, out=None):
@@ -262,7 +271,8 @@ class Survey:
 
     # ------------------------------------------------------------ workspaces
     def workspace(self, name):
-        """Device scratch owned by this survey (torch allocations, reused)."""
+        """Device scratch of this survey (torch allocations, reused; a pool
+        shared by several surveys can be installed with use_workspaces)."""
         nbytes = {"fwd": self.sizes.fwd_ws_bytes, "ckpt": self.sizes.ckpt_bytes,
                   "adj": self.sizes.adj_ws_bytes}[name]
         t = self._ws.get(name)
@@ -270,6 +280,16 @@ class Survey:
             t = torch.empty(max(1, nbytes), dtype=torch.uint8, device=self.device)
             self._ws[name] = t
         return t
+
+    def use_workspaces(self, pool):
+        """Share device scratch: pool maps 'fwd', 'ckpt', 'adj' to uint8 tensors
+        at least as large as this survey needs."""
+        for name in ("fwd", "ckpt", "adj"):
+            need = {"fwd": self.sizes.fwd_ws_bytes, "ckpt": self.sizes.ckpt_bytes,
+                    "adj": self.sizes.adj_ws_bytes}[name]
+            if pool[name].numel() < need:
+                raise ValueError("shared %s workspace too small" % name)
+        self._ws = dict(pool)
 
     def free_workspaces(self):
         self._ws.clear()
@@ -292,15 +312,17 @@ class Survey:
         _check(rc, self._h)
         return traces
 
-    def misfit(self, traces, observed, resid=None):
-        """Eq. 1 and 5: returns (resid, J as a 0-d float64 device tensor)."""
+    def misfit(self, traces, observed, resid=None, J=None, accumulate=False):
+        """Eq. 1 and 5: returns (resid, J as a 0-d float64 device tensor); with
+        accumulate, J (given) is added to."""
         z = self.sizes
         if resid is None:
             resid = torch.empty(z.trace_elems, dtype=torch.float32, device=self.device)
-        J = torch.empty((), dtype=torch.float64, device=self.device)
+        if J is None:
+            J = torch.empty((), dtype=torch.float64, device=self.device)
         _check(load().bhfwi_misfit(self._h, _stream(), _f32(traces, z.trace_elems),
                                    _f32(observed, z.trace_elems), _f32(resid, z.trace_elems),
-                                   _ptr(J)), self._h)
+                                   _ptr(J), 1 if accumulate else 0), self._h)
         return resid, J
 
     def adjoint_model(self, lam, mu, rho, wavelet, resid, ckpt=None, acc=None):
@@ -320,15 +342,17 @@ class Survey:
         _check(rc, self._h)
         return acc
 
-    def gradient(self, mu, acc, out=None):
-        """Gradient finalize: returns (g_lam, g_mu, illum) on the global grid."""
+    def gradient(self, mu, acc, out=None, accumulate=False):
+        """Gradient finalize: returns (g_lam, g_mu, illum) on the global grid
+        (added to `out` when accumulate)."""
         shp = self.model_shape
         if out is None:
             out = tuple(torch.empty(shp, dtype=torch.float32, device=self.device)
                         for _ in range(3))
         g_lam, g_mu, illum = out
         _check(load().bhfwi_gradient(self._h, _stream(), _f32(mu), _f32(acc), _f32(g_lam),
-                                     _f32(g_mu), _f32(illum)), self._h)
+                                     _f32(g_mu), _f32(illum), 1 if accumulate else 0),
+               self._h)
         return g_lam, g_mu, illum
 
     def precondition(self, illum, mask, eps, g_lam, g_mu):

@@ -35,3 +35,26 @@ class BoreholeFWI(torch.autograd.Function):
         survey.last_illum = illum
         ctx.ckpt = None
         return g_lam, g_mu, None, None, None
+
+
+class Moduli(torch.autograd.Function):
+    """Eq. 3-4 as a differentiable op (forward and chain rule in the library),
+    so that BoreholeFWI gradients reach a (Vp, Vs) parameterisation."""
+
+    @staticmethod
+    def forward(ctx, vp, vs, rho):
+        from ._lib import moduli
+        lam, mu = moduli(vp.detach().contiguous(), vs.detach().contiguous(), rho)
+        ctx.save_for_backward(vp.detach(), vs.detach(), rho)
+        return lam, mu
+
+    @staticmethod
+    def backward(ctx, g_lam, g_mu):
+        from ._lib import moduli_grad
+        vp, vs, rho = ctx.saved_tensors
+        if g_lam is None:
+            g_lam = torch.zeros_like(vp)
+        if g_mu is None:
+            g_mu = torch.zeros_like(vp)
+        g_vp, g_vs = moduli_grad(vp, vs, rho, g_lam.contiguous(), g_mu.contiguous())
+        return g_vp, g_vs, None

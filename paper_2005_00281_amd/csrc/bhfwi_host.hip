@@ -741,6 +741,18 @@ int bhfwi_moduli(void* stream, int64_t n, const float* vp, const float* vs, cons
     return hipGetLastError() == hipSuccess ? BHFWI_OK : BHFWI_EHIP;
 }
 
+int bhfwi_moduli_grad(void* stream, int64_t n, const float* vp, const float* vs,
+                      const float* rho, const float* g_lam, const float* g_mu, float* g_vp,
+                      float* g_vs)
+{
+    if (n < 0 || (n > 0 && (!vp || !vs || !rho || !g_lam || !g_mu || !g_vp || !g_vs)))
+        return BHFWI_EINVAL;
+    if (n == 0) return BHFWI_OK;
+    hipLaunchKernelGGL(bhfwi::k_moduli_grad, dim3(grid1d(n)), dim3(256), 0, (hipStream_t)stream,
+                       (long long)n, vp, vs, rho, g_lam, g_mu, g_vp, g_vs);
+    return hipGetLastError() == hipSuccess ? BHFWI_OK : BHFWI_EHIP;
+}
+
 int bhfwi_velocities(void* stream, int64_t n, const float* lam, const float* mu,
                      const float* rho, float* vp, float* vs)
 {
@@ -790,7 +802,7 @@ int bhfwi_fwd_model(bhfwi_ctx* c, void* stream, const float* lam, const float* m
 }
 
 int bhfwi_misfit(bhfwi_ctx* c, void* stream, const float* traces, const float* observed,
-                 float* resid, double* J_dev)
+                 float* resid, double* J_dev, int32_t accumulate)
 {
     if (int rc = check_ctx(c)) return rc;
     if (!traces || !observed || !resid || !J_dev)
@@ -800,7 +812,8 @@ int bhfwi_misfit(bhfwi_ctx* c, void* stream, const float* traces, const float* o
     double* part = (double*)((float*)c->d_scratch + 4 * kPartBlocks);
     hipLaunchKernelGGL(bhfwi::k_misfit_partial, dim3(nb), dim3(256), 0, st,
                        (long long)c->trace_len, traces, observed, resid, part);
-    hipLaunchKernelGGL(bhfwi::k_sum_partials, dim3(1), dim3(256), 0, st, nb, part, J_dev);
+    hipLaunchKernelGGL(bhfwi::k_sum_partials, dim3(1), dim3(256), 0, st, nb, part, J_dev,
+                       accumulate ? 1 : 0);
     HIPOK(c, hipGetLastError());
     return BHFWI_OK;
 }
@@ -866,15 +879,17 @@ int bhfwi_adjoint_model(bhfwi_ctx* c, void* stream, const float* lam, const floa
 }
 
 int bhfwi_gradient(bhfwi_ctx* c, void* stream, const float* mu, const float* acc, float* g_lam,
-                   float* g_mu, float* illum)
+                   float* g_mu, float* illum, int32_t accumulate)
 {
     if (int rc = check_ctx(c)) return rc;
     if (!mu || !acc || !g_lam || !g_mu || !illum)
         return fail(c, BHFWI_EINVAL, "gradient: null pointer");
     hipStream_t st = (hipStream_t)stream;
-    launch_fill(st, g_lam, c->model_len, 0.0f);
-    launch_fill(st, g_mu, c->model_len, 0.0f);
-    launch_fill(st, illum, c->model_len, 0.0f);
+    if (!accumulate) {
+        launch_fill(st, g_lam, c->model_len, 0.0f);
+        launch_fill(st, g_mu, c->model_len, 0.0f);
+        launch_fill(st, illum, c->model_len, 0.0f);
+    }
     for (int s = 0; s < c->nshot; ++s) {
         const int64_t cells = (int64_t)c->sd[s].NR * c->sd[s].NZ;
         hipLaunchKernelGGL(bhfwi::k_finalize_shot, dim3(grid1d(cells)), dim3(256), 0, st,

@@ -657,6 +657,19 @@ __global__ void k_moduli(long long n, const float* __restrict__ vp, const float*
     }
 }
 
+__global__ void k_moduli_grad(long long n, const float* __restrict__ vp,
+                              const float* __restrict__ vs, const float* __restrict__ rho,
+                              const float* __restrict__ g_lam, const float* __restrict__ g_mu,
+                              float* __restrict__ g_vp, float* __restrict__ g_vs)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const float r2 = 2.0f * rho[i], gl = g_lam[i];
+        g_vp[i] = r2 * vp[i] * gl;
+        g_vs[i] = r2 * vs[i] * (g_mu[i] - 2.0f * gl);
+    }
+}
+
 __global__ void k_velocities(long long n, const float* __restrict__ lam,
                              const float* __restrict__ mu, const float* __restrict__ rho,
                              float* __restrict__ vp, float* __restrict__ vs)
@@ -692,7 +705,7 @@ k_misfit_partial(long long n, const float* __restrict__ d, const float* __restri
 }
 
 __global__ void __launch_bounds__(256)
-k_sum_partials(int np, const double* __restrict__ part, double* __restrict__ out)
+k_sum_partials(int np, const double* __restrict__ part, double* __restrict__ out, int add)
 {
     __shared__ double sh[256];
     double s = 0.0;
@@ -703,7 +716,7 @@ k_sum_partials(int np, const double* __restrict__ part, double* __restrict__ out
         if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = sh[0];
+    if (threadIdx.x == 0) *out = add ? *out + sh[0] : sh[0];
 }
 
 // Add one shot's accumulators into the global grids; folds the tau_rz-node

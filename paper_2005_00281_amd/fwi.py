@@ -3,11 +3,13 @@ figure: forward modelling, data residue, adjoint modelling, gradient,
 model update), every step on the GPU through libbhfwi.
 
 The model is carried as P and S velocities (density fixed, as the Method
-section treats it); each iteration converts them to moduli (Eq. 3-4), runs the
-forward with checkpoints (Eq. 2), the misfit (Eq. 1, 5), the adjoint with the
-fused correlation (Eq. 6-8), the gradient finalize, the diagonal
-preconditioner, the update (Eq. 9-10) and the conversion back (Eq. 11-12).
-All buffers persist across iterations so that the captured HIP graphs replay.
+section treats it); each iteration converts them to moduli (Eq. 3-4), runs for
+each group of shots the forward with checkpoints (Eq. 2), the misfit (Eq. 1,
+5), the adjoint with the fused correlation (Eq. 6-8) and the gradient
+finalize (summed over groups), then the diagonal preconditioner, the update
+(Eq. 9-10) and the conversion back (Eq. 11-12).  All buffers persist across
+iterations so that the captured HIP graphs replay; the groups share one set
+of workspaces.
 """
 from __future__ import annotations
 
@@ -17,37 +19,57 @@ from . import _lib
 
 
 class Inversion:
-    def __init__(self, survey, vp, vs, rho, wavelet, observed, mask, eps=1e-3, eta=0.02,
+    def __init__(self, surveys, vp, vs, rho, wavelets, observed, mask, eps=1e-3, eta=0.02,
                  bounds=(1000.0, 7000.0, 300.0, 4500.0)):
-        self.sv = survey
+        if not isinstance(surveys, (list, tuple)):
+            surveys, wavelets, observed = [surveys], [wavelets], [observed]
+        self.surveys = list(surveys)
         self.vp, self.vs, self.rho = vp, vs, rho
-        self.wavelet, self.observed = wavelet, observed
+        self.wavelets, self.observed = list(wavelets), list(observed)
         self.mask = mask
         self.eps, self.eta, self.bounds = float(eps), float(eta), tuple(bounds)
-        z = survey.sizes
         dev = vp.device
+        need = {k: max(getattr(sv.sizes, k + "_bytes") for sv in self.surveys)
+                for k in ("fwd_ws", "ckpt", "adj_ws")}
+        self.pool = {"fwd": torch.empty(max(1, need["fwd_ws"]), dtype=torch.uint8, device=dev),
+                     "ckpt": torch.empty(max(1, need["ckpt"]), dtype=torch.uint8, device=dev),
+                     "adj": torch.empty(max(1, need["adj_ws"]), dtype=torch.uint8, device=dev)}
+        for sv in self.surveys:
+            sv.use_workspaces(self.pool)
+        self.acc = torch.empty(max(sv.sizes.acc_elems for sv in self.surveys),
+                               dtype=torch.float32, device=dev)
+        self.traces = [torch.empty(sv.sizes.trace_elems, dtype=torch.float32, device=dev)
+                       for sv in self.surveys]
+        self.resid = [torch.empty_like(t) for t in self.traces]
         self.lam = torch.empty_like(vp)
         self.mu = torch.empty_like(vp)
-        self.traces = torch.empty(z.trace_elems, dtype=torch.float32, device=dev)
-        self.resid = torch.empty(z.trace_elems, dtype=torch.float32, device=dev)
-        self.acc = torch.empty(z.acc_elems, dtype=torch.float32, device=dev)
         self.g_lam = torch.empty_like(vp)
         self.g_mu = torch.empty_like(vp)
         self.illum = torch.empty_like(vp)
-        self.ckpt = survey.workspace("ckpt")
+        self.J = torch.zeros((), dtype=torch.float64, device=dev)
+
+    def gradient(self):
+        """Eq. 2, 1, 5, 6-8 and the finalize over every group; leaves the
+        misfit in self.J and the raw gradient and illumination on the model."""
+        _lib.moduli(self.vp, self.vs, self.rho, out=(self.lam, self.mu))
+        for g, sv in enumerate(self.surveys):
+            ckpt = self.pool["ckpt"]
+            sv.fwd_model(self.lam, self.mu, self.rho, self.wavelets[g], store_ckpt=True,
+                         ckpt=ckpt, traces=self.traces[g])
+            sv.misfit(self.traces[g], self.observed[g], resid=self.resid[g], J=self.J,
+                      accumulate=g > 0)
+            sv.adjoint_model(self.lam, self.mu, self.rho, self.wavelets[g], self.resid[g],
+                             ckpt=ckpt, acc=self.acc)
+            sv.gradient(self.mu, self.acc, out=(self.g_lam, self.g_mu, self.illum),
+                        accumulate=g > 0)
+        return self.J
 
     def iterate(self):
         """One iteration; returns (J, alpha) as device scalars (no host sync)."""
-        sv = self.sv
-        _lib.moduli(self.vp, self.vs, self.rho, out=(self.lam, self.mu))
-        sv.fwd_model(self.lam, self.mu, self.rho, self.wavelet, store_ckpt=True,
-                     ckpt=self.ckpt, traces=self.traces)
-        _, J = sv.misfit(self.traces, self.observed, resid=self.resid)
-        sv.adjoint_model(self.lam, self.mu, self.rho, self.wavelet, self.resid, ckpt=self.ckpt,
-                         acc=self.acc)
-        sv.gradient(self.mu, self.acc, out=(self.g_lam, self.g_mu, self.illum))
+        self.gradient()
+        sv = self.surveys[0]
         sv.precondition(self.illum, self.mask, self.eps, self.g_lam, self.g_mu)
-        alpha = sv.update(self.lam, self.mu, self.rho, self.g_lam, self.g_mu, self.mask, self.eta,
-                          bounds=self.bounds)
+        alpha = sv.update(self.lam, self.mu, self.rho, self.g_lam, self.g_mu, self.mask,
+                          self.eta, bounds=self.bounds)
         _lib.velocities(self.lam, self.mu, self.rho, out=(self.vp, self.vs))
-        return J, alpha
+        return self.J, alpha

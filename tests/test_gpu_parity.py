@@ -340,3 +340,39 @@ def test_autotune_picks_a_valid_shape_and_stays_correct(tmp_path):
     sv2 = survey(w, ckpt=64)
     again = sv2.autotune(lam, mu, rho, wav, cache=cache)  # served from the cache
     assert again["tune"] == entry["tune"]
+
+
+def test_shot_groups_sum_to_the_single_survey_gradient():
+    """Two shot groups evaluated one after the other with shared workspaces
+    (misfit and gradient accumulated) give the one-survey result to FP32
+    rounding."""
+    from paper_2005_00281_amd.fwi import Inversion
+    w = _multi_shot_workload()
+    _say("shot groups")
+    lam, mu, rho = gpu_models(w, "true")
+    vp, vs = f32(w.vp_start), f32(w.vs_start)
+    mask = torch.as_tensor(w.mask, device=_dev())
+
+    def build(groups):
+        svs, wavs, obss = [], [], []
+        for g in groups:
+            import copy
+            w1 = copy.copy(w)
+            w1.shots = [w.shots[s] for s in g]
+            sv = survey(w1, ckpt=50, tune=T(tb=4, tbw=8))
+            wav = sv.pack_wavelets([w.shots[s].wavelet for s in g])
+            obss.append(sv.fwd_model(lam, mu, rho, wav).clone())
+            sv.free_workspaces()
+            svs.append(sv)
+            wavs.append(wav)
+        return Inversion(svs, vp.clone(), vs.clone(), rho, wavs, obss, mask)
+
+    one = build([[0, 1, 2]])
+    two = build([[0, 2], [1]])
+    J1 = one.gradient().item()
+    g1 = [t.cpu().numpy() for t in (one.g_lam, one.g_mu, one.illum)]
+    J2 = two.gradient().item()
+    g2 = [t.cpu().numpy() for t in (two.g_lam, two.g_mu, two.illum)]
+    assert abs(J1 - J2) <= 1e-12 * abs(J1)
+    for a, b in zip(g1, g2):
+        assert rel_l2(b, a) <= 1e-6

@@ -129,3 +129,30 @@ def test_gradient_vanishes_at_true_model():
     assert J == 0.0
     gl, gm, _ = oracle.gradient(g, lt, mt, rho, sh.wavelet, r, seg=30)
     assert not gl.any() and not gm.any()
+
+
+def test_velocity_gradient_chain_rule_matches_differences():
+    """dJ/dVp, dJ/dVs from the oracle's chain rule of Eq. 3-4 against central
+    differences of the misfit in velocity space (directional, formation)."""
+    w, sh, g = _tiny(nr=12, nz=24, p=4, nt=150)
+    rho = np.ascontiguousarray(w.rho)
+    lt, mt, _ = oracle_models(w, 0, "true")
+    dobs = oracle.forward(g, lt, mt, rho, sh.wavelet)
+
+    def J(vp, vs):
+        lam, mu = oracle.moduli(vp, vs, rho)
+        return oracle.misfit(oracle.forward(g, lam, mu, rho, sh.wavelet), dobs)[0]
+
+    vp, vs = w.vp_start.copy(), w.vs_start.copy()
+    lam, mu = oracle.moduli(vp, vs, rho)
+    _, r = oracle.misfit(oracle.forward(g, lam, mu, rho, sh.wavelet), dobs)
+    gl, gm, _ = oracle.gradient(g, lam, mu, rho, sh.wavelet, r, seg=40)
+    gvp, gvs = oracle.moduli_grad(vp, vs, rho, gl, gm)
+    rng = np.random.default_rng(8)
+    form = w.mask.astype(bool)
+    dvp = rng.standard_normal(vp.shape) * form * vp
+    dvs = rng.standard_normal(vs.shape) * form * vs
+    eps = 1e-6
+    fd = (J(vp + eps * dvp, vs + eps * dvs) - J(vp - eps * dvp, vs - eps * dvs)) / (2 * eps)
+    an = float((gvp * dvp).sum() + (gvs * dvs).sum())
+    assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)

@@ -1,0 +1,36 @@
+"""HBM planner: every shot lands in exactly one group, groups fit the budget,
+and the chosen checkpoint interval minimises checkpoint + history memory."""
+import pytest
+
+import workloads
+from paper_2005_00281_amd import plan
+
+
+@pytest.mark.parametrize("name,budget", [("c3", 240e9), ("c4", 240e9), ("c4", 120e9)])
+def test_groups_partition_and_fit(name, budget):
+    w = workloads.make(name)
+    p = plan.plan(w.shots, budget)
+    flat = sorted(s for g in p.groups for s in g)
+    assert flat == list(range(len(w.shots)))
+    assert p.bytes_workspace + p.bytes_traces <= budget
+    assert len(p.groups) == len(p.ckpt_every)
+
+
+def test_interval_minimises_memory():
+    w = workloads.make("c3")
+    K = plan.best_interval(w.shots)
+    mem = lambda k: sum(plan.workspace_bytes(w.shots, k).values())
+    for other in (K // 2, K - 8, K + 8, 2 * K):
+        assert mem(K) <= mem(other)
+
+
+def test_single_shot_keeps_requested_interval():
+    w = workloads.make("c2")
+    p = plan.plan(w.shots, 1e12, ckpt_every=250)
+    assert p.groups == [[0]] and p.ckpt_every == [250]
+
+
+def test_impossible_budget_raises():
+    w = workloads.make("c2")
+    with pytest.raises(MemoryError):
+        plan.plan(w.shots, 1e6)
