@@ -32,6 +32,54 @@ ADJ_BYTES_PER_CELL_STEP = 92
 FWD_BYTES_PER_CELL_STEP = 60
 REC_BYTES_PER_CELL_STEP = 68
 
+# HBM traffic of the adjoint kernel, from two rocprofv3 --pmc runs of
+# "bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-autotune" (FETCH_SIZE,
+# then WRITE_SIZE; mean KiB per dispatch).  The counters are scaled by what
+# they read for a device copy of 1 GiB from cold memory (bench.py
+# --copy-calibration): FETCH_SIZE 524307 KiB for 1048576 KiB read,
+# WRITE_SIZE 1048576 KiB for 1048576 KiB written.  An entry holds only for
+# the kernel sources it was measured on (SHA-256 of the files below) and the
+# same kernel shape, tile map and workload; otherwise traffic is null.
+PMC_FETCH_SCALE = 1048576.0 / 524307.125
+PMC_WRITE_SCALE = 1048576.0 / 1048576.0
+PMC_SOURCES = ("paper_2005_00281_amd/csrc/bhfwi_tb_adj.hip",
+               "paper_2005_00281_amd/csrc/bhfwi_tb_fwd.hip",
+               "paper_2005_00281_amd/csrc/bhfwi_internal.h")
+PMC_TRAFFIC = {
+    # (kernel, tile_map, workload, sources sha256[:16]): (FETCH KiB, WRITE KiB)
+    ("k_adj_tb<4, 16, 8>", 1, "c2", "c81676813632d2fe"): (37680.81, 31162.98),
+}
+
+
+def kernel_sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in PMC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def copy_bandwidth():
+    """Device-to-device copy of 2 GiB (reads + writes counted): the practical
+    HBM ceiling on this GPU, best of 5."""
+    import torch
+    n = 1 << 29
+    src = torch.ones(n, device="cuda")
+    dst = torch.empty(n, device="cuda")
+    dst.copy_(src)
+    best = 1e30
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * 4 * n / (best * 1e-3) / 1e9
+
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
@@ -88,6 +136,8 @@ def main():
     ap.add_argument("--tb", type=int, default=-1,
                     help="forward steps per launch in the LDS-tiled kernels (-1: default)")
     ap.add_argument("--tb-rows", type=int, default=0)
+    ap.add_argument("--tb-waves", type=int, default=0)
+    ap.add_argument("--tile-map", type=int, default=-1)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -142,7 +192,8 @@ def main():
         for sv in surveys:
             sv.set_tune(rows_per_wave=args.rows or None,
                         tb_steps=args.tb if args.tb >= 0 else None,
-                        tb_rows=args.tb_rows or None)
+                        tb_rows=args.tb_rows or None, tb_waves=args.tb_waves or None,
+                        tile_map=args.tile_map if args.tile_map >= 0 else None)
     else:
         lam_s, mu_s = P.moduli(f32(w.vp_start), f32(w.vs_start), rho)
         t_at = time.perf_counter()
@@ -199,8 +250,15 @@ def main():
     T = tune["tb_steps"]
     kname = ("k_adj_tb<%d, %d, %d>" % (T, tune["tb_rows"], tune["tb_waves"]) if T >= 2
              else "k_adj_step<%d>" % (tune["rows_per_wave"] if tune["rows_per_wave"] <= 4 else 0))
+    pmc = PMC_TRAFFIC.get((kname, tune.get("tile_map", 1), args.workload, kernel_sources_sha()))
+    traffic = (None if pmc is None
+               else int(1024 * (pmc[0] * PMC_FETCH_SCALE + pmc[1] * PMC_WRITE_SCALE)))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                "copy-calibrated)",
+                "traffic_GBs": (round(traffic / (adj_avg * 1e-3) / 1e9, 1)
+                                if traffic is not None else None),
                 "kernel": kname, "avg_launch_us": round(adj_avg * 1e3, 3),
                 "steps_per_launch": round(steps_per_launch, 3),
                 "bytes_per_launch": int(adj_bytes),
@@ -248,6 +306,9 @@ def main():
                  "form": "one shot per launch sequence, one step per launch (wave march, "
                          "2 rows per wave), no HIP graph, same checkpoint interval"}
 
+    copy_bw = copy_bandwidth()
+    log("device copy %.1f GB/s" % copy_bw)
+
     base = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -268,6 +329,7 @@ def main():
                    "tune": tune},
         "roofline": roofline,
         "iteration_hbm_frac_at_220B": round(it_frac, 4),
+        "copy_GBs": round(copy_bw, 1),
         "shots_iters_per_s": round(len(w.shots) / (ms * 1e-3), 4),
         "plain": plain,
         "batched_vs_plain": (round(len(w.shots) / (ms * 1e-3) / plain["shots_iters_per_s"], 3)

@@ -102,7 +102,29 @@ typedef struct {
                                  (tb_steps, tb_rows, tb_waves): (2|3|4, 16, 4),
                                  (2|3|4, 16, 8), (2|3|4|6, 24, 8),
                                  (4|6|8, 32, 8) */
+    int32_t tile_map;         /* order of the tiles of a temporally blocked launch:
+                                 0: axial tile fastest, workgroups in table order;
+                                 1: radial tile fastest, and each of the 8 XCDs of
+                                 the GPU walks one contiguous chunk of the table
+                                 so that tiles with overlapping halos share its L2 */
 } bhfwi_tune;
+
+/* Memory of one group of shots evaluated together (bhfwi_plan_bytes). */
+typedef struct {
+    int32_t ckpt_every;       /* checkpoint interval the figures are for */
+    int32_t pad_;
+    int64_t fwd_ws_bytes, ckpt_bytes, adj_ws_bytes, acc_bytes;  /* as bhfwi_sizes */
+    int64_t total_bytes;      /* their sum */
+} bhfwi_plan_bytes_t;
+
+/* Result of bhfwi_plan. */
+typedef struct {
+    int32_t ngroups;
+    int32_t pad_;
+    int64_t workspace_bytes;  /* workspaces shared by the groups: per kind the
+                                 maximum over groups, summed over kinds */
+    int64_t trace_bytes;      /* traces, residuals and observed data of all shots */
+} bhfwi_plan_info;
 
 /* Per-kernel time sums collected while tune.time_kernels is on: the forward
  * step of bhfwi_fwd_model, the recompute step (forward step storing v) and
@@ -142,6 +164,25 @@ int bhfwi_autotune(bhfwi_ctx *ctx, void *stream, const float *lam, const float *
                    const float *rho, const float *wavelet, float *traces, void *fwd_ws,
                    int64_t fwd_ws_bytes, void *adj_ws, int64_t adj_ws_bytes, float *acc,
                    int32_t probe_steps, bhfwi_tune *best, float *best_ms);
+
+/* HBM planner (host only; no device is touched).  One-level checkpointing
+ * of a group keeps ceil(nt_max/K) - 1 forward states of F floats and the
+ * velocity history of one K-step segment (2 K C floats for C cells), least
+ * near K = sqrt(nt_max F / (2 C)).
+ * bhfwi_plan_bytes: the workspace bytes of shots[0..nshot) as one context with
+ * interval ckpt_every, or with the memory-optimal multiple of 8 when
+ * ckpt_every <= 0 (the figures bhfwi_sizes reports for such a context).
+ * bhfwi_plan: splits the shots into the fewest groups (at most max_groups;
+ * <= 0: nshot), balanced longest-processing-time first on NR NZ nt, whose
+ * shared workspaces plus all trace buffers fit budget_bytes.  Outputs (host):
+ * group_of[s] for every shot (groups numbered from 0), ckpt_out[g] for every
+ * group (nshot entries suffice), *info.  BHFWI_ENOMEM when even nshot groups
+ * do not fit; BHFWI_EINVAL on bad sizes.  Text via bhfwi_last_error(NULL). */
+int bhfwi_plan_bytes(const bhfwi_shot *shots, int32_t nshot, int32_t ckpt_every,
+                     bhfwi_plan_bytes_t *out);
+int bhfwi_plan(const bhfwi_shot *shots, int32_t nshot, int64_t budget_bytes,
+               int32_t ckpt_every, int32_t max_groups, int32_t *group_of, int32_t *ckpt_out,
+               bhfwi_plan_info *info);
 
 /* Read (and with reset != 0 clear) the sums of bhfwi_kernel_times_t. */
 int bhfwi_kernel_times(bhfwi_ctx *ctx, bhfwi_kernel_times_t *out, int32_t reset);
@@ -201,9 +242,31 @@ int bhfwi_gradient(bhfwi_ctx *ctx, void *stream, const float *mu, const float *a
 /* Diagonal preconditioner (Numerical Examples section, Fig. 6): with
  * E = illum and Emax its maximum over mask cells, g <- g / (E + eps Emax) for
  * lam and mu on mask cells, 0 elsewhere.  n elements, device arrays;
- * mask is uint8 (1 = invert this cell). */
+ * mask is uint8 (1 = invert this cell).  gpg (device double, nullable)
+ * receives sum over mask cells of g . P g for both parameters, taken before
+ * the scaling (deterministic two-level sum): minus the slope of the misfit
+ * along the preconditioned step, as bhfwi_line_search needs it. */
 int bhfwi_precondition(bhfwi_ctx *ctx, void *stream, int64_t n, const float *illum,
-                       const uint8_t *mask, float eps, float *g_lam, float *g_mu);
+                       const uint8_t *mask, float eps, float *g_lam, float *g_mu, double *gpg);
+
+/* Device-side status: synchronises the stream and returns BHFWI_ENONFINITE
+ * (text via bhfwi_last_error) if any bhfwi_misfit or bhfwi_precondition
+ * since the last call met a non-finite sum (NaN or Inf in the traces or the
+ * gradients), clearing the flag; BHFWI_OK otherwise. */
+int bhfwi_status(bhfwi_ctx *ctx, void *stream);
+
+/* Step length of a parabolic line search along the preconditioned gradient
+ * (Eq. 9-10; the paper leaves the step rule open beyond letting alpha bound
+ * the greatest change).  Inputs, all device scalars: J0 the misfit of the
+ * current model, J1 the misfit after a trial update of length alpha1 (the
+ * greatest-change rule of bhfwi_update), gpg from bhfwi_precondition.  The
+ * parabola through J0 with slope -gpg and through J1 gives
+ * alpha = gpg alpha1^2 / (2 (J1 - J0 + gpg alpha1)), clamped to
+ * [alpha1/10, 3 alpha1] when that curvature is positive; otherwise alpha =
+ * alpha1 if J1 <= J0, else alpha1/2.  alpha1 <= 0 gives 0.  Writes alpha_out
+ * (device float) without synchronising. */
+int bhfwi_line_search(bhfwi_ctx *ctx, void *stream, const double *J0, const double *J1,
+                      const double *gpg, const float *alpha1, float *alpha_out);
 
 /* Velocity box applied after the update. */
 typedef struct {
@@ -213,11 +276,14 @@ typedef struct {
 /* Eq. 9-10 on mask cells: lam -= alpha g_lam, mu -= alpha g_mu, with one
  * alpha = eta / max(max|g_lam|/max|lam|, max|g_mu|/max|mu|) over mask cells
  * (the step controls the greatest change), or alpha = alpha_override when it
- * is > 0; then mu is clipped to rho [vs_min^2, vs_max^2] and lam + 2 mu to
- * rho [vp_min^2, vp_max^2].  alpha_out (device float, nullable) receives alpha. */
+ * is > 0, or alpha = *alpha_in (device float, nullable; takes precedence,
+ * e.g. the output of bhfwi_line_search); then mu is clipped to
+ * rho [vs_min^2, vs_max^2] and lam + 2 mu to rho [vp_min^2, vp_max^2].
+ * alpha_out (device float, nullable) receives alpha. */
 int bhfwi_update(bhfwi_ctx *ctx, void *stream, int64_t n, float *lam, float *mu,
                  const float *rho, const float *g_lam, const float *g_mu, const uint8_t *mask,
-                 float eta, float alpha_override, const bhfwi_bounds *bounds, float *alpha_out);
+                 float eta, float alpha_override, const float *alpha_in,
+                 const bhfwi_bounds *bounds, float *alpha_out);
 
 #ifdef __cplusplus
 }

@@ -74,6 +74,9 @@ def _load():
         lib.orc_propagate_adjoint.argtypes = [G, _D, _D, _D, _D, C.c_int32]
         lib.orc_propagate_adjoint.restype = C.c_int
         lib.orc_precondition.argtypes = [C.c_int64, _D, _U8, C.c_double, _D, _D]
+        lib.orc_precondition.restype = C.c_double
+        lib.orc_line_search.argtypes = [C.c_double] * 4
+        lib.orc_line_search.restype = C.c_double
         lib.orc_update.argtypes = [C.c_int64, _D, _D, _D, _D, _D, _U8, C.c_double,
                                    C.c_double, C.c_double, C.c_double, C.c_double,
                                    C.c_double]
@@ -218,14 +221,20 @@ def propagate(g: Geom, lam, mu, rho, state, nsteps, adjoint=False):
     return st
 
 
-def precondition(illum, mask, eps, g_lam, g_mu):
-    """Diagonal preconditioner P = 1/(E + eps max E) applied to both gradients."""
+def precondition(illum, mask, eps, g_lam, g_mu, return_gpg=False):
+    """Diagonal preconditioner P = 1/(E + eps max E) applied to both gradients;
+    with return_gpg also sum(g . P g) over mask cells."""
     il = _f64(illum)
     m = np.ascontiguousarray(mask, dtype=np.uint8)
     gl, gm = np.array(g_lam, np.float64, order="C"), np.array(g_mu, np.float64, order="C")
-    _load().orc_precondition(il.size, _p(il), m.ctypes.data_as(_U8), float(eps),
-                             _p(gl), _p(gm))
-    return gl, gm
+    gpg = _load().orc_precondition(il.size, _p(il), m.ctypes.data_as(_U8), float(eps),
+                                   _p(gl), _p(gm))
+    return (gl, gm, gpg) if return_gpg else (gl, gm)
+
+
+def line_search(J0, J1, gpg, alpha1):
+    """Parabolic step length (reading of the step rule of Eq. 9-10)."""
+    return _load().orc_line_search(float(J0), float(J1), float(gpg), float(alpha1))
 
 
 def update(lam, mu, rho, g_lam, g_mu, mask, eta, alpha_override=0.0,

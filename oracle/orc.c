@@ -642,10 +642,10 @@ int orc_propagate_adjoint(const orc_geom *g, const double *lam, const double *mu
     return 0;
 }
 
-void orc_precondition(int64_t n, const double *illum, const uint8_t *mask, double eps,
-                      double *g_lam, double *g_mu)
+double orc_precondition(int64_t n, const double *illum, const uint8_t *mask, double eps,
+                        double *g_lam, double *g_mu)
 {
-    double emax = 0.0;
+    double emax = 0.0, gpg = 0.0;
     for (int64_t c = 0; c < n; ++c)
         if (mask[c] && illum[c] > emax) emax = illum[c];
     for (int64_t c = 0; c < n; ++c) {
@@ -655,9 +655,29 @@ void orc_precondition(int64_t n, const double *illum, const uint8_t *mask, doubl
             continue;
         }
         double p = 1.0 / (illum[c] + eps * emax);
-        g_lam[c] *= p;
-        g_mu[c] *= p;
+        double pl = p * g_lam[c], pm = p * g_mu[c];
+        gpg += g_lam[c] * pl + g_mu[c] * pm;
+        g_lam[c] = pl;
+        g_mu[c] = pm;
     }
+    return gpg;
+}
+
+double orc_line_search(double J0, double J1, double gpg, double alpha1)
+{
+    /* Model the misfit along the step m - a*Pg as a quadratic q(a) through
+     * q(0) = J0 with q'(0) = -gpg and q(alpha1) = J1. */
+    if (!(alpha1 > 0)) return 0.0;
+    double slope = -gpg;
+    double curv = (J1 - J0 - slope * alpha1) / (alpha1 * alpha1);
+    if (curv > 0) {
+        double a = -slope / (2.0 * curv);
+        if (a < 0.1 * alpha1) a = 0.1 * alpha1;
+        if (a > 3.0 * alpha1) a = 3.0 * alpha1;
+        return a;
+    }
+    /* no interior minimum: keep the trial step if it helped, else halve it */
+    return J1 <= J0 ? alpha1 : 0.5 * alpha1;
 }
 
 double orc_update(int64_t n, double *lam, double *mu, const double *rho, const double *g_lam,

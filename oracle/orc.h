@@ -85,9 +85,19 @@ int orc_propagate_adjoint(const orc_geom *g, const double *lam, const double *mu
                           const double *rho, double *astate, int32_t nsteps);
 
 /* Diagonal preconditioner (reading of the Numerical Examples section and
- * Fig. 6): P = 1 / (E + eps * max_{mask} E); g <- P*g on mask cells, 0 elsewhere. */
-void orc_precondition(int64_t n, const double *illum, const uint8_t *mask, double eps,
-                      double *g_lam, double *g_mu);
+ * Fig. 6): P = 1 / (E + eps * max_{mask} E); g <- P*g on mask cells, 0 elsewhere.
+ * Returns sum over mask cells of g.(P g) (both parameters): minus the slope of
+ * the misfit along the preconditioned descent step. */
+double orc_precondition(int64_t n, const double *illum, const uint8_t *mask, double eps,
+                        double *g_lam, double *g_mu);
+
+/* Step length of the parabolic line search (reading of Eq. 9-10, whose alpha
+ * the paper leaves as a free choice): the quadratic through J0 (slope -gpg) at
+ * 0 and J1 at the trial step alpha1; its minimiser clamped to
+ * [alpha1/10, 3 alpha1] when the quadratic is convex, else alpha1 when
+ * J1 <= J0 and alpha1/2 otherwise; 0 when alpha1 <= 0.  Pinned by exact
+ * quadratics and by each branch. */
+double orc_line_search(double J0, double J1, double gpg, double alpha1);
 
 /* Eq. 9-10 with one alpha chosen so that the largest change relative to the
  * largest modulus is eta (alpha_override > 0 uses that alpha instead), then a

@@ -14,6 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbhfwi.so")
 
 BHFWI_STORE_CKPT = 1
+BHFWI_ENOMEM = -3
 _ERRORS = {-1: "EINVAL", -2: "ECFL", -3: "ENOMEM", -4: "EHIP", -5: "ENONFINITE",
            -6: "EUNSUPPORTED"}
 
@@ -45,7 +46,19 @@ class Sizes(C.Structure):
 class Tune(C.Structure):
     _fields_ = [("rows_per_wave", C.c_int32), ("waves_per_block", C.c_int32),
                 ("use_graph", C.c_int32), ("time_kernels", C.c_int32),
-                ("tb_steps", C.c_int32), ("tb_rows", C.c_int32), ("tb_waves", C.c_int32)]
+                ("tb_steps", C.c_int32), ("tb_rows", C.c_int32), ("tb_waves", C.c_int32),
+                ("tile_map", C.c_int32)]
+
+
+class PlanBytes(C.Structure):
+    _fields_ = [("ckpt_every", C.c_int32), ("pad_", C.c_int32), ("fwd_ws_bytes", C.c_int64),
+                ("ckpt_bytes", C.c_int64), ("adj_ws_bytes", C.c_int64), ("acc_bytes", C.c_int64),
+                ("total_bytes", C.c_int64)]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [("ngroups", C.c_int32), ("pad_", C.c_int32), ("workspace_bytes", C.c_int64),
+                ("trace_bytes", C.c_int64)]
 
 
 class KernelTimes(C.Structure):
@@ -63,7 +76,8 @@ EXPORTS = ["bhfwi_create", "bhfwi_destroy", "bhfwi_last_error", "bhfwi_sizes",
            "bhfwi_set_tune", "bhfwi_get_tune", "bhfwi_autotune", "bhfwi_kernel_times",
            "bhfwi_moduli", "bhfwi_moduli_grad", "bhfwi_velocities",
            "bhfwi_fwd_model", "bhfwi_misfit", "bhfwi_adjoint_model", "bhfwi_gradient",
-           "bhfwi_precondition", "bhfwi_update"]
+           "bhfwi_precondition", "bhfwi_status", "bhfwi_line_search", "bhfwi_update", "bhfwi_plan_bytes",
+           "bhfwi_plan"]
 
 _lib = None
 
@@ -96,8 +110,13 @@ def load(path: str = LIB_PATH):
     L.bhfwi_misfit.argtypes = [P, V, P, P, P, P, I32]
     L.bhfwi_adjoint_model.argtypes = [P, V, P, P, P, P, P, P, I64, P, I64, P, I64, P]
     L.bhfwi_gradient.argtypes = [P, V, P, P, P, P, P, I32]
-    L.bhfwi_precondition.argtypes = [P, V, I64, P, P, F, P, P]
-    L.bhfwi_update.argtypes = [P, V, I64, P, P, P, P, P, P, F, F, C.POINTER(Bounds), P]
+    L.bhfwi_precondition.argtypes = [P, V, I64, P, P, F, P, P, P]
+    L.bhfwi_line_search.argtypes = [P, V, P, P, P, P, P]
+    L.bhfwi_status.argtypes = [P, V]
+    L.bhfwi_plan_bytes.argtypes = [C.POINTER(Shot), I32, I32, C.POINTER(PlanBytes)]
+    L.bhfwi_plan.argtypes = [C.POINTER(Shot), I32, I64, I32, I32, C.POINTER(C.c_int32),
+                             C.POINTER(C.c_int32), C.POINTER(PlanInfo)]
+    L.bhfwi_update.argtypes = [P, V, I64, P, P, P, P, P, P, F, F, P, C.POINTER(Bounds), P]
     for name in EXPORTS:
         if name not in ("bhfwi_destroy", "bhfwi_last_error"):
             getattr(L, name).restype = C.c_int
@@ -124,6 +143,12 @@ def _f32(t, n=None):
         raise ValueError("expected a contiguous float32 device tensor")
     if n is not None and t.numel() < n:
         raise ValueError("tensor has %d elements, %d needed" % (t.numel(), n))
+    return C.c_void_p(t.data_ptr())
+
+
+def _f64(t):
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous float64 device tensor")
     return C.c_void_p(t.data_ptr())
 
 
@@ -157,6 +182,41 @@ def velocities(lam, mu, rho, out=None):
     return vp, vs
 
 
+def shot_array(shots, NZg=None):
+    """bhfwi_shot array and packed receiver rows for shots (see Survey)."""
+    arr = (Shot * len(shots))()
+    recs = []
+    for s, sh in enumerate(shots):
+        rk = np.asarray(sh.rec_k, np.int32)
+        NZ = sh.nz + 2 * sh.pz
+        arr[s] = Shot(sh.nr, sh.nz, sh.pr, sh.pz, sh.dr, sh.dz, sh.dt, sh.nt, sh.f0,
+                      sh.vmax, sh.src_k, len(rk), len(recs), 0,
+                      int(getattr(sh, "win_k0", 0)), NZg if NZg is not None else NZ)
+        recs.extend(int(x) for x in rk)
+    return arr, recs
+
+
+def plan_bytes(shots, ckpt_every=0):
+    """bhfwi_plan_bytes: workspace bytes of shots as one context."""
+    arr, _ = shot_array(shots)
+    out = PlanBytes()
+    _check(load().bhfwi_plan_bytes(arr, len(shots), int(ckpt_every or 0), C.byref(out)), None)
+    return out
+
+
+def plan(shots, budget_bytes, ckpt_every=0, max_groups=0):
+    """bhfwi_plan: (group of each shot, interval of each group, PlanInfo)."""
+    arr, _ = shot_array(shots)
+    n = len(shots)
+    gof, kout, info = (C.c_int32 * n)(), (C.c_int32 * n)(), PlanInfo()
+    rc = load().bhfwi_plan(arr, n, int(budget_bytes), int(ckpt_every or 0), int(max_groups or 0),
+                           gof, kout, C.byref(info))
+    if rc == BHFWI_ENOMEM:
+        raise MemoryError("no grouping of %d shots fits %.1f GB" % (n, budget_bytes / 1e9))
+    _check(rc, None)
+    return list(gof), list(kout[:info.ngroups]), info
+
+
 class Survey:
     """A set of shots over one global model, bound to one HIP device.
 
@@ -168,16 +228,10 @@ class Survey:
         L = load()
         self.model_shape = tuple(int(x) for x in model_shape)
         NRg, NZg = self.model_shape
-        arr = (Shot * len(shots))()
-        recs = []
         for s, sh in enumerate(shots):
-            rk = np.asarray(sh.rec_k, np.int32)
-            NR, NZ = sh.nr + sh.pr, sh.nz + 2 * sh.pz
-            if NR > NRg:
+            if sh.nr + sh.pr > NRg:
                 raise ValueError("shot %d has more radial rows than the model" % s)
-            arr[s] = Shot(sh.nr, sh.nz, sh.pr, sh.pz, sh.dr, sh.dz, sh.dt, sh.nt, sh.f0,
-                          sh.vmax, sh.src_k, len(rk), len(recs), 0, int(sh.win_k0), NZg)
-            recs.extend(int(x) for x in rk)
+        arr, recs = shot_array(shots, NZg)
         rec_arr = (C.c_int32 * max(1, len(recs)))(*recs)
         h = C.c_void_p()
         rc = L.bhfwi_create(C.byref(h), int(device), arr, len(shots), rec_arr, len(recs),
@@ -198,17 +252,16 @@ class Survey:
             self._h = None
 
     # ---------------------------------------------------------------- tuning
-    def set_tune(self, rows_per_wave=None, waves_per_block=None, use_graph=None,
-                 time_kernels=None, tb_steps=None, tb_rows=None, tb_waves=None):
-        """Change any subset of the tunables (None keeps the current value)."""
+    def set_tune(self, **kw):
+        """Change any subset of the bhfwi_tune fields (a value of None keeps
+        the current one)."""
+        names = [n for n, _ in Tune._fields_]
+        bad = set(kw) - set(names)
+        if bad:
+            raise TypeError("unknown tunables %s" % sorted(bad))
         cur = Tune()
         _check(load().bhfwi_get_tune(self._h, C.byref(cur)), self._h)
-        new = {}
-        for name, v in (("rows_per_wave", rows_per_wave), ("waves_per_block", waves_per_block),
-                        ("use_graph", use_graph), ("time_kernels", time_kernels),
-                        ("tb_steps", tb_steps), ("tb_rows", tb_rows), ("tb_waves", tb_waves)):
-            new[name] = int(getattr(cur, name) if v is None else v)
-        t = Tune(**new)
+        t = Tune(**{n: int(getattr(cur, n) if kw.get(n) is None else kw[n]) for n in names})
         _check(load().bhfwi_set_tune(self._h, C.byref(t)), self._h)
         _check(load().bhfwi_sizes(self._h, C.byref(self.sizes)), self._h)
 
@@ -355,23 +408,38 @@ class Survey:
                self._h)
         return g_lam, g_mu, illum
 
-    def precondition(self, illum, mask, eps, g_lam, g_mu):
-        """Diagonal preconditioner, in place on g_lam and g_mu."""
+    def precondition(self, illum, mask, eps, g_lam, g_mu, gpg=None):
+        """Diagonal preconditioner, in place on g_lam and g_mu; with gpg (a
+        float64 device scalar) also the sum of g . P g over mask cells."""
         if mask.dtype != torch.uint8:
             raise ValueError("mask must be uint8")
         _check(load().bhfwi_precondition(self._h, _stream(), illum.numel(), _f32(illum),
-                                         _ptr(mask), float(eps), _f32(g_lam), _f32(g_mu)),
-               self._h)
+                                         _ptr(mask), float(eps), _f32(g_lam), _f32(g_mu),
+                                         _f64(gpg) if gpg is not None else None), self._h)
         return g_lam, g_mu
 
+    def status(self):
+        """bhfwi_status on the current stream: raises on non-finite data."""
+        _check(load().bhfwi_status(self._h, _stream()), self._h)
+
+    def line_search(self, J0, J1, gpg, alpha1, out=None):
+        """Parabolic step length from device scalars (bhfwi_line_search)."""
+        out = torch.empty((), dtype=torch.float32, device=self.device) if out is None else out
+        _check(load().bhfwi_line_search(self._h, _stream(), _f64(J0), _f64(J1), _f64(gpg),
+                                        _f32(alpha1), _f32(out)), self._h)
+        return out
+
     def update(self, lam, mu, rho, g_lam, g_mu, mask, eta, alpha_override=0.0,
-               bounds=(0.0, 1e30, 0.0, 1e30)):
-        """Eq. 9-10 in place on lam, mu; returns alpha as a device tensor."""
+               bounds=(0.0, 1e30, 0.0, 1e30), alpha_in=None):
+        """Eq. 9-10 in place on lam, mu; returns alpha as a device tensor.
+        alpha_in (float32 device scalar) sets alpha directly."""
         alpha = torch.empty((), dtype=torch.float32, device=self.device)
         b = Bounds(*[float(x) for x in bounds])
         _check(load().bhfwi_update(self._h, _stream(), lam.numel(), _f32(lam), _f32(mu),
                                    _f32(rho), _f32(g_lam), _f32(g_mu), _ptr(mask), float(eta),
-                                   float(alpha_override), C.byref(b), _ptr(alpha)), self._h)
+                                   float(alpha_override),
+                                   _f32(alpha_in) if alpha_in is not None else None,
+                                   C.byref(b), _ptr(alpha)), self._h)
         return alpha
 
     # ---------------------------------------------------------------- layout

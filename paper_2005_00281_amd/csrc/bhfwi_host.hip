@@ -23,6 +23,66 @@ constexpr int64_t kAlign = 64;     // floats (256 bytes) between packed blocks
 
 int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// Packed lengths (floats) of one shot: its cells, forward state (6 fields and
+// 4 PML memories per strip) and adjoint state (6 fields and 5 per strip).
+struct ShotLens {
+    int64_t cells, fst, ast;
+};
+
+ShotLens shot_lens(const bhfwi_shot& h)
+{
+    const int64_t NR = (int64_t)h.nr + h.npml_r, NZ = (int64_t)h.nz + 2 * (int64_t)h.npml_z;
+    const int64_t pr = (int64_t)h.npml_r * NZ, pz = NR * 2 * h.npml_z;
+    return {align_up(NR * NZ), align_up(6 * NR * NZ + 4 * pr + 4 * pz),
+            align_up(6 * NR * NZ + 5 * pr + 5 * pz)};
+}
+
+bhfwi_plan_bytes_t group_bytes(const bhfwi_shot* shots, const int* idx, int n, int K)
+{
+    int64_t C = 0, F = 0, A = 0;
+    int ntmax = 0;
+    for (int q = 0; q < n; ++q) {
+        const ShotLens l = shot_lens(shots[idx[q]]);
+        C += l.cells;
+        F += l.fst;
+        A += l.ast;
+        ntmax = std::max(ntmax, shots[idx[q]].nt);
+    }
+    const int64_t nseg = (ntmax + K - 1) / K;
+    bhfwi_plan_bytes_t b{};
+    b.ckpt_every = K;
+    b.fwd_ws_bytes = 8 * F;
+    b.ckpt_bytes = 4 * std::max<int64_t>(0, nseg - 1) * F;
+    b.adj_ws_bytes = 4 * (2 * A + 2 * (int64_t)K * C);
+    b.acc_bytes = 16 * C;
+    b.total_bytes = b.fwd_ws_bytes + b.ckpt_bytes + b.adj_ws_bytes + b.acc_bytes;
+    return b;
+}
+
+int best_interval(const bhfwi_shot* shots, const int* idx, int n)
+{
+    int64_t C = 0, F = 0;
+    int ntmax = 0;
+    for (int q = 0; q < n; ++q) {
+        const ShotLens l = shot_lens(shots[idx[q]]);
+        C += l.cells;
+        F += l.fst;
+        ntmax = std::max(ntmax, shots[idx[q]].nt);
+    }
+    const int64_t k = (int64_t)std::sqrt((double)ntmax * (double)F / (2.0 * (double)C));
+    int best = 0;
+    int64_t best_b = 0;
+    for (int64_t cand : {k / 8 * 8, (k + 7) / 8 * 8}) {
+        const int K = (int)std::min<int64_t>(std::max<int64_t>(8, cand), ntmax);
+        const int64_t b = group_bytes(shots, idx, n, K).total_bytes;
+        if (!best || b < best_b) {
+            best = K;
+            best_b = b;
+        }
+    }
+    return best;
+}
+
 thread_local std::string g_create_err;  // message of the last failed bhfwi_create
 
 }  // namespace
@@ -49,6 +109,7 @@ struct bhfwi_ctx {
     int4* d_work = nullptr;
     int4* d_tiles = nullptr;
     void* d_scratch = nullptr;
+    int* d_status = nullptr;  // device word raised by kernels that see non-finite sums
     hipStream_t cap_stream = nullptr;  // private stream that graphs are captured on
     struct Graph {
         std::vector<uintptr_t> key;
@@ -129,11 +190,19 @@ void rebuild_work(bhfwi_ctx* c)
         const int T = c->tune.tb_steps, TR = c->tune.tb_rows - 2 * T, TZ = 64 - 2 * T;
         for (int s : order) {
             const ShotDev& S = c->sd[s];
-            for (int i0 = 0; i0 < S.NR; i0 += TR)
-                for (int k0 = 0; k0 < S.NZ; k0 += TZ) {
-                    c->tiles.push_back(make_int4(s, k0, i0, std::min(i0 + TR, S.NR)));
-                    c->tiles_nt.push_back(S.nt);
-                }
+            if (c->tune.tile_map == 1) {
+                for (int k0 = 0; k0 < S.NZ; k0 += TZ)
+                    for (int i0 = 0; i0 < S.NR; i0 += TR) {
+                        c->tiles.push_back(make_int4(s, k0, i0, std::min(i0 + TR, S.NR)));
+                        c->tiles_nt.push_back(S.nt);
+                    }
+            } else {
+                for (int i0 = 0; i0 < S.NR; i0 += TR)
+                    for (int k0 = 0; k0 < S.NZ; k0 += TZ) {
+                        c->tiles.push_back(make_int4(s, k0, i0, std::min(i0 + TR, S.NR)));
+                        c->tiles_nt.push_back(S.nt);
+                    }
+            }
         }
     }
 }
@@ -269,9 +338,9 @@ void adj_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const flo
 #define BHFWI_TB(TT, RR, WW)                                                                 \
     if (T == TT && TRE == RR && W == WW) {                                                   \
         hipLaunchKernelGGL((bhfwi::k_fwd_tb<TT, RR, WW>), dim3(nact), dim3(64 * WW), 0, st,  \
-                           c->d_shots, c->d_tiles, nact, n0, nsteps, lam, mu, rho, wav,      \
-                           c->d_rec, c->d_pml_r, c->d_pml_z, in, out, traces, hist,          \
-                           (long long)(2 * c->cells), (long long)c->cells);                  \
+                           c->d_shots, c->d_tiles, nact, c->tune.tile_map, n0, nsteps, lam,  \
+                           mu, rho, wav, c->d_rec, c->d_pml_r, c->d_pml_z, in, out, traces,  \
+                           hist, (long long)(2 * c->cells), (long long)c->cells);            \
         return;                                                                              \
     }
 
@@ -291,9 +360,9 @@ void fwd_tb_launch(bhfwi_ctx* c, hipStream_t st, int n0, int nsteps, const float
 #define BHFWI_TBA(TT, RR, WW)                                                                \
     if (T == TT && TRE == RR && W == WW) {                                                   \
         hipLaunchKernelGGL((bhfwi::k_adj_tb<TT, RR, WW>), dim3(nact), dim3(64 * WW), 0, st,  \
-                           c->d_shots, c->d_tiles, nact, n_hi, nsteps, lam, mu, rho,         \
-                           c->d_rec, resid, c->d_pml_r, c->d_pml_z, in, out, hist_hi,        \
-                           (long long)(2 * c->cells), acc, (long long)c->cells);             \
+                           c->d_shots, c->d_tiles, nact, c->tune.tile_map, n_hi, nsteps,     \
+                           lam, mu, rho, c->d_rec, resid, c->d_pml_r, c->d_pml_z, in, out,   \
+                           hist_hi, (long long)(2 * c->cells), acc, (long long)c->cells);    \
         return;                                                                              \
     }
 
@@ -362,6 +431,7 @@ int run_sequence(bhfwi_ctx* c, hipStream_t st, std::vector<uintptr_t> key, F&& r
     key.push_back((uintptr_t)c->tune.tb_steps);
     key.push_back((uintptr_t)c->tune.tb_rows);
     key.push_back((uintptr_t)c->tune.tb_waves);
+    key.push_back((uintptr_t)c->tune.tile_map);
     for (size_t g = 0; g < c->graphs.size(); ++g)
         if (c->graphs[g].key == key) {
             HIPOK(c, hipGraphLaunch(c->graphs[g].exec, st));
@@ -463,12 +533,13 @@ int bhfwi_create(bhfwi_ctx** out, int32_t hip_device, const bhfwi_shot* shots, i
         S.model_ld = h.model_ld;
         S.psir_len = (int64_t)h.npml_r * NZ;
         S.psiz_len = NR * 2 * h.npml_z;
+        const ShotLens lens = shot_lens(h);
         S.cell_off = cell_off;
-        cell_off += align_up(NR * NZ);
+        cell_off += lens.cells;
         S.fst_off = fst;
-        fst += align_up(6 * NR * NZ + 4 * S.psir_len + 4 * S.psiz_len);
+        fst += lens.fst;
         S.ast_off = ast;
-        ast += align_up(6 * NR * NZ + 5 * S.psir_len + 5 * S.psiz_len);
+        ast += lens.ast;
         S.trace_off = tr;
         tr += (int64_t)h.nrec * h.nt;
         S.wave_off = wv;
@@ -521,6 +592,7 @@ int bhfwi_create(bhfwi_ctx** out, int32_t hip_device, const bhfwi_shot* shots, i
     c->tune.tb_steps = 4;  // measured best on single shots; bhfwi_autotune refines
     c->tune.tb_rows = 16;
     c->tune.tb_waves = 8;
+    c->tune.tile_map = 1;
     rebuild_work(c);
 
     hipError_t e = hipSetDevice(hip_device);
@@ -541,6 +613,8 @@ int bhfwi_create(bhfwi_ctx** out, int32_t hip_device, const bhfwi_shot* shots, i
     CREATE_HIP(hipMalloc(&c->d_pml_z, sizeof(float) * pmz.size()));
     CREATE_HIP(hipMemcpy(c->d_pml_z, pmz.data(), sizeof(float) * pmz.size(), hipMemcpyHostToDevice));
     CREATE_HIP(hipMalloc(&c->d_scratch, 4 * sizeof(float) * kPartBlocks + sizeof(double) * kPartBlocks));
+    CREATE_HIP(hipMalloc(&c->d_status, sizeof(int)));
+    CREATE_HIP(hipMemset(c->d_status, 0, sizeof(int)));
 #undef CREATE_HIP
     if (int rc = upload_work(c)) return bail(rc);
     *out = c;
@@ -561,6 +635,7 @@ void bhfwi_destroy(bhfwi_ctx* c)
     if (c->d_work) (void)hipFree(c->d_work);
     if (c->d_tiles) (void)hipFree(c->d_tiles);
     if (c->d_scratch) (void)hipFree(c->d_scratch);
+    if (c->d_status) (void)hipFree(c->d_status);
     delete c;
 }
 
@@ -588,11 +663,94 @@ int bhfwi_sizes(const bhfwi_ctx* c, bhfwi_sizes_t* o)
     return BHFWI_OK;
 }
 
+int bhfwi_plan_bytes(const bhfwi_shot* shots, int32_t nshot, int32_t ckpt_every,
+                     bhfwi_plan_bytes_t* out)
+{
+    if (!shots || nshot < 1 || !out) {
+        g_create_err = "plan_bytes: bad arguments";
+        return BHFWI_EINVAL;
+    }
+    for (int s = 0; s < nshot; ++s)
+        if (shots[s].nr < 2 || shots[s].nz < 2 || shots[s].npml_r < 0 || shots[s].npml_z < 0 ||
+            shots[s].nt < 1) {
+            g_create_err = "plan_bytes: bad grid sizes";
+            return BHFWI_EINVAL;
+        }
+    std::vector<int> idx(nshot);
+    for (int s = 0; s < nshot; ++s) idx[s] = s;
+    const int K = ckpt_every > 0 ? ckpt_every : best_interval(shots, idx.data(), nshot);
+    *out = group_bytes(shots, idx.data(), nshot, K);
+    return BHFWI_OK;
+}
+
+int bhfwi_plan(const bhfwi_shot* shots, int32_t nshot, int64_t budget_bytes,
+               int32_t ckpt_every, int32_t max_groups, int32_t* group_of, int32_t* ckpt_out,
+               bhfwi_plan_info* info)
+{
+    bhfwi_plan_bytes_t probe;
+    if (int rc = bhfwi_plan_bytes(shots, nshot, ckpt_every, &probe)) return rc;
+    if (!group_of || !ckpt_out || !info) {
+        g_create_err = "plan: null output";
+        return BHFWI_EINVAL;
+    }
+    std::vector<int64_t> load(nshot);
+    std::vector<int> order(nshot);
+    int64_t trace = 0;
+    for (int s = 0; s < nshot; ++s) {
+        const bhfwi_shot& h = shots[s];
+        load[s] = ((int64_t)h.nr + h.npml_r) * ((int64_t)h.nz + 2 * (int64_t)h.npml_z) * h.nt;
+        order[s] = s;
+        trace += 4 * (int64_t)h.nrec * h.nt;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return load[a] > load[b]; });
+    const int64_t trace_bytes = 3 * trace;  // traces, residuals, observed data
+    const int gmax = max_groups > 0 ? std::min<int>(max_groups, nshot) : nshot;
+    for (int G = 1; G <= gmax; ++G) {
+        std::vector<std::vector<int>> groups(G);
+        std::vector<int64_t> tot(G, 0);
+        for (int s : order) {
+            const int g = (int)(std::min_element(tot.begin(), tot.end()) - tot.begin());
+            groups[g].push_back(s);
+            tot[g] += load[s];
+        }
+        int64_t ws[4] = {0, 0, 0, 0};
+        std::vector<int> Ks;
+        std::vector<std::vector<int>> used;
+        for (auto& g : groups) {
+            if (g.empty()) continue;
+            std::sort(g.begin(), g.end());
+            const int n = (int)g.size();
+            const int K = ckpt_every > 0 ? ckpt_every : best_interval(shots, g.data(), n);
+            const bhfwi_plan_bytes_t b = group_bytes(shots, g.data(), n, K);
+            ws[0] = std::max(ws[0], b.fwd_ws_bytes);
+            ws[1] = std::max(ws[1], b.ckpt_bytes);
+            ws[2] = std::max(ws[2], b.adj_ws_bytes);
+            ws[3] = std::max(ws[3], b.acc_bytes);
+            Ks.push_back(K);
+            used.push_back(g);
+        }
+        const int64_t wsb = ws[0] + ws[1] + ws[2] + ws[3];
+        if (wsb + trace_bytes <= budget_bytes) {
+            for (size_t q = 0; q < used.size(); ++q) {
+                for (int s : used[q]) group_of[s] = (int32_t)q;
+                ckpt_out[q] = Ks[q];
+            }
+            info->ngroups = (int32_t)used.size();
+            info->pad_ = 0;
+            info->workspace_bytes = wsb;
+            info->trace_bytes = trace_bytes;
+            return BHFWI_OK;
+        }
+    }
+    g_create_err = "plan: no grouping of the shots fits the budget";
+    return BHFWI_ENOMEM;
+}
+
 int bhfwi_set_tune(bhfwi_ctx* c, const bhfwi_tune* t)
 {
     if (!c || !t) return BHFWI_EINVAL;
     if (t->rows_per_wave < 1 || t->use_graph < 0 || t->use_graph > 1 || t->time_kernels < 0 ||
-        t->time_kernels > 1 || t->tb_steps < 0 ||
+        t->time_kernels > 1 || t->tb_steps < 0 || t->tile_map < 0 || t->tile_map > 1 ||
         (t->tb_steps >= 2 && !tb_supported(t->tb_steps, t->tb_rows, t->tb_waves)) ||
         !(t->waves_per_block == 1 || t->waves_per_block == 2 || t->waves_per_block == 4 ||
           t->waves_per_block == 8))
@@ -628,13 +786,14 @@ int bhfwi_autotune(bhfwi_ctx* c, void* stream, const float* lam, const float* mu
         t.tb_steps = 0;
         cand.push_back(t);
     }
-#define BHFWI_TBC(TT, RR, WW)      \
-    {                              \
-        bhfwi_tune t = base;       \
-        t.tb_steps = TT;           \
-        t.tb_rows = RR;            \
-        t.tb_waves = WW;           \
-        cand.push_back(t);         \
+#define BHFWI_TBC(TT, RR, WW)            \
+    for (int map = 0; map < 2; ++map) {  \
+        bhfwi_tune t = base;             \
+        t.tb_steps = TT;                 \
+        t.tb_rows = RR;                  \
+        t.tb_waves = WW;                 \
+        t.tile_map = map;                \
+        cand.push_back(t);               \
     }
     BHFWI_TB_SHAPES(BHFWI_TBC)
 #undef BHFWI_TBC
@@ -813,7 +972,7 @@ int bhfwi_misfit(bhfwi_ctx* c, void* stream, const float* traces, const float* o
     hipLaunchKernelGGL(bhfwi::k_misfit_partial, dim3(nb), dim3(256), 0, st,
                        (long long)c->trace_len, traces, observed, resid, part);
     hipLaunchKernelGGL(bhfwi::k_sum_partials, dim3(1), dim3(256), 0, st, nb, part, J_dev,
-                       accumulate ? 1 : 0);
+                       accumulate ? 1 : 0, c->d_status);
     HIPOK(c, hipGetLastError());
     return BHFWI_OK;
 }
@@ -900,7 +1059,7 @@ int bhfwi_gradient(bhfwi_ctx* c, void* stream, const float* mu, const float* acc
 }
 
 int bhfwi_precondition(bhfwi_ctx* c, void* stream, int64_t n, const float* illum,
-                       const uint8_t* mask, float eps, float* g_lam, float* g_mu)
+                       const uint8_t* mask, float eps, float* g_lam, float* g_mu, double* gpg)
 {
     if (int rc = check_ctx(c)) return rc;
     if (n < 1 || !illum || !mask || !g_lam || !g_mu || !(eps >= 0))
@@ -911,15 +1070,46 @@ int bhfwi_precondition(bhfwi_ctx* c, void* stream, int64_t n, const float* illum
     hipLaunchKernelGGL(bhfwi::k_absmax_partial, dim3(nb), dim3(256), 0, st, (long long)n, mask,
                        illum, (const float*)nullptr, (const float*)nullptr,
                        (const float*)nullptr, part);
-    hipLaunchKernelGGL(bhfwi::k_precond_apply, dim3(grid1d(n)), dim3(256), 0, st, (long long)n,
-                       mask, illum, eps, part, nb, g_lam, g_mu);
+    const int na = grid1d(n, kPartBlocks);
+    double* dpart = gpg ? (double*)((float*)c->d_scratch + 4 * kPartBlocks) : nullptr;
+    hipLaunchKernelGGL(bhfwi::k_precond_apply, dim3(na), dim3(256), 0, st, (long long)n, mask,
+                       illum, eps, part, nb, g_lam, g_mu, dpart);
+    if (gpg)
+        hipLaunchKernelGGL(bhfwi::k_sum_partials, dim3(1), dim3(256), 0, st, na, dpart, gpg, 0,
+                           c->d_status);
+    HIPOK(c, hipGetLastError());
+    return BHFWI_OK;
+}
+
+int bhfwi_status(bhfwi_ctx* c, void* stream)
+{
+    if (int rc = check_ctx(c)) return rc;
+    HIPOK(c, hipStreamSynchronize((hipStream_t)stream));
+    int h = 0;
+    HIPOK(c, hipMemcpy(&h, c->d_status, sizeof(int), hipMemcpyDeviceToHost));
+    if (!h) return BHFWI_OK;
+    const int zero = 0;
+    HIPOK(c, hipMemcpy(c->d_status, &zero, sizeof(int), hipMemcpyHostToDevice));
+    return fail(c, BHFWI_ENONFINITE, "non-finite misfit or line-search slope: the traces or "
+                                     "gradients hold NaN or Inf");
+}
+
+int bhfwi_line_search(bhfwi_ctx* c, void* stream, const double* J0, const double* J1,
+                      const double* gpg, const float* alpha1, float* alpha_out)
+{
+    if (int rc = check_ctx(c)) return rc;
+    if (!J0 || !J1 || !gpg || !alpha1 || !alpha_out)
+        return fail(c, BHFWI_EINVAL, "line_search: null pointer");
+    hipLaunchKernelGGL(bhfwi::k_line_search, dim3(1), dim3(64), 0, (hipStream_t)stream, J0, J1,
+                       gpg, alpha1, alpha_out);
     HIPOK(c, hipGetLastError());
     return BHFWI_OK;
 }
 
 int bhfwi_update(bhfwi_ctx* c, void* stream, int64_t n, float* lam, float* mu, const float* rho,
                  const float* g_lam, const float* g_mu, const uint8_t* mask, float eta,
-                 float alpha_override, const bhfwi_bounds* b, float* alpha_out)
+                 float alpha_override, const float* alpha_in, const bhfwi_bounds* b,
+                 float* alpha_out)
 {
     if (int rc = check_ctx(c)) return rc;
     if (n < 1 || !lam || !mu || !rho || !g_lam || !g_mu || !mask || !b)
@@ -931,7 +1121,8 @@ int bhfwi_update(bhfwi_ctx* c, void* stream, int64_t n, float* lam, float* mu, c
                        g_lam, g_mu, (const float*)lam, (const float*)mu, part);
     hipLaunchKernelGGL(bhfwi::k_update_apply, dim3(grid1d(n)), dim3(256), 0, st, (long long)n,
                        mask, lam, mu, rho, g_lam, g_mu, (const float*)part, nb, eta,
-                       alpha_override, b->vp_min, b->vp_max, b->vs_min, b->vs_max, alpha_out);
+                       alpha_override, alpha_in, b->vp_min, b->vp_max, b->vs_min, b->vs_max,
+                       alpha_out);
     HIPOK(c, hipGetLastError());
     return BHFWI_OK;
 }

@@ -8,6 +8,17 @@ namespace bhfwi {
 
 constexpr int kOwn = 62;  // axial rows owned by one wave64 (lanes 1..62)
 
+// Workgroup b of a launch is dispatched to XCD b % 8.  With map == 1 the n
+// workgroups are renumbered so that XCD x walks one contiguous chunk of the
+// work table, [x*(n/8) + min(x, n%8), ...), in table order: tiles that are
+// neighbours in the table (and share halo rows) then meet in the same L2.
+__device__ inline int xcd_chunk(int b, int n, int map)
+{
+    if (map != 1) return b;
+    const int x = b & 7, l = b >> 3, per = n >> 3, rem = n & 7;
+    return x * per + min(x, rem) + l;
+}
+
 // One shot as the kernels see it.  Offsets are in floats.
 struct ShotDev {
     int NR, NZ, nr, nz, pr, pz;

@@ -704,8 +704,11 @@ k_misfit_partial(long long n, const float* __restrict__ d, const float* __restri
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
+// Sum of np partials into *out (or added to it).  With status != nullptr a
+// non-finite sum raises status[0] to 1.
 __global__ void __launch_bounds__(256)
-k_sum_partials(int np, const double* __restrict__ part, double* __restrict__ out, int add)
+k_sum_partials(int np, const double* __restrict__ part, double* __restrict__ out, int add,
+               int* __restrict__ status)
 {
     __shared__ double sh[256];
     double s = 0.0;
@@ -716,7 +719,10 @@ k_sum_partials(int np, const double* __restrict__ part, double* __restrict__ out
         if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = add ? *out + sh[0] : sh[0];
+    if (threadIdx.x == 0) {
+        *out = add ? *out + sh[0] : sh[0];
+        if (status && !isfinite(sh[0])) status[0] = 1;
+    }
 }
 
 // Add one shot's accumulators into the global grids; folds the tau_rz-node
@@ -804,13 +810,19 @@ __device__ float reduce_part_max(const float* __restrict__ part, int np, int q, 
     return r;
 }
 
+// Scales both gradients by P = 1/(E + eps max E) on mask cells (0 elsewhere).
+// With dot != nullptr also writes the block sums of g . P g (both
+// parameters, double) to dot[blockIdx.x]: the directional derivative of the
+// misfit along the preconditioned step, used by the line search.
 __global__ void __launch_bounds__(256)
 k_precond_apply(long long n, const uint8_t* __restrict__ mask, const float* __restrict__ illum,
                 float eps, const float* __restrict__ part, int np, float* __restrict__ g_lam,
-                float* __restrict__ g_mu)
+                float* __restrict__ g_mu, double* __restrict__ dot)
 {
     __shared__ float sh[256];
+    __shared__ double shd[256];
     const float emax = reduce_part_max(part, np, 0, sh);
+    double s = 0.0;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         if (!mask[i]) {
@@ -819,9 +831,43 @@ k_precond_apply(long long n, const uint8_t* __restrict__ mask, const float* __re
             continue;
         }
         const float p = 1.0f / (illum[i] + eps * emax);
-        g_lam[i] *= p;
-        g_mu[i] *= p;
+        const float gl = g_lam[i], gm = g_mu[i];
+        g_lam[i] = gl * p;
+        g_mu[i] = gm * p;
+        s += (double)p * ((double)gl * gl + (double)gm * gm);
     }
+    if (!dot) return;  // uniform
+    shd[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) shd[threadIdx.x] += shd[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) dot[blockIdx.x] = shd[0];
+}
+
+// Step length of the parabolic line search.  With the misfit J0 at the
+// current model, J1 at the trial step alpha1 and the slope -gpg of J along
+// the preconditioned step at alpha = 0, the parabola
+//   J(a) = J0 - gpg a + c a^2,   c = (J1 - J0 + gpg alpha1) / alpha1^2
+// has its minimum at gpg / (2c) when c > 0; that value is kept inside
+// [alpha1/10, 3 alpha1].  Without a minimum (c <= 0) the trial step is kept
+// if it lowered the misfit and halved otherwise.  One thread.
+__global__ void k_line_search(const double* __restrict__ J0, const double* __restrict__ J1,
+                              const double* __restrict__ gpg, const float* __restrict__ alpha1,
+                              float* __restrict__ alpha_out)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const double a1 = alpha1[0], j0 = J0[0], j1 = J1[0], g = gpg[0];
+    double a = 0.0;
+    if (a1 > 0.0) {
+        const double c = (j1 - j0 + g * a1) / (a1 * a1);
+        if (c > 0.0)
+            a = fmin(fmax(g / (2.0 * c), 0.1 * a1), 3.0 * a1);
+        else
+            a = (j1 <= j0) ? a1 : 0.5 * a1;
+    }
+    alpha_out[0] = (float)a;
 }
 
 // part holds the maxima of |g_lam|, |g_mu|, |lam|, |mu| over mask cells.
@@ -830,12 +876,12 @@ k_update_apply(long long n, const uint8_t* __restrict__ mask, float* __restrict_
                float* __restrict__ mu, const float* __restrict__ rho,
                const float* __restrict__ g_lam, const float* __restrict__ g_mu,
                const float* __restrict__ part, int np, float eta, float alpha_override,
-               float vp_min, float vp_max, float vs_min, float vs_max,
-               float* __restrict__ alpha_out)
+               const float* __restrict__ alpha_in, float vp_min, float vp_max, float vs_min,
+               float vs_max, float* __restrict__ alpha_out)
 {
     __shared__ float sh[256];
-    float alpha = alpha_override;
-    if (!(alpha > 0.f)) {
+    float alpha = alpha_in ? alpha_in[0] : alpha_override;
+    if (!alpha_in && !(alpha > 0.f)) {
         const float gl = reduce_part_max(part, np, 0, sh);
         const float gm = reduce_part_max(part, np, 1, sh);
         const float lm = reduce_part_max(part, np, 2, sh);

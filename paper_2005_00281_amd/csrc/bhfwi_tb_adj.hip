@@ -25,8 +25,8 @@ namespace bhfwi {
 
 template <int T, int TRE, int W>
 __global__ void __launch_bounds__(64 * W)
-k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int nwork, int n_hi,
-         int nsteps, const float* __restrict__ lam, const float* __restrict__ mu,
+k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int nwork, int map,
+         int n_hi, int nsteps, const float* __restrict__ lam, const float* __restrict__ mu,
          const float* __restrict__ rho, const int* __restrict__ rec_k,
          const float* __restrict__ resid, const float* __restrict__ pml_r,
          const float* __restrict__ pml_z, const float* __restrict__ ain,
@@ -40,7 +40,7 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
     __shared__ float L[NPL][LDW];
     __shared__ float Lres[T][64];  // residual/3 of this lane's receiver, per step
 
-    const int wg = blockIdx.x;
+    const int wg = xcd_chunk(blockIdx.x, nwork, map);
     if (wg >= nwork) return;
     const int4 wk = work[wg];
     const ShotDev& S = shots[wk.x];
@@ -175,15 +175,19 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
 #pragma unroll
         for (int t = 0; t < T; ++t) Lres[t][lane] = rsum[t] * (1.0f / 3.0f);
     }
-    // stored v^{n+1/2} of the first step; later steps are fetched one step ahead
+    // stored v^{n+1/2} of the first step; later steps are fetched one step ahead.
+    // The correlation of the owned cells reads it on the owned tile and one
+    // cell around it only (rows T-1 .. TRE-T, lanes T-1 .. 64-T).
     float hvr[RPT], hvz[RPT];
+    const bool hlane = kin && lane >= T - 1 && lane <= 64 - T;
     auto fetch_hist = [&](int t) {
         const float* __restrict__ vrh = hist_hi - (long long)t * hist_stride + S.cell_off;
         const float* __restrict__ vzh = vrh + cells_total;
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
-            const int i = wk.z - T + wave + W * j;
-            const bool in = kin && i >= 0 && i < NR;
+            const int e = wave + W * j;
+            const int i = wk.z - T + e;
+            const bool in = hlane && e >= T - 1 && e <= TRE - T && i >= 0 && i < NR;
             const long long c = (long long)(in ? i : 0) * NZ + kc;
             hvr[j] = in ? vrh[c] : 0.f;
             hvz[j] = in ? vzh[c] : 0.f;

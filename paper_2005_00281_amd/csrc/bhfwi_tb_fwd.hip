@@ -28,7 +28,8 @@ struct IntC {
 
 template <int T, int TRE, int W>
 __global__ void __launch_bounds__(64 * W)
-k_fwd_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int nwork, int n0,
+k_fwd_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int nwork, int map,
+         int n0,
          int nsteps, const float* __restrict__ lam, const float* __restrict__ mu,
          const float* __restrict__ rho, const float* __restrict__ wavelet,
          const int* __restrict__ rec_k, const float* __restrict__ pml_r,
@@ -43,7 +44,7 @@ k_fwd_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
     __shared__ float L[NPL][LDW];
     __shared__ float Lwav[T];  // source samples of this launch's steps
 
-    const int wg = blockIdx.x;
+    const int wg = xcd_chunk(blockIdx.x, nwork, map);
     if (wg >= nwork) return;
     const int4 wk = work[wg];
     const ShotDev& S = shots[wk.x];

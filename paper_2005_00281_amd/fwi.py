@@ -10,6 +10,13 @@ finalize (summed over groups), then the diagonal preconditioner, the update
 (Eq. 9-10) and the conversion back (Eq. 11-12).  All buffers persist across
 iterations so that the captured HIP graphs replay; the groups share one set
 of workspaces.
+
+With line_search=True the step length comes from a parabolic line search:
+a trial update with the greatest-change rule, one forward pass (no
+checkpoints) of every group on the trial model for its misfit, and the
+minimum of the parabola through the two misfits and the slope along the
+preconditioned gradient (bhfwi_line_search); the whole iteration stays on
+the device without a host synchronisation.
 """
 from __future__ import annotations
 
@@ -20,7 +27,7 @@ from . import _lib
 
 class Inversion:
     def __init__(self, surveys, vp, vs, rho, wavelets, observed, mask, eps=1e-3, eta=0.02,
-                 bounds=(1000.0, 7000.0, 300.0, 4500.0)):
+                 bounds=(1000.0, 7000.0, 300.0, 4500.0), line_search=False):
         if not isinstance(surveys, (list, tuple)):
             surveys, wavelets, observed = [surveys], [wavelets], [observed]
         self.surveys = list(surveys)
@@ -47,6 +54,12 @@ class Inversion:
         self.g_mu = torch.empty_like(vp)
         self.illum = torch.empty_like(vp)
         self.J = torch.zeros((), dtype=torch.float64, device=dev)
+        self.line_search = bool(line_search)
+        if self.line_search:
+            self.J1 = torch.zeros((), dtype=torch.float64, device=dev)
+            self.gpg = torch.zeros((), dtype=torch.float64, device=dev)
+            self.lam1 = torch.empty_like(vp)
+            self.mu1 = torch.empty_like(vp)
 
     def gradient(self):
         """Eq. 2, 1, 5, 6-8 and the finalize over every group; leaves the
@@ -65,11 +78,32 @@ class Inversion:
         return self.J
 
     def iterate(self):
-        """One iteration; returns (J, alpha) as device scalars (no host sync)."""
+        """One iteration; returns (J, alpha) as device scalars (no host sync).
+        J is a copy: the misfit buffer is overwritten by the next iteration."""
         self.gradient()
         sv = self.surveys[0]
-        sv.precondition(self.illum, self.mask, self.eps, self.g_lam, self.g_mu)
-        alpha = sv.update(self.lam, self.mu, self.rho, self.g_lam, self.g_mu, self.mask,
-                          self.eta, bounds=self.bounds)
+        if not self.line_search:
+            sv.precondition(self.illum, self.mask, self.eps, self.g_lam, self.g_mu)
+            alpha = sv.update(self.lam, self.mu, self.rho, self.g_lam, self.g_mu, self.mask,
+                              self.eta, bounds=self.bounds)
+        else:
+            alpha = self._line_search_step()
         _lib.velocities(self.lam, self.mu, self.rho, out=(self.vp, self.vs))
-        return self.J, alpha
+        return self.J.clone(), alpha
+
+    def _line_search_step(self):
+        sv = self.surveys[0]
+        sv.precondition(self.illum, self.mask, self.eps, self.g_lam, self.g_mu, gpg=self.gpg)
+        self.lam1.copy_(self.lam)
+        self.mu1.copy_(self.mu)
+        alpha1 = sv.update(self.lam1, self.mu1, self.rho, self.g_lam, self.g_mu, self.mask,
+                           self.eta, bounds=self.bounds)
+        for g, svg in enumerate(self.surveys):
+            svg.fwd_model(self.lam1, self.mu1, self.rho, self.wavelets[g],
+                          traces=self.traces[g])
+            svg.misfit(self.traces[g], self.observed[g], resid=self.resid[g], J=self.J1,
+                       accumulate=g > 0)
+        alpha = sv.line_search(self.J, self.J1, self.gpg, alpha1)
+        sv.update(self.lam, self.mu, self.rho, self.g_lam, self.g_mu, self.mask, self.eta,
+                  bounds=self.bounds, alpha_in=alpha)
+        return alpha

@@ -48,16 +48,17 @@ def survey(w, ckpt=250, tune=None):
     return sv
 
 
-def T(rows=4, wpb=4, graph=1, tb=0, tbr=16, tbw=4):
+def T(rows=4, wpb=4, graph=1, tb=0, tbr=16, tbw=4, tmap=1):
     return dict(rows_per_wave=rows, waves_per_block=wpb, use_graph=graph, tb_steps=tb,
-                tb_rows=tbr, tb_waves=tbw)
+                tb_rows=tbr, tb_waves=tbw, tile_map=tmap)
 
 
 FWD_TUNES = [T(1, 1, 0), T(2, 4, 1), T(3, 2, 1), T(4, 4, 0), T(16, 4, 1), T(64, 8, 0),
              T(tb=2), T(tb=3, graph=0), T(tb=4), T(tb=4, tbw=8), T(tb=6, tbr=24, tbw=8, graph=0),
-             T(tb=8, tbr=32, tbw=8), T(tb=3, tbr=24, tbw=8)]
+             T(tb=8, tbr=32, tbw=8), T(tb=3, tbr=24, tbw=8), T(tb=4, tmap=0)]
 GRAD_TUNES = [T(1, 1, 1), T(2, 4, 0), T(4, 4, 1), T(5, 4, 1), T(64, 8, 0), T(tb=4),
-              T(tb=3, graph=0), T(tb=4, tbw=8), T(tb=6, tbr=24, tbw=8), T(tb=8, tbr=32, tbw=8)]
+              T(tb=3, graph=0), T(tb=4, tbw=8), T(tb=6, tbr=24, tbw=8), T(tb=8, tbr=32, tbw=8),
+              T(tb=4, tbw=8, tmap=0)]
 
 
 def oracle_traces(w, s=0, which="start"):
@@ -376,3 +377,68 @@ def test_shot_groups_sum_to_the_single_survey_gradient():
     assert abs(J1 - J2) <= 1e-12 * abs(J1)
     for a, b in zip(g1, g2):
         assert rel_l2(b, a) <= 1e-6
+
+
+def test_line_search_iteration_parity():
+    """One preconditioned iteration with the parabolic line search (trial
+    step, forward-only misfit, step length on the device) against the same
+    steps in the FP64 oracle on the oracle's observed data."""
+    from paper_2005_00281_amd.fwi import Inversion
+    w = workloads.tiny(nr=30, nz=100, p=6, nt=300)
+    sh = w.shots[0]
+    _say("line search iteration", sh.NR, sh.NZ, sh.nt)
+    g = geom(sh)
+    bounds = (1000.0, 7000.0, 300.0, 4500.0)
+    lam_o, mu_o, rho_o = oracle_models(w, 0, "start")
+    lt, mt, _ = oracle_models(w, 0, "true")
+    d_obs = oracle.forward(g, lt, mt, rho_o, sh.wavelet)
+    J0_o, r_o = oracle.misfit(oracle.forward(g, lam_o, mu_o, rho_o, sh.wavelet), d_obs)
+    gl, gm, il = oracle.gradient(g, lam_o, mu_o, rho_o, sh.wavelet, r_o, seg=50)
+    pl, pm, gpg_o = oracle.precondition(il, w.mask, 1e-3, gl, gm, return_gpg=True)
+    l1, m1, a1_o = oracle.update(lam_o, mu_o, rho_o, pl, pm, w.mask, 0.02,
+                                 vp_bounds=bounds[:2], vs_bounds=bounds[2:])
+    J1_o = oracle.misfit(oracle.forward(g, l1, m1, rho_o, sh.wavelet), d_obs)[0]
+    a_o = oracle.line_search(J0_o, J1_o, gpg_o, a1_o)
+    l2, m2, _ = oracle.update(lam_o, mu_o, rho_o, pl, pm, w.mask, 0.02, alpha_override=a_o,
+                              vp_bounds=bounds[:2], vs_bounds=bounds[2:])
+    vp_o, vs_o = oracle.velocities(l2, m2, rho_o)
+
+    sv = survey(w, ckpt=50, tune=T(tb=4, tbw=8))
+    wav = sv.pack_wavelets([sh.wavelet])
+    rho = f32(w.rho)
+    mask = torch.as_tensor(w.mask, device=_dev())
+    inv = Inversion(sv, f32(w.vp_start), f32(w.vs_start), rho, wav, f32(d_obs.ravel()), mask,
+                    eta=0.02, bounds=bounds, line_search=True)
+    J0, a = inv.iterate()
+    J0, a, J1, gpg = J0.item(), a.item(), inv.J1.item(), inv.gpg.item()
+    print("[case] J0 %.6g/%.6g J1 %.6g/%.6g gpg %.6g/%.6g alpha %.6g/%.6g (trial %.6g)" % (
+        J0, J0_o, J1, J1_o, gpg, gpg_o, a, a_o, a1_o), flush=True)
+    assert abs(J0 - J0_o) <= 1e-3 * J0_o
+    assert abs(J1 - J1_o) <= 1e-3 * J1_o
+    assert abs(gpg - gpg_o) <= 2e-3 * gpg_o
+    assert abs(a - a_o) <= 1e-2 * a_o
+    # the model change matches the oracle's to the step-length tolerance
+    dvp_o, dvs_o = vp_o - w.vp_start, vs_o - w.vs_start
+    dvp = inv.vp.cpu().numpy() - w.vp_start.astype(np.float32)
+    dvs = inv.vs.cpu().numpy() - w.vs_start.astype(np.float32)
+    assert rel_l2(dvp, dvp_o) <= 2e-2 and rel_l2(dvs, dvs_o) <= 2e-2
+
+
+def test_status_reports_non_finite_traces():
+    """A NaN in the traces reaches the device status word through the misfit
+    sum; bhfwi_status reports it once and clears it."""
+    from paper_2005_00281_amd._lib import BhfwiError
+    w = workloads.tiny()
+    _say("status word")
+    sv = survey(w)
+    n = sv.sizes.trace_elems
+    d = torch.zeros(n, dtype=torch.float32, device=_dev())
+    o = torch.zeros_like(d)
+    sv.misfit(d, o)
+    sv.status()  # clean
+    d[n // 2] = float("nan")
+    sv.misfit(d, o)
+    with pytest.raises(BhfwiError) as e:
+        sv.status()
+    assert e.value.code == -5
+    sv.status()  # cleared

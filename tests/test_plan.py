@@ -34,3 +34,21 @@ def test_impossible_budget_raises():
     w = workloads.make("c2")
     with pytest.raises(MemoryError):
         plan.plan(w.shots, 1e6)
+
+
+@pytest.mark.gpu
+def test_plan_bytes_are_the_context_sizes():
+    """The planner's figures are the workspace sizes a context of the same
+    shots asks for."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2005_00281_amd as P
+    w = workloads.make("c4")
+    p = plan.plan(w.shots, 120e9)
+    for grp, K in zip(p.groups, p.ckpt_every):
+        shots = [w.shots[s] for s in grp]
+        z = P.Survey(shots, (w.NRg, w.NZg), ckpt_every=K).sizes
+        b = plan.workspace_bytes(shots, K)
+        assert (z.fwd_ws_bytes, z.ckpt_bytes, z.adj_ws_bytes, 4 * z.acc_elems) == \
+            (b["fwd"], b["ckpt"], b["adj"], b["acc"])
