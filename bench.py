@@ -147,6 +147,9 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=0.0,
                     help="HBM budget for the planner (0: 80%% of the device)")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="time one gradient evaluation per temporally blocked shape "
+                         "(stderr only) before the benchmark")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -201,6 +204,26 @@ def main():
             entry = sv.autotune(lam_s, mu_s, rho, wav)
         log("autotune %.1f s -> %s" % (time.perf_counter() - t_at, entry["tune"]))
         del lam_s, mu_s
+    if args.sweep:
+        keep = surveys[0].get_tune()
+        shapes = [(T, R, W_) for (T, R, W_) in
+                  [(2, 16, 4), (3, 16, 4), (4, 16, 4), (2, 16, 8), (3, 16, 8), (4, 16, 8),
+                   (2, 24, 8), (3, 24, 8), (4, 24, 8), (6, 24, 8), (4, 32, 8), (6, 32, 8),
+                   (8, 32, 8), (2, 16, 16), (3, 16, 16), (4, 16, 16), (4, 32, 16), (6, 32, 16),
+                   (8, 32, 16)]]
+        for (T, R, W_) in shapes:
+            for tmap in (0, 1):
+                for x in surveys:
+                    x.set_tune(tb_steps=T, tb_rows=R, tb_waves=W_, tile_map=tmap)
+                inv.gradient()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                inv.gradient()
+                torch.cuda.synchronize()
+                log("sweep T %d rows %d waves %d map %d: %.2f ms per gradient" % (
+                    T, R, W_, tmap, (time.perf_counter() - t0) * 1e3))
+        for x in surveys:
+            x.set_tune(**keep)
     if args.no_graph:
         for sv in surveys:
             sv.set_tune(use_graph=0)

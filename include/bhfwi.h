@@ -98,10 +98,11 @@ typedef struct {
                                  T = tb_steps at a time in LDS-tiled kernels;
                                  0 or 1: one step per launch (wave march) */
     int32_t tb_rows;          /* radial rows of a tile including its halo */
-    int32_t tb_waves;         /* wave64 per tile workgroup (4 or 8).  Supported
+    int32_t tb_waves;         /* wave64 per tile workgroup (4, 8 or 16).  Supported
                                  (tb_steps, tb_rows, tb_waves): (2|3|4, 16, 4),
                                  (2|3|4, 16, 8), (2|3|4|6, 24, 8),
-                                 (4|6|8, 32, 8) */
+                                 (4|6|8, 32, 8), (2|3|4, 16, 16),
+                                 (4|6|8, 32, 16) */
     int32_t tile_map;         /* order of the tiles of a temporally blocked launch:
                                  0: axial tile fastest, workgroups in table order;
                                  1: radial tile fastest, and each of the 8 XCDs of

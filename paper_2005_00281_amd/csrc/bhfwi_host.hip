@@ -333,7 +333,8 @@ void adj_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const flo
 // Supported temporally blocked shapes: (steps T, tile rows incl. halo, waves).
 #define BHFWI_TB_SHAPES(X) \
     X(2, 16, 4) X(3, 16, 4) X(4, 16, 4) X(2, 16, 8) X(3, 16, 8) X(4, 16, 8) X(2, 24, 8) \
-    X(3, 24, 8) X(4, 24, 8) X(6, 24, 8) X(4, 32, 8) X(6, 32, 8) X(8, 32, 8)
+    X(3, 24, 8) X(4, 24, 8) X(6, 24, 8) X(4, 32, 8) X(6, 32, 8) X(8, 32, 8) X(2, 16, 16) \
+    X(3, 16, 16) X(4, 16, 16) X(4, 32, 16) X(6, 32, 16) X(8, 32, 16)
 
 #define BHFWI_TB(TT, RR, WW)                                                                 \
     if (T == TT && TRE == RR && W == WW) {                                                   \
@@ -589,9 +590,9 @@ int bhfwi_create(bhfwi_ctx** out, int32_t hip_device, const bhfwi_shot* shots, i
     c->tune.waves_per_block = 4;
     c->tune.use_graph = 1;
     c->tune.time_kernels = 0;
-    c->tune.tb_steps = 4;  // measured best on single shots; bhfwi_autotune refines
-    c->tune.tb_rows = 16;
-    c->tune.tb_waves = 8;
+    c->tune.tb_steps = 6;  // measured best on single and batched shots; bhfwi_autotune refines
+    c->tune.tb_rows = 32;
+    c->tune.tb_waves = 16;
     c->tune.tile_map = 1;
     rebuild_work(c);
 

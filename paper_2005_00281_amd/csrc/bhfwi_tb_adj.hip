@@ -13,6 +13,9 @@
 //   B  correlate; transposed stress update into a_v at R and Z nodes, then
 //      the transposed velocity update products -> LDS;
 //   C  gather the products into a_tau.
+// Only values needed by the radial neighbour rows (other waves) go through
+// LDS; the axial neighbours are lanes of the same wave and are read with DPP
+// wavefront shifts, which keeps the LDS footprint at 8 planes.
 // The gradient and illumination sums stay in registers for the T steps and
 // are added to the accumulators once per launch (owned cells only).  As in
 // the forward kernel the step loop has no per-cell branches: zero
@@ -24,7 +27,7 @@
 namespace bhfwi {
 
 template <int T, int TRE, int W>
-__global__ void __launch_bounds__(64 * W)
+__global__ void __launch_bounds__(64 * W, (TRE == W && W >= 16) ? 8 : 1)
 k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int nwork, int map,
          int n_hi, int nsteps, const float* __restrict__ lam, const float* __restrict__ mu,
          const float* __restrict__ rho, const int* __restrict__ rec_k,
@@ -36,7 +39,7 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
     static_assert(TRE % W == 0 && TRE > 2 * T && 64 > 2 * T, "tile too small for the halo");
     constexpr int RPT = TRE / W;
     constexpr int LDW = (TRE + 2) * 64;
-    enum { ERR = 0, ETT, EZZ, EZ, ER, UR, HR, DZR, DZZ, ZR, HVR, HVZ, NPL };
+    enum { ERR = 0, ETT, ER, UR, HR, ZR, HVR, HVZ, NPL };
     __shared__ float L[NPL][LDW];
     __shared__ float Lres[T][64];  // residual/3 of this lane's receiver, per step
 
@@ -124,10 +127,10 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
         dbR[j] = up ? dt * 2.0f / (r_im + r0) : 0.f;
         dbZ[j] = in ? dt * 2.0f / (r0 + r_kp) : 0.f;
         dmuS[j] = up ? dt * mu_harm(m_im, m0, m_imkp, m_kp) : 0.f;
-        rR[j] = (iin && i >= 1) ? 0.5f / (i * dr) : 0.f;
-        rRm[j] = (iin && i >= 1) ? 0.5f / ((i - 0.5f) * dr) : 0.f;
-        rZ[j] = iin ? 0.5f / ((i + 0.5f) * dr) : 0.f;
-        mrow[j] = (iin && i >= 1) ? 1.f : 0.f;
+        rR[j] = wave_uniform((iin && i >= 1) ? 0.5f / (i * dr) : 0.f);
+        rRm[j] = wave_uniform((iin && i >= 1) ? 0.5f / ((i - 0.5f) * dr) : 0.f);
+        rZ[j] = wave_uniform(iin ? 0.5f / ((i + 0.5f) * dr) : 0.f);
+        mrow[j] = wave_uniform((iin && i >= 1) ? 1.f : 0.f);
         qA[j] = qB[j] = qC[j] = qD[j] = 0.f;
         pTr[j] = pRr[j] = pTz[j] = pZz[j] = pG[j] = pH[j] = 0.f;
         a_ri[j] = a_rh[j] = 0.f;
@@ -157,6 +160,10 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
                 pG[j] = Ai[q + 4 * LZ];
             }
         }
+        a_ri[j] = wave_uniform(a_ri[j]);
+        b_ri[j] = wave_uniform(b_ri[j]);
+        a_rh[j] = wave_uniform(a_rh[j]);
+        b_rh[j] = wave_uniform(b_rh[j]);
     }
 
     // the residual of every step of this launch at this lane's receiver (if
@@ -236,8 +243,6 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
                 }
                 L[ERR][x] = Err;
                 L[ETT][x] = Ett;
-                L[EZZ][x] = Ezz;
-                L[EZ][x] = Ez;
                 L[ER][x] = Er;
                 Err_[j] = Err;
                 Ett_[j] = Ett;
@@ -261,7 +266,8 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
                 const int x = (wave + W * j + 1) * 64 + lane;
                 // Eq. 7-8 with the strain rates of v^{n+1/2} and dJ/dtau^{n+1}
                 const float vr0 = vr0_[j], vr1 = L[HVR][x + 64], vz0 = vz0_[j];
-                const float vz_km = L[HVZ][x - 1], vr_kp = L[HVR][x + 1], vz_im = L[HVZ][x - 64];
+                const float vz_km = from_lane_below(vz0), vr_kp = from_lane_above(vr0);
+                const float vz_im = L[HVZ][x - 64];
                 const float err = (vr1 - vr0) * idr;
                 const float ett = (vr1 + vr0) * rZ[j];
                 const float ezz = (vz0 - vz_km) * idz;
@@ -284,8 +290,9 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
                 ge[j] += dt * (ur * ur + uz * uz);
                 // transposed stress update into a_v, then the transposed velocity update
                 avr[j] += mrow[j] * ((L[ERR][x - 64] - Err_[j]) * idr + L[ETT][x - 64] * rRm[j] +
-                                     Ett_[j] * rZ[j] + (L[EZ][x - 1] - Ez_[j]) * idz);
-                avz[j] += (Ezz_[j] - L[EZZ][x + 1]) * idz + (Er_[j] - L[ER][x + 64]) * idr;
+                                     Ett_[j] * rZ[j] + (from_lane_below(Ez_[j]) - Ez_[j]) * idz);
+                avz[j] += (Ezz_[j] - from_lane_above(Ezz_[j])) * idz +
+                          (Er_[j] - L[ER][x + 64]) * idr;
                 const float W1 = dbR[j] * avr[j];
                 float aDr = W1, aDzR = W1;
                 const float W2 = dbZ[j] * avz[j];
@@ -311,8 +318,6 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
                 ZS_[j] = -aDrZ * idr + W2 * rZ[j];
                 L[UR][x] = U_[j];
                 L[HR][x] = H_[j];
-                L[DZR][x] = aDzR;
-                L[DZZ][x] = aDzZ;
                 L[ZR][x] = aDrZ * idr + W2 * rZ[j];
             }
             __syncthreads();
@@ -323,8 +328,9 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
                 const float h0 = H_[j], h1 = L[HR][x + 64];
                 trr[j] += U_[j] + h0 - L[UR][x + 64] + h1;
                 ttt[j] -= h0 + h1;
-                tzz[j] += (L[DZZ][x - 1] - DzZ_[j]) * idz;
-                trz[j] += mrow[j] * ((DzR_[j] - L[DZR][x + 1]) * idz + ZS_[j] + L[ZR][x - 64]);
+                tzz[j] += (from_lane_below(DzZ_[j]) - DzZ_[j]) * idz;
+                trz[j] += mrow[j] * ((DzR_[j] - from_lane_above(DzR_[j])) * idz + ZS_[j] +
+                                     L[ZR][x - 64]);
             }
         }
     };

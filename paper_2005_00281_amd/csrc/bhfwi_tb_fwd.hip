@@ -7,7 +7,8 @@
 // coefficients and its PML memories in registers (thread (wave w, lane l)
 // holds rows w, w+W, ..., so a row index is uniform over a wave), and shares
 // the fields through LDS (with a zeroed guard row above and below) for the
-// neighbour reads.  Every step needs the neighbours' previous values, so the
+// radial neighbour reads; axial neighbours are lanes of the same wave, read
+// with DPP wavefront shifts.  Every step needs the neighbours' previous values, so the
 // correct region shrinks by one cell per step on every side; after T steps it
 // is exactly the owned tile, which is all that is written back.  State
 // crosses HBM once per T steps instead of once per step.
@@ -27,7 +28,7 @@ struct IntC {
 };
 
 template <int T, int TRE, int W>
-__global__ void __launch_bounds__(64 * W)
+__global__ void __launch_bounds__(64 * W, (TRE == W && W >= 16) ? 8 : 1)
 k_fwd_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int nwork, int map,
          int n0,
          int nsteps, const float* __restrict__ lam, const float* __restrict__ mu,
@@ -40,7 +41,7 @@ k_fwd_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
     static_assert(TRE % W == 0 && TRE > 2 * T && 64 > 2 * T, "tile too small for the halo");
     constexpr int RPT = TRE / W;  // rows per thread
     constexpr int LDW = (TRE + 2) * 64;   // one LDS plane with guard rows
-    enum { TRR = 0, TTT, TZZ, TRZ, VR, VZ, NPL };
+    enum { TRR = 0, TTT, TRZ, VR, VZ, NPL };
     __shared__ float L[NPL][LDW];
     __shared__ float Lwav[T];  // source samples of this launch's steps
 
@@ -131,8 +132,8 @@ k_fwd_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
         dbZ[j] = in ? dt * 2.0f / (r0 + r_kp) : 0.f;
         dmuS[j] = up ? dt * mu_harm(m_im, m0, m_imkp, m_kp) : 0.f;
         srcw[j] = (in && i == 0 && k == S.src_k) ? S.src_scale : 0.f;
-        rR[j] = (iin && i >= 1) ? 0.5f / (i * dr) : 0.f;
-        rZ[j] = iin ? 0.5f / ((i + 0.5f) * dr) : 0.f;
+        rR[j] = wave_uniform((iin && i >= 1) ? 0.5f / (i * dr) : 0.f);
+        rZ[j] = wave_uniform(iin ? 0.5f / ((i + 0.5f) * dr) : 0.f);
         pA[j] = pB[j] = pC[j] = pD[j] = pE[j] = pF[j] = pG[j] = pH[j] = 0.f;
         a_ri[j] = a_rh[j] = 0.f;
         b_ri[j] = b_rh[j] = 1.f;
@@ -158,10 +159,13 @@ k_fwd_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
                 pG[j] = Fi[q + 3 * LZ];
             }
         }
+        a_ri[j] = wave_uniform(a_ri[j]);
+        b_ri[j] = wave_uniform(b_ri[j]);
+        a_rh[j] = wave_uniform(a_rh[j]);
+        b_rh[j] = wave_uniform(b_rh[j]);
         const int x = (e + 1) * 64 + lane;
         L[TRR][x] = trr[j];
         L[TTT][x] = ttt[j];
-        L[TZZ][x] = tzz[j];
         L[TRZ][x] = trz[j];
         L[VR][x] = vr[j];
         L[VZ][x] = vz[j];
@@ -178,8 +182,8 @@ k_fwd_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
             for (int j = 0; j < RPT; ++j) {
                 const int x = (wave + W * j + 1) * 64 + lane;
                 const float trr_m = L[TRR][x - 64], ttt_m = L[TTT][x - 64];
-                const float trz_km = L[TRZ][x - 1], trz_ip = L[TRZ][x + 64];
-                const float tzz_kp = L[TZZ][x + 1];
+                const float trz_km = from_lane_below(trz[j]), trz_ip = L[TRZ][x + 64];
+                const float tzz_kp = from_lane_above(tzz[j]);
                 float Dr = (trr[j] - trr_m) * idr;
                 float Dz = (trz[j] - trz_km) * idz;
                 float Dr2 = (trz_ip - trz[j]) * idr;
@@ -205,8 +209,8 @@ k_fwd_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
             for (int j = 0; j < RPT; ++j) {
                 const int e = wave + W * j;
                 const int x = (e + 1) * 64 + lane;
-                const float vr_ip = L[VR][x + 64], vz_km = L[VZ][x - 1];
-                const float vr_kp = L[VR][x + 1], vz_im = L[VZ][x - 64];
+                const float vr_ip = L[VR][x + 64], vz_km = from_lane_below(vz[j]);
+                const float vr_kp = from_lane_above(vr[j]), vz_im = L[VZ][x - 64];
                 float err = (vr_ip - vr[j]) * idr;
                 const float ett = (vr_ip + vr[j]) * rZ[j];
                 float ezz = (vz[j] - vz_km) * idz;
@@ -229,7 +233,6 @@ k_fwd_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
                 trz[j] += dmuS[j] * (ez + er);
                 L[TRR][x] = trr[j];
                 L[TTT][x] = ttt[j];
-                L[TZZ][x] = tzz[j];
                 L[TRZ][x] = trz[j];
                 const int i = wk.z - T + e;
                 const bool own = kin && lown && e >= T && e < TRE - T && i < NR;

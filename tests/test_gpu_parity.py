@@ -55,10 +55,12 @@ def T(rows=4, wpb=4, graph=1, tb=0, tbr=16, tbw=4, tmap=1):
 
 FWD_TUNES = [T(1, 1, 0), T(2, 4, 1), T(3, 2, 1), T(4, 4, 0), T(16, 4, 1), T(64, 8, 0),
              T(tb=2), T(tb=3, graph=0), T(tb=4), T(tb=4, tbw=8), T(tb=6, tbr=24, tbw=8, graph=0),
-             T(tb=8, tbr=32, tbw=8), T(tb=3, tbr=24, tbw=8), T(tb=4, tmap=0)]
+             T(tb=8, tbr=32, tbw=8), T(tb=3, tbr=24, tbw=8), T(tb=4, tmap=0), T(tb=4, tbw=16),
+             T(tb=3, tbw=16, graph=0), T(tb=6, tbr=32, tbw=16)]
 GRAD_TUNES = [T(1, 1, 1), T(2, 4, 0), T(4, 4, 1), T(5, 4, 1), T(64, 8, 0), T(tb=4),
               T(tb=3, graph=0), T(tb=4, tbw=8), T(tb=6, tbr=24, tbw=8), T(tb=8, tbr=32, tbw=8),
-              T(tb=4, tbw=8, tmap=0)]
+              T(tb=4, tbw=8, tmap=0), T(tb=4, tbw=16), T(tb=2, tbw=16, graph=0),
+              T(tb=8, tbr=32, tbw=16)]
 
 
 def oracle_traces(w, s=0, which="start"):
