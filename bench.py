@@ -51,6 +51,25 @@ PMC_TRAFFIC = {
 }
 
 
+# temporally blocked shapes (T, tile rows incl. halo, waves) of both kernels,
+# and those of the forward kernel only
+TB_SHAPES = [(2, 16, 4), (3, 16, 4), (4, 16, 4), (2, 16, 8), (3, 16, 8), (4, 16, 8),
+             (2, 24, 8), (3, 24, 8), (4, 24, 8), (6, 24, 8), (4, 32, 8), (6, 32, 8),
+             (8, 32, 8), (2, 16, 16), (3, 16, 16), (4, 16, 16), (4, 32, 16), (6, 32, 16),
+             (8, 32, 16)]
+FWD_ONLY_SHAPES = [(4, 48, 16), (6, 48, 16), (8, 48, 16)]
+
+
+def adj_shape(tune):
+    """(T, rows, waves) of the adjoint kernel under a tune (T < 2: one step
+    per launch)."""
+    if tune["adj_tb_steps"] >= 2:
+        return (tune["adj_tb_steps"], tune["adj_tb_rows"], tune["adj_tb_waves"])
+    if tune["adj_tb_steps"] == 1:
+        return (0, 0, 0)
+    return (tune["tb_steps"], tune["tb_rows"], tune["tb_waves"])
+
+
 def kernel_sources_sha():
     import hashlib
     h = hashlib.sha256()
@@ -138,6 +157,10 @@ def main():
     ap.add_argument("--tb-rows", type=int, default=0)
     ap.add_argument("--tb-waves", type=int, default=0)
     ap.add_argument("--tile-map", type=int, default=-1)
+    ap.add_argument("--adj-tb", type=int, default=-1,
+                    help="adjoint steps per launch (0: as the forward, 1: one per launch)")
+    ap.add_argument("--adj-tb-rows", type=int, default=0)
+    ap.add_argument("--adj-tb-waves", type=int, default=0)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -191,12 +214,15 @@ def main():
     del lam_t, mu_t
     mask = torch.as_tensor(w.mask, device=dev)
     inv = Inversion(surveys, f32(w.vp_start), f32(w.vs_start), rho, wavs, observed, mask)
-    if args.tb >= 0 or args.rows or args.no_autotune:
+    if args.tb >= 0 or args.adj_tb >= 0 or args.rows or args.no_autotune:
         for sv in surveys:
             sv.set_tune(rows_per_wave=args.rows or None,
                         tb_steps=args.tb if args.tb >= 0 else None,
                         tb_rows=args.tb_rows or None, tb_waves=args.tb_waves or None,
-                        tile_map=args.tile_map if args.tile_map >= 0 else None)
+                        tile_map=args.tile_map if args.tile_map >= 0 else None,
+                        adj_tb_steps=args.adj_tb if args.adj_tb >= 0 else None,
+                        adj_tb_rows=args.adj_tb_rows or None,
+                        adj_tb_waves=args.adj_tb_waves or None)
     else:
         lam_s, mu_s = P.moduli(f32(w.vp_start), f32(w.vs_start), rho)
         t_at = time.perf_counter()
@@ -206,22 +232,31 @@ def main():
         del lam_s, mu_s
     if args.sweep:
         keep = surveys[0].get_tune()
-        shapes = [(T, R, W_) for (T, R, W_) in
-                  [(2, 16, 4), (3, 16, 4), (4, 16, 4), (2, 16, 8), (3, 16, 8), (4, 16, 8),
-                   (2, 24, 8), (3, 24, 8), (4, 24, 8), (6, 24, 8), (4, 32, 8), (6, 32, 8),
-                   (8, 32, 8), (2, 16, 16), (3, 16, 16), (4, 16, 16), (4, 32, 16), (6, 32, 16),
-                   (8, 32, 16)]]
-        for (T, R, W_) in shapes:
+        a0 = adj_shape(keep)
+
+        def timed(**kw):
+            for x in surveys:
+                x.set_tune(**kw)
+            inv.gradient()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            inv.gradient()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) * 1e3
+
+        # forward shapes with the adjoint held at the tuned one, then the reverse
+        for (T, R, W_) in TB_SHAPES + FWD_ONLY_SHAPES:
             for tmap in (0, 1):
-                for x in surveys:
-                    x.set_tune(tb_steps=T, tb_rows=R, tb_waves=W_, tile_map=tmap)
-                inv.gradient()
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                inv.gradient()
-                torch.cuda.synchronize()
-                log("sweep T %d rows %d waves %d map %d: %.2f ms per gradient" % (
-                    T, R, W_, tmap, (time.perf_counter() - t0) * 1e3))
+                ms = timed(tb_steps=T, tb_rows=R, tb_waves=W_, tile_map=tmap,
+                           adj_tb_steps=a0[0] if a0[0] >= 2 else 1, adj_tb_rows=a0[1],
+                           adj_tb_waves=a0[2])
+                log("sweep fwd T %d rows %d waves %d map %d: %.2f ms per gradient" % (
+                    T, R, W_, tmap, ms))
+        for x in surveys:
+            x.set_tune(**keep)
+        for (T, R, W_) in TB_SHAPES:
+            ms = timed(adj_tb_steps=T, adj_tb_rows=R, adj_tb_waves=W_)
+            log("sweep adj T %d rows %d waves %d: %.2f ms per gradient" % (T, R, W_, ms))
         for x in surveys:
             x.set_tune(**keep)
     if args.no_graph:
@@ -270,8 +305,8 @@ def main():
     adj_avg = adj_ms / max(1, adj_n)
     adj_bytes = ADJ_BYTES_PER_CELL_STEP * z.cell_steps / max(1, adj_n)  # per launch
     achieved = adj_bytes / (adj_avg * 1e-3) / 1e9
-    T = tune["tb_steps"]
-    kname = ("k_adj_tb<%d, %d, %d>" % (T, tune["tb_rows"], tune["tb_waves"]) if T >= 2
+    ashape = adj_shape(tune)
+    kname = ("k_adj_tb<%d, %d, %d>" % ashape if ashape[0] >= 2
              else "k_adj_step<%d>" % (tune["rows_per_wave"] if tune["rows_per_wave"] <= 4 else 0))
     pmc = PMC_TRAFFIC.get((kname, tune.get("tile_map", 1), args.workload, kernel_sources_sha()))
     traffic = (None if pmc is None
@@ -308,7 +343,7 @@ def main():
             sh = w.shots[s_]
             g_ = [i for i, g in enumerate(pl.groups) if s_ in g][0]
             sv1 = P.Survey([sh], (w.NRg, w.NZg), ckpt_every=pl.ckpt_every[g_])
-            sv1.set_tune(rows_per_wave=2, tb_steps=0, use_graph=0)
+            sv1.set_tune(rows_per_wave=2, tb_steps=0, adj_tb_steps=0, use_graph=0)
             wav1 = sv1.pack_wavelets([sh.wavelet])
             off = sum(len(w.shots[q].rec_k) * w.shots[q].nt for q in pl.groups[g_] if q < s_)
             obs1 = observed[g_][off: off + len(sh.rec_k) * sh.nt].clone()

@@ -94,7 +94,7 @@ typedef struct {
     int32_t time_kernels;     /* 1 (with use_graph 0): bracket every time-step
                                  kernel with a pair of HIP events on its stream;
                                  read the sums with bhfwi_kernel_times */
-    int32_t tb_steps;         /* >= 2: forward, recompute and adjoint steps run
+    int32_t tb_steps;         /* >= 2: forward and recompute steps run
                                  T = tb_steps at a time in LDS-tiled kernels;
                                  0 or 1: one step per launch (wave march) */
     int32_t tb_rows;          /* radial rows of a tile including its halo */
@@ -102,12 +102,19 @@ typedef struct {
                                  (tb_steps, tb_rows, tb_waves): (2|3|4, 16, 4),
                                  (2|3|4, 16, 8), (2|3|4|6, 24, 8),
                                  (4|6|8, 32, 8), (2|3|4, 16, 16),
-                                 (4|6|8, 32, 16) */
+                                 (4|6|8, 32, 16), (4|6|8, 48, 16) */
     int32_t tile_map;         /* order of the tiles of a temporally blocked launch:
                                  0: axial tile fastest, workgroups in table order;
                                  1: radial tile fastest, and each of the 8 XCDs of
                                  the GPU walks one contiguous chunk of the table
                                  so that tiles with overlapping halos share its L2 */
+    int32_t adj_tb_steps;     /* adjoint: 0 = the forward's shape (tb_*), 1 = one
+                                 step per launch (wave march), >= 2 = its own
+                                 shape (adj_tb_steps, adj_tb_rows, adj_tb_waves)
+                                 from the supported forward shapes except
+                                 (4|6|8, 48, 16) */
+    int32_t adj_tb_rows;
+    int32_t adj_tb_waves;
 } bhfwi_tune;
 
 /* Memory of one group of shots evaluated together (bhfwi_plan_bytes). */
@@ -153,12 +160,14 @@ const char *bhfwi_last_error(const bhfwi_ctx *ctx);
 int bhfwi_sizes(const bhfwi_ctx *ctx, bhfwi_sizes_t *out);
 int bhfwi_set_tune(bhfwi_ctx *ctx, const bhfwi_tune *tune);
 int bhfwi_get_tune(const bhfwi_ctx *ctx, bhfwi_tune *out);
-/* Autotuner: times every supported kernel shape (one-step wave marches of 1,
- * 2 and 4 rows per wave and every temporally blocked shape) on this survey --
- * probe_steps forward steps storing the velocity history from a zero state,
- * then the adjoint over the same steps driven by a zero residual -- keeps the
- * fastest as the context's tune, copies it to *best (host) and its time to
- * *best_ms (host).  probe_steps is clamped to [1, min(ckpt_every, nt)].
+/* Autotuner: times, on this survey, every forward kernel shape (one-step wave
+ * marches of 1, 2 and 4 rows per wave, every temporally blocked shape in both
+ * tile maps) over probe_steps forward steps storing the velocity history from
+ * a zero state and keeps the fastest; then every adjoint shape (marches and
+ * tiles) over the same steps driven by a zero residual.  Installs the result
+ * as the context's tune, copies it to *best (host) and the sum of the two
+ * probe times to *best_ms (host).  probe_steps is clamped to
+ * [1, min(ckpt_every, nt)].
  * traces (trace_elems floats), fwd_ws, adj_ws and acc are scratch; their
  * contents are overwritten.  Synchronises the stream. */
 int bhfwi_autotune(bhfwi_ctx *ctx, void *stream, const float *lam, const float *mu,

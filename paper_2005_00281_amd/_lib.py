@@ -47,7 +47,8 @@ class Tune(C.Structure):
     _fields_ = [("rows_per_wave", C.c_int32), ("waves_per_block", C.c_int32),
                 ("use_graph", C.c_int32), ("time_kernels", C.c_int32),
                 ("tb_steps", C.c_int32), ("tb_rows", C.c_int32), ("tb_waves", C.c_int32),
-                ("tile_map", C.c_int32)]
+                ("tile_map", C.c_int32), ("adj_tb_steps", C.c_int32),
+                ("adj_tb_rows", C.c_int32), ("adj_tb_waves", C.c_int32)]
 
 
 class PlanBytes(C.Structure):

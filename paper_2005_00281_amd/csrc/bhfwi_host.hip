@@ -87,6 +87,20 @@ thread_local std::string g_create_err;  // message of the last failed bhfwi_crea
 
 }  // namespace
 
+// Tiles (shot, k0, i0, i1) of one temporally blocked shape, ordered by the
+// nt of their shot (non-increasing), with a device copy.
+struct TileSet {
+    std::vector<int4> t;
+    std::vector<int> nt;
+    int4* d = nullptr;
+};
+
+// A temporally blocked kernel shape: T steps per launch, TRE tile rows
+// including the halo, W waves per workgroup; T = 0 means one step per launch.
+struct Shape {
+    int T, TRE, W;
+};
+
 struct bhfwi_ctx {
     int device = 0;
     int nshot = 0;
@@ -97,17 +111,15 @@ struct bhfwi_ctx {
     std::vector<ShotDev> sd;
     int64_t cells = 0, fst_len = 0, ast_len = 0, trace_len = 0, wave_len = 0, cell_steps = 0;
     int nt_max = 0, nseg = 0;
-    bhfwi_tune tune{16, 4, 1, 0, 0, 16, 4};
+    bhfwi_tune tune{};
     std::vector<int4> work;
     std::vector<int> work_nt;  // nt of each work item's shot, non-increasing
-    std::vector<int4> tiles;   // temporally blocked tiles (shot, k0, i0, i1)
-    std::vector<int> tiles_nt;
+    TileSet ftiles, atiles;    // temporally blocked tiles of the forward / adjoint shape
     ShotDev* d_shots = nullptr;
     int* d_rec = nullptr;
     float* d_pml_r = nullptr;
     float* d_pml_z = nullptr;
     int4* d_work = nullptr;
-    int4* d_tiles = nullptr;
     void* d_scratch = nullptr;
     int* d_status = nullptr;  // device word raised by kernels that see non-finite sums
     hipStream_t cap_stream = nullptr;  // private stream that graphs are captured on
@@ -166,6 +178,60 @@ void pml_coef(double x, double d0, double f0, double dt, float* a, float* b)
     *a = (float)(d * (bb - 1.0) / (d + al));
 }
 
+Shape fwd_shape(const bhfwi_ctx* c)
+{
+    const bhfwi_tune& t = c->tune;
+    return t.tb_steps >= 2 ? Shape{t.tb_steps, t.tb_rows, t.tb_waves} : Shape{0, 0, 0};
+}
+
+// The adjoint runs its own shape when adj_tb_steps >= 2, one step per launch
+// when it is 1, and the forward's shape when it is 0.
+Shape adj_shape(const bhfwi_ctx* c)
+{
+    const bhfwi_tune& t = c->tune;
+    if (t.adj_tb_steps >= 2) return Shape{t.adj_tb_steps, t.adj_tb_rows, t.adj_tb_waves};
+    if (t.adj_tb_steps == 1) return Shape{0, 0, 0};
+    return fwd_shape(c);
+}
+
+void build_tiles(const bhfwi_ctx* c, const std::vector<int>& order, Shape sh, TileSet* ts)
+{
+    ts->t.clear();
+    ts->nt.clear();
+    if (sh.T < 2) return;
+    const int TR = sh.TRE - 2 * sh.T, TZ = 64 - 2 * sh.T;
+    for (int s : order) {
+        const ShotDev& S = c->sd[s];
+        if (c->tune.tile_map == 1) {
+            for (int k0 = 0; k0 < S.NZ; k0 += TZ)
+                for (int i0 = 0; i0 < S.NR; i0 += TR) {
+                    ts->t.push_back(make_int4(s, k0, i0, std::min(i0 + TR, S.NR)));
+                    ts->nt.push_back(S.nt);
+                }
+        } else {
+            for (int i0 = 0; i0 < S.NR; i0 += TR)
+                for (int k0 = 0; k0 < S.NZ; k0 += TZ) {
+                    ts->t.push_back(make_int4(s, k0, i0, std::min(i0 + TR, S.NR)));
+                    ts->nt.push_back(S.nt);
+                }
+        }
+    }
+}
+
+int upload_tiles(bhfwi_ctx* c, TileSet* ts)
+{
+    if (ts->d) {
+        HIPOK(c, hipFree(ts->d));
+        ts->d = nullptr;
+    }
+    if (!ts->t.empty()) {
+        HIPOK(c, hipMalloc(&ts->d, sizeof(int4) * ts->t.size()));
+        HIPOK(c, hipMemcpy(ts->d, ts->t.data(), sizeof(int4) * ts->t.size(),
+                           hipMemcpyHostToDevice));
+    }
+    return BHFWI_OK;
+}
+
 void rebuild_work(bhfwi_ctx* c)
 {
     c->work.clear();
@@ -184,27 +250,8 @@ void rebuild_work(bhfwi_ctx* c)
                 c->work_nt.push_back(S.nt);
             }
     }
-    c->tiles.clear();
-    c->tiles_nt.clear();
-    if (c->tune.tb_steps >= 2) {
-        const int T = c->tune.tb_steps, TR = c->tune.tb_rows - 2 * T, TZ = 64 - 2 * T;
-        for (int s : order) {
-            const ShotDev& S = c->sd[s];
-            if (c->tune.tile_map == 1) {
-                for (int k0 = 0; k0 < S.NZ; k0 += TZ)
-                    for (int i0 = 0; i0 < S.NR; i0 += TR) {
-                        c->tiles.push_back(make_int4(s, k0, i0, std::min(i0 + TR, S.NR)));
-                        c->tiles_nt.push_back(S.nt);
-                    }
-            } else {
-                for (int i0 = 0; i0 < S.NR; i0 += TR)
-                    for (int k0 = 0; k0 < S.NZ; k0 += TZ) {
-                        c->tiles.push_back(make_int4(s, k0, i0, std::min(i0 + TR, S.NR)));
-                        c->tiles_nt.push_back(S.nt);
-                    }
-            }
-        }
-    }
+    build_tiles(c, order, fwd_shape(c), &c->ftiles);
+    build_tiles(c, order, adj_shape(c), &c->atiles);
 }
 
 int upload_work(bhfwi_ctx* c)
@@ -213,19 +260,11 @@ int upload_work(bhfwi_ctx* c)
         HIPOK(c, hipFree(c->d_work));
         c->d_work = nullptr;
     }
-    if (c->d_tiles) {
-        HIPOK(c, hipFree(c->d_tiles));
-        c->d_tiles = nullptr;
-    }
     HIPOK(c, hipMalloc(&c->d_work, sizeof(int4) * c->work.size()));
     HIPOK(c, hipMemcpy(c->d_work, c->work.data(), sizeof(int4) * c->work.size(),
                        hipMemcpyHostToDevice));
-    if (!c->tiles.empty()) {
-        HIPOK(c, hipMalloc(&c->d_tiles, sizeof(int4) * c->tiles.size()));
-        HIPOK(c, hipMemcpy(c->d_tiles, c->tiles.data(), sizeof(int4) * c->tiles.size(),
-                           hipMemcpyHostToDevice));
-    }
-    return BHFWI_OK;
+    if (int rc = upload_tiles(c, &c->ftiles)) return rc;
+    return upload_tiles(c, &c->atiles);
 }
 
 int default_rows(const bhfwi_ctx* c)
@@ -246,11 +285,10 @@ int active_items(const bhfwi_ctx* c, int n)
     return (int)(it - c->work_nt.begin());
 }
 
-int active_tiles(const bhfwi_ctx* c, int n)
+int active_tiles(const TileSet& ts, int n)
 {
-    auto it = std::partition_point(c->tiles_nt.begin(), c->tiles_nt.end(),
-                                   [n](int nt) { return nt > n; });
-    return (int)(it - c->tiles_nt.begin());
+    auto it = std::partition_point(ts.nt.begin(), ts.nt.end(), [n](int nt) { return nt > n; });
+    return (int)(it - ts.nt.begin());
 }
 
 int check_ctx(bhfwi_ctx* c)
@@ -331,63 +369,96 @@ void adj_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const flo
 }
 
 // Supported temporally blocked shapes: (steps T, tile rows incl. halo, waves).
-#define BHFWI_TB_SHAPES(X) \
+// The adjoint holds more per-cell state than the forward, so its tiles stop
+// at two rows per thread.
+#define BHFWI_ADJ_SHAPES(X) \
     X(2, 16, 4) X(3, 16, 4) X(4, 16, 4) X(2, 16, 8) X(3, 16, 8) X(4, 16, 8) X(2, 24, 8) \
     X(3, 24, 8) X(4, 24, 8) X(6, 24, 8) X(4, 32, 8) X(6, 32, 8) X(8, 32, 8) X(2, 16, 16) \
     X(3, 16, 16) X(4, 16, 16) X(4, 32, 16) X(6, 32, 16) X(8, 32, 16)
+#define BHFWI_FWD_SHAPES(X) BHFWI_ADJ_SHAPES(X) X(4, 48, 16) X(6, 48, 16) X(8, 48, 16)
 
 #define BHFWI_TB(TT, RR, WW)                                                                 \
     if (T == TT && TRE == RR && W == WW) {                                                   \
         hipLaunchKernelGGL((bhfwi::k_fwd_tb<TT, RR, WW>), dim3(nact), dim3(64 * WW), 0, st,  \
-                           c->d_shots, c->d_tiles, nact, c->tune.tile_map, n0, nsteps, lam,  \
+                           c->d_shots, c->ftiles.d, nact, c->tune.tile_map, n0, nsteps, lam, \
                            mu, rho, wav, c->d_rec, c->d_pml_r, c->d_pml_z, in, out, traces,  \
                            hist, (long long)(2 * c->cells), (long long)c->cells);            \
         return;                                                                              \
     }
 
-// nsteps (<= tb_steps) forward steps from step n0 in LDS-tiled kernels.
+// nsteps (<= the forward shape's T) forward steps from step n0 in LDS-tiled kernels.
 void fwd_tb_launch(bhfwi_ctx* c, hipStream_t st, int n0, int nsteps, const float* lam,
                    const float* mu, const float* rho, const float* wav, const float* in,
                    float* out, float* traces, float* hist)
 {
-    const int nact = active_tiles(c, n0);
+    const int nact = active_tiles(c->ftiles, n0);
     if (nact <= 0) return;
-    const int T = c->tune.tb_steps, TRE = c->tune.tb_rows, W = c->tune.tb_waves;
+    const Shape sh = fwd_shape(c);
+    const int T = sh.T, TRE = sh.TRE, W = sh.W;
     EvScope ev(c, st, hist ? 1 : 0);
-    BHFWI_TB_SHAPES(BHFWI_TB)
+    BHFWI_FWD_SHAPES(BHFWI_TB)
 }
 #undef BHFWI_TB
 
 #define BHFWI_TBA(TT, RR, WW)                                                                \
     if (T == TT && TRE == RR && W == WW) {                                                   \
         hipLaunchKernelGGL((bhfwi::k_adj_tb<TT, RR, WW>), dim3(nact), dim3(64 * WW), 0, st,  \
-                           c->d_shots, c->d_tiles, nact, c->tune.tile_map, n_hi, nsteps,     \
+                           c->d_shots, c->atiles.d, nact, c->tune.tile_map, n_hi, nsteps,    \
                            lam, mu, rho, c->d_rec, resid, c->d_pml_r, c->d_pml_z, in, out,   \
                            hist_hi, (long long)(2 * c->cells), acc, (long long)c->cells);    \
         return;                                                                              \
     }
 
-// nsteps (<= tb_steps) adjoint steps n_hi, n_hi - 1, ... in LDS-tiled kernels;
-// hist_hi is the history slot of step n_hi.
+// nsteps (<= the adjoint shape's T) adjoint steps n_hi, n_hi - 1, ... in
+// LDS-tiled kernels; hist_hi is the history slot of step n_hi.
 void adj_tb_launch(bhfwi_ctx* c, hipStream_t st, int n_hi, int nsteps, const float* lam,
                    const float* mu, const float* rho, const float* resid, const float* in,
                    float* out, const float* hist_hi, float* acc)
 {
-    const int nact = active_tiles(c, n_hi - nsteps + 1);
+    const int nact = active_tiles(c->atiles, n_hi - nsteps + 1);
     if (nact <= 0) return;
-    const int T = c->tune.tb_steps, TRE = c->tune.tb_rows, W = c->tune.tb_waves;
+    const Shape sh = adj_shape(c);
+    const int T = sh.T, TRE = sh.TRE, W = sh.W;
     EvScope ev(c, st, 2);
-    BHFWI_TB_SHAPES(BHFWI_TBA)
+    BHFWI_ADJ_SHAPES(BHFWI_TBA)
 }
 #undef BHFWI_TBA
 
-bool tb_supported(int T, int TRE, int W)
-{
 #define BHFWI_TBS(TT, RR, WW) \
     if (T == TT && TRE == RR && W == WW) return true;
-    BHFWI_TB_SHAPES(BHFWI_TBS)
-#undef BHFWI_TBS
+bool fwd_supported(int T, int TRE, int W)
+{
+    BHFWI_FWD_SHAPES(BHFWI_TBS)
     return false;
+}
+bool adj_supported(int T, int TRE, int W)
+{
+    BHFWI_ADJ_SHAPES(BHFWI_TBS)
+    return false;
+}
+#undef BHFWI_TBS
+
+// Adjoint steps [n0, n1) run backwards from n1 - 1 in buffers ab[*m & 1] ->
+// ab[(*m + 1) & 1]; hist holds v of step n at slot n - n0.
+void adj_range(bhfwi_ctx* c, hipStream_t st, int n0, int n1, const float* lam, const float* mu,
+               const float* rho, const float* resid, float* const ab[2], int* m,
+               const float* hist, float* acc)
+{
+    const int64_t hslot = 2 * c->cells;
+    const Shape sh = adj_shape(c);
+    if (sh.T >= 2) {
+        for (int n = n1 - 1; n >= n0;) {
+            const int nb = std::min(sh.T, n - n0 + 1);
+            adj_tb_launch(c, st, n, nb, lam, mu, rho, resid, ab[*m & 1], ab[(*m + 1) & 1],
+                          hist + (int64_t)(n - n0) * hslot, acc);
+            ++*m;
+            n -= nb;
+        }
+    } else {
+        for (int n = n1 - 1; n >= n0; --n, ++*m)
+            adj_launch(c, st, n, lam, mu, rho, resid, ab[*m & 1], ab[(*m + 1) & 1],
+                       hist + (int64_t)(n - n0) * hslot, acc);
+    }
 }
 
 // Forward steps [n0, n1) from buffer b[*parity] (ping-pong), one launch per
@@ -398,7 +469,7 @@ void fwd_range(bhfwi_ctx* c, hipStream_t st, int n0, int n1, const float* lam, c
                float* traces, float* hist, int hist_base)
 {
     const int64_t hslot = 2 * c->cells;
-    const int T = c->tune.tb_steps >= 2 ? c->tune.tb_steps : 1;
+    const int T = std::max(1, fwd_shape(c).T);
     for (int n = n0; n < n1;) {
         const int nb = std::min(T, n1 - n);
         float* h = hist ? hist + (int64_t)(n - hist_base) * hslot : nullptr;
@@ -433,6 +504,9 @@ int run_sequence(bhfwi_ctx* c, hipStream_t st, std::vector<uintptr_t> key, F&& r
     key.push_back((uintptr_t)c->tune.tb_rows);
     key.push_back((uintptr_t)c->tune.tb_waves);
     key.push_back((uintptr_t)c->tune.tile_map);
+    key.push_back((uintptr_t)c->tune.adj_tb_steps);
+    key.push_back((uintptr_t)c->tune.adj_tb_rows);
+    key.push_back((uintptr_t)c->tune.adj_tb_waves);
     for (size_t g = 0; g < c->graphs.size(); ++g)
         if (c->graphs[g].key == key) {
             HIPOK(c, hipGraphLaunch(c->graphs[g].exec, st));
@@ -634,7 +708,8 @@ void bhfwi_destroy(bhfwi_ctx* c)
     if (c->d_pml_r) (void)hipFree(c->d_pml_r);
     if (c->d_pml_z) (void)hipFree(c->d_pml_z);
     if (c->d_work) (void)hipFree(c->d_work);
-    if (c->d_tiles) (void)hipFree(c->d_tiles);
+    if (c->ftiles.d) (void)hipFree(c->ftiles.d);
+    if (c->atiles.d) (void)hipFree(c->atiles.d);
     if (c->d_scratch) (void)hipFree(c->d_scratch);
     if (c->d_status) (void)hipFree(c->d_status);
     delete c;
@@ -752,7 +827,11 @@ int bhfwi_set_tune(bhfwi_ctx* c, const bhfwi_tune* t)
     if (!c || !t) return BHFWI_EINVAL;
     if (t->rows_per_wave < 1 || t->use_graph < 0 || t->use_graph > 1 || t->time_kernels < 0 ||
         t->time_kernels > 1 || t->tb_steps < 0 || t->tile_map < 0 || t->tile_map > 1 ||
-        (t->tb_steps >= 2 && !tb_supported(t->tb_steps, t->tb_rows, t->tb_waves)) ||
+        (t->tb_steps >= 2 && !fwd_supported(t->tb_steps, t->tb_rows, t->tb_waves)) ||
+        t->adj_tb_steps < 0 ||
+        (t->adj_tb_steps >= 2 && !adj_supported(t->adj_tb_steps, t->adj_tb_rows, t->adj_tb_waves)) ||
+        (t->adj_tb_steps == 0 && t->tb_steps >= 2 &&
+         !adj_supported(t->tb_steps, t->tb_rows, t->tb_waves)) ||
         !(t->waves_per_block == 1 || t->waves_per_block == 2 || t->waves_per_block == 4 ||
           t->waves_per_block == 8))
         return fail(c, BHFWI_EINVAL, "bad tune (rows %d, waves/block %d)", t->rows_per_wave,
@@ -779,12 +858,56 @@ int bhfwi_autotune(bhfwi_ctx* c, void* stream, const float* lam, const float* mu
         return fail(c, BHFWI_ENOMEM, "autotune: workspace too small");
     hipStream_t st = (hipStream_t)stream;
     const int P = std::max(1, std::min<int>(probe_steps, std::min(c->ckpt_every, c->nt_max)));
-    std::vector<bhfwi_tune> cand;
     const bhfwi_tune base = c->tune;
+    float* fb[2] = {(float*)fwd_ws, (float*)fwd_ws + c->fst_len};
+    float* ab[2] = {(float*)adj_ws, (float*)adj_ws + c->ast_len};
+    float* hist = (float*)adj_ws + 2 * c->ast_len;
+    hipEvent_t e0, e1;
+    HIPOK(c, hipEventCreate(&e0));
+    HIPOK(c, hipEventCreate(&e1));
+    auto install = [&](const bhfwi_tune& t) {
+        HIPOK(c, hipStreamSynchronize(st));
+        clear_graphs(c);
+        c->tune = t;
+        c->tune.use_graph = 0;
+        c->tune.time_kernels = 0;
+        rebuild_work(c);
+        return upload_work(c);
+    };
+    auto run_fwd = [&]() {
+        launch_fill(st, fb[0], 2 * c->fst_len, 0.0f);
+        launch_fill(st, traces, c->trace_len, 0.0f);
+        int parity = 0;
+        fwd_range(c, st, 0, P, lam, mu, rho, wavelet, fb, &parity, nullptr, hist, 0);
+    };
+    auto run_adj = [&]() {
+        launch_fill(st, ab[0], 2 * c->ast_len, 0.0f);
+        int m = 0;
+        adj_range(c, st, 0, P, lam, mu, rho, traces, ab, &m, hist, acc);
+    };
+    // best of repetitions 2 and 3 of `phase` (the first warms up)
+    auto time_it = [&](auto&& phase, float* out) {
+        float tmin = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            HIPOK(c, hipEventRecord(e0, st));
+            phase();
+            HIPOK(c, hipEventRecord(e1, st));
+            HIPOK(c, hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPOK(c, hipEventElapsedTime(&ms, e0, e1));
+            if (rep > 0) tmin = std::min(tmin, ms);
+        }
+        *out = tmin;
+        return BHFWI_OK;
+    };
+    // Phase 1: the forward kernel, storing the velocity history (as the
+    // recompute does): one-step wave marches and every forward tile shape.
+    std::vector<bhfwi_tune> cand;
     for (int r : {1, 2, 4}) {
         bhfwi_tune t = base;
         t.rows_per_wave = r;
         t.tb_steps = 0;
+        t.adj_tb_steps = 0;
         cand.push_back(t);
     }
 #define BHFWI_TBC(TT, RR, WW)            \
@@ -794,60 +917,60 @@ int bhfwi_autotune(bhfwi_ctx* c, void* stream, const float* lam, const float* mu
         t.tb_rows = RR;                  \
         t.tb_waves = WW;                 \
         t.tile_map = map;                \
+        t.adj_tb_steps = 1;              \
         cand.push_back(t);               \
     }
-    BHFWI_TB_SHAPES(BHFWI_TBC)
+    BHFWI_FWD_SHAPES(BHFWI_TBC)
 #undef BHFWI_TBC
-    float* fb[2] = {(float*)fwd_ws, (float*)fwd_ws + c->fst_len};
-    float* ab[2] = {(float*)adj_ws, (float*)adj_ws + c->ast_len};
-    float* hist = (float*)adj_ws + 2 * c->ast_len;
-    const int64_t hslot = 2 * c->cells;
-    hipEvent_t e0, e1;
-    HIPOK(c, hipEventCreate(&e0));
-    HIPOK(c, hipEventCreate(&e1));
-    float best_t = 1e30f;
+    float best_f = 1e30f;
     bhfwi_tune best_tune = base;
     for (const bhfwi_tune& t : cand) {
-        HIPOK(c, hipStreamSynchronize(st));
-        clear_graphs(c);
-        c->tune = t;
-        c->tune.use_graph = 0;
-        c->tune.time_kernels = 0;
-        rebuild_work(c);
-        if (int rc = upload_work(c)) return rc;
-        float tmin = 1e30f;
-        for (int rep = 0; rep < 3; ++rep) {
-            launch_fill(st, fb[0], 2 * c->fst_len, 0.0f);
-            launch_fill(st, ab[0], 2 * c->ast_len, 0.0f);
-            launch_fill(st, traces, c->trace_len, 0.0f);
-            HIPOK(c, hipEventRecord(e0, st));
-            int parity = 0;
-            fwd_range(c, st, 0, P, lam, mu, rho, wavelet, fb, &parity, nullptr, hist, 0);
-            int m = 0;
-            if (c->tune.tb_steps >= 2) {
-                for (int n = P - 1; n >= 0;) {
-                    const int nb = std::min(c->tune.tb_steps, n + 1);
-                    adj_tb_launch(c, st, n, nb, lam, mu, rho, traces, ab[m & 1],
-                                  ab[(m + 1) & 1], hist + (int64_t)n * hslot, acc);
-                    ++m;
-                    n -= nb;
-                }
-            } else {
-                for (int n = P - 1; n >= 0; --n, ++m)
-                    adj_launch(c, st, n, lam, mu, rho, traces, ab[m & 1], ab[(m + 1) & 1],
-                               hist + (int64_t)n * hslot, acc);
-            }
-            HIPOK(c, hipEventRecord(e1, st));
-            HIPOK(c, hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIPOK(c, hipEventElapsedTime(&ms, e0, e1));
-            if (rep > 0) tmin = std::min(tmin, ms);  // first repetition warms up
-        }
-        if (tmin < best_t) {
-            best_t = tmin;
+        if (int rc = install(t)) return rc;
+        float ms;
+        if (int rc = time_it(run_fwd, &ms)) return rc;
+        if (ms < best_f) {
+            best_f = ms;
             best_tune = t;
         }
     }
+    // Phase 2: the adjoint with the fused correlation over the history the
+    // chosen forward wrote: one step per launch and every adjoint tile shape.
+    if (int rc = install(best_tune)) return rc;
+    run_fwd();
+    cand.clear();
+    if (best_tune.tb_steps >= 2) {
+        for (int r : {1, 2, 4}) {
+            bhfwi_tune t = best_tune;
+            t.rows_per_wave = r;
+            t.adj_tb_steps = 1;
+            cand.push_back(t);
+        }
+    } else {
+        cand.push_back(best_tune);  // adjoint marches with the forward's rows
+    }
+#define BHFWI_TBC(TT, RR, WW)       \
+    {                               \
+        bhfwi_tune t = best_tune;   \
+        t.adj_tb_steps = TT;        \
+        t.adj_tb_rows = RR;         \
+        t.adj_tb_waves = WW;        \
+        cand.push_back(t);          \
+    }
+    BHFWI_ADJ_SHAPES(BHFWI_TBC)
+#undef BHFWI_TBC
+    float best_a = 1e30f;
+    bhfwi_tune best_adj = best_tune;
+    for (const bhfwi_tune& t : cand) {
+        if (int rc = install(t)) return rc;
+        float ms;
+        if (int rc = time_it(run_adj, &ms)) return rc;
+        if (ms < best_a) {
+            best_a = ms;
+            best_adj = t;
+        }
+    }
+    best_tune = best_adj;
+    const float best_t = best_f + best_a;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     clear_graphs(c);
@@ -1016,19 +1139,7 @@ int bhfwi_adjoint_model(bhfwi_ctx* c, void* stream, const float* lam, const floa
                                      sizeof(float) * c->fst_len, hipMemcpyDeviceToDevice, s);
             int parity = 0;
             fwd_range(c, s, n0, n1, lam, mu, rho, wavelet, fbc, &parity, nullptr, hist, n0);
-            if (c->tune.tb_steps >= 2) {
-                for (int n = n1 - 1; n >= n0;) {
-                    const int nb = std::min(c->tune.tb_steps, n - n0 + 1);
-                    adj_tb_launch(c, s, n, nb, lam, mu, rho, resid, ab[m & 1], ab[(m + 1) & 1],
-                                  hist + (int64_t)(n - n0) * hslot, acc);
-                    ++m;
-                    n -= nb;
-                }
-            } else {
-                for (int n = n1 - 1; n >= n0; --n, ++m)
-                    adj_launch(c, s, n, lam, mu, rho, resid, ab[m & 1], ab[(m + 1) & 1],
-                               hist + (int64_t)(n - n0) * hslot, acc);
-            }
+            adj_range(c, s, n0, n1, lam, mu, rho, resid, ab, &m, hist, acc);
         }
     };
     return run_sequence(c, st,

@@ -48,19 +48,23 @@ def survey(w, ckpt=250, tune=None):
     return sv
 
 
-def T(rows=4, wpb=4, graph=1, tb=0, tbr=16, tbw=4, tmap=1):
+def T(rows=4, wpb=4, graph=1, tb=0, tbr=16, tbw=4, tmap=1, atb=0, atbr=16, atbw=8):
     return dict(rows_per_wave=rows, waves_per_block=wpb, use_graph=graph, tb_steps=tb,
-                tb_rows=tbr, tb_waves=tbw, tile_map=tmap)
+                tb_rows=tbr, tb_waves=tbw, tile_map=tmap, adj_tb_steps=atb, adj_tb_rows=atbr,
+                adj_tb_waves=atbw)
 
 
 FWD_TUNES = [T(1, 1, 0), T(2, 4, 1), T(3, 2, 1), T(4, 4, 0), T(16, 4, 1), T(64, 8, 0),
              T(tb=2), T(tb=3, graph=0), T(tb=4), T(tb=4, tbw=8), T(tb=6, tbr=24, tbw=8, graph=0),
              T(tb=8, tbr=32, tbw=8), T(tb=3, tbr=24, tbw=8), T(tb=4, tmap=0), T(tb=4, tbw=16),
-             T(tb=3, tbw=16, graph=0), T(tb=6, tbr=32, tbw=16)]
+             T(tb=3, tbw=16, graph=0), T(tb=6, tbr=32, tbw=16), T(tb=6, tbr=48, tbw=16, atb=1),
+             T(tb=8, tbr=48, tbw=16, graph=0, atb=1)]
 GRAD_TUNES = [T(1, 1, 1), T(2, 4, 0), T(4, 4, 1), T(5, 4, 1), T(64, 8, 0), T(tb=4),
               T(tb=3, graph=0), T(tb=4, tbw=8), T(tb=6, tbr=24, tbw=8), T(tb=8, tbr=32, tbw=8),
               T(tb=4, tbw=8, tmap=0), T(tb=4, tbw=16), T(tb=2, tbw=16, graph=0),
-              T(tb=8, tbr=32, tbw=16)]
+              T(tb=8, tbr=32, tbw=16), T(tb=6, tbr=48, tbw=16, atb=6, atbr=32, atbw=16),
+              T(tb=4, tbr=48, tbw=16, atb=3, atbr=16, atbw=8, graph=0),
+              T(tb=6, tbr=32, tbw=16, atb=1, rows=2), T(tb=0, rows=2, atb=4, atbr=16, atbw=16)]
 
 
 def oracle_traces(w, s=0, which="start"):
@@ -179,7 +183,7 @@ def test_checkpoint_interval_is_exact(tune):
         outs.append([t.cpu().numpy() for t in sv.gradient(mu, acc)])
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
-            if tune["tb_steps"] >= 2:
+            if tune["tb_steps"] >= 2 or tune["adj_tb_steps"] >= 2:
                 assert rel_l2(b, a) <= 1e-6, rel_l2(b, a)
             else:
                 assert np.array_equal(a, b)
