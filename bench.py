@@ -47,7 +47,7 @@ PMC_SOURCES = ("paper_2005_00281_amd/csrc/bhfwi_tb_adj.hip",
                "paper_2005_00281_amd/csrc/bhfwi_internal.h")
 PMC_TRAFFIC = {
     # (kernel, tile_map, workload, sources sha256[:16]): (FETCH KiB, WRITE KiB)
-    ("k_adj_tb<4, 16, 8>", 1, "c2", "c81676813632d2fe"): (37680.81, 31162.98),
+    ("k_adj_tb<6, 32, 16>", 1, "c2", "0358d0a223858015"): (48355.94, 30985.60),
 }
 
 
