@@ -170,6 +170,13 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=0.0,
                     help="HBM budget for the planner (0: 80%% of the device)")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--progress", action="store_true",
+                    help="synchronise and log after every shot group (long workloads)")
+    ap.add_argument("--kt-groups", type=int, default=0,
+                    help="shot groups in the per-kernel timing pass (0: all)")
+    ap.add_argument("--line-search", type=int, default=-1,
+                    help="1: parabolic line search each iteration (one extra forward); "
+                         "-1: as the workload specifies (the 128-shot workload uses it)")
     ap.add_argument("--sweep", action="store_true",
                     help="time one gradient evaluation per temporally blocked shape "
                          "(stderr only) before the benchmark")
@@ -208,12 +215,23 @@ def main():
         wavs.append(sv.pack_wavelets([w.shots[s].wavelet for s in g]))
     lam_t, mu_t = P.moduli(f32(w.vp_true), f32(w.vs_true), rho)
     observed = []
-    for sv, wav in zip(surveys, wavs):
+    for g, (sv, wav) in enumerate(zip(surveys, wavs)):
         observed.append(sv.fwd_model(lam_t, mu_t, rho, wav).clone())
         sv.free_workspaces()
+        if args.progress:
+            torch.cuda.synchronize()
+            log("observed data: group %d of %d" % (g + 1, len(surveys)))
     del lam_t, mu_t
     mask = torch.as_tensor(w.mask, device=dev)
-    inv = Inversion(surveys, f32(w.vp_start), f32(w.vs_start), rho, wavs, observed, mask)
+    line_search = (bool(w.meta.get("line_search", False)) if args.line_search < 0
+                   else bool(args.line_search))
+    inv = Inversion(surveys, f32(w.vp_start), f32(w.vs_start), rho, wavs, observed, mask,
+                    line_search=line_search)
+    if args.progress:
+        def _progress(stage, g):
+            torch.cuda.synchronize()
+            log("%s: group %d of %d done" % (stage, g + 1, len(surveys)))
+        inv.after_group = _progress
     if args.tb >= 0 or args.adj_tb >= 0 or args.rows or args.no_autotune:
         for sv in surveys:
             sv.set_tune(rows_per_wave=args.rows or None,
@@ -285,25 +303,28 @@ def main():
     value = 2 * z.cell_steps / (ms * 1e-3) / 1e9
     log("ms/iteration %.2f, J %s" % (ms, [round(float(j), 6) for j in Js]))
 
-    # per-kernel durations: one more (untimed) iteration with every time-step
-    # kernel bracketed by HIP events on the stream it runs on
-    for x in surveys:
+    # per-kernel durations: one more (untimed) gradient evaluation, of the first
+    # --kt-groups shot groups (all by default), with every time-step kernel
+    # bracketed by HIP events on the stream it runs on
+    timed = surveys[:args.kt_groups] if args.kt_groups > 0 else surveys
+    for x in timed:
         x.set_tune(use_graph=0, time_kernels=1)
         x.kernel_times(reset=True)
-    inv.iterate()
+    all_surveys, inv.surveys = inv.surveys, timed
+    inv.gradient()
+    inv.surveys = all_surveys
     kt = {"fwd": [0.0, 0], "rec": [0.0, 0], "adj": [0.0, 0]}
-    for x in surveys:
+    for x in timed:
         for k, (ms_, n_) in x.kernel_times(reset=True).items():
             kt[k][0] += ms_
             kt[k][1] += n_
         x.set_tune(use_graph=tune["use_graph"], time_kernels=0)
-    # the adjoint launches of different groups cover different shots
-    adj_launch_sets = len(surveys)
+    cs_timed = sum(x.sizes.cell_steps for x in timed)
     adj_ms, adj_n = kt["adj"]
-    # every adjoint step of the iteration ran once: nt cell-steps of every shot
-    steps_per_launch = adj_launch_sets * z.nt_max / max(1, adj_n)
+    # every adjoint step of the timed groups ran once: nt cell-steps of every shot
+    steps_per_launch = sum(x.sizes.nt_max for x in timed) / max(1, adj_n)
     adj_avg = adj_ms / max(1, adj_n)
-    adj_bytes = ADJ_BYTES_PER_CELL_STEP * z.cell_steps / max(1, adj_n)  # per launch
+    adj_bytes = ADJ_BYTES_PER_CELL_STEP * cs_timed / max(1, adj_n)  # per launch
     achieved = adj_bytes / (adj_avg * 1e-3) / 1e9
     ashape = adj_shape(tune)
     kname = ("k_adj_tb<%d, %d, %d>" % ashape if ashape[0] >= 2
@@ -327,9 +348,11 @@ def main():
     for k, (kms, kn) in kt.items():
         if kn:
             kernels[k] = {"avg_us": round(kms * 1e3 / kn, 3), "launches": kn,
-                          "achieved_GBs": round(per_cs[k] * z.cell_steps / (kms * 1e-3) / 1e9, 1)}
-    # iteration-level roofline: 220 B per cell-step over one gradient evaluation
-    it_frac = (220 * z.cell_steps / (ms * 1e-3)) / (HBM_PEAK_GBS * 1e9)
+                          "achieved_GBs": round(per_cs[k] * cs_timed / (kms * 1e-3) / 1e9, 1)}
+    # iteration-level roofline: 220 B per cell-step for one gradient evaluation
+    # (forward, recompute, adjoint), plus 60 B for the line search's forward
+    it_bytes = 220 + (FWD_BYTES_PER_CELL_STEP if line_search else 0)
+    it_frac = (it_bytes * z.cell_steps / (ms * 1e-3)) / (HBM_PEAK_GBS * 1e9)
 
     # plain form: one shot per survey, one step per launch, no graph, same
     # checkpoint interval; per-shot gradient-evaluation times, extrapolated
@@ -384,9 +407,11 @@ def main():
                        w.shots[0].dt, w.shots[0].f0, len(w.shots[0].rec_k),
                        pl.ckpt_every)),
                    "cell_steps_per_iteration": int(z.cell_steps),
+                   "line_search": line_search,
                    "tune": tune},
         "roofline": roofline,
-        "iteration_hbm_frac_at_220B": round(it_frac, 4),
+        "iteration_hbm_frac": round(it_frac, 4),
+        "iteration_bytes_per_cell_step": it_bytes,
         "copy_GBs": round(copy_bw, 1),
         "shots_iters_per_s": round(len(w.shots) / (ms * 1e-3), 4),
         "plain": plain,

@@ -55,6 +55,7 @@ class Inversion:
         self.illum = torch.empty_like(vp)
         self.J = torch.zeros((), dtype=torch.float64, device=dev)
         self.line_search = bool(line_search)
+        self.after_group = None  # optional callback(stage, group) after each group's work
         if self.line_search:
             self.J1 = torch.zeros((), dtype=torch.float64, device=dev)
             self.gpg = torch.zeros((), dtype=torch.float64, device=dev)
@@ -75,6 +76,8 @@ class Inversion:
                              ckpt=ckpt, acc=self.acc)
             sv.gradient(self.mu, self.acc, out=(self.g_lam, self.g_mu, self.illum),
                         accumulate=g > 0)
+            if self.after_group:
+                self.after_group("gradient", g)
         return self.J
 
     def iterate(self):
@@ -103,6 +106,8 @@ class Inversion:
                           traces=self.traces[g])
             svg.misfit(self.traces[g], self.observed[g], resid=self.resid[g], J=self.J1,
                        accumulate=g > 0)
+            if self.after_group:
+                self.after_group("line search", g)
         alpha = sv.line_search(self.J, self.J1, self.gpg, alpha1)
         sv.update(self.lam, self.mu, self.rho, self.g_lam, self.g_mu, self.mask, self.eta,
                   bounds=self.bounds, alpha_in=alpha)

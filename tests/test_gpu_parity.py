@@ -448,3 +448,41 @@ def test_status_reports_non_finite_traces():
         sv.status()
     assert e.value.code == -5
     sv.status()  # cleared
+
+
+def test_velocity_parameterisation_autograd():
+    """Moduli (Eq. 3-4 with its chain rule in the library) chained into
+    BoreholeFWI: dJ/dVp and dJ/dVs match the oracle's gradient pushed through
+    the oracle's chain rule (<= 1e-3), and the chain-rule kernel alone matches
+    it elementwise."""
+    import paper_2005_00281_amd as P
+    w = workloads.tiny(nr=30, nz=100, p=6, nt=300)
+    sh = w.shots[0]
+    _say("velocity parameterisation", sh.NR, sh.NZ)
+    lam_o, mu_o, rho_o = oracle_models(w, 0, "start")
+    lt, mt, _ = oracle_models(w, 0, "true")
+    d_obs = oracle.forward(geom(sh), lt, mt, rho_o, sh.wavelet)
+    _, r_o = oracle.misfit(oracle.forward(geom(sh), lam_o, mu_o, rho_o, sh.wavelet), d_obs)
+    gl_o, gm_o, _ = oracle.gradient(geom(sh), lam_o, mu_o, rho_o, sh.wavelet, r_o, seg=64)
+    gvp_o, gvs_o = oracle.moduli_grad(w.vp_start, w.vs_start, w.rho, gl_o, gm_o)
+
+    sv = survey(w, ckpt=64)
+    rho = f32(w.rho)
+    wav = sv.pack_wavelets([sh.wavelet])
+    obs = f32(d_obs.ravel())
+    vp = f32(w.vp_start).requires_grad_(True)
+    vs = f32(w.vs_start).requires_grad_(True)
+    lam, mu = P.Moduli.apply(vp, vs, rho)
+    tr = P.BoreholeFWI.apply(lam, mu, sv, rho, wav)
+    loss = 0.5 * ((tr - obs).double() ** 2).sum()
+    loss.backward()
+    assert rel_l2(vp.grad.cpu().numpy(), gvp_o) <= 1e-3
+    assert rel_l2(vs.grad.cpu().numpy(), gvs_o) <= 1e-3
+    # the chain-rule kernel on its own, same FP32 inputs
+    rng = np.random.default_rng(5)
+    gl, gm = rng.standard_normal(w.vp_start.shape), rng.standard_normal(w.vp_start.shape)
+    a, b = P.moduli_grad(f32(w.vp_start), f32(w.vs_start), rho, f32(gl), f32(gm))
+    ao, bo = oracle.moduli_grad(w.vp_start.astype(np.float32), w.vs_start.astype(np.float32),
+                                w.rho.astype(np.float32), gl.astype(np.float32),
+                                gm.astype(np.float32))
+    assert rel_l2(a.cpu().numpy(), ao) <= 1e-6 and rel_l2(b.cpu().numpy(), bo) <= 1e-6

@@ -324,8 +324,10 @@ def batched_uneven(seed=SEED, name="c4", nshot=96, h=2.5e-3, p=20, nrec=13,
 
 def large_layered(seed=SEED, nshot=128, **kw) -> Workload:
     """128 shots of 512 x 16384 cells, 16000 steps, 8 kHz, layered + radial damage."""
-    return batched_layered(seed=seed, name="c5", nshot=nshot, nr=512, nz=16384, nt=16000,
-                           f0=8e3, iters=10, cfg_id=5, **kw)
+    wl = batched_layered(seed=seed, name="c5", nshot=nshot, nr=512, nz=16384, nt=16000,
+                         f0=8e3, iters=10, cfg_id=5, **kw)
+    wl.meta["line_search"] = True
+    return wl
 
 
 # --------------------------------------------------------------------------
