@@ -57,7 +57,8 @@ TB_SHAPES = [(2, 16, 4), (3, 16, 4), (4, 16, 4), (2, 16, 8), (3, 16, 8), (4, 16,
              (2, 24, 8), (3, 24, 8), (4, 24, 8), (6, 24, 8), (4, 32, 8), (6, 32, 8),
              (8, 32, 8), (2, 16, 16), (3, 16, 16), (4, 16, 16), (4, 32, 16), (6, 32, 16),
              (8, 32, 16)]
-FWD_ONLY_SHAPES = [(4, 48, 16), (6, 48, 16), (8, 48, 16)]
+FWD_ONLY_SHAPES = [(4, 48, 16), (6, 48, 16), (8, 48, 16), (4, 64, 16), (8, 64, 16)]
+ADJ_ONLY_SHAPES = [(4, 48, 16), (6, 48, 16), (8, 48, 16)]
 
 
 def adj_shape(tune):
@@ -272,7 +273,7 @@ def main():
                     T, R, W_, tmap, ms))
         for x in surveys:
             x.set_tune(**keep)
-        for (T, R, W_) in TB_SHAPES:
+        for (T, R, W_) in TB_SHAPES + ADJ_ONLY_SHAPES:
             ms = timed(adj_tb_steps=T, adj_tb_rows=R, adj_tb_waves=W_)
             log("sweep adj T %d rows %d waves %d: %.2f ms per gradient" % (T, R, W_, ms))
         for x in surveys:
@@ -326,8 +327,12 @@ def main():
     adj_avg = adj_ms / max(1, adj_n)
     adj_bytes = ADJ_BYTES_PER_CELL_STEP * cs_timed / max(1, adj_n)  # per launch
     achieved = adj_bytes / (adj_avg * 1e-3) / 1e9
-    ashape = adj_shape(tune)
-    kname = ("k_adj_tb<%d, %d, %d>" % ashape if ashape[0] >= 2
+    # the adjoint block: interior tiles in the PML-free kernel, then the PML
+    # (sub-)tiles in the kernel that carries the PML memories
+    kshapes = sv.kernel_shapes()
+    kname = ("k_adj_tb<%d, %d, %d, 0> + k_adj_tb<%d, %d, %d, 1>" % (kshapes["adj"] +
+                                                                    kshapes["adj_pml"])
+             if kshapes["adj"][0] >= 2
              else "k_adj_step<%d>" % (tune["rows_per_wave"] if tune["rows_per_wave"] <= 4 else 0))
     pmc = PMC_TRAFFIC.get((kname, tune.get("tile_map", 1), args.workload, kernel_sources_sha()))
     traffic = (None if pmc is None
@@ -355,8 +360,9 @@ def main():
     it_frac = (it_bytes * z.cell_steps / (ms * 1e-3)) / (HBM_PEAK_GBS * 1e9)
 
     # plain form: one shot per survey, one step per launch, no graph, same
-    # checkpoint interval; per-shot gradient-evaluation times, extrapolated
-    # over all shots by cell-steps
+    # checkpoint interval and the same iteration (line search included when
+    # the batched run has it); per-shot iteration times, extrapolated over all
+    # shots by cell-steps
     plain = None
     if args.plain_shots > 0:
         del inv
@@ -370,11 +376,12 @@ def main():
             wav1 = sv1.pack_wavelets([sh.wavelet])
             off = sum(len(w.shots[q].rec_k) * w.shots[q].nt for q in pl.groups[g_] if q < s_)
             obs1 = observed[g_][off: off + len(sh.rec_k) * sh.nt].clone()
-            inv1 = Inversion(sv1, f32(w.vp_start), f32(w.vs_start), rho, wav1, obs1, mask)
-            inv1.gradient()
+            inv1 = Inversion(sv1, f32(w.vp_start), f32(w.vs_start), rho, wav1, obs1, mask,
+                             line_search=line_search)
+            inv1.iterate()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            inv1.gradient()
+            inv1.iterate()
             torch.cuda.synchronize()
             per_cs.append((time.perf_counter() - t0) / (sh.cells * sh.nt))
             del inv1, sv1
@@ -385,7 +392,8 @@ def main():
                  "ms_per_iteration": round(t_plain * 1e3, 1),
                  "measured_shots": len(per_cs), "extrapolated": len(per_cs) < len(w.shots),
                  "form": "one shot per launch sequence, one step per launch (wave march, "
-                         "2 rows per wave), no HIP graph, same checkpoint interval"}
+                         "2 rows per wave), no HIP graph, same checkpoint interval, same "
+                         "iteration"}
 
     copy_bw = copy_bandwidth()
     log("device copy %.1f GB/s" % copy_bw)
@@ -408,6 +416,7 @@ def main():
                        pl.ckpt_every)),
                    "cell_steps_per_iteration": int(z.cell_steps),
                    "line_search": line_search,
+                   "kernel_shapes": kshapes,
                    "tune": tune},
         "roofline": roofline,
         "iteration_hbm_frac": round(it_frac, 4),

@@ -102,7 +102,12 @@ typedef struct {
                                  (tb_steps, tb_rows, tb_waves): (2|3|4, 16, 4),
                                  (2|3|4, 16, 8), (2|3|4|6, 24, 8),
                                  (4|6|8, 32, 8), (2|3|4, 16, 16),
-                                 (4|6|8, 32, 16), (4|6|8, 48, 16) */
+                                 (4|6|8, 32, 16), (4|6|8, 48, 16), (4|8, 64, 16).
+                                 Tiles that touch a PML layer run a kernel
+                                 that carries the PML memories; for the 64-row
+                                 shapes they are cut into sub-tiles of a
+                                 smaller shape with the same T
+                                 (bhfwi_kernel_shapes reports it) */
     int32_t tile_map;         /* order of the tiles of a temporally blocked launch:
                                  0: axial tile fastest, workgroups in table order;
                                  1: radial tile fastest, and each of the 8 XCDs of
@@ -111,8 +116,9 @@ typedef struct {
     int32_t adj_tb_steps;     /* adjoint: 0 = the forward's shape (tb_*), 1 = one
                                  step per launch (wave march), >= 2 = its own
                                  shape (adj_tb_steps, adj_tb_rows, adj_tb_waves)
-                                 from the supported forward shapes except
-                                 (4|6|8, 48, 16) */
+                                 from the supported forward shapes except the
+                                 64-row ones; PML tiles of the 48-row shapes
+                                 run as sub-tiles of a smaller shape */
     int32_t adj_tb_rows;
     int32_t adj_tb_waves;
 } bhfwi_tune;
@@ -193,6 +199,12 @@ int bhfwi_plan_bytes(const bhfwi_shot *shots, int32_t nshot, int32_t ckpt_every,
 int bhfwi_plan(const bhfwi_shot *shots, int32_t nshot, int64_t budget_bytes,
                int32_t ckpt_every, int32_t max_groups, int32_t *group_of, int32_t *ckpt_out,
                bhfwi_plan_info *info);
+
+/* The temporally blocked kernel shapes the current tune runs, 12 int32 to
+ * out (host): (T, rows, waves) of the forward kernel on tiles clear of the
+ * PML, of the forward kernel on the PML sub-tiles, and the same two for the
+ * adjoint; T = 0 where that part runs one step per launch. */
+int bhfwi_kernel_shapes(const bhfwi_ctx *ctx, int32_t *out);
 
 /* Read (and with reset != 0 clear) the sums of bhfwi_kernel_times_t. */
 int bhfwi_kernel_times(bhfwi_ctx *ctx, bhfwi_kernel_times_t *out, int32_t reset);

@@ -78,7 +78,7 @@ EXPORTS = ["bhfwi_create", "bhfwi_destroy", "bhfwi_last_error", "bhfwi_sizes",
            "bhfwi_moduli", "bhfwi_moduli_grad", "bhfwi_velocities",
            "bhfwi_fwd_model", "bhfwi_misfit", "bhfwi_adjoint_model", "bhfwi_gradient",
            "bhfwi_precondition", "bhfwi_status", "bhfwi_line_search", "bhfwi_update", "bhfwi_plan_bytes",
-           "bhfwi_plan"]
+           "bhfwi_plan", "bhfwi_kernel_shapes"]
 
 _lib = None
 
@@ -114,6 +114,7 @@ def load(path: str = LIB_PATH):
     L.bhfwi_precondition.argtypes = [P, V, I64, P, P, F, P, P, P]
     L.bhfwi_line_search.argtypes = [P, V, P, P, P, P, P]
     L.bhfwi_status.argtypes = [P, V]
+    L.bhfwi_kernel_shapes.argtypes = [P, C.POINTER(C.c_int32)]
     L.bhfwi_plan_bytes.argtypes = [C.POINTER(Shot), I32, I32, C.POINTER(PlanBytes)]
     L.bhfwi_plan.argtypes = [C.POINTER(Shot), I32, I64, I32, I32, C.POINTER(C.c_int32),
                              C.POINTER(C.c_int32), C.POINTER(PlanInfo)]
@@ -265,6 +266,15 @@ class Survey:
         t = Tune(**{n: int(getattr(cur, n) if kw.get(n) is None else kw[n]) for n in names})
         _check(load().bhfwi_set_tune(self._h, C.byref(t)), self._h)
         _check(load().bhfwi_sizes(self._h, C.byref(self.sizes)), self._h)
+
+    def kernel_shapes(self):
+        """{'fwd', 'fwd_pml', 'adj', 'adj_pml'}: (T, rows, waves) of the
+        temporally blocked kernels the current tune runs (T = 0: one step per
+        launch)."""
+        out = (C.c_int32 * 12)()
+        _check(load().bhfwi_kernel_shapes(self._h, out), self._h)
+        names = ("fwd", "fwd_pml", "adj", "adj_pml")
+        return {n: tuple(out[3 * q: 3 * q + 3]) for q, n in enumerate(names)}
 
     def get_tune(self):
         t = Tune()

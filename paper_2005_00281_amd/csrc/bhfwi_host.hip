@@ -87,18 +87,22 @@ thread_local std::string g_create_err;  // message of the last failed bhfwi_crea
 
 }  // namespace
 
-// Tiles (shot, k0, i0, i1) of one temporally blocked shape, ordered by the
-// nt of their shot (non-increasing), with a device copy.
-struct TileSet {
-    std::vector<int4> t;
-    std::vector<int> nt;
-    int4* d = nullptr;
-};
-
 // A temporally blocked kernel shape: T steps per launch, TRE tile rows
 // including the halo, W waves per workgroup; T = 0 means one step per launch.
 struct Shape {
     int T, TRE, W;
+};
+
+// Tiles (shot, k0, i0, i1) of one temporally blocked shape in two lists:
+// [0] tiles clear of every PML layer, run by the PML-free kernel of the shape;
+// [1] the tiles that touch a PML layer, cut into sub-tiles of shape `pml`
+// (same T, fewer rows) and run by the kernel that carries the PML memories.
+// Each list is ordered by the nt of its shot (non-increasing).
+struct TileSet {
+    std::vector<int4> t[2];
+    std::vector<int> nt[2];
+    int4* d[2] = {nullptr, nullptr};
+    Shape pml{0, 0, 0};
 };
 
 struct bhfwi_ctx {
@@ -178,6 +182,8 @@ void pml_coef(double x, double d0, double f0, double dt, float* a, float* b)
     *a = (float)(d * (bb - 1.0) / (d + al));
 }
 
+Shape pml_shape(Shape sh, bool adj);
+
 Shape fwd_shape(const bhfwi_ctx* c)
 {
     const bhfwi_tune& t = c->tune;
@@ -194,40 +200,60 @@ Shape adj_shape(const bhfwi_ctx* c)
     return fwd_shape(c);
 }
 
-void build_tiles(const bhfwi_ctx* c, const std::vector<int>& order, Shape sh, TileSet* ts)
+// Whether a tile of shape sh at (i0, k0) -- with its halo -- reaches a PML
+// layer: the test the kernels apply to pick their PML loop.
+bool touches_pml(const ShotDev& S, Shape sh, int i0, int k0)
 {
-    ts->t.clear();
-    ts->nt.clear();
+    const int ihi = i0 - sh.T + sh.TRE - 1, klo = k0 - sh.T, khi = k0 - sh.T + 63;
+    return ihi >= S.nr || klo < S.pz || khi >= S.NZ - S.pz;
+}
+
+void build_tiles(const bhfwi_ctx* c, const std::vector<int>& order, Shape sh, Shape pml,
+                 TileSet* ts)
+{
+    for (int q = 0; q < 2; ++q) {
+        ts->t[q].clear();
+        ts->nt[q].clear();
+    }
+    ts->pml = pml;
     if (sh.T < 2) return;
-    const int TR = sh.TRE - 2 * sh.T, TZ = 64 - 2 * sh.T;
+    const int TR = sh.TRE - 2 * sh.T, TZ = 64 - 2 * sh.T, TRp = pml.TRE - 2 * pml.T;
+    auto add = [&](int s, int k0, int i0) {
+        const ShotDev& S = c->sd[s];
+        if (!touches_pml(S, sh, i0, k0)) {
+            ts->t[0].push_back(make_int4(s, k0, i0, std::min(i0 + TR, S.NR)));
+            ts->nt[0].push_back(S.nt);
+            return;
+        }
+        for (int i = i0; i < std::min(i0 + TR, S.NR); i += TRp) {
+            ts->t[1].push_back(make_int4(s, k0, i, std::min(i + TRp, S.NR)));
+            ts->nt[1].push_back(S.nt);
+        }
+    };
     for (int s : order) {
         const ShotDev& S = c->sd[s];
         if (c->tune.tile_map == 1) {
             for (int k0 = 0; k0 < S.NZ; k0 += TZ)
-                for (int i0 = 0; i0 < S.NR; i0 += TR) {
-                    ts->t.push_back(make_int4(s, k0, i0, std::min(i0 + TR, S.NR)));
-                    ts->nt.push_back(S.nt);
-                }
+                for (int i0 = 0; i0 < S.NR; i0 += TR) add(s, k0, i0);
         } else {
             for (int i0 = 0; i0 < S.NR; i0 += TR)
-                for (int k0 = 0; k0 < S.NZ; k0 += TZ) {
-                    ts->t.push_back(make_int4(s, k0, i0, std::min(i0 + TR, S.NR)));
-                    ts->nt.push_back(S.nt);
-                }
+                for (int k0 = 0; k0 < S.NZ; k0 += TZ) add(s, k0, i0);
         }
     }
 }
 
 int upload_tiles(bhfwi_ctx* c, TileSet* ts)
 {
-    if (ts->d) {
-        HIPOK(c, hipFree(ts->d));
-        ts->d = nullptr;
-    }
-    if (!ts->t.empty()) {
-        HIPOK(c, hipMalloc(&ts->d, sizeof(int4) * ts->t.size()));
-        HIPOK(c, hipMemcpy(ts->d, ts->t.data(), sizeof(int4) * ts->t.size(),
-                           hipMemcpyHostToDevice));
+    for (int q = 0; q < 2; ++q) {
+        if (ts->d[q]) {
+            HIPOK(c, hipFree(ts->d[q]));
+            ts->d[q] = nullptr;
+        }
+        if (!ts->t[q].empty()) {
+            HIPOK(c, hipMalloc(&ts->d[q], sizeof(int4) * ts->t[q].size()));
+            HIPOK(c, hipMemcpy(ts->d[q], ts->t[q].data(), sizeof(int4) * ts->t[q].size(),
+                               hipMemcpyHostToDevice));
+        }
     }
     return BHFWI_OK;
 }
@@ -250,8 +276,9 @@ void rebuild_work(bhfwi_ctx* c)
                 c->work_nt.push_back(S.nt);
             }
     }
-    build_tiles(c, order, fwd_shape(c), &c->ftiles);
-    build_tiles(c, order, adj_shape(c), &c->atiles);
+    const Shape fs = fwd_shape(c), as = adj_shape(c);
+    build_tiles(c, order, fs, pml_shape(fs, false), &c->ftiles);
+    build_tiles(c, order, as, pml_shape(as, true), &c->atiles);
 }
 
 int upload_work(bhfwi_ctx* c)
@@ -285,10 +312,11 @@ int active_items(const bhfwi_ctx* c, int n)
     return (int)(it - c->work_nt.begin());
 }
 
-int active_tiles(const TileSet& ts, int n)
+int active_tiles(const TileSet& ts, int q, int n)
 {
-    auto it = std::partition_point(ts.nt.begin(), ts.nt.end(), [n](int nt) { return nt > n; });
-    return (int)(it - ts.nt.begin());
+    auto it = std::partition_point(ts.nt[q].begin(), ts.nt[q].end(),
+                                   [n](int nt) { return nt > n; });
+    return (int)(it - ts.nt[q].begin());
 }
 
 int check_ctx(bhfwi_ctx* c)
@@ -368,75 +396,134 @@ void adj_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const flo
                    resid, c->d_pml_r, c->d_pml_z, in, out, hist, acc, (long long)c->cells);
 }
 
-// Supported temporally blocked shapes: (steps T, tile rows incl. halo, waves).
-// The adjoint holds more per-cell state than the forward, so its tiles stop
-// at two rows per thread.
-#define BHFWI_ADJ_SHAPES(X) \
+// Supported temporally blocked shapes: (steps T, tile rows incl. halo,
+// waves).  *_PML lists the shapes whose kernel carries the PML memories (all
+// tiles may use them); *_INT adds shapes compiled only without them, for
+// tiles clear of the PML: with fewer live values per cell they afford more
+// rows per thread.  A tile of an interior-only shape that touches a PML layer
+// is cut into sub-tiles of a *_PML shape with the same T (pml_shape).
+#define BHFWI_ADJ_PML(X) \
     X(2, 16, 4) X(3, 16, 4) X(4, 16, 4) X(2, 16, 8) X(3, 16, 8) X(4, 16, 8) X(2, 24, 8) \
     X(3, 24, 8) X(4, 24, 8) X(6, 24, 8) X(4, 32, 8) X(6, 32, 8) X(8, 32, 8) X(2, 16, 16) \
     X(3, 16, 16) X(4, 16, 16) X(4, 32, 16) X(6, 32, 16) X(8, 32, 16)
-#define BHFWI_FWD_SHAPES(X) BHFWI_ADJ_SHAPES(X) X(4, 48, 16) X(6, 48, 16) X(8, 48, 16)
+#define BHFWI_ADJ_INT(X) BHFWI_ADJ_PML(X) X(4, 48, 16) X(6, 48, 16) X(8, 48, 16)
+#define BHFWI_FWD_PML(X) BHFWI_ADJ_PML(X) X(4, 48, 16) X(6, 48, 16) X(8, 48, 16)
+#define BHFWI_FWD_INT(X) BHFWI_FWD_PML(X) X(4, 64, 16) X(8, 64, 16)
+
+#define BHFWI_TBS(TT, RR, WW) \
+    if (sh.T == TT && sh.TRE == RR && sh.W == WW) return true;
+bool fwd_pml_ok(Shape sh) { BHFWI_FWD_PML(BHFWI_TBS) return false; }
+bool fwd_int_ok(Shape sh) { BHFWI_FWD_INT(BHFWI_TBS) return false; }
+bool adj_pml_ok(Shape sh) { BHFWI_ADJ_PML(BHFWI_TBS) return false; }
+bool adj_int_ok(Shape sh) { BHFWI_ADJ_INT(BHFWI_TBS) return false; }
+#undef BHFWI_TBS
+
+// Shape for the PML tiles of interior shape sh: sh itself when its kernel can
+// carry the PML, else the PML-capable shape with the same T whose owned rows
+// divide sh's (most rows, then most waves); T = 0 if there is none.
+Shape pml_shape(Shape sh, bool adj)
+{
+    if (sh.T < 2) return Shape{0, 0, 0};
+    if (adj ? adj_pml_ok(sh) : fwd_pml_ok(sh)) return sh;
+    Shape best{0, 0, 0};
+    const int TR = sh.TRE - 2 * sh.T;
+    auto consider = [&](int T, int R, int W) {
+        const int TRp = R - 2 * T;
+        if (T != sh.T || TRp <= 0 || TR % TRp) return;
+        if (R > best.TRE || (R == best.TRE && W > best.W)) best = Shape{T, R, W};
+    };
+#define BHFWI_TBP(TT, RR, WW) consider(TT, RR, WW);
+    if (adj) {
+        BHFWI_ADJ_PML(BHFWI_TBP)
+    } else {
+        BHFWI_FWD_PML(BHFWI_TBP)
+    }
+#undef BHFWI_TBP
+    return best;
+}
+
+bool fwd_supported(int T, int TRE, int W)
+{
+    const Shape sh{T, TRE, W};
+    return fwd_int_ok(sh) && pml_shape(sh, false).T >= 2;
+}
+bool adj_supported(int T, int TRE, int W)
+{
+    const Shape sh{T, TRE, W};
+    return adj_int_ok(sh) && pml_shape(sh, true).T >= 2;
+}
 
 #define BHFWI_TB(TT, RR, WW)                                                                 \
     if (T == TT && TRE == RR && W == WW) {                                                   \
-        hipLaunchKernelGGL((bhfwi::k_fwd_tb<TT, RR, WW>), dim3(nact), dim3(64 * WW), 0, st,  \
-                           c->d_shots, c->ftiles.d, nact, c->tune.tile_map, n0, nsteps, lam, \
-                           mu, rho, wav, c->d_rec, c->d_pml_r, c->d_pml_z, in, out, traces,  \
-                           hist, (long long)(2 * c->cells), (long long)c->cells);            \
-        return;                                                                              \
+        hipLaunchKernelGGL((bhfwi::k_fwd_tb<TT, RR, WW, PMV>), dim3(nact), dim3(64 * WW), 0, \
+                           st, c->d_shots, c->ftiles.d[q], nact, c->tune.tile_map, n0,       \
+                           nsteps, lam, mu, rho, wav, c->d_rec, c->d_pml_r, c->d_pml_z, in,  \
+                           out, traces, hist, (long long)(2 * c->cells),                    \
+                           (long long)c->cells);                                             \
+        continue;                                                                            \
     }
 
-// nsteps (<= the forward shape's T) forward steps from step n0 in LDS-tiled kernels.
+// nsteps (<= the forward shape's T) forward steps from step n0 in LDS-tiled
+// kernels: the interior tiles, then the PML sub-tiles.
 void fwd_tb_launch(bhfwi_ctx* c, hipStream_t st, int n0, int nsteps, const float* lam,
                    const float* mu, const float* rho, const float* wav, const float* in,
                    float* out, float* traces, float* hist)
 {
-    const int nact = active_tiles(c->ftiles, n0);
-    if (nact <= 0) return;
-    const Shape sh = fwd_shape(c);
-    const int T = sh.T, TRE = sh.TRE, W = sh.W;
+    const int na[2] = {active_tiles(c->ftiles, 0, n0), active_tiles(c->ftiles, 1, n0)};
+    if (na[0] + na[1] <= 0) return;
     EvScope ev(c, st, hist ? 1 : 0);
-    BHFWI_FWD_SHAPES(BHFWI_TB)
+    for (int q = 0; q < 2; ++q) {
+        const int nact = na[q];
+        if (nact <= 0) continue;
+        const Shape sh = q ? c->ftiles.pml : fwd_shape(c);
+        const int T = sh.T, TRE = sh.TRE, W = sh.W;
+        if (q == 0) {
+            constexpr int PMV = 0;
+            BHFWI_FWD_INT(BHFWI_TB)
+        } else {
+            constexpr int PMV = 1;
+            BHFWI_FWD_PML(BHFWI_TB)
+        }
+    }
 }
 #undef BHFWI_TB
 
 #define BHFWI_TBA(TT, RR, WW)                                                                \
     if (T == TT && TRE == RR && W == WW) {                                                   \
-        hipLaunchKernelGGL((bhfwi::k_adj_tb<TT, RR, WW>), dim3(nact), dim3(64 * WW), 0, st,  \
-                           c->d_shots, c->atiles.d, nact, c->tune.tile_map, n_hi, nsteps,    \
-                           lam, mu, rho, c->d_rec, resid, c->d_pml_r, c->d_pml_z, in, out,   \
-                           hist_hi, (long long)(2 * c->cells), acc, (long long)c->cells);    \
-        return;                                                                              \
+        hipLaunchKernelGGL((bhfwi::k_adj_tb<TT, RR, WW, PMV>), dim3(nact), dim3(64 * WW), 0, \
+                           st, c->d_shots, c->atiles.d[q], nact, c->tune.tile_map, n_hi,     \
+                           nsteps, lam, mu, rho, c->d_rec, resid, c->d_pml_r, c->d_pml_z,    \
+                           in, out, hist_hi, (long long)(2 * c->cells), acc,                \
+                           (long long)c->cells);                                             \
+        continue;                                                                            \
     }
 
 // nsteps (<= the adjoint shape's T) adjoint steps n_hi, n_hi - 1, ... in
-// LDS-tiled kernels; hist_hi is the history slot of step n_hi.
+// LDS-tiled kernels (interior tiles, then PML sub-tiles); hist_hi is the
+// history slot of step n_hi.
 void adj_tb_launch(bhfwi_ctx* c, hipStream_t st, int n_hi, int nsteps, const float* lam,
                    const float* mu, const float* rho, const float* resid, const float* in,
                    float* out, const float* hist_hi, float* acc)
 {
-    const int nact = active_tiles(c->atiles, n_hi - nsteps + 1);
-    if (nact <= 0) return;
-    const Shape sh = adj_shape(c);
-    const int T = sh.T, TRE = sh.TRE, W = sh.W;
+    const int n_lo = n_hi - nsteps + 1;
+    const int na[2] = {active_tiles(c->atiles, 0, n_lo), active_tiles(c->atiles, 1, n_lo)};
+    if (na[0] + na[1] <= 0) return;
     EvScope ev(c, st, 2);
-    BHFWI_ADJ_SHAPES(BHFWI_TBA)
+    for (int q = 0; q < 2; ++q) {
+        const int nact = na[q];
+        if (nact <= 0) continue;
+        const Shape sh = q ? c->atiles.pml : adj_shape(c);
+        const int T = sh.T, TRE = sh.TRE, W = sh.W;
+        if (q == 0) {
+            constexpr int PMV = 0;
+            BHFWI_ADJ_INT(BHFWI_TBA)
+        } else {
+            constexpr int PMV = 1;
+            BHFWI_ADJ_PML(BHFWI_TBA)
+        }
+    }
 }
 #undef BHFWI_TBA
-
-#define BHFWI_TBS(TT, RR, WW) \
-    if (T == TT && TRE == RR && W == WW) return true;
-bool fwd_supported(int T, int TRE, int W)
-{
-    BHFWI_FWD_SHAPES(BHFWI_TBS)
-    return false;
-}
-bool adj_supported(int T, int TRE, int W)
-{
-    BHFWI_ADJ_SHAPES(BHFWI_TBS)
-    return false;
-}
-#undef BHFWI_TBS
 
 // Adjoint steps [n0, n1) run backwards from n1 - 1 in buffers ab[*m & 1] ->
 // ab[(*m + 1) & 1]; hist holds v of step n at slot n - n0.
@@ -708,8 +795,10 @@ void bhfwi_destroy(bhfwi_ctx* c)
     if (c->d_pml_r) (void)hipFree(c->d_pml_r);
     if (c->d_pml_z) (void)hipFree(c->d_pml_z);
     if (c->d_work) (void)hipFree(c->d_work);
-    if (c->ftiles.d) (void)hipFree(c->ftiles.d);
-    if (c->atiles.d) (void)hipFree(c->atiles.d);
+    for (int q = 0; q < 2; ++q) {
+        if (c->ftiles.d[q]) (void)hipFree(c->ftiles.d[q]);
+        if (c->atiles.d[q]) (void)hipFree(c->atiles.d[q]);
+    }
     if (c->d_scratch) (void)hipFree(c->d_scratch);
     if (c->d_status) (void)hipFree(c->d_status);
     delete c;
@@ -844,6 +933,18 @@ int bhfwi_set_tune(bhfwi_ctx* c, const bhfwi_tune* t)
     return upload_work(c);
 }
 
+int bhfwi_kernel_shapes(const bhfwi_ctx* c, int32_t* out)
+{
+    if (!c || !out) return BHFWI_EINVAL;
+    const Shape s[4] = {fwd_shape(c), c->ftiles.pml, adj_shape(c), c->atiles.pml};
+    for (int q = 0; q < 4; ++q) {
+        out[3 * q] = s[q].T;
+        out[3 * q + 1] = s[q].TRE;
+        out[3 * q + 2] = s[q].W;
+    }
+    return BHFWI_OK;
+}
+
 int bhfwi_autotune(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
                    const float* rho, const float* wavelet, float* traces, void* fwd_ws,
                    int64_t fwd_ws_bytes, void* adj_ws, int64_t adj_ws_bytes, float* acc,
@@ -920,7 +1021,7 @@ int bhfwi_autotune(bhfwi_ctx* c, void* stream, const float* lam, const float* mu
         t.adj_tb_steps = 1;              \
         cand.push_back(t);               \
     }
-    BHFWI_FWD_SHAPES(BHFWI_TBC)
+    BHFWI_FWD_INT(BHFWI_TBC)
 #undef BHFWI_TBC
     float best_f = 1e30f;
     bhfwi_tune best_tune = base;
@@ -956,7 +1057,7 @@ int bhfwi_autotune(bhfwi_ctx* c, void* stream, const float* lam, const float* mu
         t.adj_tb_waves = WW;        \
         cand.push_back(t);          \
     }
-    BHFWI_ADJ_SHAPES(BHFWI_TBC)
+    BHFWI_ADJ_INT(BHFWI_TBC)
 #undef BHFWI_TBC
     float best_a = 1e30f;
     bhfwi_tune best_adj = best_tune;

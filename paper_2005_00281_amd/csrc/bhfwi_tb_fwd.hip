@@ -27,8 +27,8 @@ struct IntC {
     static constexpr int value = V;
 };
 
-template <int T, int TRE, int W>
-__global__ void __launch_bounds__(64 * W, (TRE == W && W >= 16) ? 8 : 1)
+template <int T, int TRE, int W, int PM>
+__global__ void __launch_bounds__(64 * W, (W >= 16 && (TRE == W || (PM == 0 && TRE <= 3 * W))) ? 8 : 1)
 k_fwd_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int nwork, int map,
          int n0,
          int nsteps, const float* __restrict__ lam, const float* __restrict__ mu,
@@ -66,7 +66,8 @@ k_fwd_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
     const float dt = S.dt, idr = S.inv_dr, idz = S.inv_dz, dr = S.dr;
     const int ihi = wk.z - T + TRE - 1;
     const int klo = wk.y - T, khi = wk.y - T + 63;
-    const bool tile_pml = (ihi >= nr) || (klo < pz) || (khi >= NZ - pz);
+    // PM = 0: the launch holds only tiles clear of every PML layer
+    const bool tile_pml = PM != 0 && ((ihi >= nr) || (klo < pz) || (khi >= NZ - pz));
 
     const float* __restrict__ Fi = sin + S.fst_off;
     float* __restrict__ Fo = sout + S.fst_off;

@@ -58,13 +58,17 @@ FWD_TUNES = [T(1, 1, 0), T(2, 4, 1), T(3, 2, 1), T(4, 4, 0), T(16, 4, 1), T(64, 
              T(tb=2), T(tb=3, graph=0), T(tb=4), T(tb=4, tbw=8), T(tb=6, tbr=24, tbw=8, graph=0),
              T(tb=8, tbr=32, tbw=8), T(tb=3, tbr=24, tbw=8), T(tb=4, tmap=0), T(tb=4, tbw=16),
              T(tb=3, tbw=16, graph=0), T(tb=6, tbr=32, tbw=16), T(tb=6, tbr=48, tbw=16, atb=1),
-             T(tb=8, tbr=48, tbw=16, graph=0, atb=1)]
+             T(tb=8, tbr=48, tbw=16, graph=0, atb=1), T(tb=8, tbr=64, tbw=16, atb=1),
+             T(tb=4, tbr=64, tbw=16, atb=1, graph=0)]
 GRAD_TUNES = [T(1, 1, 1), T(2, 4, 0), T(4, 4, 1), T(5, 4, 1), T(64, 8, 0), T(tb=4),
               T(tb=3, graph=0), T(tb=4, tbw=8), T(tb=6, tbr=24, tbw=8), T(tb=8, tbr=32, tbw=8),
               T(tb=4, tbw=8, tmap=0), T(tb=4, tbw=16), T(tb=2, tbw=16, graph=0),
               T(tb=8, tbr=32, tbw=16), T(tb=6, tbr=48, tbw=16, atb=6, atbr=32, atbw=16),
               T(tb=4, tbr=48, tbw=16, atb=3, atbr=16, atbw=8, graph=0),
-              T(tb=6, tbr=32, tbw=16, atb=1, rows=2), T(tb=0, rows=2, atb=4, atbr=16, atbw=16)]
+              T(tb=6, tbr=32, tbw=16, atb=1, rows=2), T(tb=0, rows=2, atb=4, atbr=16, atbw=16),
+              T(tb=8, tbr=64, tbw=16, atb=6, atbr=48, atbw=16),
+              T(tb=4, tbr=64, tbw=16, atb=4, atbr=48, atbw=16, graph=0),
+              T(tb=8, tbr=48, tbw=16, atb=8, atbr=48, atbw=16)]
 
 
 def oracle_traces(w, s=0, which="start"):
@@ -486,3 +490,19 @@ def test_velocity_parameterisation_autograd():
                                 w.rho.astype(np.float32), gl.astype(np.float32),
                                 gm.astype(np.float32))
     assert rel_l2(a.cpu().numpy(), ao) <= 1e-6 and rel_l2(b.cpu().numpy(), bo) <= 1e-6
+
+
+def test_kernel_shapes_report_the_pml_sub_tiles():
+    """Interior-only shapes hand their PML tiles to a PML-capable shape with
+    the same T whose owned rows divide theirs."""
+    w = workloads.tiny()
+    _say("kernel shapes")
+    sv = survey(w, tune=T(tb=8, tbr=64, tbw=16, atb=6, atbr=48, atbw=16))
+    ks = sv.kernel_shapes()
+    assert ks["fwd"] == (8, 64, 16) and ks["fwd_pml"] == (8, 32, 16)
+    assert ks["adj"] == (6, 48, 16) and ks["adj_pml"] == (6, 24, 8)
+    sv.set_tune(**T(tb=6, tbr=32, tbw=16))
+    ks = sv.kernel_shapes()
+    assert ks["fwd"] == ks["fwd_pml"] == ks["adj"] == ks["adj_pml"] == (6, 32, 16)
+    sv.set_tune(**T(rows=2))
+    assert sv.kernel_shapes()["adj"][0] == 0
