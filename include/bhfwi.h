@@ -121,6 +121,10 @@ typedef struct {
                                  run as sub-tiles of a smaller shape */
     int32_t adj_tb_rows;
     int32_t adj_tb_waves;
+    int32_t pml_overlap;      /* 1: the PML tiles of a time block run on a second
+                                 stream alongside the interior tiles (forked and
+                                 joined around the block); 0: after them on the
+                                 caller's stream */
 } bhfwi_tune;
 
 /* Memory of one group of shots evaluated together (bhfwi_plan_bytes). */

@@ -48,7 +48,8 @@ class Tune(C.Structure):
                 ("use_graph", C.c_int32), ("time_kernels", C.c_int32),
                 ("tb_steps", C.c_int32), ("tb_rows", C.c_int32), ("tb_waves", C.c_int32),
                 ("tile_map", C.c_int32), ("adj_tb_steps", C.c_int32),
-                ("adj_tb_rows", C.c_int32), ("adj_tb_waves", C.c_int32)]
+                ("adj_tb_rows", C.c_int32), ("adj_tb_waves", C.c_int32),
+                ("pml_overlap", C.c_int32)]
 
 
 class PlanBytes(C.Structure):

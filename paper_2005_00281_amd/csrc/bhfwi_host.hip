@@ -127,6 +127,8 @@ struct bhfwi_ctx {
     void* d_scratch = nullptr;
     int* d_status = nullptr;  // device word raised by kernels that see non-finite sums
     hipStream_t cap_stream = nullptr;  // private stream that graphs are captured on
+    hipStream_t pml_stream = nullptr;  // second stream for the PML tiles of a block
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     struct Graph {
         std::vector<uintptr_t> key;
         hipGraphExec_t exec;
@@ -453,10 +455,42 @@ bool adj_supported(int T, int TRE, int W)
     return adj_int_ok(sh) && pml_shape(sh, true).T >= 2;
 }
 
+// The PML tiles of a block run on a second stream, forked from and joined
+// back into st around the block (in a captured graph: two parallel branches),
+// so that they share the GPU with the interior tiles instead of following
+// them.  Returns the stream for list q.
+struct PmlFork {
+    bhfwi_ctx* c;
+    hipStream_t st;
+    bool on = false;
+    PmlFork(bhfwi_ctx* c_, hipStream_t st_, const int na[2]) : c(c_), st(st_)
+    {
+        if (!c->tune.pml_overlap || na[0] <= 0 || na[1] <= 0) return;
+        if (!c->pml_stream &&
+            hipStreamCreateWithFlags(&c->pml_stream, hipStreamNonBlocking) != hipSuccess)
+            return;
+        if (!c->ev_fork && hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess)
+            return;
+        if (!c->ev_join && hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
+            return;
+        if (hipEventRecord(c->ev_fork, st) != hipSuccess) return;
+        if (hipStreamWaitEvent(c->pml_stream, c->ev_fork, 0) != hipSuccess) return;
+        on = true;
+    }
+    hipStream_t stream(int q) const { return (on && q == 1) ? c->pml_stream : st; }
+    ~PmlFork()
+    {
+        if (!on) return;
+        (void)hipEventRecord(c->ev_join, c->pml_stream);
+        (void)hipStreamWaitEvent(st, c->ev_join, 0);
+    }
+};
+
 #define BHFWI_TB(TT, RR, WW)                                                                 \
     if (T == TT && TRE == RR && W == WW) {                                                   \
         hipLaunchKernelGGL((bhfwi::k_fwd_tb<TT, RR, WW, PMV>), dim3(nact), dim3(64 * WW), 0, \
-                           st, c->d_shots, c->ftiles.d[q], nact, c->tune.tile_map, n0,       \
+                           fork.stream(q), c->d_shots, c->ftiles.d[q], nact,                 \
+                           c->tune.tile_map, n0,                                             \
                            nsteps, lam, mu, rho, wav, c->d_rec, c->d_pml_r, c->d_pml_z, in,  \
                            out, traces, hist, (long long)(2 * c->cells),                    \
                            (long long)c->cells);                                             \
@@ -472,7 +506,8 @@ void fwd_tb_launch(bhfwi_ctx* c, hipStream_t st, int n0, int nsteps, const float
     const int na[2] = {active_tiles(c->ftiles, 0, n0), active_tiles(c->ftiles, 1, n0)};
     if (na[0] + na[1] <= 0) return;
     EvScope ev(c, st, hist ? 1 : 0);
-    for (int q = 0; q < 2; ++q) {
+    PmlFork fork(c, st, na);
+    for (int q = 1; q >= 0; --q) {
         const int nact = na[q];
         if (nact <= 0) continue;
         const Shape sh = q ? c->ftiles.pml : fwd_shape(c);
@@ -491,7 +526,8 @@ void fwd_tb_launch(bhfwi_ctx* c, hipStream_t st, int n0, int nsteps, const float
 #define BHFWI_TBA(TT, RR, WW)                                                                \
     if (T == TT && TRE == RR && W == WW) {                                                   \
         hipLaunchKernelGGL((bhfwi::k_adj_tb<TT, RR, WW, PMV>), dim3(nact), dim3(64 * WW), 0, \
-                           st, c->d_shots, c->atiles.d[q], nact, c->tune.tile_map, n_hi,     \
+                           fork.stream(q), c->d_shots, c->atiles.d[q], nact,                 \
+                           c->tune.tile_map, n_hi,                                           \
                            nsteps, lam, mu, rho, c->d_rec, resid, c->d_pml_r, c->d_pml_z,    \
                            in, out, hist_hi, (long long)(2 * c->cells), acc,                \
                            (long long)c->cells);                                             \
@@ -509,7 +545,8 @@ void adj_tb_launch(bhfwi_ctx* c, hipStream_t st, int n_hi, int nsteps, const flo
     const int na[2] = {active_tiles(c->atiles, 0, n_lo), active_tiles(c->atiles, 1, n_lo)};
     if (na[0] + na[1] <= 0) return;
     EvScope ev(c, st, 2);
-    for (int q = 0; q < 2; ++q) {
+    PmlFork fork(c, st, na);
+    for (int q = 1; q >= 0; --q) {
         const int nact = na[q];
         if (nact <= 0) continue;
         const Shape sh = q ? c->atiles.pml : adj_shape(c);
@@ -594,6 +631,7 @@ int run_sequence(bhfwi_ctx* c, hipStream_t st, std::vector<uintptr_t> key, F&& r
     key.push_back((uintptr_t)c->tune.adj_tb_steps);
     key.push_back((uintptr_t)c->tune.adj_tb_rows);
     key.push_back((uintptr_t)c->tune.adj_tb_waves);
+    key.push_back((uintptr_t)c->tune.pml_overlap);
     for (size_t g = 0; g < c->graphs.size(); ++g)
         if (c->graphs[g].key == key) {
             HIPOK(c, hipGraphLaunch(c->graphs[g].exec, st));
@@ -755,6 +793,7 @@ int bhfwi_create(bhfwi_ctx** out, int32_t hip_device, const bhfwi_shot* shots, i
     c->tune.tb_rows = 32;
     c->tune.tb_waves = 16;
     c->tune.tile_map = 1;
+    c->tune.pml_overlap = 1;
     rebuild_work(c);
 
     hipError_t e = hipSetDevice(hip_device);
@@ -790,6 +829,9 @@ void bhfwi_destroy(bhfwi_ctx* c)
     clear_graphs(c);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->pml_stream) (void)hipStreamDestroy(c->pml_stream);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->d_shots) (void)hipFree(c->d_shots);
     if (c->d_rec) (void)hipFree(c->d_rec);
     if (c->d_pml_r) (void)hipFree(c->d_pml_r);
@@ -916,6 +958,7 @@ int bhfwi_set_tune(bhfwi_ctx* c, const bhfwi_tune* t)
     if (!c || !t) return BHFWI_EINVAL;
     if (t->rows_per_wave < 1 || t->use_graph < 0 || t->use_graph > 1 || t->time_kernels < 0 ||
         t->time_kernels > 1 || t->tb_steps < 0 || t->tile_map < 0 || t->tile_map > 1 ||
+        t->pml_overlap < 0 || t->pml_overlap > 1 ||
         (t->tb_steps >= 2 && !fwd_supported(t->tb_steps, t->tb_rows, t->tb_waves)) ||
         t->adj_tb_steps < 0 ||
         (t->adj_tb_steps >= 2 && !adj_supported(t->adj_tb_steps, t->adj_tb_rows, t->adj_tb_waves)) ||

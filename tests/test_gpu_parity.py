@@ -48,10 +48,10 @@ def survey(w, ckpt=250, tune=None):
     return sv
 
 
-def T(rows=4, wpb=4, graph=1, tb=0, tbr=16, tbw=4, tmap=1, atb=0, atbr=16, atbw=8):
+def T(rows=4, wpb=4, graph=1, tb=0, tbr=16, tbw=4, tmap=1, atb=0, atbr=16, atbw=8, ovl=1):
     return dict(rows_per_wave=rows, waves_per_block=wpb, use_graph=graph, tb_steps=tb,
                 tb_rows=tbr, tb_waves=tbw, tile_map=tmap, adj_tb_steps=atb, adj_tb_rows=atbr,
-                adj_tb_waves=atbw)
+                adj_tb_waves=atbw, pml_overlap=ovl)
 
 
 FWD_TUNES = [T(1, 1, 0), T(2, 4, 1), T(3, 2, 1), T(4, 4, 0), T(16, 4, 1), T(64, 8, 0),
@@ -59,7 +59,7 @@ FWD_TUNES = [T(1, 1, 0), T(2, 4, 1), T(3, 2, 1), T(4, 4, 0), T(16, 4, 1), T(64, 
              T(tb=8, tbr=32, tbw=8), T(tb=3, tbr=24, tbw=8), T(tb=4, tmap=0), T(tb=4, tbw=16),
              T(tb=3, tbw=16, graph=0), T(tb=6, tbr=32, tbw=16), T(tb=6, tbr=48, tbw=16, atb=1),
              T(tb=8, tbr=48, tbw=16, graph=0, atb=1), T(tb=8, tbr=64, tbw=16, atb=1),
-             T(tb=4, tbr=64, tbw=16, atb=1, graph=0)]
+             T(tb=4, tbr=64, tbw=16, atb=1, graph=0), T(tb=8, tbr=64, tbw=16, atb=1, ovl=0)]
 GRAD_TUNES = [T(1, 1, 1), T(2, 4, 0), T(4, 4, 1), T(5, 4, 1), T(64, 8, 0), T(tb=4),
               T(tb=3, graph=0), T(tb=4, tbw=8), T(tb=6, tbr=24, tbw=8), T(tb=8, tbr=32, tbw=8),
               T(tb=4, tbw=8, tmap=0), T(tb=4, tbw=16), T(tb=2, tbw=16, graph=0),
@@ -68,7 +68,9 @@ GRAD_TUNES = [T(1, 1, 1), T(2, 4, 0), T(4, 4, 1), T(5, 4, 1), T(64, 8, 0), T(tb=
               T(tb=6, tbr=32, tbw=16, atb=1, rows=2), T(tb=0, rows=2, atb=4, atbr=16, atbw=16),
               T(tb=8, tbr=64, tbw=16, atb=6, atbr=48, atbw=16),
               T(tb=4, tbr=64, tbw=16, atb=4, atbr=48, atbw=16, graph=0),
-              T(tb=8, tbr=48, tbw=16, atb=8, atbr=48, atbw=16)]
+              T(tb=8, tbr=48, tbw=16, atb=8, atbr=48, atbw=16),
+              T(tb=8, tbr=48, tbw=16, atb=6, atbr=32, atbw=16, ovl=0),
+              T(tb=8, tbr=48, tbw=16, atb=6, atbr=32, atbw=16, ovl=1, graph=0)]
 
 
 def oracle_traces(w, s=0, which="start"):
@@ -506,3 +508,33 @@ def test_kernel_shapes_report_the_pml_sub_tiles():
     assert ks["fwd"] == ks["fwd_pml"] == ks["adj"] == ks["adj_pml"] == (6, 32, 16)
     sv.set_tune(**T(rows=2))
     assert sv.kernel_shapes()["adj"][0] == 0
+
+
+@pytest.mark.parametrize("ovl", [0, 1])
+def test_graph_replays_equal_eager_launches(ovl):
+    """The captured launch sequence (with the PML tiles on a forked stream
+    when ovl = 1) replayed several times, with eager work and host
+    synchronisations in between, gives the eager result bit for bit."""
+    w = workloads.tiny(nr=60, nz=200, p=8, nt=160)
+    _say("graph replays", ovl)
+    lam, mu, rho = gpu_models(w)
+    r = f32(np.random.default_rng(3).standard_normal(len(w.shots[0].rec_k) * w.shots[0].nt))
+    base = dict(tb=8, tbr=64, tbw=16, atb=6, atbr=48, atbw=16, ovl=ovl)
+    outs = {}
+    for graph in (0, 1):
+        sv = survey(w, ckpt=40, tune=T(graph=graph, **base))
+        wav = sv.pack_wavelets([w.shots[0].wavelet])
+        reps = []
+        for _ in range(3 if graph else 1):
+            tr = sv.fwd_model(lam, mu, rho, wav, store_ckpt=True).clone()
+            acc = sv.adjoint_model(lam, mu, rho, wav, r)
+            g = [t.cpu().numpy() for t in sv.gradient(mu, acc)]
+            torch.cuda.synchronize()
+            _ = (lam * 2).sum().item()  # unrelated eager work between replays
+            reps.append((tr.cpu().numpy(), g))
+        outs[graph] = reps
+    e_tr, e_g = outs[0][0]
+    for tr, g in outs[1]:
+        assert np.array_equal(tr, e_tr)
+        for a, b in zip(g, e_g):
+            assert np.array_equal(a, b)
