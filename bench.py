@@ -278,6 +278,10 @@ def main():
             log("sweep adj T %d rows %d waves %d: %.2f ms per gradient" % (T, R, W_, ms))
         for x in surveys:
             x.set_tune(**keep)
+        for ovl in (0, 1):
+            log("sweep pml_overlap %d: %.2f ms per gradient" % (ovl, timed(pml_overlap=ovl)))
+        for x in surveys:
+            x.set_tune(**keep)
     if args.no_graph:
         for sv in surveys:
             sv.set_tune(use_graph=0)
