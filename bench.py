@@ -164,6 +164,11 @@ def main():
     ap.add_argument("--adj-tb-waves", type=int, default=0)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2005_00281_amd",
+                                                         "tune_cache.json"),
+                    help="autotuner results per device and survey shape ('' : none)")
+    ap.add_argument("--retune", action="store_true",
+                    help="re-run the autotuner and record its choice in the tune cache")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=120)
     ap.add_argument("--plain-shots", type=int, default=2,
@@ -243,11 +248,23 @@ def main():
                         adj_tb_rows=args.adj_tb_rows or None,
                         adj_tb_waves=args.adj_tb_waves or None)
     else:
+        # the autotuner's choice for this device and survey shape: from the
+        # tune cache when it holds one (--retune re-measures and records it)
         lam_s, mu_s = P.moduli(f32(w.vp_start), f32(w.vs_start), rho)
+        cache = args.tune_cache or None
+        if cache and args.retune and os.path.exists(cache):
+            import json as _json
+            with open(cache) as f:
+                table = _json.load(f)
+            for sv in surveys:
+                table.pop(sv.shape_key(), None)
+            with open(cache, "w") as f:
+                _json.dump(table, f, indent=1, sort_keys=True)
         t_at = time.perf_counter()
         for sv, wav in zip(surveys, wavs):
-            entry = sv.autotune(lam_s, mu_s, rho, wav)
-        log("autotune %.1f s -> %s" % (time.perf_counter() - t_at, entry["tune"]))
+            entry = sv.autotune(lam_s, mu_s, rho, wav, cache=cache)
+        log("autotune %.1f s -> %s%s" % (time.perf_counter() - t_at, entry["tune"],
+                                          " (tune cache)" if entry.get("cached") else ""))
         del lam_s, mu_s
     if args.sweep:
         keep = surveys[0].get_tune()

@@ -303,10 +303,10 @@ class Survey:
                 table = json.load(f)
         if key in table:
             self.set_tune(**table[key]["tune"])
-            return table[key]
+            return dict(table[key], cached=True)
         z = self.sizes
         if probe_steps is None:
-            probe_steps = min(z.ckpt_every, z.nt_max, 96)
+            probe_steps = min(z.ckpt_every, z.nt_max, 256)
         tr = torch.empty(z.trace_elems, dtype=torch.float32, device=self.device)
         acc = torch.empty(z.acc_elems, dtype=torch.float32, device=self.device)
         fw, aw = self.workspace("fwd"), self.workspace("adj")

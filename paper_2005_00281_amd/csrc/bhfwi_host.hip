@@ -1030,9 +1030,9 @@ int bhfwi_autotune(bhfwi_ctx* c, void* stream, const float* lam, const float* mu
         adj_range(c, st, 0, P, lam, mu, rho, traces, ab, &m, hist, acc);
     };
     // best of repetitions 2 and 3 of `phase` (the first warms up)
-    auto time_it = [&](auto&& phase, float* out) {
+    auto time_it = [&](auto&& phase, float* out, int reps) {
         float tmin = 1e30f;
-        for (int rep = 0; rep < 3; ++rep) {
+        for (int rep = 0; rep < reps; ++rep) {
             HIPOK(c, hipEventRecord(e0, st));
             phase();
             HIPOK(c, hipEventRecord(e1, st));
@@ -1068,15 +1068,30 @@ int bhfwi_autotune(bhfwi_ctx* c, void* stream, const float* lam, const float* mu
 #undef BHFWI_TBC
     float best_f = 1e30f;
     bhfwi_tune best_tune = base;
-    for (const bhfwi_tune& t : cand) {
-        if (int rc = install(t)) return rc;
-        float ms;
-        if (int rc = time_it(run_fwd, &ms)) return rc;
-        if (ms < best_f) {
-            best_f = ms;
-            best_tune = t;
+    // every candidate with 3 repetitions, then the 4 fastest again with 6
+    auto pick = [&](auto&& phase, float* best_ms_out, bhfwi_tune* best_out) {
+        std::vector<std::pair<float, int>> tm;
+        for (int q = 0; q < (int)cand.size(); ++q) {
+            if (int rc = install(cand[q])) return rc;
+            float ms;
+            if (int rc = time_it(phase, &ms, 3)) return rc;
+            tm.push_back({ms, q});
         }
-    }
+        std::sort(tm.begin(), tm.end());
+        *best_ms_out = 1e30f;
+        for (int r = 0; r < (int)std::min<size_t>(4, tm.size()); ++r) {
+            if (int rc = install(cand[tm[r].second])) return rc;
+            float ms;
+            if (int rc = time_it(phase, &ms, 6)) return rc;
+            ms = std::min(ms, tm[r].first);
+            if (ms < *best_ms_out) {
+                *best_ms_out = ms;
+                *best_out = cand[tm[r].second];
+            }
+        }
+        return BHFWI_OK;
+    };
+    if (int rc = pick(run_fwd, &best_f, &best_tune)) return rc;
     // Phase 2: the adjoint with the fused correlation over the history the
     // chosen forward wrote: one step per launch and every adjoint tile shape.
     if (int rc = install(best_tune)) return rc;
@@ -1104,15 +1119,7 @@ int bhfwi_autotune(bhfwi_ctx* c, void* stream, const float* lam, const float* mu
 #undef BHFWI_TBC
     float best_a = 1e30f;
     bhfwi_tune best_adj = best_tune;
-    for (const bhfwi_tune& t : cand) {
-        if (int rc = install(t)) return rc;
-        float ms;
-        if (int rc = time_it(run_adj, &ms)) return rc;
-        if (ms < best_a) {
-            best_a = ms;
-            best_adj = t;
-        }
-    }
+    if (int rc = pick(run_adj, &best_a, &best_adj)) return rc;
     best_tune = best_adj;
     const float best_t = best_f + best_a;
     (void)hipEventDestroy(e0);
