@@ -160,6 +160,7 @@ def main():
     ap.add_argument("--tile-map", type=int, default=-1)
     ap.add_argument("--adj-tb", type=int, default=-1,
                     help="adjoint steps per launch (0: as the forward, 1: one per launch)")
+    ap.add_argument("--pml-overlap", type=int, default=-1)
     ap.add_argument("--adj-tb-rows", type=int, default=0)
     ap.add_argument("--adj-tb-waves", type=int, default=0)
     ap.add_argument("--no-graph", action="store_true")
@@ -302,6 +303,9 @@ def main():
     if args.no_graph:
         for sv in surveys:
             sv.set_tune(use_graph=0)
+    if args.pml_overlap >= 0:
+        for sv in surveys:
+            sv.set_tune(pml_overlap=args.pml_overlap)
     sv = surveys[0]
     tune = sv.get_tune()
 

@@ -123,8 +123,8 @@ typedef struct {
     int32_t adj_tb_waves;
     int32_t pml_overlap;      /* 1: the PML tiles of a time block run on a second
                                  stream alongside the interior tiles (forked and
-                                 joined around the block); 0: after them on the
-                                 caller's stream */
+                                 joined around the block); 0 (default): after
+                                 them on the caller's stream */
 } bhfwi_tune;
 
 /* Memory of one group of shots evaluated together (bhfwi_plan_bytes). */

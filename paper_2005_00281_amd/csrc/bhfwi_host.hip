@@ -507,7 +507,7 @@ void fwd_tb_launch(bhfwi_ctx* c, hipStream_t st, int n0, int nsteps, const float
     if (na[0] + na[1] <= 0) return;
     EvScope ev(c, st, hist ? 1 : 0);
     PmlFork fork(c, st, na);
-    for (int q = 1; q >= 0; --q) {
+    for (int q = 0; q < 2; ++q) {
         const int nact = na[q];
         if (nact <= 0) continue;
         const Shape sh = q ? c->ftiles.pml : fwd_shape(c);
@@ -546,7 +546,7 @@ void adj_tb_launch(bhfwi_ctx* c, hipStream_t st, int n_hi, int nsteps, const flo
     if (na[0] + na[1] <= 0) return;
     EvScope ev(c, st, 2);
     PmlFork fork(c, st, na);
-    for (int q = 1; q >= 0; --q) {
+    for (int q = 0; q < 2; ++q) {
         const int nact = na[q];
         if (nact <= 0) continue;
         const Shape sh = q ? c->atiles.pml : adj_shape(c);
@@ -793,7 +793,7 @@ int bhfwi_create(bhfwi_ctx** out, int32_t hip_device, const bhfwi_shot* shots, i
     c->tune.tb_rows = 32;
     c->tune.tb_waves = 16;
     c->tune.tile_map = 1;
-    c->tune.pml_overlap = 1;
+    c->tune.pml_overlap = 0;  // measured: concurrent PML tiles crowd out interior ones
     rebuild_work(c);
 
     hipError_t e = hipSetDevice(hip_device);
