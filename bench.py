@@ -262,8 +262,15 @@ def main():
             with open(cache, "w") as f:
                 _json.dump(table, f, indent=1, sort_keys=True)
         t_at = time.perf_counter()
-        for sv, wav in zip(surveys, wavs):
+        tuned = {}  # set of shot shapes -> tune of the first group that has it
+        for g, (sv, wav) in enumerate(zip(surveys, wavs)):
+            shapes = frozenset((sh.nr, sh.nz, sh.pr, sh.pz, sh.nt)
+                               for sh in (w.shots[s] for s in pl.groups[g]))
+            if shapes in tuned:  # a group of the same shot shapes: same kernels
+                sv.set_tune(**tuned[shapes])
+                continue
             entry = sv.autotune(lam_s, mu_s, rho, wav, cache=cache)
+            tuned[shapes] = entry["tune"]
         log("autotune %.1f s -> %s%s" % (time.perf_counter() - t_at, entry["tune"],
                                           " (tune cache)" if entry.get("cached") else ""))
         del lam_s, mu_s
