@@ -271,6 +271,7 @@ def main():
                 continue
             entry = sv.autotune(lam_s, mu_s, rho, wav, cache=cache)
             tuned[shapes] = entry["tune"]
+            log("tune key %s%s" % (sv.shape_key()[:60], " (cached)" if entry.get("cached") else ""))
         log("autotune %.1f s -> %s%s" % (time.perf_counter() - t_at, entry["tune"],
                                           " (tune cache)" if entry.get("cached") else ""))
         del lam_s, mu_s

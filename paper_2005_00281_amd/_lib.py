@@ -283,14 +283,18 @@ class Survey:
         return {name: getattr(t, name) for name, _ in Tune._fields_}
 
     def shape_key(self):
-        """Key of the autotune cache: device name and the multiset of shot shapes."""
+        """Key of the autotune cache: GPU architecture and compute-unit count,
+        checkpoint interval and the multiset of shot shapes."""
         shapes = sorted((sh.nr + sh.pr, sh.nz + 2 * sh.pz, sh.nt) for sh in self.shots)
         hist = {}
         for s in shapes:
             hist[s] = hist.get(s, 0) + 1
-        return "%s|K%d|%s" % (torch.cuda.get_device_name(self.device), self.sizes.ckpt_every,
-                              ";".join("%dx%dx%d*%d" % (a, b, c, n)
-                                       for (a, b, c), n in sorted(hist.items())))
+        p = torch.cuda.get_device_properties(self.device)
+        arch = getattr(p, "gcnArchName", "") or torch.cuda.get_device_name(self.device)
+        return "%s/%dCU|K%d|%s" % (arch.split(":")[0], p.multi_processor_count,
+                                  self.sizes.ckpt_every,
+                                  ";".join("%dx%dx%d*%d" % (a, b, c, n)
+                                           for (a, b, c), n in sorted(hist.items())))
 
     def autotune(self, lam, mu, rho, wavelet, probe_steps=None, cache=None):
         """Pick the fastest kernel shape for this survey (bhfwi_autotune) and
