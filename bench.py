@@ -131,6 +131,68 @@ def cpu_baseline(w, nt_sample):
                       "checkpointed gradient, %.1f s" % (nt_sample, sh.nt, cs, dt)}
 
 
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def semblance_bench(steps):
+    """Starting-model stage at the 128-shot workload's scale: the slowness-time
+    coherence of 128 gathers of 13 receivers x 16000 samples (0.25 us), 560
+    slownesses of 1 us/m from 150 us/m, 150 us windows every 10 samples, and
+    the P and S picks.  Work model per (gather, slowness, staged sample): 13
+    interpolated reads at 5 FP32 operations each (shift split, two loads
+    folded into one FMA, stack add, energy FMA) plus the square of the stack;
+    per window two double differences.  Prints one JSON line."""
+    import numpy as np
+    import torch
+    import paper_2005_00281_amd as P
+    dev = torch.device("cuda", 0)
+    G, M, nt, dt = 128, 13, 16000, 0.25e-6
+    p0, dp, npp, stride, win = 150e-6, 1e-6, 560, 10, 600
+    ntau = (nt - win) // stride + 1
+    rng = np.random.default_rng(11)
+    t = np.arange(nt) * dt
+    off = 0.1524 * np.arange(M)
+    x = np.empty((G, M, nt), np.float32)
+    true_p, true_s = np.empty(G), np.empty(G)
+    for g in range(G):
+        sp, ss = 1 / rng.uniform(3000, 5500), 1 / rng.uniform(1700, 3000)
+        true_p[g], true_s[g] = sp, ss
+        for m in range(M):
+            a = (np.pi * 8e3 * (t - 1e-3 - sp * off[m])) ** 2
+            b = (np.pi * 8e3 * (t - 2e-3 - ss * off[m])) ** 2
+            x[g, m] = (1 - 2 * a) * np.exp(-a) + 3 * (1 - 2 * b) * np.exp(-b)
+    xt = torch.as_tensor(x, device=dev)
+    ot = torch.as_tensor(np.tile(off, (G, 1)), dtype=torch.float32, device=dev)
+    P.semblance(xt, dt, ot, p0, dp, npp, stride, ntau, win)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        coh = P.semblance(xt, dt, ot, p0, dp, npp, stride, ntau, win)
+        pP, _ = P.semblance_pick(coh, p0, dp, 1 / 6000, 1 / 2000)
+        pS, _ = P.semblance_pick(coh, p0, dp, 0.0, 0.999 / 1500, p_ref=pP, ref_scale=1.4)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    span = 2048
+    chunk = (span - win) // stride + 1
+    staged = G * npp * sum(min(span, (min(ntau, c + chunk) - 1 - c) * stride + win)
+                           for c in range(0, ntau, chunk))
+    flops = staged * (5 * M + 1)
+    achieved = flops / (ms * 1e-3) / 1e12
+    out = {"metric": "starting-model semblance: coherence cells per second", "unit": "Gcells/s",
+           "value": round(G * npp * ntau / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 3),
+           "steps": steps, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "128 gathers x 13 receivers x 16000 samples, 560 slownesses, "
+                                  "%d windows of %d samples" % (ntau, win)},
+           "max_pick_error_us_per_m": round(1e6 * max(
+               np.abs(pP.cpu().numpy() - true_p).max(), np.abs(pS.cpu().numpy() - true_s).max()), 3),
+           "roofline": {"bound": "alu", "achieved": round(achieved, 2),
+                        "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None}}
+    print(json.dumps(out), flush=True)
+
+
 def copy_calibration():
     """One device copy of 1 GiB from memory that is not in any cache, for
     scaling the FETCH_SIZE / WRITE_SIZE counters (bytes known exactly)."""
@@ -177,6 +239,8 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=0.0,
                     help="HBM budget for the planner (0: 80%% of the device)")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--semblance", action="store_true",
+                    help="measure the starting-model semblance stage instead")
     ap.add_argument("--progress", action="store_true",
                     help="synchronise and log after every shot group (long workloads)")
     ap.add_argument("--kt-groups", type=int, default=0,
@@ -190,6 +254,9 @@ def main():
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.semblance:
+        semblance_bench(max(1, args.steps))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU; this build has no multi-GPU path "

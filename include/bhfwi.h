@@ -213,6 +213,44 @@ int bhfwi_kernel_shapes(const bhfwi_ctx *ctx, int32_t *out);
 /* Read (and with reset != 0 clear) the sums of bhfwi_kernel_times_t. */
 int bhfwi_kernel_times(bhfwi_ctx *ctx, bhfwi_kernel_times_t *out, int32_t reset);
 
+/* ---- Starting model (Introduction; Numerical Examples section, Fig. 3-4):
+ * the paper starts its inversions from velocities picked by semblance
+ * analysis of the array waveforms -- near-source data for the formation at
+ * the wall, far-source data for the formation 1 m away -- interpolated
+ * linearly in radius.  These calls do not need a context. */
+
+/* Slowness-time coherence of ngather receiver gathers (device arrays):
+ * traces [g][nrec][nt] (nrec <= 64), offset [g][nrec] (m, axial distance of
+ * each receiver from the gather's first), slownesses p0 + j dp (s/m),
+ * j < np, windows of win (<= 2048) samples starting at sample i*tau_stride,
+ * i < ntau.  coh [g][np][ntau] (device, overwritten) =
+ *   sum_window (sum_m x_m(n + p off_m/dt))^2 / (nrec sum_window sum_m x_m^2),
+ * with each receiver read p*off_m/dt samples later, linearly interpolated
+ * between samples and zero outside its record; 0 for a window without
+ * energy.  energy (nullable, same shape) receives the window energy
+ * sum_window sum_m x_m^2.
+ * FP32 data and products, window sums as differences of prefix sums in
+ * double.  Returns BHFWI_EINVAL on bad sizes. */
+int bhfwi_semblance(void *stream, int32_t ngather, int32_t nrec, int32_t nt,
+                    const float *traces, float dt, const float *offset, int32_t np, float p0,
+                    float dp, int32_t ntau, int32_t tau_stride, int32_t win, float *coh,
+                    float *energy);
+/* Per gather, the slowness of the largest coherence over all windows among
+ * slownesses in [lo, p_hi], lo = max(p_lo, ref_scale * p_ref[g]) when p_ref
+ * (device, ngather) is given (e.g. the S band above a multiple of the picked
+ * P slowness); ties go to the smaller slowness.  p_out, c_out: device,
+ * ngather floats (0 and 0 if the band holds no slowness). */
+int bhfwi_semblance_pick(void *stream, int32_t ngather, int32_t np, int32_t ntau,
+                         const float *coh, float p0, float dp, const float *p_ref,
+                         float ref_scale, float p_lo, float p_hi, float *p_out, float *c_out);
+/* Starting velocities on an NR x NZ grid (device): per axial row k, the wall
+ * values vp_wall[k], vs_wall[k] at r = a, the far values vp_far[k],
+ * vs_far[k] at r = a + dist, linear in r = (i + 1/2) dr between and constant
+ * beyond; cells with r < a take vp_fluid and vs = 0. */
+int bhfwi_starting_model(void *stream, int32_t NR, int32_t NZ, float dr, float a, float dist,
+                         const float *vp_wall, const float *vs_wall, const float *vp_far,
+                         const float *vs_far, float vp_fluid, float *vp, float *vs);
+
 /* Eq. 3-4 (Method section): lam = rho vp^2 - 2 rho vs^2, mu = rho vs^2,
  * n elements, device arrays. */
 int bhfwi_moduli(void *stream, int64_t n, const float *vp, const float *vs, const float *rho,

@@ -76,6 +76,11 @@ def _load():
         lib.orc_precondition.argtypes = [C.c_int64, _D, _U8, C.c_double, _D, _D]
         lib.orc_precondition.restype = C.c_double
         lib.orc_line_search.argtypes = [C.c_double] * 4
+        I32 = C.c_int32
+        lib.orc_semblance.argtypes = [I32, I32, _D, C.c_double, _D, I32, C.c_double, C.c_double,
+                                      I32, I32, I32, _D, _D]
+        lib.orc_starting_model.argtypes = [I32, I32, C.c_double, C.c_double, C.c_double, _D, _D,
+                                           _D, _D, C.c_double, _D, _D]
         lib.orc_line_search.restype = C.c_double
         lib.orc_update.argtypes = [C.c_int64, _D, _D, _D, _D, _D, _U8, C.c_double,
                                    C.c_double, C.c_double, C.c_double, C.c_double,
@@ -248,3 +253,39 @@ def update(lam, mu, rho, g_lam, g_mu, mask, eta, alpha_override=0.0,
                            float(vp_bounds[0]), float(vp_bounds[1]),
                            float(vs_bounds[0]), float(vs_bounds[1]))
     return l, m, a
+
+
+def semblance(traces, dt, offset, p0, dp, np_, tau_stride, ntau, win, return_energy=False):
+    """Slowness-time coherence map [np_, ntau] of traces [nrec, nt] (the
+    semblance analysis of the Introduction and Fig. 4); with return_energy
+    also the window energies (the denominators)."""
+    x = _f64(traces)
+    nrec, nt = x.shape
+    off = _f64(offset)
+    assert off.size == nrec
+    coh, en = np.zeros((np_, ntau)), np.zeros((np_, ntau))
+    _load().orc_semblance(nrec, nt, _p(x), float(dt), _p(off), int(np_), float(p0), float(dp),
+                          int(ntau), int(tau_stride), int(win), _p(coh), _p(en))
+    return (coh, en) if return_energy else coh
+
+
+def pick_slowness(coh, p0, dp, p_lo, p_hi):
+    """The slowness of the largest coherence among slownesses in [p_lo, p_hi]
+    (all window times): (p, coherence)."""
+    c = np.asarray(coh)
+    p = p0 + dp * np.arange(c.shape[0])
+    band = (p >= p_lo) & (p <= p_hi)
+    best = c[band].max(axis=1)
+    j = int(np.argmax(best))
+    return float(p[band][j]), float(best[j])
+
+
+def starting_model(NR, NZ, dr, a, dist, vp_wall, vs_wall, vp_far, vs_far, vp_fluid):
+    """Velocities linear in radius from the wall values to the far values at
+    a + dist (Numerical Examples section); per-row inputs of length NZ."""
+    args = [_f64(np.broadcast_to(np.asarray(v, np.float64), (NZ,)))
+            for v in (vp_wall, vs_wall, vp_far, vs_far)]
+    vp, vs = np.zeros((NR, NZ)), np.zeros((NR, NZ))
+    _load().orc_starting_model(int(NR), int(NZ), float(dr), float(a), float(dist),
+                               *[_p(v) for v in args], float(vp_fluid), _p(vp), _p(vs))
+    return vp, vs

@@ -713,3 +713,70 @@ double orc_update(int64_t n, double *lam, double *mu, const double *rho, const d
     }
     return alpha;
 }
+
+/* ---------------------------------------------------------------------------
+ * Starting model (Introduction; Numerical Examples section, Fig. 3-4):
+ * slowness-time coherence over the receiver array (the semblance analysis the
+ * paper cites to Kimball and Marzetta), then velocities linear in radius from
+ * the near-source values at the borehole wall to the far-source values 1 m
+ * into the formation.
+ * ------------------------------------------------------------------------- */
+
+/* Trace m at the fractional sample position u, linear between samples, zero
+ * outside the record. */
+static double trace_at(const double *x, int32_t nt, double u)
+{
+    if (!(u >= 0.0) || u > (double)(nt - 1)) return 0.0;
+    int32_t n = (int32_t)floor(u);
+    if (n >= nt - 1) return x[nt - 1];
+    double f = u - n;
+    return (1.0 - f) * x[n] + f * x[n + 1];
+}
+
+void orc_semblance(int32_t nrec, int32_t nt, const double *traces, double dt,
+                   const double *offset, int32_t np, double p0, double dp,
+                   int32_t ntau, int32_t tau_stride, int32_t win, double *coh,
+                   double *energy)
+{
+    for (int32_t j = 0; j < np; ++j) {
+        double p = p0 + j * dp;
+        for (int32_t i = 0; i < ntau; ++i) {
+            int32_t n0 = i * tau_stride;
+            double num = 0.0, den = 0.0;
+            for (int32_t n = n0; n < n0 + win; ++n) {
+                double stack = 0.0, energy = 0.0;
+                for (int32_t m = 0; m < nrec; ++m) {
+                    /* the arrival at receiver m comes p*offset_m later */
+                    double v = trace_at(traces + (int64_t)m * nt, nt, n + p * offset[m] / dt);
+                    stack += v;
+                    energy += v * v;
+                }
+                num += stack * stack;
+                den += energy;
+            }
+            coh[(int64_t)j * ntau + i] = den > 0.0 ? num / (nrec * den) : 0.0;
+            if (energy) energy[(int64_t)j * ntau + i] = den;
+        }
+    }
+}
+
+void orc_starting_model(int32_t NR, int32_t NZ, double dr, double a, double dist,
+                        const double *vp_wall, const double *vs_wall, const double *vp_far,
+                        const double *vs_far, double vp_fluid, double *vp, double *vs)
+{
+    for (int32_t i = 0; i < NR; ++i) {
+        double r = (i + 0.5) * dr;
+        for (int32_t k = 0; k < NZ; ++k) {
+            int64_t c = (int64_t)i * NZ + k;
+            if (r < a) {
+                vp[c] = vp_fluid;
+                vs[c] = 0.0;
+                continue;
+            }
+            double f = (r - a) / dist;
+            if (f > 1.0) f = 1.0;
+            vp[c] = vp_wall[k] + f * (vp_far[k] - vp_wall[k]);
+            vs[c] = vs_wall[k] + f * (vs_far[k] - vs_wall[k]);
+        }
+    }
+}

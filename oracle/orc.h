@@ -102,6 +102,30 @@ double orc_line_search(double J0, double J1, double gpg, double alpha1);
 /* Eq. 9-10 with one alpha chosen so that the largest change relative to the
  * largest modulus is eta (alpha_override > 0 uses that alpha instead), then a
  * velocity box clip.  Only mask cells change.  Returns alpha. */
+/* Semblance (slowness-time coherence) of an on-axis receiver array, the
+ * analysis the paper builds its starting models from (Introduction; Fig. 4).
+ * traces[m*nt + n]: receiver m at sample n; offset[m]: its axial distance
+ * from the array's first receiver (m); slownesses p0 + j dp (s/m),
+ * j < np; windows of win samples starting at sample i*tau_stride, i < ntau.
+ * coh[j*ntau + i] = sum_n (sum_m x_m(n + p off_m/dt))^2 /
+ *                   (nrec sum_n sum_m x_m(n + p off_m/dt)^2),
+ * traces interpolated linearly between samples and zero outside the record;
+ * 0 where the window holds no energy.  energy (nullable) receives the
+ * denominator sum_n sum_m x^2.  Pinned by plane waves (coherence 1 at their
+ * slowness) and by the formation velocities of modelled data. */
+void orc_semblance(int32_t nrec, int32_t nt, const double *traces, double dt,
+                   const double *offset, int32_t np, double p0, double dp,
+                   int32_t ntau, int32_t tau_stride, int32_t win, double *coh,
+                   double *energy);
+
+/* Starting model (Numerical Examples section): per axial row k, formation
+ * velocities vp_wall/vs_wall at the borehole wall r = a and vp_far/vs_far at
+ * r = a + dist, linear in r between and constant beyond; cells with
+ * r = (i + 1/2) dr < a are fluid (vp_fluid, vs = 0).  NR x NZ outputs. */
+void orc_starting_model(int32_t NR, int32_t NZ, double dr, double a, double dist,
+                        const double *vp_wall, const double *vs_wall, const double *vp_far,
+                        const double *vs_far, double vp_fluid, double *vp, double *vs);
+
 double orc_update(int64_t n, double *lam, double *mu, const double *rho,
                   const double *g_lam, const double *g_mu, const uint8_t *mask,
                   double eta, double alpha_override,

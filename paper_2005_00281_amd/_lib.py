@@ -79,7 +79,8 @@ EXPORTS = ["bhfwi_create", "bhfwi_destroy", "bhfwi_last_error", "bhfwi_sizes",
            "bhfwi_moduli", "bhfwi_moduli_grad", "bhfwi_velocities",
            "bhfwi_fwd_model", "bhfwi_misfit", "bhfwi_adjoint_model", "bhfwi_gradient",
            "bhfwi_precondition", "bhfwi_status", "bhfwi_line_search", "bhfwi_update", "bhfwi_plan_bytes",
-           "bhfwi_plan", "bhfwi_kernel_shapes"]
+           "bhfwi_plan", "bhfwi_kernel_shapes", "bhfwi_semblance", "bhfwi_semblance_pick",
+           "bhfwi_starting_model"]
 
 _lib = None
 
@@ -116,6 +117,9 @@ def load(path: str = LIB_PATH):
     L.bhfwi_line_search.argtypes = [P, V, P, P, P, P, P]
     L.bhfwi_status.argtypes = [P, V]
     L.bhfwi_kernel_shapes.argtypes = [P, C.POINTER(C.c_int32)]
+    L.bhfwi_semblance.argtypes = [V, I32, I32, I32, P, F, P, I32, F, F, I32, I32, I32, P, P]
+    L.bhfwi_semblance_pick.argtypes = [V, I32, I32, I32, P, F, F, P, F, F, F, P, P]
+    L.bhfwi_starting_model.argtypes = [V, I32, I32, F, F, F, P, P, P, P, F, P, P]
     L.bhfwi_plan_bytes.argtypes = [C.POINTER(Shot), I32, I32, C.POINTER(PlanBytes)]
     L.bhfwi_plan.argtypes = [C.POINTER(Shot), I32, I64, I32, I32, C.POINTER(C.c_int32),
                              C.POINTER(C.c_int32), C.POINTER(PlanInfo)]
@@ -175,6 +179,54 @@ def moduli_grad(vp, vs, rho, g_lam, g_mu):
     _check(load().bhfwi_moduli_grad(_stream(), vp.numel(), _f32(vp), _f32(vs), _f32(rho),
                                     _f32(g_lam), _f32(g_mu), _f32(g_vp), _f32(g_vs)))
     return g_vp, g_vs
+
+
+def semblance(traces, dt, offset, p0, dp, np_, tau_stride, ntau, win, energy=False):
+    """Slowness-time coherence (bhfwi_semblance) of gathers [G, nrec, nt] (or
+    one gather [nrec, nt]) with receiver offsets [G, nrec] (or [nrec]);
+    returns coh [G, np_, ntau] (and the window energies)."""
+    one = traces.dim() == 2
+    x = traces.unsqueeze(0) if one else traces
+    off = (offset.unsqueeze(0).expand(x.shape[0], -1).contiguous()
+           if offset.dim() == 1 and not one else offset)
+    G, nrec, nt = x.shape
+    coh = torch.empty((G, np_, ntau), dtype=torch.float32, device=x.device)
+    en = torch.empty_like(coh) if energy else None
+    _check(load().bhfwi_semblance(_stream(), G, nrec, nt, _f32(x.contiguous()), float(dt),
+                                  _f32(off.contiguous()), int(np_), float(p0), float(dp),
+                                  int(ntau), int(tau_stride), int(win), _f32(coh),
+                                  _f32(en) if en is not None else None))
+    if one:
+        coh = coh[0]
+        en = en[0] if en is not None else None
+    return (coh, en) if energy else coh
+
+
+def semblance_pick(coh, p0, dp, p_lo, p_hi, p_ref=None, ref_scale=1.0):
+    """Slowness of the largest coherence in [max(p_lo, ref_scale p_ref), p_hi]
+    per gather (bhfwi_semblance_pick): (p [G], coherence [G]) device tensors."""
+    c = coh.unsqueeze(0) if coh.dim() == 2 else coh
+    G, np_, ntau = c.shape
+    p = torch.empty(G, dtype=torch.float32, device=c.device)
+    cc = torch.empty_like(p)
+    _check(load().bhfwi_semblance_pick(_stream(), G, np_, ntau, _f32(c.contiguous()), float(p0),
+                                       float(dp), _f32(p_ref) if p_ref is not None else None,
+                                       float(ref_scale), float(p_lo), float(p_hi), _f32(p),
+                                       _f32(cc)))
+    return p, cc
+
+
+def starting_model(NR, NZ, dr, a, dist, vp_wall, vs_wall, vp_far, vs_far, vp_fluid):
+    """Velocities linear in radius from the wall values (per axial row, device
+    tensors of NZ) to the far values at a + dist (bhfwi_starting_model)."""
+    dev = vp_wall.device
+    vp = torch.empty((NR, NZ), dtype=torch.float32, device=dev)
+    vs = torch.empty_like(vp)
+    _check(load().bhfwi_starting_model(_stream(), int(NR), int(NZ), float(dr), float(a),
+                                       float(dist), _f32(vp_wall, NZ), _f32(vs_wall, NZ),
+                                       _f32(vp_far, NZ), _f32(vs_far, NZ), float(vp_fluid),
+                                       _f32(vp), _f32(vs)))
+    return vp, vs
 
 
 def velocities(lam, mu, rho, out=None):

@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "bhfwi_host.hip")
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("bhfwi_host.hip", "bhfwi_semblance.hip")]
 OUT = os.path.join(HERE, "libbhfwi.so")
 
 HIPCC_FLAGS = [
@@ -20,7 +20,7 @@ HIPCC_FLAGS = [
 
 def build(verbose: bool = False) -> str:
     tmp = OUT + ".tmp%d" % os.getpid()
-    cmd = ["hipcc"] + HIPCC_FLAGS + ["-o", tmp, SRC]
+    cmd = ["hipcc"] + HIPCC_FLAGS + ["-o", tmp] + SRCS
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

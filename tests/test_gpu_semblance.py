@@ -1,0 +1,113 @@
+"""Parity of the starting-model kernels (semblance, peak picking, radial
+interpolation) with the FP64 oracle, through the C-ABI.
+
+Coherence is compared where the window holds energy (at least 1e-6 of the
+gather's largest window energy: below that the ratio is round-off of round-off
+in either precision) to 1e-4 absolute; energies to 1e-4 relative.  Picks are
+the same slowness, or one whose oracle coherence is within 1e-4 of the
+oracle's maximum (adjacent slownesses can tie to FP32 rounding).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def ricker(t, f0):
+    a = (math.pi * f0 * t) ** 2
+    return (1 - 2 * a) * np.exp(-a)
+
+
+def gathers(nt=9000, dt=1e-6, nrec=13, sp=0.1524, seed=0):
+    """Three gathers: two plane arrivals; the same plus noise with receiver
+    gains; noise only."""
+    rng = np.random.default_rng(seed)
+    t = np.arange(nt) * dt
+    off = sp * np.arange(nrec)
+    g1 = np.stack([ricker(t - 0.8e-3 - off[m] / 4300, 11e3) +
+                   3 * ricker(t - 1.6e-3 - off[m] / 2450, 11e3) for m in range(nrec)])
+    g2 = g1 * rng.uniform(0.7, 1.3, (nrec, 1)) + 0.05 * rng.standard_normal((nrec, nt))
+    g3 = rng.standard_normal((nrec, nt))
+    return np.stack([g1, g2, g3]).astype(np.float32), off
+
+
+P0, DP, NP = 1.0e-4, 1.0e-6, 620
+
+
+def test_semblance_map_parity_chunked_and_batched():
+    import paper_2005_00281_amd as P
+    dev = _dev()
+    x, off = gathers()
+    stride, win = 7, 500
+    ntau = (x.shape[2] - win // 2) // stride  # the last windows run past the record
+    _say("semblance map", x.shape, ntau)
+    coh, en = P.semblance(torch.as_tensor(x, device=dev), 1e-6,
+                          torch.as_tensor(off, dtype=torch.float32, device=dev), P0, DP, NP,
+                          stride, ntau, win, energy=True)
+    coh, en = coh.cpu().numpy(), en.cpu().numpy()
+    for g in range(x.shape[0]):
+        co, eo = oracle.semblance(x[g], 1e-6, off.astype(np.float32), P0, DP, NP, stride, ntau,
+                                  win, return_energy=True)
+        m = eo >= 1e-6 * eo.max()
+        assert m.sum() > 0.5 * m.size
+        assert np.abs(coh[g][m] - co[m]).max() <= 1e-4
+        assert np.abs(en[g][m] - eo[m]).max() <= 1e-4 * eo.max()
+
+
+def test_semblance_pick_parity():
+    import paper_2005_00281_amd as P
+    dev = _dev()
+    x, off = gathers(seed=1)
+    stride, win = 10, 400
+    ntau = (x.shape[2] - win) // stride + 1
+    _say("semblance pick", x.shape)
+    coh = P.semblance(torch.as_tensor(x, device=dev), 1e-6,
+                      torch.as_tensor(off, dtype=torch.float32, device=dev), P0, DP, NP, stride,
+                      ntau, win)
+    # bands with edges half way between grid slownesses
+    lo_p, hi_p = P0 + 60.5 * DP, P0 + 300.5 * DP
+    pP, cP = P.semblance_pick(coh, P0, DP, lo_p, hi_p)
+    pS, cS = P.semblance_pick(coh, P0, DP, 0.0, P0 + 560.5 * DP, p_ref=pP, ref_scale=1.4)
+    pP, pS = pP.cpu().numpy(), pS.cpu().numpy()
+    for g in range(2):
+        co = oracle.semblance(x[g], 1e-6, off.astype(np.float32), P0, DP, NP, stride, ntau, win)
+        po, c_o = oracle.pick_slowness(co, P0, DP, lo_p, hi_p)
+        rowmax = co.max(axis=1)
+        for pg, ref in ((pP[g], po), (pS[g], None)):
+            if ref is None:  # S band above 1.4 x the oracle's P pick
+                ref, _ = oracle.pick_slowness(co, P0, DP, 1.4 * po, P0 + 560.5 * DP)
+            jg, jo = int(round((pg - P0) / DP)), int(round((ref - P0) / DP))
+            assert jg == jo or rowmax[jg] >= rowmax[jo] - 1e-4, (g, pg, ref)
+        assert abs(pP[g] - 1 / 4300) <= DP and abs(pS[g] - 1 / 2450) <= DP
+
+
+def test_starting_model_parity():
+    import paper_2005_00281_amd as P
+    dev = _dev()
+    NR, NZ, dr = 260, 75, 5e-3
+    rng = np.random.default_rng(2)
+    rows = [rng.uniform(a, b, NZ) for a, b in ((2800, 3300), (1500, 1900), (3800, 4400),
+                                                (2100, 2500))]
+    _say("starting model", NR, NZ)
+    vp, vs = P.starting_model(NR, NZ, dr, 0.1, 1.0,
+                              *[torch.as_tensor(r, dtype=torch.float32, device=dev) for r in rows],
+                              1500.0)
+    vpo, vso = oracle.starting_model(NR, NZ, dr, 0.1, 1.0, *[r.astype(np.float32) for r in rows],
+                                     1500.0)
+    assert np.abs(vp.cpu().numpy() - vpo).max() <= 1e-6 * vpo.max()
+    assert np.abs(vs.cpu().numpy() - vso).max() <= 1e-6 * vpo.max()
