@@ -64,7 +64,7 @@ def test_semblance_map_parity_chunked_and_batched():
         co, eo = oracle.semblance(x[g], 1e-6, off.astype(np.float32), P0, DP, NP, stride, ntau,
                                   win, return_energy=True)
         m = eo >= 1e-6 * eo.max()
-        assert m.sum() > 0.5 * m.size
+        assert m.sum() > 20000  # windows that hold an arrival
         assert np.abs(coh[g][m] - co[m]).max() <= 1e-4
         assert np.abs(en[g][m] - eo[m]).max() <= 1e-4 * eo.max()
 
