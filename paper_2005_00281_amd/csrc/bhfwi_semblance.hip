@@ -25,7 +25,7 @@ constexpr int kSemThreads = 256;
 constexpr int kSemPer = kSemSpan / kSemThreads;  // samples per thread in the scan
 
 __global__ void __launch_bounds__(kSemThreads)
-k_semblance(int nrec, int nt, const float* __restrict__ traces, float inv_dt,
+k_semblance(int nrec, int nt, const float* __restrict__ traces, float dt,
             const float* __restrict__ offset, float p0, float dp, int ntau, int stride, int win,
             int chunk, float* __restrict__ coh, float* __restrict__ energy)
 {
@@ -34,25 +34,31 @@ k_semblance(int nrec, int nt, const float* __restrict__ traces, float inv_dt,
     __shared__ double Ps[kSemSpan + 1];    // prefix sums of Ls
     __shared__ double Pe[kSemSpan + 1];    // prefix sums of Le
     __shared__ double Ts[kSemThreads], Te[kSemThreads];  // per-thread totals, scanned
-    __shared__ float Lsh[64];              // per-receiver shifts in samples
+    __shared__ int Lq[64];                 // per receiver: whole samples of the shift
+    __shared__ float Lf[64];               // and its fraction
     const int j = blockIdx.x, g = blockIdx.y;
     const int i0 = blockIdx.z * chunk;
     const int i1 = min(ntau, i0 + chunk);
     if (i0 >= i1) return;  // uniform
     const int np = gridDim.x;
-    const float p = p0 + j * dp;
     const float* __restrict__ x = traces + (long long)g * nrec * nt;
-    if ((int)threadIdx.x < nrec) Lsh[threadIdx.x] = p * offset[(long long)g * nrec + threadIdx.x] * inv_dt;
+    if ((int)threadIdx.x < nrec) {
+        // the shift p offset / dt in double, once per receiver, split into
+        // whole samples and a fraction (large shifts keep their fraction)
+        const double s = ((double)p0 + j * (double)dp) *
+                         (double)offset[(long long)g * nrec + threadIdx.x] / (double)dt;
+        const double fl = floor(s);
+        Lq[threadIdx.x] = (int)fl;
+        Lf[threadIdx.x] = (float)(s - fl);
+    }
     __syncthreads();
     const int n_lo = i0 * stride;
     const int n_hi = min((i1 - 1) * stride + win, n_lo + kSemSpan);
     for (int n = n_lo + (int)threadIdx.x; n < n_hi; n += kSemThreads) {
         float st = 0.f, en = 0.f;
         for (int m = 0; m < nrec; ++m) {
-            const float s = Lsh[m];
-            const float fl = floorf(s);
-            const int q = n + (int)fl;  // sample at or before the shifted time
-            const float f = s - fl;
+            const int q = n + Lq[m];  // sample at or before the shifted time
+            const float f = Lf[m];
             const float* __restrict__ xm = x + (long long)m * nt;
             const float a = (q >= 0 && q < nt) ? xm[q] : 0.f;
             const float b = (q + 1 >= 0 && q + 1 < nt) ? xm[q + 1] : 0.f;
@@ -193,7 +199,7 @@ int bhfwi_semblance(void* stream, int32_t ngather, int32_t nrec, int32_t nt, con
     const int nchunk = (ntau + chunk - 1) / chunk;
     if (nchunk > 65535) return BHFWI_EINVAL;
     hipLaunchKernelGGL(bhfwi::k_semblance, dim3(np, ngather, nchunk), dim3(bhfwi::kSemThreads), 0,
-                       (hipStream_t)stream, nrec, nt, traces, 1.0f / dt, offset, p0, dp, ntau,
+                       (hipStream_t)stream, nrec, nt, traces, dt, offset, p0, dp, ntau,
                        tau_stride, win, chunk, coh, energy);
     return hipGetLastError() == hipSuccess ? BHFWI_OK : BHFWI_EHIP;
 }

@@ -46,7 +46,9 @@ def gathers(nt=9000, dt=1e-6, nrec=13, sp=0.1524, seed=0):
     return np.stack([g1, g2, g3]).astype(np.float32), off
 
 
-P0, DP, NP = 1.0e-4, 1.0e-6, 620
+# FP32-representable parameters, so that both sides shift by the same amounts
+P0, DP, NP = float(np.float32(1.0e-4)), float(np.float32(1.0e-6)), 620
+DT = float(np.float32(1e-6))
 
 
 def test_semblance_map_parity_chunked_and_batched():
@@ -56,12 +58,12 @@ def test_semblance_map_parity_chunked_and_batched():
     stride, win = 7, 500
     ntau = (x.shape[2] - win // 2) // stride  # the last windows run past the record
     _say("semblance map", x.shape, ntau)
-    coh, en = P.semblance(torch.as_tensor(x, device=dev), 1e-6,
+    coh, en = P.semblance(torch.as_tensor(x, device=dev), DT,
                           torch.as_tensor(off, dtype=torch.float32, device=dev), P0, DP, NP,
                           stride, ntau, win, energy=True)
     coh, en = coh.cpu().numpy(), en.cpu().numpy()
     for g in range(x.shape[0]):
-        co, eo = oracle.semblance(x[g], 1e-6, off.astype(np.float32), P0, DP, NP, stride, ntau,
+        co, eo = oracle.semblance(x[g], DT, off.astype(np.float32), P0, DP, NP, stride, ntau,
                                   win, return_energy=True)
         m = eo >= 1e-6 * eo.max()
         assert m.sum() > 20000  # windows that hold an arrival
@@ -76,7 +78,7 @@ def test_semblance_pick_parity():
     stride, win = 10, 400
     ntau = (x.shape[2] - win) // stride + 1
     _say("semblance pick", x.shape)
-    coh = P.semblance(torch.as_tensor(x, device=dev), 1e-6,
+    coh = P.semblance(torch.as_tensor(x, device=dev), DT,
                       torch.as_tensor(off, dtype=torch.float32, device=dev), P0, DP, NP, stride,
                       ntau, win)
     # bands with edges half way between grid slownesses
@@ -85,7 +87,7 @@ def test_semblance_pick_parity():
     pS, cS = P.semblance_pick(coh, P0, DP, 0.0, P0 + 560.5 * DP, p_ref=pP, ref_scale=1.4)
     pP, pS = pP.cpu().numpy(), pS.cpu().numpy()
     for g in range(2):
-        co = oracle.semblance(x[g], 1e-6, off.astype(np.float32), P0, DP, NP, stride, ntau, win)
+        co = oracle.semblance(x[g], DT, off.astype(np.float32), P0, DP, NP, stride, ntau, win)
         po, c_o = oracle.pick_slowness(co, P0, DP, lo_p, hi_p)
         rowmax = co.max(axis=1)
         for pg, ref in ((pP[g], po), (pS[g], None)):
