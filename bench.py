@@ -163,14 +163,15 @@ def semblance_bench(steps):
             x[g, m] = (1 - 2 * a) * np.exp(-a) + 3 * (1 - 2 * b) * np.exp(-b)
     xt = torch.as_tensor(x, device=dev)
     ot = torch.as_tensor(np.tile(off, (G, 1)), dtype=torch.float32, device=dev)
-    P.semblance(xt, dt, ot, p0, dp, npp, stride, ntau, win)
+    P.semblance(xt, dt, ot, p0, dp, npp, stride, ntau, win, energy=True)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(steps):
-        coh = P.semblance(xt, dt, ot, p0, dp, npp, stride, ntau, win)
-        pP, _ = P.semblance_pick(coh, p0, dp, 1 / 6000, 1 / 2000)
-        pS, _ = P.semblance_pick(coh, p0, dp, 0.0, 0.999 / 1500, p_ref=pP, ref_scale=1.4)
+        coh, en = P.semblance(xt, dt, ot, p0, dp, npp, stride, ntau, win, energy=True)
+        pP, _ = P.semblance_pick(coh, p0, dp, 1 / 6000, 1 / 2000, energy=en, rel_floor=1e-6)
+        pS, _ = P.semblance_pick(coh, p0, dp, 0.0, 0.999 / 1500, p_ref=pP, ref_scale=1.4,
+                                 energy=en, rel_floor=1e-6)
     e1.record()
     e1.synchronize()
     ms = e0.elapsed_time(e1) / steps

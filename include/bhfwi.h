@@ -229,20 +229,23 @@ int bhfwi_kernel_times(bhfwi_ctx *ctx, bhfwi_kernel_times_t *out, int32_t reset)
  * between samples and zero outside its record; 0 for a window without
  * energy.  energy (nullable, same shape) receives the window energy
  * sum_window sum_m x_m^2.
- * FP32 data and products, window sums as differences of prefix sums in
- * double.  Returns BHFWI_EINVAL on bad sizes. */
+ * FP32 data and interpolation, stack, energy and window sums in double
+ * (window sums as differences of prefix sums).  Returns BHFWI_EINVAL on bad sizes. */
 int bhfwi_semblance(void *stream, int32_t ngather, int32_t nrec, int32_t nt,
                     const float *traces, float dt, const float *offset, int32_t np, float p0,
                     float dp, int32_t ntau, int32_t tau_stride, int32_t win, float *coh,
                     float *energy);
-/* Per gather, the slowness of the largest coherence over all windows among
- * slownesses in [lo, p_hi], lo = max(p_lo, ref_scale * p_ref[g]) when p_ref
- * (device, ngather) is given (e.g. the S band above a multiple of the picked
- * P slowness); ties go to the smaller slowness.  p_out, c_out: device,
- * ngather floats (0 and 0 if the band holds no slowness). */
+/* Per gather, the slowness of the largest coherence among slownesses in
+ * [lo, p_hi], lo = max(p_lo, ref_scale * p_ref[g]) when p_ref (device,
+ * ngather) is given (e.g. the S band above a multiple of the picked P
+ * slowness), over the windows whose energy (the map bhfwi_semblance writes;
+ * nullable: all windows) is at least rel_floor times the gather's largest;
+ * ties go to the smaller slowness.  p_out, c_out: device, ngather floats (0
+ * and 0 if the band holds no slowness). */
 int bhfwi_semblance_pick(void *stream, int32_t ngather, int32_t np, int32_t ntau,
-                         const float *coh, float p0, float dp, const float *p_ref,
-                         float ref_scale, float p_lo, float p_hi, float *p_out, float *c_out);
+                         const float *coh, const float *energy, float rel_floor, float p0,
+                         float dp, const float *p_ref, float ref_scale, float p_lo, float p_hi,
+                         float *p_out, float *c_out);
 /* Starting velocities on an NR x NZ grid (device): per axial row k, the wall
  * values vp_wall[k], vs_wall[k] at r = a, the far values vp_far[k],
  * vs_far[k] at r = a + dist, linear in r = (i + 1/2) dr between and constant

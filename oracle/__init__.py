@@ -269,10 +269,14 @@ def semblance(traces, dt, offset, p0, dp, np_, tau_stride, ntau, win, return_ene
     return (coh, en) if return_energy else coh
 
 
-def pick_slowness(coh, p0, dp, p_lo, p_hi):
-    """The slowness of the largest coherence among slownesses in [p_lo, p_hi]
-    (all window times): (p, coherence)."""
-    c = np.asarray(coh)
+def pick_slowness(coh, p0, dp, p_lo, p_hi, energy=None, rel_floor=0.0):
+    """The slowness of the largest coherence among slownesses in [p_lo, p_hi],
+    over the windows whose energy is at least rel_floor times the largest
+    window energy (all windows without energy): (p, coherence)."""
+    c = np.asarray(coh, np.float64)
+    if energy is not None:
+        e = np.asarray(energy)
+        c = np.where(e >= rel_floor * e.max(), c, -1.0)
     p = p0 + dp * np.arange(c.shape[0])
     band = (p >= p_lo) & (p <= p_hi)
     best = c[band].max(axis=1)

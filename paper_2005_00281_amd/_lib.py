@@ -118,7 +118,7 @@ def load(path: str = LIB_PATH):
     L.bhfwi_status.argtypes = [P, V]
     L.bhfwi_kernel_shapes.argtypes = [P, C.POINTER(C.c_int32)]
     L.bhfwi_semblance.argtypes = [V, I32, I32, I32, P, F, P, I32, F, F, I32, I32, I32, P, P]
-    L.bhfwi_semblance_pick.argtypes = [V, I32, I32, I32, P, F, F, P, F, F, F, P, P]
+    L.bhfwi_semblance_pick.argtypes = [V, I32, I32, I32, P, P, F, F, F, P, F, F, F, P, P]
     L.bhfwi_starting_model.argtypes = [V, I32, I32, F, F, F, P, P, P, P, F, P, P]
     L.bhfwi_plan_bytes.argtypes = [C.POINTER(Shot), I32, I32, C.POINTER(PlanBytes)]
     L.bhfwi_plan.argtypes = [C.POINTER(Shot), I32, I64, I32, I32, C.POINTER(C.c_int32),
@@ -202,15 +202,20 @@ def semblance(traces, dt, offset, p0, dp, np_, tau_stride, ntau, win, energy=Fal
     return (coh, en) if energy else coh
 
 
-def semblance_pick(coh, p0, dp, p_lo, p_hi, p_ref=None, ref_scale=1.0):
+def semblance_pick(coh, p0, dp, p_lo, p_hi, p_ref=None, ref_scale=1.0, energy=None,
+                   rel_floor=0.0):
     """Slowness of the largest coherence in [max(p_lo, ref_scale p_ref), p_hi]
-    per gather (bhfwi_semblance_pick): (p [G], coherence [G]) device tensors."""
+    over windows with energy >= rel_floor x the gather's largest, per gather
+    (bhfwi_semblance_pick): (p [G], coherence [G]) device tensors."""
     c = coh.unsqueeze(0) if coh.dim() == 2 else coh
+    e = None if energy is None else (energy.unsqueeze(0) if energy.dim() == 2 else energy)
     G, np_, ntau = c.shape
     p = torch.empty(G, dtype=torch.float32, device=c.device)
     cc = torch.empty_like(p)
-    _check(load().bhfwi_semblance_pick(_stream(), G, np_, ntau, _f32(c.contiguous()), float(p0),
-                                       float(dp), _f32(p_ref) if p_ref is not None else None,
+    _check(load().bhfwi_semblance_pick(_stream(), G, np_, ntau, _f32(c.contiguous()),
+                                       _f32(e.contiguous()) if e is not None else None,
+                                       float(rel_floor), float(p0), float(dp),
+                                       _f32(p_ref) if p_ref is not None else None,
                                        float(ref_scale), float(p_lo), float(p_hi), _f32(p),
                                        _f32(cc)))
     return p, cc

@@ -7,9 +7,9 @@
 // first forms, for every sample of the chunk's time range, the squared stack
 // of the moveout-corrected receivers and their energy (receiver m read
 // p*offset_m/dt samples later, linearly interpolated, zero outside the
-// record) into LDS, turns both series into prefix sums in double (a
-// workgroup scan), and then takes every window's sums as a difference of two
-// prefix values.  The time range of a chunk is at most kSemSpan samples, so
+// record; accumulated in double) into LDS, turns both series into prefix
+// sums in place (a workgroup scan), and then takes every window's sums as a
+// difference of two prefix values.  The time range of a chunk is at most kSemSpan samples, so
 // the LDS footprint does not depend on the record length.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -29,10 +29,10 @@ k_semblance(int nrec, int nt, const float* __restrict__ traces, float dt,
             const float* __restrict__ offset, float p0, float dp, int ntau, int stride, int win,
             int chunk, float* __restrict__ coh, float* __restrict__ energy)
 {
-    __shared__ float Ls[kSemSpan];         // stack^2
-    __shared__ float Le[kSemSpan];         // energy
-    __shared__ double Ps[kSemSpan + 1];    // prefix sums of Ls
-    __shared__ double Pe[kSemSpan + 1];    // prefix sums of Le
+    // Ps[k], Pe[k]: first the squared stack and the energy of sample
+    // n_lo + k - 1, then (in place) their prefix sums over samples < n_lo + k
+    __shared__ double Ps[kSemSpan + 1];
+    __shared__ double Pe[kSemSpan + 1];
     __shared__ double Ts[kSemThreads], Te[kSemThreads];  // per-thread totals, scanned
     __shared__ int Lq[64];                 // per receiver: whole samples of the shift
     __shared__ float Lf[64];               // and its fraction
@@ -54,8 +54,9 @@ k_semblance(int nrec, int nt, const float* __restrict__ traces, float dt,
     __syncthreads();
     const int n_lo = i0 * stride;
     const int n_hi = min((i1 - 1) * stride + win, n_lo + kSemSpan);
+    const int len = n_hi - n_lo;
     for (int n = n_lo + (int)threadIdx.x; n < n_hi; n += kSemThreads) {
-        float st = 0.f, en = 0.f;
+        double st = 0.0, en = 0.0;
         for (int m = 0; m < nrec; ++m) {
             const int q = n + Lq[m];  // sample at or before the shifted time
             const float f = Lf[m];
@@ -66,20 +67,21 @@ k_semblance(int nrec, int nt, const float* __restrict__ traces, float dt,
             float v = 0.f;
             if (q >= 0 && (q < nt - 1 || (q == nt - 1 && f == 0.f))) v = a + f * (b - a);
             st += v;
-            en += v * v;
+            en += (double)v * v;
         }
-        Ls[n - n_lo] = st * st;
-        Le[n - n_lo] = en;
+        Ps[n - n_lo + 1] = st * st;
+        Pe[n - n_lo + 1] = en;
     }
     __syncthreads();
     // prefix sums: each thread totals kSemPer consecutive samples, the totals
-    // are scanned (Hillis-Steele), then each thread writes its running sums
-    const int len = n_hi - n_lo, t0 = threadIdx.x * kSemPer;
+    // are scanned (Hillis-Steele), then each thread turns its own samples
+    // into running sums
+    const int t0 = threadIdx.x * kSemPer + 1;
     double ts = 0.0, te = 0.0;
     for (int q = 0; q < kSemPer; ++q)
-        if (t0 + q < len) {
-            ts += Ls[t0 + q];
-            te += Le[t0 + q];
+        if (t0 + q <= len) {
+            ts += Ps[t0 + q];
+            te += Pe[t0 + q];
         }
     Ts[threadIdx.x] = ts;
     Te[threadIdx.x] = te;
@@ -93,17 +95,17 @@ k_semblance(int nrec, int nt, const float* __restrict__ traces, float dt,
         __syncthreads();
     }
     double rs = Ts[threadIdx.x] - ts, re = Te[threadIdx.x] - te;  // exclusive
+    for (int q = 0; q < kSemPer; ++q)
+        if (t0 + q <= len) {
+            rs += Ps[t0 + q];
+            re += Pe[t0 + q];
+            Ps[t0 + q] = rs;
+            Pe[t0 + q] = re;
+        }
     if (threadIdx.x == 0) {
         Ps[0] = 0.0;
         Pe[0] = 0.0;
     }
-    for (int q = 0; q < kSemPer; ++q)
-        if (t0 + q < len) {
-            rs += Ls[t0 + q];
-            re += Le[t0 + q];
-            Ps[t0 + q + 1] = rs;
-            Pe[t0 + q + 1] = re;
-        }
     __syncthreads();
     for (int i = i0 + (int)threadIdx.x; i < i1; i += kSemThreads) {
         const int a0 = i * stride - n_lo;
@@ -115,25 +117,45 @@ k_semblance(int nrec, int nt, const float* __restrict__ traces, float dt,
 }
 
 // Largest coherence over the slownesses of [lo, hi] (lo raised to
-// ref_scale * p_ref[g] when p_ref is given) and all windows; ties go to the
-// smaller slowness.  One workgroup per gather.
+// ref_scale * p_ref[g] when p_ref is given) and the windows whose energy is
+// at least rel_floor times the gather's largest window energy (all windows
+// when energy is null); ties go to the smaller slowness.  One workgroup per
+// gather.
 __global__ void __launch_bounds__(kSemThreads)
-k_semblance_pick(int np, int ntau, const float* __restrict__ coh, float p0, float dp,
+k_semblance_pick(int np, int ntau, const float* __restrict__ coh,
+                 const float* __restrict__ energy, float rel_floor, float p0, float dp,
                  const float* __restrict__ p_ref, float ref_scale, float lo, float hi,
                  float* __restrict__ p_out, float* __restrict__ c_out)
 {
     __shared__ float Sc[kSemThreads];
     __shared__ int Sj[kSemThreads];
     const int g = blockIdx.x;
+    const long long base = (long long)g * np * ntau;
+    float floor_e = 0.f;
+    if (energy) {
+        float m = 0.f;
+        for (long long q = threadIdx.x; q < (long long)np * ntau; q += kSemThreads)
+            m = fmaxf(m, energy[base + q]);
+        Sc[threadIdx.x] = m;
+        __syncthreads();
+        for (int o = kSemThreads / 2; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) Sc[threadIdx.x] = fmaxf(Sc[threadIdx.x], Sc[threadIdx.x + o]);
+            __syncthreads();
+        }
+        floor_e = rel_floor * Sc[0];
+        __syncthreads();
+    }
     const float l = p_ref ? fmaxf(lo, ref_scale * p_ref[g]) : lo;
     float best = -1.f;
     int bj = np;
     for (int j = threadIdx.x; j < np; j += kSemThreads) {
         const float p = p0 + j * dp;
         if (p < l || p > hi) continue;
-        const float* __restrict__ c = coh + ((long long)g * np + j) * ntau;
+        const float* __restrict__ c = coh + base + (long long)j * ntau;
+        const float* __restrict__ e = energy ? energy + base + (long long)j * ntau : nullptr;
         float m = -1.f;
-        for (int i = 0; i < ntau; ++i) m = fmaxf(m, c[i]);
+        for (int i = 0; i < ntau; ++i)
+            if (!e || e[i] >= floor_e) m = fmaxf(m, c[i]);
         if (m > best) {
             best = m;
             bj = j;
@@ -205,14 +227,16 @@ int bhfwi_semblance(void* stream, int32_t ngather, int32_t nrec, int32_t nt, con
 }
 
 int bhfwi_semblance_pick(void* stream, int32_t ngather, int32_t np, int32_t ntau,
-                         const float* coh, float p0, float dp, const float* p_ref,
-                         float ref_scale, float p_lo, float p_hi, float* p_out, float* c_out)
+                         const float* coh, const float* energy, float rel_floor, float p0,
+                         float dp, const float* p_ref, float ref_scale, float p_lo, float p_hi,
+                         float* p_out, float* c_out)
 {
-    if (ngather < 1 || np < 1 || ntau < 1 || !coh || !p_out || !c_out || !(p_hi >= p_lo))
+    if (ngather < 1 || np < 1 || ntau < 1 || !coh || !p_out || !c_out || !(p_hi >= p_lo) ||
+        !(rel_floor >= 0.f))
         return BHFWI_EINVAL;
     hipLaunchKernelGGL(bhfwi::k_semblance_pick, dim3(ngather), dim3(bhfwi::kSemThreads), 0,
-                       (hipStream_t)stream, np, ntau, coh, p0, dp, p_ref, ref_scale, p_lo, p_hi,
-                       p_out, c_out);
+                       (hipStream_t)stream, np, ntau, coh, energy, rel_floor, p0, dp, p_ref,
+                       ref_scale, p_lo, p_hi, p_out, c_out);
     return hipGetLastError() == hipSuccess ? BHFWI_OK : BHFWI_EHIP;
 }
 

@@ -78,21 +78,25 @@ def test_semblance_pick_parity():
     stride, win = 10, 400
     ntau = (x.shape[2] - win) // stride + 1
     _say("semblance pick", x.shape)
-    coh = P.semblance(torch.as_tensor(x, device=dev), DT,
-                      torch.as_tensor(off, dtype=torch.float32, device=dev), P0, DP, NP, stride,
-                      ntau, win)
-    # bands with edges half way between grid slownesses
-    lo_p, hi_p = P0 + 60.5 * DP, P0 + 300.5 * DP
-    pP, cP = P.semblance_pick(coh, P0, DP, lo_p, hi_p)
-    pS, cS = P.semblance_pick(coh, P0, DP, 0.0, P0 + 560.5 * DP, p_ref=pP, ref_scale=1.4)
+    coh, en = P.semblance(torch.as_tensor(x, device=dev), DT,
+                          torch.as_tensor(off, dtype=torch.float32, device=dev), P0, DP, NP,
+                          stride, ntau, win, energy=True)
+    # bands with edges half way between grid slownesses; windows with at
+    # least 1e-6 of the largest window energy
+    lo_p, hi_p, fl = P0 + 60.5 * DP, P0 + 300.5 * DP, 1e-6
+    pP, cP = P.semblance_pick(coh, P0, DP, lo_p, hi_p, energy=en, rel_floor=fl)
+    pS, cS = P.semblance_pick(coh, P0, DP, 0.0, P0 + 560.5 * DP, p_ref=pP, ref_scale=1.4,
+                              energy=en, rel_floor=fl)
     pP, pS = pP.cpu().numpy(), pS.cpu().numpy()
     for g in range(2):
-        co = oracle.semblance(x[g], DT, off.astype(np.float32), P0, DP, NP, stride, ntau, win)
-        po, c_o = oracle.pick_slowness(co, P0, DP, lo_p, hi_p)
-        rowmax = co.max(axis=1)
+        co, eo = oracle.semblance(x[g], DT, off.astype(np.float32), P0, DP, NP, stride, ntau,
+                                  win, return_energy=True)
+        po, c_o = oracle.pick_slowness(co, P0, DP, lo_p, hi_p, energy=eo, rel_floor=fl)
+        rowmax = np.where(eo >= fl * eo.max(), co, -1.0).max(axis=1)
         for pg, ref in ((pP[g], po), (pS[g], None)):
             if ref is None:  # S band above 1.4 x the oracle's P pick
-                ref, _ = oracle.pick_slowness(co, P0, DP, 1.4 * po, P0 + 560.5 * DP)
+                ref, _ = oracle.pick_slowness(co, P0, DP, 1.4 * po, P0 + 560.5 * DP, energy=eo,
+                                              rel_floor=fl)
             jg, jo = int(round((pg - P0) / DP)), int(round((ref - P0) / DP))
             assert jg == jo or rowmax[jg] >= rowmax[jo] - 1e-4, (g, pg, ref)
         assert abs(pP[g] - 1 / 4300) <= DP and abs(pS[g] - 1 / 2450) <= DP

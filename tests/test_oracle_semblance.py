@@ -80,6 +80,23 @@ def test_two_arrivals_are_picked_in_their_bands():
     assert abs(pS - 1 / 2400) <= 0.5e-6 + 1e-12
 
 
+def test_energy_floor_ignores_faint_windows():
+    """A faint early arrival (1e-4 amplitude) is perfectly coherent; with an
+    energy floor of 1e-6 of the largest window energy the pick is the strong
+    arrival's slowness instead."""
+    dt, sp = 1e-6, 0.1524
+    faint, off = plane_wave(13, 4000, dt, sp, 1 / 5000, 0.4e-3, 12e3, amp=np.full(13, 1e-4))
+    strong, _ = plane_wave(13, 4000, dt, sp, 1 / 3500, 1.5e-3, 12e3)
+    rng = np.random.default_rng(3)
+    x = faint + strong * rng.uniform(0.5, 1.5, (13, 1)) + 1e-8 * rng.standard_normal((13, 4000))
+    coh, en = oracle.semblance(x, dt, off, 1e-4, 1e-6, 400, 10, 360, 300, return_energy=True)
+    p_all, _ = oracle.pick_slowness(coh, 1e-4, 1e-6, 1 / 6000, 1 / 3000)
+    p_floor, _ = oracle.pick_slowness(coh, 1e-4, 1e-6, 1 / 6000, 1 / 3000, energy=en,
+                                      rel_floor=1e-6)
+    assert abs(p_all - 1 / 5000) <= 0.5e-6 + 1e-12
+    assert abs(p_floor - 1 / 3500) <= 0.5e-6 + 1e-12
+
+
 def test_starting_model_is_linear_in_radius():
     NR, NZ, dr, a, dist = 300, 3, 5e-3, 0.1, 1.0
     vp, vs = oracle.starting_model(NR, NZ, dr, a, dist, [3000, 3100, 3200], 1700,
@@ -108,8 +125,9 @@ def test_modelled_borehole_waveforms_give_the_formation_velocities():
     off = (np.asarray(sh.rec_k) - sh.rec_k[0]) * sh.dz
     win = int(round(0.15e-3 / sh.dt))
     p0, dp, stride = 1.5e-4, 1e-6, 10
-    coh = oracle.semblance(d, sh.dt, off, p0, dp, 560, stride, (sh.nt - win) // stride + 1, win)
-    pP, _ = oracle.pick_slowness(coh, p0, dp, 1 / 6000, 1 / 2000)
-    pS, _ = oracle.pick_slowness(coh, p0, dp, 1.4 * pP, 0.999 / 1500)
+    coh, en = oracle.semblance(d, sh.dt, off, p0, dp, 560, stride, (sh.nt - win) // stride + 1,
+                               win, return_energy=True)
+    pP, _ = oracle.pick_slowness(coh, p0, dp, 1 / 6000, 1 / 2000, energy=en, rel_floor=1e-6)
+    pS, _ = oracle.pick_slowness(coh, p0, dp, 1.4 * pP, 0.999 / 1500, energy=en, rel_floor=1e-6)
     assert abs(1 / pP - 4000) / 4000 < 0.015, 1 / pP
     assert abs(1 / pS - 2300) / 2300 < 0.03, 1 / pS
