@@ -136,7 +136,8 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 def semblance_bench(steps):
     """Starting-model stage at the 128-shot workload's scale: the slowness-time
-    coherence of 128 gathers of 13 receivers x 16000 samples (0.25 us), 560
+    coherence of 128 gathers of 13 receivers x 16000 samples (0.25 us; a P
+    and a weaker S plane arrival, Vp/Vs in [1.6, 1.9], in noise), 560
     slownesses of 1 us/m from 150 us/m, 150 us windows every 10 samples, and
     the P and S picks.  Work model per (gather, slowness, staged sample): 13
     interpolated reads at 5 FP32 operations each (shift split, two loads
@@ -155,12 +156,14 @@ def semblance_bench(steps):
     x = np.empty((G, M, nt), np.float32)
     true_p, true_s = np.empty(G), np.empty(G)
     for g in range(G):
-        sp, ss = 1 / rng.uniform(3000, 5500), 1 / rng.uniform(1700, 3000)
+        vp = rng.uniform(3000, 5500)
+        sp, ss = 1 / vp, rng.uniform(1.6, 1.9) / vp
         true_p[g], true_s[g] = sp, ss
         for m in range(M):
             a = (np.pi * 8e3 * (t - 1e-3 - sp * off[m])) ** 2
             b = (np.pi * 8e3 * (t - 2e-3 - ss * off[m])) ** 2
-            x[g, m] = (1 - 2 * a) * np.exp(-a) + 3 * (1 - 2 * b) * np.exp(-b)
+            x[g, m] = (3 * (1 - 2 * a) * np.exp(-a) + (1 - 2 * b) * np.exp(-b) +
+                       0.05 * rng.standard_normal(nt))
     xt = torch.as_tensor(x, device=dev)
     ot = torch.as_tensor(np.tile(off, (G, 1)), dtype=torch.float32, device=dev)
     P.semblance(xt, dt, ot, p0, dp, npp, stride, ntau, win, energy=True)

@@ -240,12 +240,14 @@ int bhfwi_semblance(void *stream, int32_t ngather, int32_t nrec, int32_t nt,
  * ngather) is given (e.g. the S band above a multiple of the picked P
  * slowness), over the windows whose energy (the map bhfwi_semblance writes;
  * nullable: all windows) is at least rel_floor times the gather's largest;
- * ties go to the smaller slowness.  p_out, c_out: device, ngather floats (0
- * and 0 if the band holds no slowness). */
+ * ties go to the smaller slowness.  proj (device, [ngather][np], written):
+ * per slowness the largest coherence over those windows (-1 if none), the
+ * coherence-versus-slowness projection.  p_out, c_out: device, ngather
+ * floats (0 and 0 if the band holds no slowness). */
 int bhfwi_semblance_pick(void *stream, int32_t ngather, int32_t np, int32_t ntau,
                          const float *coh, const float *energy, float rel_floor, float p0,
                          float dp, const float *p_ref, float ref_scale, float p_lo, float p_hi,
-                         float *p_out, float *c_out);
+                         float *proj, float *p_out, float *c_out);
 /* Starting velocities on an NR x NZ grid (device): per axial row k, the wall
  * values vp_wall[k], vs_wall[k] at r = a, the far values vp_far[k],
  * vs_far[k] at r = a + dist, linear in r = (i + 1/2) dr between and constant

@@ -118,7 +118,7 @@ def load(path: str = LIB_PATH):
     L.bhfwi_status.argtypes = [P, V]
     L.bhfwi_kernel_shapes.argtypes = [P, C.POINTER(C.c_int32)]
     L.bhfwi_semblance.argtypes = [V, I32, I32, I32, P, F, P, I32, F, F, I32, I32, I32, P, P]
-    L.bhfwi_semblance_pick.argtypes = [V, I32, I32, I32, P, P, F, F, F, P, F, F, F, P, P]
+    L.bhfwi_semblance_pick.argtypes = [V, I32, I32, I32, P, P, F, F, F, P, F, F, F, P, P, P]
     L.bhfwi_starting_model.argtypes = [V, I32, I32, F, F, F, P, P, P, P, F, P, P]
     L.bhfwi_plan_bytes.argtypes = [C.POINTER(Shot), I32, I32, C.POINTER(PlanBytes)]
     L.bhfwi_plan.argtypes = [C.POINTER(Shot), I32, I64, I32, I32, C.POINTER(C.c_int32),
@@ -203,22 +203,24 @@ def semblance(traces, dt, offset, p0, dp, np_, tau_stride, ntau, win, energy=Fal
 
 
 def semblance_pick(coh, p0, dp, p_lo, p_hi, p_ref=None, ref_scale=1.0, energy=None,
-                   rel_floor=0.0):
+                   rel_floor=0.0, return_proj=False):
     """Slowness of the largest coherence in [max(p_lo, ref_scale p_ref), p_hi]
     over windows with energy >= rel_floor x the gather's largest, per gather
-    (bhfwi_semblance_pick): (p [G], coherence [G]) device tensors."""
+    (bhfwi_semblance_pick): (p [G], coherence [G]) device tensors, and with
+    return_proj the coherence-versus-slowness projection [G, np]."""
     c = coh.unsqueeze(0) if coh.dim() == 2 else coh
     e = None if energy is None else (energy.unsqueeze(0) if energy.dim() == 2 else energy)
     G, np_, ntau = c.shape
     p = torch.empty(G, dtype=torch.float32, device=c.device)
     cc = torch.empty_like(p)
+    proj = torch.empty((G, np_), dtype=torch.float32, device=c.device)
     _check(load().bhfwi_semblance_pick(_stream(), G, np_, ntau, _f32(c.contiguous()),
                                        _f32(e.contiguous()) if e is not None else None,
                                        float(rel_floor), float(p0), float(dp),
                                        _f32(p_ref) if p_ref is not None else None,
-                                       float(ref_scale), float(p_lo), float(p_hi), _f32(p),
-                                       _f32(cc)))
-    return p, cc
+                                       float(ref_scale), float(p_lo), float(p_hi), _f32(proj),
+                                       _f32(p), _f32(cc)))
+    return (p, cc, proj) if return_proj else (p, cc)
 
 
 def starting_model(NR, NZ, dr, a, dist, vp_wall, vs_wall, vp_far, vs_far, vp_fluid):

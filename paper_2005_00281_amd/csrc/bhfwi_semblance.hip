@@ -7,9 +7,10 @@
 // first forms, for every sample of the chunk's time range, the squared stack
 // of the moveout-corrected receivers and their energy (receiver m read
 // p*offset_m/dt samples later, linearly interpolated, zero outside the
-// record; accumulated in double) into LDS, turns both series into prefix
-// sums in place (a workgroup scan), and then takes every window's sums as a
-// difference of two prefix values.  The time range of a chunk is at most kSemSpan samples, so
+// record) into LDS, turns both series into prefix sums in double (a
+// workgroup scan), and then takes every window's sums as a difference of two
+// prefix values.  Neighbouring samples of a receiver are read once: lane l
+// takes sample q + 1 from lane l + 1.  The time range of a chunk is at most kSemSpan samples, so
 // the LDS footprint does not depend on the record length.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -24,15 +25,22 @@ constexpr int kSemSpan = 2048;  // samples staged per workgroup
 constexpr int kSemThreads = 256;
 constexpr int kSemPer = kSemSpan / kSemThreads;  // samples per thread in the scan
 
+// lane l <- lane l + 1 of the same wave64 (DPP wavefront shift); lane 63 <- 0
+__device__ inline float sem_from_lane_above(float v)
+{
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
+}
+
 __global__ void __launch_bounds__(kSemThreads)
 k_semblance(int nrec, int nt, const float* __restrict__ traces, float dt,
             const float* __restrict__ offset, float p0, float dp, int ntau, int stride, int win,
             int chunk, float* __restrict__ coh, float* __restrict__ energy)
 {
-    // Ps[k], Pe[k]: first the squared stack and the energy of sample
-    // n_lo + k - 1, then (in place) their prefix sums over samples < n_lo + k
-    __shared__ double Ps[kSemSpan + 1];
-    __shared__ double Pe[kSemSpan + 1];
+    __shared__ float Ls[kSemSpan];         // squared stack of each staged sample
+    __shared__ float Le[kSemSpan];         // its energy
+    __shared__ double Ps[kSemSpan + 1];    // prefix sums of Ls
+    __shared__ double Pe[kSemSpan + 1];    // prefix sums of Le
     __shared__ double Ts[kSemThreads], Te[kSemThreads];  // per-thread totals, scanned
     __shared__ int Lq[64];                 // per receiver: whole samples of the shift
     __shared__ float Lf[64];               // and its fraction
@@ -41,6 +49,7 @@ k_semblance(int nrec, int nt, const float* __restrict__ traces, float dt,
     const int i1 = min(ntau, i0 + chunk);
     if (i0 >= i1) return;  // uniform
     const int np = gridDim.x;
+    const int lane = threadIdx.x & 63;
     const float* __restrict__ x = traces + (long long)g * nrec * nt;
     if ((int)threadIdx.x < nrec) {
         // the shift p offset / dt in double, once per receiver, split into
@@ -55,33 +64,41 @@ k_semblance(int nrec, int nt, const float* __restrict__ traces, float dt,
     const int n_lo = i0 * stride;
     const int n_hi = min((i1 - 1) * stride + win, n_lo + kSemSpan);
     const int len = n_hi - n_lo;
-    for (int n = n_lo + (int)threadIdx.x; n < n_hi; n += kSemThreads) {
-        double st = 0.0, en = 0.0;
+    // every lane takes part in every pass (the pass count is uniform) so
+    // that the neighbouring sample can come from the next lane
+    for (int base = n_lo; base < n_hi; base += kSemThreads) {
+        const int n = base + (int)threadIdx.x;
+        const bool act = n < n_hi;
+        const bool own_next = lane == 63 || n + 1 >= n_hi;
+        float st = 0.f, en = 0.f;
         for (int m = 0; m < nrec; ++m) {
             const int q = n + Lq[m];  // sample at or before the shifted time
             const float f = Lf[m];
             const float* __restrict__ xm = x + (long long)m * nt;
-            const float a = (q >= 0 && q < nt) ? xm[q] : 0.f;
-            const float b = (q + 1 >= 0 && q + 1 < nt) ? xm[q + 1] : 0.f;
+            const float a = (act && q >= 0 && q < nt) ? xm[q] : 0.f;
+            float b = sem_from_lane_above(a);  // sample q + 1, held by the next lane
+            if (own_next) b = (act && q + 1 >= 0 && q + 1 < nt) ? xm[q + 1] : 0.f;
             // the shifted time lies inside the record, or at its last sample
             float v = 0.f;
             if (q >= 0 && (q < nt - 1 || (q == nt - 1 && f == 0.f))) v = a + f * (b - a);
             st += v;
-            en += (double)v * v;
+            en += v * v;
         }
-        Ps[n - n_lo + 1] = st * st;
-        Pe[n - n_lo + 1] = en;
+        if (act) {
+            Ls[n - n_lo] = st * st;
+            Le[n - n_lo] = en;
+        }
     }
     __syncthreads();
-    // prefix sums: each thread totals kSemPer consecutive samples, the totals
-    // are scanned (Hillis-Steele), then each thread turns its own samples
-    // into running sums
-    const int t0 = threadIdx.x * kSemPer + 1;
+    // prefix sums in double: each thread totals kSemPer consecutive samples,
+    // the totals are scanned (Hillis-Steele), then each thread writes the
+    // running sums of its samples
+    const int t0 = threadIdx.x * kSemPer;
     double ts = 0.0, te = 0.0;
     for (int q = 0; q < kSemPer; ++q)
-        if (t0 + q <= len) {
-            ts += Ps[t0 + q];
-            te += Pe[t0 + q];
+        if (t0 + q < len) {
+            ts += Ls[t0 + q];
+            te += Le[t0 + q];
         }
     Ts[threadIdx.x] = ts;
     Te[threadIdx.x] = te;
@@ -96,11 +113,11 @@ k_semblance(int nrec, int nt, const float* __restrict__ traces, float dt,
     }
     double rs = Ts[threadIdx.x] - ts, re = Te[threadIdx.x] - te;  // exclusive
     for (int q = 0; q < kSemPer; ++q)
-        if (t0 + q <= len) {
-            rs += Ps[t0 + q];
-            re += Pe[t0 + q];
-            Ps[t0 + q] = rs;
-            Pe[t0 + q] = re;
+        if (t0 + q < len) {
+            rs += Ls[t0 + q];
+            re += Le[t0 + q];
+            Ps[t0 + q + 1] = rs;
+            Pe[t0 + q + 1] = re;
         }
     if (threadIdx.x == 0) {
         Ps[0] = 0.0;
@@ -116,46 +133,74 @@ k_semblance(int nrec, int nt, const float* __restrict__ traces, float dt,
     }
 }
 
-// Largest coherence over the slownesses of [lo, hi] (lo raised to
-// ref_scale * p_ref[g] when p_ref is given) and the windows whose energy is
-// at least rel_floor times the gather's largest window energy (all windows
-// when energy is null); ties go to the smaller slowness.  One workgroup per
-// gather.
+__global__ void k_sem_fill(float* __restrict__ p, int n, float v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Largest window energy of each gather, into emax[g] (non-negative floats
+// order as their bit patterns); grid (slices, gathers).
 __global__ void __launch_bounds__(kSemThreads)
-k_semblance_pick(int np, int ntau, const float* __restrict__ coh,
-                 const float* __restrict__ energy, float rel_floor, float p0, float dp,
-                 const float* __restrict__ p_ref, float ref_scale, float lo, float hi,
-                 float* __restrict__ p_out, float* __restrict__ c_out)
+k_sem_emax(long long cells, const float* __restrict__ energy, float* __restrict__ emax)
+{
+    __shared__ float S[kSemThreads];
+    const int g = blockIdx.y;
+    const float* __restrict__ e = energy + (long long)g * cells;
+    float m = 0.f;
+    for (long long q = (long long)blockIdx.x * kSemThreads + threadIdx.x; q < cells;
+         q += (long long)gridDim.x * kSemThreads)
+        m = fmaxf(m, e[q]);
+    S[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = kSemThreads / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) S[threadIdx.x] = fmaxf(S[threadIdx.x], S[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax((unsigned int*)&emax[g], __float_as_uint(S[0]));
+}
+
+// proj[g][j]: the largest coherence of slowness j over the windows whose
+// energy is at least rel_floor * emax[g] (all windows when energy is null);
+// -1 when none qualifies.  Grid (np, gathers).
+__global__ void __launch_bounds__(kSemThreads)
+k_sem_proj(int ntau, const float* __restrict__ coh, const float* __restrict__ energy,
+           const float* __restrict__ emax, float rel_floor, float* __restrict__ proj)
+{
+    __shared__ float S[kSemThreads];
+    const int j = blockIdx.x, g = blockIdx.y, np = gridDim.x;
+    const long long row = ((long long)g * np + j) * ntau;
+    const float fl = energy ? rel_floor * emax[g] : 0.f;
+    float m = -1.f;
+    for (int i = threadIdx.x; i < ntau; i += kSemThreads)
+        if (!energy || energy[row + i] >= fl) m = fmaxf(m, coh[row + i]);
+    S[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = kSemThreads / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) S[threadIdx.x] = fmaxf(S[threadIdx.x], S[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) proj[(long long)g * np + j] = S[0];
+}
+
+// The slowness of the largest proj[g][j] among slownesses in [lo, hi] (lo
+// raised to ref_scale * p_ref[g] when p_ref is given); ties go to the
+// smaller slowness.  One workgroup per gather.
+__global__ void __launch_bounds__(kSemThreads)
+k_sem_argmax(int np, const float* __restrict__ proj, float p0, float dp,
+             const float* __restrict__ p_ref, float ref_scale, float lo, float hi,
+             float* __restrict__ p_out, float* __restrict__ c_out)
 {
     __shared__ float Sc[kSemThreads];
     __shared__ int Sj[kSemThreads];
     const int g = blockIdx.x;
-    const long long base = (long long)g * np * ntau;
-    float floor_e = 0.f;
-    if (energy) {
-        float m = 0.f;
-        for (long long q = threadIdx.x; q < (long long)np * ntau; q += kSemThreads)
-            m = fmaxf(m, energy[base + q]);
-        Sc[threadIdx.x] = m;
-        __syncthreads();
-        for (int o = kSemThreads / 2; o > 0; o >>= 1) {
-            if ((int)threadIdx.x < o) Sc[threadIdx.x] = fmaxf(Sc[threadIdx.x], Sc[threadIdx.x + o]);
-            __syncthreads();
-        }
-        floor_e = rel_floor * Sc[0];
-        __syncthreads();
-    }
     const float l = p_ref ? fmaxf(lo, ref_scale * p_ref[g]) : lo;
     float best = -1.f;
     int bj = np;
     for (int j = threadIdx.x; j < np; j += kSemThreads) {
         const float p = p0 + j * dp;
         if (p < l || p > hi) continue;
-        const float* __restrict__ c = coh + base + (long long)j * ntau;
-        const float* __restrict__ e = energy ? energy + base + (long long)j * ntau : nullptr;
-        float m = -1.f;
-        for (int i = 0; i < ntau; ++i)
-            if (!e || e[i] >= floor_e) m = fmaxf(m, c[i]);
+        const float m = proj[(long long)g * np + j];
         if (m > best) {
             best = m;
             bj = j;
@@ -176,7 +221,7 @@ k_semblance_pick(int np, int ntau, const float* __restrict__ coh,
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const bool found = Sj[0] < np;
+        const bool found = Sj[0] < np && Sc[0] >= 0.f;
         p_out[g] = found ? p0 + Sj[0] * dp : 0.f;
         c_out[g] = found ? Sc[0] : 0.f;
     }
@@ -229,14 +274,22 @@ int bhfwi_semblance(void* stream, int32_t ngather, int32_t nrec, int32_t nt, con
 int bhfwi_semblance_pick(void* stream, int32_t ngather, int32_t np, int32_t ntau,
                          const float* coh, const float* energy, float rel_floor, float p0,
                          float dp, const float* p_ref, float ref_scale, float p_lo, float p_hi,
-                         float* p_out, float* c_out)
+                         float* proj, float* p_out, float* c_out)
 {
-    if (ngather < 1 || np < 1 || ntau < 1 || !coh || !p_out || !c_out || !(p_hi >= p_lo) ||
-        !(rel_floor >= 0.f))
+    if (ngather < 1 || ngather > 65535 || np < 1 || ntau < 1 || !coh || !proj || !p_out ||
+        !c_out || !(p_hi >= p_lo) || !(rel_floor >= 0.f))
         return BHFWI_EINVAL;
-    hipLaunchKernelGGL(bhfwi::k_semblance_pick, dim3(ngather), dim3(bhfwi::kSemThreads), 0,
-                       (hipStream_t)stream, np, ntau, coh, energy, rel_floor, p0, dp, p_ref,
-                       ref_scale, p_lo, p_hi, p_out, c_out);
+    hipStream_t st = (hipStream_t)stream;
+    if (energy) {  // c_out holds each gather's largest window energy meanwhile
+        hipLaunchKernelGGL(bhfwi::k_sem_fill, dim3((ngather + 255) / 256), dim3(256), 0, st, c_out,
+                           ngather, 0.f);
+        hipLaunchKernelGGL(bhfwi::k_sem_emax, dim3(64, ngather), dim3(bhfwi::kSemThreads), 0, st,
+                           (long long)np * ntau, energy, c_out);
+    }
+    hipLaunchKernelGGL(bhfwi::k_sem_proj, dim3(np, ngather), dim3(bhfwi::kSemThreads), 0, st,
+                       ntau, coh, energy, (const float*)c_out, rel_floor, proj);
+    hipLaunchKernelGGL(bhfwi::k_sem_argmax, dim3(ngather), dim3(bhfwi::kSemThreads), 0, st, np,
+                       (const float*)proj, p0, dp, p_ref, ref_scale, p_lo, p_hi, p_out, c_out);
     return hipGetLastError() == hipSuccess ? BHFWI_OK : BHFWI_EHIP;
 }
 
