@@ -84,7 +84,9 @@ def test_semblance_pick_parity():
     # bands with edges half way between grid slownesses; windows with at
     # least 1e-6 of the largest window energy
     lo_p, hi_p, fl = P0 + 60.5 * DP, P0 + 300.5 * DP, 1e-6
-    pP, cP = P.semblance_pick(coh, P0, DP, lo_p, hi_p, energy=en, rel_floor=fl)
+    pP, cP, proj = P.semblance_pick(coh, P0, DP, lo_p, hi_p, energy=en, rel_floor=fl,
+                                    return_proj=True)
+    proj = proj.cpu().numpy()
     pS, cS = P.semblance_pick(coh, P0, DP, 0.0, P0 + 560.5 * DP, p_ref=pP, ref_scale=1.4,
                               energy=en, rel_floor=fl)
     pP, pS = pP.cpu().numpy(), pS.cpu().numpy()
@@ -93,6 +95,8 @@ def test_semblance_pick_parity():
                                   win, return_energy=True)
         po, c_o = oracle.pick_slowness(co, P0, DP, lo_p, hi_p, energy=eo, rel_floor=fl)
         rowmax = np.where(eo >= fl * eo.max(), co, -1.0).max(axis=1)
+        # the coherence-versus-slowness projection itself
+        assert np.abs(proj[g] - rowmax).max() <= 1e-4
         for pg, ref in ((pP[g], po), (pS[g], None)):
             if ref is None:  # S band above 1.4 x the oracle's P pick
                 ref, _ = oracle.pick_slowness(co, P0, DP, 1.4 * po, P0 + 560.5 * DP, energy=eo,
