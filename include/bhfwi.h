@@ -229,8 +229,8 @@ int bhfwi_kernel_times(bhfwi_ctx *ctx, bhfwi_kernel_times_t *out, int32_t reset)
  * between samples and zero outside its record; 0 for a window without
  * energy.  energy (nullable, same shape) receives the window energy
  * sum_window sum_m x_m^2.
- * FP32 data and interpolation, stack, energy and window sums in double
- * (window sums as differences of prefix sums).  Returns BHFWI_EINVAL on bad sizes. */
+ * FP32 data, interpolation, stack and energy; window sums in double (as
+ * differences of prefix sums).  Returns BHFWI_EINVAL on bad sizes. */
 int bhfwi_semblance(void *stream, int32_t ngather, int32_t nrec, int32_t nt,
                     const float *traces, float dt, const float *offset, int32_t np, float p0,
                     float dp, int32_t ntau, int32_t tau_stride, int32_t win, float *coh,

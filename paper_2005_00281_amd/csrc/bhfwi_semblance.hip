@@ -7,10 +7,9 @@
 // first forms, for every sample of the chunk's time range, the squared stack
 // of the moveout-corrected receivers and their energy (receiver m read
 // p*offset_m/dt samples later, linearly interpolated, zero outside the
-// record) into LDS, turns both series into prefix sums in double (a
+// record) into LDS, turns both series into prefix sums in double in place (a
 // workgroup scan), and then takes every window's sums as a difference of two
-// prefix values.  Neighbouring samples of a receiver are read once: lane l
-// takes sample q + 1 from lane l + 1.  The time range of a chunk is at most kSemSpan samples, so
+// prefix values.  The time range of a chunk is at most kSemSpan samples, so
 // the LDS footprint does not depend on the record length.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -25,22 +24,15 @@ constexpr int kSemSpan = 2048;  // samples staged per workgroup
 constexpr int kSemThreads = 256;
 constexpr int kSemPer = kSemSpan / kSemThreads;  // samples per thread in the scan
 
-// lane l <- lane l + 1 of the same wave64 (DPP wavefront shift); lane 63 <- 0
-__device__ inline float sem_from_lane_above(float v)
-{
-    return __builtin_bit_cast(
-        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
-}
-
 __global__ void __launch_bounds__(kSemThreads)
 k_semblance(int nrec, int nt, const float* __restrict__ traces, float dt,
             const float* __restrict__ offset, float p0, float dp, int ntau, int stride, int win,
             int chunk, float* __restrict__ coh, float* __restrict__ energy)
 {
-    __shared__ float Ls[kSemSpan];         // squared stack of each staged sample
-    __shared__ float Le[kSemSpan];         // its energy
-    __shared__ double Ps[kSemSpan + 1];    // prefix sums of Ls
-    __shared__ double Pe[kSemSpan + 1];    // prefix sums of Le
+    // Ps[k], Pe[k]: first the squared stack and the energy of sample
+    // n_lo + k - 1, then (in place) their prefix sums over samples < n_lo + k
+    __shared__ double Ps[kSemSpan + 1];
+    __shared__ double Pe[kSemSpan + 1];
     __shared__ double Ts[kSemThreads], Te[kSemThreads];  // per-thread totals, scanned
     __shared__ int Lq[64];                 // per receiver: whole samples of the shift
     __shared__ float Lf[64];               // and its fraction
@@ -49,7 +41,6 @@ k_semblance(int nrec, int nt, const float* __restrict__ traces, float dt,
     const int i1 = min(ntau, i0 + chunk);
     if (i0 >= i1) return;  // uniform
     const int np = gridDim.x;
-    const int lane = threadIdx.x & 63;
     const float* __restrict__ x = traces + (long long)g * nrec * nt;
     if ((int)threadIdx.x < nrec) {
         // the shift p offset / dt in double, once per receiver, split into
@@ -64,41 +55,33 @@ k_semblance(int nrec, int nt, const float* __restrict__ traces, float dt,
     const int n_lo = i0 * stride;
     const int n_hi = min((i1 - 1) * stride + win, n_lo + kSemSpan);
     const int len = n_hi - n_lo;
-    // every lane takes part in every pass (the pass count is uniform) so
-    // that the neighbouring sample can come from the next lane
-    for (int base = n_lo; base < n_hi; base += kSemThreads) {
-        const int n = base + (int)threadIdx.x;
-        const bool act = n < n_hi;
-        const bool own_next = lane == 63 || n + 1 >= n_hi;
+    for (int n = n_lo + (int)threadIdx.x; n < n_hi; n += kSemThreads) {
         float st = 0.f, en = 0.f;
         for (int m = 0; m < nrec; ++m) {
             const int q = n + Lq[m];  // sample at or before the shifted time
             const float f = Lf[m];
             const float* __restrict__ xm = x + (long long)m * nt;
-            const float a = (act && q >= 0 && q < nt) ? xm[q] : 0.f;
-            float b = sem_from_lane_above(a);  // sample q + 1, held by the next lane
-            if (own_next) b = (act && q + 1 >= 0 && q + 1 < nt) ? xm[q + 1] : 0.f;
+            const float a = (q >= 0 && q < nt) ? xm[q] : 0.f;
+            const float b = (q + 1 >= 0 && q + 1 < nt) ? xm[q + 1] : 0.f;
             // the shifted time lies inside the record, or at its last sample
             float v = 0.f;
             if (q >= 0 && (q < nt - 1 || (q == nt - 1 && f == 0.f))) v = a + f * (b - a);
             st += v;
             en += v * v;
         }
-        if (act) {
-            Ls[n - n_lo] = st * st;
-            Le[n - n_lo] = en;
-        }
+        Ps[n - n_lo + 1] = (double)st * st;
+        Pe[n - n_lo + 1] = en;
     }
     __syncthreads();
     // prefix sums in double: each thread totals kSemPer consecutive samples,
-    // the totals are scanned (Hillis-Steele), then each thread writes the
-    // running sums of its samples
-    const int t0 = threadIdx.x * kSemPer;
+    // the totals are scanned (Hillis-Steele), then each thread turns its own
+    // samples into running sums
+    const int t0 = threadIdx.x * kSemPer + 1;
     double ts = 0.0, te = 0.0;
     for (int q = 0; q < kSemPer; ++q)
-        if (t0 + q < len) {
-            ts += Ls[t0 + q];
-            te += Le[t0 + q];
+        if (t0 + q <= len) {
+            ts += Ps[t0 + q];
+            te += Pe[t0 + q];
         }
     Ts[threadIdx.x] = ts;
     Te[threadIdx.x] = te;
@@ -113,11 +96,11 @@ k_semblance(int nrec, int nt, const float* __restrict__ traces, float dt,
     }
     double rs = Ts[threadIdx.x] - ts, re = Te[threadIdx.x] - te;  // exclusive
     for (int q = 0; q < kSemPer; ++q)
-        if (t0 + q < len) {
-            rs += Ls[t0 + q];
-            re += Le[t0 + q];
-            Ps[t0 + q + 1] = rs;
-            Pe[t0 + q + 1] = re;
+        if (t0 + q <= len) {
+            rs += Ps[t0 + q];
+            re += Pe[t0 + q];
+            Ps[t0 + q] = rs;
+            Pe[t0 + q] = re;
         }
     if (threadIdx.x == 0) {
         Ps[0] = 0.0;
