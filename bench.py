@@ -46,8 +46,10 @@ PMC_SOURCES = ("paper_2005_00281_amd/csrc/bhfwi_tb_adj.hip",
                "paper_2005_00281_amd/csrc/bhfwi_tb_fwd.hip",
                "paper_2005_00281_amd/csrc/bhfwi_internal.h")
 PMC_TRAFFIC = {
-    # (kernel, tile_map, workload, sources sha256[:16]): (FETCH KiB, WRITE KiB)
-    ("k_adj_tb<6, 32, 16>", 1, "c2", "0358d0a223858015"): (48355.94, 30985.60),
+    # (kernel, tile_map, workload, sources sha256[:16]): (FETCH KiB, WRITE KiB), summed
+    # over the kernels of one launch block
+    ("k_adj_tb<8, 32, 16, 0> + k_adj_tb<8, 32, 16, 1>", 1, "c2", "18dbee857d657428"):
+        (50206.73 + 9997.84, 33649.91 + 5494.22),
 }
 
 
@@ -443,7 +445,7 @@ def main():
                else int(1024 * (pmc[0] * PMC_FETCH_SCALE + pmc[1] * PMC_WRITE_SCALE)))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                "traffic_unit": "bytes per time block (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                 "copy-calibrated)",
                 "traffic_GBs": (round(traffic / (adj_avg * 1e-3) / 1e9, 1)
                                 if traffic is not None else None),
