@@ -219,27 +219,34 @@ void build_tiles(const bhfwi_ctx* c, const std::vector<int>& order, Shape sh, Sh
     }
     ts->pml = pml;
     if (sh.T < 2) return;
+    // Columns of TZ axial rows (the same T, hence TZ, for both shapes).  In a
+    // column clear of the axial PML, interior tiles of TR rows cover the rows
+    // whose haloed window stays below the radial PML; the rest of the
+    // column, and every column that reaches the axial PML, is covered by PML
+    // tiles of TRp rows.
     const int TR = sh.TRE - 2 * sh.T, TZ = 64 - 2 * sh.T, TRp = pml.TRE - 2 * pml.T;
-    auto add = [&](int s, int k0, int i0) {
-        const ShotDev& S = c->sd[s];
-        if (!touches_pml(S, sh, i0, k0)) {
-            ts->t[0].push_back(make_int4(s, k0, i0, std::min(i0 + TR, S.NR)));
-            ts->nt[0].push_back(S.nt);
-            return;
-        }
-        for (int i = i0; i < std::min(i0 + TR, S.NR); i += TRp) {
-            ts->t[1].push_back(make_int4(s, k0, i, std::min(i + TRp, S.NR)));
-            ts->nt[1].push_back(S.nt);
-        }
-    };
+    std::vector<int2> tl[2];  // (k0, i0) of one shot's tiles
     for (int s : order) {
         const ShotDev& S = c->sd[s];
-        if (c->tune.tile_map == 1) {
-            for (int k0 = 0; k0 < S.NZ; k0 += TZ)
-                for (int i0 = 0; i0 < S.NR; i0 += TR) add(s, k0, i0);
-        } else {
-            for (int i0 = 0; i0 < S.NR; i0 += TR)
-                for (int k0 = 0; k0 < S.NZ; k0 += TZ) add(s, k0, i0);
+        tl[0].clear();
+        tl[1].clear();
+        for (int k0 = 0; k0 < S.NZ; k0 += TZ) {
+            int i0 = 0;
+            if (!touches_pml(S, sh, 0, k0))
+                for (; i0 < S.NR && !touches_pml(S, sh, i0, k0); i0 += TR)
+                    tl[0].push_back(make_int2(k0, i0));
+            for (; i0 < S.NR; i0 += TRp) tl[1].push_back(make_int2(k0, i0));
+        }
+        for (int q = 0; q < 2; ++q) {
+            if (c->tune.tile_map == 0)  // axial tile fastest
+                std::stable_sort(tl[q].begin(), tl[q].end(), [](int2 a, int2 b) {
+                    return a.y != b.y ? a.y < b.y : a.x < b.x;
+                });
+            const int rows = q ? TRp : TR;
+            for (const int2 kt : tl[q]) {
+                ts->t[q].push_back(make_int4(s, kt.x, kt.y, std::min(kt.y + rows, S.NR)));
+                ts->nt[q].push_back(S.nt);
+            }
         }
     }
 }
@@ -420,18 +427,15 @@ bool adj_pml_ok(Shape sh) { BHFWI_ADJ_PML(BHFWI_TBS) return false; }
 bool adj_int_ok(Shape sh) { BHFWI_ADJ_INT(BHFWI_TBS) return false; }
 #undef BHFWI_TBS
 
-// Shape for the PML tiles of interior shape sh: sh itself when its kernel can
-// carry the PML, else the PML-capable shape with the same T whose owned rows
-// divide sh's (most rows, then most waves); T = 0 if there is none.
+// Shape for the PML tiles of interior shape sh: the PML-capable shape with
+// the same T and the most rows (the least halo per owned row), then the most
+// waves; T = 0 if there is none.
 Shape pml_shape(Shape sh, bool adj)
 {
     if (sh.T < 2) return Shape{0, 0, 0};
-    if (adj ? adj_pml_ok(sh) : fwd_pml_ok(sh)) return sh;
     Shape best{0, 0, 0};
-    const int TR = sh.TRE - 2 * sh.T;
     auto consider = [&](int T, int R, int W) {
-        const int TRp = R - 2 * T;
-        if (T != sh.T || TRp <= 0 || TR % TRp) return;
+        if (T != sh.T) return;
         if (R > best.TRE || (R == best.TRE && W > best.W)) best = Shape{T, R, W};
     };
 #define BHFWI_TBP(TT, RR, WW) consider(TT, RR, WW);
