@@ -427,15 +427,20 @@ bool adj_pml_ok(Shape sh) { BHFWI_ADJ_PML(BHFWI_TBS) return false; }
 bool adj_int_ok(Shape sh) { BHFWI_ADJ_INT(BHFWI_TBS) return false; }
 #undef BHFWI_TBS
 
-// Shape for the PML tiles of interior shape sh: the PML-capable shape with
-// the same T and the most rows (the least halo per owned row), then the most
-// waves; T = 0 if there is none.
+// Shape for the PML tiles of interior shape sh: sh itself when its kernel can
+// carry the PML, else the PML-capable shape with the same T whose owned rows
+// divide sh's (most rows, then most waves); T = 0 if there is none.  (Taller
+// PML tiles were measured slower: the PML band of a single shot then holds
+// fewer workgroups than the GPU has compute units.)
 Shape pml_shape(Shape sh, bool adj)
 {
     if (sh.T < 2) return Shape{0, 0, 0};
+    if (adj ? adj_pml_ok(sh) : fwd_pml_ok(sh)) return sh;
     Shape best{0, 0, 0};
+    const int TR = sh.TRE - 2 * sh.T;
     auto consider = [&](int T, int R, int W) {
-        if (T != sh.T) return;
+        const int TRp = R - 2 * T;
+        if (T != sh.T || TRp <= 0 || TR % TRp) return;
         if (R > best.TRE || (R == best.TRE && W > best.W)) best = Shape{T, R, W};
     };
 #define BHFWI_TBP(TT, RR, WW) consider(TT, RR, WW);

@@ -495,18 +495,18 @@ def test_velocity_parameterisation_autograd():
 
 
 def test_kernel_shapes_report_the_pml_sub_tiles():
-    """The PML tiles of a shape run in the PML-capable shape with the same T
-    and the most rows (then the most waves)."""
+    """Interior-only shapes hand their PML tiles to a PML-capable shape with
+    the same T whose owned rows divide theirs; PML-capable shapes keep their
+    own."""
     w = workloads.tiny()
     _say("kernel shapes")
     sv = survey(w, tune=T(tb=8, tbr=64, tbw=16, atb=6, atbr=48, atbw=16))
     ks = sv.kernel_shapes()
-    assert ks["fwd"] == (8, 64, 16) and ks["fwd_pml"] == (8, 48, 16)
-    assert ks["adj"] == (6, 48, 16) and ks["adj_pml"] == (6, 32, 16)
+    assert ks["fwd"] == (8, 64, 16) and ks["fwd_pml"] == (8, 32, 16)
+    assert ks["adj"] == (6, 48, 16) and ks["adj_pml"] == (6, 24, 8)
     sv.set_tune(**T(tb=6, tbr=32, tbw=16))
     ks = sv.kernel_shapes()
-    assert ks["fwd"] == (6, 32, 16) and ks["fwd_pml"] == (6, 48, 16)
-    assert ks["adj"] == ks["adj_pml"] == (6, 32, 16)
+    assert ks["fwd"] == ks["fwd_pml"] == ks["adj"] == ks["adj_pml"] == (6, 32, 16)
     sv.set_tune(**T(rows=2))
     assert sv.kernel_shapes()["adj"][0] == 0
 
