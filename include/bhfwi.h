@@ -156,8 +156,8 @@ typedef struct {
  * model_len elements.  rec_k (host, nrec_total entries) holds the receiver
  * rows of every shot.
  * ckpt_every > 0 is the forward checkpoint interval in steps.  Validates the
- * geometry (receiver and source rows inside the grid, windows inside the
- * model) and the CFL condition vmax dt sqrt(1/dr^2 + 1/dz^2) < 1 with vmax =
+ * geometry (receiver and source rows inside the grid, at most one receiver
+ * per row of a shot, windows inside the model) and the CFL condition vmax dt sqrt(1/dr^2 + 1/dz^2) < 1 with vmax =
  * pml_vmax.  Uploads the shot table, receiver rows and PML profiles to the
  * device selected by hip_device. */
 int bhfwi_create(bhfwi_ctx **out, int32_t hip_device, const bhfwi_shot *shots, int32_t nshot,

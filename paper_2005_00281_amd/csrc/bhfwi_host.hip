@@ -717,6 +717,14 @@ int bhfwi_create(bhfwi_ctx** out, int32_t hip_device, const bhfwi_shot* shots, i
             if (rec_k[h.rec_off + j] < 0 || rec_k[h.rec_off + j] >= NZ)
                 return bail(fail(c, BHFWI_EINVAL, "shot %d: receiver row %d outside grid", s,
                                  rec_k[h.rec_off + j]));
+        {  // one receiver per row: the kernels record one trace per axial row
+            std::vector<int32_t> rows(rec_k + h.rec_off, rec_k + h.rec_off + h.nrec);
+            std::sort(rows.begin(), rows.end());
+            for (size_t j = 1; j < rows.size(); ++j)
+                if (rows[j] == rows[j - 1])
+                    return bail(fail(c, BHFWI_EINVAL, "shot %d: two receivers on row %d", s,
+                                     rows[j]));
+        }
         if (h.model_off < 0 || h.model_ld < NZ ||
             h.model_off + (NR - 1) * h.model_ld + NZ > model_len)
             return bail(fail(c, BHFWI_EINVAL, "shot %d: model window outside the model", s));

@@ -40,7 +40,8 @@ def test_binding_lists_every_declared_symbol():
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libbhfwi.so not built")
 def test_create_rejects_bad_geometry_without_gpu_work():
     """Validation happens before any device call: a receiver outside the
-    grid and a CFL violation are refused with their codes."""
+    grid, a CFL violation, a window outside the model and two receivers on
+    one row are refused with their codes."""
     from paper_2005_00281_amd import _lib
     L = _lib.load()
     sh = (_lib.Shot * 1)()
@@ -57,3 +58,8 @@ def test_create_rejects_bad_geometry_without_gpu_work():
     sh[0].model_off = 5  # window runs past the model
     rc = L.bhfwi_create(ctypes.byref(h), 0, sh, 1, rec, 1, 20 * 40, 10)
     assert rc == -1 and b"model window" in L.bhfwi_last_error(None)
+    sh[0].model_off = 0
+    two = (ctypes.c_int32 * 2)(12, 12)  # two receivers on one row
+    sh[0].nrec = 2
+    rc = L.bhfwi_create(ctypes.byref(h), 0, sh, 1, two, 2, 20 * 40, 10)
+    assert rc == -1 and b"two receivers" in L.bhfwi_last_error(None)

@@ -322,6 +322,68 @@ def batched_uneven(seed=SEED, name="c4", nshot=96, h=2.5e-3, p=20, nrec=13,
                     meta=dict(iters=1))
 
 
+# Monopole sources of the acquisition (Numerical Examples section): lower-near,
+# far and ultra-far, below a 13-receiver array at 0.5 ft spacing; the tool logs
+# every 0.5 ft.  The paper gives no source offsets, only that the realigned
+# data form one source with 39 receivers; they are taken as 8, 21 and 34
+# receiver spacings (1.22, 3.20, 5.18 m) from the source to the first receiver:
+# whole multiples of the logging step (so the three sources realign onto
+# common source positions) 13 steps apart (so the three arrays tile one
+# contiguous 39-receiver array).
+SOURCE_OFFSETS_STEPS = (8, 21, 34)
+
+
+def realigned_receivers(z_src, nrec=13, spacing=REC_SPACING_HALF_FOOT,
+                        offsets_steps=SOURCE_OFFSETS_STEPS):
+    """Receiver depths of one realigned gather: every source kind's array, as
+    it stood when that source was at z_src (3 x 13 = 39 receivers)."""
+    return [z_src + (o + j) * spacing for o in offsets_steps for j in range(nrec)]
+
+
+def realign(raw, offsets_steps=SOURCE_OFFSETS_STEPS):
+    """Data of the logging run, raw[d][q][j] (tool depth d every 0.5 ft, source
+    kind q, receiver j), re-sorted into common-source gathers out[s][q*nrec+j]
+    for source positions s = 0 .. D - 1 - max(offsets): source kind q at depth
+    d sits at position d - offsets_steps[q] (positions counted from the
+    array's first receiver at depth 0)."""
+    raw = np.asarray(raw)
+    D, Q, nrec = raw.shape[:3]
+    omax = max(offsets_steps)
+    S = D - omax
+    if S < 1:
+        raise ValueError("the logging run is shorter than the largest source offset")
+    out = np.empty((S, Q * nrec) + raw.shape[3:], raw.dtype)
+    for s in range(S):
+        for q, o in enumerate(offsets_steps):
+            # source q at position s: the tool's first receiver was o steps above
+            out[s, q * nrec:(q + 1) * nrec] = raw[s + o, q]
+    return out
+
+
+def full_acquisition(seed=SEED, name="acq", nsrc=8, nr=256, h=2.5e-3, p=20, dt=0.25e-6,
+                     nt=16000, f0=10e3, nrec=13, cfg_id=6) -> Workload:
+    """Realigned full acquisition over the layered formation of the batched
+    workloads: nsrc source positions every 0.5 ft, each shot with the 39
+    receivers of the near, far and ultra-far arrays (realigned_receivers).
+    Each shot's window spans 0.3 m below its source to 0.4 m above its last
+    receiver; the record (nt dt = 4 ms by default) covers the S arrival at the
+    farthest receiver (7 m)."""
+    rng = np.random.default_rng([seed, cfg_id, 0])
+    step_k = int(round(REC_SPACING_HALF_FOOT / h))
+    z_rec = realigned_receivers(0.3, nrec)
+    nz = int(math.ceil((z_rec[-1] + 0.4) / h))
+    NR, NZ = nr + p, nz + 2 * p
+    NZg = (nsrc - 1) * step_k + NZ
+    vp_t, vs_t, vp_s, vs_s, rho, fl = _layered_model(NR, NZg, h, p, rng)
+    shots = []
+    for s in range(nsrc):
+        k0 = s * step_k
+        vmax = max(vp_t[:, k0:k0 + NZ].max(), vp_s[:, k0:k0 + NZ].max())
+        shots.append(_shot(nr, nz, p, p, h, dt, nt, f0, vmax, 0.3, z_rec, k0))
+    return Workload(name, shots, NR, NZg, vp_t, vs_t, vp_s, vs_s, rho,
+                    _mask(NR, NZg, nr, p, fl), meta=dict(iters=1, ckpt=250))
+
+
 def large_layered(seed=SEED, nshot=128, **kw) -> Workload:
     """128 shots of 512 x 16384 cells, 16000 steps, 8 kHz, layered + radial damage."""
     wl = batched_layered(seed=seed, name="c5", nshot=nshot, nr=512, nz=16384, nt=16000,
@@ -371,6 +433,7 @@ CONFIGS = {
     "c3": batched_layered,
     "c4": batched_uneven,
     "c5": large_layered,
+    "acq": full_acquisition,
 }
 
 
