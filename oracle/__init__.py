@@ -63,7 +63,7 @@ def _load():
         lib.orc_forward.restype = C.c_int
         lib.orc_misfit.argtypes = [C.c_int64, _D, _D, _D]
         lib.orc_misfit.restype = C.c_double
-        lib.orc_gradient.argtypes = [G, _D, _D, _D, _D, _D, C.c_int32, _D, _D, _D]
+        lib.orc_gradient.argtypes = [G, _D, _D, _D, _D, _D, C.c_int32, _D, _D, _D, _D]
         lib.orc_gradient.restype = C.c_int
         lib.orc_source_adjoint.argtypes = [G, _D, _D, _D, _D, _D]
         lib.orc_source_adjoint.restype = C.c_int
@@ -187,18 +187,20 @@ def misfit(d, dobs):
     return J, r
 
 
-def gradient(g: Geom, lam, mu, rho, wavelet, resid, seg=200):
-    """Eq. 6-8 via the exact discrete transpose; returns (glam, gmu, illum)."""
+def gradient(g: Geom, lam, mu, rho, wavelet, resid, seg=200, density=False):
+    """Eq. 6-8 via the exact discrete transpose; returns (glam, gmu, illum),
+    and dJ/drho as a fourth output with density=True."""
     shp = (g.NR, g.NZ)
     lam, mu, rho = _f64(lam, shp), _f64(mu, shp), _f64(rho, shp)
     w, r = _f64(wavelet), _f64(resid)
     gc, rk = g._c()
     assert r.size == len(rk) * g.nt
     gl, gm, il = np.zeros(shp), np.zeros(shp), np.zeros(shp)
+    gr = np.zeros(shp) if density else None
     rc = _load().orc_gradient(C.byref(gc), _p(lam), _p(mu), _p(rho), _p(w), _p(r),
-                              int(seg), _p(gl), _p(gm), _p(il))
+                              int(seg), _p(gl), _p(gm), _p(il), _p(gr) if density else None)
     _check(rc, "gradient")
-    return gl, gm, il
+    return (gl, gm, il, gr) if density else (gl, gm, il)
 
 
 def source_adjoint(g: Geom, lam, mu, rho, resid):

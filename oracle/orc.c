@@ -183,7 +183,11 @@ static double mu_S(const grid *G, int i, int k)
  * stored: eps[0..3] planes = e_rr', e_tt, e_zz' (C nodes), e_rz' (S nodes),
  * where ' marks the PML-modified difference.
  * ------------------------------------------------------------------------- */
-static void fwd_step(const grid *G, state *s, int src_k, double srcval, double *eps)
+/* One leapfrog step.  eps (nullable) receives the strain rates the stress
+ * update used (4 N); dvb (nullable) receives d v^{n+1/2} / d b for v_r and v_z
+ * (2 N: dt times the bracket the buoyancy multiplies). */
+static void fwd_step(const grid *G, state *s, int src_k, double srcval, double *eps,
+                     double *dvb)
 {
     const int NR = G->NR, NZ = G->NZ;
     const double dr = G->dr, dz = G->dz, dt = G->dt;
@@ -210,6 +214,7 @@ static void fwd_step(const grid *G, state *s, int src_k, double srcval, double *
             }
             double hoop = ((trr[c] - ttt[c]) + (trr[cm] - ttt[cm])) / (2.0 * ri);
             vr[c] += dt * buoy_R(G, i, k) * (Dr + Dz + hoop);
+            if (dvb) dvb[c] = dt * (Dr + Dz + hoop);
         }
     }
     /* velocity: Z nodes */
@@ -231,6 +236,7 @@ static void fwd_step(const grid *G, state *s, int src_k, double srcval, double *
             }
             double hoop = (trz_ip + trz[c]) / (2.0 * rh);
             vz[c] += dt * buoy_Z(G, i, k) * (Dr + Dz + hoop);
+            if (dvb) dvb[N + c] = dt * (Dr + Dz + hoop);
         }
     }
     /* stress: C nodes */
@@ -296,13 +302,14 @@ static void fwd_step(const grid *G, state *s, int src_k, double srcval, double *
  * Exact transpose of fwd_step (without source), applied to the adjoint state a.
  * Order is the reverse of the forward: stress phase first, then velocity.
  * ------------------------------------------------------------------------- */
-static void adj_step(const grid *G, state *a)
+/* Transpose of one step, in two halves: the stress phase (after which a->vr,
+ * a->vz hold dJ/dv^{n+1/2}) and the velocity phase. */
+static void adj_stress_phase(const grid *G, state *a)
 {
     const int NR = G->NR, NZ = G->NZ;
     const double dr = G->dr, dz = G->dz, dt = G->dt;
     double *avr = a->vr, *avz = a->vz, *atrr = a->trr, *attt = a->ttt, *atzz = a->tzz,
            *atrz = a->trz;
-    double *qA = a->psi[0], *qB = a->psi[1], *qC = a->psi[2], *qD = a->psi[3];
     double *qE = a->psi[4], *qF = a->psi[5], *qG = a->psi[6], *qH = a->psi[7];
 
     /* transpose of the stress phase: C nodes */
@@ -353,6 +360,16 @@ static void adj_step(const grid *G, state *a)
             avz[IX(i - 1, k)] -= g_er / dr;
         }
     }
+}
+
+static void adj_velocity_phase(const grid *G, state *a)
+{
+    const int NR = G->NR, NZ = G->NZ;
+    const double dr = G->dr, dz = G->dz, dt = G->dt;
+    double *avr = a->vr, *avz = a->vz, *atrr = a->trr, *attt = a->ttt, *atzz = a->tzz,
+           *atrz = a->trz;
+    double *qA = a->psi[0], *qB = a->psi[1], *qC = a->psi[2], *qD = a->psi[3];
+
     /* transpose of the velocity phase: R nodes, i >= 1 */
     for (int i = 1; i < NR; ++i) {
         double ri = i * dr;
@@ -404,6 +421,12 @@ static void adj_step(const grid *G, state *a)
             atzz[c] -= g_Dz / dz;
         }
     }
+}
+
+static void adj_step(const grid *G, state *a)
+{
+    adj_stress_phase(G, a);
+    adj_velocity_phase(G, a);
 }
 
 static double src_scale(const grid *G)
@@ -476,7 +499,7 @@ int orc_forward(const orc_geom *g, const double *lam, const double *mu, const do
     state_bind(&s, mem, N);
     double sc = src_scale(&G);
     for (int n = 0; n < g->nt; ++n) {
-        fwd_step(&G, &s, g->src_k, sc * wavelet[n], NULL);
+        fwd_step(&G, &s, g->src_k, sc * wavelet[n], NULL, NULL);
         for (int j = 0; j < g->nrec; ++j) {
             size_t c = IX(0, g->rec_k[j]);
             traces[(size_t)j * g->nt + n] = (s.trr[c] + s.ttt[c] + s.tzz[c]) / 3.0;
@@ -512,7 +535,7 @@ static void inject_residual(const orc_geom *g, int NZ, state *a, const double *r
 
 int orc_gradient(const orc_geom *g, const double *lam, const double *mu, const double *rho,
                  const double *wavelet, const double *resid, int32_t seg, double *glam,
-                 double *gmu, double *illum)
+                 double *gmu, double *illum, double *grho)
 {
     grid G;
     if (seg <= 0 || grid_init(&G, g, lam, mu, rho) || !geom_ok(g)) return -1;
@@ -525,8 +548,12 @@ int orc_gradient(const orc_geom *g, const double *lam, const double *mu, const d
     double *amem = calloc(SL, sizeof(double));
     double *eps = malloc((size_t)seg * 4 * N * sizeof(double));
     double *gmuS = calloc(N, sizeof(double));
-    if (!ckpt || !fmem || !amem || !eps || !gmuS) {
-        free(ckpt); free(fmem); free(amem); free(eps); free(gmuS);
+    /* for the density: d v^{n+1/2} / d b per step of a segment, and
+     * dJ/db at the v_r and v_z nodes */
+    double *dvb = grho ? malloc((size_t)seg * 2 * N * sizeof(double)) : NULL;
+    double *gb = grho ? calloc(2 * N, sizeof(double)) : NULL;
+    if (!ckpt || !fmem || !amem || !eps || !gmuS || (grho && (!dvb || !gb))) {
+        free(ckpt); free(fmem); free(amem); free(eps); free(gmuS); free(dvb); free(gb);
         grid_free(&G);
         return -1;
     }
@@ -541,7 +568,7 @@ int orc_gradient(const orc_geom *g, const double *lam, const double *mu, const d
     /* forward pass: checkpoints every seg steps, illumination from v^{n+1/2} */
     for (int n = 0; n < nt; ++n) {
         if (n % seg == 0) memcpy(ckpt + (size_t)(n / seg) * SL, fmem, SL * sizeof(double));
-        fwd_step(&G, &s, g->src_k, sc * wavelet[n], NULL);
+        fwd_step(&G, &s, g->src_k, sc * wavelet[n], NULL, NULL);
         for (int i = 0; i < NR; ++i)
             for (int k = 0; k < NZ; ++k) {
                 size_t c = IX(i, k);
@@ -557,7 +584,8 @@ int orc_gradient(const orc_geom *g, const double *lam, const double *mu, const d
         int n0 = j * seg, n1 = n0 + seg < nt ? n0 + seg : nt;
         memcpy(fmem, ckpt + (size_t)j * SL, SL * sizeof(double));
         for (int n = n0; n < n1; ++n)
-            fwd_step(&G, &s, g->src_k, sc * wavelet[n], eps + (size_t)(n - n0) * 4 * N);
+            fwd_step(&G, &s, g->src_k, sc * wavelet[n], eps + (size_t)(n - n0) * 4 * N,
+                     dvb ? dvb + (size_t)(n - n0) * 2 * N : NULL);
         for (int n = n1 - 1; n >= n0; --n) {
             inject_residual(g, NZ, &a, resid, n);
             const double *e = eps + (size_t)(n - n0) * 4 * N;
@@ -569,8 +597,36 @@ int orc_gradient(const orc_geom *g, const double *lam, const double *mu, const d
                 gmu[c] += dt * 2.0 * (err * a.trr[c] + ett * a.ttt[c] + ezz * a.tzz[c]);
                 gmuS[c] += dt * e[3 * N + c] * a.trz[c];
             }
-            adj_step(&G, &a);
+            adj_stress_phase(&G, &a);
+            if (gb) {
+                /* v^{n+1/2} = v^{n-1/2} + b dv/db: dJ/db += dJ/dv^{n+1/2} dv/db */
+                const double *d = dvb + (size_t)(n - n0) * 2 * N;
+                for (size_t c = 0; c < N; ++c) {
+                    gb[c] += a.vr[c] * d[c];
+                    gb[N + c] += a.vz[c] * d[N + c];
+                }
+            }
+            adj_velocity_phase(&G, &a);
         }
+    }
+    if (grho) {
+        /* b_R = 2/(rho[i-1,k] + rho[i,k]) and b_Z = 2/(rho[i,k] + rho[i,k1]):
+         * d b / d rho = -b^2/2 for each of the two cells (k1 = k on the top row
+         * counts twice) */
+        memset(grho, 0, N * sizeof(double));
+        for (int i = 1; i < NR; ++i)
+            for (int k = 0; k < NZ; ++k) {
+                double b = buoy_R(&G, i, k), t = -0.5 * b * b * gb[IX(i, k)];
+                grho[IX(i - 1, k)] += t;
+                grho[IX(i, k)] += t;
+            }
+        for (int i = 0; i < NR; ++i)
+            for (int k = 0; k < NZ; ++k) {
+                int k1 = k + 1 < NZ ? k + 1 : NZ - 1;
+                double b = buoy_Z(&G, i, k), t = -0.5 * b * b * gb[N + IX(i, k)];
+                grho[IX(i, k)] += t;
+                grho[IX(i, k1)] += t;
+            }
     }
     /* rigidity at tau_rz nodes is the harmonic mean of the four adjacent C cells:
      * d muS / d mu_c = muS^2 / (4 mu_c^2) per occurrence of c among the four */
@@ -585,7 +641,7 @@ int orc_gradient(const orc_geom *g, const double *lam, const double *mu, const d
                 gmu[nb[q]] += gmuS[IX(i, k)] * ms * ms / (4.0 * mc * mc);
             }
         }
-    free(ckpt); free(fmem); free(amem); free(eps); free(gmuS);
+    free(ckpt); free(fmem); free(amem); free(eps); free(gmuS); free(dvb); free(gb);
     grid_free(&G);
     return 0;
 }
@@ -624,7 +680,7 @@ int orc_propagate(const orc_geom *g, const double *lam, const double *mu, const 
     size_t N = (size_t)G.NR * G.NZ;
     state s;
     state_bind(&s, st, N);
-    for (int n = 0; n < nsteps; ++n) fwd_step(&G, &s, g->src_k, 0.0, NULL);
+    for (int n = 0; n < nsteps; ++n) fwd_step(&G, &s, g->src_k, 0.0, NULL, NULL);
     grid_free(&G);
     return 0;
 }

@@ -63,11 +63,13 @@ double orc_misfit(int64_t n, const double *d, const double *dobs, double *resid)
  * segment storing the strain rates it used, correlates them with the adjoint
  * stresses.  Outputs (NR*NZ each, overwritten): glam = dJ/dlambda,
  * gmu = dJ/dmu (the tau_rz-node harmonic-mean chain rule included; cells with
- * mu <= 0 get only their own-node term), illum = sum_n dt |v|^2 at C nodes.
+ * mu <= 0 get only their own-node term), illum = sum_n dt |v|^2 at C nodes,
+ * grho (nullable) = dJ/drho through the buoyancies of the velocity update
+ * (density held fixed by the paper, inverted jointly as an extension).
  * Pinned by brute-force central differences and by dot-product tests. */
 int orc_gradient(const orc_geom *g, const double *lam, const double *mu, const double *rho,
                  const double *wavelet, const double *resid, int32_t seg,
-                 double *glam, double *gmu, double *illum);
+                 double *glam, double *gmu, double *illum, double *grho);
 
 /* Transpose of the map wavelet -> traces for a fixed model: wadj[n] =
  * d<traces, resid>/d wavelet[n].  Used by the source-to-trace dot-product test. */

@@ -156,3 +156,77 @@ def test_velocity_gradient_chain_rule_matches_differences():
     fd = (J(vp + eps * dvp, vs + eps * dvs) - J(vp - eps * dvp, vs - eps * dvs)) / (2 * eps)
     an = float((gvp * dvp).sum() + (gvs * dvs).sum())
     assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
+
+
+def _rho_setup(nr=12, nz=24, p=4, nt=150):
+    """Misfit against data from a model whose density differs from the
+    starting one, so dJ/drho is far from zero."""
+    w, sh, g = _tiny(nr=nr, nz=nz, p=p, nt=nt)
+    lam, mu, rho = oracle_models(w, 0, "start")
+    lt, mt, rt = oracle_models(w, 0, "true")
+    rng = np.random.default_rng(11)
+    rt = rt * (1.0 + 0.05 * rng.standard_normal(rt.shape))
+    dobs = oracle.forward(g, lt, mt, rt, sh.wavelet)
+
+    def J(r):
+        return oracle.misfit(oracle.forward(g, lam, mu, r, sh.wavelet), dobs)[0]
+
+    J0, res = oracle.misfit(oracle.forward(g, lam, mu, rho, sh.wavelet), dobs)
+    out = oracle.gradient(g, lam, mu, rho, sh.wavelet, res, seg=37, density=True)
+    base = oracle.gradient(g, lam, mu, rho, sh.wavelet, res, seg=37)
+    return g, lam, mu, rho, J, out, base
+
+
+@pytest.mark.slow
+def test_density_gradient_matches_central_differences_every_cell():
+    """dJ/drho by central differences at h = 1e-6 rho for every cell of the
+    padded grid: both buoyancy stencils (radial pair and axial pair), the
+    axis row, the clamped top row and the PML are each reached."""
+    g, lam, mu, rho, J, (gl, gm, il, gr), _ = _rho_setup()
+    scale = np.abs(gr).max()
+    assert scale > 0
+    bad = []
+    for i in range(g.NR):
+        for k in range(g.NZ):
+            h = 1e-6 * rho[i, k]
+            p, q = rho.copy(), rho.copy()
+            p[i, k] += h
+            q[i, k] -= h
+            fd = (J(p) - J(q)) / (2 * h)
+            if abs(fd - gr[i, k]) > 1e-6 * scale + 1e-5 * abs(fd):
+                bad.append((i, k, fd, gr[i, k]))
+    assert not bad, bad[:10]
+
+
+@pytest.mark.parametrize("region", ["formation", "fluid", "pml"])
+def test_density_gradient_directional_derivative(region):
+    g, lam, mu, rho, J, (gl, gm, il, gr), _ = _rho_setup()
+    NR, NZ = g.NR, g.NZ
+    ii, kk = np.meshgrid(np.arange(NR), np.arange(NZ), indexing="ij")
+    fluid = (mu == 0)
+    pml = (ii >= g.nr) | (kk < g.pz) | (kk >= g.pz + g.nz)
+    sel = {"formation": ~fluid & ~pml, "fluid": fluid & ~pml, "pml": pml}[region]
+    rng = np.random.default_rng(6)
+    d = rng.standard_normal((NR, NZ)) * sel * rho
+    eps = 1e-6
+    fd = (J(rho + eps * d) - J(rho - eps * d)) / (2 * eps)
+    an = float((gr * d).sum())
+    assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
+
+
+def test_density_output_leaves_modulus_gradients_unchanged():
+    """Asking for dJ/drho changes nothing else the gradient routine returns."""
+    g, lam, mu, rho, J, (gl, gm, il, gr), (bl, bm, bi) = _rho_setup()
+    assert np.array_equal(gl, bl) and np.array_equal(gm, bm) and np.array_equal(il, bi)
+
+
+def test_density_gradient_vanishes_for_zero_residual():
+    """With data generated from the same model the residual is zero and so is
+    every gradient, dJ/drho included."""
+    w, sh, g = _tiny(nr=10, nz=20, p=3, nt=80)
+    lam, mu, rho = oracle_models(w, 0, "start")
+    d = oracle.forward(g, lam, mu, rho, sh.wavelet)
+    J0, res = oracle.misfit(d, d)
+    assert J0 == 0.0
+    gl, gm, il, gr = oracle.gradient(g, lam, mu, rho, sh.wavelet, res, seg=20, density=True)
+    assert not gr.any()
