@@ -261,10 +261,13 @@ int bhfwi_starting_model(void *stream, int32_t NR, int32_t NZ, float dr, float a
 int bhfwi_moduli(void *stream, int64_t n, const float *vp, const float *vs, const float *rho,
                  float *lam, float *mu);
 /* Chain rule of Eq. 3-4 for a velocity parameterisation:
- * g_vp = 2 rho vp g_lam, g_vs = 2 rho vs (g_mu - 2 g_lam); n elements, device. */
+ * g_vp = 2 rho vp g_lam, g_vs = 2 rho vs (g_mu - 2 g_lam); n elements, device.
+ * g_rho (nullable; overwritten) receives the moduli's share of dJ/drho at
+ * fixed velocities, (vp^2 - 2 vs^2) g_lam + vs^2 g_mu, to be added to the
+ * buoyancy part from bhfwi_gradient_density for a (vp, vs, rho) inversion. */
 int bhfwi_moduli_grad(void *stream, int64_t n, const float *vp, const float *vs,
                       const float *rho, const float *g_lam, const float *g_mu, float *g_vp,
-                      float *g_vs);
+                      float *g_vs, float *g_rho);
 /* Eq. 11-12: vp = sqrt((lam + 2 mu)/rho), vs = sqrt(mu/rho). */
 int bhfwi_velocities(void *stream, int64_t n, const float *lam, const float *mu,
                      const float *rho, float *vp, float *vs);
@@ -307,6 +310,28 @@ int bhfwi_adjoint_model(bhfwi_ctx *ctx, void *stream, const float *lam, const fl
  * accumulate != 0 (contexts holding further groups of shots of one model). */
 int bhfwi_gradient(bhfwi_ctx *ctx, void *stream, const float *mu, const float *acc,
                    float *g_lam, float *g_mu, float *illum, int32_t accumulate);
+
+/* bhfwi_adjoint_model plus the density gradient.  The paper inverts lambda
+ * and mu with the density held fixed (Method section); this extension
+ * differentiates the misfit through the buoyancies of the velocity update of
+ * Eq. 2 as well, for joint inversion.  acc as for bhfwi_adjoint_model;
+ * acc_rho (device, 2 * cells floats, overwritten, not null) receives per shot
+ * b dJ/db at the v_r nodes (plane 0) and at the v_z nodes (plane 1), b the
+ * buoyancy of that node.  Same cost as bhfwi_adjoint_model plus two
+ * multiply-adds per node and step; no further history is stored. */
+int bhfwi_adjoint_model_density(bhfwi_ctx *ctx, void *stream, const float *lam,
+                                const float *mu, const float *rho, const float *wavelet,
+                                const float *resid, void *fwd_ws, int64_t fwd_ws_bytes,
+                                const void *ckpt, int64_t ckpt_bytes, void *adj_ws,
+                                int64_t adj_ws_bytes, float *acc, float *acc_rho);
+
+/* Density gradient finalize: with b_R = 2/(rho[i-1,k] + rho[i,k]) and
+ * b_Z = 2/(rho[i,k] + rho[i,k1]), k1 = min(k+1, NZ-1), every node adds
+ * -(b/2) (b dJ/db) to each of its two cells; gathered per cell and summed
+ * over shots in shot order (deterministic).  g_rho (device, model_len)
+ * overwritten, or added to when accumulate != 0. */
+int bhfwi_gradient_density(bhfwi_ctx *ctx, void *stream, const float *rho,
+                           const float *acc_rho, float *g_rho, int32_t accumulate);
 
 /* Diagonal preconditioner (Numerical Examples section, Fig. 6): with
  * E = illum and Emax its maximum over mask cells, g <- g / (E + eps Emax) for

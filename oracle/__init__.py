@@ -58,7 +58,7 @@ def _load():
         G = C.POINTER(_Geom)
         lib.orc_moduli.argtypes = [C.c_int64, _D, _D, _D, _D, _D]
         lib.orc_velocities.argtypes = [C.c_int64, _D, _D, _D, _D, _D]
-        lib.orc_moduli_grad.argtypes = [C.c_int64, _D, _D, _D, _D, _D, _D, _D]
+        lib.orc_moduli_grad.argtypes = [C.c_int64, _D, _D, _D, _D, _D, _D, _D, _D]
         lib.orc_forward.argtypes = [G, _D, _D, _D, _D, _D, _D]
         lib.orc_forward.restype = C.c_int
         lib.orc_misfit.argtypes = [C.c_int64, _D, _D, _D]
@@ -147,12 +147,15 @@ def moduli(vp, vs, rho):
     return lam, mu
 
 
-def moduli_grad(vp, vs, rho, glam, gmu):
-    """Chain rule of Eq. 3-4: (dJ/dVp, dJ/dVs) from (dJ/dlambda, dJ/dmu)."""
+def moduli_grad(vp, vs, rho, glam, gmu, density=False):
+    """Chain rule of Eq. 3-4: (dJ/dVp, dJ/dVs) from (dJ/dlambda, dJ/dmu); with
+    density=True also the moduli's share of dJ/drho at fixed velocities."""
     vp, vs, rho, gl, gm = (_f64(a) for a in (vp, vs, rho, glam, gmu))
     gvp, gvs = np.empty_like(vp), np.empty_like(vp)
-    _load().orc_moduli_grad(vp.size, _p(vp), _p(vs), _p(rho), _p(gl), _p(gm), _p(gvp), _p(gvs))
-    return gvp, gvs
+    gr = np.empty_like(vp) if density else None
+    _load().orc_moduli_grad(vp.size, _p(vp), _p(vs), _p(rho), _p(gl), _p(gm), _p(gvp), _p(gvs),
+                            _p(gr) if density else None)
+    return (gvp, gvs, gr) if density else (gvp, gvs)
 
 
 def velocities(lam, mu, rho):

@@ -457,7 +457,8 @@ void orc_moduli(int64_t n, const double *vp, const double *vs, const double *rho
 }
 
 void orc_moduli_grad(int64_t n, const double *vp, const double *vs, const double *rho,
-                     const double *glam, const double *gmu, double *gvp, double *gvs)
+                     const double *glam, const double *gmu, double *gvp, double *gvs,
+                     double *grho)
 {
     for (int64_t c = 0; c < n; ++c) {
         /* lambda = rho vp^2 - 2 rho vs^2, mu = rho vs^2 */
@@ -466,6 +467,11 @@ void orc_moduli_grad(int64_t n, const double *vp, const double *vs, const double
         double dm_dvs = 2.0 * rho[c] * vs[c];
         gvp[c] = dl_dvp * glam[c];
         gvs[c] = dl_dvs * glam[c] + dm_dvs * gmu[c];
+        if (grho) {
+            double dl_drho = vp[c] * vp[c] - 2.0 * vs[c] * vs[c];
+            double dm_drho = vs[c] * vs[c];
+            grho[c] = dl_drho * glam[c] + dm_drho * gmu[c];
+        }
     }
 }
 

@@ -41,10 +41,13 @@ typedef struct {
 void orc_moduli(int64_t n, const double *vp, const double *vs, const double *rho,
                 double *lam, double *mu);
 /* Chain rule of Eq. 3-4: dJ/dVp = 2 rho Vp dJ/dlambda,
- * dJ/dVs = -4 rho Vs dJ/dlambda + 2 rho Vs dJ/dmu.  Pinned by central
- * differences of the misfit in velocity space. */
+ * dJ/dVs = -4 rho Vs dJ/dlambda + 2 rho Vs dJ/dmu, and (grho nullable) the
+ * moduli's share of dJ/drho at fixed velocities,
+ * (Vp^2 - 2 Vs^2) dJ/dlambda + Vs^2 dJ/dmu.  Pinned by central differences
+ * of the misfit in velocity space. */
 void orc_moduli_grad(int64_t n, const double *vp, const double *vs, const double *rho,
-                     const double *glam, const double *gmu, double *gvp, double *gvs);
+                     const double *glam, const double *gmu, double *gvp, double *gvs,
+                     double *grho);
 /* Eq. 11-12: Vp = sqrt((lambda+2mu)/rho), Vs = sqrt(mu/rho). */
 void orc_velocities(int64_t n, const double *lam, const double *mu, const double *rho,
                     double *vp, double *vs);

@@ -80,7 +80,7 @@ EXPORTS = ["bhfwi_create", "bhfwi_destroy", "bhfwi_last_error", "bhfwi_sizes",
            "bhfwi_fwd_model", "bhfwi_misfit", "bhfwi_adjoint_model", "bhfwi_gradient",
            "bhfwi_precondition", "bhfwi_status", "bhfwi_line_search", "bhfwi_update", "bhfwi_plan_bytes",
            "bhfwi_plan", "bhfwi_kernel_shapes", "bhfwi_semblance", "bhfwi_semblance_pick",
-           "bhfwi_starting_model"]
+           "bhfwi_starting_model", "bhfwi_adjoint_model_density", "bhfwi_gradient_density"]
 
 _lib = None
 
@@ -108,11 +108,14 @@ def load(path: str = LIB_PATH):
                                  C.POINTER(C.c_float)]
     L.bhfwi_moduli.argtypes = [V, I64, P, P, P, P, P]
     L.bhfwi_velocities.argtypes = [V, I64, P, P, P, P, P]
-    L.bhfwi_moduli_grad.argtypes = [V, I64, P, P, P, P, P, P, P]
+    L.bhfwi_moduli_grad.argtypes = [V, I64, P, P, P, P, P, P, P, P]
     L.bhfwi_fwd_model.argtypes = [P, V, P, P, P, P, P, P, I64, P, I64, I32]
     L.bhfwi_misfit.argtypes = [P, V, P, P, P, P, I32]
     L.bhfwi_adjoint_model.argtypes = [P, V, P, P, P, P, P, P, I64, P, I64, P, I64, P]
     L.bhfwi_gradient.argtypes = [P, V, P, P, P, P, P, I32]
+    L.bhfwi_adjoint_model_density.argtypes = [P, V, P, P, P, P, P, P, I64, P, I64, P, I64, P,
+                                              P]
+    L.bhfwi_gradient_density.argtypes = [P, V, P, P, P, I32]
     L.bhfwi_precondition.argtypes = [P, V, I64, P, P, F, P, P, P]
     L.bhfwi_line_search.argtypes = [P, V, P, P, P, P, P]
     L.bhfwi_status.argtypes = [P, V]
@@ -173,12 +176,15 @@ def moduli(vp, vs, rho, out=None):
     return lam, mu
 
 
-def moduli_grad(vp, vs, rho, g_lam, g_mu):
-    """Chain rule of Eq. 3-4: (g_vp, g_vs) from (g_lam, g_mu)."""
+def moduli_grad(vp, vs, rho, g_lam, g_mu, density=False):
+    """Chain rule of Eq. 3-4: (g_vp, g_vs) from (g_lam, g_mu); with density=True
+    also the moduli's share of dJ/drho at fixed velocities."""
     g_vp, g_vs = torch.empty_like(vp), torch.empty_like(vp)
+    g_rho = torch.empty_like(vp) if density else None
     _check(load().bhfwi_moduli_grad(_stream(), vp.numel(), _f32(vp), _f32(vs), _f32(rho),
-                                    _f32(g_lam), _f32(g_mu), _f32(g_vp), _f32(g_vs)))
-    return g_vp, g_vs
+                                    _f32(g_lam), _f32(g_mu), _f32(g_vp), _f32(g_vs),
+                                    _f32(g_rho) if density else None))
+    return (g_vp, g_vs, g_rho) if density else (g_vp, g_vs)
 
 
 def semblance(traces, dt, offset, p0, dp, np_, tau_stride, ntau, win, energy=False):
@@ -469,6 +475,38 @@ class Survey:
             _ptr(ckpt), ckpt.numel(), _ptr(aw), aw.numel(), _f32(acc, z.acc_elems))
         _check(rc, self._h)
         return acc
+
+    def adjoint_model_density(self, lam, mu, rho, wavelet, resid, ckpt=None, acc=None,
+                              acc_rho=None):
+        """adjoint_model plus the density correlation: returns (acc, acc_rho),
+        acc_rho [2, cells] = b dJ/db at the v_r and v_z nodes."""
+        z = self.sizes
+        if acc is None:
+            acc = torch.empty(z.acc_elems, dtype=torch.float32, device=self.device)
+        if acc_rho is None:
+            acc_rho = torch.empty(2 * z.cells, dtype=torch.float32, device=self.device)
+        if ckpt is None:
+            ckpt = self.workspace("ckpt")
+        fw, aw = self.workspace("fwd"), self.workspace("adj")
+        n = self.model_shape[0] * self.model_shape[1]
+        rc = load().bhfwi_adjoint_model_density(
+            self._h, _stream(), _f32(lam, n), _f32(mu, n), _f32(rho, n),
+            _f32(wavelet, z.wavelet_elems), _f32(resid, z.trace_elems), _ptr(fw), fw.numel(),
+            _ptr(ckpt), ckpt.numel(), _ptr(aw), aw.numel(), _f32(acc, z.acc_elems),
+            _f32(acc_rho, 2 * z.cells))
+        _check(rc, self._h)
+        return acc, acc_rho
+
+    def gradient_density(self, rho, acc_rho, out=None, accumulate=False):
+        """dJ/drho on the global grid from adjoint_model_density's acc_rho
+        (added to `out` when accumulate)."""
+        if out is None:
+            out = torch.empty(self.model_shape, dtype=torch.float32, device=self.device)
+        n = self.model_shape[0] * self.model_shape[1]
+        _check(load().bhfwi_gradient_density(self._h, _stream(), _f32(rho, n),
+                                             _f32(acc_rho, 2 * self.sizes.cells), _f32(out, n),
+                                             1 if accumulate else 0), self._h)
+        return out
 
     def gradient(self, mu, acc, out=None, accumulate=False):
         """Gradient finalize: returns (g_lam, g_mu, illum) on the global grid

@@ -7,6 +7,8 @@ Eq. 1 it is the residual of Eq. 5); the adjoint kernels recompute each
 checkpoint segment and correlate (Eq. 6-8); the finalize kernel returns
 dJ/dlambda and dJ/dmu on the global model grid.  The illumination of the
 same pass is left on the survey as ``last_illum`` for the preconditioner.
+When rho requires grad the density correlation runs in the same adjoint pass
+(joint inversion, an extension of the paper's fixed density).
 """
 from __future__ import annotations
 
@@ -18,23 +20,29 @@ class BoreholeFWI(torch.autograd.Function):
     def forward(ctx, lam, mu, survey, rho, wavelet):
         z = survey.sizes
         ckpt = torch.empty(max(1, z.ckpt_bytes), dtype=torch.uint8, device=lam.device)
-        traces = survey.fwd_model(lam.detach(), mu.detach(), rho, wavelet, store_ckpt=True,
-                                  ckpt=ckpt)
+        traces = survey.fwd_model(lam.detach(), mu.detach(), rho.detach(), wavelet,
+                                  store_ckpt=True, ckpt=ckpt)
         ctx.survey = survey
         ctx.ckpt = ckpt
-        ctx.save_for_backward(lam.detach(), mu.detach(), rho, wavelet)
+        ctx.save_for_backward(lam.detach(), mu.detach(), rho.detach(), wavelet)
         return traces
 
     @staticmethod
     def backward(ctx, grad_traces):
         lam, mu, rho, wavelet = ctx.saved_tensors
         survey = ctx.survey
-        acc = survey.adjoint_model(lam, mu, rho, wavelet, grad_traces.contiguous().float(),
-                                   ckpt=ctx.ckpt)
+        resid = grad_traces.contiguous().float()
+        g_rho = None
+        if ctx.needs_input_grad[3]:
+            acc, acc_rho = survey.adjoint_model_density(lam, mu, rho, wavelet, resid,
+                                                        ckpt=ctx.ckpt)
+            g_rho = survey.gradient_density(rho, acc_rho)
+        else:
+            acc = survey.adjoint_model(lam, mu, rho, wavelet, resid, ckpt=ctx.ckpt)
         g_lam, g_mu, illum = survey.gradient(mu, acc)
         survey.last_illum = illum
         ctx.ckpt = None
-        return g_lam, g_mu, None, None, None
+        return g_lam, g_mu, None, g_rho, None
 
 
 class Moduli(torch.autograd.Function):
@@ -44,8 +52,9 @@ class Moduli(torch.autograd.Function):
     @staticmethod
     def forward(ctx, vp, vs, rho):
         from ._lib import moduli
-        lam, mu = moduli(vp.detach().contiguous(), vs.detach().contiguous(), rho)
-        ctx.save_for_backward(vp.detach(), vs.detach(), rho)
+        lam, mu = moduli(vp.detach().contiguous(), vs.detach().contiguous(),
+                         rho.detach().contiguous())
+        ctx.save_for_backward(vp.detach(), vs.detach(), rho.detach())
         return lam, mu
 
     @staticmethod
@@ -56,5 +65,9 @@ class Moduli(torch.autograd.Function):
             g_lam = torch.zeros_like(vp)
         if g_mu is None:
             g_mu = torch.zeros_like(vp)
+        if ctx.needs_input_grad[2]:
+            g_vp, g_vs, g_rho = moduli_grad(vp, vs, rho, g_lam.contiguous(), g_mu.contiguous(),
+                                            density=True)
+            return g_vp, g_vs, g_rho
         g_vp, g_vs = moduli_grad(vp, vs, rho, g_lam.contiguous(), g_mu.contiguous())
         return g_vp, g_vs, None

@@ -394,7 +394,7 @@ void fwd_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const flo
 
 void adj_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const float* mu,
                 const float* rho, const float* resid, const float* in, float* out,
-                const float* hist, float* acc)
+                const float* hist, float* acc, float* acc_rho)
 {
     const int nact = active_items(c, n);
     if (nact <= 0) return;
@@ -402,7 +402,8 @@ void adj_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const flo
     EvScope ev(c, st, 2);
     BHFWI_DISPATCH(c->tune.rows_per_wave, bhfwi::k_adj_step, dim3((nact + wpb - 1) / wpb),
                    dim3(64 * wpb), 0, st, c->d_shots, c->d_work, nact, n, lam, mu, rho, c->d_rec,
-                   resid, c->d_pml_r, c->d_pml_z, in, out, hist, acc, (long long)c->cells);
+                   resid, c->d_pml_r, c->d_pml_z, in, out, hist, acc, acc_rho,
+                   (long long)c->cells);
 }
 
 // Supported temporally blocked shapes: (steps T, tile rows incl. halo,
@@ -534,21 +535,28 @@ void fwd_tb_launch(bhfwi_ctx* c, hipStream_t st, int n0, int nsteps, const float
 
 #define BHFWI_TBA(TT, RR, WW)                                                                \
     if (T == TT && TRE == RR && W == WW) {                                                   \
-        hipLaunchKernelGGL((bhfwi::k_adj_tb<TT, RR, WW, PMV>), dim3(nact), dim3(64 * WW), 0, \
-                           fork.stream(q), c->d_shots, c->atiles.d[q], nact,                 \
-                           c->tune.tile_map, n_hi,                                           \
-                           nsteps, lam, mu, rho, c->d_rec, resid, c->d_pml_r, c->d_pml_z,    \
-                           in, out, hist_hi, (long long)(2 * c->cells), acc,                \
-                           (long long)c->cells);                                             \
+        if (acc_rho)                                                                         \
+            hipLaunchKernelGGL((bhfwi::k_adj_tb<TT, RR, WW, PMV, 1>), dim3(nact),            \
+                               dim3(64 * WW), 0, fork.stream(q), c->d_shots, c->atiles.d[q], \
+                               nact, c->tune.tile_map, n_hi, nsteps, lam, mu, rho, c->d_rec, \
+                               resid, c->d_pml_r, c->d_pml_z, in, out, hist_hi,              \
+                               (long long)(2 * c->cells), acc, acc_rho, (long long)c->cells); \
+        else                                                                                 \
+            hipLaunchKernelGGL((bhfwi::k_adj_tb<TT, RR, WW, PMV, 0>), dim3(nact),            \
+                               dim3(64 * WW), 0, fork.stream(q), c->d_shots, c->atiles.d[q], \
+                               nact, c->tune.tile_map, n_hi, nsteps, lam, mu, rho, c->d_rec, \
+                               resid, c->d_pml_r, c->d_pml_z, in, out, hist_hi,              \
+                               (long long)(2 * c->cells), acc, nullptr, (long long)c->cells); \
         continue;                                                                            \
     }
 
 // nsteps (<= the adjoint shape's T) adjoint steps n_hi, n_hi - 1, ... in
 // LDS-tiled kernels (interior tiles, then PML sub-tiles); hist_hi is the
-// history slot of step n_hi.
+// history slot of step n_hi; acc_rho (nullable) selects the kernels that also
+// accumulate the density correlation.
 void adj_tb_launch(bhfwi_ctx* c, hipStream_t st, int n_hi, int nsteps, const float* lam,
                    const float* mu, const float* rho, const float* resid, const float* in,
-                   float* out, const float* hist_hi, float* acc)
+                   float* out, const float* hist_hi, float* acc, float* acc_rho)
 {
     const int n_lo = n_hi - nsteps + 1;
     const int na[2] = {active_tiles(c->atiles, 0, n_lo), active_tiles(c->atiles, 1, n_lo)};
@@ -575,7 +583,7 @@ void adj_tb_launch(bhfwi_ctx* c, hipStream_t st, int n_hi, int nsteps, const flo
 // ab[(*m + 1) & 1]; hist holds v of step n at slot n - n0.
 void adj_range(bhfwi_ctx* c, hipStream_t st, int n0, int n1, const float* lam, const float* mu,
                const float* rho, const float* resid, float* const ab[2], int* m,
-               const float* hist, float* acc)
+               const float* hist, float* acc, float* acc_rho)
 {
     const int64_t hslot = 2 * c->cells;
     const Shape sh = adj_shape(c);
@@ -583,14 +591,14 @@ void adj_range(bhfwi_ctx* c, hipStream_t st, int n0, int n1, const float* lam, c
         for (int n = n1 - 1; n >= n0;) {
             const int nb = std::min(sh.T, n - n0 + 1);
             adj_tb_launch(c, st, n, nb, lam, mu, rho, resid, ab[*m & 1], ab[(*m + 1) & 1],
-                          hist + (int64_t)(n - n0) * hslot, acc);
+                          hist + (int64_t)(n - n0) * hslot, acc, acc_rho);
             ++*m;
             n -= nb;
         }
     } else {
         for (int n = n1 - 1; n >= n0; --n, ++*m)
             adj_launch(c, st, n, lam, mu, rho, resid, ab[*m & 1], ab[(*m + 1) & 1],
-                       hist + (int64_t)(n - n0) * hslot, acc);
+                       hist + (int64_t)(n - n0) * hslot, acc, acc_rho);
     }
 }
 
@@ -1044,7 +1052,7 @@ int bhfwi_autotune(bhfwi_ctx* c, void* stream, const float* lam, const float* mu
     auto run_adj = [&]() {
         launch_fill(st, ab[0], 2 * c->ast_len, 0.0f);
         int m = 0;
-        adj_range(c, st, 0, P, lam, mu, rho, traces, ab, &m, hist, acc);
+        adj_range(c, st, 0, P, lam, mu, rho, traces, ab, &m, hist, acc, nullptr);
     };
     // best of repetitions 2 and 3 of `phase` (the first warms up)
     auto time_it = [&](auto&& phase, float* out, int reps) {
@@ -1194,13 +1202,13 @@ int bhfwi_moduli(void* stream, int64_t n, const float* vp, const float* vs, cons
 
 int bhfwi_moduli_grad(void* stream, int64_t n, const float* vp, const float* vs,
                       const float* rho, const float* g_lam, const float* g_mu, float* g_vp,
-                      float* g_vs)
+                      float* g_vs, float* g_rho)
 {
     if (n < 0 || (n > 0 && (!vp || !vs || !rho || !g_lam || !g_mu || !g_vp || !g_vs)))
         return BHFWI_EINVAL;
     if (n == 0) return BHFWI_OK;
     hipLaunchKernelGGL(bhfwi::k_moduli_grad, dim3(grid1d(n)), dim3(256), 0, (hipStream_t)stream,
-                       (long long)n, vp, vs, rho, g_lam, g_mu, g_vp, g_vs);
+                       (long long)n, vp, vs, rho, g_lam, g_mu, g_vp, g_vs, g_rho);
     return hipGetLastError() == hipSuccess ? BHFWI_OK : BHFWI_EHIP;
 }
 
@@ -1269,10 +1277,14 @@ int bhfwi_misfit(bhfwi_ctx* c, void* stream, const float* traces, const float* o
     return BHFWI_OK;
 }
 
-int bhfwi_adjoint_model(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
-                        const float* rho, const float* wavelet, const float* resid,
-                        void* fwd_ws, int64_t fwd_ws_bytes, const void* ckpt,
-                        int64_t ckpt_bytes, void* adj_ws, int64_t adj_ws_bytes, float* acc)
+namespace {
+
+// Shared body of bhfwi_adjoint_model and bhfwi_adjoint_model_density
+// (acc_rho null for the former).
+int adjoint_impl(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
+                 const float* rho, const float* wavelet, const float* resid, void* fwd_ws,
+                 int64_t fwd_ws_bytes, const void* ckpt, int64_t ckpt_bytes, void* adj_ws,
+                 int64_t adj_ws_bytes, float* acc, float* acc_rho)
 {
     if (int rc = check_ctx(c)) return rc;
     bhfwi_sizes_t z;
@@ -1297,6 +1309,7 @@ int bhfwi_adjoint_model(bhfwi_ctx* c, void* stream, const float* lam, const floa
         launch_fill(s, fb[0], 2 * c->fst_len, 0.0f);
         launch_fill(s, ab[0], 2 * c->ast_len, 0.0f);
         launch_fill(s, acc, 4 * c->cells, 0.0f);
+        if (acc_rho) launch_fill(s, acc_rho, 2 * c->cells, 0.0f);
         int m = 0;
         for (int j = c->nseg - 1; j >= 0; --j) {
             const int n0 = j * K, n1 = std::min(n0 + K, c->nt_max);
@@ -1307,14 +1320,53 @@ int bhfwi_adjoint_model(bhfwi_ctx* c, void* stream, const float* lam, const floa
                                      sizeof(float) * c->fst_len, hipMemcpyDeviceToDevice, s);
             int parity = 0;
             fwd_range(c, s, n0, n1, lam, mu, rho, wavelet, fbc, &parity, nullptr, hist, n0);
-            adj_range(c, s, n0, n1, lam, mu, rho, resid, ab, &m, hist, acc);
+            adj_range(c, s, n0, n1, lam, mu, rho, resid, ab, &m, hist, acc, acc_rho);
         }
     };
     return run_sequence(c, st,
                         {2, (uintptr_t)lam, (uintptr_t)mu, (uintptr_t)rho, (uintptr_t)wavelet,
                          (uintptr_t)resid, (uintptr_t)fwd_ws, (uintptr_t)ckpt, (uintptr_t)adj_ws,
-                         (uintptr_t)acc},
+                         (uintptr_t)acc, (uintptr_t)acc_rho},
                         record);
+}
+
+}  // namespace
+
+int bhfwi_adjoint_model(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
+                        const float* rho, const float* wavelet, const float* resid,
+                        void* fwd_ws, int64_t fwd_ws_bytes, const void* ckpt,
+                        int64_t ckpt_bytes, void* adj_ws, int64_t adj_ws_bytes, float* acc)
+{
+    return adjoint_impl(c, stream, lam, mu, rho, wavelet, resid, fwd_ws, fwd_ws_bytes, ckpt,
+                        ckpt_bytes, adj_ws, adj_ws_bytes, acc, nullptr);
+}
+
+int bhfwi_adjoint_model_density(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
+                                const float* rho, const float* wavelet, const float* resid,
+                                void* fwd_ws, int64_t fwd_ws_bytes, const void* ckpt,
+                                int64_t ckpt_bytes, void* adj_ws, int64_t adj_ws_bytes,
+                                float* acc, float* acc_rho)
+{
+    if (int rc = check_ctx(c)) return rc;
+    if (!acc_rho) return fail(c, BHFWI_EINVAL, "adjoint_model_density: null acc_rho");
+    return adjoint_impl(c, stream, lam, mu, rho, wavelet, resid, fwd_ws, fwd_ws_bytes, ckpt,
+                        ckpt_bytes, adj_ws, adj_ws_bytes, acc, acc_rho);
+}
+
+int bhfwi_gradient_density(bhfwi_ctx* c, void* stream, const float* rho, const float* acc_rho,
+                           float* g_rho, int32_t accumulate)
+{
+    if (int rc = check_ctx(c)) return rc;
+    if (!rho || !acc_rho || !g_rho) return fail(c, BHFWI_EINVAL, "gradient_density: null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    if (!accumulate) launch_fill(st, g_rho, c->model_len, 0.0f);
+    for (int s = 0; s < c->nshot; ++s) {
+        const int64_t cells = (int64_t)c->sd[s].NR * c->sd[s].NZ;
+        hipLaunchKernelGGL(bhfwi::k_finalize_rho_shot, dim3(grid1d(cells)), dim3(256), 0, st,
+                           c->d_shots, s, rho, acc_rho, (long long)c->cells, g_rho);
+    }
+    HIPOK(c, hipGetLastError());
+    return BHFWI_OK;
 }
 
 int bhfwi_gradient(bhfwi_ctx* c, void* stream, const float* mu, const float* acc, float* g_lam,

@@ -317,7 +317,7 @@ k_adj_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
            const float* __restrict__ resid, const float* __restrict__ pml_r,
            const float* __restrict__ pml_z, const float* __restrict__ ain,
            float* __restrict__ aout, const float* __restrict__ hist, float* __restrict__ acc,
-           long long cells_total)
+           float* __restrict__ acc_rho, long long cells_total)
 {
     int w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     w = __builtin_amdgcn_readfirstlane(w);
@@ -511,6 +511,8 @@ k_adj_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
                 aDz += a_zi * qv;
             }
             if (own_ip) Ao[oVR + c] = avr;
+            // density correlation (optional): increment of a_v times v^{n+1/2}
+            if (acc_rho && own_ip) acc_rho[S.cell_off + c] += (avr - Q.avr) * Q.vrh;
             R1_aDr = aDr;
             R1_aDzR = aDz;
             R1_hR = W * (0.5f / (ip * dr));
@@ -536,6 +538,7 @@ k_adj_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
                 aDz += a_zh * qv;
             }
             if (own_i) Ao[oVZ + c] = avz;
+            if (acc_rho && own_i) acc_rho[cells_total + S.cell_off + c] += (avz - P.avz) * P.vzh;
             Z_aDrZ = aDr;
             Z_WZ = W;
             Z_aDzZ = aDz;
@@ -660,13 +663,16 @@ __global__ void k_moduli(long long n, const float* __restrict__ vp, const float*
 __global__ void k_moduli_grad(long long n, const float* __restrict__ vp,
                               const float* __restrict__ vs, const float* __restrict__ rho,
                               const float* __restrict__ g_lam, const float* __restrict__ g_mu,
-                              float* __restrict__ g_vp, float* __restrict__ g_vs)
+                              float* __restrict__ g_vp, float* __restrict__ g_vs,
+                              float* __restrict__ g_rho)
 {
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const float r2 = 2.0f * rho[i], gl = g_lam[i];
-        g_vp[i] = r2 * vp[i] * gl;
-        g_vs[i] = r2 * vs[i] * (g_mu[i] - 2.0f * gl);
+        const float r2 = 2.0f * rho[i], gl = g_lam[i], gm = g_mu[i];
+        const float a = vp[i], b = vs[i];
+        g_vp[i] = r2 * a * gl;
+        g_vs[i] = r2 * b * (gm - 2.0f * gl);
+        if (g_rho) g_rho[i] = (a * a - 2.0f * b * b) * gl + b * b * gm;
     }
 }
 
@@ -765,6 +771,40 @@ __global__ void k_finalize_shot(const ShotDev* __restrict__ shots, int s,
         g_lam[m] += gl[c];
         g_mu[m] += gm[c] + fold;
         illum[m] += ge[c];
+    }
+}
+
+// Add one shot's density correlation into the global dJ/drho.  acc_rho holds
+// b dJ/db at the R nodes (plane 0) and the Z nodes (plane 1); with
+// b_R = 2/(rho[i-1,k] + rho[i,k]) and b_Z = 2/(rho[i,k] + rho[i,k1])
+// (k1 = min(k+1, NZ-1)) each node adds -(b/2) (b dJ/db) to both of its cells.
+// Gathered per cell, so no atomics: the R nodes (i,k) and (i+1,k), the Z
+// nodes (i,k) and (i,k-1); on the top row k1 = k and the own Z node counts
+// twice.
+__global__ void k_finalize_rho_shot(const ShotDev* __restrict__ shots, int s,
+                                    const float* __restrict__ rho,
+                                    const float* __restrict__ acc_rho, long long cells_total,
+                                    float* __restrict__ g_rho)
+{
+    const ShotDev& S = shots[s];
+    const int NR = S.NR, NZ = S.NZ;
+    const long long cells = (long long)NR * NZ;
+    const float* sR = acc_rho + S.cell_off;
+    const float* sZ = acc_rho + cells_total + S.cell_off;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += stride) {
+        const int i = (int)(c / NZ), k = (int)(c % NZ);
+        auto R = [&](int ii, int kk) {
+            return rho[S.model_off + (long long)ii * S.model_ld + kk];
+        };
+        const float r0 = R(i, k);
+        float g = 0.f;
+        if (i >= 1) g -= sR[c] / (R(i - 1, k) + r0);
+        if (i + 1 < NR) g -= sR[c + NZ] / (r0 + R(i + 1, k));
+        const int k1 = (k + 1 < NZ) ? k + 1 : k;
+        g -= (k1 == k ? 2.0f : 1.0f) * sZ[c] / (r0 + R(i, k1));
+        if (k >= 1) g -= sZ[c - 1] / (R(i, k - 1) + r0);
+        g_rho[S.model_off + (long long)i * S.model_ld + k] += g;
     }
 }
 

@@ -20,13 +20,23 @@
 // are added to the accumulators once per launch (owned cells only).  As in
 // the forward kernel the step loop has no per-cell branches: zero
 // coefficients keep cells outside the grid and the axis nodes inert.
+//
+// RHO = 1 adds the density correlation (an extension: the paper holds the
+// density fixed).  The velocity update is v^{n+1/2} = v^{n-1/2} + b dv_n with
+// buoyancy b, so dJ/db = sum_n a_v^n dv_n with a_v^n the adjoint velocity
+// after the transposed stress update of step n.  Summed by parts, with
+// a_v^{nt} = 0 and v^{-1/2} = 0, b dJ/db = sum_n (a_v^n - a_v^{n+1}) v^{n+1/2},
+// and a_v^n - a_v^{n+1} is exactly the phase-B increment of a_v (the
+// transposed velocity update leaves a_v unchanged).  The kernel accumulates
+// that increment times the stored v^{n+1/2} at the R and Z nodes, so no
+// history beyond the velocities already kept is needed.
 #pragma once
 #include "bhfwi_internal.h"
 #include "bhfwi_tb_fwd.hip"
 
 namespace bhfwi {
 
-template <int T, int TRE, int W, int PM>
+template <int T, int TRE, int W, int PM, int RHO>
 __global__ void __launch_bounds__(64 * W, (W >= 16 && (TRE == W || (PM == 0 && TRE <= 2 * W))) ? 8 : 1)
 k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int nwork, int map,
          int n_hi, int nsteps, const float* __restrict__ lam, const float* __restrict__ mu,
@@ -34,7 +44,7 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
          const float* __restrict__ resid, const float* __restrict__ pml_r,
          const float* __restrict__ pml_z, const float* __restrict__ ain,
          float* __restrict__ aout, const float* __restrict__ hist_hi, long long hist_stride,
-         float* __restrict__ acc, long long cells_total)
+         float* __restrict__ acc, float* __restrict__ acc_rho, long long cells_total)
 {
     static_assert(TRE % W == 0 && TRE > 2 * T && 64 > 2 * T, "tile too small for the halo");
     constexpr int RPT = TRE / W;
@@ -92,6 +102,7 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
         pH[RPT];
     float a_ri[RPT], b_ri[RPT], a_rh[RPT], b_rh[RPT];
     float gl[RPT], gm[RPT], gs[RPT], ge[RPT];
+    float gR[RPT], gZ[RPT];  // density correlation (RHO = 1)
     float a_zi = 0.f, b_zi = 1.f, a_zh = 0.f, b_zh = 1.f;
     if (zp) {
         a_zi = pzt[k];
@@ -137,6 +148,7 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
         a_ri[j] = a_rh[j] = 0.f;
         b_ri[j] = b_rh[j] = 1.f;
         gl[j] = gm[j] = gs[j] = ge[j] = 0.f;
+        gR[j] = gZ[j] = 0.f;
         if (tile_pml) {
             if (iin && i >= nr) {
                 a_ri[j] = prt[i];
@@ -290,10 +302,17 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
                 gs[j] += dt * dgs;
                 ge[j] += dt * (ur * ur + uz * uz);
                 // transposed stress update into a_v, then the transposed velocity update
-                avr[j] += mrow[j] * ((L[ERR][x - 64] - Err_[j]) * idr + L[ETT][x - 64] * rRm[j] +
-                                     Ett_[j] * rZ[j] + (from_lane_below(Ez_[j]) - Ez_[j]) * idz);
-                avz[j] += (Ezz_[j] - from_lane_above(Ezz_[j])) * idz +
-                          (Er_[j] - L[ER][x + 64]) * idr;
+                const float dar =
+                    mrow[j] * ((L[ERR][x - 64] - Err_[j]) * idr + L[ETT][x - 64] * rRm[j] +
+                               Ett_[j] * rZ[j] + (from_lane_below(Ez_[j]) - Ez_[j]) * idz);
+                const float daz = (Ezz_[j] - from_lane_above(Ezz_[j])) * idz +
+                                  (Er_[j] - L[ER][x + 64]) * idr;
+                avr[j] += dar;
+                avz[j] += daz;
+                if constexpr (RHO != 0) {
+                    gR[j] += dar * vr0;
+                    gZ[j] += daz * vz0;
+                }
                 const float W1 = dbR[j] * avr[j];
                 float aDr = W1, aDzR = W1;
                 const float W2 = dbZ[j] * avz[j];
@@ -379,6 +398,11 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
         g[cells_total] += gm[j];
         if (i >= 1) g[2 * cells_total] += gs[j];
         g[3 * cells_total] += ge[j];
+        if constexpr (RHO != 0) {
+            float* gr = acc_rho + S.cell_off + c;
+            if (i >= 1) gr[0] += gR[j];
+            gr[cells_total] += gZ[j];
+        }
     }
 }
 

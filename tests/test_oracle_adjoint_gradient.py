@@ -230,3 +230,39 @@ def test_density_gradient_vanishes_for_zero_residual():
     assert J0 == 0.0
     gl, gm, il, gr = oracle.gradient(g, lam, mu, rho, sh.wavelet, res, seg=20, density=True)
     assert not gr.any()
+
+
+def test_velocity_density_parameterisation_matches_central_differences():
+    """Joint (Vp, Vs, rho): the density enters both through the moduli of
+    Eq. 3-4 and through the buoyancies; dJ/drho at fixed velocities is the
+    moduli's share plus the buoyancy part.  Directional central differences
+    along a perturbation of all three on formation cells."""
+    w, sh, g = _tiny(nr=12, nz=24, p=4, nt=150)
+    lt, mt, rt = oracle_models(w, 0, "true")
+    rt = rt * (1.0 + 0.05 * np.random.default_rng(12).standard_normal(rt.shape))
+    dobs = oracle.forward(g, lt, mt, rt, sh.wavelet)
+
+    def J(vp, vs, r):
+        lam, mu = oracle.moduli(vp, vs, r)
+        return oracle.misfit(oracle.forward(g, lam, mu, r, sh.wavelet), dobs)[0]
+
+    vp, vs, rho = w.vp_start.copy(), w.vs_start.copy(), np.ascontiguousarray(w.rho)
+    lam, mu = oracle.moduli(vp, vs, rho)
+    _, r = oracle.misfit(oracle.forward(g, lam, mu, rho, sh.wavelet), dobs)
+    gl, gm, _, grb = oracle.gradient(g, lam, mu, rho, sh.wavelet, r, seg=40, density=True)
+    gvp, gvs, grm = oracle.moduli_grad(vp, vs, rho, gl, gm, density=True)
+    grho = grm + grb
+    rng = np.random.default_rng(9)
+    form = w.mask.astype(bool)
+    dvp = rng.standard_normal(vp.shape) * form * vp
+    dvs = rng.standard_normal(vs.shape) * form * vs
+    drh = rng.standard_normal(rho.shape) * form * rho
+    eps = 1e-6
+    fd = (J(vp + eps * dvp, vs + eps * dvs, rho + eps * drh)
+          - J(vp - eps * dvp, vs - eps * dvs, rho - eps * drh)) / (2 * eps)
+    an = float((gvp * dvp).sum() + (gvs * dvs).sum() + (grho * drh).sum())
+    assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
+    # the density direction alone, so that its share is not hidden by the others
+    fd = (J(vp, vs, rho + eps * drh) - J(vp, vs, rho - eps * drh)) / (2 * eps)
+    an = float((grho * drh).sum())
+    assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
