@@ -254,6 +254,13 @@ def main():
     ap.add_argument("--line-search", type=int, default=-1,
                     help="1: parabolic line search each iteration (one extra forward); "
                          "-1: as the workload specifies (the 128-shot workload uses it)")
+    ap.add_argument("--density", action="store_true",
+                    help="joint inversion: the density gradient and step as well (an "
+                         "extension; the paper keeps the density fixed)")
+    ap.add_argument("--precond", default="illum", choices=("illum", "pseudo_hessian"),
+                    help="diagonal of the preconditioner")
+    ap.add_argument("--taper", default="",
+                    help="r0,r1 in metres: a radial taper on top of the diagonal")
     ap.add_argument("--sweep", action="store_true",
                     help="time one gradient evaluation per temporally blocked shape "
                          "(stderr only) before the benchmark")
@@ -305,8 +312,16 @@ def main():
     mask = torch.as_tensor(w.mask, device=dev)
     line_search = (bool(w.meta.get("line_search", False)) if args.line_search < 0
                    else bool(args.line_search))
+    if args.density and line_search:
+        log("--density: the line search steps lambda and mu only; running without it")
+        line_search = False
+    row_weight = None
+    if args.taper:
+        r0, r1 = (float(x) for x in args.taper.split(","))
+        row_weight = P.radial_taper(w.NRg, w.shots[0].dr, r0, r1)
     inv = Inversion(surveys, f32(w.vp_start), f32(w.vs_start), rho, wavs, observed, mask,
-                    line_search=line_search)
+                    line_search=line_search, density=args.density, precond=args.precond,
+                    row_weight=row_weight)
     if args.progress:
         def _progress(stage, g):
             torch.cuda.synchronize()
@@ -436,8 +451,9 @@ def main():
     # the adjoint block: interior tiles in the PML-free kernel, then the PML
     # (sub-)tiles in the kernel that carries the PML memories
     kshapes = sv.kernel_shapes()
-    kname = ("k_adj_tb<%d, %d, %d, 0> + k_adj_tb<%d, %d, %d, 1>" % (kshapes["adj"] +
-                                                                    kshapes["adj_pml"])
+    xm = (1 if args.density else 0) | (2 if args.precond == "pseudo_hessian" else 0)
+    kname = ("k_adj_tb<%d, %d, %d, 0, %d> + k_adj_tb<%d, %d, %d, 1, %d>" % (
+             kshapes["adj"] + (xm,) + kshapes["adj_pml"] + (xm,))
              if kshapes["adj"][0] >= 2
              else "k_adj_step<%d>" % (tune["rows_per_wave"] if tune["rows_per_wave"] <= 4 else 0))
     pmc = PMC_TRAFFIC.get((kname, tune.get("tile_map", 1), args.workload, kernel_sources_sha()))
@@ -482,8 +498,9 @@ def main():
             wav1 = sv1.pack_wavelets([sh.wavelet])
             off = sum(len(w.shots[q].rec_k) * w.shots[q].nt for q in pl.groups[g_] if q < s_)
             obs1 = observed[g_][off: off + len(sh.rec_k) * sh.nt].clone()
-            inv1 = Inversion(sv1, f32(w.vp_start), f32(w.vs_start), rho, wav1, obs1, mask,
-                             line_search=line_search)
+            inv1 = Inversion(sv1, f32(w.vp_start), f32(w.vs_start), rho.clone(), wav1, obs1,
+                             mask, line_search=line_search, density=args.density,
+                             precond=args.precond, row_weight=row_weight)
             inv1.iterate()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -522,6 +539,8 @@ def main():
                        pl.ckpt_every)),
                    "cell_steps_per_iteration": int(z.cell_steps),
                    "line_search": line_search,
+                   "density": bool(args.density), "precond": args.precond,
+                   "taper": args.taper or None,
                    "kernel_shapes": kshapes,
                    "tune": tune},
         "roofline": roofline,

@@ -325,6 +325,33 @@ int bhfwi_adjoint_model_density(bhfwi_ctx *ctx, void *stream, const float *lam,
                                 const void *ckpt, int64_t ckpt_bytes, void *adj_ws,
                                 int64_t adj_ws_bytes, float *acc, float *acc_rho);
 
+/* bhfwi_adjoint_model with optional extra outputs, each selected by a
+ * non-null pointer (device, 2 * cells floats, overwritten, per shot on the
+ * shot's padded grid):
+ *   acc_rho  the density correlation, as for bhfwi_adjoint_model_density;
+ *   acc_h    the virtual-source pseudo-Hessian diagonal, an alternative to the
+ *            illumination as the diagonal of the preconditioner (the paper
+ *            gives that preconditioner only as diagonal, Numerical Examples
+ *            section, Fig. 6): the squared derivative of the stress update with
+ *            respect to each modulus applied to the forward wavefield, summed
+ *            over steps.  With the strain rates of v^{n+1/2} at C cell (i,k),
+ *            plane 0 H_lambda = sum_n 3 dt^2 (e_rr + e_tt + e_zz)^2 and plane 1
+ *            H_mu = sum_n dt^2 (4 (e_rr^2 + e_tt^2 + e_zz^2) + (e_z + e_r)^2),
+ *            the last from the tau_rz node (i,k) (i >= 1).
+ * Each extra output adds two multiply-adds per node and step to the adjoint
+ * kernels; no further history is stored. */
+int bhfwi_adjoint_model_ex(bhfwi_ctx *ctx, void *stream, const float *lam, const float *mu,
+                           const float *rho, const float *wavelet, const float *resid,
+                           void *fwd_ws, int64_t fwd_ws_bytes, const void *ckpt,
+                           int64_t ckpt_bytes, void *adj_ws, int64_t adj_ws_bytes, float *acc,
+                           float *acc_rho, float *acc_h);
+
+/* Sums every shot's window of acc_h (from bhfwi_adjoint_model_ex) into the
+ * global grids h_lam and h_mu (device, model_len) in shot order:
+ * overwritten, or added to when accumulate != 0. */
+int bhfwi_gradient_hessian(bhfwi_ctx *ctx, void *stream, const float *acc_h, float *h_lam,
+                           float *h_mu, int32_t accumulate);
+
 /* Density gradient finalize: with b_R = 2/(rho[i-1,k] + rho[i,k]) and
  * b_Z = 2/(rho[i,k] + rho[i,k1]), k1 = min(k+1, NZ-1), every node adds
  * -(b/2) (b dJ/db) to each of its two cells; gathered per cell and summed
@@ -342,6 +369,36 @@ int bhfwi_gradient_density(bhfwi_ctx *ctx, void *stream, const float *rho,
  * along the preconditioned step, as bhfwi_line_search needs it. */
 int bhfwi_precondition(bhfwi_ctx *ctx, void *stream, int64_t n, const float *illum,
                        const uint8_t *mask, float eps, float *g_lam, float *g_mu, double *gpg);
+
+/* One gradient through a general diagonal preconditioner (alternatives to
+ * the illumination of bhfwi_precondition; the paper fixes only that it is
+ * diagonal and suppresses the near-wall guided waves, Fig. 6):
+ * g <- w[c / ld] g / (d + eps max d) on mask cells, 0 elsewhere, with d =
+ * diag (nullable: the factor is then 1; max over mask cells) and w =
+ * row_weight (nullable: 1), one weight per radial row of ld elements (a
+ * radial taper).  n elements, device arrays.  gpg (device double, nullable)
+ * receives sum over mask cells of g . P g taken before the scaling,
+ * overwritten, or added to when accumulate != 0 (one call per parameter). */
+int bhfwi_precondition_diag(bhfwi_ctx *ctx, void *stream, int64_t n, int32_t ld,
+                            const float *diag, const float *row_weight, const uint8_t *mask,
+                            float eps, float *g, double *gpg, int32_t accumulate);
+
+/* Radial taper for bhfwi_precondition_diag: w[i] for the nrow radial rows of
+ * C cells, r = (i + 1/2) dr: 0 for r <= r0, sin^2(pi/2 (r - r0)/(r1 - r0))
+ * between, 1 for r >= r1 (a step at r0 when r1 == r0).  It mutes the gradient
+ * next to the borehole wall, where the guided waves dominate it.  w device,
+ * nrow floats. */
+int bhfwi_radial_taper(void *stream, int32_t nrow, float dr, float r0, float r1, float *w);
+
+/* Density step of a joint inversion (the paper keeps the density fixed):
+ * the greatest-change rule applied to the density on its own,
+ * alpha = eta max|rho| / max|g_rho| over mask cells, then
+ * rho <- clamp(rho - alpha g_rho, rho_min, rho_max) on mask cells.  n
+ * elements, device arrays; alpha_out (device float, nullable) receives alpha.
+ * Call before bhfwi_update so that its velocity bounds use the new density. */
+int bhfwi_update_density(bhfwi_ctx *ctx, void *stream, int64_t n, float *rho,
+                         const float *g_rho, const uint8_t *mask, float eta, float rho_min,
+                         float rho_max, float *alpha_out);
 
 /* Device-side status: synchronises the stream and returns BHFWI_ENONFINITE
  * (text via bhfwi_last_error) if any bhfwi_misfit or bhfwi_precondition

@@ -63,7 +63,8 @@ def _load():
         lib.orc_forward.restype = C.c_int
         lib.orc_misfit.argtypes = [C.c_int64, _D, _D, _D]
         lib.orc_misfit.restype = C.c_double
-        lib.orc_gradient.argtypes = [G, _D, _D, _D, _D, _D, C.c_int32, _D, _D, _D, _D]
+        lib.orc_gradient.argtypes = [G, _D, _D, _D, _D, _D, C.c_int32, _D, _D, _D, _D, _D,
+                                     _D]
         lib.orc_gradient.restype = C.c_int
         lib.orc_source_adjoint.argtypes = [G, _D, _D, _D, _D, _D]
         lib.orc_source_adjoint.restype = C.c_int
@@ -190,9 +191,10 @@ def misfit(d, dobs):
     return J, r
 
 
-def gradient(g: Geom, lam, mu, rho, wavelet, resid, seg=200, density=False):
+def gradient(g: Geom, lam, mu, rho, wavelet, resid, seg=200, density=False, hessian=False):
     """Eq. 6-8 via the exact discrete transpose; returns (glam, gmu, illum),
-    and dJ/drho as a fourth output with density=True."""
+    then dJ/drho with density=True, then (H_lambda, H_mu), the
+    virtual-source pseudo-Hessian diagonal, with hessian=True."""
     shp = (g.NR, g.NZ)
     lam, mu, rho = _f64(lam, shp), _f64(mu, shp), _f64(rho, shp)
     w, r = _f64(wavelet), _f64(resid)
@@ -200,10 +202,17 @@ def gradient(g: Geom, lam, mu, rho, wavelet, resid, seg=200, density=False):
     assert r.size == len(rk) * g.nt
     gl, gm, il = np.zeros(shp), np.zeros(shp), np.zeros(shp)
     gr = np.zeros(shp) if density else None
+    hl, hm = (np.zeros(shp), np.zeros(shp)) if hessian else (None, None)
+    opt = lambda a: _p(a) if a is not None else None  # noqa: E731
     rc = _load().orc_gradient(C.byref(gc), _p(lam), _p(mu), _p(rho), _p(w), _p(r),
-                              int(seg), _p(gl), _p(gm), _p(il), _p(gr) if density else None)
+                              int(seg), _p(gl), _p(gm), _p(il), opt(gr), opt(hl), opt(hm))
     _check(rc, "gradient")
-    return (gl, gm, il, gr) if density else (gl, gm, il)
+    out = (gl, gm, il)
+    if density:
+        out += (gr,)
+    if hessian:
+        out += (hl, hm)
+    return out
 
 
 def source_adjoint(g: Geom, lam, mu, rho, resid):
@@ -240,6 +249,47 @@ def precondition(illum, mask, eps, g_lam, g_mu, return_gpg=False):
     gpg = _load().orc_precondition(il.size, _p(il), m.ctypes.data_as(_U8), float(eps),
                                    _p(gl), _p(gm))
     return (gl, gm, gpg) if return_gpg else (gl, gm)
+
+
+def precondition_diag(g, mask, eps, diag=None, row_weight=None, return_gpg=False):
+    """A general diagonal preconditioner for one gradient [NR, NZ] (the paper
+    fixes only that it is diagonal): P = w[i] / (d + eps max_mask d) on mask
+    cells, 0 elsewhere, d = diag (P = w without it), w = row_weight per
+    radial row (1 without it).  With return_gpg also sum over mask of g P g."""
+    g = np.array(g, np.float64)
+    mk = np.asarray(mask).astype(bool)
+    p = np.ones_like(g)
+    if diag is not None:
+        d = np.asarray(diag, np.float64)
+        p = 1.0 / (d + eps * np.abs(d[mk]).max())
+    if row_weight is not None:
+        p = p * np.asarray(row_weight, np.float64)[:, None]
+    p = np.where(mk, p, 0.0)
+    gpg = float((g * p * g).sum())
+    out = g * p
+    return (out, gpg) if return_gpg else out
+
+
+def radial_taper(NR, dr, r0, r1):
+    """Weight per radial row of C cells (r = (i + 1/2) dr): 0 inside r0,
+    sin^2 ramp to 1 at r1, 1 beyond; mutes the gradient next to the
+    borehole wall where the guided waves dominate it."""
+    r = (np.arange(NR) + 0.5) * dr
+    x = np.clip((r - r0) / max(r1 - r0, 1e-30), 0.0, 1.0)
+    return np.sin(0.5 * np.pi * x) ** 2
+
+
+def update_density(rho, g_rho, mask, eta, rho_min, rho_max):
+    """Density step of a joint inversion: alpha = eta max|rho| / max|g| over
+    mask cells, rho - alpha g clamped to [rho_min, rho_max] there; returns
+    (rho, alpha)."""
+    r = np.array(rho, np.float64)
+    g = np.asarray(g_rho, np.float64)
+    mk = np.asarray(mask).astype(bool)
+    gmax = np.abs(g[mk]).max()
+    alpha = eta * np.abs(r[mk]).max() / gmax if gmax > 0 else 0.0
+    r[mk] = np.clip(r[mk] - alpha * g[mk], rho_min, rho_max)
+    return r, alpha
 
 
 def line_search(J0, J1, gpg, alpha1):

@@ -541,7 +541,7 @@ static void inject_residual(const orc_geom *g, int NZ, state *a, const double *r
 
 int orc_gradient(const orc_geom *g, const double *lam, const double *mu, const double *rho,
                  const double *wavelet, const double *resid, int32_t seg, double *glam,
-                 double *gmu, double *illum, double *grho)
+                 double *gmu, double *illum, double *grho, double *hl, double *hm)
 {
     grid G;
     if (seg <= 0 || grid_init(&G, g, lam, mu, rho) || !geom_ok(g)) return -1;
@@ -570,6 +570,8 @@ int orc_gradient(const orc_geom *g, const double *lam, const double *mu, const d
     memset(glam, 0, N * sizeof(double));
     memset(gmu, 0, N * sizeof(double));
     memset(illum, 0, N * sizeof(double));
+    if (hl) memset(hl, 0, N * sizeof(double));
+    if (hm) memset(hm, 0, N * sizeof(double));
 
     /* forward pass: checkpoints every seg steps, illumination from v^{n+1/2} */
     for (int n = 0; n < nt; ++n) {
@@ -582,6 +584,20 @@ int orc_gradient(const orc_geom *g, const double *lam, const double *mu, const d
                 double vz_km = k > 0 ? s.vz[IX(i, k - 1)] : 0.0;
                 double ur = 0.5 * (s.vr[c] + vr_ip), uz = 0.5 * (vz_km + s.vz[c]);
                 illum[c] += dt * (ur * ur + uz * uz);
+                if (hl || hm) {
+                    /* virtual sources: d(stress update)/d(modulus) applied to
+                     * v^{n+1/2}, with the plain strain rates of the stencil */
+                    double rh = (i + 0.5) * G.dr;
+                    double err = (vr_ip - s.vr[c]) / G.dr, ett = (vr_ip + s.vr[c]) / (2.0 * rh);
+                    double ezz = (s.vz[c] - vz_km) / G.dz, es = 0.0;
+                    if (i >= 1) {
+                        double vr_kp = k + 1 < NZ ? s.vr[IX(i, k + 1)] : 0.0;
+                        es = (vr_kp - s.vr[c]) / G.dz + (s.vz[c] - s.vz[IX(i - 1, k)]) / G.dr;
+                    }
+                    double dv = err + ett + ezz;
+                    if (hl) hl[c] += dt * dt * 3.0 * dv * dv;
+                    if (hm) hm[c] += dt * dt * (4.0 * (err * err + ett * ett + ezz * ezz) + es * es);
+                }
             }
     }
 

@@ -68,11 +68,16 @@ double orc_misfit(int64_t n, const double *d, const double *dobs, double *resid)
  * gmu = dJ/dmu (the tau_rz-node harmonic-mean chain rule included; cells with
  * mu <= 0 get only their own-node term), illum = sum_n dt |v|^2 at C nodes,
  * grho (nullable) = dJ/drho through the buoyancies of the velocity update
- * (density held fixed by the paper, inverted jointly as an extension).
+ * (density held fixed by the paper, inverted jointly as an extension);
+ * hl, hm (nullable) = the virtual-source pseudo-Hessian diagonal: with the
+ * plain strain rates of v^{n+1/2} at C cells, hl = sum_n 3 dt^2 (div v)^2
+ * and hm = sum_n dt^2 (4 (e_rr^2 + e_tt^2 + e_zz^2) + (e_z + e_r)^2), the
+ * last term that of the tau_rz node with the cell's index (i >= 1).
  * Pinned by brute-force central differences and by dot-product tests. */
 int orc_gradient(const orc_geom *g, const double *lam, const double *mu, const double *rho,
                  const double *wavelet, const double *resid, int32_t seg,
-                 double *glam, double *gmu, double *illum, double *grho);
+                 double *glam, double *gmu, double *illum, double *grho, double *hl,
+                 double *hm);
 
 /* Transpose of the map wavelet -> traces for a fixed model: wadj[n] =
  * d<traces, resid>/d wavelet[n].  Used by the source-to-trace dot-product test. */

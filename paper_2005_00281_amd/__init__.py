@@ -6,6 +6,6 @@ include/bhfwi.h).  This package is the Python binding: ``Survey`` wraps the
 C-ABI, ``BoreholeFWI`` is the torch.autograd.Function around the forward and
 adjoint kernels, ``fwi`` holds the iteration driver.
 """
-from ._lib import (BhfwiError, Survey, load, moduli, moduli_grad, semblance,  # noqa: F401
-                   semblance_pick, starting_model, velocities)
+from ._lib import (BhfwiError, Survey, load, moduli, moduli_grad, radial_taper,  # noqa: F401
+                   semblance, semblance_pick, starting_model, velocities)
 from .autograd import BoreholeFWI, Moduli  # noqa: F401

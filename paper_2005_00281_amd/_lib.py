@@ -80,7 +80,9 @@ EXPORTS = ["bhfwi_create", "bhfwi_destroy", "bhfwi_last_error", "bhfwi_sizes",
            "bhfwi_fwd_model", "bhfwi_misfit", "bhfwi_adjoint_model", "bhfwi_gradient",
            "bhfwi_precondition", "bhfwi_status", "bhfwi_line_search", "bhfwi_update", "bhfwi_plan_bytes",
            "bhfwi_plan", "bhfwi_kernel_shapes", "bhfwi_semblance", "bhfwi_semblance_pick",
-           "bhfwi_starting_model", "bhfwi_adjoint_model_density", "bhfwi_gradient_density"]
+           "bhfwi_starting_model", "bhfwi_adjoint_model_density", "bhfwi_gradient_density",
+           "bhfwi_adjoint_model_ex", "bhfwi_gradient_hessian", "bhfwi_precondition_diag",
+           "bhfwi_radial_taper", "bhfwi_update_density"]
 
 _lib = None
 
@@ -116,6 +118,11 @@ def load(path: str = LIB_PATH):
     L.bhfwi_adjoint_model_density.argtypes = [P, V, P, P, P, P, P, P, I64, P, I64, P, I64, P,
                                               P]
     L.bhfwi_gradient_density.argtypes = [P, V, P, P, P, I32]
+    L.bhfwi_adjoint_model_ex.argtypes = [P, V, P, P, P, P, P, P, I64, P, I64, P, I64, P, P, P]
+    L.bhfwi_gradient_hessian.argtypes = [P, V, P, P, P, I32]
+    L.bhfwi_precondition_diag.argtypes = [P, V, I64, I32, P, P, P, F, P, P, I32]
+    L.bhfwi_radial_taper.argtypes = [V, I32, F, F, F, P]
+    L.bhfwi_update_density.argtypes = [P, V, I64, P, P, P, F, F, F, P]
     L.bhfwi_precondition.argtypes = [P, V, I64, P, P, F, P, P, P]
     L.bhfwi_line_search.argtypes = [P, V, P, P, P, P, P]
     L.bhfwi_status.argtypes = [P, V]
@@ -185,6 +192,14 @@ def moduli_grad(vp, vs, rho, g_lam, g_mu, density=False):
                                     _f32(g_lam), _f32(g_mu), _f32(g_vp), _f32(g_vs),
                                     _f32(g_rho) if density else None))
     return (g_vp, g_vs, g_rho) if density else (g_vp, g_vs)
+
+
+def radial_taper(nrow, dr, r0, r1, device=None):
+    """Weights per radial row for precondition_diag (bhfwi_radial_taper)."""
+    w = torch.empty(nrow, dtype=torch.float32, device=device or torch.device("cuda", 0))
+    _check(load().bhfwi_radial_taper(_stream(), int(nrow), float(dr), float(r0), float(r1),
+                                     _f32(w)))
+    return w
 
 
 def semblance(traces, dt, offset, p0, dp, np_, tau_stride, ntau, win, energy=False):
@@ -496,6 +511,68 @@ class Survey:
             _f32(acc_rho, 2 * z.cells))
         _check(rc, self._h)
         return acc, acc_rho
+
+    def adjoint_model_ex(self, lam, mu, rho, wavelet, resid, ckpt=None, acc=None,
+                         density=False, hessian=False, acc_rho=None, acc_h=None):
+        """adjoint_model with the optional outputs: returns (acc, acc_rho or
+        None, acc_h or None); acc_h [2, cells] is the virtual-source
+        pseudo-Hessian diagonal (H_lambda, H_mu) per shot."""
+        z = self.sizes
+        if acc is None:
+            acc = torch.empty(z.acc_elems, dtype=torch.float32, device=self.device)
+        if density and acc_rho is None:
+            acc_rho = torch.empty(2 * z.cells, dtype=torch.float32, device=self.device)
+        if hessian and acc_h is None:
+            acc_h = torch.empty(2 * z.cells, dtype=torch.float32, device=self.device)
+        if not density:
+            acc_rho = None
+        if not hessian:
+            acc_h = None
+        if ckpt is None:
+            ckpt = self.workspace("ckpt")
+        fw, aw = self.workspace("fwd"), self.workspace("adj")
+        n = self.model_shape[0] * self.model_shape[1]
+        rc = load().bhfwi_adjoint_model_ex(
+            self._h, _stream(), _f32(lam, n), _f32(mu, n), _f32(rho, n),
+            _f32(wavelet, z.wavelet_elems), _f32(resid, z.trace_elems), _ptr(fw), fw.numel(),
+            _ptr(ckpt), ckpt.numel(), _ptr(aw), aw.numel(), _f32(acc, z.acc_elems),
+            _f32(acc_rho, 2 * z.cells) if density else None,
+            _f32(acc_h, 2 * z.cells) if hessian else None)
+        _check(rc, self._h)
+        return acc, acc_rho, acc_h
+
+    def gradient_hessian(self, acc_h, out=None, accumulate=False):
+        """(H_lambda, H_mu) on the global grid from adjoint_model_ex's acc_h
+        (added to `out` when accumulate)."""
+        if out is None:
+            out = tuple(torch.empty(self.model_shape, dtype=torch.float32, device=self.device)
+                        for _ in range(2))
+        n = self.model_shape[0] * self.model_shape[1]
+        _check(load().bhfwi_gradient_hessian(self._h, _stream(), _f32(acc_h, 2 * self.sizes.cells),
+                                             _f32(out[0], n), _f32(out[1], n),
+                                             1 if accumulate else 0), self._h)
+        return out
+
+    def precondition_diag(self, g, mask, eps, diag=None, row_weight=None, gpg=None,
+                          accumulate=False):
+        """One gradient through P = w[row] / (d + eps max d) (in place)."""
+        n = g.numel()
+        _check(load().bhfwi_precondition_diag(
+            self._h, _stream(), n, int(g.shape[-1]), _f32(diag, n) if diag is not None else None,
+            _f32(row_weight, n // g.shape[-1]) if row_weight is not None else None, _ptr(mask),
+            float(eps), _f32(g, n), _ptr(gpg) if gpg is not None else None,
+            1 if accumulate else 0), self._h)
+        return g
+
+    def update_density(self, rho, g_rho, mask, eta, rho_min, rho_max, alpha=None):
+        """Density step (in place); returns alpha as a device scalar."""
+        if alpha is None:
+            alpha = torch.empty((), dtype=torch.float32, device=self.device)
+        n = rho.numel()
+        _check(load().bhfwi_update_density(self._h, _stream(), n, _f32(rho, n), _f32(g_rho, n),
+                                           _ptr(mask), float(eta), float(rho_min),
+                                           float(rho_max), _f32(alpha)), self._h)
+        return alpha
 
     def gradient_density(self, rho, acc_rho, out=None, accumulate=False):
         """dJ/drho on the global grid from adjoint_model_density's acc_rho

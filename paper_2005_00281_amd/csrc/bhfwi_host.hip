@@ -394,7 +394,7 @@ void fwd_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const flo
 
 void adj_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const float* mu,
                 const float* rho, const float* resid, const float* in, float* out,
-                const float* hist, float* acc, float* acc_rho)
+                const float* hist, float* acc, float* acc_rho, float* acc_h)
 {
     const int nact = active_items(c, n);
     if (nact <= 0) return;
@@ -402,7 +402,7 @@ void adj_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const flo
     EvScope ev(c, st, 2);
     BHFWI_DISPATCH(c->tune.rows_per_wave, bhfwi::k_adj_step, dim3((nact + wpb - 1) / wpb),
                    dim3(64 * wpb), 0, st, c->d_shots, c->d_work, nact, n, lam, mu, rho, c->d_rec,
-                   resid, c->d_pml_r, c->d_pml_z, in, out, hist, acc, acc_rho,
+                   resid, c->d_pml_r, c->d_pml_z, in, out, hist, acc, acc_rho, acc_h,
                    (long long)c->cells);
 }
 
@@ -533,31 +533,39 @@ void fwd_tb_launch(bhfwi_ctx* c, hipStream_t st, int n0, int nsteps, const float
 }
 #undef BHFWI_TB
 
+// One adjoint block kernel with the optional outputs xm (bit 0 density, bit 1
+// pseudo-Hessian) selected at run time.
+template <int TT, int RR, int WW, int PMV, class... Args>
+void launch_adj_tb(int xm, dim3 grid, dim3 block, hipStream_t s, Args... a)
+{
+    switch (xm) {
+    case 1: hipLaunchKernelGGL((bhfwi::k_adj_tb<TT, RR, WW, PMV, 1>), grid, block, 0, s, a...); break;
+    case 2: hipLaunchKernelGGL((bhfwi::k_adj_tb<TT, RR, WW, PMV, 2>), grid, block, 0, s, a...); break;
+    case 3: hipLaunchKernelGGL((bhfwi::k_adj_tb<TT, RR, WW, PMV, 3>), grid, block, 0, s, a...); break;
+    default: hipLaunchKernelGGL((bhfwi::k_adj_tb<TT, RR, WW, PMV, 0>), grid, block, 0, s, a...); break;
+    }
+}
+
 #define BHFWI_TBA(TT, RR, WW)                                                                \
     if (T == TT && TRE == RR && W == WW) {                                                   \
-        if (acc_rho)                                                                         \
-            hipLaunchKernelGGL((bhfwi::k_adj_tb<TT, RR, WW, PMV, 1>), dim3(nact),            \
-                               dim3(64 * WW), 0, fork.stream(q), c->d_shots, c->atiles.d[q], \
-                               nact, c->tune.tile_map, n_hi, nsteps, lam, mu, rho, c->d_rec, \
-                               resid, c->d_pml_r, c->d_pml_z, in, out, hist_hi,              \
-                               (long long)(2 * c->cells), acc, acc_rho, (long long)c->cells); \
-        else                                                                                 \
-            hipLaunchKernelGGL((bhfwi::k_adj_tb<TT, RR, WW, PMV, 0>), dim3(nact),            \
-                               dim3(64 * WW), 0, fork.stream(q), c->d_shots, c->atiles.d[q], \
-                               nact, c->tune.tile_map, n_hi, nsteps, lam, mu, rho, c->d_rec, \
-                               resid, c->d_pml_r, c->d_pml_z, in, out, hist_hi,              \
-                               (long long)(2 * c->cells), acc, nullptr, (long long)c->cells); \
+        launch_adj_tb<TT, RR, WW, PMV>(xm, dim3(nact), dim3(64 * WW), fork.stream(q),         \
+                                       c->d_shots, c->atiles.d[q], nact, c->tune.tile_map,   \
+                                       n_hi, nsteps, lam, mu, rho, c->d_rec, resid,          \
+                                       c->d_pml_r, c->d_pml_z, in, out, hist_hi,             \
+                                       (long long)(2 * c->cells), acc, acc_rho, acc_h,       \
+                                       (long long)c->cells);                                 \
         continue;                                                                            \
     }
 
 // nsteps (<= the adjoint shape's T) adjoint steps n_hi, n_hi - 1, ... in
 // LDS-tiled kernels (interior tiles, then PML sub-tiles); hist_hi is the
-// history slot of step n_hi; acc_rho (nullable) selects the kernels that also
-// accumulate the density correlation.
+// history slot of step n_hi; acc_rho and acc_h (nullable) select the kernels
+// that also accumulate the density correlation and the pseudo-Hessian.
 void adj_tb_launch(bhfwi_ctx* c, hipStream_t st, int n_hi, int nsteps, const float* lam,
                    const float* mu, const float* rho, const float* resid, const float* in,
-                   float* out, const float* hist_hi, float* acc, float* acc_rho)
+                   float* out, const float* hist_hi, float* acc, float* acc_rho, float* acc_h)
 {
+    const int xm = (acc_rho ? 1 : 0) | (acc_h ? 2 : 0);
     const int n_lo = n_hi - nsteps + 1;
     const int na[2] = {active_tiles(c->atiles, 0, n_lo), active_tiles(c->atiles, 1, n_lo)};
     if (na[0] + na[1] <= 0) return;
@@ -583,7 +591,7 @@ void adj_tb_launch(bhfwi_ctx* c, hipStream_t st, int n_hi, int nsteps, const flo
 // ab[(*m + 1) & 1]; hist holds v of step n at slot n - n0.
 void adj_range(bhfwi_ctx* c, hipStream_t st, int n0, int n1, const float* lam, const float* mu,
                const float* rho, const float* resid, float* const ab[2], int* m,
-               const float* hist, float* acc, float* acc_rho)
+               const float* hist, float* acc, float* acc_rho, float* acc_h)
 {
     const int64_t hslot = 2 * c->cells;
     const Shape sh = adj_shape(c);
@@ -591,14 +599,14 @@ void adj_range(bhfwi_ctx* c, hipStream_t st, int n0, int n1, const float* lam, c
         for (int n = n1 - 1; n >= n0;) {
             const int nb = std::min(sh.T, n - n0 + 1);
             adj_tb_launch(c, st, n, nb, lam, mu, rho, resid, ab[*m & 1], ab[(*m + 1) & 1],
-                          hist + (int64_t)(n - n0) * hslot, acc, acc_rho);
+                          hist + (int64_t)(n - n0) * hslot, acc, acc_rho, acc_h);
             ++*m;
             n -= nb;
         }
     } else {
         for (int n = n1 - 1; n >= n0; --n, ++*m)
             adj_launch(c, st, n, lam, mu, rho, resid, ab[*m & 1], ab[(*m + 1) & 1],
-                       hist + (int64_t)(n - n0) * hslot, acc, acc_rho);
+                       hist + (int64_t)(n - n0) * hslot, acc, acc_rho, acc_h);
     }
 }
 
@@ -1052,7 +1060,7 @@ int bhfwi_autotune(bhfwi_ctx* c, void* stream, const float* lam, const float* mu
     auto run_adj = [&]() {
         launch_fill(st, ab[0], 2 * c->ast_len, 0.0f);
         int m = 0;
-        adj_range(c, st, 0, P, lam, mu, rho, traces, ab, &m, hist, acc, nullptr);
+        adj_range(c, st, 0, P, lam, mu, rho, traces, ab, &m, hist, acc, nullptr, nullptr);
     };
     // best of repetitions 2 and 3 of `phase` (the first warms up)
     auto time_it = [&](auto&& phase, float* out, int reps) {
@@ -1280,11 +1288,11 @@ int bhfwi_misfit(bhfwi_ctx* c, void* stream, const float* traces, const float* o
 namespace {
 
 // Shared body of bhfwi_adjoint_model and bhfwi_adjoint_model_density
-// (acc_rho null for the former).
+// and bhfwi_adjoint_model_ex (acc_rho and acc_h null for the first).
 int adjoint_impl(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
                  const float* rho, const float* wavelet, const float* resid, void* fwd_ws,
                  int64_t fwd_ws_bytes, const void* ckpt, int64_t ckpt_bytes, void* adj_ws,
-                 int64_t adj_ws_bytes, float* acc, float* acc_rho)
+                 int64_t adj_ws_bytes, float* acc, float* acc_rho, float* acc_h)
 {
     if (int rc = check_ctx(c)) return rc;
     bhfwi_sizes_t z;
@@ -1310,6 +1318,7 @@ int adjoint_impl(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
         launch_fill(s, ab[0], 2 * c->ast_len, 0.0f);
         launch_fill(s, acc, 4 * c->cells, 0.0f);
         if (acc_rho) launch_fill(s, acc_rho, 2 * c->cells, 0.0f);
+        if (acc_h) launch_fill(s, acc_h, 2 * c->cells, 0.0f);
         int m = 0;
         for (int j = c->nseg - 1; j >= 0; --j) {
             const int n0 = j * K, n1 = std::min(n0 + K, c->nt_max);
@@ -1320,13 +1329,13 @@ int adjoint_impl(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
                                      sizeof(float) * c->fst_len, hipMemcpyDeviceToDevice, s);
             int parity = 0;
             fwd_range(c, s, n0, n1, lam, mu, rho, wavelet, fbc, &parity, nullptr, hist, n0);
-            adj_range(c, s, n0, n1, lam, mu, rho, resid, ab, &m, hist, acc, acc_rho);
+            adj_range(c, s, n0, n1, lam, mu, rho, resid, ab, &m, hist, acc, acc_rho, acc_h);
         }
     };
     return run_sequence(c, st,
                         {2, (uintptr_t)lam, (uintptr_t)mu, (uintptr_t)rho, (uintptr_t)wavelet,
                          (uintptr_t)resid, (uintptr_t)fwd_ws, (uintptr_t)ckpt, (uintptr_t)adj_ws,
-                         (uintptr_t)acc, (uintptr_t)acc_rho},
+                         (uintptr_t)acc, (uintptr_t)acc_rho, (uintptr_t)acc_h},
                         record);
 }
 
@@ -1338,7 +1347,7 @@ int bhfwi_adjoint_model(bhfwi_ctx* c, void* stream, const float* lam, const floa
                         int64_t ckpt_bytes, void* adj_ws, int64_t adj_ws_bytes, float* acc)
 {
     return adjoint_impl(c, stream, lam, mu, rho, wavelet, resid, fwd_ws, fwd_ws_bytes, ckpt,
-                        ckpt_bytes, adj_ws, adj_ws_bytes, acc, nullptr);
+                        ckpt_bytes, adj_ws, adj_ws_bytes, acc, nullptr, nullptr);
 }
 
 int bhfwi_adjoint_model_density(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
@@ -1350,7 +1359,36 @@ int bhfwi_adjoint_model_density(bhfwi_ctx* c, void* stream, const float* lam, co
     if (int rc = check_ctx(c)) return rc;
     if (!acc_rho) return fail(c, BHFWI_EINVAL, "adjoint_model_density: null acc_rho");
     return adjoint_impl(c, stream, lam, mu, rho, wavelet, resid, fwd_ws, fwd_ws_bytes, ckpt,
-                        ckpt_bytes, adj_ws, adj_ws_bytes, acc, acc_rho);
+                        ckpt_bytes, adj_ws, adj_ws_bytes, acc, acc_rho, nullptr);
+}
+
+int bhfwi_adjoint_model_ex(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
+                           const float* rho, const float* wavelet, const float* resid,
+                           void* fwd_ws, int64_t fwd_ws_bytes, const void* ckpt,
+                           int64_t ckpt_bytes, void* adj_ws, int64_t adj_ws_bytes, float* acc,
+                           float* acc_rho, float* acc_h)
+{
+    return adjoint_impl(c, stream, lam, mu, rho, wavelet, resid, fwd_ws, fwd_ws_bytes, ckpt,
+                        ckpt_bytes, adj_ws, adj_ws_bytes, acc, acc_rho, acc_h);
+}
+
+int bhfwi_gradient_hessian(bhfwi_ctx* c, void* stream, const float* acc_h, float* h_lam,
+                           float* h_mu, int32_t accumulate)
+{
+    if (int rc = check_ctx(c)) return rc;
+    if (!acc_h || !h_lam || !h_mu) return fail(c, BHFWI_EINVAL, "gradient_hessian: null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    if (!accumulate) {
+        launch_fill(st, h_lam, c->model_len, 0.0f);
+        launch_fill(st, h_mu, c->model_len, 0.0f);
+    }
+    for (int s = 0; s < c->nshot; ++s) {
+        const int64_t cells = (int64_t)c->sd[s].NR * c->sd[s].NZ;
+        hipLaunchKernelGGL(bhfwi::k_window_add2, dim3(grid1d(cells)), dim3(256), 0, st,
+                           c->d_shots, s, acc_h, (long long)c->cells, h_lam, h_mu);
+    }
+    HIPOK(c, hipGetLastError());
+    return BHFWI_OK;
 }
 
 int bhfwi_gradient_density(bhfwi_ctx* c, void* stream, const float* rho, const float* acc_rho,
@@ -1409,6 +1447,58 @@ int bhfwi_precondition(bhfwi_ctx* c, void* stream, int64_t n, const float* illum
     if (gpg)
         hipLaunchKernelGGL(bhfwi::k_sum_partials, dim3(1), dim3(256), 0, st, na, dpart, gpg, 0,
                            c->d_status);
+    HIPOK(c, hipGetLastError());
+    return BHFWI_OK;
+}
+
+int bhfwi_precondition_diag(bhfwi_ctx* c, void* stream, int64_t n, int32_t ld,
+                            const float* diag, const float* row_weight, const uint8_t* mask,
+                            float eps, float* g, double* gpg, int32_t accumulate)
+{
+    if (int rc = check_ctx(c)) return rc;
+    if (n < 1 || ld < 1 || !mask || !g || !(eps >= 0))
+        return fail(c, BHFWI_EINVAL, "precondition_diag: bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    const int nb = grid1d(n, kPartBlocks);
+    float* part = (float*)c->d_scratch;
+    if (diag)
+        hipLaunchKernelGGL(bhfwi::k_absmax_partial, dim3(nb), dim3(256), 0, st, (long long)n,
+                           mask, diag, (const float*)nullptr, (const float*)nullptr,
+                           (const float*)nullptr, part);
+    double* dpart = gpg ? (double*)((float*)c->d_scratch + 4 * kPartBlocks) : nullptr;
+    hipLaunchKernelGGL(bhfwi::k_precond_diag_apply, dim3(nb), dim3(256), 0, st, (long long)n,
+                       (int)ld, mask, diag, row_weight, eps, (const float*)part, nb, g, dpart);
+    if (gpg)
+        hipLaunchKernelGGL(bhfwi::k_sum_partials, dim3(1), dim3(256), 0, st, nb, dpart, gpg,
+                           accumulate ? 1 : 0, c->d_status);
+    HIPOK(c, hipGetLastError());
+    return BHFWI_OK;
+}
+
+int bhfwi_radial_taper(void* stream, int32_t nrow, float dr, float r0, float r1, float* w)
+{
+    if (nrow < 1 || !w || !(dr > 0) || !(r1 >= r0)) return BHFWI_EINVAL;
+    hipLaunchKernelGGL(bhfwi::k_radial_taper, dim3((nrow + 255) / 256), dim3(256), 0,
+                       (hipStream_t)stream, (int)nrow, dr, r0, r1, w);
+    return hipGetLastError() == hipSuccess ? BHFWI_OK : BHFWI_EHIP;
+}
+
+int bhfwi_update_density(bhfwi_ctx* c, void* stream, int64_t n, float* rho, const float* g_rho,
+                         const uint8_t* mask, float eta, float rho_min, float rho_max,
+                         float* alpha_out)
+{
+    if (int rc = check_ctx(c)) return rc;
+    if (n < 1 || !rho || !g_rho || !mask || !(rho_min > 0) || !(rho_max >= rho_min))
+        return fail(c, BHFWI_EINVAL, "update_density: bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    const int nb = grid1d(n, kPartBlocks);
+    float* part = (float*)c->d_scratch;
+    hipLaunchKernelGGL(bhfwi::k_absmax_partial, dim3(nb), dim3(256), 0, st, (long long)n, mask,
+                       g_rho, (const float*)rho, (const float*)nullptr, (const float*)nullptr,
+                       part);
+    hipLaunchKernelGGL(bhfwi::k_update_density_apply, dim3(grid1d(n)), dim3(256), 0, st,
+                       (long long)n, mask, rho, g_rho, (const float*)part, nb, eta, rho_min,
+                       rho_max, alpha_out);
     HIPOK(c, hipGetLastError());
     return BHFWI_OK;
 }

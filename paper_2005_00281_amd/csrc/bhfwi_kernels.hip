@@ -317,7 +317,7 @@ k_adj_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
            const float* __restrict__ resid, const float* __restrict__ pml_r,
            const float* __restrict__ pml_z, const float* __restrict__ ain,
            float* __restrict__ aout, const float* __restrict__ hist, float* __restrict__ acc,
-           float* __restrict__ acc_rho, long long cells_total)
+           float* __restrict__ acc_rho, float* __restrict__ acc_h, long long cells_total)
 {
     int w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     w = __builtin_amdgcn_readfirstlane(w);
@@ -495,9 +495,10 @@ k_adj_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
         const float Ez1_km = sh_up(X1.Ez);
         if (ip >= 1 && ip < NR) {
             const long long c = (long long)ip * NZ + kc;
-            const float avr = Q.avr + (X0.Err - X1.Err) * idr +
-                              X0.Ett * (0.5f / ((ip - 0.5f) * dr)) +
+            // the increment first: the density correlation needs it unrounded
+            const float dar = (X0.Err - X1.Err) * idr + X0.Ett * (0.5f / ((ip - 0.5f) * dr)) +
                               X1.Ett * (0.5f / ((ip + 0.5f) * dr)) + (Ez1_km - X1.Ez) * idz;
+            const float avr = Q.avr + dar;
             const float W = kin ? dt * (2.0f / (X0.rho + X1.rho)) * avr : 0.f;
             float aDr = W, aDz = W;
             if (ip >= nr) {  // A-bar
@@ -512,7 +513,7 @@ k_adj_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
             }
             if (own_ip) Ao[oVR + c] = avr;
             // density correlation (optional): increment of a_v times v^{n+1/2}
-            if (acc_rho && own_ip) acc_rho[S.cell_off + c] += (avr - Q.avr) * Q.vrh;
+            if (acc_rho && own_ip) acc_rho[S.cell_off + c] += dar * Q.vrh;
             R1_aDr = aDr;
             R1_aDzR = aDz;
             R1_hR = W * (0.5f / (ip * dr));
@@ -524,7 +525,8 @@ k_adj_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
         if (top) rho0_kp = X0.rho;
         if (i >= 0) {
             const long long c = (long long)i * NZ + kc;
-            const float avz = P.avz + (X0.Ezz - Ezz0_kp) * idz + (X0.Er - X1.Er) * idr;
+            const float daz = (X0.Ezz - Ezz0_kp) * idz + (X0.Er - X1.Er) * idr;
+            const float avz = P.avz + daz;
             const float W = kin ? dt * (2.0f / (X0.rho + rho0_kp)) * avz : 0.f;
             float aDr = W, aDz = W;
             if (i >= nr) {  // C-bar (radial, half position)
@@ -538,7 +540,7 @@ k_adj_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
                 aDz += a_zh * qv;
             }
             if (own_i) Ao[oVZ + c] = avz;
-            if (acc_rho && own_i) acc_rho[cells_total + S.cell_off + c] += (avz - P.avz) * P.vzh;
+            if (acc_rho && own_i) acc_rho[cells_total + S.cell_off + c] += daz * P.vzh;
             Z_aDrZ = aDr;
             Z_WZ = W;
             Z_aDzZ = aDz;
@@ -575,13 +577,21 @@ k_adj_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
             }
             const float ur = 0.5f * (vrh0 + vrh1), uz = 0.5f * (vzh0_km + vzh0);
             const float dge = dt * (ur * ur + uz * uz);
-            float dgs = 0.f;
+            float dgs = 0.f, es = 0.f;
             if (i >= 1) {
                 const float ez = (vrh0_kp - vrh0) * idz;
                 const float er = (vzh0 - vzhm) * idr;
+                es = ez + er;
                 dgs = dt * (ez + er) * X0.trz;
                 if (zp) dgs += a_zh * ez * X0.pG;
                 if (i >= nr) dgs += prt[i] * er * X0.pH;
+            }
+            // virtual-source pseudo-Hessian diagonal (optional)
+            if (acc_h && own) {
+                const float dv = err + ett + ezz;
+                acc_h[S.cell_off + c] += dt * dt * (3.0f * dv * dv);
+                acc_h[cells_total + S.cell_off + c] +=
+                    dt * dt * (4.0f * (err * err + ett * ett + ezz * ezz) + es * es);
             }
             if (own) {
                 Ao[oTRR + c] = nrr;
@@ -808,6 +818,23 @@ __global__ void k_finalize_rho_shot(const ShotDev* __restrict__ shots, int s,
     }
 }
 
+// Add two per-shot planes (src, src + cells_total) of one shot's window into
+// the global grids d0, d1.
+__global__ void k_window_add2(const ShotDev* __restrict__ shots, int s,
+                              const float* __restrict__ src, long long cells_total,
+                              float* __restrict__ d0, float* __restrict__ d1)
+{
+    const ShotDev& S = shots[s];
+    const int NZ = S.NZ;
+    const long long cells = (long long)S.NR * NZ;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += stride) {
+        const long long m = S.model_off + (c / NZ) * S.model_ld + (c % NZ);
+        d0[m] += src[S.cell_off + c];
+        d1[m] += src[cells_total + S.cell_off + c];
+    }
+}
+
 // Block-wise maxima over mask cells of up to four arrays (|x|), written as
 // non-negative floats to part[4 * block + q].
 __global__ void __launch_bounds__(256)
@@ -884,6 +911,74 @@ k_precond_apply(long long n, const uint8_t* __restrict__ mask, const float* __re
         __syncthreads();
     }
     if (threadIdx.x == 0) dot[blockIdx.x] = shd[0];
+}
+
+// One gradient scaled by P = w[row] / (d + eps max d) on mask cells (0
+// elsewhere); d (nullable: P without it is w alone) is a diagonal such as the
+// illumination or a pseudo-Hessian, w (nullable) a weight per radial row of
+// ld elements.  dot (nullable) receives the block sums of g . P g.
+__global__ void __launch_bounds__(256)
+k_precond_diag_apply(long long n, int ld, const uint8_t* __restrict__ mask,
+                     const float* __restrict__ diag, const float* __restrict__ roww, float eps,
+                     const float* __restrict__ part, int np, float* __restrict__ g,
+                     double* __restrict__ dot)
+{
+    __shared__ float sh[256];
+    __shared__ double shd[256];
+    const float dmax = diag ? reduce_part_max(part, np, 0, sh) : 0.f;
+    double s = 0.0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        if (!mask[i]) {
+            g[i] = 0.f;
+            continue;
+        }
+        float p = diag ? 1.0f / (diag[i] + eps * dmax) : 1.0f;
+        if (roww) p *= roww[i / ld];
+        const float gi = g[i];
+        g[i] = gi * p;
+        s += (double)p * ((double)gi * gi);
+    }
+    if (!dot) return;  // uniform
+    shd[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) shd[threadIdx.x] += shd[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) dot[blockIdx.x] = shd[0];
+}
+
+// Radial taper per row of C cells, r = (i + 1/2) dr: 0 inside r0, a sin^2
+// ramp to 1 at r1, 1 beyond.
+__global__ void k_radial_taper(int nrow, float dr, float r0, float r1, float* __restrict__ w)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrow) return;
+    const float r = (i + 0.5f) * dr;
+    const float x = fminf(fmaxf((r - r0) / fmaxf(r1 - r0, 1e-30f), 0.f), 1.f);
+    const float s = sinf(0.5f * 3.14159265358979f * x);
+    w[i] = s * s;
+}
+
+// Density step with its own greatest-change rule: alpha = eta max|rho| /
+// max|g| over mask cells (part: block maxima of |g| in slot 0 and of rho in
+// slot 1), rho <- clamp(rho - alpha g, rho_min, rho_max) on mask cells.
+__global__ void __launch_bounds__(256)
+k_update_density_apply(long long n, const uint8_t* __restrict__ mask, float* __restrict__ rho,
+                       const float* __restrict__ g, const float* __restrict__ part, int np,
+                       float eta, float rho_min, float rho_max, float* __restrict__ alpha_out)
+{
+    __shared__ float sh[256];
+    const float gmax = reduce_part_max(part, np, 0, sh);
+    const float rmax = reduce_part_max(part, np, 1, sh);
+    const float alpha = gmax > 0.f ? eta * rmax / gmax : 0.f;
+    if (alpha_out && blockIdx.x == 0 && threadIdx.x == 0) *alpha_out = alpha;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        if (!mask[i]) continue;
+        rho[i] = fminf(fmaxf(rho[i] - alpha * g[i], rho_min), rho_max);
+    }
 }
 
 // Step length of the parabolic line search.  With the misfit J0 at the

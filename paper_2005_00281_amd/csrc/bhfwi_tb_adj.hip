@@ -21,8 +21,10 @@
 // the forward kernel the step loop has no per-cell branches: zero
 // coefficients keep cells outside the grid and the axis nodes inert.
 //
-// RHO = 1 adds the density correlation (an extension: the paper holds the
-// density fixed).  The velocity update is v^{n+1/2} = v^{n-1/2} + b dv_n with
+// Optional outputs, selected by the bits of X (extensions of the paper, which
+// holds the density fixed and gives the preconditioner only as diagonal):
+//
+// X & 1 adds the density correlation.  The velocity update is v^{n+1/2} = v^{n-1/2} + b dv_n with
 // buoyancy b, so dJ/db = sum_n a_v^n dv_n with a_v^n the adjoint velocity
 // after the transposed stress update of step n.  Summed by parts, with
 // a_v^{nt} = 0 and v^{-1/2} = 0, b dJ/db = sum_n (a_v^n - a_v^{n+1}) v^{n+1/2},
@@ -30,13 +32,19 @@
 // transposed velocity update leaves a_v unchanged).  The kernel accumulates
 // that increment times the stored v^{n+1/2} at the R and Z nodes, so no
 // history beyond the velocities already kept is needed.
+//
+// X & 2 adds the virtual-source pseudo-Hessian diagonal: with the strain
+// rates of v^{n+1/2}, H_lambda += 3 dt^2 (e_rr + e_tt + e_zz)^2 (the lambda
+// derivative of the three normal-stress updates) and H_mu += dt^2 (4 (e_rr^2 +
+// e_tt^2 + e_zz^2) + (e_z + e_r)^2), the last term that of the tau_rz node with
+// the cell's index.
 #pragma once
 #include "bhfwi_internal.h"
 #include "bhfwi_tb_fwd.hip"
 
 namespace bhfwi {
 
-template <int T, int TRE, int W, int PM, int RHO>
+template <int T, int TRE, int W, int PM, int X>
 __global__ void __launch_bounds__(64 * W, (W >= 16 && (TRE == W || (PM == 0 && TRE <= 2 * W))) ? 8 : 1)
 k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int nwork, int map,
          int n_hi, int nsteps, const float* __restrict__ lam, const float* __restrict__ mu,
@@ -44,9 +52,11 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
          const float* __restrict__ resid, const float* __restrict__ pml_r,
          const float* __restrict__ pml_z, const float* __restrict__ ain,
          float* __restrict__ aout, const float* __restrict__ hist_hi, long long hist_stride,
-         float* __restrict__ acc, float* __restrict__ acc_rho, long long cells_total)
+         float* __restrict__ acc, float* __restrict__ acc_rho, float* __restrict__ acc_h,
+         long long cells_total)
 {
     static_assert(TRE % W == 0 && TRE > 2 * T && 64 > 2 * T, "tile too small for the halo");
+    constexpr bool RHO = (X & 1) != 0, HES = (X & 2) != 0;
     constexpr int RPT = TRE / W;
     constexpr int LDW = (TRE + 2) * 64;
     enum { ERR = 0, ETT, ER, UR, HR, ZR, HVR, HVZ, NPL };
@@ -102,7 +112,8 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
         pH[RPT];
     float a_ri[RPT], b_ri[RPT], a_rh[RPT], b_rh[RPT];
     float gl[RPT], gm[RPT], gs[RPT], ge[RPT];
-    float gR[RPT], gZ[RPT];  // density correlation (RHO = 1)
+    float gR[RPT], gZ[RPT];  // density correlation (X & 1)
+    float hL[RPT], hM[RPT];  // pseudo-Hessian diagonal (X & 2)
     float a_zi = 0.f, b_zi = 1.f, a_zh = 0.f, b_zh = 1.f;
     if (zp) {
         a_zi = pzt[k];
@@ -148,7 +159,7 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
         a_ri[j] = a_rh[j] = 0.f;
         b_ri[j] = b_rh[j] = 1.f;
         gl[j] = gm[j] = gs[j] = ge[j] = 0.f;
-        gR[j] = gZ[j] = 0.f;
+        gR[j] = gZ[j] = hL[j] = hM[j] = 0.f;
         if (tile_pml) {
             if (iin && i >= nr) {
                 a_ri[j] = prt[i];
@@ -296,6 +307,11 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
                     dgm += idt * 2.0f * (a_rh[j] * err * pRr[j] + a_zi * ezz * pZz[j]);
                     dgs += idt * (a_zh * ez * pG[j] + a_ri[j] * er * pH[j]);
                 }
+                if constexpr (HES) {
+                    const float dv = err + ett + ezz, es = mrow[j] * (ez + er);
+                    hL[j] += 3.0f * dv * dv;
+                    hM[j] += 4.0f * (err * err + ett * ett + ezz * ezz) + es * es;
+                }
                 const float ur = 0.5f * (vr0 + vr1), uz = 0.5f * (vz_km + vz0);
                 gl[j] += dt * dgl;
                 gm[j] += dt * dgm;
@@ -309,7 +325,7 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
                                   (Er_[j] - L[ER][x + 64]) * idr;
                 avr[j] += dar;
                 avz[j] += daz;
-                if constexpr (RHO != 0) {
+                if constexpr (RHO) {
                     gR[j] += dar * vr0;
                     gZ[j] += daz * vz0;
                 }
@@ -398,10 +414,15 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
         g[cells_total] += gm[j];
         if (i >= 1) g[2 * cells_total] += gs[j];
         g[3 * cells_total] += ge[j];
-        if constexpr (RHO != 0) {
+        if constexpr (RHO) {
             float* gr = acc_rho + S.cell_off + c;
             if (i >= 1) gr[0] += gR[j];
             gr[cells_total] += gZ[j];
+        }
+        if constexpr (HES) {
+            float* h = acc_h + S.cell_off + c;
+            h[0] += dt * dt * hL[j];
+            h[cells_total] += dt * dt * hM[j];
         }
     }
 }

@@ -17,6 +17,19 @@ checkpoints) of every group on the trial model for its misfit, and the
 minimum of the parabola through the two misfits and the slope along the
 preconditioned gradient (bhfwi_line_search); the whole iteration stays on
 the device without a host synchronisation.
+
+Extensions beyond the paper's fixed density and illumination preconditioner
+(all optional, off by default):
+  density=True     joint inversion: the adjoint pass also accumulates
+                   dJ/drho, preconditioned with the illumination and stepped
+                   with its own greatest-change rule (eta_rho, rho_bounds)
+                   before the moduli update;
+  precond="pseudo_hessian"
+                   the virtual-source pseudo-Hessian diagonals H_lambda and
+                   H_mu of the same adjoint pass replace the illumination as
+                   the diagonals of the lambda and mu preconditioners;
+  row_weight       a weight per radial row of the model (radial_taper) applied
+                   on top of the diagonal, muting the near-wall gradient.
 """
 from __future__ import annotations
 
@@ -27,7 +40,12 @@ from . import _lib
 
 class Inversion:
     def __init__(self, surveys, vp, vs, rho, wavelets, observed, mask, eps=1e-3, eta=0.02,
-                 bounds=(1000.0, 7000.0, 300.0, 4500.0), line_search=False):
+                 bounds=(1000.0, 7000.0, 300.0, 4500.0), line_search=False, density=False,
+                 eta_rho=None, rho_bounds=(1000.0, 3500.0), precond="illum", row_weight=None):
+        if precond not in ("illum", "pseudo_hessian"):
+            raise ValueError("precond must be 'illum' or 'pseudo_hessian'")
+        if density and line_search:
+            raise ValueError("the line search steps lambda and mu only; use density without it")
         if not isinstance(surveys, (list, tuple)):
             surveys, wavelets, observed = [surveys], [wavelets], [observed]
         self.surveys = list(surveys)
@@ -54,6 +72,20 @@ class Inversion:
         self.g_mu = torch.empty_like(vp)
         self.illum = torch.empty_like(vp)
         self.J = torch.zeros((), dtype=torch.float64, device=dev)
+        self.density = bool(density)
+        self.hessian = precond == "pseudo_hessian"
+        self.eta_rho = float(eta if eta_rho is None else eta_rho)
+        self.rho_bounds = tuple(rho_bounds)
+        self.row_weight = row_weight
+        cells = max(sv.sizes.cells for sv in self.surveys)
+        if self.density:
+            self.acc_rho = torch.empty(2 * cells, dtype=torch.float32, device=dev)
+            self.g_rho = torch.empty_like(vp)
+            self.alpha_rho = torch.zeros((), dtype=torch.float32, device=dev)
+        if self.hessian:
+            self.acc_h = torch.empty(2 * cells, dtype=torch.float32, device=dev)
+            self.h_lam = torch.empty_like(vp)
+            self.h_mu = torch.empty_like(vp)
         self.line_search = bool(line_search)
         self.after_group = None  # optional callback(stage, group) after each group's work
         if self.line_search:
@@ -72,8 +104,21 @@ class Inversion:
                          ckpt=ckpt, traces=self.traces[g])
             sv.misfit(self.traces[g], self.observed[g], resid=self.resid[g], J=self.J,
                       accumulate=g > 0)
-            sv.adjoint_model(self.lam, self.mu, self.rho, self.wavelets[g], self.resid[g],
-                             ckpt=ckpt, acc=self.acc)
+            if self.density or self.hessian:
+                sv.adjoint_model_ex(self.lam, self.mu, self.rho, self.wavelets[g],
+                                    self.resid[g], ckpt=ckpt, acc=self.acc,
+                                    density=self.density, hessian=self.hessian,
+                                    acc_rho=self.acc_rho if self.density else None,
+                                    acc_h=self.acc_h if self.hessian else None)
+                if self.density:
+                    sv.gradient_density(self.rho, self.acc_rho, out=self.g_rho,
+                                        accumulate=g > 0)
+                if self.hessian:
+                    sv.gradient_hessian(self.acc_h, out=(self.h_lam, self.h_mu),
+                                        accumulate=g > 0)
+            else:
+                sv.adjoint_model(self.lam, self.mu, self.rho, self.wavelets[g], self.resid[g],
+                                 ckpt=ckpt, acc=self.acc)
             sv.gradient(self.mu, self.acc, out=(self.g_lam, self.g_mu, self.illum),
                         accumulate=g > 0)
             if self.after_group:
@@ -85,8 +130,12 @@ class Inversion:
         J is a copy: the misfit buffer is overwritten by the next iteration."""
         self.gradient()
         sv = self.surveys[0]
+        if self.density:
+            sv.precondition_diag(self.g_rho, self.mask, self.eps, self.illum, self.row_weight)
+            sv.update_density(self.rho, self.g_rho, self.mask, self.eta_rho, *self.rho_bounds,
+                              alpha=self.alpha_rho)
         if not self.line_search:
-            sv.precondition(self.illum, self.mask, self.eps, self.g_lam, self.g_mu)
+            self._precondition()
             alpha = sv.update(self.lam, self.mu, self.rho, self.g_lam, self.g_mu, self.mask,
                               self.eta, bounds=self.bounds)
         else:
@@ -94,9 +143,21 @@ class Inversion:
         _lib.velocities(self.lam, self.mu, self.rho, out=(self.vp, self.vs))
         return self.J.clone(), alpha
 
+    def _precondition(self, gpg=None):
+        """The lambda and mu gradients through the chosen diagonal (and the
+        row weights); gpg (nullable) receives sum g . P g over both."""
+        sv = self.surveys[0]
+        if not self.hessian and self.row_weight is None:
+            sv.precondition(self.illum, self.mask, self.eps, self.g_lam, self.g_mu, gpg=gpg)
+            return
+        d_l, d_m = (self.h_lam, self.h_mu) if self.hessian else (self.illum, self.illum)
+        sv.precondition_diag(self.g_lam, self.mask, self.eps, d_l, self.row_weight, gpg=gpg)
+        sv.precondition_diag(self.g_mu, self.mask, self.eps, d_m, self.row_weight, gpg=gpg,
+                             accumulate=True)
+
     def _line_search_step(self):
         sv = self.surveys[0]
-        sv.precondition(self.illum, self.mask, self.eps, self.g_lam, self.g_mu, gpg=self.gpg)
+        self._precondition(gpg=self.gpg)
         self.lam1.copy_(self.lam)
         self.mu1.copy_(self.mu)
         alpha1 = sv.update(self.lam1, self.mu1, self.rho, self.g_lam, self.g_mu, self.mask,
