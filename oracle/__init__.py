@@ -66,6 +66,13 @@ def _load():
         lib.orc_gradient.argtypes = [G, _D, _D, _D, _D, _D, C.c_int32, _D, _D, _D, _D, _D,
                                      _D]
         lib.orc_gradient.restype = C.c_int
+        lib.orc_forward_asm.argtypes = [G, C.c_int32, _D, _D, _D, _D, _D, _D]
+        lib.orc_forward_asm.restype = C.c_int
+        lib.orc_propagate_asm.argtypes = [G, C.c_int32, _D, _D, _D, _D, C.c_int32, C.c_int32]
+        lib.orc_propagate_asm.restype = C.c_int
+        lib.orc_gradient_asm.argtypes = [G, C.c_int32, _D, _D, _D, _D, _D, C.c_int32, _D, _D,
+                                         _D]
+        lib.orc_gradient_asm.restype = C.c_int
         lib.orc_source_adjoint.argtypes = [G, _D, _D, _D, _D, _D]
         lib.orc_source_adjoint.restype = C.c_int
         lib.orc_state_len.argtypes = [G]
@@ -167,9 +174,10 @@ def velocities(lam, mu, rho):
     return vp, vs
 
 
-def forward(g: Geom, lam, mu, rho, wavelet, return_state=False):
+def forward(g: Geom, lam, mu, rho, wavelet, return_state=False, order=2, assembled=False):
     """Eq. 2 forward modelling; returns traces [nrec, nt] (and the final state,
-    14 x NR x NZ, when asked)."""
+    14 x NR x NZ, when asked).  order=4, or assembled=True, runs the
+    assembled-operator step (orc_forward_asm) of that spatial order."""
     shp = (g.NR, g.NZ)
     lam, mu, rho = _f64(lam, shp), _f64(mu, shp), _f64(rho, shp)
     w = _f64(wavelet)
@@ -177,6 +185,11 @@ def forward(g: Geom, lam, mu, rho, wavelet, return_state=False):
     gc, rk = g._c()
     tr = np.zeros((len(rk), g.nt))
     st = np.zeros((14,) + shp) if return_state else None
+    if order != 2 or assembled:
+        rc = _load().orc_forward_asm(C.byref(gc), int(order), _p(lam), _p(mu), _p(rho), _p(w),
+                                     _p(tr), _p(st) if st is not None else None)
+        _check(rc, "forward_asm")
+        return (tr, st) if return_state else tr
     rc = _load().orc_forward(C.byref(gc), _p(lam), _p(mu), _p(rho), _p(w), _p(tr),
                              _p(st) if st is not None else None)
     _check(rc, "forward")
@@ -191,16 +204,25 @@ def misfit(d, dobs):
     return J, r
 
 
-def gradient(g: Geom, lam, mu, rho, wavelet, resid, seg=200, density=False, hessian=False):
+def gradient(g: Geom, lam, mu, rho, wavelet, resid, seg=200, density=False, hessian=False,
+             order=2, assembled=False):
     """Eq. 6-8 via the exact discrete transpose; returns (glam, gmu, illum),
     then dJ/drho with density=True, then (H_lambda, H_mu), the
-    virtual-source pseudo-Hessian diagonal, with hessian=True."""
+    virtual-source pseudo-Hessian diagonal, with hessian=True.  order=4, or
+    assembled=True, uses the assembled operators (modulus gradients only)."""
     shp = (g.NR, g.NZ)
     lam, mu, rho = _f64(lam, shp), _f64(mu, shp), _f64(rho, shp)
     w, r = _f64(wavelet), _f64(resid)
     gc, rk = g._c()
     assert r.size == len(rk) * g.nt
     gl, gm, il = np.zeros(shp), np.zeros(shp), np.zeros(shp)
+    if order != 2 or assembled:
+        if density or hessian:
+            raise ValueError("the assembled operators give the modulus gradients only")
+        rc = _load().orc_gradient_asm(C.byref(gc), int(order), _p(lam), _p(mu), _p(rho), _p(w),
+                                      _p(r), int(seg), _p(gl), _p(gm), _p(il))
+        _check(rc, "gradient_asm")
+        return gl, gm, il
     gr = np.zeros(shp) if density else None
     hl, hm = (np.zeros(shp), np.zeros(shp)) if hessian else (None, None)
     opt = lambda a: _p(a) if a is not None else None  # noqa: E731
@@ -227,7 +249,7 @@ def source_adjoint(g: Geom, lam, mu, rho, resid):
     return out
 
 
-def propagate(g: Geom, lam, mu, rho, state, nsteps, adjoint=False):
+def propagate(g: Geom, lam, mu, rho, state, nsteps, adjoint=False, order=2, assembled=False):
     """nsteps source-free steps (or their exact transpose) on a full state."""
     shp = (g.NR, g.NZ)
     lam, mu, rho = _f64(lam, shp), _f64(mu, shp), _f64(rho, shp)
@@ -235,6 +257,10 @@ def propagate(g: Geom, lam, mu, rho, state, nsteps, adjoint=False):
     gc, rk = g._c()
     lib = _load()
     assert st.size == lib.orc_state_len(C.byref(gc))
+    if order != 2 or assembled:
+        _check(lib.orc_propagate_asm(C.byref(gc), int(order), _p(lam), _p(mu), _p(rho), _p(st),
+                                     int(nsteps), 1 if adjoint else 0), "propagate_asm")
+        return st
     fn = lib.orc_propagate_adjoint if adjoint else lib.orc_propagate
     _check(fn(C.byref(gc), _p(lam), _p(mu), _p(rho), _p(st), int(nsteps)), "propagate")
     return st

@@ -528,6 +528,24 @@ double orc_misfit(int64_t n, const double *d, const double *dobs, double *resid)
     return J;
 }
 
+/* Rigidity at tau_rz nodes is the harmonic mean of the four adjacent C cells:
+ * d muS / d mu_c = muS^2 / (4 mu_c^2) per occurrence of c among the four. */
+static void fold_mu_s(const grid *G, const double *gmuS, double *gmu)
+{
+    const int NR = G->NR, NZ = G->NZ;
+    for (int i = 1; i < NR; ++i)
+        for (int k = 0; k < NZ; ++k) {
+            double ms = mu_S(G, i, k);
+            if (!(ms > 0)) continue;
+            int k1 = k + 1 < NZ ? k + 1 : NZ - 1;
+            size_t nb[4] = {IX(i - 1, k), IX(i, k), IX(i - 1, k1), IX(i, k1)};
+            for (int q = 0; q < 4; ++q) {
+                double mc = G->mu[nb[q]];
+                gmu[nb[q]] += gmuS[IX(i, k)] * ms * ms / (4.0 * mc * mc);
+            }
+        }
+}
+
 static void inject_residual(const orc_geom *g, int NZ, state *a, const double *resid, int n)
 {
     for (int j = 0; j < g->nrec; ++j) {
@@ -650,19 +668,7 @@ int orc_gradient(const orc_geom *g, const double *lam, const double *mu, const d
                 grho[IX(i, k1)] += t;
             }
     }
-    /* rigidity at tau_rz nodes is the harmonic mean of the four adjacent C cells:
-     * d muS / d mu_c = muS^2 / (4 mu_c^2) per occurrence of c among the four */
-    for (int i = 1; i < NR; ++i)
-        for (int k = 0; k < NZ; ++k) {
-            double ms = mu_S(&G, i, k);
-            if (!(ms > 0)) continue;
-            int k1 = k + 1 < NZ ? k + 1 : NZ - 1;
-            size_t nb[4] = {IX(i - 1, k), IX(i, k), IX(i - 1, k1), IX(i, k1)};
-            for (int q = 0; q < 4; ++q) {
-                double mc = mu[nb[q]];
-                gmu[nb[q]] += gmuS[IX(i, k)] * ms * ms / (4.0 * mc * mc);
-            }
-        }
+    fold_mu_s(&G, gmuS, gmu);
     free(ckpt); free(fmem); free(amem); free(eps); free(gmuS); free(dvb); free(gb);
     grid_free(&G);
     return 0;
@@ -857,4 +863,506 @@ void orc_starting_model(int32_t NR, int32_t NZ, double dr, double a, double dist
             vs[c] = vs_wall[k] + f * (vs_far[k] - vs_wall[k]);
         }
     }
+}
+
+/* ===========================================================================
+ * Assembled operators: the leapfrog step of Eq. 2 written as two sparse linear
+ * maps over the 14-plane state, V (velocity update and its PML memories) then
+ * S (stress update and its PML memories), for staggered differences of order
+ * 2 or 4 in space.  The fourth-order scheme (the finite-difference scheme the
+ * Method section cites is of this family; the order is a reading) replaces
+ * every staggered difference and every two-point 1/r average by
+ *     D f = [c1 (f(+1/2) - f(-1/2)) + c2 (f(+3/2) - f(-3/2))] / h,
+ *     I f =  g1 (f(+1/2) + f(-1/2)) + g2 (f(+3/2) + f(-3/2)),
+ * c1 = 9/8, c2 = -1/24, g1 = 9/16, g2 = -1/16 (order 2: 1, 0, 1/2, 0, which is
+ * the hand-written step above).  D + I/r is then exactly the conservative
+ * (1/r) d(r f)/dr of the wider stencil.  Values beyond the outer radius and
+ * the axial ends are zero; across the axis the fields are mirrored: those at
+ * half radial positions (normal stresses, v_z) are even, those at integer
+ * positions (v_r, tau_rz) odd and zero on the axis.  Medium averaging, PML,
+ * source and receivers are those of the second-order step.
+ *
+ * Each row of V and S is assembled from the stencil as written; the adjoint is
+ * the transpose of the assembled rows applied in scatter form, so it is exact
+ * by construction.
+ * ========================================================================= */
+enum { P_VR = 0, P_VZ, P_TRR, P_TTT, P_TZZ, P_TRZ, P_PA, P_PB, P_PC, P_PD, P_PE, P_PF, P_PG,
+       P_PH, P_N };
+
+typedef struct {
+    size_t n, cap;
+    int64_t *col;
+    double *val;
+} lform;
+
+typedef struct {
+    size_t nrow, nnz, cap;
+    size_t *ptr;
+    int64_t *col;
+    double *val;
+} spm;
+
+typedef struct {
+    const grid *G;
+    size_t N;
+    double c1, c2, g1, g2;
+} asm_ctx;
+
+static int lf_push(lform *L, int64_t col, double v)
+{
+    if (v == 0.0) return 0;
+    if (L->n == L->cap) {
+        size_t nc = L->cap ? 2 * L->cap : 32;
+        int64_t *c = realloc(L->col, nc * sizeof(int64_t));
+        if (!c) return -1;
+        L->col = c;
+        double *w = realloc(L->val, nc * sizeof(double));
+        if (!w) return -1;
+        L->val = w;
+        L->cap = nc;
+    }
+    L->col[L->n] = col;
+    L->val[L->n] = v;
+    ++L->n;
+    return 0;
+}
+
+/* the value of plane p at radial row i, axial row k, with the axis mirror and
+ * zero outside the grid */
+static void lf_at(lform *L, const asm_ctx *A, int p, int i, int k, double v)
+{
+    const int NR = A->G->NR, NZ = A->G->NZ;
+    if (k < 0 || k >= NZ) return;
+    const int odd = (p == P_VR || p == P_TRZ);
+    if (i < 0) {
+        if (odd) {
+            i = -i;
+            v = -v;
+        } else {
+            i = -1 - i;
+        }
+    }
+    if (odd && i == 0) return; /* zero on the axis */
+    if (i >= NR) return;
+    lf_push(L, (int64_t)p * (int64_t)A->N + (int64_t)IX(i, k), v);
+}
+
+/* D (scaled by s/h) and I (scaled by s) along r or z of plane p; lo is the
+ * index of the input just below the output node */
+static void lf_D(lform *L, const asm_ctx *A, int p, int radial, int i, int k, int lo, double s)
+{
+    const double h = radial ? A->G->dr : A->G->dz;
+    const double w1 = A->c1 * s / h, w2 = A->c2 * s / h;
+    if (radial) {
+        lf_at(L, A, p, lo + 1, k, w1);
+        lf_at(L, A, p, lo, k, -w1);
+        lf_at(L, A, p, lo + 2, k, w2);
+        lf_at(L, A, p, lo - 1, k, -w2);
+    } else {
+        lf_at(L, A, p, i, lo + 1, w1);
+        lf_at(L, A, p, i, lo, -w1);
+        lf_at(L, A, p, i, lo + 2, w2);
+        lf_at(L, A, p, i, lo - 1, -w2);
+    }
+}
+static void lf_I(lform *L, const asm_ctx *A, int p, int i, int k, int lo, double s)
+{
+    lf_at(L, A, p, lo + 1, k, A->g1 * s);
+    lf_at(L, A, p, lo, k, A->g1 * s);
+    lf_at(L, A, p, lo + 2, k, A->g2 * s);
+    lf_at(L, A, p, lo - 1, k, A->g2 * s);
+}
+
+static void lf_scaled(lform *dst, const lform *src, double s)
+{
+    for (size_t q = 0; q < src->n; ++q) lf_push(dst, src->col[q], s * src->val[q]);
+}
+
+static int spm_row(spm *M, const lform *L)
+{
+    if (M->nnz + L->n > M->cap) {
+        size_t nc = M->cap ? M->cap : 1024;
+        while (nc < M->nnz + L->n) nc *= 2;
+        int64_t *c = realloc(M->col, nc * sizeof(int64_t));
+        if (!c) return -1;
+        M->col = c;
+        double *w = realloc(M->val, nc * sizeof(double));
+        if (!w) return -1;
+        M->val = w;
+        M->cap = nc;
+    }
+    memcpy(M->col + M->nnz, L->col, L->n * sizeof(int64_t));
+    memcpy(M->val + M->nnz, L->val, L->n * sizeof(double));
+    M->nnz += L->n;
+    M->ptr[++M->nrow] = M->nnz;
+    return 0;
+}
+
+static void spm_free(spm *M)
+{
+    free(M->ptr);
+    free(M->col);
+    free(M->val);
+}
+
+/* y = M x (all rows) or y += M^T x */
+static void spm_apply(const spm *M, const double *x, double *y)
+{
+    for (size_t r = 0; r < M->nrow; ++r) {
+        double s = 0.0;
+        for (size_t q = M->ptr[r]; q < M->ptr[r + 1]; ++q) s += M->val[q] * x[M->col[q]];
+        y[r] = s;
+    }
+}
+static void spm_apply_t(const spm *M, const double *x, double *y)
+{
+    for (size_t r = 0; r < M->nrow; ++r) {
+        const double xr = x[r];
+        if (xr == 0.0) continue;
+        for (size_t q = M->ptr[r]; q < M->ptr[r + 1]; ++q) y[M->col[q]] += M->val[q] * xr;
+    }
+}
+
+/* A derivative form D with its PML memory: with the memory on, the row of the
+ * memory is psi' = b psi + a D and the derivative used is D + psi' =
+ * (1 + a) D + b psi. */
+static void pml_pair(const asm_ctx *A, const lform *D, int on, double a, double b, int64_t psi,
+                     lform *eff, lform *psirow)
+{
+    if (on) {
+        lf_scaled(eff, D, 1.0 + a);
+        lf_push(eff, psi, b);
+        lf_push(psirow, psi, b);
+        lf_scaled(psirow, D, a);
+    } else {
+        lf_scaled(eff, D, 1.0);
+        lf_push(psirow, psi, 1.0);
+    }
+    (void)A;
+}
+
+typedef struct {
+    spm V, S, E; /* E: 4 N strain rows (e_rr', e_tt, e_zz', e_z' + e_r') over the state after V */
+} asm_ops;
+
+static void ops_free(asm_ops *O)
+{
+    spm_free(&O->V);
+    spm_free(&O->S);
+    spm_free(&O->E);
+}
+
+static int ops_build(const grid *G, int order, asm_ops *O)
+{
+    memset(O, 0, sizeof(*O));
+    asm_ctx A;
+    A.G = G;
+    A.N = (size_t)G->NR * G->NZ;
+    if (order == 2) {
+        A.c1 = 1.0; A.c2 = 0.0; A.g1 = 0.5; A.g2 = 0.0;
+    } else if (order == 4) {
+        A.c1 = 9.0 / 8.0; A.c2 = -1.0 / 24.0; A.g1 = 9.0 / 16.0; A.g2 = -1.0 / 16.0;
+    } else {
+        return -1;
+    }
+    const int NR = G->NR, NZ = G->NZ;
+    const size_t N = A.N;
+    const double dt = G->dt, dr = G->dr;
+    O->V.ptr = calloc(P_N * N + 1, sizeof(size_t));
+    O->S.ptr = calloc(P_N * N + 1, sizeof(size_t));
+    O->E.ptr = calloc(4 * N + 1, sizeof(size_t));
+    if (!O->V.ptr || !O->S.ptr || !O->E.ptr) {
+        ops_free(O);
+        return -1;
+    }
+    /* rows of V and S in state order: plane-major, then (i, k); each plane's
+     * rows are collected per node first (some nodes define several planes) */
+    lform *rowV = calloc(P_N * N, sizeof(lform)), *rowS = calloc(P_N * N, sizeof(lform));
+    lform *rowE = calloc(4 * N, sizeof(lform));
+    if (!rowV || !rowS || !rowE) {
+        free(rowV); free(rowS); free(rowE);
+        ops_free(O);
+        return -1;
+    }
+#define ROW(R, p, c) (&(R)[(size_t)(p) * N + (c)])
+#define COL(p, c) ((int64_t)(p) * (int64_t)N + (int64_t)(c))
+    for (int i = 0; i < NR; ++i)
+        for (int k = 0; k < NZ; ++k) {
+            const size_t c = IX(i, k);
+            lform t = {0};
+            /* ---- V: v_r at R(i,k), i >= 1 */
+            if (i >= 1) {
+                lform Dr = {0}, Dz = {0}, vr = {0};
+                lf_D(&Dr, &A, P_TRR, 1, i, k, i - 1, 1.0);
+                lf_D(&Dz, &A, P_TRZ, 0, i, k, k - 1, 1.0);
+                const double bR = buoy_R(G, i, k), ri = i * dr;
+                lf_push(&vr, COL(P_VR, c), 1.0);
+                lform eff = {0};
+                pml_pair(&A, &Dr, G->onr_i[i], G->ar_i[i], G->br_i[i], COL(P_PA, c), &eff,
+                         ROW(rowV, P_PA, c));
+                pml_pair(&A, &Dz, G->onz_i[k], G->az_i[k], G->bz_i[k], COL(P_PB, c), &eff,
+                         ROW(rowV, P_PB, c));
+                lf_I(&eff, &A, P_TRR, i, k, i - 1, 1.0 / ri);
+                lf_I(&eff, &A, P_TTT, i, k, i - 1, -1.0 / ri);
+                lf_scaled(&vr, &eff, dt * bR);
+                *ROW(rowV, P_VR, c) = vr;
+                free(Dr.col); free(Dr.val); free(Dz.col); free(Dz.val);
+                free(eff.col); free(eff.val);
+            } else {
+                lf_push(ROW(rowV, P_VR, c), COL(P_VR, c), 1.0);
+                lf_push(ROW(rowV, P_PA, c), COL(P_PA, c), 1.0);
+                lf_push(ROW(rowV, P_PB, c), COL(P_PB, c), 1.0);
+            }
+            /* ---- V: v_z at Z(i,k) */
+            {
+                lform Dr = {0}, Dz = {0}, vz = {0}, eff = {0};
+                lf_D(&Dr, &A, P_TRZ, 1, i, k, i, 1.0);
+                lf_D(&Dz, &A, P_TZZ, 0, i, k, k, 1.0);
+                const double bZ = buoy_Z(G, i, k), rh = (i + 0.5) * dr;
+                lf_push(&vz, COL(P_VZ, c), 1.0);
+                pml_pair(&A, &Dr, G->onr_h[i], G->ar_h[i], G->br_h[i], COL(P_PC, c), &eff,
+                         ROW(rowV, P_PC, c));
+                pml_pair(&A, &Dz, G->onz_h[k], G->az_h[k], G->bz_h[k], COL(P_PD, c), &eff,
+                         ROW(rowV, P_PD, c));
+                lf_I(&eff, &A, P_TRZ, i, k, i, 1.0 / rh);
+                lf_scaled(&vz, &eff, dt * bZ);
+                *ROW(rowV, P_VZ, c) = vz;
+                free(Dr.col); free(Dr.val); free(Dz.col); free(Dz.val);
+                free(eff.col); free(eff.val);
+            }
+            /* V leaves the stresses and their memories alone */
+            for (int p = P_TRR; p <= P_TRZ; ++p) lf_push(ROW(rowV, p, c), COL(p, c), 1.0);
+            for (int p = P_PE; p <= P_PH; ++p) lf_push(ROW(rowV, p, c), COL(p, c), 1.0);
+
+            /* ---- S: normal stresses at C(i,k) */
+            {
+                lform Dr = {0}, Dz = {0}, err = {0}, ett = {0}, ezz = {0};
+                lf_D(&Dr, &A, P_VR, 1, i, k, i, 1.0);
+                lf_D(&Dz, &A, P_VZ, 0, i, k, k - 1, 1.0);
+                const double rh = (i + 0.5) * dr;
+                pml_pair(&A, &Dr, G->onr_h[i], G->ar_h[i], G->br_h[i], COL(P_PE, c), &err,
+                         ROW(rowS, P_PE, c));
+                pml_pair(&A, &Dz, G->onz_i[k], G->az_i[k], G->bz_i[k], COL(P_PF, c), &ezz,
+                         ROW(rowS, P_PF, c));
+                lf_I(&ett, &A, P_VR, i, k, i, 1.0 / rh);
+                const double l = G->lam[c], m = G->mu[c];
+                const double wr[3] = {l + 2.0 * m, l, l}, wt[3] = {l, l + 2.0 * m, l},
+                             wz[3] = {l, l, l + 2.0 * m};
+                const int pl[3] = {P_TRR, P_TTT, P_TZZ};
+                for (int q = 0; q < 3; ++q) {
+                    lform *R = ROW(rowS, pl[q], c);
+                    lf_push(R, COL(pl[q], c), 1.0);
+                    lf_scaled(R, &err, dt * wr[q]);
+                    lf_scaled(R, &ett, dt * wt[q]);
+                    lf_scaled(R, &ezz, dt * wz[q]);
+                }
+                lf_scaled(ROW(rowE, 0, c), &err, 1.0);
+                lf_scaled(ROW(rowE, 1, c), &ett, 1.0);
+                lf_scaled(ROW(rowE, 2, c), &ezz, 1.0);
+                free(Dr.col); free(Dr.val); free(Dz.col); free(Dz.val);
+                free(err.col); free(err.val); free(ett.col); free(ett.val);
+                free(ezz.col); free(ezz.val);
+            }
+            /* ---- S: tau_rz at S(i,k), i >= 1 */
+            if (i >= 1) {
+                lform Dz = {0}, Dr = {0}, es = {0};
+                lf_D(&Dz, &A, P_VR, 0, i, k, k, 1.0);
+                lf_D(&Dr, &A, P_VZ, 1, i, k, i - 1, 1.0);
+                pml_pair(&A, &Dz, G->onz_h[k], G->az_h[k], G->bz_h[k], COL(P_PG, c), &es,
+                         ROW(rowS, P_PG, c));
+                pml_pair(&A, &Dr, G->onr_i[i], G->ar_i[i], G->br_i[i], COL(P_PH, c), &es,
+                         ROW(rowS, P_PH, c));
+                lform *R = ROW(rowS, P_TRZ, c);
+                lf_push(R, COL(P_TRZ, c), 1.0);
+                lf_scaled(R, &es, dt * mu_S(G, i, k));
+                lf_scaled(ROW(rowE, 3, c), &es, 1.0);
+                free(Dz.col); free(Dz.val); free(Dr.col); free(Dr.val);
+                free(es.col); free(es.val);
+            } else {
+                lf_push(ROW(rowS, P_TRZ, c), COL(P_TRZ, c), 1.0);
+                lf_push(ROW(rowS, P_PG, c), COL(P_PG, c), 1.0);
+                lf_push(ROW(rowS, P_PH, c), COL(P_PH, c), 1.0);
+            }
+            /* S leaves the velocities and their memories alone */
+            for (int p = P_VR; p <= P_VZ; ++p) lf_push(ROW(rowS, p, c), COL(p, c), 1.0);
+            for (int p = P_PA; p <= P_PD; ++p) lf_push(ROW(rowS, p, c), COL(p, c), 1.0);
+            (void)t;
+        }
+    int rc = 0;
+    for (size_t r = 0; r < P_N * N && !rc; ++r) rc |= spm_row(&O->V, &rowV[r]);
+    for (size_t r = 0; r < P_N * N && !rc; ++r) rc |= spm_row(&O->S, &rowS[r]);
+    for (size_t r = 0; r < 4 * N && !rc; ++r) rc |= spm_row(&O->E, &rowE[r]);
+    for (size_t r = 0; r < P_N * N; ++r) {
+        free(rowV[r].col); free(rowV[r].val); free(rowS[r].col); free(rowS[r].val);
+    }
+    for (size_t r = 0; r < 4 * N; ++r) {
+        free(rowE[r].col); free(rowE[r].val);
+    }
+    free(rowV); free(rowS); free(rowE);
+#undef ROW
+#undef COL
+    if (rc) ops_free(O);
+    return rc;
+}
+
+/* one step s <- S (V s) plus the source; eps (nullable, 4 N) receives the
+ * strain rates the stress update used */
+static void asm_step(const asm_ops *O, size_t N, int NZ, double *s, double *tmp, int src_k,
+                     double srcval, double *eps)
+{
+    spm_apply(&O->V, s, tmp);
+    if (eps) spm_apply(&O->E, tmp, eps);
+    spm_apply(&O->S, tmp, s);
+    size_t c = IX(0, src_k);
+    s[P_TRR * N + c] += srcval;
+    s[P_TTT * N + c] += srcval;
+    s[P_TZZ * N + c] += srcval;
+}
+
+/* the transpose of asm_step without the source: a <- V^T (S^T a) */
+static void asm_step_t(const asm_ops *O, size_t N, double *a, double *tmp)
+{
+    memset(tmp, 0, P_N * N * sizeof(double));
+    spm_apply_t(&O->S, a, tmp);
+    memset(a, 0, P_N * N * sizeof(double));
+    spm_apply_t(&O->V, tmp, a);
+}
+
+int orc_forward_asm(const orc_geom *g, int32_t order, const double *lam, const double *mu,
+                    const double *rho, const double *wavelet, double *traces,
+                    double *final_state)
+{
+    grid G;
+    if (grid_init(&G, g, lam, mu, rho) || !geom_ok(g)) return -1;
+    asm_ops O;
+    if (ops_build(&G, order, &O)) {
+        grid_free(&G);
+        return -1;
+    }
+    const int NZ = G.NZ;
+    const size_t N = (size_t)G.NR * G.NZ;
+    double *s = calloc(P_N * N, sizeof(double)), *tmp = calloc(P_N * N, sizeof(double));
+    int rc = (!s || !tmp) ? -1 : 0;
+    const double sc = src_scale(&G);
+    for (int n = 0; n < g->nt && !rc; ++n) {
+        asm_step(&O, N, NZ, s, tmp, g->src_k, sc * wavelet[n], NULL);
+        for (int j = 0; j < g->nrec; ++j) {
+            size_t c = IX(0, g->rec_k[j]);
+            traces[(size_t)j * g->nt + n] = (s[P_TRR * N + c] + s[P_TTT * N + c] +
+                                             s[P_TZZ * N + c]) / 3.0;
+        }
+    }
+    if (!rc && final_state) memcpy(final_state, s, P_N * N * sizeof(double));
+    free(s); free(tmp);
+    ops_free(&O);
+    grid_free(&G);
+    return rc;
+}
+
+int orc_propagate_asm(const orc_geom *g, int32_t order, const double *lam, const double *mu,
+                      const double *rho, double *st, int32_t nsteps, int32_t adjoint)
+{
+    grid G;
+    if (grid_init(&G, g, lam, mu, rho) || !geom_ok(g)) return -1;
+    asm_ops O;
+    if (ops_build(&G, order, &O)) {
+        grid_free(&G);
+        return -1;
+    }
+    const int NZ = G.NZ;
+    const size_t N = (size_t)G.NR * G.NZ;
+    double *tmp = calloc(P_N * N, sizeof(double));
+    if (!tmp) {
+        ops_free(&O);
+        grid_free(&G);
+        return -1;
+    }
+    for (int n = 0; n < nsteps; ++n) {
+        if (adjoint)
+            asm_step_t(&O, N, st, tmp);
+        else
+            asm_step(&O, N, NZ, st, tmp, g->src_k, 0.0, NULL);
+    }
+    free(tmp);
+    ops_free(&O);
+    grid_free(&G);
+    return 0;
+}
+
+int orc_gradient_asm(const orc_geom *g, int32_t order, const double *lam, const double *mu,
+                     const double *rho, const double *wavelet, const double *resid,
+                     int32_t seg, double *glam, double *gmu, double *illum)
+{
+    grid G;
+    if (seg <= 0 || grid_init(&G, g, lam, mu, rho) || !geom_ok(g)) return -1;
+    asm_ops O;
+    if (ops_build(&G, order, &O)) {
+        grid_free(&G);
+        return -1;
+    }
+    const int NR = G.NR, NZ = G.NZ, nt = g->nt;
+    const double dt = G.dt;
+    const size_t N = (size_t)NR * NZ, SL = P_N * N;
+    const int nseg = (nt + seg - 1) / seg;
+    double *ckpt = malloc((size_t)(nseg > 0 ? nseg : 1) * SL * sizeof(double));
+    double *s = calloc(SL, sizeof(double)), *a = calloc(SL, sizeof(double));
+    double *tmp = calloc(SL, sizeof(double));
+    double *eps = malloc((size_t)seg * 4 * N * sizeof(double));
+    double *gmuS = calloc(N, sizeof(double));
+    if (!ckpt || !s || !a || !tmp || !eps || !gmuS) {
+        free(ckpt); free(s); free(a); free(tmp); free(eps); free(gmuS);
+        ops_free(&O);
+        grid_free(&G);
+        return -1;
+    }
+    const double sc = src_scale(&G);
+    memset(glam, 0, N * sizeof(double));
+    memset(gmu, 0, N * sizeof(double));
+    memset(illum, 0, N * sizeof(double));
+    /* forward pass: checkpoints, illumination from v^{n+1/2} averaged to C nodes */
+    for (int n = 0; n < nt; ++n) {
+        if (n % seg == 0) memcpy(ckpt + (size_t)(n / seg) * SL, s, SL * sizeof(double));
+        asm_step(&O, N, NZ, s, tmp, g->src_k, sc * wavelet[n], NULL);
+        const double *vr = s + P_VR * N, *vz = s + P_VZ * N;
+        for (int i = 0; i < NR; ++i)
+            for (int k = 0; k < NZ; ++k) {
+                size_t c = IX(i, k);
+                double vr_ip = i + 1 < NR ? vr[IX(i + 1, k)] : 0.0;
+                double vz_km = k > 0 ? vz[IX(i, k - 1)] : 0.0;
+                double ur = 0.5 * (vr[c] + vr_ip), uz = 0.5 * (vz_km + vz[c]);
+                illum[c] += dt * (ur * ur + uz * uz);
+            }
+    }
+    /* reverse pass, one segment at a time */
+    for (int j = nseg - 1; j >= 0; --j) {
+        int n0 = j * seg, n1 = n0 + seg < nt ? n0 + seg : nt;
+        memcpy(s, ckpt + (size_t)j * SL, SL * sizeof(double));
+        for (int n = n0; n < n1; ++n)
+            asm_step(&O, N, NZ, s, tmp, g->src_k, sc * wavelet[n], eps + (size_t)(n - n0) * 4 * N);
+        for (int n = n1 - 1; n >= n0; --n) {
+            for (int q = 0; q < g->nrec; ++q) {
+                size_t c = IX(0, g->rec_k[q]);
+                double r3 = resid[(size_t)q * nt + n] / 3.0;
+                a[P_TRR * N + c] += r3;
+                a[P_TTT * N + c] += r3;
+                a[P_TZZ * N + c] += r3;
+            }
+            const double *e = eps + (size_t)(n - n0) * 4 * N;
+            /* Eq. 7 and Eq. 8 with the strain rates of this scheme */
+            for (size_t c = 0; c < N; ++c) {
+                double err = e[c], ett = e[N + c], ezz = e[2 * N + c];
+                double atr = a[P_TRR * N + c], att = a[P_TTT * N + c], atz = a[P_TZZ * N + c];
+                double sa = atr + att + atz;
+                glam[c] += dt * (err + ett + ezz) * sa;
+                gmu[c] += dt * 2.0 * (err * atr + ett * att + ezz * atz);
+                gmuS[c] += dt * e[3 * N + c] * a[P_TRZ * N + c];
+            }
+            asm_step_t(&O, N, a, tmp);
+        }
+    }
+    fold_mu_s(&G, gmuS, gmu);
+    free(ckpt); free(s); free(a); free(tmp); free(eps); free(gmuS);
+    ops_free(&O);
+    grid_free(&G);
+    return 0;
 }

@@ -140,4 +140,26 @@ double orc_update(int64_t n, double *lam, double *mu, const double *rho,
                   const double *g_lam, const double *g_mu, const uint8_t *mask,
                   double eta, double alpha_override,
                   double vp_min, double vp_max, double vs_min, double vs_max);
+
+/* The step of Eq. 2 assembled as sparse rows (velocity phase, then stress
+ * phase) for staggered differences of order 2 or 4 in space, the adjoint as
+ * the transpose of the assembled rows.  order 2 is the scheme of
+ * orc_forward/orc_gradient written another way (a cross-check of either);
+ * order 4 uses D f = [9/8 (f(+1/2) - f(-1/2)) - 1/24 (f(+3/2) - f(-3/2))] / h
+ * and I f = 9/16 (f(+1/2) + f(-1/2)) - 1/16 (f(+3/2) + f(-3/2)) for every
+ * difference and 1/r average, with the fields mirrored across the axis (even
+ * at half radial positions, odd and zero on the axis at integer ones).
+ * Same arguments and outputs as orc_forward, orc_propagate(_adjoint) and
+ * orc_gradient (no density or pseudo-Hessian outputs).  Pinned: order 2
+ * against the hand-written step, order 4 by closed forms, convergence, dot
+ * products and central differences. */
+int orc_forward_asm(const orc_geom *g, int32_t order, const double *lam, const double *mu,
+                    const double *rho, const double *wavelet, double *traces,
+                    double *final_state);
+int orc_propagate_asm(const orc_geom *g, int32_t order, const double *lam, const double *mu,
+                      const double *rho, double *st, int32_t nsteps, int32_t adjoint);
+int orc_gradient_asm(const orc_geom *g, int32_t order, const double *lam, const double *mu,
+                     const double *rho, const double *wavelet, const double *resid,
+                     int32_t seg, double *glam, double *gmu, double *illum);
+
 #endif
