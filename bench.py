@@ -254,6 +254,9 @@ def main():
     ap.add_argument("--line-search", type=int, default=-1,
                     help="1: parabolic line search each iteration (one extra forward); "
                          "-1: as the workload specifies (the 128-shot workload uses it)")
+    ap.add_argument("--order", type=int, default=2, choices=(2, 4),
+                    help="spatial order of the step (4: the four-point stencils, one step "
+                         "per launch)")
     ap.add_argument("--density", action="store_true",
                     help="joint inversion: the density gradient and step as well (an "
                          "extension; the paper keeps the density fixed)")
@@ -297,7 +300,7 @@ def main():
     rho = f32(w.rho)
     surveys, wavs = [], []
     for g, K in zip(pl.groups, pl.ckpt_every):
-        sv = P.Survey([w.shots[s] for s in g], (w.NRg, w.NZg), ckpt_every=K)
+        sv = P.Survey([w.shots[s] for s in g], (w.NRg, w.NZg), ckpt_every=K, order=args.order)
         surveys.append(sv)
         wavs.append(sv.pack_wavelets([w.shots[s].wavelet for s in g]))
     lam_t, mu_t = P.moduli(f32(w.vp_true), f32(w.vs_true), rho)
@@ -452,7 +455,8 @@ def main():
     # (sub-)tiles in the kernel that carries the PML memories
     kshapes = sv.kernel_shapes()
     xm = (1 if args.density else 0) | (2 if args.precond == "pseudo_hessian" else 0)
-    kname = ("k_adj_tb<%d, %d, %d, 0, %d> + k_adj_tb<%d, %d, %d, 1, %d>" % (
+    kname = ("k_adj4_drivers + k_adj4_velocity + k_adj4_stress" if args.order == 4
+             else "k_adj_tb<%d, %d, %d, 0, %d> + k_adj_tb<%d, %d, %d, 1, %d>" % (
              kshapes["adj"] + (xm,) + kshapes["adj_pml"] + (xm,))
              if kshapes["adj"][0] >= 2
              else "k_adj_step<%d>" % (tune["rows_per_wave"] if tune["rows_per_wave"] <= 4 else 0))
@@ -493,7 +497,7 @@ def main():
         for s_ in range(min(args.plain_shots, len(w.shots))):
             sh = w.shots[s_]
             g_ = [i for i, g in enumerate(pl.groups) if s_ in g][0]
-            sv1 = P.Survey([sh], (w.NRg, w.NZg), ckpt_every=pl.ckpt_every[g_])
+            sv1 = P.Survey([sh], (w.NRg, w.NZg), ckpt_every=pl.ckpt_every[g_], order=args.order)
             sv1.set_tune(rows_per_wave=2, tb_steps=0, adj_tb_steps=0, use_graph=0)
             wav1 = sv1.pack_wavelets([sh.wavelet])
             off = sum(len(w.shots[q].rec_k) * w.shots[q].nt for q in pl.groups[g_] if q < s_)
@@ -539,6 +543,7 @@ def main():
                        pl.ckpt_every)),
                    "cell_steps_per_iteration": int(z.cell_steps),
                    "line_search": line_search,
+                   "order": args.order,
                    "density": bool(args.density), "precond": args.precond,
                    "taper": args.taper or None,
                    "kernel_shapes": kshapes,

@@ -168,6 +168,19 @@ void bhfwi_destroy(bhfwi_ctx *ctx);
  * bhfwi_create on this thread. */
 const char *bhfwi_last_error(const bhfwi_ctx *ctx);
 int bhfwi_sizes(const bhfwi_ctx *ctx, bhfwi_sizes_t *out);
+/* Spatial order of the step, 2 (default) or 4.  The paper names its
+ * finite-difference scheme only by citation; order 4 replaces every staggered
+ * difference and two-point 1/r average by its four-point form,
+ * D f = [9/8 (f(+1/2) - f(-1/2)) - 1/24 (f(+3/2) - f(-3/2))] / h and
+ * I f = 9/16 (f(+1/2) + f(-1/2)) - 1/16 (f(+3/2) + f(-3/2)), with the fields
+ * mirrored across the axis (even at half radial positions, odd at integer
+ * ones).  Applies to bhfwi_fwd_model and bhfwi_adjoint_model (modulus
+ * gradients only: no density or pseudo-Hessian outputs, no autotune; one
+ * step per launch).  Order 4 needs the stricter stability bound
+ * vmax dt sqrt(1/dr^2 + 1/dz^2) < 6/7 (BHFWI_ECFL otherwise) and
+ * N_SCR = 11 more planes of cells floats in adj_ws: query bhfwi_sizes after
+ * this call.  Synchronises the device. */
+int bhfwi_set_order(bhfwi_ctx *ctx, int32_t order);
 int bhfwi_set_tune(bhfwi_ctx *ctx, const bhfwi_tune *tune);
 int bhfwi_get_tune(const bhfwi_ctx *ctx, bhfwi_tune *out);
 /* Autotuner: times, on this survey, every forward kernel shape (one-step wave

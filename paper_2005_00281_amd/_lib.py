@@ -82,7 +82,7 @@ EXPORTS = ["bhfwi_create", "bhfwi_destroy", "bhfwi_last_error", "bhfwi_sizes",
            "bhfwi_plan", "bhfwi_kernel_shapes", "bhfwi_semblance", "bhfwi_semblance_pick",
            "bhfwi_starting_model", "bhfwi_adjoint_model_density", "bhfwi_gradient_density",
            "bhfwi_adjoint_model_ex", "bhfwi_gradient_hessian", "bhfwi_precondition_diag",
-           "bhfwi_radial_taper", "bhfwi_update_density"]
+           "bhfwi_radial_taper", "bhfwi_update_density", "bhfwi_set_order"]
 
 _lib = None
 
@@ -122,6 +122,7 @@ def load(path: str = LIB_PATH):
     L.bhfwi_gradient_hessian.argtypes = [P, V, P, P, P, I32]
     L.bhfwi_precondition_diag.argtypes = [P, V, I64, I32, P, P, P, F, P, P, I32]
     L.bhfwi_radial_taper.argtypes = [V, I32, F, F, F, P]
+    L.bhfwi_set_order.argtypes = [P, I32]
     L.bhfwi_update_density.argtypes = [P, V, I64, P, P, P, F, F, F, P]
     L.bhfwi_precondition.argtypes = [P, V, I64, P, P, F, P, P, P]
     L.bhfwi_line_search.argtypes = [P, V, P, P, P, P, P]
@@ -307,7 +308,7 @@ class Survey:
     rec_k (int array) and win_k0 (first global row of the shot's window);
     model_shape: (NRg, NZg) of the global model."""
 
-    def __init__(self, shots, model_shape, ckpt_every=250, device=0):
+    def __init__(self, shots, model_shape, ckpt_every=250, device=0, order=2):
         L = load()
         self.model_shape = tuple(int(x) for x in model_shape)
         NRg, NZg = self.model_shape
@@ -324,9 +325,20 @@ class Survey:
         self.device = torch.device("cuda", device)
         self.nshot = len(shots)
         self.shots = list(shots)
+        self.order = 2
         self.sizes = Sizes()
         _check(L.bhfwi_sizes(h, C.byref(self.sizes)), h)
         self._ws = {}
+        if order != 2:
+            self.set_order(order)
+
+    def set_order(self, order):
+        """Spatial order of the step (2 or 4, bhfwi_set_order); refreshes the
+        workspace sizes."""
+        _check(load().bhfwi_set_order(self._h, int(order)), self._h)
+        self.order = int(order)
+        _check(load().bhfwi_sizes(self._h, C.byref(self.sizes)), self._h)
+        self._ws.clear()
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -378,8 +390,11 @@ class Survey:
 
     def autotune(self, lam, mu, rho, wavelet, probe_steps=None, cache=None):
         """Pick the fastest kernel shape for this survey (bhfwi_autotune) and
-        install it; with cache (a JSON path) reuse and record the choice."""
+        install it; with cache (a JSON path) reuse and record the choice.  The
+        fourth-order kernels have no shapes to tune: the current tune is kept."""
         import json
+        if self.order != 2:
+            return {"tune": self.get_tune(), "ms": None, "cached": False}
         key = self.shape_key()
         table = {}
         if cache and os.path.exists(cache):

@@ -4,6 +4,7 @@
 #include "bhfwi_kernels.hip"
 #include "bhfwi_tb_fwd.hip"
 #include "bhfwi_tb_adj.hip"
+#include "bhfwi_o4.hip"
 
 #include <algorithm>
 #include <cmath>
@@ -115,6 +116,7 @@ struct bhfwi_ctx {
     std::vector<ShotDev> sd;
     int64_t cells = 0, fst_len = 0, ast_len = 0, trace_len = 0, wave_len = 0, cell_steps = 0;
     int nt_max = 0, nseg = 0;
+    int order = 2;  // spatial order of the step: 2 or 4 (bhfwi_set_order)
     bhfwi_tune tune{};
     std::vector<int4> work;
     std::vector<int> work_nt;  // nt of each work item's shot, non-increasing
@@ -406,6 +408,38 @@ void adj_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const flo
                    (long long)c->cells);
 }
 
+// Fourth-order step n: velocities, then stresses (one thread per cell).
+void fwd4_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const float* mu,
+                 const float* rho, const float* wav, const float* in, float* out, float* traces,
+                 float* hist)
+{
+    const long long ncell = c->cells;
+    const dim3 grid((unsigned)((ncell + 255) / 256));
+    EvScope ev(c, st, hist ? 1 : 0);
+    hipLaunchKernelGGL(bhfwi::o4::k_fwd4_vel, grid, dim3(256), 0, st, c->d_shots, c->nshot, ncell,
+                       n, rho, c->d_pml_r, c->d_pml_z, in, out, hist, (long long)c->cells);
+    hipLaunchKernelGGL(bhfwi::o4::k_fwd4_str, grid, dim3(256), 0, st, c->d_shots, c->nshot, ncell,
+                       n, lam, mu, wav, c->d_rec, c->d_pml_r, c->d_pml_z, in, out, traces);
+}
+
+// Fourth-order adjoint step n: drivers and correlation, adjoint velocities,
+// adjoint stresses; scr holds N_SCR planes of cells floats.
+void adj4_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const float* mu,
+                 const float* rho, const float* resid, const float* in, float* out,
+                 const float* hist, float* acc, float* scr)
+{
+    const long long ncell = c->cells;
+    const dim3 grid((unsigned)((ncell + 255) / 256));
+    EvScope ev(c, st, 2);
+    hipLaunchKernelGGL(bhfwi::o4::k_adj4_drivers, grid, dim3(256), 0, st, c->d_shots, c->nshot,
+                       ncell, n, lam, mu, c->d_rec, resid, c->d_pml_r, c->d_pml_z, in, out, hist,
+                       scr, acc, (long long)c->cells);
+    hipLaunchKernelGGL(bhfwi::o4::k_adj4_velocity, grid, dim3(256), 0, st, c->d_shots, c->nshot,
+                       ncell, n, rho, c->d_pml_r, c->d_pml_z, in, out, scr, (long long)c->cells);
+    hipLaunchKernelGGL(bhfwi::o4::k_adj4_stress, grid, dim3(256), 0, st, c->d_shots, c->nshot,
+                       ncell, n, out, (const float*)scr, (long long)c->cells);
+}
+
 // Supported temporally blocked shapes: (steps T, tile rows incl. halo,
 // waves).  *_PML lists the shapes whose kernel carries the PML memories (all
 // tiles may use them); *_INT adds shapes compiled only without them, for
@@ -591,9 +625,15 @@ void adj_tb_launch(bhfwi_ctx* c, hipStream_t st, int n_hi, int nsteps, const flo
 // ab[(*m + 1) & 1]; hist holds v of step n at slot n - n0.
 void adj_range(bhfwi_ctx* c, hipStream_t st, int n0, int n1, const float* lam, const float* mu,
                const float* rho, const float* resid, float* const ab[2], int* m,
-               const float* hist, float* acc, float* acc_rho, float* acc_h)
+               const float* hist, float* acc, float* acc_rho, float* acc_h, float* scr = nullptr)
 {
     const int64_t hslot = 2 * c->cells;
+    if (c->order == 4) {
+        for (int n = n1 - 1; n >= n0; --n, ++*m)
+            adj4_launch(c, st, n, lam, mu, rho, resid, ab[*m & 1], ab[(*m + 1) & 1],
+                        hist + (int64_t)(n - n0) * hslot, acc, scr);
+        return;
+    }
     const Shape sh = adj_shape(c);
     if (sh.T >= 2) {
         for (int n = n1 - 1; n >= n0;) {
@@ -618,6 +658,14 @@ void fwd_range(bhfwi_ctx* c, hipStream_t st, int n0, int n1, const float* lam, c
                float* traces, float* hist, int hist_base)
 {
     const int64_t hslot = 2 * c->cells;
+    if (c->order == 4) {
+        for (int n = n0; n < n1; ++n) {
+            float* h = hist ? hist + (int64_t)(n - hist_base) * hslot : nullptr;
+            fwd4_launch(c, st, n, lam, mu, rho, wav, b[*parity], b[*parity ^ 1], traces, h);
+            *parity ^= 1;
+        }
+        return;
+    }
     const int T = std::max(1, fwd_shape(c).T);
     for (int n = n0; n < n1;) {
         const int nb = std::min(T, n1 - n);
@@ -657,6 +705,7 @@ int run_sequence(bhfwi_ctx* c, hipStream_t st, std::vector<uintptr_t> key, F&& r
     key.push_back((uintptr_t)c->tune.adj_tb_rows);
     key.push_back((uintptr_t)c->tune.adj_tb_waves);
     key.push_back((uintptr_t)c->tune.pml_overlap);
+    key.push_back((uintptr_t)c->order);
     for (size_t g = 0; g < c->graphs.size(); ++g)
         if (c->graphs[g].key == key) {
             HIPOK(c, hipGraphLaunch(c->graphs[g].exec, st));
@@ -890,7 +939,8 @@ int bhfwi_sizes(const bhfwi_ctx* c, bhfwi_sizes_t* o)
     o->fwd_ws_bytes = 2 * c->fst_len * (int64_t)sizeof(float);
     o->ckpt_bytes = (int64_t)std::max(0, c->nseg - 1) * c->fst_len * (int64_t)sizeof(float);
     o->adj_ws_bytes =
-        (2 * c->ast_len + 2 * (int64_t)c->ckpt_every * c->cells) * (int64_t)sizeof(float);
+        (2 * c->ast_len + 2 * (int64_t)c->ckpt_every * c->cells +
+         (c->order == 4 ? (int64_t)bhfwi::o4::N_SCR * c->cells : 0)) * (int64_t)sizeof(float);
     o->acc_elems = 4 * c->cells;
     o->trace_elems = c->trace_len;
     o->wavelet_elems = c->wave_len;
@@ -1009,6 +1059,26 @@ int bhfwi_set_tune(bhfwi_ctx* c, const bhfwi_tune* t)
     return upload_work(c);
 }
 
+int bhfwi_set_order(bhfwi_ctx* c, int32_t order)
+{
+    if (int rc = check_ctx(c)) return rc;
+    if (order != 2 && order != 4) return fail(c, BHFWI_EINVAL, "order %d: 2 or 4", order);
+    // the four-point stencils lower the stability limit by 1/(|C1| + |C2|) = 6/7
+    const double lim = order == 4 ? 6.0 / 7.0 : 1.0;
+    for (int s = 0; s < c->nshot; ++s) {
+        const bhfwi_shot& h = c->shots[s];
+        const double cfl = (double)h.pml_vmax * h.dt *
+                           std::sqrt(1.0 / ((double)h.dr * h.dr) + 1.0 / ((double)h.dz * h.dz));
+        if (!(cfl < lim))
+            return fail(c, BHFWI_ECFL, "shot %d: vmax dt sqrt(1/dr^2+1/dz^2) = %.4f >= %.4f for "
+                                       "order %d", s, cfl, lim, order);
+    }
+    HIPOK(c, hipDeviceSynchronize());
+    clear_graphs(c);
+    c->order = order;
+    return BHFWI_OK;
+}
+
 int bhfwi_kernel_shapes(const bhfwi_ctx* c, int32_t* out)
 {
     if (!c || !out) return BHFWI_EINVAL;
@@ -1027,6 +1097,8 @@ int bhfwi_autotune(bhfwi_ctx* c, void* stream, const float* lam, const float* mu
                    int32_t probe_steps, bhfwi_tune* best, float* best_ms)
 {
     if (int rc = check_ctx(c)) return rc;
+    if (c->order != 2)
+        return fail(c, BHFWI_EINVAL, "autotune: the fourth-order kernels have no tunable shapes");
     bhfwi_sizes_t z;
     bhfwi_sizes(c, &z);
     if (!lam || !mu || !rho || !wavelet || !traces || !fwd_ws || !adj_ws || !acc || !best)
@@ -1299,6 +1371,9 @@ int adjoint_impl(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
     bhfwi_sizes(c, &z);
     if (!lam || !mu || !rho || !wavelet || !resid || !fwd_ws || !adj_ws || !acc)
         return fail(c, BHFWI_EINVAL, "adjoint_model: null pointer");
+    if (c->order == 4 && (acc_rho || acc_h))
+        return fail(c, BHFWI_EINVAL, "adjoint_model: the fourth-order kernels give the modulus "
+                                     "gradients only");
     if (fwd_ws_bytes < z.fwd_ws_bytes || adj_ws_bytes < z.adj_ws_bytes)
         return fail(c, BHFWI_ENOMEM, "adjoint_model: workspace too small (fwd %lld/%lld, adj %lld/%lld)",
                     (long long)fwd_ws_bytes, (long long)z.fwd_ws_bytes, (long long)adj_ws_bytes,
@@ -1310,6 +1385,7 @@ int adjoint_impl(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
     float* fb[2] = {(float*)fwd_ws, (float*)fwd_ws + c->fst_len};
     float* ab[2] = {(float*)adj_ws, (float*)adj_ws + c->ast_len};
     float* hist = (float*)adj_ws + 2 * c->ast_len;
+    float* scr = hist + 2 * (int64_t)c->ckpt_every * c->cells;  // fourth order only
     const int64_t hslot = 2 * c->cells;
     const int K = c->ckpt_every;
     float* const fbc[2] = {fb[0], fb[1]};
@@ -1329,7 +1405,7 @@ int adjoint_impl(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
                                      sizeof(float) * c->fst_len, hipMemcpyDeviceToDevice, s);
             int parity = 0;
             fwd_range(c, s, n0, n1, lam, mu, rho, wavelet, fbc, &parity, nullptr, hist, n0);
-            adj_range(c, s, n0, n1, lam, mu, rho, resid, ab, &m, hist, acc, acc_rho, acc_h);
+            adj_range(c, s, n0, n1, lam, mu, rho, resid, ab, &m, hist, acc, acc_rho, acc_h, scr);
         }
     };
     return run_sequence(c, st,

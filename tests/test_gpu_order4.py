@@ -1,0 +1,164 @@
+"""Parity of the fourth-order HIP kernels (bhfwi_set_order(4)) with the
+oracle's assembled fourth-order operators.
+
+Tolerances as for the second-order path: traces relative L2 <= 1e-4,
+gradients <= 1e-3 (all cells and the interior; PML cells alone <= 1e-2),
+illumination <= 1e-4; exact equality where the same FP32 arithmetic is
+repeated (batched vs single shot).
+"""
+import copy
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from util import geom, oracle_models, rel_l2
+from test_gpu_parity import T, _dev, _multi_shot_workload, _regions, _say, f32, gpu_models
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def survey4(w, ckpt=250, graph=1):
+    import paper_2005_00281_amd as P
+    sv = P.Survey(w.shots, (w.NRg, w.NZg), ckpt_every=ckpt, order=4)
+    sv.set_tune(use_graph=graph)
+    return sv
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_order4_forward_parity_tiny_ragged(graph):
+    w = workloads.tiny(nr=40, nz=150, p=6, nt=300)
+    sh = w.shots[0]
+    _say("order 4 fwd tiny", sh.NR, sh.NZ, "graph", graph)
+    lam_o, mu_o, rho_o = oracle_models(w, 0, "start")
+    d_o = oracle.forward(geom(sh), lam_o, mu_o, rho_o, sh.wavelet, order=4)
+    sv = survey4(w, graph=graph)
+    lam, mu, rho = gpu_models(w)
+    tr = sv.fwd_model(lam, mu, rho, sv.pack_wavelets([sh.wavelet]))
+    torch.cuda.synchronize()
+    d_g = sv.unpack_traces(tr)[0]
+    assert rel_l2(d_g, d_o) <= 1e-4, rel_l2(d_g, d_o)
+    # and it is not the second-order result
+    d2 = oracle.forward(geom(sh), lam_o, mu_o, rho_o, sh.wavelet)
+    assert rel_l2(d_g, d2) > 1e-2
+
+
+@pytest.mark.parametrize("ckpt,graph", [(37, 1), (300, 0)])
+def test_order4_gradient_parity_tiny(ckpt, graph):
+    w = workloads.tiny(nr=40, nz=150, p=6, nt=300)
+    sh = w.shots[0]
+    _say("order 4 grad tiny", ckpt, graph)
+    lam_o, mu_o, rho_o = oracle_models(w, 0, "start")
+    lt, mt, _ = oracle_models(w, 0, "true")
+    d_obs = oracle.forward(geom(sh), lt, mt, rho_o, sh.wavelet, order=4)
+    d_o = oracle.forward(geom(sh), lam_o, mu_o, rho_o, sh.wavelet, order=4)
+    _, r = oracle.misfit(d_o, d_obs)
+    gl_o, gm_o, il_o = oracle.gradient(geom(sh), lam_o, mu_o, rho_o, sh.wavelet, r, seg=50,
+                                       order=4)
+    sv = survey4(w, ckpt=ckpt, graph=graph)
+    lam, mu, rho = gpu_models(w)
+    wav = sv.pack_wavelets([sh.wavelet])
+    sv.fwd_model(lam, mu, rho, wav, store_ckpt=True)
+    acc = sv.adjoint_model(lam, mu, rho, wav, f32(r.ravel()))
+    gl, gm, il = (t.cpu().numpy() for t in sv.gradient(mu, acc))
+    reg = _regions(sh, gl.shape)
+    errs = {k: (rel_l2(gl[m], gl_o[m]), rel_l2(gm[m], gm_o[m])) for k, m in reg.items()}
+    print("[case] rel-L2 (g_lam, g_mu) by region:", errs, "illum", rel_l2(il, il_o))
+    assert errs["all"][0] <= 1e-3 and errs["all"][1] <= 1e-3
+    assert errs["interior"][0] <= 1e-3 and errs["interior"][1] <= 1e-3
+    for k in ("pml_r", "pml_z"):
+        assert errs[k][0] <= 1e-2 and errs[k][1] <= 1e-2, (k, errs[k])
+    assert rel_l2(il, il_o) <= 1e-4
+
+
+def test_order4_single_shot_128x512():
+    """The 128 x 512 workload (4000 steps, 10 kHz, water-filled hole): every
+    trace and the formation gradient."""
+    w = workloads.make("c1")
+    sh = w.shots[0]
+    _say("order 4 c1", sh.NR, sh.NZ, sh.nt)
+    lam_o, mu_o, rho_o = oracle_models(w, 0, "start")
+    lt, mt, _ = oracle_models(w, 0, "true")
+    d_obs = oracle.forward(geom(sh), lt, mt, rho_o, sh.wavelet, order=4)
+    d_o = oracle.forward(geom(sh), lam_o, mu_o, rho_o, sh.wavelet, order=4)
+    _, r = oracle.misfit(d_o, d_obs)
+    gl_o, gm_o, _ = oracle.gradient(geom(sh), lam_o, mu_o, rho_o, sh.wavelet, r, seg=200,
+                                    order=4)
+    sv = survey4(w)
+    lam, mu, rho = gpu_models(w)
+    wav = sv.pack_wavelets([sh.wavelet])
+    tr = sv.fwd_model(lam, mu, rho, wav, store_ckpt=True)
+    d_g = sv.unpack_traces(tr)[0]
+    for j in range(d_o.shape[0]):
+        assert rel_l2(d_g[j], d_o[j]) <= 1e-4, (j, rel_l2(d_g[j], d_o[j]))
+    acc = sv.adjoint_model(lam, mu, rho, wav, f32(r.ravel()))
+    gl, gm, _ = (t.cpu().numpy() for t in sv.gradient(mu, acc))
+    form = w.mask.astype(bool)
+    assert rel_l2(gl[form], gl_o[form]) <= 1e-3 and rel_l2(gm[form], gm_o[form]) <= 1e-3
+
+
+def test_order4_batched_equals_single_shots():
+    """Three shots over one global model with ragged nt and receiver counts:
+    the batched fourth-order traces and gradient are the single-shot ones bit
+    for bit (gradient: their shot-order sum)."""
+    w = _multi_shot_workload()
+    _say("order 4 batched", [(s.NR, s.NZ, s.nt) for s in w.shots])
+    lam, mu, rho = gpu_models(w)
+    sv = survey4(w, ckpt=50)
+    wav = sv.pack_wavelets([s.wavelet for s in w.shots])
+    tr = sv.fwd_model(lam, mu, rho, wav, store_ckpt=True)
+    torch.manual_seed(0)
+    r = torch.randn(sv.sizes.trace_elems, device=_dev())
+    g_b = [t.cpu().numpy() for t in sv.gradient(mu, sv.adjoint_model(lam, mu, rho, wav, r))]
+    tr_b = sv.unpack_traces(tr)
+    r_np = r.cpu().numpy()
+    sums = [np.zeros((w.NRg, w.NZg), np.float32) for _ in range(3)]
+    for s, (off, nrec, nt) in enumerate(sv.trace_slices()):
+        w1 = copy.copy(w)
+        w1.shots = [w.shots[s]]
+        sv1 = survey4(w1, ckpt=50)
+        wav1 = sv1.pack_wavelets([w.shots[s].wavelet])
+        tr1 = sv1.fwd_model(lam, mu, rho, wav1, store_ckpt=True)
+        assert np.array_equal(sv1.unpack_traces(tr1)[0], tr_b[s])
+        acc1 = sv1.adjoint_model(lam, mu, rho, wav1, f32(r_np[off: off + nrec * nt]))
+        for q, t in enumerate(sv1.gradient(mu, acc1)):
+            sums[q] += t.cpu().numpy()
+        lo, mo, ro = oracle_models(w, s, "start")
+        d_o = oracle.forward(geom(w.shots[s]), lo, mo, ro, w.shots[s].wavelet, order=4)
+        assert rel_l2(tr_b[s], d_o) <= 1e-4
+    for q in range(3):
+        assert np.array_equal(sums[q], g_b[q]), q
+
+
+def test_order4_rules():
+    """Order 3 is rejected, a time step within the second-order bound but not
+    the fourth-order one is rejected, the adjoint workspace grows by eleven
+    planes, and the extra adjoint outputs are refused at order 4."""
+    import paper_2005_00281_amd as P
+    from paper_2005_00281_amd._lib import BhfwiError
+    w = workloads.tiny(nr=20, nz=60, p=4, nt=50)
+    _say("order 4 rules")
+    sv = P.Survey(w.shots, (w.NRg, w.NZg), ckpt_every=25)
+    a2 = sv.sizes.adj_ws_bytes
+    with pytest.raises(BhfwiError):
+        sv.set_order(3)
+    sv.set_order(4)
+    assert sv.sizes.adj_ws_bytes == a2 + 11 * 4 * sv.sizes.cells
+    lam, mu, rho = gpu_models(w)
+    wav = sv.pack_wavelets([w.shots[0].wavelet])
+    sv.fwd_model(lam, mu, rho, wav, store_ckpt=True)
+    r = torch.zeros(sv.sizes.trace_elems, device=_dev())
+    with pytest.raises(BhfwiError):
+        sv.adjoint_model_ex(lam, mu, rho, wav, r, density=True)
+    sv.set_order(2)
+    assert sv.sizes.adj_ws_bytes == a2
+    w2 = copy.deepcopy(w)
+    sh = w2.shots[0]
+    # Courant 0.9 of the second-order limit: fine for order 2, not for order 4
+    sh.dt = 0.9 / (sh.vmax * np.sqrt(1 / sh.dr ** 2 + 1 / sh.dz ** 2))
+    sv2 = P.Survey(w2.shots, (w2.NRg, w2.NZg), ckpt_every=25)
+    with pytest.raises(BhfwiError):
+        sv2.set_order(4)
