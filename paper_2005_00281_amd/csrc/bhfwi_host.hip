@@ -117,6 +117,8 @@ struct bhfwi_ctx {
     int64_t cells = 0, fst_len = 0, ast_len = 0, trace_len = 0, wave_len = 0, cell_steps = 0;
     int nt_max = 0, nseg = 0;
     int order = 2;  // spatial order of the step: 2 or 4 (bhfwi_set_order)
+    int* d_tile4 = nullptr;  // fourth order: first tile of each shot (nshot + 1)
+    int ntile4 = 0;
     bhfwi_tune tune{};
     std::vector<int4> work;
     std::vector<int> work_nt;  // nt of each work item's shot, non-increasing
@@ -413,13 +415,14 @@ void fwd4_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const fl
                  const float* rho, const float* wav, const float* in, float* out, float* traces,
                  float* hist)
 {
-    const long long ncell = c->cells;
-    const dim3 grid((unsigned)((ncell + 255) / 256));
+    const dim3 grid((unsigned)c->ntile4), block(bhfwi::o4::TK * bhfwi::o4::TI);
     EvScope ev(c, st, hist ? 1 : 0);
-    hipLaunchKernelGGL(bhfwi::o4::k_fwd4_vel, grid, dim3(256), 0, st, c->d_shots, c->nshot, ncell,
-                       n, rho, c->d_pml_r, c->d_pml_z, in, out, hist, (long long)c->cells);
-    hipLaunchKernelGGL(bhfwi::o4::k_fwd4_str, grid, dim3(256), 0, st, c->d_shots, c->nshot, ncell,
-                       n, lam, mu, wav, c->d_rec, c->d_pml_r, c->d_pml_z, in, out, traces);
+    hipLaunchKernelGGL(bhfwi::o4::k_fwd4_vel, grid, block, 0, st, c->d_shots, c->d_tile4,
+                       c->nshot, n, rho, c->d_pml_r, c->d_pml_z, in, out, hist,
+                       (long long)c->cells);
+    hipLaunchKernelGGL(bhfwi::o4::k_fwd4_str, grid, block, 0, st, c->d_shots, c->d_tile4,
+                       c->nshot, n, lam, mu, wav, c->d_rec, c->d_pml_r, c->d_pml_z, in, out,
+                       traces);
 }
 
 // Fourth-order adjoint step n: drivers and correlation, adjoint velocities,
@@ -428,16 +431,17 @@ void adj4_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const fl
                  const float* rho, const float* resid, const float* in, float* out,
                  const float* hist, float* acc, float* scr)
 {
-    const long long ncell = c->cells;
-    const dim3 grid((unsigned)((ncell + 255) / 256));
+    const dim3 grid((unsigned)c->ntile4), block(bhfwi::o4::TK * bhfwi::o4::TI);
     EvScope ev(c, st, 2);
-    hipLaunchKernelGGL(bhfwi::o4::k_adj4_drivers, grid, dim3(256), 0, st, c->d_shots, c->nshot,
-                       ncell, n, lam, mu, c->d_rec, resid, c->d_pml_r, c->d_pml_z, in, out, hist,
-                       scr, acc, (long long)c->cells);
-    hipLaunchKernelGGL(bhfwi::o4::k_adj4_velocity, grid, dim3(256), 0, st, c->d_shots, c->nshot,
-                       ncell, n, rho, c->d_pml_r, c->d_pml_z, in, out, scr, (long long)c->cells);
-    hipLaunchKernelGGL(bhfwi::o4::k_adj4_stress, grid, dim3(256), 0, st, c->d_shots, c->nshot,
-                       ncell, n, out, (const float*)scr, (long long)c->cells);
+    hipLaunchKernelGGL(bhfwi::o4::k_adj4_drivers, grid, block, 0, st, c->d_shots, c->d_tile4,
+                       c->nshot, n, lam, mu, c->d_rec, resid, c->d_pml_r, c->d_pml_z, in, out,
+                       hist, scr, acc, (long long)c->cells);
+    hipLaunchKernelGGL(bhfwi::o4::k_adj4_velocity, grid, block, 0, st, c->d_shots, c->d_tile4,
+                       c->nshot, n, rho, c->d_pml_r, c->d_pml_z, in, out, scr,
+                       (long long)c->cells);
+    hipLaunchKernelGGL(bhfwi::o4::k_adj4_stress, grid, block, 0, st, c->d_shots, c->d_tile4,
+                       c->nshot, n, c->d_pml_r, c->d_pml_z, out, (const float*)scr,
+                       (long long)c->cells);
 }
 
 // Supported temporally blocked shapes: (steps T, tile rows incl. halo,
@@ -919,6 +923,7 @@ void bhfwi_destroy(bhfwi_ctx* c)
     if (c->d_pml_r) (void)hipFree(c->d_pml_r);
     if (c->d_pml_z) (void)hipFree(c->d_pml_z);
     if (c->d_work) (void)hipFree(c->d_work);
+    if (c->d_tile4) (void)hipFree(c->d_tile4);
     for (int q = 0; q < 2; ++q) {
         if (c->ftiles.d[q]) (void)hipFree(c->ftiles.d[q]);
         if (c->atiles.d[q]) (void)hipFree(c->atiles.d[q]);
@@ -1075,6 +1080,19 @@ int bhfwi_set_order(bhfwi_ctx* c, int32_t order)
     }
     HIPOK(c, hipDeviceSynchronize());
     clear_graphs(c);
+    if (order == 4 && !c->d_tile4) {
+        // tiles of TI radial x TK axial cells, shot by shot
+        std::vector<int> start(c->nshot + 1, 0);
+        for (int s = 0; s < c->nshot; ++s) {
+            const bhfwi::ShotDev& S = c->sd[s];
+            start[s + 1] = start[s] + ((S.NR + bhfwi::o4::TI - 1) / bhfwi::o4::TI) *
+                                          ((S.NZ + bhfwi::o4::TK - 1) / bhfwi::o4::TK);
+        }
+        HIPOK(c, hipMalloc(&c->d_tile4, sizeof(int) * (c->nshot + 1)));
+        HIPOK(c, hipMemcpy(c->d_tile4, start.data(), sizeof(int) * (c->nshot + 1),
+                           hipMemcpyHostToDevice));
+        c->ntile4 = start[c->nshot];
+    }
     c->order = order;
     return BHFWI_OK;
 }
