@@ -229,6 +229,9 @@ def main():
     ap.add_argument("--adj-tb", type=int, default=-1,
                     help="adjoint steps per launch (0: as the forward, 1: one per launch)")
     ap.add_argument("--pml-overlap", type=int, default=-1)
+    ap.add_argument("--rec-overlap", type=int, default=-1,
+                    help="1: recompute segment j-1 on a second stream during the adjoint of "
+                         "segment j (default: the tune's)")
     ap.add_argument("--adj-tb-rows", type=int, default=0)
     ap.add_argument("--adj-tb-waves", type=int, default=0)
     ap.add_argument("--no-graph", action="store_true")
@@ -322,14 +325,6 @@ def main():
     if args.taper:
         r0, r1 = (float(x) for x in args.taper.split(","))
         row_weight = P.radial_taper(w.NRg, w.shots[0].dr, r0, r1)
-    inv = Inversion(surveys, f32(w.vp_start), f32(w.vs_start), rho, wavs, observed, mask,
-                    line_search=line_search, density=args.density, precond=args.precond,
-                    row_weight=row_weight)
-    if args.progress:
-        def _progress(stage, g):
-            torch.cuda.synchronize()
-            log("%s: group %d of %d done" % (stage, g + 1, len(surveys)))
-        inv.after_group = _progress
     if args.tb >= 0 or args.adj_tb >= 0 or args.rows or args.no_autotune:
         for sv in surveys:
             sv.set_tune(rows_per_wave=args.rows or None,
@@ -366,6 +361,18 @@ def main():
         log("autotune %.1f s -> %s%s" % (time.perf_counter() - t_at, entry["tune"],
                                           " (tune cache)" if entry.get("cached") else ""))
         del lam_s, mu_s
+    if args.rec_overlap >= 0:
+        for sv in surveys:
+            sv.set_tune(rec_overlap=args.rec_overlap)
+    # the shared workspaces of the iteration are sized for the tune in force
+    inv = Inversion(surveys, f32(w.vp_start), f32(w.vs_start), rho, wavs, observed, mask,
+                    line_search=line_search, density=args.density, precond=args.precond,
+                    row_weight=row_weight)
+    if args.progress:
+        def _progress(stage, g):
+            torch.cuda.synchronize()
+            log("%s: group %d of %d done" % (stage, g + 1, len(surveys)))
+        inv.after_group = _progress
     if args.sweep:
         keep = surveys[0].get_tune()
         a0 = adj_shape(keep)

@@ -125,6 +125,13 @@ typedef struct {
                                  stream alongside the interior tiles (forked and
                                  joined around the block); 0 (default): after
                                  them on the caller's stream */
+    int32_t rec_overlap;      /* 1: bhfwi_adjoint_model recomputes checkpoint
+                                 segment j-1 on a second stream while the adjoint
+                                 of segment j runs (two velocity histories:
+                                 adj_ws_bytes grows by 8 ckpt_every cells bytes;
+                                 query bhfwi_sizes after setting it); the results
+                                 are bit-identical to 0 (default).  Not combined
+                                 with pml_overlap. */
 } bhfwi_tune;
 
 /* Memory of one group of shots evaluated together (bhfwi_plan_bytes). */

@@ -49,7 +49,7 @@ class Tune(C.Structure):
                 ("tb_steps", C.c_int32), ("tb_rows", C.c_int32), ("tb_waves", C.c_int32),
                 ("tile_map", C.c_int32), ("adj_tb_steps", C.c_int32),
                 ("adj_tb_rows", C.c_int32), ("adj_tb_waves", C.c_int32),
-                ("pml_overlap", C.c_int32)]
+                ("pml_overlap", C.c_int32), ("rec_overlap", C.c_int32)]
 
 
 class PlanBytes(C.Structure):

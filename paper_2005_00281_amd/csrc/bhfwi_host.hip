@@ -132,6 +132,9 @@ struct bhfwi_ctx {
     int* d_status = nullptr;  // device word raised by kernels that see non-finite sums
     hipStream_t cap_stream = nullptr;  // private stream that graphs are captured on
     hipStream_t pml_stream = nullptr;  // second stream for the PML tiles of a block
+    hipStream_t rec_stream = nullptr;  // recompute stream of the overlapped adjoint
+    hipEvent_t ev_rec_start = nullptr, ev_rec[2] = {nullptr, nullptr},
+               ev_adj[2] = {nullptr, nullptr};
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     struct Graph {
         std::vector<uintptr_t> key;
@@ -709,6 +712,7 @@ int run_sequence(bhfwi_ctx* c, hipStream_t st, std::vector<uintptr_t> key, F&& r
     key.push_back((uintptr_t)c->tune.adj_tb_rows);
     key.push_back((uintptr_t)c->tune.adj_tb_waves);
     key.push_back((uintptr_t)c->tune.pml_overlap);
+    key.push_back((uintptr_t)c->tune.rec_overlap);
     key.push_back((uintptr_t)c->order);
     for (size_t g = 0; g < c->graphs.size(); ++g)
         if (c->graphs[g].key == key) {
@@ -916,6 +920,12 @@ void bhfwi_destroy(bhfwi_ctx* c)
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->pml_stream) (void)hipStreamDestroy(c->pml_stream);
+    if (c->rec_stream) (void)hipStreamDestroy(c->rec_stream);
+    if (c->ev_rec_start) (void)hipEventDestroy(c->ev_rec_start);
+    for (int q = 0; q < 2; ++q) {
+        if (c->ev_rec[q]) (void)hipEventDestroy(c->ev_rec[q]);
+        if (c->ev_adj[q]) (void)hipEventDestroy(c->ev_adj[q]);
+    }
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->d_shots) (void)hipFree(c->d_shots);
@@ -944,7 +954,7 @@ int bhfwi_sizes(const bhfwi_ctx* c, bhfwi_sizes_t* o)
     o->fwd_ws_bytes = 2 * c->fst_len * (int64_t)sizeof(float);
     o->ckpt_bytes = (int64_t)std::max(0, c->nseg - 1) * c->fst_len * (int64_t)sizeof(float);
     o->adj_ws_bytes =
-        (2 * c->ast_len + 2 * (int64_t)c->ckpt_every * c->cells +
+        (2 * c->ast_len + (c->tune.rec_overlap ? 4 : 2) * (int64_t)c->ckpt_every * c->cells +
          (c->order == 4 ? (int64_t)bhfwi::o4::N_SCR * c->cells : 0)) * (int64_t)sizeof(float);
     o->acc_elems = 4 * c->cells;
     o->trace_elems = c->trace_len;
@@ -1046,7 +1056,8 @@ int bhfwi_set_tune(bhfwi_ctx* c, const bhfwi_tune* t)
     if (!c || !t) return BHFWI_EINVAL;
     if (t->rows_per_wave < 1 || t->use_graph < 0 || t->use_graph > 1 || t->time_kernels < 0 ||
         t->time_kernels > 1 || t->tb_steps < 0 || t->tile_map < 0 || t->tile_map > 1 ||
-        t->pml_overlap < 0 || t->pml_overlap > 1 ||
+        t->pml_overlap < 0 || t->pml_overlap > 1 || t->rec_overlap < 0 || t->rec_overlap > 1 ||
+        (t->rec_overlap && t->pml_overlap) ||
         (t->tb_steps >= 2 && !fwd_supported(t->tb_steps, t->tb_rows, t->tb_waves)) ||
         t->adj_tb_steps < 0 ||
         (t->adj_tb_steps >= 2 && !adj_supported(t->adj_tb_steps, t->adj_tb_rows, t->adj_tb_waves)) ||
@@ -1403,11 +1414,57 @@ int adjoint_impl(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
     float* fb[2] = {(float*)fwd_ws, (float*)fwd_ws + c->fst_len};
     float* ab[2] = {(float*)adj_ws, (float*)adj_ws + c->ast_len};
     float* hist = (float*)adj_ws + 2 * c->ast_len;
-    float* scr = hist + 2 * (int64_t)c->ckpt_every * c->cells;  // fourth order only
+    const int nhist = c->tune.rec_overlap ? 2 : 1;  // velocity histories
+    float* scr = hist + nhist * 2 * (int64_t)c->ckpt_every * c->cells;  // fourth order only
     const int64_t hslot = 2 * c->cells;
     const int K = c->ckpt_every;
     float* const fbc[2] = {fb[0], fb[1]};
+    const bool ovl = c->tune.rec_overlap && c->nseg > 1;
+    if (ovl) {
+        if (!c->rec_stream)
+            HIPOK(c, hipStreamCreateWithFlags(&c->rec_stream, hipStreamNonBlocking));
+        if (!c->ev_rec_start)
+            HIPOK(c, hipEventCreateWithFlags(&c->ev_rec_start, hipEventDisableTiming));
+        for (int q = 0; q < 2; ++q) {
+            if (!c->ev_rec[q]) HIPOK(c, hipEventCreateWithFlags(&c->ev_rec[q], hipEventDisableTiming));
+            if (!c->ev_adj[q]) HIPOK(c, hipEventCreateWithFlags(&c->ev_adj[q], hipEventDisableTiming));
+        }
+    }
+    // Overlapped form: the recompute of segment j (history j & 1) runs on the
+    // recompute stream as soon as the adjoint of segment j + 2, the last
+    // reader of that history, is done; the adjoint of segment j waits for it.
+    auto record_ovl = [&](hipStream_t s) {
+        hipStream_t r = c->rec_stream;
+        launch_fill(s, fb[0], 2 * c->fst_len, 0.0f);
+        launch_fill(s, ab[0], 2 * c->ast_len, 0.0f);
+        launch_fill(s, acc, 4 * c->cells, 0.0f);
+        if (acc_rho) launch_fill(s, acc_rho, 2 * c->cells, 0.0f);
+        if (acc_h) launch_fill(s, acc_h, 2 * c->cells, 0.0f);
+        (void)hipEventRecord(c->ev_rec_start, s);
+        (void)hipStreamWaitEvent(r, c->ev_rec_start, 0);
+        int m = 0;
+        for (int j = c->nseg - 1; j >= 0; --j) {
+            const int n0 = j * K, n1 = std::min(n0 + K, c->nt_max);
+            float* h = hist + (j & 1) * 2 * (int64_t)K * c->cells;
+            if (j + 2 <= c->nseg - 1) (void)hipStreamWaitEvent(r, c->ev_adj[j & 1], 0);
+            if (j == 0)
+                launch_fill(r, fb[0], c->fst_len, 0.0f);
+            else
+                (void)hipMemcpyAsync(fb[0], (const float*)ckpt + (int64_t)(j - 1) * c->fst_len,
+                                     sizeof(float) * c->fst_len, hipMemcpyDeviceToDevice, r);
+            int parity = 0;
+            fwd_range(c, r, n0, n1, lam, mu, rho, wavelet, fbc, &parity, nullptr, h, n0);
+            (void)hipEventRecord(c->ev_rec[j & 1], r);
+            (void)hipStreamWaitEvent(s, c->ev_rec[j & 1], 0);
+            adj_range(c, s, n0, n1, lam, mu, rho, resid, ab, &m, h, acc, acc_rho, acc_h, scr);
+            (void)hipEventRecord(c->ev_adj[j & 1], s);
+        }
+    };
     auto record = [&](hipStream_t s) {
+        if (ovl) {
+            record_ovl(s);
+            return;
+        }
         launch_fill(s, fb[0], 2 * c->fst_len, 0.0f);
         launch_fill(s, ab[0], 2 * c->ast_len, 0.0f);
         launch_fill(s, acc, 4 * c->cells, 0.0f);

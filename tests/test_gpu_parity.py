@@ -48,10 +48,11 @@ def survey(w, ckpt=250, tune=None):
     return sv
 
 
-def T(rows=4, wpb=4, graph=1, tb=0, tbr=16, tbw=4, tmap=1, atb=0, atbr=16, atbw=8, ovl=1):
+def T(rows=4, wpb=4, graph=1, tb=0, tbr=16, tbw=4, tmap=1, atb=0, atbr=16, atbw=8, ovl=1,
+      rov=0):
     return dict(rows_per_wave=rows, waves_per_block=wpb, use_graph=graph, tb_steps=tb,
                 tb_rows=tbr, tb_waves=tbw, tile_map=tmap, adj_tb_steps=atb, adj_tb_rows=atbr,
-                adj_tb_waves=atbw, pml_overlap=ovl)
+                adj_tb_waves=atbw, pml_overlap=0 if rov else ovl, rec_overlap=rov)
 
 
 FWD_TUNES = [T(1, 1, 0), T(2, 4, 1), T(3, 2, 1), T(4, 4, 0), T(16, 4, 1), T(64, 8, 0),
@@ -70,7 +71,9 @@ GRAD_TUNES = [T(1, 1, 1), T(2, 4, 0), T(4, 4, 1), T(5, 4, 1), T(64, 8, 0), T(tb=
               T(tb=4, tbr=64, tbw=16, atb=4, atbr=48, atbw=16, graph=0),
               T(tb=8, tbr=48, tbw=16, atb=8, atbr=48, atbw=16),
               T(tb=8, tbr=48, tbw=16, atb=6, atbr=32, atbw=16, ovl=0),
-              T(tb=8, tbr=48, tbw=16, atb=6, atbr=32, atbw=16, ovl=1, graph=0)]
+              T(tb=8, tbr=48, tbw=16, atb=6, atbr=32, atbw=16, ovl=1, graph=0),
+              T(tb=8, tbr=64, tbw=16, atb=8, atbr=32, atbw=16, rov=1),
+              T(tb=6, tbr=32, tbw=16, rov=1, graph=0), T(2, 4, 1, rov=1)]
 
 
 def oracle_traces(w, s=0, which="start"):
@@ -167,6 +170,34 @@ def test_gradient_parity_single_shot_128x512():
     assert rel_l2(gm[form], gm_o[form]) <= 1e-3, rel_l2(gm[form], gm_o[form])
     assert rel_l2(gl, gl_o) <= 1e-3 and rel_l2(gm, gm_o) <= 1e-3
     assert rel_l2(il, il_o) <= 1e-4
+
+
+@pytest.mark.parametrize("tune", [T(tb=8, tbr=64, tbw=16, atb=8, atbr=32, atbw=16),
+                                  T(tb=4, graph=0), T(4, 4, 1)])
+def test_overlapped_recompute_is_bit_identical(tune):
+    """rec_overlap = 1 recomputes segment j - 1 on a second stream during the
+    adjoint of segment j: the same kernels on the same data, so the gradient
+    equals the sequential one bit for bit (several segments, a ragged last
+    one, a three-shot batch with ragged nt)."""
+    w = _multi_shot_workload()
+    _say("overlapped recompute", tune)
+    lam, mu, rho = gpu_models(w)
+    torch.manual_seed(1)
+    outs = []
+    for rov in (0, 1):
+        sv = survey(w, ckpt=37, tune=dict(tune, rec_overlap=rov, pml_overlap=0))
+        wav = sv.pack_wavelets([s.wavelet for s in w.shots])
+        sv.fwd_model(lam, mu, rho, wav, store_ckpt=True)
+        if rov == 0:
+            r = torch.randn(sv.sizes.trace_elems, device=_dev())
+        acc = sv.adjoint_model(lam, mu, rho, wav, r)
+        outs.append([t.cpu().numpy() for t in sv.gradient(mu, acc)])
+        # a second call replays the same sequence (graph or not)
+        acc = sv.adjoint_model(lam, mu, rho, wav, r)
+        outs.append([t.cpu().numpy() for t in sv.gradient(mu, acc)])
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
 
 
 @pytest.mark.parametrize("tune", [T(4, 4, 1), T(tb=4)])
