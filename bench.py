@@ -403,7 +403,10 @@ def main():
         for x in surveys:
             x.set_tune(**keep)
         for ovl in (0, 1):
-            log("sweep pml_overlap %d: %.2f ms per gradient" % (ovl, timed(pml_overlap=ovl)))
+            # the PML stream and the recompute stream are not combined
+            rov = 0 if ovl else keep["rec_overlap"]
+            log("sweep pml_overlap %d (rec_overlap %d): %.2f ms per gradient" % (
+                ovl, rov, timed(pml_overlap=ovl, rec_overlap=rov)))
         for x in surveys:
             x.set_tune(**keep)
     if args.no_graph:
