@@ -48,8 +48,8 @@ PMC_SOURCES = ("paper_2005_00281_amd/csrc/bhfwi_tb_adj.hip",
 PMC_TRAFFIC = {
     # (kernel, tile_map, workload, sources sha256[:16]): (FETCH KiB, WRITE KiB), summed
     # over the kernels of one launch block
-    ("k_adj_tb<8, 32, 16, 0> + k_adj_tb<8, 32, 16, 1>", 1, "c2", "18dbee857d657428"):
-        (50206.73 + 9997.84, 33649.91 + 5494.22),
+    ("k_adj_tb<8, 48, 16, 0, 0> + k_adj_tb<8, 32, 16, 1, 0>", 1, "c2", "191dde93b7917663"):
+        (42121.50 + 11808.14, 22375.56 + 6724.69),
 }
 
 
