@@ -1,0 +1,82 @@
+"""Parity at the benchmark's full grid (340 x 2088 padded cells, one shot) in
+the launch configuration the benchmark times: the tune-cache entry of that
+workload (forward 8x64x16 with 8x32x16 PML sub-tiles, adjoint 8x48x16,
+recompute overlapped with the adjoint on a second stream, HIP graphs) and its
+checkpoint interval of 250 steps.
+
+The record is cut to 900 steps (four checkpoint segments, the last one
+ragged, so the overlap is exercised) and the source is moved 30 rows above the
+third receiver so that the waves reach four receivers inside it (the Ricker
+wavelet alone is delayed by 1.5/f0 = 500 steps); the oracle then finishes in
+under two minutes.  Tolerances as everywhere: traces relative L2 <= 1e-4, gradients
+<= 1e-3, illumination <= 1e-4.
+"""
+import copy
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from util import geom, oracle_models, rel_l2
+from test_gpu_parity import _say, f32, gpu_models
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+NT = 900
+
+
+def _bench_tune():
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_2005_00281_amd", "tune_cache.json")
+    with open(path) as f:
+        table = json.load(f)
+    key = [k for k in table if k.endswith("|K250|340x2088x8000*1")]
+    assert len(key) == 1, key
+    return table[key[0]]["tune"]
+
+
+def test_full_grid_in_the_benchmark_launch_configuration():
+    import paper_2005_00281_amd as P
+    w = copy.copy(workloads.make("c2"))
+    sh = copy.copy(w.shots[0])
+    sh.nt = NT
+    sh.wavelet = sh.wavelet[:NT]
+    sh.src_k = int(sh.rec_k[2]) + 30
+    w.shots = [sh]
+    tune = _bench_tune()
+    assert tune["rec_overlap"] == 1 and tune["adj_tb_rows"] == 48
+    _say("full grid", sh.NR, sh.NZ, NT, tune)
+    g = geom(sh)
+    lam_o, mu_o, rho_o = oracle_models(w, 0, "start")
+    lt, mt, _ = oracle_models(w, 0, "true")
+    d_obs = oracle.forward(g, lt, mt, rho_o, sh.wavelet)
+    d_o = oracle.forward(g, lam_o, mu_o, rho_o, sh.wavelet)
+    _, r = oracle.misfit(d_o, d_obs)
+    assert np.abs(r).max() > 1e-3 * np.abs(d_o).max()  # the arrivals are inside the record
+    gl_o, gm_o, il_o = oracle.gradient(g, lam_o, mu_o, rho_o, sh.wavelet, r, seg=250)
+
+    sv = P.Survey(w.shots, (w.NRg, w.NZg), ckpt_every=250)
+    sv.set_tune(**tune)
+    assert sv.kernel_shapes()["adj"] == (8, 48, 16)
+    lam, mu, rho = gpu_models(w)
+    wav = sv.pack_wavelets([sh.wavelet])
+    tr = sv.fwd_model(lam, mu, rho, wav, store_ckpt=True)
+    d_g = sv.unpack_traces(tr)[0]
+    assert rel_l2(d_g, d_o) <= 1e-4, rel_l2(d_g, d_o)
+    strong = [j for j in range(d_o.shape[0]) if np.abs(d_o[j]).max() > 1e-2 * np.abs(d_o).max()]
+    assert len(strong) >= 4
+    for j in strong:
+        assert rel_l2(d_g[j], d_o[j]) <= 1e-4, (j, rel_l2(d_g[j], d_o[j]))
+    acc = sv.adjoint_model(lam, mu, rho, wav, f32(r.ravel()))
+    gl, gm, il = (t.cpu().numpy() for t in sv.gradient(mu, acc))
+    torch.cuda.synchronize()
+    form = w.mask.astype(bool)
+    errs = (rel_l2(gl, gl_o), rel_l2(gm, gm_o), rel_l2(gl[form], gl_o[form]),
+            rel_l2(gm[form], gm_o[form]), rel_l2(il, il_o))
+    print("[case] full grid rel-L2 g_lam %.3g g_mu %.3g (formation %.3g %.3g) illum %.3g" % errs)
+    assert max(errs[:4]) <= 1e-3 and errs[4] <= 1e-4
