@@ -38,18 +38,19 @@ REC_BYTES_PER_CELL_STEP = 68
 # they read for a device copy of 1 GiB from cold memory (bench.py
 # --copy-calibration): FETCH_SIZE 524307 KiB for 1048576 KiB read,
 # WRITE_SIZE 1048576 KiB for 1048576 KiB written.  An entry holds only for
-# the kernel sources it was measured on (SHA-256 of the files below) and the
-# same kernel shape, tile map and workload; otherwise traffic is null.
+# the kernel sources and the host code that tiles their launches as they were
+# measured (SHA-256 of the files below) and the same kernel shape, tile map and
+# workload; otherwise traffic is null.
 PMC_FETCH_SCALE = 1048576.0 / 524307.125
 PMC_WRITE_SCALE = 1048576.0 / 1048576.0
 PMC_SOURCES = ("paper_2005_00281_amd/csrc/bhfwi_tb_adj.hip",
                "paper_2005_00281_amd/csrc/bhfwi_tb_fwd.hip",
-               "paper_2005_00281_amd/csrc/bhfwi_internal.h")
+               "paper_2005_00281_amd/csrc/bhfwi_internal.h",
+               "paper_2005_00281_amd/csrc/bhfwi_host.hip")
 PMC_TRAFFIC = {
     # (kernel, tile_map, workload, sources sha256[:16]): (FETCH KiB, WRITE KiB), summed
     # over the kernels of one launch block
-    ("k_adj_tb<8, 48, 16, 0, 0> + k_adj_tb<8, 32, 16, 1, 0>", 1, "c2", "191dde93b7917663"):
-        (42121.50 + 11808.14, 22375.56 + 6724.69),
+
 }
 
 
@@ -229,6 +230,9 @@ def main():
     ap.add_argument("--adj-tb", type=int, default=-1,
                     help="adjoint steps per launch (0: as the forward, 1: one per launch)")
     ap.add_argument("--pml-overlap", type=int, default=-1)
+    ap.add_argument("--full-history", type=int, default=-1,
+                    help="1: keep the velocity history of every step (no checkpoints, no "
+                         "recompute) when it fits (default: the tune's)")
     ap.add_argument("--rec-overlap", type=int, default=-1,
                     help="1: recompute segment j-1 on a second stream during the adjoint of "
                          "segment j (default: the tune's)")
@@ -364,6 +368,9 @@ def main():
     if args.rec_overlap >= 0:
         for sv in surveys:
             sv.set_tune(rec_overlap=args.rec_overlap)
+    if args.full_history >= 0:
+        for sv in surveys:
+            sv.set_tune(full_history=args.full_history)
     # the shared workspaces of the iteration are sized for the tune in force
     inv = Inversion(surveys, f32(w.vp_start), f32(w.vs_start), rho, wavs, observed, mask,
                     line_search=line_search, density=args.density, precond=args.precond,

@@ -132,6 +132,15 @@ typedef struct {
                                  query bhfwi_sizes after setting it); the results
                                  are bit-identical to 0 (default).  Not combined
                                  with pml_overlap. */
+    int32_t full_history;     /* 1: no checkpoints and no recompute: the forward
+                                 of bhfwi_fwd_model with BHFWI_STORE_CKPT writes
+                                 v^{n+1/2} of every step into ckpt (ckpt_bytes
+                                 becomes 8 nt_max cells bytes; adj_ws_bytes
+                                 drops its history) and bhfwi_adjoint_model reads
+                                 it there.  For surveys whose whole history fits
+                                 in HBM; rec_overlap then has nothing to do.
+                                 Gradients equal the checkpointed ones to FP32
+                                 regrouping of the correlation sums. */
 } bhfwi_tune;
 
 /* Memory of one group of shots evaluated together (bhfwi_plan_bytes). */

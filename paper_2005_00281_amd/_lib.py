@@ -49,7 +49,8 @@ class Tune(C.Structure):
                 ("tb_steps", C.c_int32), ("tb_rows", C.c_int32), ("tb_waves", C.c_int32),
                 ("tile_map", C.c_int32), ("adj_tb_steps", C.c_int32),
                 ("adj_tb_rows", C.c_int32), ("adj_tb_waves", C.c_int32),
-                ("pml_overlap", C.c_int32), ("rec_overlap", C.c_int32)]
+                ("pml_overlap", C.c_int32), ("rec_overlap", C.c_int32),
+                ("full_history", C.c_int32)]
 
 
 class PlanBytes(C.Structure):
@@ -403,6 +404,9 @@ class Survey:
         if key in table:
             self.set_tune(**table[key]["tune"])
             return dict(table[key], cached=True)
+        full = self.get_tune()["full_history"]
+        if full:  # the probe needs the checkpointed form's history in adj_ws
+            self.set_tune(full_history=0)
         z = self.sizes
         if probe_steps is None:
             probe_steps = min(z.ckpt_every, z.nt_max, 256)
@@ -415,6 +419,9 @@ class Survey:
                                      _f32(rho, n), _f32(wavelet, z.wavelet_elems), _f32(tr),
                                      _ptr(fw), fw.numel(), _ptr(aw), aw.numel(), _f32(acc),
                                      int(probe_steps), C.byref(best), C.byref(ms)), self._h)
+        if full:
+            best.full_history = 1
+            self.set_tune(full_history=1)
         _check(load().bhfwi_sizes(self._h, C.byref(self.sizes)), self._h)
         entry = {"tune": {name: getattr(best, name) for name, _ in Tune._fields_},
                  "probe_ms": ms.value, "probe_steps": int(probe_steps)}

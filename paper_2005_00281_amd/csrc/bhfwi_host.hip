@@ -713,6 +713,7 @@ int run_sequence(bhfwi_ctx* c, hipStream_t st, std::vector<uintptr_t> key, F&& r
     key.push_back((uintptr_t)c->tune.adj_tb_waves);
     key.push_back((uintptr_t)c->tune.pml_overlap);
     key.push_back((uintptr_t)c->tune.rec_overlap);
+    key.push_back((uintptr_t)c->tune.full_history);
     key.push_back((uintptr_t)c->order);
     for (size_t g = 0; g < c->graphs.size(); ++g)
         if (c->graphs[g].key == key) {
@@ -952,10 +953,14 @@ int bhfwi_sizes(const bhfwi_ctx* c, bhfwi_sizes_t* o)
 {
     if (!c || !o) return BHFWI_EINVAL;
     o->fwd_ws_bytes = 2 * c->fst_len * (int64_t)sizeof(float);
-    o->ckpt_bytes = (int64_t)std::max(0, c->nseg - 1) * c->fst_len * (int64_t)sizeof(float);
-    o->adj_ws_bytes =
-        (2 * c->ast_len + (c->tune.rec_overlap ? 4 : 2) * (int64_t)c->ckpt_every * c->cells +
-         (c->order == 4 ? (int64_t)bhfwi::o4::N_SCR * c->cells : 0)) * (int64_t)sizeof(float);
+    const bool full = c->tune.full_history != 0;
+    o->ckpt_bytes = (full ? 2 * (int64_t)c->nt_max * c->cells
+                          : (int64_t)std::max(0, c->nseg - 1) * c->fst_len) *
+                    (int64_t)sizeof(float);
+    const int64_t hist = full ? 0 : (c->tune.rec_overlap ? 4 : 2) * (int64_t)c->ckpt_every * c->cells;
+    o->adj_ws_bytes = (2 * c->ast_len + hist +
+                       (c->order == 4 ? (int64_t)bhfwi::o4::N_SCR * c->cells : 0)) *
+                      (int64_t)sizeof(float);
     o->acc_elems = 4 * c->cells;
     o->trace_elems = c->trace_len;
     o->wavelet_elems = c->wave_len;
@@ -1057,6 +1062,7 @@ int bhfwi_set_tune(bhfwi_ctx* c, const bhfwi_tune* t)
     if (t->rows_per_wave < 1 || t->use_graph < 0 || t->use_graph > 1 || t->time_kernels < 0 ||
         t->time_kernels > 1 || t->tb_steps < 0 || t->tile_map < 0 || t->tile_map > 1 ||
         t->pml_overlap < 0 || t->pml_overlap > 1 || t->rec_overlap < 0 || t->rec_overlap > 1 ||
+        t->full_history < 0 || t->full_history > 1 ||
         (t->rec_overlap && t->pml_overlap) ||
         (t->tb_steps >= 2 && !fwd_supported(t->tb_steps, t->tb_rows, t->tb_waves)) ||
         t->adj_tb_steps < 0 ||
@@ -1136,6 +1142,10 @@ int bhfwi_autotune(bhfwi_ctx* c, void* stream, const float* lam, const float* mu
         return fail(c, BHFWI_ENOMEM, "autotune: workspace too small");
     hipStream_t st = (hipStream_t)stream;
     const int P = std::max(1, std::min<int>(probe_steps, std::min(c->ckpt_every, c->nt_max)));
+    // the probe keeps its own velocity history after the adjoint states
+    if (adj_ws_bytes < (2 * c->ast_len + 2 * (int64_t)P * c->cells) * (int64_t)sizeof(float))
+        return fail(c, BHFWI_ENOMEM, "autotune: adj_ws holds no history for %d probe steps "
+                                     "(tune with full_history 0)", P);
     const bhfwi_tune base = c->tune;
     float* fb[2] = {(float*)fwd_ws, (float*)fwd_ws + c->fst_len};
     float* ab[2] = {(float*)adj_ws, (float*)adj_ws + c->ast_len};
@@ -1350,9 +1360,15 @@ int bhfwi_fwd_model(bhfwi_ctx* c, void* stream, const float* lam, const float* m
     hipStream_t st = (hipStream_t)stream;
     float* b[2] = {(float*)fwd_ws, (float*)fwd_ws + c->fst_len};
     const int K = c->ckpt_every;
+    const bool full = c->tune.full_history != 0;
     auto record = [&](hipStream_t s) {
         launch_fill(s, b[0], 2 * c->fst_len, 0.0f);
         int parity = 0;
+        if (store && full) {  // the velocity history of every step, no checkpoints
+            fwd_range(c, s, 0, c->nt_max, lam, mu, rho, wavelet, b, &parity, traces,
+                      (float*)ckpt, 0);
+            return;
+        }
         for (int n = 0; n < c->nt_max; n += K) {
             const int n1 = std::min(n + K, c->nt_max);
             fwd_range(c, s, n, n1, lam, mu, rho, wavelet, b, &parity, traces, nullptr, 0);
@@ -1413,13 +1429,14 @@ int adjoint_impl(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
     hipStream_t st = (hipStream_t)stream;
     float* fb[2] = {(float*)fwd_ws, (float*)fwd_ws + c->fst_len};
     float* ab[2] = {(float*)adj_ws, (float*)adj_ws + c->ast_len};
+    const bool full = c->tune.full_history != 0;
     float* hist = (float*)adj_ws + 2 * c->ast_len;
-    const int nhist = c->tune.rec_overlap ? 2 : 1;  // velocity histories
+    const int nhist = full ? 0 : c->tune.rec_overlap ? 2 : 1;  // velocity histories in adj_ws
     float* scr = hist + nhist * 2 * (int64_t)c->ckpt_every * c->cells;  // fourth order only
     const int64_t hslot = 2 * c->cells;
     const int K = c->ckpt_every;
     float* const fbc[2] = {fb[0], fb[1]};
-    const bool ovl = c->tune.rec_overlap && c->nseg > 1;
+    const bool ovl = !full && c->tune.rec_overlap && c->nseg > 1;
     if (ovl) {
         if (!c->rec_stream)
             HIPOK(c, hipStreamCreateWithFlags(&c->rec_stream, hipStreamNonBlocking));
@@ -1460,7 +1477,21 @@ int adjoint_impl(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
             (void)hipEventRecord(c->ev_adj[j & 1], s);
         }
     };
+    // Full history: the forward stored v^{n+1/2} of every step in ckpt.
+    auto record_full = [&](hipStream_t s) {
+        launch_fill(s, ab[0], 2 * c->ast_len, 0.0f);
+        launch_fill(s, acc, 4 * c->cells, 0.0f);
+        if (acc_rho) launch_fill(s, acc_rho, 2 * c->cells, 0.0f);
+        if (acc_h) launch_fill(s, acc_h, 2 * c->cells, 0.0f);
+        int m = 0;
+        adj_range(c, s, 0, c->nt_max, lam, mu, rho, resid, ab, &m, (const float*)ckpt, acc,
+                  acc_rho, acc_h, scr);
+    };
     auto record = [&](hipStream_t s) {
+        if (full) {
+            record_full(s);
+            return;
+        }
         if (ovl) {
             record_ovl(s);
             return;

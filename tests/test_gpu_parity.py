@@ -49,10 +49,11 @@ def survey(w, ckpt=250, tune=None):
 
 
 def T(rows=4, wpb=4, graph=1, tb=0, tbr=16, tbw=4, tmap=1, atb=0, atbr=16, atbw=8, ovl=1,
-      rov=0):
+      rov=0, full=0):
     return dict(rows_per_wave=rows, waves_per_block=wpb, use_graph=graph, tb_steps=tb,
                 tb_rows=tbr, tb_waves=tbw, tile_map=tmap, adj_tb_steps=atb, adj_tb_rows=atbr,
-                adj_tb_waves=atbw, pml_overlap=0 if rov else ovl, rec_overlap=rov)
+                adj_tb_waves=atbw, pml_overlap=0 if rov else ovl, rec_overlap=rov,
+                full_history=full)
 
 
 FWD_TUNES = [T(1, 1, 0), T(2, 4, 1), T(3, 2, 1), T(4, 4, 0), T(16, 4, 1), T(64, 8, 0),
@@ -73,7 +74,9 @@ GRAD_TUNES = [T(1, 1, 1), T(2, 4, 0), T(4, 4, 1), T(5, 4, 1), T(64, 8, 0), T(tb=
               T(tb=8, tbr=48, tbw=16, atb=6, atbr=32, atbw=16, ovl=0),
               T(tb=8, tbr=48, tbw=16, atb=6, atbr=32, atbw=16, ovl=1, graph=0),
               T(tb=8, tbr=64, tbw=16, atb=8, atbr=32, atbw=16, rov=1),
-              T(tb=6, tbr=32, tbw=16, rov=1, graph=0), T(2, 4, 1, rov=1)]
+              T(tb=6, tbr=32, tbw=16, rov=1, graph=0), T(2, 4, 1, rov=1),
+              T(tb=8, tbr=64, tbw=16, atb=8, atbr=48, atbw=16, full=1),
+              T(tb=4, tbw=8, graph=0, full=1), T(2, 4, 1, full=1, rov=1)]
 
 
 def oracle_traces(w, s=0, which="start"):
@@ -197,6 +200,36 @@ def test_overlapped_recompute_is_bit_identical(tune):
         outs.append([t.cpu().numpy() for t in sv.gradient(mu, acc)])
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("tune", [T(tb=8, tbr=64, tbw=16, atb=8, atbr=48, atbw=16),
+                                  T(tb=4, graph=0), T(4, 4, 1)])
+def test_full_history_matches_checkpointed(tune):
+    """full_history = 1: the forward keeps v of every step and the adjoint
+    reads it, with no checkpoints or recompute.  One step per launch repeats
+    the same arithmetic (bit for bit); time blocks regroup the FP32
+    correlation sums at the former checkpoint boundaries (<= 1e-6)."""
+    w = _multi_shot_workload()
+    _say("full history", tune)
+    lam, mu, rho = gpu_models(w)
+    torch.manual_seed(3)
+    outs, trs = [], []
+    for full in (0, 1):
+        sv = survey(w, ckpt=37, tune=dict(tune, full_history=full))
+        if full:
+            assert sv.sizes.ckpt_bytes == 8 * sv.sizes.nt_max * sv.sizes.cells
+        wav = sv.pack_wavelets([s.wavelet for s in w.shots])
+        trs.append(sv.fwd_model(lam, mu, rho, wav, store_ckpt=True).cpu().numpy())
+        if full == 0:
+            r = torch.randn(sv.sizes.trace_elems, device=_dev())
+        acc = sv.adjoint_model(lam, mu, rho, wav, r)
+        outs.append([t.cpu().numpy() for t in sv.gradient(mu, acc)])
+    assert np.array_equal(trs[0], trs[1])
+    for a, b in zip(outs[0], outs[1]):
+        if tune["tb_steps"] >= 2:
+            assert rel_l2(b, a) <= 1e-6, rel_l2(b, a)
+        else:
             assert np.array_equal(a, b)
 
 
