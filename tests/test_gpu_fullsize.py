@@ -1,8 +1,9 @@
 """Parity at the benchmark's full grid (340 x 2088 padded cells, one shot) in
 the launch configuration the benchmark times: the tune-cache entry of that
-workload (forward 8x64x16 with 8x32x16 PML sub-tiles, adjoint 8x48x16,
-recompute overlapped with the adjoint on a second stream, HIP graphs) and its
-checkpoint interval of 250 steps.
+workload (forward 8x64x16 with 8x32x16 PML sub-tiles, adjoint 8x48x16, the
+velocity history of every step kept instead of checkpoints, HIP graphs), and
+in the checkpointed form with the recompute overlapped on a second stream
+(checkpoints every 250 steps).
 
 The record is cut to 900 steps (four checkpoint segments, the last one
 ragged, so the overlap is exercised) and the source is moved 30 rows above the
@@ -40,17 +41,14 @@ def _bench_tune():
     return table[key[0]]["tune"]
 
 
-def test_full_grid_in_the_benchmark_launch_configuration():
-    import paper_2005_00281_amd as P
+@pytest.fixture(scope="module")
+def full_grid():
     w = copy.copy(workloads.make("c2"))
     sh = copy.copy(w.shots[0])
     sh.nt = NT
     sh.wavelet = sh.wavelet[:NT]
     sh.src_k = int(sh.rec_k[2]) + 30
     w.shots = [sh]
-    tune = _bench_tune()
-    assert tune["rec_overlap"] == 1 and tune["adj_tb_rows"] == 48
-    _say("full grid", sh.NR, sh.NZ, NT, tune)
     g = geom(sh)
     lam_o, mu_o, rho_o = oracle_models(w, 0, "start")
     lt, mt, _ = oracle_models(w, 0, "true")
@@ -59,7 +57,19 @@ def test_full_grid_in_the_benchmark_launch_configuration():
     _, r = oracle.misfit(d_o, d_obs)
     assert np.abs(r).max() > 1e-3 * np.abs(d_o).max()  # the arrivals are inside the record
     gl_o, gm_o, il_o = oracle.gradient(g, lam_o, mu_o, rho_o, sh.wavelet, r, seg=250)
+    return w, r, (d_o, gl_o, gm_o, il_o)
 
+
+@pytest.mark.parametrize("form", ["benchmark", "overlapped recompute"])
+def test_full_grid_in_the_benchmark_launch_configuration(full_grid, form):
+    import paper_2005_00281_amd as P
+    w, r, (d_o, gl_o, gm_o, il_o) = full_grid
+    sh = w.shots[0]
+    tune = dict(_bench_tune())
+    assert tune["full_history"] == 1 and tune["adj_tb_rows"] == 48
+    if form != "benchmark":
+        tune.update(full_history=0, rec_overlap=1)
+    _say("full grid", form, sh.NR, sh.NZ, NT, tune)
     sv = P.Survey(w.shots, (w.NRg, w.NZg), ckpt_every=250)
     sv.set_tune(**tune)
     assert sv.kernel_shapes()["adj"] == (8, 48, 16)
