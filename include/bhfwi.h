@@ -308,7 +308,8 @@ int bhfwi_velocities(void *stream, int64_t n, const float *lam, const float *mu,
  * normal stress at each receiver after each step (Method section: pressure
  * recorded in the fluid).  fwd_ws (>= fwd_ws_bytes) is scratch for the state.
  * With BHFWI_STORE_CKPT, ckpt (>= ckpt_bytes) receives the state every
- * ckpt_every steps for bhfwi_adjoint_model. */
+ * ckpt_every steps for bhfwi_adjoint_model, or, with the tune's
+ * full_history, the velocities v^{n+1/2} of every step. */
 int bhfwi_fwd_model(bhfwi_ctx *ctx, void *stream, const float *lam, const float *mu,
                     const float *rho, const float *wavelet, float *traces, void *fwd_ws,
                     int64_t fwd_ws_bytes, void *ckpt, int64_t ckpt_bytes, int32_t flags);
@@ -323,7 +324,8 @@ int bhfwi_misfit(bhfwi_ctx *ctx, void *stream, const float *traces, const float 
  * driven by resid = dJ/dtraces (packed), fused with the zero-lag correlation
  * of Eq. 7-8.  Each checkpoint segment is recomputed from ckpt (written by
  * bhfwi_fwd_model with BHFWI_STORE_CKPT and the same model) storing v, then
- * run backwards.  acc (device, acc_elems floats, overwritten) receives per
+ * run backwards (with the tune's full_history, ckpt already holds v of every
+ * step and nothing is recomputed).  acc (device, acc_elems floats, overwritten) receives per
  * shot, on the shot's padded grid: plane 0 dJ/dlambda, plane 1 the C-node
  * part of dJ/dmu, plane 2 dJ/dmu_S at tau_rz nodes, plane 3 the illumination
  * sum_n dt |v|^2.  adj_ws (>= adj_ws_bytes) is scratch. */
