@@ -233,7 +233,8 @@ def main():
     ap.add_argument("--pml-overlap", type=int, default=-1)
     ap.add_argument("--full-history", type=int, default=-1,
                     help="1: keep the velocity history of every step (no checkpoints, no "
-                         "recompute) when it fits (default: the tune's)")
+                         "recompute); default: when the plan is one group that fits the "
+                         "budget with it")
     ap.add_argument("--rec-overlap", type=int, default=-1,
                     help="1: recompute segment j-1 on a second stream during the adjoint of "
                          "segment j (default: the tune's)")
@@ -372,6 +373,10 @@ def main():
     if args.full_history >= 0:
         for sv in surveys:
             sv.set_tune(full_history=args.full_history)
+    elif len(surveys) == 1 and args.order == 2:
+        full = surveys[0].use_full_history_if_fits(budget)
+        log("full velocity history: %s (%.1f GB)" % (
+            "on" if full else "off", surveys[0].device_bytes() / 1e9))
     # the shared workspaces of the iteration are sized for the tune in force
     inv = Inversion(surveys, f32(w.vp_start), f32(w.vs_start), rho, wavs, observed, mask,
                     line_search=line_search, density=args.density, precond=args.precond,

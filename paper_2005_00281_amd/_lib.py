@@ -361,6 +361,26 @@ class Survey:
         _check(load().bhfwi_set_tune(self._h, C.byref(t)), self._h)
         _check(load().bhfwi_sizes(self._h, C.byref(self.sizes)), self._h)
 
+    def device_bytes(self):
+        """Device memory one gradient evaluation of this survey needs in the
+        current tune: workspaces, checkpoints or full history, accumulators
+        and three trace arrays (traces, residuals, observed data)."""
+        z = self.sizes
+        return (z.fwd_ws_bytes + z.ckpt_bytes + z.adj_ws_bytes + 4 * z.acc_elems +
+                12 * z.trace_elems)
+
+    def use_full_history_if_fits(self, budget_bytes):
+        """Keep the velocity history of every step (tune full_history: no
+        checkpoints, no recompute) when the survey then fits budget_bytes;
+        returns whether it does."""
+        if self.get_tune()["full_history"]:
+            return self.device_bytes() <= budget_bytes
+        self.set_tune(full_history=1)
+        if self.device_bytes() <= budget_bytes:
+            return True
+        self.set_tune(full_history=0)
+        return False
+
     def kernel_shapes(self):
         """{'fwd', 'fwd_pml', 'adj', 'adj_pml'}: (T, rows, waves) of the
         temporally blocked kernels the current tune runs (T = 0: one step per

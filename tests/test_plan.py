@@ -52,3 +52,25 @@ def test_plan_bytes_are_the_context_sizes():
         b = plan.workspace_bytes(shots, K)
         assert (z.fwd_ws_bytes, z.ckpt_bytes, z.adj_ws_bytes, 4 * z.acc_elems) == \
             (b["fwd"], b["ckpt"], b["adj"], b["acc"])
+
+
+@pytest.mark.gpu
+def test_full_history_is_taken_when_it_fits():
+    """The single-shot benchmark survey keeps its whole velocity history
+    (8 nt cells bytes in place of checkpoints) under an 80 % budget of the
+    device, and falls back to checkpoints when the budget is smaller than that
+    history."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2005_00281_amd as P
+    w = workloads.make("c2")
+    sv = P.Survey(w.shots, (w.NRg, w.NZg), ckpt_every=250)
+    ckpt_bytes = sv.sizes.ckpt_bytes
+    hist = 8 * sv.sizes.nt_max * sv.sizes.cells
+    assert sv.use_full_history_if_fits(0.8 * torch.cuda.get_device_properties(0).total_memory)
+    assert sv.get_tune()["full_history"] == 1 and sv.sizes.ckpt_bytes == hist
+    sv.set_tune(full_history=0)
+    assert sv.sizes.ckpt_bytes == ckpt_bytes
+    assert not sv.use_full_history_if_fits(hist / 2)
+    assert sv.get_tune()["full_history"] == 0 and sv.sizes.ckpt_bytes == ckpt_bytes
