@@ -373,7 +373,7 @@ def main():
     if args.full_history >= 0:
         for sv in surveys:
             sv.set_tune(full_history=args.full_history)
-    elif len(surveys) == 1 and args.order == 2:
+    elif len(surveys) == 1:
         full = surveys[0].use_full_history_if_fits(budget)
         log("full velocity history: %s (%.1f GB)" % (
             "on" if full else "off", surveys[0].device_bytes() / 1e9))
