@@ -193,9 +193,8 @@ int bhfwi_sizes(const bhfwi_ctx *ctx, bhfwi_sizes_t *out);
  * ones).  Applies to bhfwi_fwd_model and bhfwi_adjoint_model (modulus
  * gradients only: no density or pseudo-Hessian outputs, no autotune; one
  * step per launch).  Order 4 needs the stricter stability bound
- * vmax dt sqrt(1/dr^2 + 1/dz^2) < 6/7 (BHFWI_ECFL otherwise) and
- * N_SCR = 11 more planes of cells floats in adj_ws: query bhfwi_sizes after
- * this call.  Synchronises the device. */
+ * vmax dt sqrt(1/dr^2 + 1/dz^2) < 6/7 (BHFWI_ECFL otherwise).  Synchronises
+ * the device. */
 int bhfwi_set_order(bhfwi_ctx *ctx, int32_t order);
 int bhfwi_set_tune(bhfwi_ctx *ctx, const bhfwi_tune *tune);
 int bhfwi_get_tune(const bhfwi_ctx *ctx, bhfwi_tune *out);

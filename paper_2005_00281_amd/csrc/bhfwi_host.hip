@@ -413,38 +413,28 @@ void adj_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const flo
                    (long long)c->cells);
 }
 
-// Fourth-order step n: velocities, then stresses (one thread per cell).
+// Fourth-order step n in one launch (tiles of TK x TI cells).
 void fwd4_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const float* mu,
                  const float* rho, const float* wav, const float* in, float* out, float* traces,
                  float* hist)
 {
-    const dim3 grid((unsigned)c->ntile4), block(bhfwi::o4::TK * bhfwi::o4::TI);
     EvScope ev(c, st, hist ? 1 : 0);
-    hipLaunchKernelGGL(bhfwi::o4::k_fwd4_vel, grid, block, 0, st, c->d_shots, c->d_tile4,
-                       c->nshot, n, rho, c->d_pml_r, c->d_pml_z, in, out, hist,
-                       (long long)c->cells);
-    hipLaunchKernelGGL(bhfwi::o4::k_fwd4_str, grid, block, 0, st, c->d_shots, c->d_tile4,
-                       c->nshot, n, lam, mu, wav, c->d_rec, c->d_pml_r, c->d_pml_z, in, out,
-                       traces);
+    hipLaunchKernelGGL(bhfwi::o4::k_fwd4, dim3((unsigned)c->ntile4),
+                       dim3(bhfwi::o4::TK * bhfwi::o4::TI), 0, st, c->d_shots, c->d_tile4,
+                       c->nshot, n, lam, mu, rho, wav, c->d_rec, c->d_pml_r, c->d_pml_z, in, out,
+                       traces, hist, (long long)c->cells);
 }
 
-// Fourth-order adjoint step n: drivers and correlation, adjoint velocities,
-// adjoint stresses; scr holds N_SCR planes of cells floats.
+// Fourth-order adjoint step n fused with the correlation, in one launch.
 void adj4_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const float* mu,
                  const float* rho, const float* resid, const float* in, float* out,
-                 const float* hist, float* acc, float* scr)
+                 const float* hist, float* acc)
 {
-    const dim3 grid((unsigned)c->ntile4), block(bhfwi::o4::TK * bhfwi::o4::TI);
     EvScope ev(c, st, 2);
-    hipLaunchKernelGGL(bhfwi::o4::k_adj4_drivers, grid, block, 0, st, c->d_shots, c->d_tile4,
-                       c->nshot, n, lam, mu, c->d_rec, resid, c->d_pml_r, c->d_pml_z, in, out,
-                       hist, scr, acc, (long long)c->cells);
-    hipLaunchKernelGGL(bhfwi::o4::k_adj4_velocity, grid, block, 0, st, c->d_shots, c->d_tile4,
-                       c->nshot, n, rho, c->d_pml_r, c->d_pml_z, in, out, scr,
-                       (long long)c->cells);
-    hipLaunchKernelGGL(bhfwi::o4::k_adj4_stress, grid, block, 0, st, c->d_shots, c->d_tile4,
-                       c->nshot, n, c->d_pml_r, c->d_pml_z, out, (const float*)scr,
-                       (long long)c->cells);
+    hipLaunchKernelGGL(bhfwi::o4::k_adj4, dim3((unsigned)c->ntile4),
+                       dim3(bhfwi::o4::TK * bhfwi::o4::TI), 0, st, c->d_shots, c->d_tile4,
+                       c->nshot, n, lam, mu, rho, c->d_rec, resid, c->d_pml_r, c->d_pml_z, in,
+                       out, hist, acc, (long long)c->cells);
 }
 
 // Supported temporally blocked shapes: (steps T, tile rows incl. halo,
@@ -632,13 +622,13 @@ void adj_tb_launch(bhfwi_ctx* c, hipStream_t st, int n_hi, int nsteps, const flo
 // ab[(*m + 1) & 1]; hist holds v of step n at slot n - n0.
 void adj_range(bhfwi_ctx* c, hipStream_t st, int n0, int n1, const float* lam, const float* mu,
                const float* rho, const float* resid, float* const ab[2], int* m,
-               const float* hist, float* acc, float* acc_rho, float* acc_h, float* scr = nullptr)
+               const float* hist, float* acc, float* acc_rho, float* acc_h)
 {
     const int64_t hslot = 2 * c->cells;
     if (c->order == 4) {
         for (int n = n1 - 1; n >= n0; --n, ++*m)
             adj4_launch(c, st, n, lam, mu, rho, resid, ab[*m & 1], ab[(*m + 1) & 1],
-                        hist + (int64_t)(n - n0) * hslot, acc, scr);
+                        hist + (int64_t)(n - n0) * hslot, acc);
         return;
     }
     const Shape sh = adj_shape(c);
@@ -958,9 +948,7 @@ int bhfwi_sizes(const bhfwi_ctx* c, bhfwi_sizes_t* o)
                           : (int64_t)std::max(0, c->nseg - 1) * c->fst_len) *
                     (int64_t)sizeof(float);
     const int64_t hist = full ? 0 : (c->tune.rec_overlap ? 4 : 2) * (int64_t)c->ckpt_every * c->cells;
-    o->adj_ws_bytes = (2 * c->ast_len + hist +
-                       (c->order == 4 ? (int64_t)bhfwi::o4::N_SCR * c->cells : 0)) *
-                      (int64_t)sizeof(float);
+    o->adj_ws_bytes = (2 * c->ast_len + hist) * (int64_t)sizeof(float);
     o->acc_elems = 4 * c->cells;
     o->trace_elems = c->trace_len;
     o->wavelet_elems = c->wave_len;
@@ -1431,8 +1419,6 @@ int adjoint_impl(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
     float* ab[2] = {(float*)adj_ws, (float*)adj_ws + c->ast_len};
     const bool full = c->tune.full_history != 0;
     float* hist = (float*)adj_ws + 2 * c->ast_len;
-    const int nhist = full ? 0 : c->tune.rec_overlap ? 2 : 1;  // velocity histories in adj_ws
-    float* scr = hist + nhist * 2 * (int64_t)c->ckpt_every * c->cells;  // fourth order only
     const int64_t hslot = 2 * c->cells;
     const int K = c->ckpt_every;
     float* const fbc[2] = {fb[0], fb[1]};
@@ -1473,7 +1459,7 @@ int adjoint_impl(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
             fwd_range(c, r, n0, n1, lam, mu, rho, wavelet, fbc, &parity, nullptr, h, n0);
             (void)hipEventRecord(c->ev_rec[j & 1], r);
             (void)hipStreamWaitEvent(s, c->ev_rec[j & 1], 0);
-            adj_range(c, s, n0, n1, lam, mu, rho, resid, ab, &m, h, acc, acc_rho, acc_h, scr);
+            adj_range(c, s, n0, n1, lam, mu, rho, resid, ab, &m, h, acc, acc_rho, acc_h);
             (void)hipEventRecord(c->ev_adj[j & 1], s);
         }
     };
@@ -1485,7 +1471,7 @@ int adjoint_impl(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
         if (acc_h) launch_fill(s, acc_h, 2 * c->cells, 0.0f);
         int m = 0;
         adj_range(c, s, 0, c->nt_max, lam, mu, rho, resid, ab, &m, (const float*)ckpt, acc,
-                  acc_rho, acc_h, scr);
+                  acc_rho, acc_h);
     };
     auto record = [&](hipStream_t s) {
         if (full) {
@@ -1511,7 +1497,7 @@ int adjoint_impl(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
                                      sizeof(float) * c->fst_len, hipMemcpyDeviceToDevice, s);
             int parity = 0;
             fwd_range(c, s, n0, n1, lam, mu, rho, wavelet, fbc, &parity, nullptr, hist, n0);
-            adj_range(c, s, n0, n1, lam, mu, rho, resid, ab, &m, hist, acc, acc_rho, acc_h, scr);
+            adj_range(c, s, n0, n1, lam, mu, rho, resid, ab, &m, hist, acc, acc_rho, acc_h);
         }
     };
     return run_sequence(c, st,

@@ -135,8 +135,8 @@ def test_order4_batched_equals_single_shots():
 
 def test_order4_rules():
     """Order 3 is rejected, a time step within the second-order bound but not
-    the fourth-order one is rejected, the adjoint workspace grows by eleven
-    planes, and the extra adjoint outputs are refused at order 4."""
+    the fourth-order one is rejected, the workspaces are those of order 2, and
+    the extra adjoint outputs are refused at order 4."""
     import paper_2005_00281_amd as P
     from paper_2005_00281_amd._lib import BhfwiError
     w = workloads.tiny(nr=20, nz=60, p=4, nt=50)
@@ -146,7 +146,7 @@ def test_order4_rules():
     with pytest.raises(BhfwiError):
         sv.set_order(3)
     sv.set_order(4)
-    assert sv.sizes.adj_ws_bytes == a2 + 11 * 4 * sv.sizes.cells
+    assert sv.sizes.adj_ws_bytes == a2
     lam, mu, rho = gpu_models(w)
     wav = sv.pack_wavelets([w.shots[0].wavelet])
     sv.fwd_model(lam, mu, rho, wav, store_ckpt=True)
