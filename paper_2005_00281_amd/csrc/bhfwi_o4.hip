@@ -10,8 +10,9 @@
 // are mirrored: normal stresses and v_z (half radial positions) are even,
 // v_r and tau_rz (integer radial positions) odd and zero on the axis.
 //
-// One kernel per step and direction, on tiles of TK = 64 axial by TI = 8
-// radial cells with one thread per owned cell (512 threads).  The stages of
+// One kernel per step and direction, on tiles of TK = 64 axial by TI = 12
+// radial cells with one thread per owned cell (768 threads; the adjoint's LDS,
+// 62 KB, rules out taller tiles).  The stages of
 // a step stay in LDS with halo recomputation: the forward stages the stresses
 // on the tile plus four cells, forms the new velocities on the tile plus two
 // (the halo cells' values are recomputed by every tile that needs them) and
@@ -31,7 +32,7 @@ namespace o4 {
 
 constexpr float C1 = 9.0f / 8.0f, C2 = -1.0f / 24.0f, G1 = 9.0f / 16.0f, G2 = -1.0f / 16.0f;
 
-constexpr int TK = 64, TI = 8;
+constexpr int TK = 64, TI = 12;
 // P-region: the tile plus two cells; D-region: the tile plus four
 constexpr int PW = TK + 4, PH = TI + 4, PN = PW * PH;
 constexpr int DW = TK + 8, DH = TI + 8, DN = DW * DH;
@@ -146,7 +147,7 @@ __device__ inline bool owned(int i, int k, int i0, int k0, int NR, int NZ)
 // radial PML strips [A, C, E, H] of pr*NZ, then 4 axial strips [B, D, F, G]
 // of NR*2pz.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(TK * TI)
 k_fwd4(const ShotDev* __restrict__ shots, const int* __restrict__ tile_start, int nshot, int n,
        const float* __restrict__ lam, const float* __restrict__ mu,
        const float* __restrict__ rho, const float* __restrict__ wavelet,
@@ -459,7 +460,7 @@ struct Gather {
 enum { D_ERR = 0, D_ETT, D_EZZ, D_EZ, D_ER, ND };
 enum { P_UR = 0, P_HR, P_DZR, P_ZR, P_ZH, P_DZZ, NP };
 
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(TK * TI)
 k_adj4(const ShotDev* __restrict__ shots, const int* __restrict__ tile_start, int nshot, int n,
        const float* __restrict__ lam, const float* __restrict__ mu,
        const float* __restrict__ rho, const int* __restrict__ rec_k,
