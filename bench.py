@@ -258,6 +258,8 @@ def main():
                     help="measure the starting-model semblance stage instead")
     ap.add_argument("--progress", action="store_true",
                     help="synchronise and log after every shot group (long workloads)")
+    ap.add_argument("--no-kernel-times", action="store_true",
+                    help="skip the event-timed gradient evaluation (no roofline)")
     ap.add_argument("--kt-groups", type=int, default=0,
                     help="shot groups in the per-kernel timing pass (0: all)")
     ap.add_argument("--line-search", type=int, default=-1,
@@ -454,31 +456,33 @@ def main():
     # per-kernel durations: one more (untimed) gradient evaluation, of the first
     # --kt-groups shot groups (all by default), with every time-step kernel
     # bracketed by HIP events on the stream it runs on
+    # (--no-kernel-times skips it, for counter-collection runs: no roofline)
     timed = surveys[:args.kt_groups] if args.kt_groups > 0 else surveys
-    for x in timed:
-        x.set_tune(use_graph=0, time_kernels=1)
-        x.kernel_times(reset=True)
-    all_surveys, inv.surveys = inv.surveys, timed
-    inv.gradient()
-    inv.surveys = all_surveys
     kt = {"fwd": [0.0, 0], "rec": [0.0, 0], "adj": [0.0, 0]}
-    for x in timed:
-        for k, (ms_, n_) in x.kernel_times(reset=True).items():
-            kt[k][0] += ms_
-            kt[k][1] += n_
-        x.set_tune(use_graph=tune["use_graph"], time_kernels=0)
+    if not args.no_kernel_times:
+        for x in timed:
+            x.set_tune(use_graph=0, time_kernels=1)
+            x.kernel_times(reset=True)
+        all_surveys, inv.surveys = inv.surveys, timed
+        inv.gradient()
+        inv.surveys = all_surveys
+        for x in timed:
+            for k, (ms_, n_) in x.kernel_times(reset=True).items():
+                kt[k][0] += ms_
+                kt[k][1] += n_
+            x.set_tune(use_graph=tune["use_graph"], time_kernels=0)
     cs_timed = sum(x.sizes.cell_steps for x in timed)
     adj_ms, adj_n = kt["adj"]
     # every adjoint step of the timed groups ran once: nt cell-steps of every shot
     steps_per_launch = sum(x.sizes.nt_max for x in timed) / max(1, adj_n)
     adj_avg = adj_ms / max(1, adj_n)
     adj_bytes = ADJ_BYTES_PER_CELL_STEP * cs_timed / max(1, adj_n)  # per launch
-    achieved = adj_bytes / (adj_avg * 1e-3) / 1e9
+    achieved = adj_bytes / (adj_avg * 1e-3) / 1e9 if adj_n else 0.0
     # the adjoint block: interior tiles in the PML-free kernel, then the PML
     # (sub-)tiles in the kernel that carries the PML memories
     kshapes = sv.kernel_shapes()
     xm = (1 if args.density else 0) | (2 if args.precond == "pseudo_hessian" else 0)
-    kname = ("k_adj4_drivers + k_adj4_velocity + k_adj4_stress" if args.order == 4
+    kname = ("k_adj4" if args.order == 4
              else "k_adj_tb<%d, %d, %d, 0, %d> + k_adj_tb<%d, %d, %d, 1, %d>" % (
              kshapes["adj"] + (xm,) + kshapes["adj_pml"] + (xm,))
              if kshapes["adj"][0] >= 2
@@ -491,11 +495,11 @@ def main():
                 "traffic_unit": "bytes per time block (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                 "copy-calibrated)",
                 "traffic_GBs": (round(traffic / (adj_avg * 1e-3) / 1e9, 1)
-                                if traffic is not None else None),
+                                if traffic is not None and adj_n else None),
                 "kernel": kname, "avg_launch_us": round(adj_avg * 1e3, 3),
                 "steps_per_launch": round(steps_per_launch, 3),
                 "bytes_per_launch": int(adj_bytes),
-                "bytes_per_cell_step": ADJ_BYTES_PER_CELL_STEP}
+                "bytes_per_cell_step": ADJ_BYTES_PER_CELL_STEP} if adj_n else None
     per_cs = {"fwd": FWD_BYTES_PER_CELL_STEP, "rec": REC_BYTES_PER_CELL_STEP,
               "adj": ADJ_BYTES_PER_CELL_STEP}
     kernels = {}

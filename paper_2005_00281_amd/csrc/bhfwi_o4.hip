@@ -11,8 +11,8 @@
 // v_r and tau_rz (integer radial positions) odd and zero on the axis.
 //
 // One kernel per step and direction, on tiles of TK = 64 axial by TI = 12
-// radial cells with one thread per owned cell (768 threads; the adjoint's LDS,
-// 62 KB, rules out taller tiles).  The stages of
+// radial cells with one thread per owned cell (768 threads; taller tiles were
+// measured slower).  The stages of
 // a step stay in LDS with halo recomputation: the forward stages the stresses
 // on the tile plus four cells, forms the new velocities on the tile plus two
 // (the halo cells' values are recomputed by every tile that needs them) and
@@ -24,6 +24,13 @@
 // rates (Eq. 7-8).  A gather that the forward stencil reached through the
 // mirror is folded back: the gather at the mirrored (logical, negative) row is
 // added to its image with the field's parity.
+//
+// A single step per launch leaves little arithmetic to hide memory latency
+// behind, so each thread issues every load that does not depend on the LDS
+// stages of the step before the first barrier: for its owned cell and for at
+// most one halo cell of each region, the stresses (forward) or the adjoint
+// point (adjoint) of the D-region, the old velocities and buoyancies of the
+// P-region, the moduli, and the gradient accumulators.
 #pragma once
 #include "bhfwi_internal.h"
 
@@ -84,27 +91,7 @@ struct Grid {
         if (i == 0 || i >= NR) return 0.f;
         return sg * p[(long long)i * NZ + k];
     }
-    // a per-node product (zero outside the grid, no mirror: the fold does it)
-    __device__ float at(const float* __restrict__ p, int i, int k) const
-    {
-        if (k < 0 || k >= NZ || i < 0 || i >= NR) return 0.f;
-        return p[(long long)i * NZ + k];
-    }
 };
-
-enum { EVEN = 0, ODD, AT };
-
-// Stage one plane over a region (rows ilo .. ilo+h-1, columns klo ..
-// klo+w-1) in LDS with the boundary rule of its kind.
-template <int MODE>
-__device__ inline void stage(float* __restrict__ L, const Grid& g, const float* __restrict__ p,
-                             int ilo, int klo, int h, int w)
-{
-    for (int e = threadIdx.x; e < h * w; e += blockDim.x) {
-        const int i = ilo + e / w, k = klo + e % w;
-        L[e] = MODE == EVEN ? g.even(p, i, k) : MODE == ODD ? g.odd(p, i, k) : g.at(p, i, k);
-    }
-}
 
 // An LDS region read at grid cell (i, k), which must lie inside it; at()
 // reads zero at negative rows (per-node products have no mirror).
@@ -142,6 +129,69 @@ __device__ inline bool owned(int i, int k, int i0, int k0, int NR, int NZ)
     return i >= i0 && i < i0 + TI && k >= k0 && k < k0 + TK && i < NR && k < NZ;
 }
 
+// Each thread handles its owned cell in every region and at most one halo
+// cell: NHD of the D-region (the four rows above and below the tile, then
+// four columns on each side), NHP of the P-region (two of each).  The owned
+// cells come first so that their values stay in the registers of the thread
+// that finishes them.
+constexpr int NHD = DN - TK * TI, NHP = PN - TK * TI;
+static_assert(NHD <= TK * TI && NHP <= TK * TI, "one halo cell per thread");
+
+__device__ inline int d_halo(int h)
+{
+    constexpr int band = 4 * DW;
+    if (h < band) return h;
+    if (h < 2 * band) return (TI + 4) * DW + (h - band);
+    const int s = h - 2 * band, r = s >> 3, c = s & 7;
+    return (4 + r) * DW + (c < 4 ? c : TK + c);
+}
+
+__device__ inline int p_halo(int h)
+{
+    constexpr int band = 2 * PW;
+    if (h < band) return h;
+    if (h < 2 * band) return (TI + 2) * PW + (h - band);
+    const int s = h - 2 * band, r = s >> 2, c = s & 3;
+    return (2 + r) * PW + (c < 2 ? c : TK + c);
+}
+
+// The stresses at (i, k) with the mirror rules, in the order of the forward's
+// LDS planes: tau_rr, tau_tt (even), tau_rz (odd), tau_zz (even).
+__device__ inline void tau4(const Grid& g, const float* __restrict__ F, long long cells, int i,
+                            int k, float* t)
+{
+    t[0] = g.even(F + 2 * cells, i, k);
+    t[1] = g.even(F + 3 * cells, i, k);
+    t[2] = g.odd(F + 5 * cells, i, k);
+    t[3] = g.even(F + 4 * cells, i, k);
+}
+
+// What a velocity update at (i, k) reads from memory besides the stresses:
+// v^{n-1/2} and the buoyancies at the R and Z nodes (zero off the grid, and
+// the R terms on the axis).
+struct VelIn {
+    float vr, vz, bR, bZ;
+};
+
+__device__ inline VelIn vel_in(const ShotDev& S, const float* __restrict__ F,
+                               const float* __restrict__ rho, long long cells, int i, int k)
+{
+    VelIn V{0.f, 0.f, 0.f, 0.f};
+    const int NR = S.NR, NZ = S.NZ;
+    if (i >= 0 && i < NR && k >= 0 && k < NZ) {
+        const long long c = (long long)i * NZ + k;
+        const long long m = S.model_off + (long long)i * S.model_ld + k;
+        const int k1 = k + 1 < NZ ? k + 1 : NZ - 1;
+        V.vz = F[cells + c];
+        V.bZ = 2.0f / (rho[m] + rho[m - k + k1]);
+        if (i >= 1) {
+            V.vr = F[c];
+            V.bR = 2.0f / (rho[m - S.model_ld] + rho[m]);
+        }
+    }
+    return V;
+}
+
 // ---------------------------------------------------------------------------
 // Forward step.  State block as in the second-order kernels: 6 fields, then 4
 // radial PML strips [A, C, E, H] of pr*NZ, then 4 axial strips [B, D, F, G]
@@ -162,98 +212,132 @@ k_fwd4(const ShotDev* __restrict__ shots, const int* __restrict__ tile_start, in
     const float* __restrict__ Fi = sin + S.fst_off;
     float* __restrict__ Fo = sout + S.fst_off;
     const long long LR = S.psir_len, LZ = S.psiz_len, oPR = 6 * cells, oPZ = oPR + 4 * LR;
-    stage<EVEN>(Ls[0], g, Fi + 2 * cells, i0 - 4, k0 - 4, DH, DW);
-    stage<EVEN>(Ls[1], g, Fi + 3 * cells, i0 - 4, k0 - 4, DH, DW);
-    stage<ODD>(Ls[2], g, Fi + 5 * cells, i0 - 4, k0 - 4, DH, DW);
-    stage<EVEN>(Ls[3], g, Fi + 4 * cells, i0 - 4, k0 - 4, DH, DW);
+    const int tid = (int)threadIdx.x;
+    // this thread's owned cell, and its halo cell of each region (if any)
+    const int i = i0 + (tid >> 6), k = k0 + (tid & 63);
+    const bool ocell = i < NR && k < NZ;
+    const bool hd = tid < NHD, hp = tid < NHP;
+    const int ed = d_halo(hd ? tid : 0), ep = p_halo(hp ? tid : 0);
+    const int di = i0 - 4 + ed / DW, dk = k0 - 4 + ed % DW;
+    const int pi = i0 - 2 + ep / PW, pk = k0 - 2 + ep % PW;
+
+    // ---- every load that does not depend on this step's LDS stages, issued
+    // up front: the stresses of the D-region cells, v^{n-1/2} and the
+    // buoyancies of the P-region cells, the moduli of the owned cell
+    float td[2][4] = {};
+    tau4(g, Fi, cells, i, k, td[0]);
+    if (hd) tau4(g, Fi, cells, di, dk, td[1]);
+    const VelIn V0 = vel_in(S, Fi, rho, cells, i, k);
+    const VelIn V1 = hp ? vel_in(S, Fi, rho, cells, pi, pk) : VelIn{0.f, 0.f, 0.f, 0.f};
+    const long long m = S.model_off + (long long)i * S.model_ld + k;
+    const int k1 = k + 1 < NZ ? k + 1 : NZ - 1;
+    float l = 0.f, u = 0.f, muS = 0.f;
+    if (ocell) {
+        l = lam[m];
+        u = mu[m];
+        if (i >= 1) {
+            const long long mm = m - S.model_ld;
+            muS = harm4(mu[mm], u, mu[mm - k + k1], mu[m - k + k1]);
+        }
+    }
+    {
+        const int e0 = ((tid >> 6) + 4) * DW + (tid & 63) + 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            Ls[q][e0] = td[0][q];
+            if (hd) Ls[q][ed] = td[1][q];
+        }
+    }
     __syncthreads();
     const View trr{Ls[0], i0 - 4, k0 - 4, DW}, ttt{Ls[1], i0 - 4, k0 - 4, DW},
         trz{Ls[2], i0 - 4, k0 - 4, DW}, tzz{Ls[3], i0 - 4, k0 - 4, DW};
 
-    // ---- velocities on the P-region (rows >= 0 inside the grid)
-    for (int e = threadIdx.x; e < PN; e += blockDim.x) {
-        const int i = i0 - 2 + e / PW, k = k0 - 2 + e % PW;
-        float vrn = 0.f, vzn = 0.f;
-        if (i >= 0 && i < NR && k >= 0 && k < NZ) {
-            const bool own = owned(i, k, i0, k0, NR, NZ);
-            const long long c = (long long)i * NZ + k;
-            const long long m = S.model_off + (long long)i * S.model_ld + k;
-            const bool zp = k < pz || k >= NZ - pz;
-            const int kk = zp ? (k < pz ? k : k - (NZ - 2 * pz)) : 0;
-            if (i >= 1) {  // v_r at R(i, k)
-                float Dr = (C1 * (trr(i, k) - trr(i - 1, k)) +
-                            C2 * (trr(i + 1, k) - trr(i - 2, k))) * idr;
-                float Dz = (C1 * (trz(i, k) - trz(i, k - 1)) +
-                            C2 * (trz(i, k + 1) - trz(i, k - 2))) * idz;
-                auto d = [&](int ii) { return trr(ii, k) - ttt(ii, k); };
-                const float hoop = (G1 * (d(i) + d(i - 1)) + G2 * (d(i + 1) + d(i - 2))) / (i * dr);
-                if (i >= nr) {  // A
-                    const long long q = oPR + (long long)(i - nr) * NZ + k;
-                    const float psi = prt[NR + i] * Fi[q] + prt[i] * Dr;
-                    if (own) Fo[q] = psi;
-                    Dr += psi;
-                }
-                if (zp) {  // B
-                    const long long q = oPZ + (long long)i * (2 * pz) + kk;
-                    const float psi = pzt[NZ + k] * Fi[q] + pzt[k] * Dz;
-                    if (own) Fo[q] = psi;
-                    Dz += psi;
-                }
-                const float bR = 2.0f / (rho[m - S.model_ld] + rho[m]);
-                vrn = Fi[c] + dt * bR * (Dr + Dz + hoop);
+    // ---- velocities on the P-region (rows >= 0 inside the grid): the owned
+    // cell, then the halo cell; only the owned one is stored
+    auto velocity = [&](int i, int k, const VelIn& V, bool own, float& vrn, float& vzn) {
+        vrn = vzn = 0.f;
+        if (!(i >= 0 && i < NR && k >= 0 && k < NZ)) return;
+        const long long c = (long long)i * NZ + k;
+        const bool zp = k < pz || k >= NZ - pz;
+        const int kk = zp ? (k < pz ? k : k - (NZ - 2 * pz)) : 0;
+        if (i >= 1) {  // v_r at R(i, k)
+            float Dr = (C1 * (trr(i, k) - trr(i - 1, k)) +
+                        C2 * (trr(i + 1, k) - trr(i - 2, k))) * idr;
+            float Dz = (C1 * (trz(i, k) - trz(i, k - 1)) +
+                        C2 * (trz(i, k + 1) - trz(i, k - 2))) * idz;
+            auto d = [&](int ii) { return trr(ii, k) - ttt(ii, k); };
+            const float hoop = (G1 * (d(i) + d(i - 1)) + G2 * (d(i + 1) + d(i - 2))) / (i * dr);
+            if (i >= nr) {  // A
+                const long long q = oPR + (long long)(i - nr) * NZ + k;
+                const float psi = prt[NR + i] * Fi[q] + prt[i] * Dr;
+                if (own) Fo[q] = psi;
+                Dr += psi;
             }
-            {  // v_z at Z(i, k)
-                float Dr = (C1 * (trz(i + 1, k) - trz(i, k)) +
-                            C2 * (trz(i + 2, k) - trz(i - 1, k))) * idr;
-                float Dz = (C1 * (tzz(i, k + 1) - tzz(i, k)) +
-                            C2 * (tzz(i, k + 2) - tzz(i, k - 1))) * idz;
-                const float hoop = (G1 * (trz(i + 1, k) + trz(i, k)) +
-                                    G2 * (trz(i + 2, k) + trz(i - 1, k))) / ((i + 0.5f) * dr);
-                if (i >= nr) {  // C
-                    const long long q = oPR + LR + (long long)(i - nr) * NZ + k;
-                    const float psi = prt[3 * NR + i] * Fi[q] + prt[2 * NR + i] * Dr;
-                    if (own) Fo[q] = psi;
-                    Dr += psi;
-                }
-                if (zp) {  // D
-                    const long long q = oPZ + LZ + (long long)i * (2 * pz) + kk;
-                    const float psi = pzt[3 * NZ + k] * Fi[q] + pzt[2 * NZ + k] * Dz;
-                    if (own) Fo[q] = psi;
-                    Dz += psi;
-                }
-                const int k1 = k + 1 < NZ ? k + 1 : NZ - 1;
-                const float bZ = 2.0f / (rho[m] + rho[m - k + k1]);
-                vzn = Fi[cells + c] + dt * bZ * (Dr + Dz + hoop);
+            if (zp) {  // B
+                const long long q = oPZ + (long long)i * (2 * pz) + kk;
+                const float psi = pzt[NZ + k] * Fi[q] + pzt[k] * Dz;
+                if (own) Fo[q] = psi;
+                Dz += psi;
             }
-            if (own) {
-                if (i >= 1) Fo[c] = vrn;
-                Fo[cells + c] = vzn;
-                if (hist) {
-                    hist[S.cell_off + c] = vrn;
-                    hist[cells_total + S.cell_off + c] = vzn;
-                }
+            vrn = V.vr + dt * V.bR * (Dr + Dz + hoop);
+        }
+        {  // v_z at Z(i, k)
+            float Dr = (C1 * (trz(i + 1, k) - trz(i, k)) +
+                        C2 * (trz(i + 2, k) - trz(i - 1, k))) * idr;
+            float Dz = (C1 * (tzz(i, k + 1) - tzz(i, k)) +
+                        C2 * (tzz(i, k + 2) - tzz(i, k - 1))) * idz;
+            const float hoop = (G1 * (trz(i + 1, k) + trz(i, k)) +
+                                G2 * (trz(i + 2, k) + trz(i - 1, k))) / ((i + 0.5f) * dr);
+            if (i >= nr) {  // C
+                const long long q = oPR + LR + (long long)(i - nr) * NZ + k;
+                const float psi = prt[3 * NR + i] * Fi[q] + prt[2 * NR + i] * Dr;
+                if (own) Fo[q] = psi;
+                Dr += psi;
+            }
+            if (zp) {  // D
+                const long long q = oPZ + LZ + (long long)i * (2 * pz) + kk;
+                const float psi = pzt[3 * NZ + k] * Fi[q] + pzt[2 * NZ + k] * Dz;
+                if (own) Fo[q] = psi;
+                Dz += psi;
+            }
+            vzn = V.vz + dt * V.bZ * (Dr + Dz + hoop);
+        }
+        if (own) {
+            if (i >= 1) Fo[c] = vrn;
+            Fo[cells + c] = vzn;
+            if (hist) {
+                hist[S.cell_off + c] = vrn;
+                hist[cells_total + S.cell_off + c] = vzn;
             }
         }
-        Lv[0][e] = vrn;
-        Lv[1][e] = vzn;
+    };
+    {
+        float a, b;
+        velocity(i, k, V0, ocell, a, b);
+        const int e0 = ((tid >> 6) + 2) * PW + (tid & 63) + 2;
+        Lv[0][e0] = a;
+        Lv[1][e0] = b;
+        if (hp) {
+            velocity(pi, pk, V1, false, a, b);
+            Lv[0][ep] = a;
+            Lv[1][ep] = b;
+        }
     }
     __syncthreads();
     // the mirror rows below the axis: v_r odd, v_z even (uniform: i0 is the
     // workgroup's)
     if (i0 == 0) {
-        for (int e = threadIdx.x; e < 2 * PW; e += blockDim.x) {
+        for (int e = tid; e < 2 * PW; e += TK * TI) {
             const int r = e / PW, q = e % PW;  // P-region row r is grid row r - 2
-            const int i = r - 2;
-            Lv[0][r * PW + q] = -Lv[0][(-i + 2) * PW + q];
-            Lv[1][r * PW + q] = Lv[1][(-1 - i + 2) * PW + q];
+            const int im = r - 2;
+            Lv[0][r * PW + q] = -Lv[0][(-im + 2) * PW + q];
+            Lv[1][r * PW + q] = Lv[1][(-1 - im + 2) * PW + q];
         }
         __syncthreads();
     }
-    const int i = i0 + (int)(threadIdx.x >> 6), k = k0 + (int)(threadIdx.x & 63);
-    if (!(i < NR && k < NZ)) return;
+    if (!ocell) return;
     const View vr{Lv[0], i0 - 2, k0 - 2, PW}, vz{Lv[1], i0 - 2, k0 - 2, PW};
     const long long c = (long long)i * NZ + k;
-    const long long m = S.model_off + (long long)i * S.model_ld + k;
     const bool zp = k < pz || k >= NZ - pz;
     const int kk = zp ? (k < pz ? k : k - (NZ - 2 * pz)) : 0;
 
@@ -274,7 +358,6 @@ k_fwd4(const ShotDev* __restrict__ shots, const int* __restrict__ tile_start, in
         Fo[q] = psi;
         ezz += psi;
     }
-    const float l = lam[m], u = mu[m];
     const float tr = err + ett + ezz;
     float nrr = trr(i, k) + dt * (l * tr + 2.0f * u * err);
     float ntt = ttt(i, k) + dt * (l * tr + 2.0f * u * ett);
@@ -308,9 +391,6 @@ k_fwd4(const ShotDev* __restrict__ shots, const int* __restrict__ tile_start, in
             Fo[q] = psi;
             er += psi;
         }
-        const int k1 = k + 1 < NZ ? k + 1 : NZ - 1;
-        const long long mm = m - S.model_ld;
-        const float muS = harm4(mu[mm], u, mu[mm - k + k1], mu[m - k + k1]);
         Fo[5 * cells + c] = trz(i, k) + dt * muS * (ez + er);
     }
 }
@@ -460,6 +540,33 @@ struct Gather {
 enum { D_ERR = 0, D_ETT, D_EZZ, D_EZ, D_ER, ND };
 enum { P_UR = 0, P_HR, P_DZR, P_ZR, P_ZH, P_DZZ, NP };
 
+// What the transposed velocity update at (i, k) reads from memory besides the
+// drivers: the adjoint velocities and dt times the buoyancies at the R and Z
+// nodes (zero off the grid, and the R terms on the axis).
+struct AdjVelIn {
+    float ar, az, fR, fZ;
+};
+
+__device__ inline AdjVelIn adj_vel_in(const ShotDev& S, const float* __restrict__ A,
+                                      const float* __restrict__ rho, long long cells, int i, int k)
+{
+    AdjVelIn V{0.f, 0.f, 0.f, 0.f};
+    const int NR = S.NR, NZ = S.NZ;
+    const float dt = S.dt;
+    if (i >= 0 && i < NR && k >= 0 && k < NZ) {
+        const long long c = (long long)i * NZ + k;
+        const long long m = S.model_off + (long long)i * S.model_ld + k;
+        const int k1 = k + 1 < NZ ? k + 1 : NZ - 1;
+        V.az = A[cells + c];
+        V.fZ = dt * 2.0f / (rho[m] + rho[m - k + k1]);
+        if (i >= 1) {
+            V.ar = A[c];
+            V.fR = dt * 2.0f / (rho[m - S.model_ld] + rho[m]);
+        }
+    }
+    return V;
+}
+
 __global__ void __launch_bounds__(TK * TI)
 k_adj4(const ShotDev* __restrict__ shots, const int* __restrict__ tile_start, int nshot, int n,
        const float* __restrict__ lam, const float* __restrict__ mu,
@@ -476,103 +583,147 @@ k_adj4(const ShotDev* __restrict__ shots, const int* __restrict__ tile_start, in
     const float* __restrict__ Ai = ain + S.ast_off;
     float* __restrict__ Ao = aout + S.ast_off;
     const long long LR = S.psir_len, LZ = S.psiz_len, oPR = 6 * cells, oPZ = oPR + 5 * LR;
+    const int tid = (int)threadIdx.x;
+    // this thread's owned cell, and its halo cell of each region (if any)
+    const int i = i0 + (tid >> 6), k = k0 + (tid & 63);
+    const bool ocell = i < NR && k < NZ;
+    const bool hd = tid < NHD, hp = tid < NHP;
+    const int ed = d_halo(hd ? tid : 0), ep = p_halo(hp ? tid : 0);
+    const int di = i0 - 4 + ed / DW, dk = k0 - 4 + ed % DW;
+    const int pi = i0 - 2 + ep / PW, pk = k0 - 2 + ep % PW;
+    const int e0d = ((tid >> 6) + 4) * DW + (tid & 63) + 4;
+    const int e0p = ((tid >> 6) + 2) * PW + (tid & 63) + 2;
 
-    // ---- drivers of the transposed stress update on the D-region
-    for (int e = threadIdx.x; e < DN; e += blockDim.x) {
-        const int i = i0 - 4 + e / DW, k = k0 - 4 + e % DW;
-        float d[ND] = {0.f, 0.f, 0.f, 0.f, 0.f};
-        if (i >= 0 && i < NR && k >= 0 && k < NZ) {
-            const AdjPoint P = adj_point(S, i, k, n, lam, mu, rec_k, resid, prt, pzt, Ai);
-            d[D_ERR] = P.Err;
-            d[D_ETT] = P.Ett;
-            d[D_EZZ] = P.Ezz;
-            d[D_EZ] = P.Ez;
-            d[D_ER] = P.Er;
-        }
-#pragma unroll
-        for (int q = 0; q < ND; ++q) Ld[q][e] = d[q];
+    // ---- every load that does not depend on this step's LDS stages, issued
+    // up front.  The owned cell's adjoint point is kept to the end; of the
+    // halo cell only its drivers are needed.
+    AdjPoint P{};
+    if (ocell) P = adj_point(S, i, k, n, lam, mu, rec_k, resid, prt, pzt, Ai);
+    float dh[ND] = {};
+    if (hd && di >= 0 && di < NR && dk >= 0 && dk < NZ) {
+        const AdjPoint Q = adj_point(S, di, dk, n, lam, mu, rec_k, resid, prt, pzt, Ai);
+        dh[D_ERR] = Q.Err;
+        dh[D_ETT] = Q.Ett;
+        dh[D_EZZ] = Q.Ezz;
+        dh[D_EZ] = Q.Ez;
+        dh[D_ER] = Q.Er;
     }
-    stage<ODD>(Lh[0], g, hist + S.cell_off, i0 - 2, k0 - 2, PH, PW);
-    stage<EVEN>(Lh[1], g, hist + cells_total + S.cell_off, i0 - 2, k0 - 2, PH, PW);
+    // the stored v^{n+1/2} on the P-region: v_r odd, v_z even across the axis
+    const float* __restrict__ hr = hist + S.cell_off;
+    const float* __restrict__ hz = hist + cells_total + S.cell_off;
+    const float h0r = g.odd(hr, i, k), h0z = g.even(hz, i, k);
+    float h1r = 0.f, h1z = 0.f;
+    if (hp) {
+        h1r = g.odd(hr, pi, pk);
+        h1z = g.even(hz, pi, pk);
+    }
+    const AdjVelIn V0 = adj_vel_in(S, Ai, rho, cells, i, k);
+    const AdjVelIn V1 = hp ? adj_vel_in(S, Ai, rho, cells, pi, pk) : AdjVelIn{0.f, 0.f, 0.f, 0.f};
+    const long long c = (long long)i * NZ + k;
+    float* ga = acc + S.cell_off + c;
+    float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
+    if (ocell) {
+        g0 = ga[0];
+        g1 = ga[cells_total];
+        g3 = ga[3 * cells_total];
+        if (i >= 1) g2 = ga[2 * cells_total];
+    }
+    Ld[D_ERR][e0d] = P.Err;
+    Ld[D_ETT][e0d] = P.Ett;
+    Ld[D_EZZ][e0d] = P.Ezz;
+    Ld[D_EZ][e0d] = P.Ez;
+    Ld[D_ER][e0d] = P.Er;
+    Lh[0][e0p] = h0r;
+    Lh[1][e0p] = h0z;
+    if (hd) {
+#pragma unroll
+        for (int q = 0; q < ND; ++q) Ld[q][ed] = dh[q];
+    }
+    if (hp) {
+        Lh[0][ep] = h1r;
+        Lh[1][ep] = h1z;
+    }
     __syncthreads();
     const View Err{Ld[D_ERR], i0 - 4, k0 - 4, DW}, Ett{Ld[D_ETT], i0 - 4, k0 - 4, DW},
         Ezz{Ld[D_EZZ], i0 - 4, k0 - 4, DW}, Ez{Ld[D_EZ], i0 - 4, k0 - 4, DW},
         Er{Ld[D_ER], i0 - 4, k0 - 4, DW};
 
     // ---- adjoint velocities and the products of the transposed velocity
-    // update on the P-region
-    for (int e = threadIdx.x; e < PN; e += blockDim.x) {
-        const int i = i0 - 2 + e / PW, k = k0 - 2 + e % PW;
-        float p[NP] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if (i >= 0 && i < NR && k >= 0 && k < NZ) {
-            const bool own = owned(i, k, i0, k0, NR, NZ);
-            const long long c = (long long)i * NZ + k;
-            const long long m = S.model_off + (long long)i * S.model_ld + k;
-            const bool zp = k < pz || k >= NZ - pz;
-            const int kk = zp ? (k < pz ? k : k - (NZ - 2 * pz)) : 0;
-            // a_v_r at R(i, k), i >= 1: the stress update read v_r through e_rr
-            // (C, half output), e_tt (C, I / r) and e_z (S, axial half output)
-            if (i >= 1) {
-                auto q = [&](int ii) { return Ett.at(ii, k) * (1.0f / ((ii + 0.5f) * dr)); };
-                float it = G1 * (q(i - 1) + q(i)) + G2 * (q(i - 2) + q(i + 1));
-                if (i == 1) it -= G2 * q(0);  // mirror of row -1
-                const float avr = Ai[c] + Gather::Dhi_r_odd(Err, i, k) * idr + it +
-                                  Gather::Dhi_z(Ez, i, k) * idz;
-                if (own) Ao[c] = avr;
-                const float W1 = dt * 2.0f / (rho[m - S.model_ld] + rho[m]) * avr;
-                float aDr = W1, aDz = W1;
-                if (i >= nr) {  // A-bar
-                    const long long qq = oPR + (long long)(i - nr) * NZ + k;
-                    const float v = Ai[qq] + W1;
-                    if (own) Ao[qq] = prt[NR + i] * v;
-                    aDr += prt[i] * v;
-                }
-                if (zp) {  // B-bar
-                    const long long qq = oPZ + (long long)i * (2 * pz) + kk;
-                    const float v = Ai[qq] + W1;
-                    if (own) Ao[qq] = pzt[NZ + k] * v;
-                    aDz += pzt[k] * v;
-                }
-                p[P_UR] = aDr;
-                p[P_HR] = W1 / (i * dr);
-                p[P_DZR] = aDz;
-            }
-            // a_v_z at Z(i, k): read through e_zz (C, axial integer output)
-            // and e_r (S, radial integer output)
-            const float avz = Ai[cells + c] + Gather::Dlo_z(Ezz, i, k) * idz +
-                              Gather::Dlo_r_even(Er, i, k) * idr;
-            if (own) Ao[cells + c] = avz;
-            const int k1 = k + 1 < NZ ? k + 1 : NZ - 1;
-            const float W2 = dt * 2.0f / (rho[m] + rho[m - k + k1]) * avz;
-            float aDr = W2, aDz = W2;
-            if (i >= nr) {  // C-bar
-                const long long qq = oPR + LR + (long long)(i - nr) * NZ + k;
-                const float v = Ai[qq] + W2;
-                if (own) Ao[qq] = prt[3 * NR + i] * v;
-                aDr += prt[2 * NR + i] * v;
-            }
-            if (zp) {  // D-bar
-                const long long qq = oPZ + LZ + (long long)i * (2 * pz) + kk;
-                const float v = Ai[qq] + W2;
-                if (own) Ao[qq] = pzt[3 * NZ + k] * v;
-                aDz += pzt[2 * NZ + k] * v;
-            }
-            p[P_ZR] = aDr;
-            p[P_ZH] = W2 / ((i + 0.5f) * dr);
-            p[P_DZZ] = aDz;
-        }
+    // update on the P-region: the owned cell (stored), then the halo cell
+    auto products = [&](int i, int k, const AdjVelIn& V, bool own, float* p) {
 #pragma unroll
-        for (int q = 0; q < NP; ++q) Lp[q][e] = p[q];
+        for (int q = 0; q < NP; ++q) p[q] = 0.f;
+        if (!(i >= 0 && i < NR && k >= 0 && k < NZ)) return;
+        const long long c = (long long)i * NZ + k;
+        const bool zp = k < pz || k >= NZ - pz;
+        const int kk = zp ? (k < pz ? k : k - (NZ - 2 * pz)) : 0;
+        // a_v_r at R(i, k), i >= 1: the stress update read v_r through e_rr
+        // (C, half output), e_tt (C, I / r) and e_z (S, axial half output)
+        if (i >= 1) {
+            auto q = [&](int ii) { return Ett.at(ii, k) * (1.0f / ((ii + 0.5f) * dr)); };
+            float it = G1 * (q(i - 1) + q(i)) + G2 * (q(i - 2) + q(i + 1));
+            if (i == 1) it -= G2 * q(0);  // mirror of row -1
+            const float avr = V.ar + Gather::Dhi_r_odd(Err, i, k) * idr + it +
+                              Gather::Dhi_z(Ez, i, k) * idz;
+            if (own) Ao[c] = avr;
+            const float W1 = V.fR * avr;
+            float aDr = W1, aDz = W1;
+            if (i >= nr) {  // A-bar
+                const long long qq = oPR + (long long)(i - nr) * NZ + k;
+                const float v = Ai[qq] + W1;
+                if (own) Ao[qq] = prt[NR + i] * v;
+                aDr += prt[i] * v;
+            }
+            if (zp) {  // B-bar
+                const long long qq = oPZ + (long long)i * (2 * pz) + kk;
+                const float v = Ai[qq] + W1;
+                if (own) Ao[qq] = pzt[NZ + k] * v;
+                aDz += pzt[k] * v;
+            }
+            p[P_UR] = aDr;
+            p[P_HR] = W1 / (i * dr);
+            p[P_DZR] = aDz;
+        }
+        // a_v_z at Z(i, k): read through e_zz (C, axial integer output)
+        // and e_r (S, radial integer output)
+        const float avz = V.az + Gather::Dlo_z(Ezz, i, k) * idz +
+                          Gather::Dlo_r_even(Er, i, k) * idr;
+        if (own) Ao[cells + c] = avz;
+        const float W2 = V.fZ * avz;
+        float aDr = W2, aDz = W2;
+        if (i >= nr) {  // C-bar
+            const long long qq = oPR + LR + (long long)(i - nr) * NZ + k;
+            const float v = Ai[qq] + W2;
+            if (own) Ao[qq] = prt[3 * NR + i] * v;
+            aDr += prt[2 * NR + i] * v;
+        }
+        if (zp) {  // D-bar
+            const long long qq = oPZ + LZ + (long long)i * (2 * pz) + kk;
+            const float v = Ai[qq] + W2;
+            if (own) Ao[qq] = pzt[3 * NZ + k] * v;
+            aDz += pzt[2 * NZ + k] * v;
+        }
+        p[P_ZR] = aDr;
+        p[P_ZH] = W2 / ((i + 0.5f) * dr);
+        p[P_DZZ] = aDz;
+    };
+    {
+        float p[NP];
+        products(i, k, V0, ocell, p);
+#pragma unroll
+        for (int q = 0; q < NP; ++q) Lp[q][e0p] = p[q];
+        if (hp) {
+            products(pi, pk, V1, false, p);
+#pragma unroll
+            for (int q = 0; q < NP; ++q) Lp[q][ep] = p[q];
+        }
     }
     __syncthreads();
 
     // ---- the owned cell: adjoint stresses, PML memories, Eq. 7-8
-    const int i = i0 + (int)(threadIdx.x >> 6), k = k0 + (int)(threadIdx.x & 63);
-    if (!(i < NR && k < NZ)) return;
-    const long long c = (long long)i * NZ + k;
+    if (!ocell) return;
     const bool zp = k < pz || k >= NZ - pz;
     const int kk = zp ? (k < pz ? k : k - (NZ - 2 * pz)) : 0;
-    const AdjPoint P = adj_point(S, i, k, n, lam, mu, rec_k, resid, prt, pzt, Ai);
     if (i >= nr) {
         const long long q = oPR + (long long)(i - nr) * NZ + k;
         Ao[q + 2 * LR] = P.pTr;
@@ -613,14 +764,13 @@ k_adj4(const ShotDev* __restrict__ shots, const int* __restrict__ tile_start, in
     const float dgm = 2.0f * dt * (err * P.trr + ett * P.ttt + ezz * P.tzz) +
                       2.0f * (P.a_rh * err * P.pRr + P.a_zi * ezz * P.pZz);
     const float ur = 0.5f * (vr0 + vr1), uz = 0.5f * (vzm + vz0);
-    float* ga = acc + S.cell_off + c;
-    ga[0] += dgl;
-    ga[cells_total] += dgm;
-    ga[3 * cells_total] += dt * (ur * ur + uz * uz);
+    ga[0] = g0 + dgl;
+    ga[cells_total] = g1 + dgm;
+    ga[3 * cells_total] = g3 + dt * (ur * ur + uz * uz);
     if (i >= 1) {
         const float ez = (C1 * (vrh(i, k + 1) - vr0) + C2 * (vrh(i, k + 2) - vrh(i, k - 1))) * idz;
         const float er = (C1 * (vz0 - vzh(i - 1, k)) + C2 * (vzh(i + 1, k) - vzh(i - 2, k))) * idr;
-        ga[2 * cells_total] += dt * (ez + er) * P.trz + P.a_zh * ez * P.pG + P.a_ri * er * P.pH;
+        ga[2 * cells_total] = g2 + (dt * (ez + er) * P.trz + P.a_zh * ez * P.pG + P.a_ri * er * P.pH);
     }
 }
 
