@@ -71,7 +71,7 @@ def _load():
         lib.orc_propagate_asm.argtypes = [G, C.c_int32, _D, _D, _D, _D, C.c_int32, C.c_int32]
         lib.orc_propagate_asm.restype = C.c_int
         lib.orc_gradient_asm.argtypes = [G, C.c_int32, _D, _D, _D, _D, _D, C.c_int32, _D, _D,
-                                         _D]
+                                         _D, _D, _D, _D]
         lib.orc_gradient_asm.restype = C.c_int
         lib.orc_source_adjoint.argtypes = [G, _D, _D, _D, _D, _D]
         lib.orc_source_adjoint.restype = C.c_int
@@ -209,26 +209,25 @@ def gradient(g: Geom, lam, mu, rho, wavelet, resid, seg=200, density=False, hess
     """Eq. 6-8 via the exact discrete transpose; returns (glam, gmu, illum),
     then dJ/drho with density=True, then (H_lambda, H_mu), the
     virtual-source pseudo-Hessian diagonal, with hessian=True.  order=4, or
-    assembled=True, uses the assembled operators (modulus gradients only)."""
+    assembled=True, uses the assembled operators."""
     shp = (g.NR, g.NZ)
     lam, mu, rho = _f64(lam, shp), _f64(mu, shp), _f64(rho, shp)
     w, r = _f64(wavelet), _f64(resid)
     gc, rk = g._c()
     assert r.size == len(rk) * g.nt
     gl, gm, il = np.zeros(shp), np.zeros(shp), np.zeros(shp)
-    if order != 2 or assembled:
-        if density or hessian:
-            raise ValueError("the assembled operators give the modulus gradients only")
-        rc = _load().orc_gradient_asm(C.byref(gc), int(order), _p(lam), _p(mu), _p(rho), _p(w),
-                                      _p(r), int(seg), _p(gl), _p(gm), _p(il))
-        _check(rc, "gradient_asm")
-        return gl, gm, il
     gr = np.zeros(shp) if density else None
     hl, hm = (np.zeros(shp), np.zeros(shp)) if hessian else (None, None)
     opt = lambda a: _p(a) if a is not None else None  # noqa: E731
-    rc = _load().orc_gradient(C.byref(gc), _p(lam), _p(mu), _p(rho), _p(w), _p(r),
-                              int(seg), _p(gl), _p(gm), _p(il), opt(gr), opt(hl), opt(hm))
-    _check(rc, "gradient")
+    if order != 2 or assembled:
+        rc = _load().orc_gradient_asm(C.byref(gc), int(order), _p(lam), _p(mu), _p(rho), _p(w),
+                                      _p(r), int(seg), _p(gl), _p(gm), _p(il), opt(gr),
+                                      opt(hl), opt(hm))
+        _check(rc, "gradient_asm")
+    else:
+        rc = _load().orc_gradient(C.byref(gc), _p(lam), _p(mu), _p(rho), _p(w), _p(r),
+                                  int(seg), _p(gl), _p(gm), _p(il), opt(gr), opt(hl), opt(hm))
+        _check(rc, "gradient")
     out = (gl, gm, il)
     if density:
         out += (gr,)

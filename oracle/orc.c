@@ -557,6 +557,30 @@ static void inject_residual(const orc_geom *g, int NZ, state *a, const double *r
     }
 }
 
+/* dJ/drho from dJ/db at the v_r and v_z nodes (gb: 2 N).  b_R = 2/(rho[i-1,k]
+ * + rho[i,k]) and b_Z = 2/(rho[i,k] + rho[i,k1]): d b / d rho = -b^2/2 for
+ * each of the two cells (k1 = k on the top row counts twice). */
+static void rho_chain(const grid *Gp, const double *gb, double *grho)
+{
+    const grid G = *Gp;
+    const int NR = G.NR, NZ = G.NZ;
+    const size_t N = (size_t)NR * NZ;
+    memset(grho, 0, N * sizeof(double));
+    for (int i = 1; i < NR; ++i)
+        for (int k = 0; k < NZ; ++k) {
+            double b = buoy_R(&G, i, k), t = -0.5 * b * b * gb[IX(i, k)];
+            grho[IX(i - 1, k)] += t;
+            grho[IX(i, k)] += t;
+        }
+    for (int i = 0; i < NR; ++i)
+        for (int k = 0; k < NZ; ++k) {
+            int k1 = k + 1 < NZ ? k + 1 : NZ - 1;
+            double b = buoy_Z(&G, i, k), t = -0.5 * b * b * gb[N + IX(i, k)];
+            grho[IX(i, k)] += t;
+            grho[IX(i, k1)] += t;
+        }
+}
+
 int orc_gradient(const orc_geom *g, const double *lam, const double *mu, const double *rho,
                  const double *wavelet, const double *resid, int32_t seg, double *glam,
                  double *gmu, double *illum, double *grho, double *hl, double *hm)
@@ -649,25 +673,7 @@ int orc_gradient(const orc_geom *g, const double *lam, const double *mu, const d
             adj_velocity_phase(&G, &a);
         }
     }
-    if (grho) {
-        /* b_R = 2/(rho[i-1,k] + rho[i,k]) and b_Z = 2/(rho[i,k] + rho[i,k1]):
-         * d b / d rho = -b^2/2 for each of the two cells (k1 = k on the top row
-         * counts twice) */
-        memset(grho, 0, N * sizeof(double));
-        for (int i = 1; i < NR; ++i)
-            for (int k = 0; k < NZ; ++k) {
-                double b = buoy_R(&G, i, k), t = -0.5 * b * b * gb[IX(i, k)];
-                grho[IX(i - 1, k)] += t;
-                grho[IX(i, k)] += t;
-            }
-        for (int i = 0; i < NR; ++i)
-            for (int k = 0; k < NZ; ++k) {
-                int k1 = k + 1 < NZ ? k + 1 : NZ - 1;
-                double b = buoy_Z(&G, i, k), t = -0.5 * b * b * gb[N + IX(i, k)];
-                grho[IX(i, k)] += t;
-                grho[IX(i, k1)] += t;
-            }
-    }
+    if (grho) rho_chain(&G, gb, grho);
     fold_mu_s(&G, gmuS, gmu);
     free(ckpt); free(fmem); free(amem); free(eps); free(gmuS); free(dvb); free(gb);
     grid_free(&G);
@@ -1043,6 +1049,9 @@ static void pml_pair(const asm_ctx *A, const lform *D, int on, double a, double 
 
 typedef struct {
     spm V, S, E; /* E: 4 N strain rows (e_rr', e_tt, e_zz', e_z' + e_r') over the state after V */
+    spm B;       /* B: 2 N rows d v_r / d b_R, d v_z / d b_Z over the state before V */
+    spm H;       /* H: 4 N plain strain rows (no PML stretching: e_rr, e_tt, e_zz,
+                    e_z + e_r) over the state after V */
 } asm_ops;
 
 static void ops_free(asm_ops *O)
@@ -1050,6 +1059,8 @@ static void ops_free(asm_ops *O)
     spm_free(&O->V);
     spm_free(&O->S);
     spm_free(&O->E);
+    spm_free(&O->B);
+    spm_free(&O->H);
 }
 
 static int ops_build(const grid *G, int order, asm_ops *O)
@@ -1071,7 +1082,9 @@ static int ops_build(const grid *G, int order, asm_ops *O)
     O->V.ptr = calloc(P_N * N + 1, sizeof(size_t));
     O->S.ptr = calloc(P_N * N + 1, sizeof(size_t));
     O->E.ptr = calloc(4 * N + 1, sizeof(size_t));
-    if (!O->V.ptr || !O->S.ptr || !O->E.ptr) {
+    O->B.ptr = calloc(2 * N + 1, sizeof(size_t));
+    O->H.ptr = calloc(4 * N + 1, sizeof(size_t));
+    if (!O->V.ptr || !O->S.ptr || !O->E.ptr || !O->B.ptr || !O->H.ptr) {
         ops_free(O);
         return -1;
     }
@@ -1079,8 +1092,9 @@ static int ops_build(const grid *G, int order, asm_ops *O)
      * rows are collected per node first (some nodes define several planes) */
     lform *rowV = calloc(P_N * N, sizeof(lform)), *rowS = calloc(P_N * N, sizeof(lform));
     lform *rowE = calloc(4 * N, sizeof(lform));
-    if (!rowV || !rowS || !rowE) {
-        free(rowV); free(rowS); free(rowE);
+    lform *rowB = calloc(2 * N, sizeof(lform)), *rowH = calloc(4 * N, sizeof(lform));
+    if (!rowV || !rowS || !rowE || !rowB || !rowH) {
+        free(rowV); free(rowS); free(rowE); free(rowB); free(rowH);
         ops_free(O);
         return -1;
     }
@@ -1105,6 +1119,7 @@ static int ops_build(const grid *G, int order, asm_ops *O)
                 lf_I(&eff, &A, P_TRR, i, k, i - 1, 1.0 / ri);
                 lf_I(&eff, &A, P_TTT, i, k, i - 1, -1.0 / ri);
                 lf_scaled(&vr, &eff, dt * bR);
+                lf_scaled(ROW(rowB, 0, c), &eff, dt);
                 *ROW(rowV, P_VR, c) = vr;
                 free(Dr.col); free(Dr.val); free(Dz.col); free(Dz.val);
                 free(eff.col); free(eff.val);
@@ -1126,6 +1141,7 @@ static int ops_build(const grid *G, int order, asm_ops *O)
                          ROW(rowV, P_PD, c));
                 lf_I(&eff, &A, P_TRZ, i, k, i, 1.0 / rh);
                 lf_scaled(&vz, &eff, dt * bZ);
+                lf_scaled(ROW(rowB, 1, c), &eff, dt);
                 *ROW(rowV, P_VZ, c) = vz;
                 free(Dr.col); free(Dr.val); free(Dz.col); free(Dz.val);
                 free(eff.col); free(eff.val);
@@ -1139,6 +1155,8 @@ static int ops_build(const grid *G, int order, asm_ops *O)
                 lform Dr = {0}, Dz = {0}, err = {0}, ett = {0}, ezz = {0};
                 lf_D(&Dr, &A, P_VR, 1, i, k, i, 1.0);
                 lf_D(&Dz, &A, P_VZ, 0, i, k, k - 1, 1.0);
+                lf_scaled(ROW(rowH, 0, c), &Dr, 1.0);
+                lf_scaled(ROW(rowH, 2, c), &Dz, 1.0);
                 const double rh = (i + 0.5) * dr;
                 pml_pair(&A, &Dr, G->onr_h[i], G->ar_h[i], G->br_h[i], COL(P_PE, c), &err,
                          ROW(rowS, P_PE, c));
@@ -1158,6 +1176,7 @@ static int ops_build(const grid *G, int order, asm_ops *O)
                 }
                 lf_scaled(ROW(rowE, 0, c), &err, 1.0);
                 lf_scaled(ROW(rowE, 1, c), &ett, 1.0);
+                lf_scaled(ROW(rowH, 1, c), &ett, 1.0);
                 lf_scaled(ROW(rowE, 2, c), &ezz, 1.0);
                 free(Dr.col); free(Dr.val); free(Dz.col); free(Dz.val);
                 free(err.col); free(err.val); free(ett.col); free(ett.val);
@@ -1168,6 +1187,8 @@ static int ops_build(const grid *G, int order, asm_ops *O)
                 lform Dz = {0}, Dr = {0}, es = {0};
                 lf_D(&Dz, &A, P_VR, 0, i, k, k, 1.0);
                 lf_D(&Dr, &A, P_VZ, 1, i, k, i - 1, 1.0);
+                lf_scaled(ROW(rowH, 3, c), &Dz, 1.0);
+                lf_scaled(ROW(rowH, 3, c), &Dr, 1.0);
                 pml_pair(&A, &Dz, G->onz_h[k], G->az_h[k], G->bz_h[k], COL(P_PG, c), &es,
                          ROW(rowS, P_PG, c));
                 pml_pair(&A, &Dr, G->onr_i[i], G->ar_i[i], G->br_i[i], COL(P_PH, c), &es,
@@ -1192,13 +1213,18 @@ static int ops_build(const grid *G, int order, asm_ops *O)
     for (size_t r = 0; r < P_N * N && !rc; ++r) rc |= spm_row(&O->V, &rowV[r]);
     for (size_t r = 0; r < P_N * N && !rc; ++r) rc |= spm_row(&O->S, &rowS[r]);
     for (size_t r = 0; r < 4 * N && !rc; ++r) rc |= spm_row(&O->E, &rowE[r]);
+    for (size_t r = 0; r < 2 * N && !rc; ++r) rc |= spm_row(&O->B, &rowB[r]);
+    for (size_t r = 0; r < 4 * N && !rc; ++r) rc |= spm_row(&O->H, &rowH[r]);
     for (size_t r = 0; r < P_N * N; ++r) {
         free(rowV[r].col); free(rowV[r].val); free(rowS[r].col); free(rowS[r].val);
     }
     for (size_t r = 0; r < 4 * N; ++r) {
-        free(rowE[r].col); free(rowE[r].val);
+        free(rowE[r].col); free(rowE[r].val); free(rowH[r].col); free(rowH[r].val);
     }
-    free(rowV); free(rowS); free(rowE);
+    for (size_t r = 0; r < 2 * N; ++r) {
+        free(rowB[r].col); free(rowB[r].val);
+    }
+    free(rowV); free(rowS); free(rowE); free(rowB); free(rowH);
 #undef ROW
 #undef COL
     if (rc) ops_free(O);
@@ -1291,7 +1317,8 @@ int orc_propagate_asm(const orc_geom *g, int32_t order, const double *lam, const
 
 int orc_gradient_asm(const orc_geom *g, int32_t order, const double *lam, const double *mu,
                      const double *rho, const double *wavelet, const double *resid,
-                     int32_t seg, double *glam, double *gmu, double *illum)
+                     int32_t seg, double *glam, double *gmu, double *illum, double *grho,
+                     double *hl, double *hm)
 {
     grid G;
     if (seg <= 0 || grid_init(&G, g, lam, mu, rho) || !geom_ok(g)) return -1;
@@ -1309,8 +1336,16 @@ int orc_gradient_asm(const orc_geom *g, int32_t order, const double *lam, const 
     double *tmp = calloc(SL, sizeof(double));
     double *eps = malloc((size_t)seg * 4 * N * sizeof(double));
     double *gmuS = calloc(N, sizeof(double));
-    if (!ckpt || !s || !a || !tmp || !eps || !gmuS) {
+    /* density: d v^{n+1/2} / d b per step of a segment (B applied to the state
+     * before the step) and dJ/db at the v_r and v_z nodes; pseudo-Hessian: the
+     * plain strain rates of v^{n+1/2} */
+    double *dvb = grho ? malloc((size_t)seg * 2 * N * sizeof(double)) : NULL;
+    double *gb = grho ? calloc(2 * N, sizeof(double)) : NULL;
+    double *hp = (hl || hm) ? malloc(4 * N * sizeof(double)) : NULL;
+    if (!ckpt || !s || !a || !tmp || !eps || !gmuS || (grho && (!dvb || !gb)) ||
+        ((hl || hm) && !hp)) {
         free(ckpt); free(s); free(a); free(tmp); free(eps); free(gmuS);
+        free(dvb); free(gb); free(hp);
         ops_free(&O);
         grid_free(&G);
         return -1;
@@ -1319,10 +1354,24 @@ int orc_gradient_asm(const orc_geom *g, int32_t order, const double *lam, const 
     memset(glam, 0, N * sizeof(double));
     memset(gmu, 0, N * sizeof(double));
     memset(illum, 0, N * sizeof(double));
+    if (hl) memset(hl, 0, N * sizeof(double));
+    if (hm) memset(hm, 0, N * sizeof(double));
     /* forward pass: checkpoints, illumination from v^{n+1/2} averaged to C nodes */
     for (int n = 0; n < nt; ++n) {
         if (n % seg == 0) memcpy(ckpt + (size_t)(n / seg) * SL, s, SL * sizeof(double));
         asm_step(&O, N, NZ, s, tmp, g->src_k, sc * wavelet[n], NULL);
+        if (hp) {
+            /* virtual sources: d(stress update)/d(modulus) applied to v^{n+1/2},
+             * with the plain strain rates of the stencil (the stress update
+             * leaves v alone, so H may read the state after the whole step) */
+            spm_apply(&O.H, s, hp);
+            for (size_t c = 0; c < N; ++c) {
+                double err = hp[c], ett = hp[N + c], ezz = hp[2 * N + c], es = hp[3 * N + c];
+                double dv = err + ett + ezz;
+                if (hl) hl[c] += dt * dt * 3.0 * dv * dv;
+                if (hm) hm[c] += dt * dt * (4.0 * (err * err + ett * ett + ezz * ezz) + es * es);
+            }
+        }
         const double *vr = s + P_VR * N, *vz = s + P_VZ * N;
         for (int i = 0; i < NR; ++i)
             for (int k = 0; k < NZ; ++k) {
@@ -1337,8 +1386,10 @@ int orc_gradient_asm(const orc_geom *g, int32_t order, const double *lam, const 
     for (int j = nseg - 1; j >= 0; --j) {
         int n0 = j * seg, n1 = n0 + seg < nt ? n0 + seg : nt;
         memcpy(s, ckpt + (size_t)j * SL, SL * sizeof(double));
-        for (int n = n0; n < n1; ++n)
+        for (int n = n0; n < n1; ++n) {
+            if (dvb) spm_apply(&O.B, s, dvb + (size_t)(n - n0) * 2 * N);
             asm_step(&O, N, NZ, s, tmp, g->src_k, sc * wavelet[n], eps + (size_t)(n - n0) * 4 * N);
+        }
         for (int n = n1 - 1; n >= n0; --n) {
             for (int q = 0; q < g->nrec; ++q) {
                 size_t c = IX(0, g->rec_k[q]);
@@ -1358,10 +1409,21 @@ int orc_gradient_asm(const orc_geom *g, int32_t order, const double *lam, const 
                 gmuS[c] += dt * e[3 * N + c] * a[P_TRZ * N + c];
             }
             asm_step_t(&O, N, a, tmp);
+            if (gb) {
+                /* tmp now holds S^T a: at the velocity rows, dJ/dv^{n+1/2};
+                 * v^{n+1/2} = v^{n-1/2} + b dv/db gives dJ/db += that times dv/db */
+                const double *d = dvb + (size_t)(n - n0) * 2 * N;
+                for (size_t c = 0; c < N; ++c) {
+                    gb[c] += tmp[P_VR * N + c] * d[c];
+                    gb[N + c] += tmp[P_VZ * N + c] * d[N + c];
+                }
+            }
         }
     }
+    if (grho) rho_chain(&G, gb, grho);
     fold_mu_s(&G, gmuS, gmu);
     free(ckpt); free(s); free(a); free(tmp); free(eps); free(gmuS);
+    free(dvb); free(gb); free(hp);
     ops_free(&O);
     grid_free(&G);
     return 0;

@@ -150,9 +150,12 @@ double orc_update(int64_t n, double *lam, double *mu, const double *rho,
  * difference and 1/r average, with the fields mirrored across the axis (even
  * at half radial positions, odd and zero on the axis at integer ones).
  * Same arguments and outputs as orc_forward, orc_propagate(_adjoint) and
- * orc_gradient (no density or pseudo-Hessian outputs).  Pinned: order 2
- * against the hand-written step, order 4 by closed forms, convergence, dot
- * products and central differences. */
+ * orc_gradient.  The density gradient takes dv/db per step from rows of its
+ * own (the velocity rows without the buoyancy); the pseudo-Hessian takes the
+ * plain strain rates of v^{n+1/2} from rows without the PML stretching.
+ * Pinned: order 2 against the hand-written step (all outputs), order 4 by
+ * closed forms, convergence, dot products, central differences (moduli and
+ * density) and the pseudo-Hessian by differencing one step. */
 int orc_forward_asm(const orc_geom *g, int32_t order, const double *lam, const double *mu,
                     const double *rho, const double *wavelet, double *traces,
                     double *final_state);
@@ -160,6 +163,7 @@ int orc_propagate_asm(const orc_geom *g, int32_t order, const double *lam, const
                       const double *rho, double *st, int32_t nsteps, int32_t adjoint);
 int orc_gradient_asm(const orc_geom *g, int32_t order, const double *lam, const double *mu,
                      const double *rho, const double *wavelet, const double *resid,
-                     int32_t seg, double *glam, double *gmu, double *illum);
+                     int32_t seg, double *glam, double *gmu, double *illum, double *grho,
+                     double *hl, double *hm);
 
 #endif

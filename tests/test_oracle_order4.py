@@ -46,7 +46,8 @@ def _fit(d, ref):
 
 def test_assembled_order2_is_the_hand_written_step():
     """Traces, final state and gradients of the assembled order-2 operators
-    equal the hand-written step to rounding, with fluid, wall and PML."""
+    equal the hand-written step to rounding, with fluid, wall and PML: the
+    modulus gradients, the illumination, dJ/drho and the pseudo-Hessian."""
     w = workloads.tiny(nr=12, nz=30, p=4, nt=200)
     sh = w.shots[0]
     g = geom(sh)
@@ -55,10 +56,16 @@ def test_assembled_order2_is_the_hand_written_step():
     da, sta = oracle.forward(g, lam, mu, rho, sh.wavelet, return_state=True, assembled=True)
     assert rel_l2(da, d) <= 1e-13 and rel_l2(sta, st) <= 1e-13
     r = np.random.default_rng(1).standard_normal(d.shape)
-    a = oracle.gradient(g, lam, mu, rho, sh.wavelet, r, seg=37)
-    b = oracle.gradient(g, lam, mu, rho, sh.wavelet, r, seg=37, assembled=True)
+    a = oracle.gradient(g, lam, mu, rho, sh.wavelet, r, seg=37, density=True, hessian=True)
+    b = oracle.gradient(g, lam, mu, rho, sh.wavelet, r, seg=37, density=True, hessian=True,
+                        assembled=True)
+    assert len(a) == len(b) == 6
     for x, y in zip(a, b):
         assert rel_l2(y, x) <= 1e-13
+    # and the extra outputs leave the others as they were
+    c = oracle.gradient(g, lam, mu, rho, sh.wavelet, r, seg=37, assembled=True)
+    for x, y in zip(b[:3], c):
+        assert np.array_equal(x, y)
 
 
 @pytest.mark.parametrize("pml,fluid", [(5, True), (0, True), (4, False)])
@@ -190,3 +197,110 @@ def test_order4_gradient_checkpoint_interval_and_single_cells():
         q[i, k] -= h
         fd = (J(p) - J(q)) / (2 * h)
         assert abs(fd - a[0][i, k]) <= 1e-6 * scale + 1e-5 * abs(fd), ((i, k), fd, a[0][i, k])
+
+
+def _rho_setup4(nr=12, nz=24, p=4, nt=150):
+    """Order-4 misfit against data from a model whose density differs from
+    the starting one."""
+    w = workloads.tiny(nr=nr, nz=nz, p=p, nt=nt)
+    sh = w.shots[0]
+    g = geom(sh)
+    lam, mu, rho = oracle_models(w, 0, "start")
+    lt, mt, rt = oracle_models(w, 0, "true")
+    rt = rt * (1.0 + 0.05 * np.random.default_rng(11).standard_normal(rt.shape))
+    dobs = oracle.forward(g, lt, mt, rt, sh.wavelet, order=4)
+
+    def J(r):
+        return oracle.misfit(oracle.forward(g, lam, mu, r, sh.wavelet, order=4), dobs)[0]
+
+    _, res = oracle.misfit(oracle.forward(g, lam, mu, rho, sh.wavelet, order=4), dobs)
+    out = oracle.gradient(g, lam, mu, rho, sh.wavelet, res, seg=37, density=True, order=4)
+    return g, rho, mu, J, out
+
+
+@pytest.mark.parametrize("region", ["formation", "fluid", "pml"])
+def test_order4_density_gradient_directional_derivative(region):
+    """dJ/drho of the fourth-order misfit against central differences along
+    random density perturbations confined to one region."""
+    g, rho, mu, J, (gl, gm, il, gr) = _rho_setup4()
+    NR, NZ = g.NR, g.NZ
+    ii, kk = np.meshgrid(np.arange(NR), np.arange(NZ), indexing="ij")
+    fluid = (mu == 0)
+    pml = (ii >= g.nr) | (kk < g.pz) | (kk >= g.pz + g.nz)
+    sel = {"formation": ~fluid & ~pml, "fluid": fluid & ~pml, "pml": pml}[region]
+    d = np.random.default_rng(6).standard_normal((NR, NZ)) * sel * rho
+    # the PML share of dJ/drho is small against J: a step of 1e-6 leaves the
+    # difference of the misfits at the level of their rounding (3e-6 relative
+    # there), so take a step of 1e-4 and the fourth-order central difference
+    # (the O(eps^2) term of the two-point one is 1e-6 in the fluid)
+    eps = 1e-4
+    fd = (8.0 * (J(rho + eps * d) - J(rho - eps * d)) -
+          (J(rho + 2 * eps * d) - J(rho - 2 * eps * d))) / (12 * eps)
+    an = float((gr * d).sum())
+    assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
+
+
+def test_order4_density_gradient_single_cells():
+    """A few single cells: the axis row, next to the wall, the clamped top
+    row and a PML corner."""
+    g, rho, mu, J, (gl, gm, il, gr) = _rho_setup4(nr=10, nz=22, p=3, nt=120)
+    scale = np.abs(gr).max()
+    for (i, k) in [(0, g.pz + 5), (4, g.pz + 9), (5, g.pz + 2), (2, g.NZ - 1),
+                   (g.NR - 1, 0)]:
+        h = 1e-6 * rho[i, k]
+        p, q = rho.copy(), rho.copy()
+        p[i, k] += h
+        q[i, k] -= h
+        fd = (J(p) - J(q)) / (2 * h)
+        assert abs(fd - gr[i, k]) <= 1e-6 * scale + 1e-5 * abs(fd), ((i, k), fd, gr[i, k])
+
+
+@pytest.mark.slow
+def test_order4_pseudo_hessian_is_the_squared_stress_update_derivative():
+    """As at order 2: for interior cells H_lambda(c) is the sum over steps of
+    the squared change of the three normal stresses at c per unit lambda(c),
+    and H_mu(c) that per unit mu(c) plus the squared change of tau_rz at the
+    node (i, k) per unit change of its harmonic-mean rigidity, measured by
+    differencing one fourth-order step of the source-driven state."""
+    w = workloads.tiny(nr=12, nz=26, p=3, nt=30, fluid=False)
+    sh = w.shots[0]
+    g = geom(sh)
+    shp = (g.NR, g.NZ)
+    lam, mu, rho = np.full(shp, 9.0e9), np.full(shp, 6.0e9), np.full(shp, 2400.0)
+    nt = g.nt
+    r = np.zeros((len(sh.rec_k), nt))
+    _, _, _, hl, hm = oracle.gradient(g, lam, mu, rho, sh.wavelet, r, seg=nt, hessian=True,
+                                      order=4)
+    H = 1e8  # the stress update is linear in the moduli
+    states = [np.zeros((14, g.NR, g.NZ))]
+    for n in range(1, nt):
+        gn = oracle.Geom(g.nr, g.nz, g.pr, g.pz, g.dr, g.dz, g.dt, n, g.f0, g.vmax, g.src_k,
+                         g.rec_k)
+        states.append(oracle.forward(gn, lam, mu, rho, sh.wavelet, return_state=True,
+                                     order=4)[1])
+    TRR, TTT, TZZ, TRZ = 2, 3, 4, 5
+    for (i, k) in [(0, g.pz + 5), (1, g.pz + 9), (5, g.pz + 12), (g.nr - 3, g.pz + g.nz - 4)]:
+        el = np.zeros(shp)
+        el[i, k] = H
+        em = np.zeros(shp)
+        em[i, k] = H
+        es = np.zeros(shp)
+        if i >= 1:
+            es[i - 1:i + 1, k:k + 2] = H
+        hl_fd = hm_fd = 0.0
+        for n in range(nt):
+            x = states[n].ravel()
+            base = oracle.propagate(g, lam, mu, rho, x, 1, order=4).reshape(-1, g.NR, g.NZ)
+            pl = oracle.propagate(g, lam + el, mu, rho, x, 1, order=4).reshape(-1, g.NR, g.NZ)
+            pm = oracle.propagate(g, lam, mu + em, rho, x, 1, order=4).reshape(-1, g.NR, g.NZ)
+            d = (pl - base) / H
+            hl_fd += sum(d[f, i, k] ** 2 for f in (TRR, TTT, TZZ))
+            d = (pm - base) / H
+            hm_fd += sum(d[f, i, k] ** 2 for f in (TRR, TTT, TZZ))
+            if i >= 1:
+                ps = oracle.propagate(g, lam, mu + es, rho, x, 1, order=4).reshape(-1, g.NR,
+                                                                                   g.NZ)
+                hm_fd += ((ps - base)[TRZ, i, k] / H) ** 2
+        assert hl[i, k] > 0 and hm[i, k] > 0
+        assert abs(hl[i, k] - hl_fd) <= 1e-6 * hl_fd, ((i, k), hl[i, k], hl_fd)
+        assert abs(hm[i, k] - hm_fd) <= 1e-6 * hm_fd, ((i, k), hm[i, k], hm_fd)
