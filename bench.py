@@ -50,8 +50,8 @@ PMC_SOURCES = ("paper_2005_00281_amd/csrc/bhfwi_tb_adj.hip",
 PMC_TRAFFIC = {
     # (kernel, tile_map, workload, sources sha256[:16]): (FETCH KiB, WRITE KiB), summed
     # over the kernels of one launch block
-    ("k_adj_tb<8, 48, 16, 0, 0> + k_adj_tb<8, 32, 16, 1, 0>", 1, "c2", "690c535ff381726a"):
-        (42706.81 + 11959.92, 22352.52 + 6724.87),
+    ("k_adj_tb<8, 48, 16, 0, 0> + k_adj_tb<8, 32, 16, 1, 0>", 1, "c2", "5abbe2d38a75b893"):
+        (42707.47 + 11952.35, 22357.83 + 6724.99),
 }
 
 

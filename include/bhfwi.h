@@ -190,9 +190,9 @@ int bhfwi_sizes(const bhfwi_ctx *ctx, bhfwi_sizes_t *out);
  * D f = [9/8 (f(+1/2) - f(-1/2)) - 1/24 (f(+3/2) - f(-3/2))] / h and
  * I f = 9/16 (f(+1/2) + f(-1/2)) - 1/16 (f(+3/2) + f(-3/2)), with the fields
  * mirrored across the axis (even at half radial positions, odd at integer
- * ones).  Applies to bhfwi_fwd_model and bhfwi_adjoint_model (modulus
- * gradients only: no density or pseudo-Hessian outputs, no autotune; one
- * step per launch).  Order 4 needs the stricter stability bound
+ * ones).  Applies to bhfwi_fwd_model and the bhfwi_adjoint_model family,
+ * the density and pseudo-Hessian outputs included (no autotune; one step per
+ * launch).  Order 4 needs the stricter stability bound
  * vmax dt sqrt(1/dr^2 + 1/dz^2) < 6/7 (BHFWI_ECFL otherwise).  Synchronises
  * the device. */
 int bhfwi_set_order(bhfwi_ctx *ctx, int32_t order);

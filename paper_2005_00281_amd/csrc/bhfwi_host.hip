@@ -425,16 +425,27 @@ void fwd4_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const fl
                        traces, hist, (long long)c->cells);
 }
 
-// Fourth-order adjoint step n fused with the correlation, in one launch.
+// Fourth-order adjoint step n fused with the correlation, in one launch;
+// acc_rho and acc_h (nullable) select the kernels that also accumulate the
+// density correlation and the pseudo-Hessian.
 void adj4_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const float* mu,
                  const float* rho, const float* resid, const float* in, float* out,
-                 const float* hist, float* acc)
+                 const float* hist, float* acc, float* acc_rho, float* acc_h)
 {
     EvScope ev(c, st, 2);
-    hipLaunchKernelGGL(bhfwi::o4::k_adj4, dim3((unsigned)c->ntile4),
-                       dim3(bhfwi::o4::TK * bhfwi::o4::TI), 0, st, c->d_shots, c->d_tile4,
-                       c->nshot, n, lam, mu, rho, c->d_rec, resid, c->d_pml_r, c->d_pml_z, in,
-                       out, hist, acc, (long long)c->cells);
+    const int xm = (acc_rho ? 1 : 0) | (acc_h ? 2 : 0);
+#define BHFWI_A4(XX)                                                                          \
+    hipLaunchKernelGGL(bhfwi::o4::k_adj4<XX>, dim3((unsigned)c->ntile4),                     \
+                       dim3(bhfwi::o4::TK * bhfwi::o4::TI), 0, st, c->d_shots, c->d_tile4,   \
+                       c->nshot, n, lam, mu, rho, c->d_rec, resid, c->d_pml_r, c->d_pml_z, in, \
+                       out, hist, acc, acc_rho, acc_h, (long long)c->cells)
+    switch (xm) {
+    case 0: BHFWI_A4(0); break;
+    case 1: BHFWI_A4(1); break;
+    case 2: BHFWI_A4(2); break;
+    default: BHFWI_A4(3); break;
+    }
+#undef BHFWI_A4
 }
 
 // Supported temporally blocked shapes: (steps T, tile rows incl. halo,
@@ -628,7 +639,7 @@ void adj_range(bhfwi_ctx* c, hipStream_t st, int n0, int n1, const float* lam, c
     if (c->order == 4) {
         for (int n = n1 - 1; n >= n0; --n, ++*m)
             adj4_launch(c, st, n, lam, mu, rho, resid, ab[*m & 1], ab[(*m + 1) & 1],
-                        hist + (int64_t)(n - n0) * hslot, acc);
+                        hist + (int64_t)(n - n0) * hslot, acc, acc_rho, acc_h);
         return;
     }
     const Shape sh = adj_shape(c);
@@ -1404,9 +1415,6 @@ int adjoint_impl(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
     bhfwi_sizes(c, &z);
     if (!lam || !mu || !rho || !wavelet || !resid || !fwd_ws || !adj_ws || !acc)
         return fail(c, BHFWI_EINVAL, "adjoint_model: null pointer");
-    if (c->order == 4 && (acc_rho || acc_h))
-        return fail(c, BHFWI_EINVAL, "adjoint_model: the fourth-order kernels give the modulus "
-                                     "gradients only");
     if (fwd_ws_bytes < z.fwd_ws_bytes || adj_ws_bytes < z.adj_ws_bytes)
         return fail(c, BHFWI_ENOMEM, "adjoint_model: workspace too small (fwd %lld/%lld, adj %lld/%lld)",
                     (long long)fwd_ws_bytes, (long long)z.fwd_ws_bytes, (long long)adj_ws_bytes,

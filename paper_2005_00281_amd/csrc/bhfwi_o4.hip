@@ -567,6 +567,12 @@ __device__ inline AdjVelIn adj_vel_in(const ShotDev& S, const float* __restrict_
     return V;
 }
 
+// X selects extra outputs as in the second-order adjoint: bit 0 the density
+// correlation (the increment of the adjoint velocity from the transposed
+// stress update times the stored v^{n+1/2}, at the R and Z nodes, into
+// acc_rho), bit 1 the virtual-source pseudo-Hessian diagonal (the plain
+// fourth-order strain rates of v^{n+1/2}, into acc_h).
+template <int X>
 __global__ void __launch_bounds__(TK * TI)
 k_adj4(const ShotDev* __restrict__ shots, const int* __restrict__ tile_start, int nshot, int n,
        const float* __restrict__ lam, const float* __restrict__ mu,
@@ -574,8 +580,9 @@ k_adj4(const ShotDev* __restrict__ shots, const int* __restrict__ tile_start, in
        const float* __restrict__ resid, const float* __restrict__ pml_r,
        const float* __restrict__ pml_z, const float* __restrict__ ain,
        float* __restrict__ aout, const float* __restrict__ hist, float* __restrict__ acc,
-       long long cells_total)
+       float* __restrict__ acc_rho, float* __restrict__ acc_h, long long cells_total)
 {
+    constexpr bool RHO = (X & 1) != 0, HES = (X & 2) != 0;
     __shared__ float Ld[ND][DN];  // drivers on the D-region
     __shared__ float Lp[NP][PN];  // products on the P-region
     __shared__ float Lh[2][PN];   // stored v_r, v_z on the P-region
@@ -621,12 +628,22 @@ k_adj4(const ShotDev* __restrict__ shots, const int* __restrict__ tile_start, in
     const AdjVelIn V1 = hp ? adj_vel_in(S, Ai, rho, cells, pi, pk) : AdjVelIn{0.f, 0.f, 0.f, 0.f};
     const long long c = (long long)i * NZ + k;
     float* ga = acc + S.cell_off + c;
-    float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
+    float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f, gR = 0.f, gZ = 0.f, hL = 0.f, hM = 0.f;
+    float* gr = RHO ? acc_rho + S.cell_off + c : nullptr;
+    float* gh = HES ? acc_h + S.cell_off + c : nullptr;
     if (ocell) {
         g0 = ga[0];
         g1 = ga[cells_total];
         g3 = ga[3 * cells_total];
         if (i >= 1) g2 = ga[2 * cells_total];
+        if constexpr (RHO) {
+            if (i >= 1) gR = gr[0];
+            gZ = gr[cells_total];
+        }
+        if constexpr (HES) {
+            hL = gh[0];
+            hM = gh[cells_total];
+        }
     }
     Ld[D_ERR][e0d] = P.Err;
     Ld[D_ETT][e0d] = P.Ett;
@@ -650,6 +667,7 @@ k_adj4(const ShotDev* __restrict__ shots, const int* __restrict__ tile_start, in
 
     // ---- adjoint velocities and the products of the transposed velocity
     // update on the P-region: the owned cell (stored), then the halo cell
+    float dar = 0.f, daz = 0.f;  // the owned cell's a_v increments (density)
     auto products = [&](int i, int k, const AdjVelIn& V, bool own, float* p) {
 #pragma unroll
         for (int q = 0; q < NP; ++q) p[q] = 0.f;
@@ -666,6 +684,8 @@ k_adj4(const ShotDev* __restrict__ shots, const int* __restrict__ tile_start, in
             const float avr = V.ar + Gather::Dhi_r_odd(Err, i, k) * idr + it +
                               Gather::Dhi_z(Ez, i, k) * idz;
             if (own) Ao[c] = avr;
+            if (RHO && own)
+                dar = Gather::Dhi_r_odd(Err, i, k) * idr + it + Gather::Dhi_z(Ez, i, k) * idz;
             const float W1 = V.fR * avr;
             float aDr = W1, aDz = W1;
             if (i >= nr) {  // A-bar
@@ -689,6 +709,7 @@ k_adj4(const ShotDev* __restrict__ shots, const int* __restrict__ tile_start, in
         const float avz = V.az + Gather::Dlo_z(Ezz, i, k) * idz +
                           Gather::Dlo_r_even(Er, i, k) * idr;
         if (own) Ao[cells + c] = avz;
+        if (RHO && own) daz = Gather::Dlo_z(Ezz, i, k) * idz + Gather::Dlo_r_even(Er, i, k) * idr;
         const float W2 = V.fZ * avz;
         float aDr = W2, aDz = W2;
         if (i >= nr) {  // C-bar
@@ -767,10 +788,22 @@ k_adj4(const ShotDev* __restrict__ shots, const int* __restrict__ tile_start, in
     ga[0] = g0 + dgl;
     ga[cells_total] = g1 + dgm;
     ga[3 * cells_total] = g3 + dt * (ur * ur + uz * uz);
+    float es = 0.f;
     if (i >= 1) {
         const float ez = (C1 * (vrh(i, k + 1) - vr0) + C2 * (vrh(i, k + 2) - vrh(i, k - 1))) * idz;
         const float er = (C1 * (vz0 - vzh(i - 1, k)) + C2 * (vzh(i + 1, k) - vzh(i - 2, k))) * idr;
         ga[2 * cells_total] = g2 + (dt * (ez + er) * P.trz + P.a_zh * ez * P.pG + P.a_ri * er * P.pH);
+        es = ez + er;
+    }
+    (void)es;
+    if constexpr (RHO) {
+        if (i >= 1) gr[0] = gR + dar * vr0;
+        gr[cells_total] = gZ + daz * vz0;
+    }
+    if constexpr (HES) {
+        const float dv = err + ett + ezz;
+        gh[0] = hL + dt * dt * (3.0f * dv * dv);
+        gh[cells_total] = hM + dt * dt * (4.0f * (err * err + ett * ett + ezz * ezz) + es * es);
     }
 }
 

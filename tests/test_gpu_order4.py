@@ -135,8 +135,7 @@ def test_order4_batched_equals_single_shots():
 
 def test_order4_rules():
     """Order 3 is rejected, a time step within the second-order bound but not
-    the fourth-order one is rejected, the workspaces are those of order 2, and
-    the extra adjoint outputs are refused at order 4."""
+    the fourth-order one is rejected, and the workspaces are those of order 2."""
     import paper_2005_00281_amd as P
     from paper_2005_00281_amd._lib import BhfwiError
     w = workloads.tiny(nr=20, nz=60, p=4, nt=50)
@@ -150,9 +149,6 @@ def test_order4_rules():
     lam, mu, rho = gpu_models(w)
     wav = sv.pack_wavelets([w.shots[0].wavelet])
     sv.fwd_model(lam, mu, rho, wav, store_ckpt=True)
-    r = torch.zeros(sv.sizes.trace_elems, device=_dev())
-    with pytest.raises(BhfwiError):
-        sv.adjoint_model_ex(lam, mu, rho, wav, r, density=True)
     sv.set_order(2)
     assert sv.sizes.adj_ws_bytes == a2
     w2 = copy.deepcopy(w)
@@ -162,3 +158,94 @@ def test_order4_rules():
     sv2 = P.Survey(w2.shots, (w2.NRg, w2.NZg), ckpt_every=25)
     with pytest.raises(BhfwiError):
         sv2.set_order(4)
+
+
+@pytest.mark.parametrize("ckpt,full", [(37, 0), (37, 1)])
+def test_order4_density_and_pseudo_hessian_parity(ckpt, full):
+    """The density correlation and the pseudo-Hessian of the fourth-order
+    adjoint against the assembled oracle: dJ/drho <= 1e-3, H <= 1e-4 relative
+    L2; the modulus gradients with the extra outputs within 1e-6 of those
+    without."""
+    w = workloads.tiny(nr=40, nz=150, p=6, nt=300)
+    sh = w.shots[0]
+    _say("order 4 density + pseudo-Hessian", ckpt, "full history", full)
+    lam_o, mu_o, rho_o = oracle_models(w, 0, "start")
+    r = np.random.default_rng(3).standard_normal((len(sh.rec_k), sh.nt))
+    gl_o, gm_o, il_o, gr_o, hl_o, hm_o = oracle.gradient(
+        geom(sh), lam_o, mu_o, rho_o, sh.wavelet, r, seg=50, density=True, hessian=True,
+        order=4)
+    sv = survey4(w, ckpt=ckpt, full=full)
+    lam, mu, rho = gpu_models(w)
+    wav = sv.pack_wavelets([sh.wavelet])
+    sv.fwd_model(lam, mu, rho, wav, store_ckpt=True)
+    res = f32(r.ravel())
+    acc, acc_rho, acc_h = sv.adjoint_model_ex(lam, mu, rho, wav, res, density=True,
+                                              hessian=True)
+    gl, gm, il = (t.cpu().numpy() for t in sv.gradient(mu, acc))
+    gr = sv.gradient_density(rho, acc_rho).cpu().numpy()
+    hl, hm = (t.cpu().numpy() for t in sv.gradient_hessian(acc_h))
+    acc0 = sv.adjoint_model(lam, mu, rho, wav, res)
+    g0 = [t.cpu().numpy() for t in sv.gradient(mu, acc0)]
+    torch.cuda.synchronize()
+    errs = (rel_l2(gl, gl_o), rel_l2(gm, gm_o), rel_l2(il, il_o), rel_l2(gr, gr_o),
+            rel_l2(hl, hl_o), rel_l2(hm, hm_o))
+    print("[case] rel-L2 g_lam %.3g g_mu %.3g illum %.3g g_rho %.3g H_lam %.3g H_mu %.3g" % errs,
+          flush=True)
+    assert errs[0] <= 1e-3 and errs[1] <= 1e-3 and errs[2] <= 1e-4
+    assert errs[3] <= 1e-3
+    assert errs[4] <= 1e-4 and errs[5] <= 1e-4
+    for a, b in zip((gl, gm, il), g0):
+        assert rel_l2(a, b) <= 1e-6
+    # and it is not the second-order density gradient
+    gr2 = oracle.gradient(geom(sh), lam_o, mu_o, rho_o, sh.wavelet, r, seg=50,
+                          density=True)[3]
+    assert rel_l2(gr, gr2) > 1e-2
+
+
+def test_order4_joint_iteration_parity():
+    """One joint (lambda, mu, rho) iteration at order 4 with the
+    pseudo-Hessian diagonal and a radial taper, against the same steps in the
+    oracle (step lengths within 1e-2, model changes within 2e-2)."""
+    import paper_2005_00281_amd as P
+    from paper_2005_00281_amd.fwi import Inversion
+    w = workloads.tiny(nr=30, nz=100, p=6, nt=300)
+    sh = w.shots[0]
+    _say("order 4 joint iteration", sh.NR, sh.NZ, sh.nt)
+    g = geom(sh)
+    bounds = (1000.0, 7000.0, 300.0, 4500.0)
+    rb = (1500.0, 3000.0)
+    lam_o, mu_o, rho_o = oracle_models(w, 0, "start")
+    lt, mt, rt = oracle_models(w, 0, "true")
+    rt = rt * (1.0 + 0.05 * np.random.default_rng(13).standard_normal(rt.shape))
+    d_obs = oracle.forward(g, lt, mt, rt, sh.wavelet, order=4)
+    _, r_o = oracle.misfit(oracle.forward(g, lam_o, mu_o, rho_o, sh.wavelet, order=4), d_obs)
+    gl, gm, il, gr, hl, hm = oracle.gradient(g, lam_o, mu_o, rho_o, sh.wavelet, r_o, seg=50,
+                                             density=True, hessian=True, order=4)
+    dr = sh.dr
+    wt_o = oracle.radial_taper(g.NR, dr, 6 * dr, 12 * dr)
+    pr = oracle.precondition_diag(gr, w.mask, 1e-3, diag=il, row_weight=wt_o)
+    rho1, ar_o = oracle.update_density(rho_o, pr, w.mask, 0.02, *rb)
+    pl = oracle.precondition_diag(gl, w.mask, 1e-3, diag=hl, row_weight=wt_o)
+    pm = oracle.precondition_diag(gm, w.mask, 1e-3, diag=hm, row_weight=wt_o)
+    l1, m1, a_o = oracle.update(lam_o, mu_o, rho1, pl, pm, w.mask, 0.02,
+                                vp_bounds=bounds[:2], vs_bounds=bounds[2:])
+    vp_o, vs_o = oracle.velocities(l1, m1, rho1)
+
+    sv = survey4(w, ckpt=50)
+    wav = sv.pack_wavelets([sh.wavelet])
+    mask = torch.as_tensor(w.mask, device=_dev())
+    wt = P.radial_taper(g.NR, dr, 6 * dr, 12 * dr)
+    inv = Inversion(sv, f32(w.vp_start), f32(w.vs_start), f32(w.rho), wav, f32(d_obs.ravel()),
+                    mask, eta=0.02, bounds=bounds, density=True, rho_bounds=rb,
+                    precond="pseudo_hessian", row_weight=wt)
+    J0, a = inv.iterate()
+    a, ar = a.item(), inv.alpha_rho.item()
+    print("[case] alpha %.6g/%.6g alpha_rho %.6g/%.6g" % (a, a_o, ar, ar_o), flush=True)
+    assert abs(a - a_o) <= 1e-2 * a_o and abs(ar - ar_o) <= 1e-2 * ar_o
+    drho = inv.rho.cpu().numpy() - w.rho.astype(np.float32)
+    dvp = inv.vp.cpu().numpy() - w.vp_start.astype(np.float32)
+    dvs = inv.vs.cpu().numpy() - w.vs_start.astype(np.float32)
+    assert rel_l2(drho, rho1 - w.rho) <= 2e-2
+    assert rel_l2(dvp, vp_o - w.vp_start) <= 2e-2 and rel_l2(dvs, vs_o - w.vs_start) <= 2e-2
+    Js = [J0.item()] + [inv.iterate()[0].item() for _ in range(3)]
+    assert Js[-1] < Js[0], Js
