@@ -50,8 +50,8 @@ PMC_SOURCES = ("paper_2005_00281_amd/csrc/bhfwi_tb_adj.hip",
 PMC_TRAFFIC = {
     # (kernel, tile_map, workload, sources sha256[:16]): (FETCH KiB, WRITE KiB), summed
     # over the kernels of one launch block
-    ("k_adj_tb<8, 48, 16, 0, 0> + k_adj_tb<8, 32, 16, 1, 0>", 1, "c2", "5abbe2d38a75b893"):
-        (42707.47 + 11952.35, 22357.83 + 6724.99),
+    ("k_adj_tb<8, 64, 16, 0, 0> + k_adj_tb<8, 32, 16, 1, 0>", 1, "c2", "8948243f3bd241c5"):
+        (40730.22 + 11954.08, 28023.79 + 6724.72),
 }
 
 
@@ -62,7 +62,7 @@ TB_SHAPES = [(2, 16, 4), (3, 16, 4), (4, 16, 4), (2, 16, 8), (3, 16, 8), (4, 16,
              (8, 32, 8), (2, 16, 16), (3, 16, 16), (4, 16, 16), (4, 32, 16), (6, 32, 16),
              (8, 32, 16)]
 FWD_ONLY_SHAPES = [(4, 48, 16), (6, 48, 16), (8, 48, 16), (4, 64, 16), (8, 64, 16)]
-ADJ_ONLY_SHAPES = [(4, 48, 16), (6, 48, 16), (8, 48, 16)]
+ADJ_ONLY_SHAPES = [(4, 48, 16), (6, 48, 16), (8, 48, 16), (8, 64, 16)]
 
 
 def adj_shape(tune):

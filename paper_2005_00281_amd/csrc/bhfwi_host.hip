@@ -458,7 +458,8 @@ void adj4_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const fl
     X(2, 16, 4) X(3, 16, 4) X(4, 16, 4) X(2, 16, 8) X(3, 16, 8) X(4, 16, 8) X(2, 24, 8) \
     X(3, 24, 8) X(4, 24, 8) X(6, 24, 8) X(4, 32, 8) X(6, 32, 8) X(8, 32, 8) X(2, 16, 16) \
     X(3, 16, 16) X(4, 16, 16) X(4, 32, 16) X(6, 32, 16) X(8, 32, 16)
-#define BHFWI_ADJ_INT(X) BHFWI_ADJ_PML(X) X(4, 48, 16) X(6, 48, 16) X(8, 48, 16)
+#define BHFWI_ADJ_INT(X) \
+    BHFWI_ADJ_PML(X) X(4, 48, 16) X(6, 48, 16) X(8, 48, 16) X(8, 64, 16)
 #define BHFWI_FWD_PML(X) BHFWI_ADJ_PML(X) X(4, 48, 16) X(6, 48, 16) X(8, 48, 16)
 #define BHFWI_FWD_INT(X) BHFWI_FWD_PML(X) X(4, 64, 16) X(8, 64, 16)
 

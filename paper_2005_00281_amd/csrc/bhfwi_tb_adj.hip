@@ -58,6 +58,7 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
     static_assert(TRE % W == 0 && TRE > 2 * T && 64 > 2 * T, "tile too small for the halo");
     constexpr bool RHO = (X & 1) != 0, HES = (X & 2) != 0;
     constexpr int RPT = TRE / W;
+    constexpr bool LDSE = RPT >= 4;
     constexpr int LDW = (TRE + 2) * 64;
     enum { ERR = 0, ETT, ER, UR, HR, ZR, HVR, HVZ, NPL };
     __shared__ float L[NPL][LDW];
@@ -318,11 +319,16 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
                 gs[j] += dt * dgs;
                 ge[j] += dt * (ur * ur + uz * uz);
                 // transposed stress update into a_v, then the transposed velocity update
+                // with four or more rows per thread the drivers this lane
+                // wrote to LDS are read back instead of being held in registers
+                const float Err0 = LDSE ? L[ERR][x] : Err_[j];
+                const float Ett0 = LDSE ? L[ETT][x] : Ett_[j];
+                const float Er0 = LDSE ? L[ER][x] : Er_[j];
                 const float dar =
-                    mrow[j] * ((L[ERR][x - 64] - Err_[j]) * idr + L[ETT][x - 64] * rRm[j] +
-                               Ett_[j] * rZ[j] + (from_lane_below(Ez_[j]) - Ez_[j]) * idz);
+                    mrow[j] * ((L[ERR][x - 64] - Err0) * idr + L[ETT][x - 64] * rRm[j] +
+                               Ett0 * rZ[j] + (from_lane_below(Ez_[j]) - Ez_[j]) * idz);
                 const float daz = (Ezz_[j] - from_lane_above(Ezz_[j])) * idz +
-                                  (Er_[j] - L[ER][x + 64]) * idr;
+                                  (Er0 - L[ER][x + 64]) * idr;
                 avr[j] += dar;
                 avz[j] += daz;
                 if constexpr (RHO) {
@@ -355,18 +361,28 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
                 L[UR][x] = U_[j];
                 L[HR][x] = H_[j];
                 L[ZR][x] = aDrZ * idr + W2 * rZ[j];
+                if constexpr (LDSE) {
+                    // the parts of the gather that stay within this wave are
+                    // applied now, so that only LDS crosses the barrier
+                    tzz[j] += (from_lane_below(DzZ_[j]) - DzZ_[j]) * idz;
+                    trz[j] += mrow[j] * ((DzR_[j] - from_lane_above(DzR_[j])) * idz + ZS_[j]);
+                }
             }
             __syncthreads();
             // ---- C: transposed velocity update gathered into a_tau
 #pragma unroll
             for (int j = 0; j < RPT; ++j) {
                 const int x = (wave + W * j + 1) * 64 + lane;
-                const float h0 = H_[j], h1 = L[HR][x + 64];
-                trr[j] += U_[j] + h0 - L[UR][x + 64] + h1;
+                const float h0 = LDSE ? L[HR][x] : H_[j], h1 = L[HR][x + 64];
+                trr[j] += (LDSE ? L[UR][x] : U_[j]) + h0 - L[UR][x + 64] + h1;
                 ttt[j] -= h0 + h1;
-                tzz[j] += (from_lane_below(DzZ_[j]) - DzZ_[j]) * idz;
-                trz[j] += mrow[j] * ((DzR_[j] - from_lane_above(DzR_[j])) * idz + ZS_[j] +
-                                     L[ZR][x - 64]);
+                if constexpr (LDSE) {
+                    trz[j] += mrow[j] * L[ZR][x - 64];
+                } else {
+                    tzz[j] += (from_lane_below(DzZ_[j]) - DzZ_[j]) * idz;
+                    trz[j] += mrow[j] * ((DzR_[j] - from_lane_above(DzR_[j])) * idz + ZS_[j] +
+                                         L[ZR][x - 64]);
+                }
             }
         }
     };

@@ -1,6 +1,6 @@
 """Parity at the benchmark's full grid (340 x 2088 padded cells, one shot) in
 the launch configuration the benchmark times: the tune-cache entry of that
-workload (forward 8x64x16 with 8x32x16 PML sub-tiles, adjoint 8x48x16, the
+workload (forward 8x64x16 with 8x32x16 PML sub-tiles, adjoint 8x64x16, the
 velocity history of every step kept instead of checkpoints, HIP graphs), and
 in the checkpointed form with the recompute overlapped on a second stream
 (checkpoints every 250 steps).
@@ -66,13 +66,13 @@ def test_full_grid_in_the_benchmark_launch_configuration(full_grid, form):
     w, r, (d_o, gl_o, gm_o, il_o) = full_grid
     sh = w.shots[0]
     tune = dict(_bench_tune())
-    assert tune["full_history"] == 1 and tune["adj_tb_rows"] == 48
+    assert tune["full_history"] == 1 and tune["adj_tb_rows"] == 64
     if form != "benchmark":
         tune.update(full_history=0, rec_overlap=1)
     _say("full grid", form, sh.NR, sh.NZ, NT, tune)
     sv = P.Survey(w.shots, (w.NRg, w.NZg), ckpt_every=250)
     sv.set_tune(**tune)
-    assert sv.kernel_shapes()["adj"] == (8, 48, 16)
+    assert sv.kernel_shapes()["adj"] == (8, 64, 16)
     lam, mu, rho = gpu_models(w)
     wav = sv.pack_wavelets([sh.wavelet])
     tr = sv.fwd_model(lam, mu, rho, wav, store_ckpt=True)

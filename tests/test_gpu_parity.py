@@ -175,6 +175,44 @@ def test_gradient_parity_single_shot_128x512():
     assert rel_l2(il, il_o) <= 1e-4
 
 
+@pytest.mark.parametrize("extra", [False, True])
+def test_gradient_parity_64_row_adjoint_tiles(extra):
+    """The interior-only 64-row adjoint tiles (four rows per thread, some of
+    the drivers read back from LDS instead of held in registers) need a grid
+    tall enough to hold tiles clear of the PML: 126 x 252 cells give six of
+    them beside the PML sub-tiles.  With extra = True the density correlation
+    and the pseudo-Hessian ride along."""
+    w = workloads.tiny(nr=120, nz=240, p=6, nt=300)
+    sh = w.shots[0]
+    tune = T(tb=8, tbr=64, tbw=16, atb=8, atbr=64, atbw=16)
+    _say("grad 64-row adjoint tiles", tune, "extra", extra)
+    lam_o, mu_o, rho_o = oracle_models(w, 0, "start")
+    r = np.random.default_rng(11).standard_normal((len(sh.rec_k), sh.nt))
+    out = oracle.gradient(geom(sh), lam_o, mu_o, rho_o, sh.wavelet, r, seg=50, density=extra,
+                          hessian=extra)
+    sv = survey(w, ckpt=37, tune=tune)
+    ks = sv.kernel_shapes()
+    assert ks["adj"] == (8, 64, 16) and ks["adj_pml"] == (8, 32, 16)
+    lam, mu, rho = gpu_models(w)
+    wav = sv.pack_wavelets([sh.wavelet])
+    sv.fwd_model(lam, mu, rho, wav, store_ckpt=True)
+    if extra:
+        acc, acc_rho, acc_h = sv.adjoint_model_ex(lam, mu, rho, wav, f32(r.ravel()),
+                                                  density=True, hessian=True)
+    else:
+        acc = sv.adjoint_model(lam, mu, rho, wav, f32(r.ravel()))
+    gl, gm, il = (t.cpu().numpy() for t in sv.gradient(mu, acc))
+    torch.cuda.synchronize()
+    errs = (rel_l2(gl, out[0]), rel_l2(gm, out[1]), rel_l2(il, out[2]))
+    print("[case] rel-L2 g_lam %.3g g_mu %.3g illum %.3g" % errs, flush=True)
+    assert errs[0] <= 1e-3 and errs[1] <= 1e-3 and errs[2] <= 1e-4
+    if extra:
+        gr = sv.gradient_density(rho, acc_rho).cpu().numpy()
+        hl, hm = (t.cpu().numpy() for t in sv.gradient_hessian(acc_h))
+        assert rel_l2(gr, out[3]) <= 1e-3
+        assert rel_l2(hl, out[4]) <= 1e-4 and rel_l2(hm, out[5]) <= 1e-4
+
+
 @pytest.mark.parametrize("tune", [T(tb=8, tbr=64, tbw=16, atb=8, atbr=32, atbw=16),
                                   T(tb=4, graph=0), T(4, 4, 1)])
 def test_overlapped_recompute_is_bit_identical(tune):
