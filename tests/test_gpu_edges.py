@@ -1,7 +1,8 @@
 """Edge cases of the HIP path against the oracle: a grid without PML, a grid
 smaller than one tile with a record shorter than one time block, a zero
 residual, a shot without receivers inside a batch, and the largest per-shot
-grid the benchmark workloads define (532 x 16424 padded cells).
+grid the benchmark workloads define (532 x 16424 padded cells), also 48 of
+them in one batch (state buffers beyond 2^31 floats).
 
 Tolerances as in the main parity tests: traces relative L2 <= 1e-4,
 gradients <= 1e-3, exact where the same arithmetic repeats.
@@ -140,3 +141,43 @@ def test_largest_grid_forward():
     tr = sv.fwd_model(lam, mu, rho, sv.pack_wavelets([sh.wavelet]))
     d_g = sv.unpack_traces(tr)[0]
     assert rel_l2(d_g, d_o) <= 1e-4, rel_l2(d_g, d_o)
+
+
+def test_batched_offsets_beyond_int32():
+    """48 shots of the 128-shot workload's grid (532 x 16424 padded cells) in
+    one batch: each state buffer then holds more than 2^31 floats, so the
+    last shots sit at offsets an int32 cannot address.  Their traces must
+    equal those of the same shots run alone, bit for bit (150 steps, the
+    wavelet started near its peak, the source 20 rows from the first
+    receiver)."""
+    import paper_2005_00281_amd as P
+    w = workloads.make("c5", nshot=48)
+    nt = 150
+    shots = []
+    for s in w.shots:
+        sh = copy.copy(s)
+        peak = int(round(1.5 / sh.f0 / sh.dt))
+        sh.wavelet = np.ascontiguousarray(sh.wavelet[peak - 60: peak - 60 + nt])
+        sh.nt = nt
+        sh.src_k = int(sh.rec_k[0]) - 20
+        shots.append(sh)
+    w.shots = shots
+    _say("batched offsets beyond int32", len(shots), shots[0].NR, shots[0].NZ, nt)
+    tune = dict(tb_steps=8, tb_rows=48, tb_waves=16, adj_tb_steps=6, adj_tb_rows=32,
+                adj_tb_waves=16, tile_map=0)
+    sv = P.Survey(shots, (w.NRg, w.NZg), ckpt_every=250)
+    sv.set_tune(**tune)
+    assert sv.sizes.fwd_ws_bytes // 8 > 2 ** 31  # floats per state buffer
+    lam, mu, rho = gpu_models(w)
+    wav = sv.pack_wavelets([sh.wavelet for sh in shots])
+    tr = sv.unpack_traces(sv.fwd_model(lam, mu, rho, wav))
+    del sv
+    torch.cuda.empty_cache()
+    for s in (0, 46, 47):
+        sv1 = P.Survey([shots[s]], (w.NRg, w.NZg), ckpt_every=250)
+        sv1.set_tune(**tune)
+        tr1 = sv1.unpack_traces(sv1.fwd_model(lam, mu, rho, sv1.pack_wavelets([shots[s].wavelet])))
+        torch.cuda.synchronize()
+        assert np.abs(tr1[0]).max() > 0
+        assert np.array_equal(tr1[0], tr[s]), s
+        del sv1
