@@ -21,10 +21,10 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def survey4(w, ckpt=250, graph=1, full=0):
+def survey4(w, ckpt=250, graph=1, full=0, rov=0):
     import paper_2005_00281_amd as P
     sv = P.Survey(w.shots, (w.NRg, w.NZg), ckpt_every=ckpt, order=4)
-    sv.set_tune(use_graph=graph, full_history=full)
+    sv.set_tune(use_graph=graph, full_history=full, rec_overlap=rov)
     return sv
 
 
@@ -46,11 +46,12 @@ def test_order4_forward_parity_tiny_ragged(graph):
     assert rel_l2(d_g, d2) > 1e-2
 
 
-@pytest.mark.parametrize("ckpt,graph,full", [(37, 1, 0), (300, 0, 0), (37, 1, 1)])
-def test_order4_gradient_parity_tiny(ckpt, graph, full):
+@pytest.mark.parametrize("ckpt,graph,full,rov", [(37, 1, 0, 0), (300, 0, 0, 0), (37, 1, 1, 0),
+                                                (37, 1, 0, 1)])
+def test_order4_gradient_parity_tiny(ckpt, graph, full, rov):
     w = workloads.tiny(nr=40, nz=150, p=6, nt=300)
     sh = w.shots[0]
-    _say("order 4 grad tiny", ckpt, graph, "full history", full)
+    _say("order 4 grad tiny", ckpt, graph, "full history", full, "overlapped recompute", rov)
     lam_o, mu_o, rho_o = oracle_models(w, 0, "start")
     lt, mt, _ = oracle_models(w, 0, "true")
     d_obs = oracle.forward(geom(sh), lt, mt, rho_o, sh.wavelet, order=4)
@@ -58,7 +59,7 @@ def test_order4_gradient_parity_tiny(ckpt, graph, full):
     _, r = oracle.misfit(d_o, d_obs)
     gl_o, gm_o, il_o = oracle.gradient(geom(sh), lam_o, mu_o, rho_o, sh.wavelet, r, seg=50,
                                        order=4)
-    sv = survey4(w, ckpt=ckpt, graph=graph, full=full)
+    sv = survey4(w, ckpt=ckpt, graph=graph, full=full, rov=rov)
     lam, mu, rho = gpu_models(w)
     wav = sv.pack_wavelets([sh.wavelet])
     sv.fwd_model(lam, mu, rho, wav, store_ckpt=True)
