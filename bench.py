@@ -50,8 +50,8 @@ PMC_SOURCES = ("paper_2005_00281_amd/csrc/bhfwi_tb_adj.hip",
 PMC_TRAFFIC = {
     # (kernel, tile_map, workload, sources sha256[:16]): (FETCH KiB, WRITE KiB), summed
     # over the kernels of one launch block
-    ("k_adj_tb<8, 64, 16, 0, 0> + k_adj_tb<8, 32, 16, 1, 0>", 1, "c2", "8948243f3bd241c5"):
-        (40730.22 + 11954.08, 28023.79 + 6724.72),
+    ("k_adj_tb<8, 64, 16, 0, 0> + k_adj_tb<8, 32, 16, 1, 0>", 1, "c2", "cd788485fb9bd5d2"):
+        (40675.39 + 11954.05, 28025.36 + 6724.80),
 }
 
 
@@ -482,10 +482,12 @@ def main():
     # (sub-)tiles in the kernel that carries the PML memories
     kshapes = sv.kernel_shapes()
     xm = (1 if args.density else 0) | (2 if args.precond == "pseudo_hessian" else 0)
+    ka, kp = (kshapes["adj_x"], kshapes["adj_x_pml"]) if xm else (kshapes["adj"],
+                                                                  kshapes["adj_pml"])
     kname = ("k_adj4" if args.order == 4
              else "k_adj_tb<%d, %d, %d, 0, %d> + k_adj_tb<%d, %d, %d, 1, %d>" % (
-             kshapes["adj"] + (xm,) + kshapes["adj_pml"] + (xm,))
-             if kshapes["adj"][0] >= 2
+             ka + (xm,) + kp + (xm,))
+             if ka[0] >= 2
              else "k_adj_step<%d>" % (tune["rows_per_wave"] if tune["rows_per_wave"] <= 4 else 0))
     pmc = PMC_TRAFFIC.get((kname, tune.get("tile_map", 1), args.workload, kernel_sources_sha()))
     traffic = (None if pmc is None

@@ -116,9 +116,11 @@ typedef struct {
     int32_t adj_tb_steps;     /* adjoint: 0 = the forward's shape (tb_*), 1 = one
                                  step per launch (wave march), >= 2 = its own
                                  shape (adj_tb_steps, adj_tb_rows, adj_tb_waves)
-                                 from the supported forward shapes except the
-                                 64-row ones; PML tiles of the 48-row shapes
-                                 run as sub-tiles of a smaller shape */
+                                 from the supported forward shapes except
+                                 (4, 64, 16); PML tiles of the 48- and 64-row
+                                 shapes run as sub-tiles of a smaller shape,
+                                 and with extra outputs 8x64x16 runs as
+                                 8x48x16 (bhfwi_kernel_shapes) */
     int32_t adj_tb_rows;
     int32_t adj_tb_waves;
     int32_t pml_overlap;      /* 1: the PML tiles of a time block run on a second
@@ -232,10 +234,14 @@ int bhfwi_plan(const bhfwi_shot *shots, int32_t nshot, int64_t budget_bytes,
                int32_t ckpt_every, int32_t max_groups, int32_t *group_of, int32_t *ckpt_out,
                bhfwi_plan_info *info);
 
-/* The temporally blocked kernel shapes the current tune runs, 12 int32 to
+/* The temporally blocked kernel shapes the current tune runs, 18 int32 to
  * out (host): (T, rows, waves) of the forward kernel on tiles clear of the
- * PML, of the forward kernel on the PML sub-tiles, and the same two for the
- * adjoint; T = 0 where that part runs one step per launch. */
+ * PML, of the forward kernel on the PML sub-tiles, the same two for the
+ * adjoint, and the same two for the adjoint with extra outputs
+ * (bhfwi_adjoint_model_ex): an interior adjoint shape with four rows per
+ * thread runs those as the shape with three rows per thread, same T and
+ * waves (8x64x16 -> 8x48x16), whose registers hold the extra sums; T = 0
+ * where that part runs one step per launch. */
 int bhfwi_kernel_shapes(const bhfwi_ctx *ctx, int32_t *out);
 
 /* Read (and with reset != 0 clear) the sums of bhfwi_kernel_times_t. */

@@ -382,12 +382,12 @@ class Survey:
         return False
 
     def kernel_shapes(self):
-        """{'fwd', 'fwd_pml', 'adj', 'adj_pml'}: (T, rows, waves) of the
-        temporally blocked kernels the current tune runs (T = 0: one step per
-        launch)."""
-        out = (C.c_int32 * 12)()
+        """{'fwd', 'fwd_pml', 'adj', 'adj_pml', 'adj_x', 'adj_x_pml'}: (T, rows,
+        waves) of the temporally blocked kernels the current tune runs, adj_x
+        those of the adjoint with extra outputs (T = 0: one step per launch)."""
+        out = (C.c_int32 * 18)()
         _check(load().bhfwi_kernel_shapes(self._h, out), self._h)
-        names = ("fwd", "fwd_pml", "adj", "adj_pml")
+        names = ("fwd", "fwd_pml", "adj", "adj_pml", "adj_x", "adj_x_pml")
         return {n: tuple(out[3 * q: 3 * q + 3]) for q, n in enumerate(names)}
 
     def get_tune(self):

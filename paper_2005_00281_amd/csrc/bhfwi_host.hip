@@ -123,6 +123,7 @@ struct bhfwi_ctx {
     std::vector<int4> work;
     std::vector<int> work_nt;  // nt of each work item's shot, non-increasing
     TileSet ftiles, atiles;    // temporally blocked tiles of the forward / adjoint shape
+    TileSet xtiles;            // the adjoint's with extra outputs, when they differ
     ShotDev* d_shots = nullptr;
     int* d_rec = nullptr;
     float* d_pml_r = nullptr;
@@ -209,6 +210,24 @@ Shape adj_shape(const bhfwi_ctx* c)
     return fwd_shape(c);
 }
 
+bool adj_int_ok(Shape sh);
+
+// The adjoint shape of the launches with extra outputs (density correlation,
+// pseudo-Hessian): an interior shape with four rows per thread holds its
+// state in 128 VGPRs only by reading values back from LDS, and the four extra
+// register sums per row would spill, so those launches take the shape with
+// three rows per thread and the same T and waves; T = 0 when they run the
+// adjoint shape itself.
+Shape adj_x_shape(const bhfwi_ctx* c)
+{
+    const Shape a = adj_shape(c);
+    if (a.T >= 2 && a.TRE >= 4 * a.W) {
+        const Shape f{a.T, 3 * a.W, a.W};
+        if (adj_int_ok(f)) return f;
+    }
+    return Shape{0, 0, 0};
+}
+
 // Whether a tile of shape sh at (i0, k0) -- with its halo -- reaches a PML
 // layer: the test the kernels apply to pick their PML loop.
 bool touches_pml(const ShotDev& S, Shape sh, int i0, int k0)
@@ -292,9 +311,10 @@ void rebuild_work(bhfwi_ctx* c)
                 c->work_nt.push_back(S.nt);
             }
     }
-    const Shape fs = fwd_shape(c), as = adj_shape(c);
+    const Shape fs = fwd_shape(c), as = adj_shape(c), xs = adj_x_shape(c);
     build_tiles(c, order, fs, pml_shape(fs, false), &c->ftiles);
     build_tiles(c, order, as, pml_shape(as, true), &c->atiles);
+    build_tiles(c, order, xs, pml_shape(xs, true), &c->xtiles);
 }
 
 int upload_work(bhfwi_ctx* c)
@@ -307,7 +327,8 @@ int upload_work(bhfwi_ctx* c)
     HIPOK(c, hipMemcpy(c->d_work, c->work.data(), sizeof(int4) * c->work.size(),
                        hipMemcpyHostToDevice));
     if (int rc = upload_tiles(c, &c->ftiles)) return rc;
-    return upload_tiles(c, &c->atiles);
+    if (int rc = upload_tiles(c, &c->atiles)) return rc;
+    return upload_tiles(c, &c->xtiles);
 }
 
 int default_rows(const bhfwi_ctx* c)
@@ -592,7 +613,7 @@ void launch_adj_tb(int xm, dim3 grid, dim3 block, hipStream_t s, Args... a)
 #define BHFWI_TBA(TT, RR, WW)                                                                \
     if (T == TT && TRE == RR && W == WW) {                                                   \
         launch_adj_tb<TT, RR, WW, PMV>(xm, dim3(nact), dim3(64 * WW), fork.stream(q),         \
-                                       c->d_shots, c->atiles.d[q], nact, c->tune.tile_map,   \
+                                       c->d_shots, ts.d[q], nact, c->tune.tile_map,          \
                                        n_hi, nsteps, lam, mu, rho, c->d_rec, resid,          \
                                        c->d_pml_r, c->d_pml_z, in, out, hist_hi,             \
                                        (long long)(2 * c->cells), acc, acc_rho, acc_h,       \
@@ -609,15 +630,18 @@ void adj_tb_launch(bhfwi_ctx* c, hipStream_t st, int n_hi, int nsteps, const flo
                    float* out, const float* hist_hi, float* acc, float* acc_rho, float* acc_h)
 {
     const int xm = (acc_rho ? 1 : 0) | (acc_h ? 2 : 0);
+    const Shape xs = adj_x_shape(c);
+    const bool alt = xm != 0 && xs.T >= 2;
+    const TileSet& ts = alt ? c->xtiles : c->atiles;
     const int n_lo = n_hi - nsteps + 1;
-    const int na[2] = {active_tiles(c->atiles, 0, n_lo), active_tiles(c->atiles, 1, n_lo)};
+    const int na[2] = {active_tiles(ts, 0, n_lo), active_tiles(ts, 1, n_lo)};
     if (na[0] + na[1] <= 0) return;
     EvScope ev(c, st, 2);
     PmlFork fork(c, st, na);
     for (int q = 0; q < 2; ++q) {
         const int nact = na[q];
         if (nact <= 0) continue;
-        const Shape sh = q ? c->atiles.pml : adj_shape(c);
+        const Shape sh = q ? ts.pml : alt ? xs : adj_shape(c);
         const int T = sh.T, TRE = sh.TRE, W = sh.W;
         if (q == 0) {
             constexpr int PMV = 0;
@@ -940,6 +964,7 @@ void bhfwi_destroy(bhfwi_ctx* c)
     for (int q = 0; q < 2; ++q) {
         if (c->ftiles.d[q]) (void)hipFree(c->ftiles.d[q]);
         if (c->atiles.d[q]) (void)hipFree(c->atiles.d[q]);
+        if (c->xtiles.d[q]) (void)hipFree(c->xtiles.d[q]);
     }
     if (c->d_scratch) (void)hipFree(c->d_scratch);
     if (c->d_status) (void)hipFree(c->d_status);
@@ -1117,8 +1142,11 @@ int bhfwi_set_order(bhfwi_ctx* c, int32_t order)
 int bhfwi_kernel_shapes(const bhfwi_ctx* c, int32_t* out)
 {
     if (!c || !out) return BHFWI_EINVAL;
-    const Shape s[4] = {fwd_shape(c), c->ftiles.pml, adj_shape(c), c->atiles.pml};
-    for (int q = 0; q < 4; ++q) {
+    const Shape xs = adj_x_shape(c);
+    const bool alt = xs.T >= 2;
+    const Shape s[6] = {fwd_shape(c), c->ftiles.pml, adj_shape(c), c->atiles.pml,
+                        alt ? xs : adj_shape(c), alt ? c->xtiles.pml : c->atiles.pml};
+    for (int q = 0; q < 6; ++q) {
         out[3 * q] = s[q].T;
         out[3 * q + 1] = s[q].TRE;
         out[3 * q + 2] = s[q].W;

@@ -181,7 +181,9 @@ def test_gradient_parity_64_row_adjoint_tiles(extra):
     the drivers read back from LDS instead of held in registers) need a grid
     tall enough to hold tiles clear of the PML: 126 x 252 cells give six of
     them beside the PML sub-tiles.  With extra = True the density correlation
-    and the pseudo-Hessian ride along."""
+    and the pseudo-Hessian ride along, on the 48-row tiles that the library
+    takes for the extra outputs (their sums would spill at four rows per
+    thread)."""
     w = workloads.tiny(nr=120, nz=240, p=6, nt=300)
     sh = w.shots[0]
     tune = T(tb=8, tbr=64, tbw=16, atb=8, atbr=64, atbw=16)
@@ -193,6 +195,7 @@ def test_gradient_parity_64_row_adjoint_tiles(extra):
     sv = survey(w, ckpt=37, tune=tune)
     ks = sv.kernel_shapes()
     assert ks["adj"] == (8, 64, 16) and ks["adj_pml"] == (8, 32, 16)
+    assert ks["adj_x"] == (8, 48, 16) and ks["adj_x_pml"] == (8, 32, 16)
     lam, mu, rho = gpu_models(w)
     wav = sv.pack_wavelets([sh.wavelet])
     sv.fwd_model(lam, mu, rho, wav, store_ckpt=True)
@@ -606,6 +609,8 @@ def test_kernel_shapes_report_the_pml_sub_tiles():
     ks = sv.kernel_shapes()
     assert ks["fwd"] == (8, 64, 16) and ks["fwd_pml"] == (8, 32, 16)
     assert ks["adj"] == (6, 48, 16) and ks["adj_pml"] == (6, 24, 8)
+    # three rows per thread: the extra outputs run the same kernels' shapes
+    assert ks["adj_x"] == ks["adj"] and ks["adj_x_pml"] == ks["adj_pml"]
     sv.set_tune(**T(tb=6, tbr=32, tbw=16))
     ks = sv.kernel_shapes()
     assert ks["fwd"] == ks["fwd_pml"] == ks["adj"] == ks["adj_pml"] == (6, 32, 16)
