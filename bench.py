@@ -248,7 +248,7 @@ def main():
     ap.add_argument("--retune", action="store_true",
                     help="re-run the autotuner and record its choice in the tune cache")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=120)
+    ap.add_argument("--cpu-sample-steps", type=int, default=300)
     ap.add_argument("--plain-shots", type=int, default=2,
                     help="shots timed in the plain one-shot, one-step-per-launch form")
     ap.add_argument("--budget-gb", type=float, default=0.0,
