@@ -375,7 +375,9 @@ int bhfwi_adjoint_model_density(bhfwi_ctx *ctx, void *stream, const float *lam,
  *            H_mu = sum_n dt^2 (4 (e_rr^2 + e_tt^2 + e_zz^2) + (e_z + e_r)^2),
  *            the last from the tau_rz node (i,k) (i >= 1).
  * Each extra output adds two multiply-adds per node and step to the adjoint
- * kernels; no further history is stored. */
+ * kernels; no further history is stored.  Where the tune names an adjoint
+ * shape with four rows per thread, these launches run on the tiles of the
+ * shape with three (bhfwi_kernel_shapes, entries 4 and 5). */
 int bhfwi_adjoint_model_ex(bhfwi_ctx *ctx, void *stream, const float *lam, const float *mu,
                            const float *rho, const float *wavelet, const float *resid,
                            void *fwd_ws, int64_t fwd_ws_bytes, const void *ckpt,
