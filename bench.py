@@ -52,8 +52,8 @@ PMC_TRAFFIC = {
     # over the kernels of one launch block
     ("k_adj_tb<8, 64, 16, 0, 0> + k_adj_tb<8, 32, 16, 1, 0>", 1, "c2", "cd788485fb9bd5d2"):
         (40675.39 + 11954.05, 28025.36 + 6724.80),
-    ("k_adj_tb<6, 32, 16, 0, 0> + k_adj_tb<6, 32, 16, 1, 0>", 0, "c3", "cd788485fb9bd5d2"):
-        (7001810.0 + 1112738.0, 3336372.0 + 581734.0),
+    ("k_adj_tb<6, 32, 16, 0, 0> + k_adj_tb<6, 32, 16, 1, 0>", 1, "c3", "cd788485fb9bd5d2"):
+        (3843522.0 + 675508.9, 3577314.0 + 549301.2),
 }
 
 
