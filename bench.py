@@ -486,7 +486,7 @@ def main():
     xm = (1 if args.density else 0) | (2 if args.precond == "pseudo_hessian" else 0)
     ka, kp = (kshapes["adj_x"], kshapes["adj_x_pml"]) if xm else (kshapes["adj"],
                                                                   kshapes["adj_pml"])
-    kname = ("k_adj4" if args.order == 4
+    kname = ("k_adj4<%d>" % xm if args.order == 4
              else "k_adj_tb<%d, %d, %d, 0, %d> + k_adj_tb<%d, %d, %d, 1, %d>" % (
              ka + (xm,) + kp + (xm,))
              if ka[0] >= 2
