@@ -1,14 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark of the borehole FWI hot path on one MI355X.
 
-A step is one full gradient-descent FWI iteration over the workload: moduli,
-forward modelling with checkpoints, misfit, adjoint recompute + adjoint with
-the fused correlation, gradient finalize, preconditioner, update and the
-conversion back to velocities -- every step in the HIP library.  Inputs are
-seeded synthetic models already resident in HBM.
+A step is one full preconditioned gradient-descent FWI iteration over the
+workload, every stage in the HIP library: moduli (Eq. 3-4), then per group
+of shots the autograd-wrapped forward with checkpoints (Eq. 2) -- traces out
+of the BoreholeFWI torch.autograd.Function, the misfit of Eq. 1 as a torch
+expression, loss.backward() running the checkpoint recompute, the adjoint
+with the fused correlation (Eq. 6-8) and the finalize -- then the diagonal
+preconditioner, the update (Eq. 9-10) and the velocities (Eq. 11-12).
+Inputs are seeded synthetic models already resident in HBM.
 
-Default workload: one shot of 320 x 2048 cells (2.5 mm, 20-cell PML), 8000
-steps of 0.25 us, 12 kHz Ricker, 13 receivers, checkpoints every 250 steps.
+Default workload (c3): 64 tool positions every 0.15 m over one layered
+formation, each shot 256 x 4096 cells of 2.5 mm plus a 20-cell PML, 8000
+steps of 0.25 us, 10 kHz Ricker, 13 receivers, checkpoints every 250 steps
+with sequential recompute; the loss is summed over shots.
 
 Prints one JSON line.  value = Gcell-updates/s of the whole iteration
 (2 x cell-steps per iteration / wall time: one forward and one adjoint sweep).
@@ -25,37 +30,38 @@ sys.path.insert(0, ROOT)
 METRIC = ("Gcell-updates/s fwd+adj+grad and % HBM roofline; "
           "shots·FWI-iters/s batched vs plain")
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per cell and step (FP32): adjoint step with the fused
-# correlation reads/writes 6 adjoint fields, reads lambda, mu, rho and the
-# stored v_r, v_z, and reads/writes g_lambda, g_mu and the illumination
-ADJ_BYTES_PER_CELL_STEP = 92
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+# Algorithmic bytes per cell and step (FP32) of the unblocked step kernels:
+# the forward reads and writes 6 fields and reads lambda, mu, rho; the
+# recompute also stores v_r, v_z; the adjoint with the fused correlation reads
+# and writes 6 adjoint fields, reads lambda, mu, rho and the stored v_r, v_z,
+# and reads and writes g_lambda, g_mu and the illumination.
 FWD_BYTES_PER_CELL_STEP = 60
 REC_BYTES_PER_CELL_STEP = 68
+ADJ_BYTES_PER_CELL_STEP = 92
+# The same adjoint run as T-step blocks with the state in registers: per cell
+# and block the 6 adjoint fields, the model and the 3 accumulators cross HBM
+# once (48 + 12 + 24 B), the stored velocities once per step (8 B per step).
+ADJ_BLOCK_BYTES_PER_CELL = 84
+ADJ_BLOCK_BYTES_PER_CELL_STEP = 8
 
-# HBM traffic of the adjoint kernel, from two rocprofv3 --pmc runs of
-# "bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-autotune" (FETCH_SIZE,
-# then WRITE_SIZE; mean KiB per dispatch).  The counters are scaled by what
-# they read for a device copy of 1 GiB from cold memory (bench.py
-# --copy-calibration): FETCH_SIZE 524307 KiB for 1048576 KiB read,
-# WRITE_SIZE 1048576 KiB for 1048576 KiB written.  An entry holds only for
-# the kernel sources and the host code that tiles their launches as they were
-# measured (SHA-256 of the files below) and the same kernel shape, tile map and
-# workload; otherwise traffic is null.
-PMC_FETCH_SCALE = 1048576.0 / 524307.125
-PMC_WRITE_SCALE = 1048576.0 / 1048576.0
+# HBM traffic of the adjoint time block, from rocprofv3 --pmc runs of
+#   bench.py --workload W --nt 250 --steps 1 --warmup 0 --no-cpu-baseline
+#            --plain-shots 0 --no-kernel-times
+# restricted to the adjoint kernels: DRAM read and write requests of the L2
+# (TCC_EA0_RDREQ_DRAM_32B, TCC_EA0_WRREQ_WRITE_DRAM_32B, in 32-byte units;
+# a device copy of 1 GiB reads 1.000 GiB and writes 1.000 GiB on them,
+# profiles/copy_calibration.md), the mean per dispatch summed over the
+# interior and PML kernels of one block.  An entry holds only for the kernel
+# sources and host tiling it was measured on (SHA-256 of PMC_SOURCES), the
+# same shapes, tile map and workload; otherwise traffic is null.
 PMC_SOURCES = ("paper_2005_00281_amd/csrc/bhfwi_tb_adj.hip",
                "paper_2005_00281_amd/csrc/bhfwi_tb_fwd.hip",
                "paper_2005_00281_amd/csrc/bhfwi_internal.h",
                "paper_2005_00281_amd/csrc/bhfwi_host.hip")
 PMC_TRAFFIC = {
-    # (kernel, tile_map, workload, sources sha256[:16]): (FETCH KiB, WRITE KiB), summed
-    # over the kernels of one launch block
-    ("k_adj_tb<8, 64, 16, 0, 0> + k_adj_tb<8, 32, 16, 1, 0>", 1, "c2", "cd788485fb9bd5d2"):
-        (40675.39 + 11954.05, 28025.36 + 6724.80),
-    ("k_adj_tb<6, 32, 16, 0, 0> + k_adj_tb<6, 32, 16, 1, 0>", 1, "c3", "cd788485fb9bd5d2"):
-        (3843522.0 + 675508.9, 3577314.0 + 549301.2),
+    # (kernel, tile_map, workload, sources sha256[:16]): (read bytes, write bytes)
 }
-
 
 # temporally blocked shapes (T, tile rows incl. halo, waves) of both kernels,
 # and those of the forward kernel only
@@ -65,6 +71,9 @@ TB_SHAPES = [(2, 16, 4), (3, 16, 4), (4, 16, 4), (2, 16, 8), (3, 16, 8), (4, 16,
              (8, 32, 16)]
 FWD_ONLY_SHAPES = [(4, 48, 16), (6, 48, 16), (8, 48, 16), (4, 64, 16), (8, 64, 16)]
 ADJ_ONLY_SHAPES = [(4, 48, 16), (6, 48, 16), (8, 48, 16), (8, 64, 16)]
+# workloads whose configuration stores the whole velocity history (the
+# others checkpoint every ckpt steps and recompute)
+FULL_HISTORY_WORKLOADS = ("c1",)
 
 
 def adj_shape(tune):
@@ -84,6 +93,24 @@ def kernel_sources_sha():
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def adjoint_blocks(nt_shots, nt_max, seg, T):
+    """Adjoint launches each shot takes part in: steps run from nt_max - 1
+    down, cut at the segment boundaries j*seg, T steps per launch within a
+    segment; a shot takes part while the block's lowest step is below its
+    own nt."""
+    out = [0] * len(nt_shots)
+    for j0 in range(0, nt_max, seg):
+        n = min(j0 + seg, nt_max) - 1
+        while n >= j0:
+            nb = min(T, n - j0 + 1)
+            lo = n - nb + 1
+            for s, nt in enumerate(nt_shots):
+                if lo < nt:
+                    out[s] += 1
+            n -= nb
+    return out
 
 
 def copy_bandwidth():
@@ -111,33 +138,66 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, nt_sample):
-    """The FP64 oracle, as it is, on the first nt_sample steps of shot 0:
-    one forward (observed data), one forward (start model) and one gradient
-    evaluation.  Rate reported per cell-step of the gradient evaluation."""
+def host_cpu():
+    """(model name, logical CPUs this process may run on)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(w, nt_sample, max_workers):
+    """The FP64 oracle, as it is, on the host cores: one worker thread per
+    shot (the oracle's C calls release the interpreter lock), each running
+    the first nt_sample steps of its own shot -- forward modelling of the
+    start model, misfit and the checkpointed gradient evaluation -- after an
+    untimed forward of the true model for its observed data.  Rate per
+    cell-step of the gradient evaluation, summed over the shots, over the
+    wall time of the parallel part."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import numpy as np
     import oracle
-    sh = w.shots[0]
-    g = oracle.Geom(sh.nr, sh.nz, sh.pr, sh.pz, sh.dr, sh.dz, sh.dt, nt_sample, sh.f0, sh.vmax,
-                    sh.src_k, sh.rec_k)
-    win = lambda a: np.ascontiguousarray(w.window(a, 0))
-    rho = win(w.rho)
-    lt, mt = oracle.moduli(win(w.vp_true), win(w.vs_true), rho)
-    lam, mu = oracle.moduli(win(w.vp_start), win(w.vs_start), rho)
-    dobs = oracle.forward(g, lt, mt, rho, sh.wavelet)
-    t0 = time.time()
-    d = oracle.forward(g, lam, mu, rho, sh.wavelet)
-    _, r = oracle.misfit(d, dobs)
-    oracle.gradient(g, lam, mu, rho, sh.wavelet, r, seg=50)
-    dt = time.time() - t0
-    cs = sh.cells * nt_sample
-    return {"value": round(2 * cs / dt / 1e9, 5), "unit": "Gcell-updates/s", "cores": 1,
+    model, ncpu = host_cpu()
+    workers = max(1, min(max_workers, ncpu, len(w.shots)))
+    shots = list(range(workers))
+
+    def setup(s):
+        sh = w.shots[s]
+        g = oracle.Geom(sh.nr, sh.nz, sh.pr, sh.pz, sh.dr, sh.dz, sh.dt, min(nt_sample, sh.nt),
+                        sh.f0, sh.vmax, sh.src_k, sh.rec_k)
+        win = lambda a: np.ascontiguousarray(w.window(a, s))  # noqa: E731
+        rho = win(w.rho)
+        lt, mt = oracle.moduli(win(w.vp_true), win(w.vs_true), rho)
+        lam, mu = oracle.moduli(win(w.vp_start), win(w.vs_start), rho)
+        dobs = oracle.forward(g, lt, mt, rho, sh.wavelet)
+        return g, lam, mu, rho, sh.wavelet, dobs
+
+    def run(args):
+        g, lam, mu, rho, wav, dobs = args
+        d = oracle.forward(g, lam, mu, rho, wav)
+        _, r = oracle.misfit(d, dobs)
+        oracle.gradient(g, lam, mu, rho, wav, r, seg=50)
+        return g.NR * g.NZ * g.nt
+
+    with ThreadPoolExecutor(workers) as ex:
+        prepared = list(ex.map(setup, shots))
+        t0 = time.perf_counter()
+        cs = sum(ex.map(run, prepared))
+        dt = time.perf_counter() - t0
+    return {"value": round(2 * cs / dt / 1e9, 5), "unit": "Gcell-updates/s", "cores": workers,
             "kind": "oracle",
-            "sample": "shot 0, first %d of %d steps (%.3g cell-steps), forward + misfit + "
-                      "checkpointed gradient, %.1f s" % (nt_sample, sh.nt, cs, dt)}
-
-
-FP32_VECTOR_PEAK_TFLOPS = 157.3
+            "sample": "%d shot(s) of %s in parallel (one host thread each), the first %d of "
+                      "%d steps of each (%.3g cell-steps in all): forward + misfit + "
+                      "checkpointed gradient, %.1f s wall" % (
+                          workers, w.name, min(nt_sample, w.shots[0].nt), w.shots[0].nt, cs, dt),
+            "host": {"cpu_model": model, "logical_cpus": ncpu}}
 
 
 def semblance_bench(steps):
@@ -205,7 +265,7 @@ def semblance_bench(steps):
 
 def copy_calibration():
     """One device copy of 1 GiB from memory that is not in any cache, for
-    scaling the FETCH_SIZE / WRITE_SIZE counters (bytes known exactly)."""
+    scaling the L2-to-memory counters (bytes known exactly)."""
     import torch
     n = 1 << 28  # floats
     src = torch.ones(n, device="cuda")
@@ -218,12 +278,17 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": 4 * n, "copy_kib": 4 * n / 1024}))
 
 
-def main():
+def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--nt", type=int, default=0,
+                    help="record length override (profiling runs: the kernels and tune of the "
+                         "full-length workload on a shorter record)")
+    ap.add_argument("--direct", action="store_true",
+                    help="drive the C-ABI directly (Inversion without the autograd op)")
     ap.add_argument("--rows", type=int, default=0, help="rows per wave (0: library default)")
     ap.add_argument("--tb", type=int, default=-1,
                     help="forward steps per launch in the LDS-tiled kernels (-1: default)")
@@ -233,10 +298,11 @@ def main():
     ap.add_argument("--adj-tb", type=int, default=-1,
                     help="adjoint steps per launch (0: as the forward, 1: one per launch)")
     ap.add_argument("--pml-overlap", type=int, default=-1)
-    ap.add_argument("--full-history", type=int, default=-1,
+    ap.add_argument("--full-history", type=int, default=None,
                     help="1: keep the velocity history of every step (no checkpoints, no "
-                         "recompute); default: when the plan is one group that fits the "
-                         "budget with it")
+                         "recompute); 0: checkpoints and recompute; -1: full history when the "
+                         "plan is one group that fits the budget with it; default: as the "
+                         "workload's configuration states")
     ap.add_argument("--rec-overlap", type=int, default=-1,
                     help="1: recompute segment j-1 on a second stream during the adjoint of "
                          "segment j (default: the tune's)")
@@ -251,6 +317,8 @@ def main():
                     help="re-run the autotuner and record its choice in the tune cache")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=300)
+    ap.add_argument("--cpu-workers", type=int, default=16,
+                    help="most host threads for the oracle baseline (one shot each)")
     ap.add_argument("--plain-shots", type=int, default=2,
                     help="shots timed in the plain one-shot, one-step-per-launch form")
     ap.add_argument("--budget-gb", type=float, default=0.0,
@@ -280,7 +348,11 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="time one gradient evaluation per temporally blocked shape "
                          "(stderr only) before the benchmark")
-    args = ap.parse_args()
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
     if args.copy_calibration:
         copy_calibration()
         return
@@ -297,16 +369,26 @@ def main():
     import workloads
     import paper_2005_00281_amd as P
     from paper_2005_00281_amd.fwi import Inversion
-
     from paper_2005_00281_amd import plan as planner
 
     dev = torch.device("cuda", 0)
-    w = workloads.make(args.workload)
-    f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=dev)
+    nt_key = None
+    if args.nt:  # the kernels are those tuned for the full-length record
+        import inspect
+        par = inspect.signature(workloads.CONFIGS.get(args.workload, workloads.tiny)).parameters
+        if "nt" not in par:
+            sys.exit("--nt: workload %s has no single record length" % args.workload)
+        nt_key = par["nt"].default
+    w = workloads.make(args.workload, **({"nt": args.nt} if args.nt else {}))
+    f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=dev)  # noqa: E731
     log("workload", args.workload, "shots", len(w.shots), "grid", w.shots[0].NR, w.shots[0].NZ,
         "nt", w.shots[0].nt)
     budget = (args.budget_gb * 1e9 if args.budget_gb > 0
               else 0.8 * torch.cuda.get_device_properties(0).total_memory)
+    autograd = not args.direct
+    if autograd and args.precond != "illum":
+        log("--precond %s: the pseudo-Hessian diagonal needs the direct path" % args.precond)
+        autograd = False
     pl = planner.plan(w.shots, budget, ckpt_every=w.meta.get("ckpt"))
     log("plan: %d group(s) of %s shots, checkpoint every %s steps, %.1f GB workspaces" % (
         len(pl.groups), [len(g) for g in pl.groups], pl.ckpt_every, pl.bytes_workspace / 1e9))
@@ -335,6 +417,9 @@ def main():
     if args.taper:
         r0, r1 = (float(x) for x in args.taper.split(","))
         row_weight = P.radial_taper(w.NRg, w.shots[0].dr, r0, r1)
+        if autograd:
+            log("--taper: the row weights need the direct path")
+            autograd = False
     if args.tb >= 0 or args.adj_tb >= 0 or args.rows or args.no_autotune:
         for sv in surveys:
             sv.set_tune(rows_per_wave=args.rows or None,
@@ -350,13 +435,12 @@ def main():
         lam_s, mu_s = P.moduli(f32(w.vp_start), f32(w.vs_start), rho)
         cache = args.tune_cache or None
         if cache and args.retune and os.path.exists(cache):
-            import json as _json
             with open(cache) as f:
-                table = _json.load(f)
+                table = json.load(f)
             for sv in surveys:
-                table.pop(sv.shape_key(), None)
+                table.pop(sv.shape_key(nt_key), None)
             with open(cache, "w") as f:
-                _json.dump(table, f, indent=1, sort_keys=True)
+                json.dump(table, f, indent=1, sort_keys=True)
         t_at = time.perf_counter()
         tuned = {}  # set of shot shapes -> tune of the first group that has it
         for g, (sv, wav) in enumerate(zip(surveys, wavs)):
@@ -365,67 +449,41 @@ def main():
             if shapes in tuned:  # a group of the same shot shapes: same kernels
                 sv.set_tune(**tuned[shapes])
                 continue
-            entry = sv.autotune(lam_s, mu_s, rho, wav, cache=cache)
+            entry = sv.autotune(lam_s, mu_s, rho, wav, cache=cache, key=sv.shape_key(nt_key))
             tuned[shapes] = entry["tune"]
-            log("tune key %s%s" % (sv.shape_key()[:60], " (cached)" if entry.get("cached") else ""))
+            log("tune key %s%s" % (sv.shape_key(nt_key)[:60],
+                                   " (cached)" if entry.get("cached") else ""))
         log("autotune %.1f s -> %s%s" % (time.perf_counter() - t_at, entry["tune"],
                                           " (tune cache)" if entry.get("cached") else ""))
         del lam_s, mu_s
     if args.rec_overlap >= 0:
         for sv in surveys:
             sv.set_tune(rec_overlap=args.rec_overlap)
-    if args.full_history >= 0:
+    fh = args.full_history
+    if fh is None:
+        fh = 1 if args.workload in FULL_HISTORY_WORKLOADS else 0
+    if fh < 0:
+        full = len(surveys) == 1 and surveys[0].use_full_history_if_fits(budget)
+        if not full:
+            for sv in surveys:
+                sv.set_tune(full_history=0)
+    else:
         for sv in surveys:
-            sv.set_tune(full_history=args.full_history)
-    elif len(surveys) == 1:
-        full = surveys[0].use_full_history_if_fits(budget)
-        log("full velocity history: %s (%.1f GB)" % (
-            "on" if full else "off", surveys[0].device_bytes() / 1e9))
+            sv.set_tune(full_history=fh)
+        full = bool(fh)
+    log("velocity history: %s (%.1f GB per group)" % (
+        "every step" if full else "checkpoints", surveys[0].device_bytes() / 1e9))
     # the shared workspaces of the iteration are sized for the tune in force
     inv = Inversion(surveys, f32(w.vp_start), f32(w.vs_start), rho, wavs, observed, mask,
                     line_search=line_search, density=args.density, precond=args.precond,
-                    row_weight=row_weight)
+                    row_weight=row_weight, autograd=autograd)
     if args.progress:
         def _progress(stage, g):
             torch.cuda.synchronize()
             log("%s: group %d of %d done" % (stage, g + 1, len(surveys)))
         inv.after_group = _progress
     if args.sweep:
-        keep = surveys[0].get_tune()
-        a0 = adj_shape(keep)
-
-        def timed(**kw):
-            for x in surveys:
-                x.set_tune(**kw)
-            inv.gradient()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            inv.gradient()
-            torch.cuda.synchronize()
-            return (time.perf_counter() - t0) * 1e3
-
-        # forward shapes with the adjoint held at the tuned one, then the reverse
-        for (T, R, W_) in TB_SHAPES + FWD_ONLY_SHAPES:
-            for tmap in (0, 1):
-                ms = timed(tb_steps=T, tb_rows=R, tb_waves=W_, tile_map=tmap,
-                           adj_tb_steps=a0[0] if a0[0] >= 2 else 1, adj_tb_rows=a0[1],
-                           adj_tb_waves=a0[2])
-                log("sweep fwd T %d rows %d waves %d map %d: %.2f ms per gradient" % (
-                    T, R, W_, tmap, ms))
-        for x in surveys:
-            x.set_tune(**keep)
-        for (T, R, W_) in TB_SHAPES + ADJ_ONLY_SHAPES:
-            ms = timed(adj_tb_steps=T, adj_tb_rows=R, adj_tb_waves=W_)
-            log("sweep adj T %d rows %d waves %d: %.2f ms per gradient" % (T, R, W_, ms))
-        for x in surveys:
-            x.set_tune(**keep)
-        for ovl in (0, 1):
-            # the PML stream and the recompute stream are not combined
-            rov = 0 if ovl else keep["rec_overlap"]
-            log("sweep pml_overlap %d (rec_overlap %d): %.2f ms per gradient" % (
-                ovl, rov, timed(pml_overlap=ovl, rec_overlap=rov)))
-        for x in surveys:
-            x.set_tune(**keep)
+        sweep(inv, surveys)
     if args.no_graph:
         for sv in surveys:
             sv.set_tune(use_graph=0)
@@ -434,10 +492,7 @@ def main():
             sv.set_tune(pml_overlap=args.pml_overlap)
     sv = surveys[0]
     tune = sv.get_tune()
-
-    from types import SimpleNamespace
-    z = SimpleNamespace(cell_steps=sum(x.sizes.cell_steps for x in surveys),
-                        nt_max=max(x.sizes.nt_max for x in surveys))
+    cell_steps = sum(x.sizes.cell_steps for x in surveys)
 
     for _ in range(args.warmup):
         inv.iterate()
@@ -452,106 +507,27 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / max(1, args.steps)
-    value = 2 * z.cell_steps / (ms * 1e-3) / 1e9
+    value = 2 * cell_steps / (ms * 1e-3) / 1e9
     log("ms/iteration %.2f, J %s" % (ms, [round(float(j), 6) for j in Js]))
 
-    # per-kernel durations: one more (untimed) gradient evaluation, of the first
-    # --kt-groups shot groups (all by default), with every time-step kernel
-    # bracketed by HIP events on the stream it runs on
-    # (--no-kernel-times skips it, for counter-collection runs: no roofline)
-    timed = surveys[:args.kt_groups] if args.kt_groups > 0 else surveys
-    kt = {"fwd": [0.0, 0], "rec": [0.0, 0], "adj": [0.0, 0]}
-    if not args.no_kernel_times:
-        for x in timed:
-            x.set_tune(use_graph=0, time_kernels=1)
-            x.kernel_times(reset=True)
-        all_surveys, inv.surveys = inv.surveys, timed
-        inv.gradient()
-        inv.surveys = all_surveys
-        for x in timed:
-            for k, (ms_, n_) in x.kernel_times(reset=True).items():
-                kt[k][0] += ms_
-                kt[k][1] += n_
-            x.set_tune(use_graph=tune["use_graph"], time_kernels=0)
-    cs_timed = sum(x.sizes.cell_steps for x in timed)
-    adj_ms, adj_n = kt["adj"]
-    # every adjoint step of the timed groups ran once: nt cell-steps of every shot
-    steps_per_launch = sum(x.sizes.nt_max for x in timed) / max(1, adj_n)
-    adj_avg = adj_ms / max(1, adj_n)
-    adj_bytes = ADJ_BYTES_PER_CELL_STEP * cs_timed / max(1, adj_n)  # per launch
-    achieved = adj_bytes / (adj_avg * 1e-3) / 1e9 if adj_n else 0.0
-    # the adjoint block: interior tiles in the PML-free kernel, then the PML
-    # (sub-)tiles in the kernel that carries the PML memories
-    kshapes = sv.kernel_shapes()
-    xm = (1 if args.density else 0) | (2 if args.precond == "pseudo_hessian" else 0)
-    ka, kp = (kshapes["adj_x"], kshapes["adj_x_pml"]) if xm else (kshapes["adj"],
-                                                                  kshapes["adj_pml"])
-    kname = ("k_adj4<%d>" % xm if args.order == 4
-             else "k_adj_tb<%d, %d, %d, 0, %d> + k_adj_tb<%d, %d, %d, 1, %d>" % (
-             ka + (xm,) + kp + (xm,))
-             if ka[0] >= 2
-             else "k_adj_step<%d>" % (tune["rows_per_wave"] if tune["rows_per_wave"] <= 4 else 0))
-    pmc = PMC_TRAFFIC.get((kname, tune.get("tile_map", 1), args.workload, kernel_sources_sha()))
-    traffic = (None if pmc is None
-               else int(1024 * (pmc[0] * PMC_FETCH_SCALE + pmc[1] * PMC_WRITE_SCALE)))
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "traffic_unit": "bytes per time block (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
-                                "copy-calibrated)",
-                "traffic_GBs": (round(traffic / (adj_avg * 1e-3) / 1e9, 1)
-                                if traffic is not None and adj_n else None),
-                "kernel": kname, "avg_launch_us": round(adj_avg * 1e3, 3),
-                "steps_per_launch": round(steps_per_launch, 3),
-                "bytes_per_launch": int(adj_bytes),
-                "bytes_per_cell_step": ADJ_BYTES_PER_CELL_STEP} if adj_n else None
-    per_cs = {"fwd": FWD_BYTES_PER_CELL_STEP, "rec": REC_BYTES_PER_CELL_STEP,
-              "adj": ADJ_BYTES_PER_CELL_STEP}
-    kernels = {}
-    for k, (kms, kn) in kt.items():
-        if kn:
-            kernels[k] = {"avg_us": round(kms * 1e3 / kn, 3), "launches": kn,
-                          "achieved_GBs": round(per_cs[k] * cs_timed / (kms * 1e-3) / 1e9, 1)}
-    # iteration-level roofline: 220 B per cell-step for one gradient evaluation
-    # (forward, recompute, adjoint), plus 60 B for the line search's forward
-    it_bytes = 220 + (FWD_BYTES_PER_CELL_STEP if line_search else 0)
-    it_frac = (it_bytes * z.cell_steps / (ms * 1e-3)) / (HBM_PEAK_GBS * 1e9)
+    roofline, kernels = kernel_roofline(args, inv, surveys, tune, full)
 
-    # plain form: one shot per survey, one step per launch, no graph, same
-    # checkpoint interval and the same iteration (line search included when
-    # the batched run has it); per-shot iteration times, extrapolated over all
-    # shots by cell-steps
+    # iteration-level figure: the algorithmic bytes of the unblocked path per
+    # cell-step (forward, recompute, adjoint; without the recompute when the
+    # whole history is kept; plus a forward for the line search) over the
+    # iteration time; temporal blocking moves far fewer bytes, so this is an
+    # effective bandwidth and can exceed 1
+    it_bytes = (FWD_BYTES_PER_CELL_STEP + ADJ_BYTES_PER_CELL_STEP +
+                (8 if full else REC_BYTES_PER_CELL_STEP) +
+                (FWD_BYTES_PER_CELL_STEP if line_search else 0))
+    it_frac = (it_bytes * cell_steps / (ms * 1e-3)) / (HBM_PEAK_GBS * 1e9)
+
     plain = None
     if args.plain_shots > 0:
         del inv
         torch.cuda.empty_cache()
-        per_cs = []
-        for s_ in range(min(args.plain_shots, len(w.shots))):
-            sh = w.shots[s_]
-            g_ = [i for i, g in enumerate(pl.groups) if s_ in g][0]
-            sv1 = P.Survey([sh], (w.NRg, w.NZg), ckpt_every=pl.ckpt_every[g_], order=args.order)
-            sv1.set_tune(rows_per_wave=2, tb_steps=0, adj_tb_steps=0, use_graph=0)
-            wav1 = sv1.pack_wavelets([sh.wavelet])
-            off = sum(len(w.shots[q].rec_k) * w.shots[q].nt for q in pl.groups[g_] if q < s_)
-            obs1 = observed[g_][off: off + len(sh.rec_k) * sh.nt].clone()
-            inv1 = Inversion(sv1, f32(w.vp_start), f32(w.vs_start), rho.clone(), wav1, obs1,
-                             mask, line_search=line_search, density=args.density,
-                             precond=args.precond, row_weight=row_weight)
-            inv1.iterate()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            inv1.iterate()
-            torch.cuda.synchronize()
-            per_cs.append((time.perf_counter() - t0) / (sh.cells * sh.nt))
-            del inv1, sv1
-            torch.cuda.empty_cache()
-        rate = sum(per_cs) / len(per_cs)
-        t_plain = rate * sum(sh.cells * sh.nt for sh in w.shots)
-        plain = {"shots_iters_per_s": round(len(w.shots) / t_plain, 4),
-                 "ms_per_iteration": round(t_plain * 1e3, 1),
-                 "measured_shots": len(per_cs), "extrapolated": len(per_cs) < len(w.shots),
-                 "form": "one shot per launch sequence, one step per launch (wave march, "
-                         "2 rows per wave), no HIP graph, same checkpoint interval, same "
-                         "iteration"}
+        plain = plain_form(args, w, pl, observed, mask, rho, line_search, row_weight, autograd,
+                           full, f32)
 
     copy_bw = copy_bandwidth()
     log("device copy %.1f GB/s" % copy_bw)
@@ -559,28 +535,34 @@ def main():
     base = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        base = cpu_baseline(w, args.cpu_sample_steps)
+        base = cpu_baseline(w, args.cpu_sample_steps, args.cpu_workers)
 
+    history = ("velocity history of every step (no checkpoints, no recompute)" if full else
+               "checkpoints every %s steps, %s recompute" % (
+                   pl.ckpt_every, "overlapped" if tune["rec_overlap"] else "sequential"))
+    sh0 = w.shots[0]
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gcell-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": args.workload + ": " + (
-                   "%d shot(s), %dx%d padded cells (shot 0), %d steps (shot 0), dt %.3g s, "
-                   "f0 %.3g Hz, %d receivers, checkpoints every %s steps" % (
-                       len(w.shots), w.shots[0].NR, w.shots[0].NZ, w.shots[0].nt,
-                       w.shots[0].dt, w.shots[0].f0, len(w.shots[0].rec_k),
-                       pl.ckpt_every)),
-                   "cell_steps_per_iteration": int(z.cell_steps),
+        "config": {"workload": "%s: %d shot(s), %dx%d padded cells (shot 0), %d steps "
+                               "(shot 0), dt %.3g s, f0 %.3g Hz, %d receivers; %s; %s" % (
+                                   args.workload, len(w.shots), sh0.NR, sh0.NZ, sh0.nt, sh0.dt,
+                                   sh0.f0, len(sh0.rec_k), history,
+                                   "autograd op + loss.backward()" if autograd
+                                   else "C-ABI driven directly"),
+                   "history": "full" if full else "checkpoints",
+                   "autograd": autograd,
+                   "cell_steps_per_iteration": int(cell_steps),
                    "line_search": line_search,
                    "order": args.order,
                    "density": bool(args.density), "precond": args.precond,
                    "taper": args.taper or None,
-                   "kernel_shapes": kshapes,
+                   "kernel_shapes": sv.kernel_shapes(),
                    "tune": tune},
         "roofline": roofline,
-        "iteration_hbm_frac": round(it_frac, 4),
+        "iteration_effective_frac": round(it_frac, 4),
         "iteration_bytes_per_cell_step": it_bytes,
         "copy_GBs": round(copy_bw, 1),
         "shots_iters_per_s": round(len(w.shots) / (ms * 1e-3), 4),
@@ -593,6 +575,170 @@ def main():
         "cpu_baseline": base,
     }
     print(json.dumps(out), flush=True)
+
+
+def kernel_roofline(args, inv, surveys, tune, full):
+    """Per-kernel durations from one more (untimed) gradient evaluation of the
+    first --kt-groups shot groups (all by default), every time-step launch
+    bracketed by HIP events on the stream it runs on; the roofline of the
+    adjoint block (the largest share of GPU time) from them."""
+    if args.no_kernel_times:
+        return None, {}
+    timed = surveys[:args.kt_groups] if args.kt_groups > 0 else surveys
+    kt = {"fwd": [0.0, 0], "rec": [0.0, 0], "adj": [0.0, 0]}
+    for x in timed:
+        x.set_tune(use_graph=0, time_kernels=1)
+        x.kernel_times(reset=True)
+    all_surveys, inv.surveys = inv.surveys, timed
+    inv.gradient()
+    inv.surveys = all_surveys
+    for x in timed:
+        for k, (ms_, n_) in x.kernel_times(reset=True).items():
+            kt[k][0] += ms_
+            kt[k][1] += n_
+        x.set_tune(use_graph=tune["use_graph"], time_kernels=0)
+    cs_timed = sum(x.sizes.cell_steps for x in timed)
+    per_cs = {"fwd": FWD_BYTES_PER_CELL_STEP, "rec": REC_BYTES_PER_CELL_STEP,
+              "adj": ADJ_BYTES_PER_CELL_STEP}
+    kernels = {}
+    for k, (kms, kn) in kt.items():
+        if kn:
+            kernels[k] = {"avg_us": round(kms * 1e3 / kn, 3), "launches": kn,
+                          "effective_GBs": round(per_cs[k] * cs_timed / (kms * 1e-3) / 1e9, 1)}
+    adj_ms, adj_n = kt["adj"]
+    if not adj_n:
+        return None, kernels
+    sv = surveys[0]
+    kshapes = sv.kernel_shapes()
+    xm = (1 if args.density else 0) | (2 if args.precond == "pseudo_hessian" else 0)
+    ka, kp = (kshapes["adj_x"], kshapes["adj_x_pml"]) if xm else (kshapes["adj"],
+                                                                  kshapes["adj_pml"])
+    T = ka[0] if (args.order == 2 and ka[0] >= 2) else 1
+    kname = ("k_adj4<%d>" % xm if args.order == 4
+             else "k_adj_tb<%d, %d, %d, 0, %d> + k_adj_tb<%d, %d, %d, 1, %d>" % (
+             ka + (xm,) + kp + (xm,))
+             if ka[0] >= 2
+             else "k_adj_step<%d>" % (tune["rows_per_wave"] if tune["rows_per_wave"] <= 4 else 0))
+    adj_avg_s = adj_ms * 1e-3 / adj_n
+    # algorithmic bytes of the blocked adjoint over the timed groups: per cell
+    # and launch the state, model and accumulators, per cell and step the
+    # stored velocities
+    floor = 0
+    for x in timed:
+        nts = [sh.nt for sh in x.shots]
+        seg = max(nts) if full else x.sizes.ckpt_every
+        blocks = adjoint_blocks(nts, max(nts), seg, T)
+        for sh, nb in zip(x.shots, blocks):
+            floor += sh.cells * (ADJ_BLOCK_BYTES_PER_CELL * nb +
+                                 ADJ_BLOCK_BYTES_PER_CELL_STEP * sh.nt)
+    floor_per_launch = floor / adj_n
+    floor_GBs = floor_per_launch / adj_avg_s / 1e9
+    eff_GBs = ADJ_BYTES_PER_CELL_STEP * cs_timed / adj_n / adj_avg_s / 1e9
+    pmc = PMC_TRAFFIC.get((kname, tune.get("tile_map", 1), args.workload, kernel_sources_sha()))
+    traffic = None if pmc is None else int(pmc[0] + pmc[1])
+    traffic_GBs = None if traffic is None else traffic / adj_avg_s / 1e9
+    if traffic is not None:
+        achieved, basis = traffic_GBs, ("rocprofv3 DRAM read + write requests of the L2 per "
+                                         "launch (profiles/), over the HIP-event launch time")
+    else:
+        achieved, basis = floor_GBs, ("algorithmic bytes of the blocked adjoint per launch "
+                                      "(counters not taken for these kernel sources)")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "traffic_unit": "bytes per launch",
+                "basis": basis,
+                "kernel": kname, "avg_launch_us": round(adj_avg_s * 1e6, 3),
+                "launches": adj_n, "steps_per_launch": round(
+                    sum(x.sizes.nt_max for x in timed) / adj_n, 3),
+                "floor_bytes_per_launch": int(floor_per_launch),
+                "floor_GBs": round(floor_GBs, 1),
+                "floor_frac": round(floor_GBs / HBM_PEAK_GBS, 4),
+                "floor_model": "%d B per cell and launch + %d B per cell and step" % (
+                    ADJ_BLOCK_BYTES_PER_CELL, ADJ_BLOCK_BYTES_PER_CELL_STEP),
+                "effective_GBs": round(eff_GBs, 1),
+                "effective_frac": round(eff_GBs / HBM_PEAK_GBS, 4),
+                "effective_model": "%d B per cell-step, unblocked" % ADJ_BYTES_PER_CELL_STEP}
+    return roofline, kernels
+
+
+def plain_form(args, w, pl, observed, mask, rho, line_search, row_weight, autograd, full, f32):
+    """The plain form: one shot per survey, one step per launch, no graph; the
+    same checkpoint interval and history mode, the same iteration (autograd
+    op, line search) as the batched run.  Per-shot iteration times,
+    extrapolated over all shots by cell-steps."""
+    import torch
+    import paper_2005_00281_amd as P
+    from paper_2005_00281_amd.fwi import Inversion
+    per_cs = []
+    for s_ in range(min(args.plain_shots, len(w.shots))):
+        sh = w.shots[s_]
+        g_ = [i for i, g in enumerate(pl.groups) if s_ in g][0]
+        sv1 = P.Survey([sh], (w.NRg, w.NZg), ckpt_every=pl.ckpt_every[g_], order=args.order)
+        sv1.set_tune(rows_per_wave=2, tb_steps=0, adj_tb_steps=0, use_graph=0,
+                     full_history=1 if full else 0)
+        wav1 = sv1.pack_wavelets([sh.wavelet])
+        off = sum(len(w.shots[q].rec_k) * w.shots[q].nt for q in pl.groups[g_] if q < s_)
+        obs1 = observed[g_][off: off + len(sh.rec_k) * sh.nt].clone()
+        inv1 = Inversion(sv1, f32(w.vp_start), f32(w.vs_start), rho.clone(), wav1, obs1,
+                         mask, line_search=line_search, density=args.density,
+                         precond=args.precond, row_weight=row_weight, autograd=autograd)
+        inv1.iterate()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        inv1.iterate()
+        torch.cuda.synchronize()
+        per_cs.append((time.perf_counter() - t0) / (sh.cells * sh.nt))
+        del inv1, sv1
+        torch.cuda.empty_cache()
+    rate = sum(per_cs) / len(per_cs)
+    t_plain = rate * sum(sh.cells * sh.nt for sh in w.shots)
+    return {"shots_iters_per_s": round(len(w.shots) / t_plain, 4),
+            "ms_per_iteration": round(t_plain * 1e3, 1),
+            "measured_shots": len(per_cs), "extrapolated": len(per_cs) < len(w.shots),
+            "form": "one shot per launch sequence, one step per launch (wave march, 2 rows "
+                    "per wave), no HIP graph; same checkpoint interval and history mode (%s), "
+                    "same iteration (%s)" % ("full" if full else "checkpoints",
+                                             "autograd op" if autograd else "direct C-ABI")}
+
+
+def sweep(inv, surveys):
+    """One gradient evaluation per temporally blocked shape (stderr only)."""
+    import torch
+    keep = surveys[0].get_tune()
+    a0 = adj_shape(keep)
+
+    def timed(**kw):
+        for x in surveys:
+            x.set_tune(**kw)
+        inv.gradient()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        inv.gradient()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3
+
+    # forward shapes with the adjoint held at the tuned one, then the reverse
+    for (T, R, W_) in TB_SHAPES + FWD_ONLY_SHAPES:
+        for tmap in (0, 1):
+            ms = timed(tb_steps=T, tb_rows=R, tb_waves=W_, tile_map=tmap,
+                       adj_tb_steps=a0[0] if a0[0] >= 2 else 1, adj_tb_rows=a0[1],
+                       adj_tb_waves=a0[2])
+            log("sweep fwd T %d rows %d waves %d map %d: %.2f ms per gradient" % (
+                T, R, W_, tmap, ms))
+    for x in surveys:
+        x.set_tune(**keep)
+    for (T, R, W_) in TB_SHAPES + ADJ_ONLY_SHAPES:
+        ms = timed(adj_tb_steps=T, adj_tb_rows=R, adj_tb_waves=W_)
+        log("sweep adj T %d rows %d waves %d: %.2f ms per gradient" % (T, R, W_, ms))
+    for x in surveys:
+        x.set_tune(**keep)
+    for ovl in (0, 1):
+        # the PML stream and the recompute stream are not combined
+        rov = 0 if ovl else keep["rec_overlap"]
+        log("sweep pml_overlap %d (rec_overlap %d): %.2f ms per gradient" % (
+            ovl, rov, timed(pml_overlap=ovl, rec_overlap=rov)))
+    for x in surveys:
+        x.set_tune(**keep)
 
 
 if __name__ == "__main__":

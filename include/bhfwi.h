@@ -49,6 +49,11 @@ extern "C" {
 
 typedef struct bhfwi_ctx bhfwi_ctx;
 
+/* Identity of this build: the SHA-256 (hex) of the HIP sources and this
+ * header it was compiled from.  Loaders compare it with the sources on disk
+ * to refuse a stale library.  Static string; never fails. */
+const char *bhfwi_build_id(void);
+
 /* One shot (tool position), host struct. */
 typedef struct {
     int32_t nr, nz;           /* physical cells, radial and axial */
@@ -339,11 +344,19 @@ int bhfwi_adjoint_model(bhfwi_ctx *ctx, void *stream, const float *lam, const fl
                         void *fwd_ws, int64_t fwd_ws_bytes, const void *ckpt,
                         int64_t ckpt_bytes, void *adj_ws, int64_t adj_ws_bytes, float *acc);
 
-/* Gradient finalize: folds the tau_rz-node rigidity gradient into the C cells
- * (harmonic-mean chain rule), and sums every shot's window into the global
- * model grid in shot order (no atomics; deterministic).  Outputs (device,
- * model_len each): g_lam, g_mu, illum -- overwritten, or added to when
- * accumulate != 0 (contexts holding further groups of shots of one model). */
+/* Gradient finalize of Eq. 7-8 (the lambda and mu gradients, with the misfit
+ * of Eq. 1 summed over shots).  Eq. 8's tau_rz term is correlated at the
+ * tau_rz nodes, whose rigidity is the harmonic mean of the four surrounding
+ * cells (zero if any of them is fluid); this call folds that node gradient
+ * into the C cells by the chain rule d mu_S / d mu_c = mu_S^2 / (4 mu_c^2)
+ * for each occurrence of c (cells with mu = 0 keep only their own term), and
+ * sums every shot's window into the global model grid in shot order (no
+ * atomics; deterministic).  mu (device, model_len) is the model the adjoint
+ * ran on; acc (device, acc_elems) is bhfwi_adjoint_model's output.  Outputs
+ * (device, model_len each): g_lam, g_mu, illum -- overwritten, or added to
+ * when accumulate != 0 (contexts holding further groups of shots of one
+ * model).  Cells outside every shot's window receive 0 (or keep their value
+ * when accumulating).  EINVAL on a null pointer. */
 int bhfwi_gradient(bhfwi_ctx *ctx, void *stream, const float *mu, const float *acc,
                    float *g_lam, float *g_mu, float *illum, int32_t accumulate);
 

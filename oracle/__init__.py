@@ -4,9 +4,12 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  The product path (the HIP library and
 its Python binding) never does, and shares no code with it.
 
-The arithmetic lives in ``orc.c`` (plain serial C, double precision); this
-module only marshals numpy arrays through ctypes.  Each function names the
-passage of the paper it follows.
+The wave propagation, the adjoint, the gradients, the finalize, the
+preconditioner, the update and the line search live in ``orc.c`` (plain
+serial C, double precision), which this module reaches through ctypes.  A few
+elementwise extensions are written here in plain float64 numpy instead:
+``precondition_diag``, ``radial_taper``, ``update_density`` and
+``pick_slowness``.  Each function names the passage of the paper it follows.
 """
 from __future__ import annotations
 

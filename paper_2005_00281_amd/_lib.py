@@ -75,7 +75,7 @@ class Bounds(C.Structure):
                 ("vs_max", C.c_float)]
 
 
-EXPORTS = ["bhfwi_create", "bhfwi_destroy", "bhfwi_last_error", "bhfwi_sizes",
+EXPORTS = ["bhfwi_build_id", "bhfwi_create", "bhfwi_destroy", "bhfwi_last_error", "bhfwi_sizes",
            "bhfwi_set_tune", "bhfwi_get_tune", "bhfwi_autotune", "bhfwi_kernel_times",
            "bhfwi_moduli", "bhfwi_moduli_grad", "bhfwi_velocities",
            "bhfwi_fwd_model", "bhfwi_misfit", "bhfwi_adjoint_model", "bhfwi_gradient",
@@ -89,13 +89,23 @@ _lib = None
 
 
 def load(path: str = LIB_PATH):
-    """Load libbhfwi.so; raises if it has not been built."""
+    """Load libbhfwi.so; raises if it has not been built, or if it was built
+    from sources other than those on disk (its build id differs)."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
         raise RuntimeError("libbhfwi.so is not built (%s); run __graft_entry__.build()" % path)
     L = C.CDLL(path)
+    L.bhfwi_build_id.argtypes = []
+    L.bhfwi_build_id.restype = C.c_char_p
+    if path == LIB_PATH:
+        from .build import source_id
+        built, want = L.bhfwi_build_id().decode(), source_id()
+        if built != want:
+            raise RuntimeError("libbhfwi.so is stale: built from sources %s..., the sources on "
+                               "disk are %s...; run __graft_entry__.build()" % (built[:12],
+                                                                                want[:12]))
     P, V, I64, I32, F = C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_float
     L.bhfwi_create.argtypes = [C.POINTER(C.c_void_p), I32, C.POINTER(Shot), I32,
                                C.POINTER(C.c_int32), I32, I64, I32]
@@ -137,7 +147,7 @@ def load(path: str = LIB_PATH):
                              C.POINTER(C.c_int32), C.POINTER(PlanInfo)]
     L.bhfwi_update.argtypes = [P, V, I64, P, P, P, P, P, P, F, F, P, C.POINTER(Bounds), P]
     for name in EXPORTS:
-        if name not in ("bhfwi_destroy", "bhfwi_last_error"):
+        if name not in ("bhfwi_destroy", "bhfwi_last_error", "bhfwi_build_id"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -267,6 +277,18 @@ def velocities(lam, mu, rho, out=None):
     return vp, vs
 
 
+# Tune fields that are not kernel choices: the history mode decides the
+# memory layout (the HBM planner and use_full_history_if_fits set it from the
+# budget), time_kernels is an instrumentation switch.  Tune caches neither
+# store nor restore them.
+NOT_CACHED = ("full_history", "time_kernels")
+
+
+def cached_kernel_tune(tune):
+    """The part of a tune (dict) that a tune cache keeps and re-installs."""
+    return {k: v for k, v in tune.items() if k not in NOT_CACHED}
+
+
 def shot_array(shots, NZg=None):
     """bhfwi_shot array and packed receiver rows for shots (see Survey)."""
     arr = (Shot * len(shots))()
@@ -371,15 +393,13 @@ class Survey:
 
     def use_full_history_if_fits(self, budget_bytes):
         """Keep the velocity history of every step (tune full_history: no
-        checkpoints, no recompute) when the survey then fits budget_bytes;
-        returns whether it does."""
-        if self.get_tune()["full_history"]:
-            return self.device_bytes() <= budget_bytes
+        checkpoints, no recompute) when the survey then fits budget_bytes,
+        else the checkpoints; returns whether the full history is on."""
         self.set_tune(full_history=1)
-        if self.device_bytes() <= budget_bytes:
-            return True
-        self.set_tune(full_history=0)
-        return False
+        full = self.device_bytes() <= budget_bytes
+        if not full:
+            self.set_tune(full_history=0)
+        return full
 
     def kernel_shapes(self):
         """{'fwd', 'fwd_pml', 'adj', 'adj_pml', 'adj_x', 'adj_x_pml'}: (T, rows,
@@ -395,10 +415,12 @@ class Survey:
         _check(load().bhfwi_get_tune(self._h, C.byref(t)), self._h)
         return {name: getattr(t, name) for name, _ in Tune._fields_}
 
-    def shape_key(self):
+    def shape_key(self, nt=None):
         """Key of the autotune cache: GPU architecture and compute-unit count,
-        checkpoint interval and the multiset of shot shapes."""
-        shapes = sorted((sh.nr + sh.pr, sh.nz + 2 * sh.pz, sh.nt) for sh in self.shots)
+        checkpoint interval and the multiset of shot shapes (with nt, the key
+        the same shots would have with records of nt steps)."""
+        shapes = sorted((sh.nr + sh.pr, sh.nz + 2 * sh.pz, sh.nt if nt is None else int(nt))
+                        for sh in self.shots)
         hist = {}
         for s in shapes:
             hist[s] = hist.get(s, 0) + 1
@@ -409,20 +431,21 @@ class Survey:
                                   ";".join("%dx%dx%d*%d" % (a, b, c, n)
                                            for (a, b, c), n in sorted(hist.items())))
 
-    def autotune(self, lam, mu, rho, wavelet, probe_steps=None, cache=None):
+    def autotune(self, lam, mu, rho, wavelet, probe_steps=None, cache=None, key=None):
         """Pick the fastest kernel shape for this survey (bhfwi_autotune) and
-        install it; with cache (a JSON path) reuse and record the choice.  The
-        fourth-order kernels have no shapes to tune: the current tune is kept."""
+        install it; with cache (a JSON path) reuse and record the choice under
+        key (default shape_key()).  The fourth-order kernels have no shapes to
+        tune: the current tune is kept."""
         import json
         if self.order != 2:
             return {"tune": self.get_tune(), "ms": None, "cached": False}
-        key = self.shape_key()
+        key = key or self.shape_key()
         table = {}
         if cache and os.path.exists(cache):
             with open(cache) as f:
                 table = json.load(f)
         if key in table:
-            self.set_tune(**table[key]["tune"])
+            self.set_tune(**cached_kernel_tune(table[key]["tune"]))
             return dict(table[key], cached=True)
         full = self.get_tune()["full_history"]
         if full:  # the probe needs the checkpointed form's history in adj_ws
@@ -443,7 +466,8 @@ class Survey:
             best.full_history = 1
             self.set_tune(full_history=1)
         _check(load().bhfwi_sizes(self._h, C.byref(self.sizes)), self._h)
-        entry = {"tune": {name: getattr(best, name) for name, _ in Tune._fields_},
+        entry = {"tune": cached_kernel_tune({name: getattr(best, name)
+                                             for name, _ in Tune._fields_}),
                  "probe_ms": ms.value, "probe_steps": int(probe_steps)}
         if cache:
             table[key] = entry
@@ -484,6 +508,23 @@ class Survey:
 
     def free_workspaces(self):
         self._ws.clear()
+
+    def checkout_ckpt(self):
+        """(buffer, token) for the checkpoints of one autograd forward: the
+        survey's checkpoint workspace when no other forward holds it, else a
+        fresh allocation of the same size (token None)."""
+        if getattr(self, "_ckpt_owner", None) is None:
+            token = object()
+            self._ckpt_owner = token
+            return self.workspace("ckpt"), token
+        return torch.empty(max(1, self.sizes.ckpt_bytes), dtype=torch.uint8,
+                           device=self.device), None
+
+    def release_ckpt(self, token):
+        """End the reservation taken by checkout_ckpt (a no-op for a token that
+        no longer holds it)."""
+        if token is not None and getattr(self, "_ckpt_owner", None) is token:
+            self._ckpt_owner = None
 
     # ---------------------------------------------------------------- steps
     def fwd_model(self, lam, mu, rho, wavelet, store_ckpt=False, ckpt=None, traces=None):

@@ -1,7 +1,10 @@
 """torch.autograd.Function around the HIP forward and adjoint kernels.
 
-forward: Eq. 2 for every shot of the survey, storing checkpoints (a fresh
-device allocation per call, kept on the autograd context).
+forward: Eq. 2 for every shot of the survey, storing checkpoints (or, with
+the survey's full_history tune, the velocity of every step) in the survey's
+own checkpoint workspace, which stays reserved for this call until its
+backward has run or its graph is freed; a second forward issued while the
+first still holds it gets a fresh allocation.
 backward: grad_traces is dJ/dtraces for whatever loss the caller built (for
 Eq. 1 it is the residual of Eq. 5); the adjoint kernels recompute each
 checkpoint segment and correlate (Eq. 6-8); the finalize kernel returns
@@ -12,18 +15,22 @@ When rho requires grad the density correlation runs in the same adjoint pass
 """
 from __future__ import annotations
 
+import weakref
+
 import torch
 
 
 class BoreholeFWI(torch.autograd.Function):
     @staticmethod
     def forward(ctx, lam, mu, survey, rho, wavelet):
-        z = survey.sizes
-        ckpt = torch.empty(max(1, z.ckpt_bytes), dtype=torch.uint8, device=lam.device)
+        ckpt, token = survey.checkout_ckpt()
+        # the reservation ends with the backward, or with this context when no
+        # backward ever runs (no_grad, a discarded graph)
+        weakref.finalize(ctx, survey.release_ckpt, token)
         traces = survey.fwd_model(lam.detach(), mu.detach(), rho.detach(), wavelet,
                                   store_ckpt=True, ckpt=ckpt)
         ctx.survey = survey
-        ctx.ckpt = ckpt
+        ctx.ckpt, ctx.token = ckpt, token
         ctx.save_for_backward(lam.detach(), mu.detach(), rho.detach(), wavelet)
         return traces
 
@@ -42,6 +49,7 @@ class BoreholeFWI(torch.autograd.Function):
         g_lam, g_mu, illum = survey.gradient(mu, acc)
         survey.last_illum = illum
         ctx.ckpt = None
+        survey.release_ckpt(ctx.token)
         return g_lam, g_mu, None, g_rho, None
 
 

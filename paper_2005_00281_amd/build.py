@@ -1,6 +1,8 @@
 """Build libbhfwi.so in-tree with hipcc for gfx950."""
 from __future__ import annotations
 
+import glob
+import hashlib
 import os
 import subprocess
 import sys
@@ -18,9 +20,29 @@ HIPCC_FLAGS = [
 ]
 
 
+def source_files():
+    """Every file the library is compiled from: the HIP sources and headers
+    under csrc/ and the C-ABI header."""
+    files = sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")) +
+                   glob.glob(os.path.join(HERE, "csrc", "*.h")))
+    return files + [os.path.join(ROOT, "include", "bhfwi.h")]
+
+
+def source_id() -> str:
+    """SHA-256 (hex) over the names and contents of source_files(); compiled
+    into the library as its build id (bhfwi_build_id)."""
+    h = hashlib.sha256()
+    for f in source_files():
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def build(verbose: bool = False) -> str:
     tmp = OUT + ".tmp%d" % os.getpid()
-    cmd = ["hipcc"] + HIPCC_FLAGS + ["-o", tmp] + SRCS
+    cmd = (["hipcc"] + HIPCC_FLAGS + ['-DBHFWI_BUILD_ID="%s"' % source_id(), "-o", tmp] +
+           SRCS)
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -770,6 +770,11 @@ int run_sequence(bhfwi_ctx* c, hipStream_t st, std::vector<uintptr_t> key, F&& r
 
 extern "C" {
 
+#ifndef BHFWI_BUILD_ID
+#define BHFWI_BUILD_ID "unknown"
+#endif
+const char* bhfwi_build_id(void) { return BHFWI_BUILD_ID; }
+
 int bhfwi_create(bhfwi_ctx** out, int32_t hip_device, const bhfwi_shot* shots, int32_t nshot,
                  const int32_t* rec_k, int32_t nrec_total, int64_t model_len, int32_t ckpt_every)
 {

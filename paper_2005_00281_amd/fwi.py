@@ -18,6 +18,14 @@ minimum of the parabola through the two misfits and the slope along the
 preconditioned gradient (bhfwi_line_search); the whole iteration stays on
 the device without a host synchronisation.
 
+With autograd=True the gradient of each group comes from the
+torch.autograd.Function around the forward and adjoint kernels
+(BoreholeFWI): the traces are its output, the misfit of Eq. 1 is a torch
+expression of them (summed in float64), and loss.backward() runs the
+checkpoint recompute, the adjoint with the fused correlation and the
+finalize; the illumination of the same pass feeds the preconditioner.  The
+kernels and workspaces are the same as on the direct path.
+
 Extensions beyond the paper's fixed density and illumination preconditioner
 (all optional, off by default):
   density=True     joint inversion: the adjoint pass also accumulates
@@ -41,9 +49,14 @@ from . import _lib
 class Inversion:
     def __init__(self, surveys, vp, vs, rho, wavelets, observed, mask, eps=1e-3, eta=0.02,
                  bounds=(1000.0, 7000.0, 300.0, 4500.0), line_search=False, density=False,
-                 eta_rho=None, rho_bounds=(1000.0, 3500.0), precond="illum", row_weight=None):
+                 eta_rho=None, rho_bounds=(1000.0, 3500.0), precond="illum", row_weight=None,
+                 autograd=False):
         if precond not in ("illum", "pseudo_hessian"):
             raise ValueError("precond must be 'illum' or 'pseudo_hessian'")
+        if autograd and precond != "illum":
+            raise ValueError("the autograd path returns the illumination as its only "
+                             "preconditioner diagonal")
+        self.autograd = bool(autograd)
         if density and line_search:
             raise ValueError("the line search steps lambda and mu only; use density without it")
         if not isinstance(surveys, (list, tuple)):
@@ -61,8 +74,10 @@ class Inversion:
                      "adj": torch.empty(max(1, need["adj_ws"]), dtype=torch.uint8, device=dev)}
         for sv in self.surveys:
             sv.use_workspaces(self.pool)
-        self.acc = torch.empty(max(sv.sizes.acc_elems for sv in self.surveys),
-                               dtype=torch.float32, device=dev)
+        # the autograd path's backward allocates its own accumulators
+        self.acc = (None if self.autograd else
+                    torch.empty(max(sv.sizes.acc_elems for sv in self.surveys),
+                                dtype=torch.float32, device=dev))
         self.traces = [torch.empty(sv.sizes.trace_elems, dtype=torch.float32, device=dev)
                        for sv in self.surveys]
         self.resid = [torch.empty_like(t) for t in self.traces]
@@ -97,6 +112,8 @@ class Inversion:
     def gradient(self):
         """Eq. 2, 1, 5, 6-8 and the finalize over every group; leaves the
         misfit in self.J and the raw gradient and illumination on the model."""
+        if self.autograd:
+            return self._gradient_autograd()
         _lib.moduli(self.vp, self.vs, self.rho, out=(self.lam, self.mu))
         for g, sv in enumerate(self.surveys):
             ckpt = self.pool["ckpt"]
@@ -123,6 +140,33 @@ class Inversion:
                         accumulate=g > 0)
             if self.after_group:
                 self.after_group("gradient", g)
+        return self.J
+
+    def _gradient_autograd(self):
+        """gradient() through BoreholeFWI and loss.backward()."""
+        from .autograd import BoreholeFWI
+        _lib.moduli(self.vp, self.vs, self.rho, out=(self.lam, self.mu))
+        lam = self.lam.detach().requires_grad_(True)
+        mu = self.mu.detach().requires_grad_(True)
+        rho = self.rho.detach().requires_grad_(self.density)
+        for g, sv in enumerate(self.surveys):
+            traces = BoreholeFWI.apply(lam, mu, sv, rho, self.wavelets[g])
+            r = (traces - self.observed[g]).double()
+            loss = 0.5 * torch.dot(r, r)
+            loss.backward()
+            if g == 0:
+                self.J.copy_(loss.detach())
+                self.illum.copy_(sv.last_illum)
+            else:
+                self.J.add_(loss.detach())
+                self.illum.add_(sv.last_illum)
+            sv.last_illum = None
+            if self.after_group:
+                self.after_group("gradient", g)
+        self.g_lam.copy_(lam.grad)
+        self.g_mu.copy_(mu.grad)
+        if self.density:
+            self.g_rho.copy_(rho.grad)
         return self.J
 
     def iterate(self):

@@ -63,3 +63,21 @@ def test_create_rejects_bad_geometry_without_gpu_work():
     sh[0].nrec = 2
     rc = L.bhfwi_create(ctypes.byref(h), 0, sh, 1, two, 2, 20 * 40, 10)
     assert rc == -1 and b"two receivers" in L.bhfwi_last_error(None)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libbhfwi.so not built")
+def test_library_build_id_matches_the_sources(monkeypatch):
+    """The library carries the hash of the sources it was built from; the
+    loader refuses a library whose sources have changed since."""
+    from paper_2005_00281_amd import _lib, build
+    lib = ctypes.CDLL(LIB)
+    lib.bhfwi_build_id.restype = ctypes.c_char_p
+    assert lib.bhfwi_build_id().decode() == build.source_id()
+    saved = _lib._lib
+    try:
+        _lib._lib = None
+        monkeypatch.setattr(build, "source_id", lambda: "0" * 64)
+        with pytest.raises(RuntimeError, match="stale"):
+            _lib.load()
+    finally:
+        _lib._lib = saved
