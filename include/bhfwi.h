@@ -330,6 +330,23 @@ int bhfwi_fwd_model(bhfwi_ctx *ctx, void *stream, const float *lam, const float 
 int bhfwi_misfit(bhfwi_ctx *ctx, void *stream, const float *traces, const float *observed,
                  float *resid, double *J_dev, int32_t accumulate);
 
+/* bhfwi_misfit for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * no context, and no hipMalloc, hipFree or allocating library call.  Same
+ * arithmetic and outputs as bhfwi_misfit on n packed samples: resid (device,
+ * n) = traces - observed, and 0.5 sum resid^2 summed in double into *J_dev
+ * (device; overwritten, or added to when accumulate != 0).  The partial sums
+ * live in a fixed device array of the library (1024 doubles, one copy per
+ * GPU, held until the process ends); n may be any length >= 0, since the
+ * first pass never uses more than 1024 blocks.  The device is the stream's
+ * (NULL: the current device), index at most 63.  Calls that overlap on one
+ * GPU share that array and race: serialise them (one stream, or events).
+ * Returns EINVAL for n < 0 or a null pointer, EUNSUPPORTED for a device
+ * index above 63, EHIP for a runtime error; text in bhfwi_last_error(NULL).
+ * No device status word: a non-finite sum shows as a non-finite *J_dev. */
+int bhfwi_misfit_noalloc(void *stream, int64_t n, const float *traces, const float *observed,
+                         float *resid, double *J_dev, int32_t accumulate);
+
 /* Adjoint modelling (Eq. 6, as the exact transpose of the discrete forward)
  * driven by resid = dJ/dtraces (packed), fused with the zero-lag correlation
  * of Eq. 7-8.  Each checkpoint segment is recomputed from ckpt (written by

@@ -83,7 +83,8 @@ EXPORTS = ["bhfwi_build_id", "bhfwi_create", "bhfwi_destroy", "bhfwi_last_error"
            "bhfwi_plan", "bhfwi_kernel_shapes", "bhfwi_semblance", "bhfwi_semblance_pick",
            "bhfwi_starting_model", "bhfwi_adjoint_model_density", "bhfwi_gradient_density",
            "bhfwi_adjoint_model_ex", "bhfwi_gradient_hessian", "bhfwi_precondition_diag",
-           "bhfwi_radial_taper", "bhfwi_update_density", "bhfwi_set_order"]
+           "bhfwi_radial_taper", "bhfwi_update_density", "bhfwi_set_order",
+           "bhfwi_misfit_noalloc"]
 
 _lib = None
 
@@ -124,6 +125,7 @@ def load(path: str = LIB_PATH):
     L.bhfwi_moduli_grad.argtypes = [V, I64, P, P, P, P, P, P, P, P]
     L.bhfwi_fwd_model.argtypes = [P, V, P, P, P, P, P, P, I64, P, I64, I32]
     L.bhfwi_misfit.argtypes = [P, V, P, P, P, P, I32]
+    L.bhfwi_misfit_noalloc.argtypes = [V, I64, P, P, P, P, I32]
     L.bhfwi_adjoint_model.argtypes = [P, V, P, P, P, P, P, P, I64, P, I64, P, I64, P]
     L.bhfwi_gradient.argtypes = [P, V, P, P, P, P, P, I32]
     L.bhfwi_adjoint_model_density.argtypes = [P, V, P, P, P, P, P, P, I64, P, I64, P, I64, P,
@@ -204,6 +206,20 @@ def moduli_grad(vp, vs, rho, g_lam, g_mu, density=False):
                                     _f32(g_lam), _f32(g_mu), _f32(g_vp), _f32(g_vs),
                                     _f32(g_rho) if density else None))
     return (g_vp, g_vs, g_rho) if density else (g_vp, g_vs)
+
+
+def misfit_noalloc(traces, observed, resid, J, accumulate=False):
+    """bhfwi_misfit_noalloc on flat float32 device tensors of one length:
+    resid = traces - observed, J (float64 device scalar) = 0.5 sum resid^2
+    (or added to it).  Allocates nothing on the device."""
+    n = traces.numel()
+    if observed.numel() != n or resid.numel() != n:
+        raise ValueError("traces, observed and resid must have one length")
+    L = load()
+    rc = L.bhfwi_misfit_noalloc(_stream(), n, _f32(traces), _f32(observed), _f32(resid),
+                                _f64(J), 1 if accumulate else 0)
+    _check(rc, None)
+    return resid, J
 
 
 def radial_taper(nrow, dr, r0, r1, device=None):

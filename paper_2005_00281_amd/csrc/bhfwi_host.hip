@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -84,7 +85,48 @@ int best_interval(const bhfwi_shot* shots, const int* idx, int n)
     return best;
 }
 
-thread_local std::string g_create_err;  // message of the last failed bhfwi_create
+// message of the last failed context-free call on this thread (bhfwi_create,
+// bhfwi_misfit_noalloc), readable through bhfwi_last_error(NULL)
+thread_local std::string g_create_err;
+
+}  // namespace
+
+// Device scratch of the allocation-free misfit (bhfwi_misfit_noalloc): the
+// partial sums of its two-level reduction, one per block of the first pass,
+// whatever the number of samples.  Each GPU the library runs on holds its
+// own copy (8 KiB) until the process ends; calls on one GPU share it.
+constexpr int kScratchParts = 1024;
+static __device__ __align__(256) double scratch[kScratchParts];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};  // device address of `scratch`, per device
+
+// Device address of `scratch` on device dev, looked up once per device with
+// that device current (the array's name in host code is only a host-side
+// stand-in and must never reach a kernel).
+int scratch_address(int dev, double** out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e == hipSuccess && cur != dev) e = hipSetDevice(dev);
+        void* p = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur >= 0 && cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p) {
+            g_create_err = std::string("misfit_noalloc: hipGetSymbolAddress(scratch): ") +
+                           hipGetErrorString(e);
+            return BHFWI_EHIP;
+        }
+        g_scratch_dev[dev] = (double*)p;
+    }
+    *out = g_scratch_dev[dev];
+    return BHFWI_OK;
+}
 
 }  // namespace
 
@@ -1432,6 +1474,39 @@ int bhfwi_misfit(bhfwi_ctx* c, void* stream, const float* traces, const float* o
     hipLaunchKernelGGL(bhfwi::k_sum_partials, dim3(1), dim3(256), 0, st, nb, part, J_dev,
                        accumulate ? 1 : 0, c->d_status);
     HIPOK(c, hipGetLastError());
+    return BHFWI_OK;
+}
+
+int bhfwi_misfit_noalloc(void* stream, int64_t n, const float* traces, const float* observed,
+                         float* resid, double* J_dev, int32_t accumulate)
+{
+    if (n < 0 || !J_dev || (n > 0 && (!traces || !observed || !resid))) {
+        g_create_err = "misfit_noalloc: negative length or null pointer";
+        return BHFWI_EINVAL;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    int dev = -1;
+    const hipError_t e = st ? hipStreamGetDevice(st, &dev) : hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        g_create_err = std::string("misfit_noalloc: device of the stream: ") + hipGetErrorString(e);
+        return BHFWI_EHIP;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        g_create_err = "misfit_noalloc: device index beyond 63";
+        return BHFWI_EUNSUPPORTED;
+    }
+    double* part = nullptr;
+    if (int rc = scratch_address(dev, &part)) return rc;
+    const int nb = grid1d(n, kScratchParts);  // at most kScratchParts partial sums
+    hipLaunchKernelGGL(bhfwi::k_misfit_partial, dim3(nb), dim3(256), 0, st, (long long)n, traces,
+                       observed, resid, part);
+    hipLaunchKernelGGL(bhfwi::k_sum_partials, dim3(1), dim3(256), 0, st, nb,
+                       (const double*)part, J_dev, accumulate ? 1 : 0, (int*)nullptr);
+    const hipError_t le = hipGetLastError();
+    if (le != hipSuccess) {
+        g_create_err = std::string("misfit_noalloc: launch: ") + hipGetErrorString(le);
+        return BHFWI_EHIP;
+    }
     return BHFWI_OK;
 }
 
