@@ -1,0 +1,179 @@
+"""Oracle parity of what the other GPU tests check only GPU against GPU.
+
+* The gradient of a misfit summed over shots (Eq. 7-8 with Eq. 1 summed over
+  the shots): three shots over overlapping windows of one global model, of
+  ragged record lengths and receiver counts; the batched GPU grids against
+  the sum of the FP64 oracle's per-shot gradients, each placed at its own
+  window (model_ld = the global row length, not the shot's NZ).
+* A realigned full-acquisition shot: one monopole and thirty-nine receivers
+  (Numerical Examples section): traces and gradient against the oracle.
+* A long record: the 128 x 512 single-shot geometry for 8000 steps in the
+  launch shapes the 64-shot benchmark runs (8-step forward blocks on 48-row
+  tiles, 6-step adjoint blocks on 32-row tiles, XCD-chunked tile order,
+  checkpoints every 250 steps), so that the time integrals of Eq. 7-8 sum
+  8000 FP32 contributions per cell.
+
+Tolerances as everywhere: traces <= 1e-4, gradients <= 1e-3 relative L2,
+illumination <= 1e-4.  Residuals are drawn on the host (numpy, seeded) or
+come from the oracle, never from the GPU.
+"""
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from util import geom, oracle_models, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# the launch shapes of the 64-shot benchmark workload (its tune-cache entry)
+BENCH_C3 = dict(rows_per_wave=64, waves_per_block=4, use_graph=1, tb_steps=8, tb_rows=48,
+                tb_waves=16, tile_map=1, adj_tb_steps=6, adj_tb_rows=32, adj_tb_waves=16,
+                pml_overlap=0, rec_overlap=0, full_history=0)
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def f32(a):
+    return torch.as_tensor(np.ascontiguousarray(a, np.float32), device=_dev())
+
+
+def _gpu_moduli(w, which):
+    import paper_2005_00281_amd as P
+    rho = f32(w.rho)
+    vp = w.vp_start if which == "start" else w.vp_true
+    vs = w.vs_start if which == "start" else w.vs_true
+    lam, mu = P.moduli(f32(vp), f32(vs), rho)
+    return lam, mu, rho
+
+
+def _multi_shot_workload():
+    """Three shots 0.05 m apart over one layered model (windows overlap),
+    the middle one with a shorter record, the last with two receivers."""
+    w = workloads.batched_layered(nshot=3, nr=24, nz=90, h=5e-3, p=6, dt=0.5e-6, nt=260,
+                                  f0=40e3, nrec=3, step_m=0.05, cfg_id=77)
+    w.shots[1].nt = 200
+    w.shots[1].wavelet = w.shots[1].wavelet[:200]
+    w.shots[2].rec_k = w.shots[2].rec_k[:2]
+    for sh in w.shots:
+        sh.src_k = sh.pz + 10
+        sh.rec_k = np.array([sh.pz + 40 + 12 * j for j in range(len(sh.rec_k))], np.int32)
+    return w
+
+
+TUNES = [dict(rows_per_wave=4, waves_per_block=4, tb_steps=0, adj_tb_steps=0),
+         dict(tb_steps=3, tb_rows=16, tb_waves=4, adj_tb_steps=0),
+         dict(BENCH_C3),
+         dict(BENCH_C3, full_history=1, use_graph=0)]
+
+
+@pytest.mark.parametrize("tune", TUNES)
+def test_window_sum_over_shots_against_oracle(tune):
+    import paper_2005_00281_amd as P
+    w = _multi_shot_workload()
+    _say("window sum, 3 shots", [(s.NR, s.NZ, s.nt, s.win_k0) for s in w.shots], tune)
+    rng = np.random.default_rng(20050028)
+    resid = [rng.standard_normal((len(sh.rec_k), sh.nt)) for sh in w.shots]
+    # oracle: per shot on its own window, summed into the global grid
+    glob = [np.zeros((w.NRg, w.NZg)) for _ in range(3)]
+    for s, sh in enumerate(w.shots):
+        lo, mo, ro = oracle_models(w, s, "start")
+        g = oracle.gradient(geom(sh), lo, mo, ro, sh.wavelet, resid[s], seg=40)
+        for q in range(3):
+            glob[q][: sh.NR, sh.win_k0: sh.win_k0 + sh.NZ] += g[q]
+    # the windows overlap: some cells take contributions from several shots
+    cover = np.zeros((w.NRg, w.NZg), int)
+    for sh in w.shots:
+        cover[: sh.NR, sh.win_k0: sh.win_k0 + sh.NZ] += 1
+    assert cover.max() == 3
+    lam, mu, rho = _gpu_moduli(w, "start")
+    sv = P.Survey(w.shots, (w.NRg, w.NZg), ckpt_every=50)
+    sv.set_tune(**tune)
+    wav = sv.pack_wavelets([sh.wavelet for sh in w.shots])
+    sv.fwd_model(lam, mu, rho, wav, store_ckpt=True)
+    acc = sv.adjoint_model(lam, mu, rho, wav, f32(np.concatenate([r.ravel() for r in resid])))
+    g_lam, g_mu, illum = (t.cpu().numpy() for t in sv.gradient(mu, acc))
+    e = (rel_l2(g_lam, glob[0]), rel_l2(g_mu, glob[1]), rel_l2(illum, glob[2]))
+    print("rel-L2 g_lam %.2e g_mu %.2e illum %.2e" % e)
+    assert e[0] <= 1e-3 and e[1] <= 1e-3 and e[2] <= 1e-4, e
+    # overlap cells alone (two or three shots summed)
+    ov = cover >= 2
+    assert rel_l2(g_lam[ov], glob[0][ov]) <= 1e-3
+    assert rel_l2(g_mu[ov], glob[1][ov]) <= 1e-3
+    assert rel_l2(illum[ov], glob[2][ov]) <= 1e-4
+    # cells outside every window are zero
+    assert not np.any(g_lam[cover == 0]) and not np.any(illum[cover == 0])
+
+
+def test_realigned_39_receiver_shot_against_oracle():
+    """One realigned gather (near, far and ultra-far arrays as one source
+    with 39 receivers, 1.22-7.31 m offsets) over the layered formation:
+    every trace and the gradient of its misfit against the oracle."""
+    import paper_2005_00281_amd as P
+    w = workloads.full_acquisition(nsrc=1, nr=24, h=10e-3, p=8, dt=1e-6, nt=4000)
+    sh = w.shots[0]
+    assert len(sh.rec_k) == 39
+    _say("realigned 39 receivers", sh.NR, sh.NZ, sh.nt)
+    lo, mo, ro = oracle_models(w, 0, "start")
+    lt, mt, _ = oracle_models(w, 0, "true")
+    with ThreadPoolExecutor(2) as ex:
+        f_obs = ex.submit(oracle.forward, geom(sh), lt, mt, ro, sh.wavelet)
+        f_d = ex.submit(oracle.forward, geom(sh), lo, mo, ro, sh.wavelet)
+        d_obs, d_o = f_obs.result(), f_d.result()
+    _, r = oracle.misfit(d_o, d_obs)
+    gl_o, gm_o, il_o = oracle.gradient(geom(sh), lo, mo, ro, sh.wavelet, r, seg=250)
+    lam, mu, rho = _gpu_moduli(w, "start")
+    sv = P.Survey([sh], (w.NRg, w.NZg), ckpt_every=250)
+    wav = sv.pack_wavelets([sh.wavelet])
+    d_g = sv.unpack_traces(sv.fwd_model(lam, mu, rho, wav, store_ckpt=True))[0]
+    # the far receivers record the S arrival: no trace is trivially zero
+    assert np.all(np.abs(d_o).max(axis=1) > 1e-3 * np.abs(d_o).max())
+    for j in range(39):
+        assert rel_l2(d_g[j], d_o[j]) <= 1e-4, (j, rel_l2(d_g[j], d_o[j]))
+    acc = sv.adjoint_model(lam, mu, rho, wav, f32(r.ravel()))
+    gl, gm, il = (t.cpu().numpy() for t in sv.gradient(mu, acc))
+    e = (rel_l2(gl, gl_o), rel_l2(gm, gm_o), rel_l2(il, il_o))
+    print("rel-L2 g_lam %.2e g_mu %.2e illum %.2e" % e)
+    assert e[0] <= 1e-3 and e[1] <= 1e-3 and e[2] <= 1e-4, e
+
+
+def test_8000_step_record_in_the_benchmark_launch_shapes():
+    import paper_2005_00281_amd as P
+    w = workloads.single_shot_homogeneous(nt=8000)
+    sh = w.shots[0]
+    _say("long record", sh.NR, sh.NZ, sh.nt, BENCH_C3)
+    lo, mo, ro = oracle_models(w, 0, "start")
+    lt, mt, _ = oracle_models(w, 0, "true")
+    with ThreadPoolExecutor(2) as ex:
+        f_obs = ex.submit(oracle.forward, geom(sh), lt, mt, ro, sh.wavelet)
+        f_d = ex.submit(oracle.forward, geom(sh), lo, mo, ro, sh.wavelet)
+        d_obs, d_o = f_obs.result(), f_d.result()
+    _, r = oracle.misfit(d_o, d_obs)
+    gl_o, gm_o, il_o = oracle.gradient(geom(sh), lo, mo, ro, sh.wavelet, r, seg=250)
+    lam, mu, rho = _gpu_moduli(w, "start")
+    sv = P.Survey([sh], (w.NRg, w.NZg), ckpt_every=250)
+    sv.set_tune(**BENCH_C3)
+    assert sv.kernel_shapes()["adj"] == (6, 32, 16) and sv.kernel_shapes()["fwd"] == (8, 48, 16)
+    wav = sv.pack_wavelets([sh.wavelet])
+    d_g = sv.unpack_traces(sv.fwd_model(lam, mu, rho, wav, store_ckpt=True))[0]
+    for j in range(d_o.shape[0]):
+        assert rel_l2(d_g[j], d_o[j]) <= 1e-4, (j, rel_l2(d_g[j], d_o[j]))
+    acc = sv.adjoint_model(lam, mu, rho, wav, f32(r.ravel()))
+    gl, gm, il = (t.cpu().numpy() for t in sv.gradient(mu, acc))
+    e = (rel_l2(gl, gl_o), rel_l2(gm, gm_o), rel_l2(il, il_o))
+    print("rel-L2 g_lam %.2e g_mu %.2e illum %.2e" % e)
+    assert e[0] <= 1e-3 and e[1] <= 1e-3 and e[2] <= 1e-4, e
+    form = w.mask.astype(bool)
+    assert rel_l2(gl[form], gl_o[form]) <= 1e-3 and rel_l2(gm[form], gm_o[form]) <= 1e-3

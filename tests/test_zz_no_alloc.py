@@ -10,7 +10,8 @@ import torch
 
 import workloads
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="no GPU")]
 
 
 def _ptr(t):
