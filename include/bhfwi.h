@@ -361,6 +361,21 @@ int bhfwi_adjoint_model(bhfwi_ctx *ctx, void *stream, const float *lam, const fl
                         void *fwd_ws, int64_t fwd_ws_bytes, const void *ckpt,
                         int64_t ckpt_bytes, void *adj_ws, int64_t adj_ws_bytes, float *acc);
 
+/* bhfwi_adjoint_model plus the gradient with respect to the source wavelet
+ * (an extension: the paper's source is a known Ricker).  The source adds
+ * src_scale w[n] to the three normal stresses of the on-axis source cell in
+ * step n (src_scale = dt / (pi dr^2 dz)), so dJ/dw[n] = src_scale times the
+ * sum of the three adjoint normal stresses there, dJ/dtau^{n+1}: the
+ * transpose of the linear map wavelet -> traces applied to resid.  acc as
+ * for bhfwi_adjoint_model; wgrad (device, wavelet_elems floats, packed like
+ * the wavelets, overwritten, not null).  Second order only: EUNSUPPORTED
+ * after bhfwi_set_order(4).  Same cost as bhfwi_adjoint_model. */
+int bhfwi_adjoint_model_wavelet(bhfwi_ctx *ctx, void *stream, const float *lam,
+                                const float *mu, const float *rho, const float *wavelet,
+                                const float *resid, void *fwd_ws, int64_t fwd_ws_bytes,
+                                const void *ckpt, int64_t ckpt_bytes, void *adj_ws,
+                                int64_t adj_ws_bytes, float *acc, float *wgrad);
+
 /* Gradient finalize of Eq. 7-8 (the lambda and mu gradients, with the misfit
  * of Eq. 1 summed over shots).  Eq. 8's tau_rz term is correlated at the
  * tau_rz nodes, whose rigidity is the harmonic mean of the four surrounding

@@ -84,7 +84,7 @@ EXPORTS = ["bhfwi_build_id", "bhfwi_create", "bhfwi_destroy", "bhfwi_last_error"
            "bhfwi_starting_model", "bhfwi_adjoint_model_density", "bhfwi_gradient_density",
            "bhfwi_adjoint_model_ex", "bhfwi_gradient_hessian", "bhfwi_precondition_diag",
            "bhfwi_radial_taper", "bhfwi_update_density", "bhfwi_set_order",
-           "bhfwi_misfit_noalloc"]
+           "bhfwi_misfit_noalloc", "bhfwi_adjoint_model_wavelet"]
 
 _lib = None
 
@@ -132,6 +132,8 @@ def load(path: str = LIB_PATH):
                                               P]
     L.bhfwi_gradient_density.argtypes = [P, V, P, P, P, I32]
     L.bhfwi_adjoint_model_ex.argtypes = [P, V, P, P, P, P, P, P, I64, P, I64, P, I64, P, P, P]
+    L.bhfwi_adjoint_model_wavelet.argtypes = [P, V, P, P, P, P, P, P, I64, P, I64, P, I64, P,
+                                              P]
     L.bhfwi_gradient_hessian.argtypes = [P, V, P, P, P, I32]
     L.bhfwi_precondition_diag.argtypes = [P, V, I64, I32, P, P, P, F, P, P, I32]
     L.bhfwi_radial_taper.argtypes = [V, I32, F, F, F, P]
@@ -639,6 +641,28 @@ class Survey:
             _f32(acc_h, 2 * z.cells) if hessian else None)
         _check(rc, self._h)
         return acc, acc_rho, acc_h
+
+    def adjoint_model_wavelet(self, lam, mu, rho, wavelet, resid, ckpt=None, acc=None,
+                              wgrad=None):
+        """adjoint_model plus dJ/dwavelet (bhfwi_adjoint_model_wavelet): returns
+        (acc, wgrad), wgrad packed like the wavelets -- the transpose of the
+        linear map wavelet -> traces applied to resid."""
+        z = self.sizes
+        if acc is None:
+            acc = torch.empty(z.acc_elems, dtype=torch.float32, device=self.device)
+        if wgrad is None:
+            wgrad = torch.empty(z.wavelet_elems, dtype=torch.float32, device=self.device)
+        if ckpt is None:
+            ckpt = self.workspace("ckpt")
+        fw, aw = self.workspace("fwd"), self.workspace("adj")
+        n = self.model_shape[0] * self.model_shape[1]
+        rc = load().bhfwi_adjoint_model_wavelet(
+            self._h, _stream(), _f32(lam, n), _f32(mu, n), _f32(rho, n),
+            _f32(wavelet, z.wavelet_elems), _f32(resid, z.trace_elems), _ptr(fw), fw.numel(),
+            _ptr(ckpt), ckpt.numel(), _ptr(aw), aw.numel(), _f32(acc, z.acc_elems),
+            _f32(wgrad, z.wavelet_elems))
+        _check(rc, self._h)
+        return acc, wgrad
 
     def gradient_hessian(self, acc_h, out=None, accumulate=False):
         """(H_lambda, H_mu) on the global grid from adjoint_model_ex's acc_h

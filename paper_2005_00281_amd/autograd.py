@@ -11,7 +11,9 @@ checkpoint segment and correlate (Eq. 6-8); the finalize kernel returns
 dJ/dlambda and dJ/dmu on the global model grid.  The illumination of the
 same pass is left on the survey as ``last_illum`` for the preconditioner.
 When rho requires grad the density correlation runs in the same adjoint pass
-(joint inversion, an extension of the paper's fixed density).
+(joint inversion, an extension of the paper's fixed density); when the
+wavelet requires grad the same pass records dJ/dwavelet (source-signature
+estimation, also beyond the paper's known Ricker; not with rho at once).
 """
 from __future__ import annotations
 
@@ -39,18 +41,25 @@ class BoreholeFWI(torch.autograd.Function):
         lam, mu, rho, wavelet = ctx.saved_tensors
         survey = ctx.survey
         resid = grad_traces.contiguous().float()
-        g_rho = None
+        g_rho = g_wav = None
+        if ctx.needs_input_grad[3] and ctx.needs_input_grad[4]:
+            survey.release_ckpt(ctx.token)
+            raise NotImplementedError("the density and wavelet gradients are not taken in one "
+                                      "adjoint pass")
         if ctx.needs_input_grad[3]:
             acc, acc_rho = survey.adjoint_model_density(lam, mu, rho, wavelet, resid,
                                                         ckpt=ctx.ckpt)
             g_rho = survey.gradient_density(rho, acc_rho)
+        elif ctx.needs_input_grad[4]:
+            acc, g_wav = survey.adjoint_model_wavelet(lam, mu, rho, wavelet, resid,
+                                                      ckpt=ctx.ckpt)
         else:
             acc = survey.adjoint_model(lam, mu, rho, wavelet, resid, ckpt=ctx.ckpt)
         g_lam, g_mu, illum = survey.gradient(mu, acc)
         survey.last_illum = illum
         ctx.ckpt = None
         survey.release_ckpt(ctx.token)
-        return g_lam, g_mu, None, g_rho, None
+        return g_lam, g_mu, None, g_rho, g_wav
 
 
 class Moduli(torch.autograd.Function):

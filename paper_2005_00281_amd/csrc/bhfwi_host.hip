@@ -173,6 +173,7 @@ struct bhfwi_ctx {
     int4* d_work = nullptr;
     void* d_scratch = nullptr;
     int* d_status = nullptr;  // device word raised by kernels that see non-finite sums
+    float* wgrad = nullptr;       // wavelet gradient output of the adjoint being recorded
     hipStream_t cap_stream = nullptr;  // private stream that graphs are captured on
     hipStream_t pml_stream = nullptr;  // second stream for the PML tiles of a block
     hipStream_t rec_stream = nullptr;  // recompute stream of the overlapped adjoint
@@ -473,7 +474,7 @@ void adj_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const flo
     BHFWI_DISPATCH(c->tune.rows_per_wave, bhfwi::k_adj_step, dim3((nact + wpb - 1) / wpb),
                    dim3(64 * wpb), 0, st, c->d_shots, c->d_work, nact, n, lam, mu, rho, c->d_rec,
                    resid, c->d_pml_r, c->d_pml_z, in, out, hist, acc, acc_rho, acc_h,
-                   (long long)c->cells);
+                   c->wgrad, (long long)c->cells);
 }
 
 // Fourth-order step n in one launch (tiles of TK x TI cells).
@@ -648,6 +649,7 @@ void launch_adj_tb(int xm, dim3 grid, dim3 block, hipStream_t s, Args... a)
     case 1: hipLaunchKernelGGL((bhfwi::k_adj_tb<TT, RR, WW, PMV, 1>), grid, block, 0, s, a...); break;
     case 2: hipLaunchKernelGGL((bhfwi::k_adj_tb<TT, RR, WW, PMV, 2>), grid, block, 0, s, a...); break;
     case 3: hipLaunchKernelGGL((bhfwi::k_adj_tb<TT, RR, WW, PMV, 3>), grid, block, 0, s, a...); break;
+    case 4: hipLaunchKernelGGL((bhfwi::k_adj_tb<TT, RR, WW, PMV, 4>), grid, block, 0, s, a...); break;
     default: hipLaunchKernelGGL((bhfwi::k_adj_tb<TT, RR, WW, PMV, 0>), grid, block, 0, s, a...); break;
     }
 }
@@ -659,7 +661,7 @@ void launch_adj_tb(int xm, dim3 grid, dim3 block, hipStream_t s, Args... a)
                                        n_hi, nsteps, lam, mu, rho, c->d_rec, resid,          \
                                        c->d_pml_r, c->d_pml_z, in, out, hist_hi,             \
                                        (long long)(2 * c->cells), acc, acc_rho, acc_h,       \
-                                       (long long)c->cells);                                 \
+                                       c->wgrad, (long long)c->cells);                       \
         continue;                                                                            \
     }
 
@@ -671,9 +673,10 @@ void adj_tb_launch(bhfwi_ctx* c, hipStream_t st, int n_hi, int nsteps, const flo
                    const float* mu, const float* rho, const float* resid, const float* in,
                    float* out, const float* hist_hi, float* acc, float* acc_rho, float* acc_h)
 {
-    const int xm = (acc_rho ? 1 : 0) | (acc_h ? 2 : 0);
+    const int xm = (acc_rho ? 1 : 0) | (acc_h ? 2 : 0) | (c->wgrad ? 4 : 0);
     const Shape xs = adj_x_shape(c);
-    const bool alt = xm != 0 && xs.T >= 2;
+    // the extra register sums need the alternative shape; the wavelet record does not
+    const bool alt = (xm & 3) != 0 && xs.T >= 2;
     const TileSet& ts = alt ? c->xtiles : c->atiles;
     const int n_lo = n_hi - nsteps + 1;
     const int na[2] = {active_tiles(ts, 0, n_lo), active_tiles(ts, 1, n_lo)};
@@ -1517,13 +1520,17 @@ namespace {
 int adjoint_impl(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
                  const float* rho, const float* wavelet, const float* resid, void* fwd_ws,
                  int64_t fwd_ws_bytes, const void* ckpt, int64_t ckpt_bytes, void* adj_ws,
-                 int64_t adj_ws_bytes, float* acc, float* acc_rho, float* acc_h)
+                 int64_t adj_ws_bytes, float* acc, float* acc_rho, float* acc_h,
+                 float* wgrad)
 {
     if (int rc = check_ctx(c)) return rc;
     bhfwi_sizes_t z;
     bhfwi_sizes(c, &z);
     if (!lam || !mu || !rho || !wavelet || !resid || !fwd_ws || !adj_ws || !acc)
         return fail(c, BHFWI_EINVAL, "adjoint_model: null pointer");
+    if (wgrad && (acc_rho || acc_h || c->order != 2))
+        return fail(c, BHFWI_EUNSUPPORTED, "adjoint_model: the wavelet gradient is recorded by "
+                                           "the second-order adjoint without other extra outputs");
     if (fwd_ws_bytes < z.fwd_ws_bytes || adj_ws_bytes < z.adj_ws_bytes)
         return fail(c, BHFWI_ENOMEM, "adjoint_model: workspace too small (fwd %lld/%lld, adj %lld/%lld)",
                     (long long)fwd_ws_bytes, (long long)z.fwd_ws_bytes, (long long)adj_ws_bytes,
@@ -1617,11 +1624,18 @@ int adjoint_impl(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
             adj_range(c, s, n0, n1, lam, mu, rho, resid, ab, &m, hist, acc, acc_rho, acc_h);
         }
     };
+    auto record_w = [&](hipStream_t s) {
+        c->wgrad = wgrad;  // read by the adjoint launches while they are recorded
+        if (wgrad) launch_fill(s, wgrad, c->wave_len, 0.0f);
+        record(s);
+        c->wgrad = nullptr;
+    };
     return run_sequence(c, st,
                         {2, (uintptr_t)lam, (uintptr_t)mu, (uintptr_t)rho, (uintptr_t)wavelet,
                          (uintptr_t)resid, (uintptr_t)fwd_ws, (uintptr_t)ckpt, (uintptr_t)adj_ws,
-                         (uintptr_t)acc, (uintptr_t)acc_rho, (uintptr_t)acc_h},
-                        record);
+                         (uintptr_t)acc, (uintptr_t)acc_rho, (uintptr_t)acc_h,
+                         (uintptr_t)wgrad},
+                        record_w);
 }
 
 }  // namespace
@@ -1632,7 +1646,7 @@ int bhfwi_adjoint_model(bhfwi_ctx* c, void* stream, const float* lam, const floa
                         int64_t ckpt_bytes, void* adj_ws, int64_t adj_ws_bytes, float* acc)
 {
     return adjoint_impl(c, stream, lam, mu, rho, wavelet, resid, fwd_ws, fwd_ws_bytes, ckpt,
-                        ckpt_bytes, adj_ws, adj_ws_bytes, acc, nullptr, nullptr);
+                        ckpt_bytes, adj_ws, adj_ws_bytes, acc, nullptr, nullptr, nullptr);
 }
 
 int bhfwi_adjoint_model_density(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
@@ -1644,7 +1658,7 @@ int bhfwi_adjoint_model_density(bhfwi_ctx* c, void* stream, const float* lam, co
     if (int rc = check_ctx(c)) return rc;
     if (!acc_rho) return fail(c, BHFWI_EINVAL, "adjoint_model_density: null acc_rho");
     return adjoint_impl(c, stream, lam, mu, rho, wavelet, resid, fwd_ws, fwd_ws_bytes, ckpt,
-                        ckpt_bytes, adj_ws, adj_ws_bytes, acc, acc_rho, nullptr);
+                        ckpt_bytes, adj_ws, adj_ws_bytes, acc, acc_rho, nullptr, nullptr);
 }
 
 int bhfwi_adjoint_model_ex(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
@@ -1654,7 +1668,19 @@ int bhfwi_adjoint_model_ex(bhfwi_ctx* c, void* stream, const float* lam, const f
                            float* acc_rho, float* acc_h)
 {
     return adjoint_impl(c, stream, lam, mu, rho, wavelet, resid, fwd_ws, fwd_ws_bytes, ckpt,
-                        ckpt_bytes, adj_ws, adj_ws_bytes, acc, acc_rho, acc_h);
+                        ckpt_bytes, adj_ws, adj_ws_bytes, acc, acc_rho, acc_h, nullptr);
+}
+
+int bhfwi_adjoint_model_wavelet(bhfwi_ctx* c, void* stream, const float* lam, const float* mu,
+                                const float* rho, const float* wavelet, const float* resid,
+                                void* fwd_ws, int64_t fwd_ws_bytes, const void* ckpt,
+                                int64_t ckpt_bytes, void* adj_ws, int64_t adj_ws_bytes,
+                                float* acc, float* wgrad)
+{
+    if (int rc = check_ctx(c)) return rc;
+    if (!wgrad) return fail(c, BHFWI_EINVAL, "adjoint_model_wavelet: null wgrad");
+    return adjoint_impl(c, stream, lam, mu, rho, wavelet, resid, fwd_ws, fwd_ws_bytes, ckpt,
+                        ckpt_bytes, adj_ws, adj_ws_bytes, acc, nullptr, nullptr, wgrad);
 }
 
 int bhfwi_gradient_hessian(bhfwi_ctx* c, void* stream, const float* acc_h, float* h_lam,

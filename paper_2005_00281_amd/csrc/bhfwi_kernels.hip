@@ -298,6 +298,7 @@ k_fwd_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
 // ---------------------------------------------------------------------------
 struct ARaw {  // everything read from memory for one row
     float trr, ttt, tzz, trz, lam, mu, rho, avr, avz, vrh, vzh;
+    float mu_up;  // rigidity of column k + 1 (read by the top halo lane only)
     float qA, qC, qTr, qRr, qH;  // radial strips (old)
     float qB, qD, qTz, qZz, qG;  // axial strips (old)
     float gl, gm, gs, ge;        // accumulators (rows of the chunk only)
@@ -317,7 +318,8 @@ k_adj_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
            const float* __restrict__ resid, const float* __restrict__ pml_r,
            const float* __restrict__ pml_z, const float* __restrict__ ain,
            float* __restrict__ aout, const float* __restrict__ hist, float* __restrict__ acc,
-           float* __restrict__ acc_rho, float* __restrict__ acc_h, long long cells_total)
+           float* __restrict__ acc_rho, float* __restrict__ acc_h, float* __restrict__ wgrad,
+           long long cells_total)
 {
     int w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     w = __builtin_amdgcn_readfirstlane(w);
@@ -375,6 +377,7 @@ k_adj_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
     auto load = [&](int i) -> ARaw {
         ARaw X;
         X.trr = X.ttt = X.tzz = X.trz = X.lam = X.mu = X.rho = X.avr = X.avz = X.vrh = X.vzh = 0.f;
+        X.mu_up = 0.f;
         X.qA = X.qC = X.qTr = X.qRr = X.qH = X.qB = X.qD = X.qTz = X.qZz = X.qG = 0.f;
         X.gl = X.gm = X.gs = X.ge = 0.f;
         if (i < 0 || i >= NR) return X;
@@ -388,6 +391,8 @@ k_adj_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
         const long long m = mbase + (long long)i * S.model_ld;
         X.lam = ld(lam, m, kin);
         X.mu = ld(mu, m, kin);
+        // the top halo lane has no lane above it to take mu[k + 1] from
+        if (lane == 63) X.mu_up = ld(mu, m + 1, kin && k + 1 < NZ);
         X.rho = ld(rho, m, kin);
         X.vrh = ld(vrh, c, kin);
         X.vzh = ld(vzh, c, kin);
@@ -429,6 +434,7 @@ k_adj_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
         X.mu = R.mu;
         X.pTr = X.pRr = X.pTz = X.pZz = X.pG = X.pH = 0.f;
         X.mu_kp = sh_dn(R.mu);
+        if (lane == 63) X.mu_kp = R.mu_up;
         if (top) X.mu_kp = R.mu;
         X.Err = X.Ett = X.Ezz = X.Ez = X.Er = 0.f;
         if (ip < 0 || ip >= NR) return X;
@@ -564,6 +570,8 @@ k_adj_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
             const float ett = (vrh1 + vrh0) * (0.5f / rh);
             const float ezz = (vzh0 - vzh0_km) * idz;
             const float sa = X0.trr + X0.ttt + X0.tzz;
+            // source wavelet gradient (optional): dJ/dw[n] = src_scale dJ/dtau^{n+1}
+            if (wgrad && own && i == 0 && k == S.src_k) wgrad[S.wave_off + n] = S.src_scale * sa;
             float dgl = dt * (err + ett + ezz) * sa;
             float dgm = 2.0f * dt * (err * X0.trr + ett * X0.ttt + ezz * X0.tzz);
             if (i >= nr) {
@@ -617,6 +625,9 @@ k_adj_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
     float mpp = 0.f, mpp_kp = 0.f;
     if (i0 >= 2) mpp = ld(mu, mbase + (long long)(i0 - 2) * S.model_ld, kin);
     mpp_kp = sh_dn(mpp);
+    if (lane == 63)
+        mpp_kp = i0 >= 2 ? ld(mu, mbase + (long long)(i0 - 2) * S.model_ld + 1, kin && k + 1 < NZ)
+                         : 0.f;
     if (top) mpp_kp = mpp;
 
     if constexpr (RU > 0) {

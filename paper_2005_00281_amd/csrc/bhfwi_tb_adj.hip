@@ -33,6 +33,11 @@
 // that increment times the stored v^{n+1/2} at the R and Z nodes, so no
 // history beyond the velocities already kept is needed.
 //
+// X & 4 records the transpose of the source injection: at each step the sum
+// of the three adjoint normal stresses of the on-axis source cell, which is
+// dJ/dtau^{n+1} there, times the source scale gives dJ/dw[n], the gradient
+// with respect to the source wavelet (the transpose of wavelet -> traces).
+//
 // X & 2 adds the virtual-source pseudo-Hessian diagonal: with the strain
 // rates of v^{n+1/2}, H_lambda += 3 dt^2 (e_rr + e_tt + e_zz)^2 (the lambda
 // derivative of the three normal-stress updates) and H_mu += dt^2 (4 (e_rr^2 +
@@ -53,10 +58,10 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
          const float* __restrict__ pml_z, const float* __restrict__ ain,
          float* __restrict__ aout, const float* __restrict__ hist_hi, long long hist_stride,
          float* __restrict__ acc, float* __restrict__ acc_rho, float* __restrict__ acc_h,
-         long long cells_total)
+         float* __restrict__ wgrad, long long cells_total)
 {
     static_assert(TRE % W == 0 && TRE > 2 * T && 64 > 2 * T, "tile too small for the halo");
-    constexpr bool RHO = (X & 1) != 0, HES = (X & 2) != 0;
+    constexpr bool RHO = (X & 1) != 0, HES = (X & 2) != 0, WAV = (X & 4) != 0;
     constexpr int RPT = TRE / W;
     constexpr bool LDSE = RPT >= 4;
     constexpr int LDW = (TRE + 2) * 64;
@@ -247,6 +252,11 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
                     tzz[j] += v;
                 }
                 const float sa = trr[j] + ttt[j] + tzz[j];
+                if constexpr (WAV) {
+                    // the tile that owns row 0 and the source cell's lane
+                    if (i == 0 && lown && k == S.src_k)
+                        wgrad[S.wave_off + (n_hi - t)] = S.src_scale * sa;
+                }
                 float Err = dl[j] * sa + d2m[j] * trr[j];
                 const float Ett = dl[j] * sa + d2m[j] * ttt[j];
                 float Ezz = dl[j] * sa + d2m[j] * tzz[j];
