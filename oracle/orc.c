@@ -435,6 +435,33 @@ static double src_scale(const grid *G)
     return G->dt / (ORC_PI * G->dr * G->dr * G->dz);
 }
 
+/* Source scale of the assembled step of the given order.
+ *
+ * A point source must inject its whole strength in the norm in which the
+ * discrete divergence theorem holds.  With F = r v_r (even across the axis
+ * once v_r is odd) and the radial divergence h r_{i+1/2} div_i = D_i =
+ * c1 (F_{i+1} - F_i) + c2 (F_{i+2} - F_{i-1}), the sum over cells of
+ * w_i D_i telescopes to the outer boundary only if, for every interior
+ * node j, c1 (w_{j-1} - w_j) + c2 (w_{j-2} - w_{j+1}) = 0, and at the first
+ * node (which also meets the mirror image F_{-1} = F_1)
+ * c1 (w_0 - w_1) - c2 (w_0 + w_2) = 0.  With plain cell volumes (w = 1) the
+ * first condition holds and the second leaves -2 c2 F_1: order 2 (c2 = 0)
+ * conserves, order 4 does not.  Writing w_i = 1 + d_i, the interior
+ * recurrence has the roots 1 and z = 13 -/+ 2 sqrt(42) for c1 = 9/8,
+ * c2 = -1/24; the bounded solution is d_i = A z^i with z = 13 - 2 sqrt(42),
+ * and the first-node condition gives A = 2 c2 / (c1 (1 - z) - c2 (1 + z^2))
+ * = -1 / (7 + sqrt(42)).  The on-axis cell's weight is then
+ * w_0 = 1 + A = sqrt(6/7): the mirrored fourth-order step sees that fraction
+ * of the cell's volume, so the source is divided by it. */
+static double src_scale_order(const grid *G, int order)
+{
+    if (order != 4) return src_scale(G);
+    const double c1 = 9.0 / 8.0, c2 = -1.0 / 24.0;
+    const double z = 13.0 - 2.0 * sqrt(42.0);
+    const double w0 = 1.0 + 2.0 * c2 / (c1 * (1.0 - z) - c2 * (1.0 + z * z));
+    return src_scale(G) / w0;
+}
+
 static int geom_ok(const orc_geom *g)
 {
     int NZ = g->nz + 2 * g->pz;
@@ -885,8 +912,10 @@ void orc_starting_model(int32_t NR, int32_t NZ, double dr, double a, double dist
  * (1/r) d(r f)/dr of the wider stencil.  Values beyond the outer radius and
  * the axial ends are zero; across the axis the fields are mirrored: those at
  * half radial positions (normal stresses, v_z) are even, those at integer
- * positions (v_r, tau_rz) odd and zero on the axis.  Medium averaging, PML,
- * source and receivers are those of the second-order step.
+ * positions (v_r, tau_rz) odd and zero on the axis.  Medium averaging, PML
+ * and receivers are those of the second-order step; the on-axis source is
+ * divided by the axis cell's weight in the norm of the discrete divergence
+ * theorem (src_scale_order), which is 1 at order 2.
  *
  * Each row of V and S is assembled from the stencil as written; the adjoint is
  * the transpose of the assembled rows applied in scatter form, so it is exact
@@ -1269,7 +1298,7 @@ int orc_forward_asm(const orc_geom *g, int32_t order, const double *lam, const d
     const size_t N = (size_t)G.NR * G.NZ;
     double *s = calloc(P_N * N, sizeof(double)), *tmp = calloc(P_N * N, sizeof(double));
     int rc = (!s || !tmp) ? -1 : 0;
-    const double sc = src_scale(&G);
+    const double sc = src_scale_order(&G, order);
     for (int n = 0; n < g->nt && !rc; ++n) {
         asm_step(&O, N, NZ, s, tmp, g->src_k, sc * wavelet[n], NULL);
         for (int j = 0; j < g->nrec; ++j) {
@@ -1350,7 +1379,7 @@ int orc_gradient_asm(const orc_geom *g, int32_t order, const double *lam, const 
         grid_free(&G);
         return -1;
     }
-    const double sc = src_scale(&G);
+    const double sc = src_scale_order(&G, order);
     memset(glam, 0, N * sizeof(double));
     memset(gmu, 0, N * sizeof(double));
     memset(illum, 0, N * sizeof(double));
