@@ -8,7 +8,8 @@
 //   I f =  G1 (f(+1/2) + f(-1/2)) + G2 (f(+3/2) + f(-3/2)),
 // C1 = 9/8, C2 = -1/24, G1 = 9/16, G2 = -1/16.  Across the axis the fields
 // are mirrored: normal stresses and v_z (half radial positions) are even,
-// v_r and tau_rz (integer radial positions) odd and zero on the axis.
+// v_r and tau_rz (integer radial positions) odd and zero on the axis, and the
+// on-axis source is normalised by the axis cell's weight (AXIS_SRC).
 //
 // One kernel per step and direction, on tiles of TK = 64 axial by TI = 12
 // radial cells with one thread per owned cell (768 threads; taller tiles were
@@ -38,6 +39,15 @@ namespace bhfwi {
 namespace o4 {
 
 constexpr float C1 = 9.0f / 8.0f, C2 = -1.0f / 24.0f, G1 = 9.0f / 16.0f, G2 = -1.0f / 16.0f;
+
+// Source normalisation on the axis.  Mirrored across the axis, the four-point
+// radial divergence conserves the flux sum_i w_i h r_{i+1/2} div_i only for
+// near-axis cell weights w_i = 1 - z^i / (7 + sqrt 42), z = 13 - 2 sqrt 42
+// (the bounded solution of C1 (w_{j-1} - w_j) + C2 (w_{j-2} - w_{j+1}) = 0
+// that also cancels the image term C2 F_{-1} = C2 F_1 at the first node).
+// The on-axis cell weighs w_0 = sqrt(6/7) of its volume, so the source is
+// injected divided by that weight: sqrt(7/6).
+constexpr float AXIS_SRC = 1.0801234497346435f;
 
 constexpr int TK = 64, TI = 12;
 // P-region: the tile plus two cells; D-region: the tile plus four
@@ -363,7 +373,7 @@ k_fwd4(const ShotDev* __restrict__ shots, const int* __restrict__ tile_start, in
     float ntt = ttt(i, k) + dt * (l * tr + 2.0f * u * ett);
     float nzz = tzz(i, k) + dt * (l * tr + 2.0f * u * ezz);
     if (i == 0 && k == S.src_k) {
-        const float sv = S.src_scale * wavelet[S.wave_off + n];
+        const float sv = AXIS_SRC * S.src_scale * wavelet[S.wave_off + n];
         nrr += sv;
         ntt += sv;
         nzz += sv;
