@@ -57,10 +57,13 @@ ADJ_BLOCK_BYTES_PER_CELL_STEP = 8
 # same shapes, tile map and workload; otherwise traffic is null.
 PMC_SOURCES = ("paper_2005_00281_amd/csrc/bhfwi_tb_adj.hip",
                "paper_2005_00281_amd/csrc/bhfwi_tb_fwd.hip",
+               "paper_2005_00281_amd/csrc/bhfwi_kernels.hip",
                "paper_2005_00281_amd/csrc/bhfwi_internal.h",
                "paper_2005_00281_amd/csrc/bhfwi_host.hip")
 PMC_TRAFFIC = {
     # (kernel, tile_map, workload, sources sha256[:16]): (read bytes, write bytes)
+    ("k_adj_tb<6, 32, 16, 0, 0> + k_adj_tb<6, 32, 16, 1, 0>", 1, "c3", "2124f23387c3c5a7"):
+        (9441306409, 4475121044),
 }
 
 # temporally blocked shapes (T, tile rows incl. halo, waves) of both kernels,
@@ -278,6 +281,53 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": 4 * n, "copy_kib": 4 * n / 1024}))
 
 
+def trace_gaps(path):
+    """Idle time between the kernels of a rocprofv3 kernel trace (its
+    kernel_trace.csv): dispatches sorted by start, the gap after each one up
+    to the next start (0 when they overlap), summed over the whole trace and
+    over consecutive pairs of time-step kernels (the launch gaps a persistent
+    launch would remove; gaps of 1 ms or more between them are host-side
+    pauses and are counted apart).  Prints one JSON line."""
+    import csv
+    ev = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            ev.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]))
+    ev.sort()
+    step = ("k_fwd_tb", "k_adj_tb", "k_fwd_step", "k_adj_step", "k_fwd4", "k_adj4")
+    is_step = [any(x in name for x in step) for _, _, name in ev]
+    busy, end_max, gaps, step_gaps = 0, None, [], []
+    for j, (t0, t1, _) in enumerate(ev):
+        if end_max is None or t0 >= end_max:
+            busy += t1 - t0
+            if end_max is not None:
+                gaps.append(t0 - end_max)
+                if is_step[j] and is_step[j - 1]:
+                    step_gaps.append(t0 - end_max)
+        elif t1 > end_max:
+            busy += t1 - end_max
+        end_max = t1 if end_max is None else max(end_max, t1)
+    span = ev[-1][1] - ev[0][0] if ev else 0
+    # gaps of a millisecond or more are host-side pauses (stage boundaries,
+    # synchronisations), not launch latency
+    pauses = [g for g in step_gaps if g >= 1000000]
+    step_gaps = [g for g in step_gaps if g < 1000000]
+    sg = sorted(step_gaps)
+    step_busy = sum(t1 - t0 for (t0, t1, _), s in zip(ev, is_step) if s)
+    out = {"trace": os.path.basename(path), "dispatches": len(ev),
+           "step_dispatches": sum(is_step), "span_ms": round(span / 1e6, 3),
+           "busy_ms": round(busy / 1e6, 3), "idle_ms": round(sum(gaps) / 1e6, 3),
+           "step_kernel_ms": round(step_busy / 1e6, 3),
+           "step_pairs": len(sg) + len(pauses), "step_gap_ms": round(sum(sg) / 1e6, 3),
+           "host_pauses": len(pauses), "host_pause_ms": round(sum(pauses) / 1e6, 3),
+           "step_gap_frac_of_step_time": round(sum(sg) / step_busy, 5) if step_busy else None,
+           "step_gap_us": {"mean": round(sum(sg) / len(sg) / 1e3, 3) if sg else None,
+                           "p50": round(sg[len(sg) // 2] / 1e3, 3) if sg else None,
+                           "p99": round(sg[int(0.99 * (len(sg) - 1))] / 1e3, 3) if sg else None,
+                           "max": round(sg[-1] / 1e3, 3) if sg else None}}
+    print(json.dumps(out), flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -324,6 +374,8 @@ def parse():
     ap.add_argument("--budget-gb", type=float, default=0.0,
                     help="HBM budget for the planner (0: 80%% of the device)")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--trace-gaps", default="",
+                    help="summarise the idle gaps of a rocprofv3 kernel_trace.csv and exit")
     ap.add_argument("--semblance", action="store_true",
                     help="measure the starting-model semblance stage instead")
     ap.add_argument("--progress", action="store_true",
@@ -353,6 +405,9 @@ def parse():
 
 def main():
     args = parse()
+    if args.trace_gaps:
+        trace_gaps(args.trace_gaps)
+        return
     if args.copy_calibration:
         copy_calibration()
         return

@@ -25,6 +25,10 @@ __device__ inline float from_lane_above(float v)  // lane l <- lane l + 1
         float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
 }
 
+// Reciprocal within 1 ulp (one v_rcp_f32 instead of a correctly rounded
+// division): the medium coefficients and the 1/r factors are set up with it.
+__device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // A value that is the same in every lane (it depends on the radial row of
 // the wave only) kept in a scalar register.
 __device__ inline float wave_uniform(float v)

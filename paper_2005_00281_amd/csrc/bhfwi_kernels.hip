@@ -36,7 +36,7 @@ __device__ __forceinline__ float ld(const float* __restrict__ p, long long idx, 
 __device__ __forceinline__ float mu_harm(float a, float b, float c, float d)
 {
     return (a > 0.f && b > 0.f && c > 0.f && d > 0.f)
-               ? 4.0f / (1.0f / a + 1.0f / b + 1.0f / c + 1.0f / d)
+               ? 4.0f * rcp(rcp(a) + rcp(b) + rcp(c) + rcp(d))
                : 0.0f;
 }
 
@@ -166,8 +166,8 @@ k_fwd_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
                 if (st) Fo[oPZ + iz(ip)] = psi;
                 Dz += psi;
             }
-            const float hoop = ((B.trr - B.ttt) + (A.trr - A.ttt)) * (0.5f / (ip * dr));
-            const float bR = 2.0f / (A.rho + B.rho);
+            const float hoop = ((B.trr - B.ttt) + (A.trr - A.ttt)) * (0.5f * rcp(ip * dr));
+            const float bR = 2.0f * rcp(A.rho + B.rho);
             vrn1 = kin ? B.vr + dt * bR * (Dr + Dz + hoop) : 0.f;
         }
         // ---- v_z at Z(i), i >= 0
@@ -189,8 +189,8 @@ k_fwd_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
                 if (st) Fo[oPZ + LZ + iz(i)] = psi;
                 Dz += psi;
             }
-            const float hoop = (B.trz + A.trz) * (0.5f / ((i + 0.5f) * dr));
-            const float bZ = 2.0f / (A.rho + rho0_kp);
+            const float hoop = (B.trz + A.trz) * (0.5f * rcp((i + 0.5f) * dr));
+            const float bZ = 2.0f * rcp(A.rho + rho0_kp);
             vzn0 = kin ? A.vz + dt * bZ * (Dr + Dz + hoop) : 0.f;
         }
         float mu0_kp = sh_dn(A.mu);
@@ -201,7 +201,7 @@ k_fwd_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
             const long long c = (long long)i * NZ + kc;
             // ---- C node: normal stresses
             float err = (vrn1 - vrn0) * idr;
-            const float ett = (vrn1 + vrn0) * (0.5f / ((i + 0.5f) * dr));
+            const float ett = (vrn1 + vrn0) * (0.5f * rcp((i + 0.5f) * dr));
             float ezz = (vzn0 - vzn0_km) * idz;
             if (i >= nr) {  // E
                 const float psi = prt[3 * NR + i] * A.pE + prt[2 * NR + i] * err;
@@ -502,10 +502,10 @@ k_adj_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
         if (ip >= 1 && ip < NR) {
             const long long c = (long long)ip * NZ + kc;
             // the increment first: the density correlation needs it unrounded
-            const float dar = (X0.Err - X1.Err) * idr + X0.Ett * (0.5f / ((ip - 0.5f) * dr)) +
-                              X1.Ett * (0.5f / ((ip + 0.5f) * dr)) + (Ez1_km - X1.Ez) * idz;
+            const float dar = (X0.Err - X1.Err) * idr + X0.Ett * (0.5f * rcp((ip - 0.5f) * dr)) +
+                              X1.Ett * (0.5f * rcp((ip + 0.5f) * dr)) + (Ez1_km - X1.Ez) * idz;
             const float avr = Q.avr + dar;
-            const float W = kin ? dt * (2.0f / (X0.rho + X1.rho)) * avr : 0.f;
+            const float W = kin ? dt * (2.0f * rcp(X0.rho + X1.rho)) * avr : 0.f;
             float aDr = W, aDz = W;
             if (ip >= nr) {  // A-bar
                 const float qv = Q.qA + W;
@@ -522,7 +522,7 @@ k_adj_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
             if (acc_rho && own_ip) acc_rho[S.cell_off + c] += dar * Q.vrh;
             R1_aDr = aDr;
             R1_aDzR = aDz;
-            R1_hR = W * (0.5f / (ip * dr));
+            R1_hR = W * (0.5f * rcp(ip * dr));
         }
         // ---- Z(i)
         float Z_aDrZ = 0.f, Z_WZ = 0.f, Z_aDzZ = 0.f;
@@ -533,7 +533,7 @@ k_adj_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
             const long long c = (long long)i * NZ + kc;
             const float daz = (X0.Ezz - Ezz0_kp) * idz + (X0.Er - X1.Er) * idr;
             const float avz = P.avz + daz;
-            const float W = kin ? dt * (2.0f / (X0.rho + rho0_kp)) * avz : 0.f;
+            const float W = kin ? dt * (2.0f * rcp(X0.rho + rho0_kp)) * avz : 0.f;
             float aDr = W, aDz = W;
             if (i >= nr) {  // C-bar (radial, half position)
                 const float qv = P.qC + W;
@@ -564,10 +564,10 @@ k_adj_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
             const float rh = (i + 0.5f) * dr;
             float nrz = 0.f;
             if (i >= 1)
-                nrz = X0.trz + (R0_aDzR - aDzR_kp) * idz - Z_aDrZ * idr + Z_WZ * (0.5f / rh) + zm;
+                nrz = X0.trz + (R0_aDzR - aDzR_kp) * idz - Z_aDrZ * idr + Z_WZ * (0.5f * rcp(rh)) + zm;
             // Eq. 7-8: correlate the strain rates of v^{n+1/2} with dJ/dtau^{n+1}
             const float err = (vrh1 - vrh0) * idr;
-            const float ett = (vrh1 + vrh0) * (0.5f / rh);
+            const float ett = (vrh1 + vrh0) * (0.5f * rcp(rh));
             const float ezz = (vzh0 - vzh0_km) * idz;
             const float sa = X0.trr + X0.ttt + X0.tzz;
             // source wavelet gradient (optional): dJ/dw[n] = src_scale dJ/dtau^{n+1}
@@ -614,7 +614,7 @@ k_adj_step(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int
                 g_e[c] = P.ge + dge;
             }
         }
-        zm = (i >= 0) ? Z_aDrZ * idr + Z_WZ * (0.5f / ((i + 0.5f) * dr)) : 0.f;
+        zm = (i >= 0) ? Z_aDrZ * idr + Z_WZ * (0.5f * rcp((i + 0.5f) * dr)) : 0.f;
         R0_aDr = R1_aDr;
         R0_aDzR = R1_aDzR;
         R0_hR = R1_hR;

@@ -19,7 +19,10 @@
 // The gradient and illumination sums stay in registers for the T steps and
 // are added to the accumulators once per launch (owned cells only).  As in
 // the forward kernel the step loop has no per-cell branches: zero
-// coefficients keep cells outside the grid and the axis nodes inert.
+// coefficients keep cells outside the grid and the axis nodes inert.  (Unlike
+// the forward kernel it does not skip the rows that have fallen out of the
+// correct region: the branches cost more registers than the adjoint's 64
+// have to spare, and the spills cost more than the skipped rows.)
 //
 // Optional outputs, selected by the bits of X (extensions of the paper, which
 // holds the density fixed and gives the preconditioner only as diagonal):
@@ -153,12 +156,12 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
         const float m_imkp = up ? mu[mm + k1] : 0.f;
         dl[j] = in ? dt * lam[m + kc] : 0.f;
         d2m[j] = dt * 2.0f * m0;
-        dbR[j] = up ? dt * 2.0f / (r_im + r0) : 0.f;
-        dbZ[j] = in ? dt * 2.0f / (r0 + r_kp) : 0.f;
+        dbR[j] = up ? dt * 2.0f * rcp(r_im + r0) : 0.f;
+        dbZ[j] = in ? dt * 2.0f * rcp(r0 + r_kp) : 0.f;
         dmuS[j] = up ? dt * mu_harm(m_im, m0, m_imkp, m_kp) : 0.f;
-        rR[j] = wave_uniform((iin && i >= 1) ? 0.5f / (i * dr) : 0.f);
-        rRm[j] = wave_uniform((iin && i >= 1) ? 0.5f / ((i - 0.5f) * dr) : 0.f);
-        rZ[j] = wave_uniform(iin ? 0.5f / ((i + 0.5f) * dr) : 0.f);
+        rR[j] = wave_uniform((iin && i >= 1) ? 0.5f * rcp(i * dr) : 0.f);
+        rRm[j] = wave_uniform((iin && i >= 1) ? 0.5f * rcp((i - 0.5f) * dr) : 0.f);
+        rZ[j] = wave_uniform(iin ? 0.5f * rcp((i + 0.5f) * dr) : 0.f);
         mrow[j] = wave_uniform((iin && i >= 1) ? 1.f : 0.f);
         qA[j] = qB[j] = qC[j] = qD[j] = 0.f;
         pTr[j] = pRr[j] = pTz[j] = pZz[j] = pG[j] = pH[j] = 0.f;
@@ -308,26 +311,25 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
                 const float ezz = (vz0 - vz_km) * idz;
                 const float ez = (vr_kp - vr0) * idz;
                 const float er = (vz0 - vz_im) * idr;
+                // the sums leave out the factors dt (g_lambda, g_muS), 2 dt
+                // (g_mu) and dt/4 (illumination), applied once at write-back
                 const float sa = trr[j] + ttt[j] + tzz[j];
-                float dgl = (err + ett + ezz) * sa;
-                float dgm = 2.0f * (err * trr[j] + ett * ttt[j] + ezz * tzz[j]);
-                float dgs = (ez + er) * trz[j];
+                gl[j] = fmaf(err + ett + ezz, sa, gl[j]);
+                gm[j] = fmaf(err, trr[j], fmaf(ett, ttt[j], fmaf(ezz, tzz[j], gm[j])));
+                gs[j] = fmaf(ez + er, trz[j], gs[j]);
                 if constexpr (PML) {
                     const float idt = 1.0f / dt;
-                    dgl += idt * (a_rh[j] * err * pTr[j] + a_zi * ezz * pTz[j]);
-                    dgm += idt * 2.0f * (a_rh[j] * err * pRr[j] + a_zi * ezz * pZz[j]);
-                    dgs += idt * (a_zh * ez * pG[j] + a_ri[j] * er * pH[j]);
+                    gl[j] += idt * (a_rh[j] * err * pTr[j] + a_zi * ezz * pTz[j]);
+                    gm[j] += idt * (a_rh[j] * err * pRr[j] + a_zi * ezz * pZz[j]);
+                    gs[j] += idt * (a_zh * ez * pG[j] + a_ri[j] * er * pH[j]);
                 }
                 if constexpr (HES) {
                     const float dv = err + ett + ezz, es = mrow[j] * (ez + er);
                     hL[j] += 3.0f * dv * dv;
                     hM[j] += 4.0f * (err * err + ett * ett + ezz * ezz) + es * es;
                 }
-                const float ur = 0.5f * (vr0 + vr1), uz = 0.5f * (vz_km + vz0);
-                gl[j] += dt * dgl;
-                gm[j] += dt * dgm;
-                gs[j] += dt * dgs;
-                ge[j] += dt * (ur * ur + uz * uz);
+                const float ur = vr0 + vr1, uz = vz_km + vz0;  // twice the C-node means
+                ge[j] = fmaf(ur, ur, fmaf(uz, uz, ge[j]));
                 // transposed stress update into a_v, then the transposed velocity update
                 // with four or more rows per thread the drivers this lane
                 // wrote to LDS are read back instead of being held in registers
@@ -436,10 +438,10 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
             }
         }
         float* g = acc + S.cell_off + c;
-        g[0] += gl[j];
-        g[cells_total] += gm[j];
-        if (i >= 1) g[2 * cells_total] += gs[j];
-        g[3 * cells_total] += ge[j];
+        g[0] += dt * gl[j];
+        g[cells_total] += (2.0f * dt) * gm[j];
+        if (i >= 1) g[2 * cells_total] += dt * gs[j];
+        g[3 * cells_total] += (0.25f * dt) * ge[j];
         if constexpr (RHO) {
             float* gr = acc_rho + S.cell_off + c;
             if (i >= 1) gr[0] += gR[j];

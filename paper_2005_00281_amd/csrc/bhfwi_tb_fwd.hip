@@ -11,7 +11,9 @@
 // with DPP wavefront shifts.  Every step needs the neighbours' previous values, so the
 // correct region shrinks by one cell per step on every side; after T steps it
 // is exactly the owned tile, which is all that is written back.  State
-// crosses HBM once per T steps instead of once per step.
+// crosses HBM once per T steps instead of once per step.  Rows that have
+// fallen out of the correct region are skipped (whole-wave branches), which
+// trims the halo recomputation by about T (T - 1) of T TRE row-steps.
 //
 // The step loop has no per-cell branches: cells outside the grid, v_r and
 // tau_rz on the axis and the non-source cells carry zero coefficients, so the
@@ -129,12 +131,12 @@ k_fwd_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
         const float m_imkp = up ? mu[mm + k1] : 0.f;
         cl[j] = in ? dt * lam[m + kc] : 0.f;
         c2m[j] = dt * 2.0f * m0;
-        dbR[j] = up ? dt * 2.0f / (r_im + r0) : 0.f;
-        dbZ[j] = in ? dt * 2.0f / (r0 + r_kp) : 0.f;
+        dbR[j] = up ? dt * 2.0f * rcp(r_im + r0) : 0.f;
+        dbZ[j] = in ? dt * 2.0f * rcp(r0 + r_kp) : 0.f;
         dmuS[j] = up ? dt * mu_harm(m_im, m0, m_imkp, m_kp) : 0.f;
         srcw[j] = (in && i == 0 && k == S.src_k) ? S.src_scale : 0.f;
-        rR[j] = wave_uniform((iin && i >= 1) ? 0.5f / (i * dr) : 0.f);
-        rZ[j] = wave_uniform(iin ? 0.5f / ((i + 0.5f) * dr) : 0.f);
+        rR[j] = wave_uniform((iin && i >= 1) ? 0.5f * rcp(i * dr) : 0.f);
+        rZ[j] = wave_uniform(iin ? 0.5f * rcp((i + 0.5f) * dr) : 0.f);
         pA[j] = pB[j] = pC[j] = pD[j] = pE[j] = pF[j] = pG[j] = pH[j] = 0.f;
         a_ri[j] = a_rh[j] = 0.f;
         b_ri[j] = b_rh[j] = 1.f;
@@ -173,14 +175,34 @@ k_fwd_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
     }
     __syncthreads();
 
+    // byte offset of this lane's cell in each row within a history plane
+    unsigned hoff[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int i = wk.z - T + wave + W * j;
+        hoff[j] = (unsigned)(max(i, 0) * NZ + kc) * 4u;
+    }
+    // Rows that still matter at step t: the correct region shrinks one row
+    // per step on each side, so after step t only rows t + 1 .. TRE - t - 2
+    // hold correct values, and they read rows t .. TRE - t - 1 of this step.
+    // Rows e < t and e >= TRE - t are skipped (the test is uniform over a
+    // wave); a row that reads one of them is itself discarded after the step.
+    auto live = [&](int e, int t) { return e >= t && e < TRE - t; };
+
     auto steps = [&](auto PMLC) {
         constexpr bool PML = decltype(PMLC)::value != 0;
         for (int t = 0; t < ns; ++t) {
             const int n = n0 + t;
             const float wv = Lwav[t];
+            // this step's history planes (uniform base; per-row byte offsets)
+            char* const hvr_t =
+                hist ? reinterpret_cast<char*>(hist + (long long)t * hist_stride + S.cell_off)
+                     : nullptr;
+            char* const hvz_t = hist ? hvr_t + 4 * cells_total : nullptr;
             // ---- velocities (R and Z nodes) from the stresses
 #pragma unroll
             for (int j = 0; j < RPT; ++j) {
+                if (!live(wave + W * j, t)) continue;  // uniform
                 const int x = (wave + W * j + 1) * 64 + lane;
                 const float trr_m = L[TRR][x - 64], ttt_m = L[TTT][x - 64];
                 const float trz_km = from_lane_below(trz[j]), trz_ip = L[TRZ][x + 64];
@@ -209,6 +231,7 @@ k_fwd_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
 #pragma unroll
             for (int j = 0; j < RPT; ++j) {
                 const int e = wave + W * j;
+                if (!live(e, t)) continue;  // uniform
                 const int x = (e + 1) * 64 + lane;
                 const float vr_ip = L[VR][x + 64], vz_km = from_lane_below(vz[j]);
                 const float vr_kp = from_lane_above(vr[j]), vz_im = L[VZ][x - 64];
@@ -238,10 +261,8 @@ k_fwd_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
                 const int i = wk.z - T + e;
                 const bool own = kin && lown && e >= T && e < TRE - T && i < NR;
                 if (hist && own) {
-                    float* h = hist + (long long)t * hist_stride + S.cell_off;
-                    const long long c = (long long)i * NZ + k;
-                    h[c] = vr[j];
-                    h[cells_total + c] = vz[j];
+                    *reinterpret_cast<float*>(hvr_t + hoff[j]) = vr[j];
+                    *reinterpret_cast<float*>(hvz_t + hoff[j]) = vz[j];
                 }
                 if (i == 0 && own && rj >= 0)
                     traces[S.trace_off + (long long)rj * S.nt + n] =
