@@ -473,6 +473,7 @@ class Survey:
             probe_steps = min(z.ckpt_every, z.nt_max, 256)
         tr = torch.empty(z.trace_elems, dtype=torch.float32, device=self.device)
         acc = torch.empty(z.acc_elems, dtype=torch.float32, device=self.device)
+        kept = dict(self._ws)  # the probe's scratch is not kept past the call
         fw, aw = self.workspace("fwd"), self.workspace("adj")
         best, ms = Tune(), C.c_float()
         n = self.model_shape[0] * self.model_shape[1]
@@ -480,6 +481,8 @@ class Survey:
                                      _f32(rho, n), _f32(wavelet, z.wavelet_elems), _f32(tr),
                                      _ptr(fw), fw.numel(), _ptr(aw), aw.numel(), _f32(acc),
                                      int(probe_steps), C.byref(best), C.byref(ms)), self._h)
+        del fw, aw, tr, acc
+        self._ws = kept
         if full:
             best.full_history = 1
             self.set_tune(full_history=1)

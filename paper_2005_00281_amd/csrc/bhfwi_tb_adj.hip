@@ -95,7 +95,9 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
     const int ihi = wk.z - T + TRE - 1;
     const int klo = wk.y - T, khi = wk.y - T + 63;
     // PM = 0: the launch holds only tiles clear of every PML layer
-    const bool tile_pml = PM != 0 && ((ihi >= nr) || (klo < pz) || (khi >= NZ - pz));
+    const bool tile_pr = PM != 0 && ihi >= nr;                        // reaches the radial layer
+    const bool tile_pz = PM != 0 && ((klo < pz) || (khi >= NZ - pz));  // reaches an axial layer
+    const bool tile_pml = tile_pr || tile_pz;
 
     const float* __restrict__ Ai = ain + S.ast_off;
     float* __restrict__ Ao = aout + S.ast_off;
@@ -236,8 +238,12 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
     fetch_hist(t0);
     __syncthreads();
 
-    auto steps = [&](auto PMLC) {
-        constexpr bool PML = decltype(PMLC)::value != 0;
+    // The step loop in three PML forms besides the plain one: radial and
+    // axial memories, radial only, axial only.  A tile that does not reach a
+    // layer has zero coefficients for it everywhere, so leaving that layer's
+    // terms out changes nothing; most PML tiles reach the radial layer only.
+    auto steps = [&](auto PRC, auto PZC) {
+        constexpr bool PR = decltype(PRC)::value != 0, PZ = decltype(PZC)::value != 0;
         for (int t = t0; t < nsteps; ++t) {
             float Err_[RPT], Ett_[RPT], Ezz_[RPT], Ez_[RPT], Er_[RPT];
             // ---- A: residual, drivers, stage the stored velocities
@@ -265,19 +271,22 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
                 float Ezz = dl[j] * sa + d2m[j] * tzz[j];
                 float Ez = dmuS[j] * trz[j];
                 float Er = Ez;
-                if constexpr (PML) {
+                // a (lambda Phi_T + 2 mu Phi_R); dl, d2m, dmuS carry a factor dt
+                if constexpr (PR) {
                     pTr[j] = dt * sa + b_rh[j] * pTr[j];
                     pRr[j] = dt * trr[j] + b_rh[j] * pRr[j];
+                    pH[j] = dt * trz[j] + b_ri[j] * pH[j];
+                    const float idt = 1.0f / dt;
+                    Err += a_rh[j] * idt * (dl[j] * pTr[j] + d2m[j] * pRr[j]);
+                    Er += a_ri[j] * idt * dmuS[j] * pH[j];
+                }
+                if constexpr (PZ) {
                     pTz[j] = dt * sa + b_zi * pTz[j];
                     pZz[j] = dt * tzz[j] + b_zi * pZz[j];
                     pG[j] = dt * trz[j] + b_zh * pG[j];
-                    pH[j] = dt * trz[j] + b_ri[j] * pH[j];
-                    // a (lambda Phi_T + 2 mu Phi_R); dl, d2m, dmuS carry a factor dt
                     const float idt = 1.0f / dt;
-                    Err += a_rh[j] * idt * (dl[j] * pTr[j] + d2m[j] * pRr[j]);
                     Ezz += a_zi * idt * (dl[j] * pTz[j] + d2m[j] * pZz[j]);
                     Ez += a_zh * idt * dmuS[j] * pG[j];
-                    Er += a_ri[j] * idt * dmuS[j] * pH[j];
                 }
                 L[ERR][x] = Err;
                 L[ETT][x] = Ett;
@@ -317,11 +326,17 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
                 gl[j] = fmaf(err + ett + ezz, sa, gl[j]);
                 gm[j] = fmaf(err, trr[j], fmaf(ett, ttt[j], fmaf(ezz, tzz[j], gm[j])));
                 gs[j] = fmaf(ez + er, trz[j], gs[j]);
-                if constexpr (PML) {
+                if constexpr (PR) {
                     const float idt = 1.0f / dt;
-                    gl[j] += idt * (a_rh[j] * err * pTr[j] + a_zi * ezz * pTz[j]);
-                    gm[j] += idt * (a_rh[j] * err * pRr[j] + a_zi * ezz * pZz[j]);
-                    gs[j] += idt * (a_zh * ez * pG[j] + a_ri[j] * er * pH[j]);
+                    gl[j] += idt * (a_rh[j] * err * pTr[j]);
+                    gm[j] += idt * (a_rh[j] * err * pRr[j]);
+                    gs[j] += idt * (a_ri[j] * er * pH[j]);
+                }
+                if constexpr (PZ) {
+                    const float idt = 1.0f / dt;
+                    gl[j] += idt * (a_zi * ezz * pTz[j]);
+                    gm[j] += idt * (a_zi * ezz * pZz[j]);
+                    gs[j] += idt * (a_zh * ez * pG[j]);
                 }
                 if constexpr (HES) {
                     const float dv = err + ett + ezz, es = mrow[j] * (ez + er);
@@ -351,16 +366,18 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
                 float aDr = W1, aDzR = W1;
                 const float W2 = dbZ[j] * avz[j];
                 float aDrZ = W2, aDzZ = W2;
-                if constexpr (PML) {
+                if constexpr (PR) {
                     float q = qA[j] + W1;
                     qA[j] = b_ri[j] * q;
                     aDr += a_ri[j] * q;
-                    q = qB[j] + W1;
-                    qB[j] = b_zi * q;
-                    aDzR += a_zi * q;
                     q = qC[j] + W2;
                     qC[j] = b_rh[j] * q;
                     aDrZ += a_rh[j] * q;
+                }
+                if constexpr (PZ) {
+                    float q = qB[j] + W1;
+                    qB[j] = b_zi * q;
+                    aDzR += a_zi * q;
                     q = qD[j] + W2;
                     qD[j] = b_zh * q;
                     aDzZ += a_zh * q;
@@ -398,10 +415,21 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
             }
         }
     };
-    if (tile_pml)
-        steps(IntC<1>{});
-    else
-        steps(IntC<0>{});
+    if constexpr (X == 0) {
+        if (tile_pr && tile_pz)
+            steps(IntC<1>{}, IntC<1>{});
+        else if (tile_pr)
+            steps(IntC<1>{}, IntC<0>{});
+        else if (tile_pz)
+            steps(IntC<0>{}, IntC<1>{});
+        else
+            steps(IntC<0>{}, IntC<0>{});
+    } else {  // the extra outputs' registers leave no room for three PML loops
+        if (tile_pml)
+            steps(IntC<1>{}, IntC<1>{});
+        else
+            steps(IntC<0>{}, IntC<0>{});
+    }
 
     // ---- write back the owned tile and add the correlation sums
 #pragma unroll

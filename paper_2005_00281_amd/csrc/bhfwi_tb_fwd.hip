@@ -18,7 +18,8 @@
 // The step loop has no per-cell branches: cells outside the grid, v_r and
 // tau_rz on the axis and the non-source cells carry zero coefficients, so the
 // same arithmetic leaves them at zero.  The PML memories are updated only in
-// the instantiation of the loop used by tiles that touch a PML layer.
+// the instantiations of the loop used by tiles that touch a PML layer, and
+// only those of the layers (radial, axial) the tile reaches.
 #pragma once
 #include "bhfwi_internal.h"
 
@@ -69,7 +70,9 @@ k_fwd_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
     const int ihi = wk.z - T + TRE - 1;
     const int klo = wk.y - T, khi = wk.y - T + 63;
     // PM = 0: the launch holds only tiles clear of every PML layer
-    const bool tile_pml = PM != 0 && ((ihi >= nr) || (klo < pz) || (khi >= NZ - pz));
+    const bool tile_pr = PM != 0 && ihi >= nr;                        // reaches the radial layer
+    const bool tile_pz = PM != 0 && ((klo < pz) || (khi >= NZ - pz));  // reaches an axial layer
+    const bool tile_pml = tile_pr || tile_pz;
 
     const float* __restrict__ Fi = sin + S.fst_off;
     float* __restrict__ Fo = sout + S.fst_off;
@@ -189,8 +192,12 @@ k_fwd_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
     // wave); a row that reads one of them is itself discarded after the step.
     auto live = [&](int e, int t) { return e >= t && e < TRE - t; };
 
-    auto steps = [&](auto PMLC) {
-        constexpr bool PML = decltype(PMLC)::value != 0;
+    // The step loop in three PML forms besides the plain one: radial and
+    // axial memories, radial only, axial only.  A tile that does not reach a
+    // layer has zero coefficients for it everywhere, so leaving that layer's
+    // terms out changes nothing; most PML tiles reach the radial layer only.
+    auto steps = [&](auto PRC, auto PZC) {
+        constexpr bool PR = decltype(PRC)::value != 0, PZ = decltype(PZC)::value != 0;
         for (int t = 0; t < ns; ++t) {
             const int n = n0 + t;
             const float wv = Lwav[t];
@@ -211,13 +218,15 @@ k_fwd_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
                 float Dz = (trz[j] - trz_km) * idz;
                 float Dr2 = (trz_ip - trz[j]) * idr;
                 float Dz2 = (tzz_kp - tzz[j]) * idz;
-                if constexpr (PML) {
+                if constexpr (PR) {
                     pA[j] = b_ri[j] * pA[j] + a_ri[j] * Dr;
                     Dr += pA[j];
-                    pB[j] = b_zi * pB[j] + a_zi * Dz;
-                    Dz += pB[j];
                     pC[j] = b_rh[j] * pC[j] + a_rh[j] * Dr2;
                     Dr2 += pC[j];
+                }
+                if constexpr (PZ) {
+                    pB[j] = b_zi * pB[j] + a_zi * Dz;
+                    Dz += pB[j];
                     pD[j] = b_zh * pD[j] + a_zh * Dz2;
                     Dz2 += pD[j];
                 }
@@ -240,15 +249,17 @@ k_fwd_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
                 float ezz = (vz[j] - vz_km) * idz;
                 float ez = (vr_kp - vr[j]) * idz;
                 float er = (vz[j] - vz_im) * idr;
-                if constexpr (PML) {
+                if constexpr (PR) {
                     pE[j] = b_rh[j] * pE[j] + a_rh[j] * err;
                     err += pE[j];
+                    pH[j] = b_ri[j] * pH[j] + a_ri[j] * er;
+                    er += pH[j];
+                }
+                if constexpr (PZ) {
                     pF[j] = b_zi * pF[j] + a_zi * ezz;
                     ezz += pF[j];
                     pG[j] = b_zh * pG[j] + a_zh * ez;
                     ez += pG[j];
-                    pH[j] = b_ri[j] * pH[j] + a_ri[j] * er;
-                    er += pH[j];
                 }
                 const float ltr = cl[j] * (err + ett + ezz) + srcw[j] * wv;
                 trr[j] += ltr + c2m[j] * err;
@@ -271,10 +282,14 @@ k_fwd_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
             __syncthreads();
         }
     };
-    if (tile_pml)
-        steps(IntC<1>{});
+    if (tile_pr && tile_pz)
+        steps(IntC<1>{}, IntC<1>{});
+    else if (tile_pr)
+        steps(IntC<1>{}, IntC<0>{});
+    else if (tile_pz)
+        steps(IntC<0>{}, IntC<1>{});
     else
-        steps(IntC<0>{});
+        steps(IntC<0>{}, IntC<0>{});
 
     // ---- write back the owned tile
 #pragma unroll

@@ -441,7 +441,8 @@ def test_autograd_end_to_end_and_central_differences():
 
 def test_autotune_picks_a_valid_shape_and_stays_correct(tmp_path):
     """The autotuner times every shape on the survey, installs the fastest,
-    records it in the cache, and the chosen shape still matches the oracle."""
+    records it in the cache, keeps none of its scratch, and the chosen shape
+    still matches the oracle."""
     w = workloads.tiny(nr=40, nz=150, p=6, nt=300)
     _say("autotune tiny")
     d_o = oracle_traces(w)
@@ -451,6 +452,7 @@ def test_autotune_picks_a_valid_shape_and_stays_correct(tmp_path):
     cache = str(tmp_path / "tune.json")
     entry = sv.autotune(lam, mu, rho, wav, cache=cache)
     assert entry["probe_ms"] > 0
+    assert not sv._ws  # the probe's scratch is released (the caller sizes its own)
     t = sv.get_tune()
     assert t == {**t, **entry["tune"]}
     tr = sv.fwd_model(lam, mu, rho, wav)
