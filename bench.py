@@ -731,6 +731,8 @@ def plain_form(args, w, pl, observed, mask, rho, line_search, row_weight, autogr
         sv1 = P.Survey([sh], (w.NRg, w.NZg), ckpt_every=pl.ckpt_every[g_], order=args.order)
         sv1.set_tune(rows_per_wave=2, tb_steps=0, adj_tb_steps=0, use_graph=0,
                      full_history=1 if full else 0)
+        if args.order == 4:
+            sv1.set_fwd4_shape(0)
         wav1 = sv1.pack_wavelets([sh.wavelet])
         off = sum(len(w.shots[q].rec_k) * w.shots[q].nt for q in pl.groups[g_] if q < s_)
         obs1 = observed[g_][off: off + len(sh.rec_k) * sh.nt].clone()

@@ -5,6 +5,7 @@
 #include "bhfwi_tb_fwd.hip"
 #include "bhfwi_tb_adj.hip"
 #include "bhfwi_o4.hip"
+#include "bhfwi_o4_tb.hip"
 
 #include <algorithm>
 #include <cmath>
@@ -161,6 +162,8 @@ struct bhfwi_ctx {
     int order = 2;  // spatial order of the step: 2 or 4 (bhfwi_set_order)
     int* d_tile4 = nullptr;  // fourth order: first tile of each shot (nshot + 1)
     int ntile4 = 0;
+    Shape f4{2, 32, 16};  // fourth-order forward time blocks (T = 0: one step per launch)
+    TileSet f4tiles;      // their tiles (halo 3T)
     bhfwi_tune tune{};
     std::vector<int4> work;
     std::vector<int> work_nt;  // nt of each work item's shot, non-increasing
@@ -358,6 +361,10 @@ void rebuild_work(bhfwi_ctx* c)
     build_tiles(c, order, fs, pml_shape(fs, false), &c->ftiles);
     build_tiles(c, order, as, pml_shape(as, true), &c->atiles);
     build_tiles(c, order, xs, pml_shape(xs, true), &c->xtiles);
+    // fourth-order forward blocks: a three-cell halo per step, one shape for
+    // the interior and the PML tiles
+    const Shape h4{3 * c->f4.T, c->f4.TRE, c->f4.W};
+    build_tiles(c, order, h4, h4, &c->f4tiles);
 }
 
 int upload_work(bhfwi_ctx* c)
@@ -371,6 +378,7 @@ int upload_work(bhfwi_ctx* c)
                        hipMemcpyHostToDevice));
     if (int rc = upload_tiles(c, &c->ftiles)) return rc;
     if (int rc = upload_tiles(c, &c->atiles)) return rc;
+    if (int rc = upload_tiles(c, &c->f4tiles)) return rc;
     return upload_tiles(c, &c->xtiles);
 }
 
@@ -487,6 +495,51 @@ void fwd4_launch(bhfwi_ctx* c, hipStream_t st, int n, const float* lam, const fl
                        dim3(bhfwi::o4::TK * bhfwi::o4::TI), 0, st, c->d_shots, c->d_tile4,
                        c->nshot, n, lam, mu, rho, wav, c->d_rec, c->d_pml_r, c->d_pml_z, in, out,
                        traces, hist, (long long)c->cells);
+}
+
+// Fourth-order forward steps n0 .. n0 + nsteps - 1 in time blocks (interior
+// tiles, then PML tiles; the shapes compiled are listed in BHFWI_F4).
+#define BHFWI_F4(X) X(2, 32, 16)
+void fwd4_tb_launch(bhfwi_ctx* c, hipStream_t st, int n0, int nsteps, const float* lam,
+                    const float* mu, const float* rho, const float* wav, const float* in,
+                    float* out, float* traces, float* hist)
+{
+    const TileSet& ts = c->f4tiles;
+    const int na[2] = {active_tiles(ts, 0, n0), active_tiles(ts, 1, n0)};
+    if (na[0] + na[1] <= 0) return;
+    EvScope ev(c, st, hist ? 1 : 0);
+    for (int q = 0; q < 2; ++q) {
+        const int nact = na[q];
+        if (nact <= 0) continue;
+        const int T = c->f4.T, TRE = c->f4.TRE, W = c->f4.W;
+#define BHFWI_F4L(TT, RR, WW)                                                                  \
+        if (T == TT && TRE == RR && W == WW) {                                                 \
+            if (q == 0)                                                                        \
+                hipLaunchKernelGGL((bhfwi::o4::k_fwd4_tb<TT, RR, WW, 0>), dim3(nact),          \
+                                   dim3(64 * WW), 0, st, c->d_shots, ts.d[q], nact,            \
+                                   c->tune.tile_map, n0, nsteps, lam, mu, rho, wav, c->d_rec,  \
+                                   c->d_pml_r, c->d_pml_z, in, out, traces, hist,              \
+                                   (long long)(2 * c->cells), (long long)c->cells);            \
+            else                                                                               \
+                hipLaunchKernelGGL((bhfwi::o4::k_fwd4_tb<TT, RR, WW, 1>), dim3(nact),          \
+                                   dim3(64 * WW), 0, st, c->d_shots, ts.d[q], nact,            \
+                                   c->tune.tile_map, n0, nsteps, lam, mu, rho, wav, c->d_rec,  \
+                                   c->d_pml_r, c->d_pml_z, in, out, traces, hist,              \
+                                   (long long)(2 * c->cells), (long long)c->cells);            \
+            continue;                                                                          \
+        }
+        BHFWI_F4(BHFWI_F4L)
+#undef BHFWI_F4L
+    }
+}
+
+bool f4_ok(Shape sh)
+{
+#define BHFWI_F4S(TT, RR, WW) \
+    if (sh.T == TT && sh.TRE == RR && sh.W == WW) return true;
+    BHFWI_F4(BHFWI_F4S)
+#undef BHFWI_F4S
+    return sh.T == 0;
 }
 
 // Fourth-order adjoint step n fused with the correlation, in one launch;
@@ -737,10 +790,17 @@ void fwd_range(bhfwi_ctx* c, hipStream_t st, int n0, int n1, const float* lam, c
 {
     const int64_t hslot = 2 * c->cells;
     if (c->order == 4) {
-        for (int n = n0; n < n1; ++n) {
+        const int T4 = c->f4.T >= 2 ? c->f4.T : 1;
+        for (int n = n0; n < n1;) {
+            const int nb = std::min(T4, n1 - n);
             float* h = hist ? hist + (int64_t)(n - hist_base) * hslot : nullptr;
-            fwd4_launch(c, st, n, lam, mu, rho, wav, b[*parity], b[*parity ^ 1], traces, h);
+            if (T4 >= 2)
+                fwd4_tb_launch(c, st, n, nb, lam, mu, rho, wav, b[*parity], b[*parity ^ 1],
+                               traces, h);
+            else
+                fwd4_launch(c, st, n, lam, mu, rho, wav, b[*parity], b[*parity ^ 1], traces, h);
             *parity ^= 1;
+            n += nb;
         }
         return;
     }
@@ -786,6 +846,9 @@ int run_sequence(bhfwi_ctx* c, hipStream_t st, std::vector<uintptr_t> key, F&& r
     key.push_back((uintptr_t)c->tune.rec_overlap);
     key.push_back((uintptr_t)c->tune.full_history);
     key.push_back((uintptr_t)c->order);
+    key.push_back((uintptr_t)c->f4.T);
+    key.push_back((uintptr_t)c->f4.TRE);
+    key.push_back((uintptr_t)c->f4.W);
     for (size_t g = 0; g < c->graphs.size(); ++g)
         if (c->graphs[g].key == key) {
             HIPOK(c, hipGraphLaunch(c->graphs[g].exec, st));
@@ -1015,6 +1078,7 @@ void bhfwi_destroy(bhfwi_ctx* c)
         if (c->ftiles.d[q]) (void)hipFree(c->ftiles.d[q]);
         if (c->atiles.d[q]) (void)hipFree(c->atiles.d[q]);
         if (c->xtiles.d[q]) (void)hipFree(c->xtiles.d[q]);
+        if (c->f4tiles.d[q]) (void)hipFree(c->f4tiles.d[q]);
     }
     if (c->d_scratch) (void)hipFree(c->d_scratch);
     if (c->d_status) (void)hipFree(c->d_status);
@@ -1187,6 +1251,20 @@ int bhfwi_set_order(bhfwi_ctx* c, int32_t order)
     }
     c->order = order;
     return BHFWI_OK;
+}
+
+int bhfwi_set_fwd4_shape(bhfwi_ctx* c, int32_t steps, int32_t rows, int32_t waves)
+{
+    if (int rc = check_ctx(c)) return rc;
+    const Shape sh = steps >= 2 ? Shape{steps, rows, waves} : Shape{0, 0, 0};
+    if (!f4_ok(sh))
+        return fail(c, BHFWI_EINVAL, "fourth-order forward shape (%d, %d, %d) not compiled",
+                    steps, rows, waves);
+    HIPOK(c, hipDeviceSynchronize());
+    clear_graphs(c);
+    c->f4 = sh;
+    rebuild_work(c);
+    return upload_work(c);
 }
 
 int bhfwi_kernel_shapes(const bhfwi_ctx* c, int32_t* out)

@@ -19,6 +19,7 @@
 // Every global load is predicated on the lane's axial row being inside the
 // grid (outside values are zero, the boundary convention of the scheme), and
 // every store on the lane owning its cell.
+#pragma once
 #include "bhfwi_internal.h"
 
 namespace bhfwi {

@@ -14,7 +14,7 @@ LIB = os.path.join(ROOT, "paper_2005_00281_amd", "libbhfwi.so")
 def declared():
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(bhfwi_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(bhfwi_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_header_declares_the_path_entry_points():

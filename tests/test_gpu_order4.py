@@ -250,3 +250,50 @@ def test_order4_joint_iteration_parity():
     assert rel_l2(dvp, vp_o - w.vp_start) <= 2e-2 and rel_l2(dvs, vs_o - w.vs_start) <= 2e-2
     Js = [J0.item()] + [inv.iterate()[0].item() for _ in range(3)]
     assert Js[-1] < Js[0], Js
+
+
+@pytest.mark.parametrize("nr,nz,p,nt", [(40, 150, 6, 301), (5, 18, 3, 7), (24, 70, 0, 41)])
+def test_order4_blocked_forward_against_one_step_and_oracle(nr, nz, p, nt):
+    """The fourth-order forward in two-step blocks (the default) against the
+    one-step kernels and the oracle: traces and, through the gradient, the
+    stored velocity history, on a ragged grid with PML, a grid smaller than one
+    tile and an odd step count, and a grid without PML."""
+    w = workloads.tiny(nr=nr, nz=nz, p=p, nt=nt)
+    sh = w.shots[0]
+    _say("order 4 blocked forward", sh.NR, sh.NZ, sh.nt)
+    lam_o, mu_o, rho_o = oracle_models(w, 0, "start")
+    d_o = oracle.forward(geom(sh), lam_o, mu_o, rho_o, sh.wavelet, order=4)
+    r = np.random.default_rng(5).standard_normal(d_o.shape)
+    lam, mu, rho = gpu_models(w)
+    out = {}
+    for steps in (2, 0):
+        sv = survey4(w, ckpt=25)
+        sv.set_fwd4_shape(steps)
+        wav = sv.pack_wavelets([sh.wavelet])
+        tr = sv.fwd_model(lam, mu, rho, wav, store_ckpt=True)
+        acc = sv.adjoint_model(lam, mu, rho, wav, f32(r.ravel()))
+        out[steps] = (sv.unpack_traces(tr)[0], [t.cpu().numpy() for t in sv.gradient(mu, acc)])
+    torch.cuda.synchronize()
+    (d2, g2), (d1, g1) = out[2], out[0]
+    print("[case] traces blocked/one-step %.3g, vs oracle %.3g" % (
+        rel_l2(d2, d1), rel_l2(d2, d_o)), flush=True)
+    assert rel_l2(d2, d_o) <= 1e-4
+    assert rel_l2(d2, d1) <= 1e-5
+    for a, b in zip(g2, g1):
+        assert rel_l2(a, b) <= 1e-5
+
+
+def test_order4_forward_shape_rules():
+    """Uncompiled fourth-order forward shapes are refused; one step per launch
+    and the default two-step blocks are accepted."""
+    import paper_2005_00281_amd as P
+    from paper_2005_00281_amd._lib import BhfwiError
+    w = workloads.tiny(nr=20, nz=60, p=4, nt=50)
+    _say("order 4 forward shape rules")
+    sv = P.Survey(w.shots, (w.NRg, w.NZg), ckpt_every=25, order=4)
+    with pytest.raises(BhfwiError):
+        sv.set_fwd4_shape(3, 32, 16)
+    with pytest.raises(BhfwiError):
+        sv.set_fwd4_shape(2, 48, 16)
+    sv.set_fwd4_shape(0)
+    sv.set_fwd4_shape(2, 32, 16)
