@@ -53,13 +53,13 @@ ADJ_BLOCK_BYTES_PER_CELL_STEP = 8
 # a device copy of 1 GiB reads 1.000 GiB and writes 1.000 GiB on them,
 # profiles/copy_calibration.md), the mean per dispatch summed over the
 # interior and PML kernels of one block.  An entry holds only for the kernel
-# sources and host tiling it was measured on (SHA-256 of PMC_SOURCES), the
-# same shapes, tile map and workload; otherwise traffic is null.
+# sources it was measured on (SHA-256 of PMC_SOURCES: the adjoint block kernel
+# and the device code it includes), the same shapes, tile map and workload;
+# otherwise traffic is null.
 PMC_SOURCES = ("paper_2005_00281_amd/csrc/bhfwi_tb_adj.hip",
                "paper_2005_00281_amd/csrc/bhfwi_tb_fwd.hip",
                "paper_2005_00281_amd/csrc/bhfwi_kernels.hip",
-               "paper_2005_00281_amd/csrc/bhfwi_internal.h",
-               "paper_2005_00281_amd/csrc/bhfwi_host.hip")
+               "paper_2005_00281_amd/csrc/bhfwi_internal.h")
 PMC_TRAFFIC = {
     # (kernel, tile_map, workload, sources sha256[:16]): (read bytes, write bytes)
     ("k_adj_tb<6, 32, 16, 0, 0> + k_adj_tb<6, 32, 16, 1, 0>", 1, "c3", "2124f23387c3c5a7"):
@@ -732,7 +732,7 @@ def plain_form(args, w, pl, observed, mask, rho, line_search, row_weight, autogr
         sv1.set_tune(rows_per_wave=2, tb_steps=0, adj_tb_steps=0, use_graph=0,
                      full_history=1 if full else 0)
         if args.order == 4:
-            sv1.set_fwd4_shape(0)
+            sv1.set_order4_blocks(0)
         wav1 = sv1.pack_wavelets([sh.wavelet])
         off = sum(len(w.shots[q].rec_k) * w.shots[q].nt for q in pl.groups[g_] if q < s_)
         obs1 = observed[g_][off: off + len(sh.rec_k) * sh.nt].clone()

@@ -200,19 +200,20 @@ int bhfwi_sizes(const bhfwi_ctx *ctx, bhfwi_sizes_t *out);
  * ones), and the on-axis source divided by the axis cell's weight sqrt(6/7)
  * in the norm in which that divergence conserves flux.  Applies to
  * bhfwi_fwd_model and the bhfwi_adjoint_model family, the density and
- * pseudo-Hessian outputs included (no autotune; the adjoint runs one step per
- * launch, the forward in time blocks set by bhfwi_set_fwd4_shape).  Order 4
- * needs the stricter stability bound vmax dt sqrt(1/dr^2 + 1/dz^2) < 6/7
- * (BHFWI_ECFL otherwise).  Synchronises the device. */
+ * pseudo-Hessian outputs included (no autotune; time blocks set by
+ * bhfwi_set_order4_blocks).  Order 4 needs the stricter stability bound
+ * vmax dt sqrt(1/dr^2 + 1/dz^2) < 6/7 (BHFWI_ECFL otherwise).  Synchronises
+ * the device. */
 int bhfwi_set_order(bhfwi_ctx *ctx, int32_t order);
-/* Time blocks of the fourth-order forward (the step of bhfwi_set_order(4)):
- * `steps` steps per launch on workgroups of `waves` wave64 whose window is 64
- * axial by `rows` radial cells with a 3*steps-cell halo (each step reaches
- * three cells on either side).  steps < 2 runs one step per launch.  The
- * compiled shapes are (2, 32, 16), the default; others give BHFWI_EINVAL.
- * Results equal the one-step kernels' to FP32 rounding.  Synchronises the
- * device. */
-int bhfwi_set_fwd4_shape(bhfwi_ctx *ctx, int32_t steps, int32_t rows, int32_t waves);
+/* Time blocks of the fourth-order step (bhfwi_set_order(4)): the forward and
+ * the plain adjoint (with the Eq. 7-8 correlation; the density and
+ * pseudo-Hessian outputs always run one step per launch) advance `steps` steps
+ * per launch on workgroups of `waves` wave64 whose window is 64 axial by
+ * `rows` radial cells with a 3*steps-cell halo (each step reaches three cells
+ * on either side).  steps < 2 runs one step per launch.  The compiled shape is
+ * (2, 32, 16), the default; others give BHFWI_EINVAL.  Results equal the
+ * one-step kernels' to FP32 rounding.  Synchronises the device. */
+int bhfwi_set_order4_blocks(bhfwi_ctx *ctx, int32_t steps, int32_t rows, int32_t waves);
 int bhfwi_set_tune(bhfwi_ctx *ctx, const bhfwi_tune *tune);
 int bhfwi_get_tune(const bhfwi_ctx *ctx, bhfwi_tune *out);
 /* Autotuner: times, on this survey, every forward kernel shape (one-step wave

@@ -84,7 +84,7 @@ EXPORTS = ["bhfwi_build_id", "bhfwi_create", "bhfwi_destroy", "bhfwi_last_error"
            "bhfwi_starting_model", "bhfwi_adjoint_model_density", "bhfwi_gradient_density",
            "bhfwi_adjoint_model_ex", "bhfwi_gradient_hessian", "bhfwi_precondition_diag",
            "bhfwi_radial_taper", "bhfwi_update_density", "bhfwi_set_order",
-           "bhfwi_set_fwd4_shape",
+           "bhfwi_set_order4_blocks",
            "bhfwi_misfit_noalloc", "bhfwi_adjoint_model_wavelet"]
 
 _lib = None
@@ -139,7 +139,7 @@ def load(path: str = LIB_PATH):
     L.bhfwi_precondition_diag.argtypes = [P, V, I64, I32, P, P, P, F, P, P, I32]
     L.bhfwi_radial_taper.argtypes = [V, I32, F, F, F, P]
     L.bhfwi_set_order.argtypes = [P, I32]
-    L.bhfwi_set_fwd4_shape.argtypes = [P, I32, I32, I32]
+    L.bhfwi_set_order4_blocks.argtypes = [P, I32, I32, I32]
     L.bhfwi_update_density.argtypes = [P, V, I64, P, P, P, F, F, F, P]
     L.bhfwi_precondition.argtypes = [P, V, I64, P, P, F, P, P, P]
     L.bhfwi_line_search.argtypes = [P, V, P, P, P, P, P]
@@ -383,10 +383,11 @@ class Survey:
         _check(load().bhfwi_sizes(self._h, C.byref(self.sizes)), self._h)
         self._ws.clear()
 
-    def set_fwd4_shape(self, steps, rows=32, waves=16):
-        """Time blocks of the fourth-order forward (bhfwi_set_fwd4_shape):
-        steps per launch (< 2: one step per launch), window rows, waves."""
-        _check(load().bhfwi_set_fwd4_shape(self._h, int(steps), int(rows), int(waves)),
+    def set_order4_blocks(self, steps, rows=32, waves=16):
+        """Time blocks of the fourth-order forward and plain adjoint
+        (bhfwi_set_order4_blocks): steps per launch (< 2: one step per
+        launch), window rows, waves."""
+        _check(load().bhfwi_set_order4_blocks(self._h, int(steps), int(rows), int(waves)),
                self._h)
 
     def __del__(self):

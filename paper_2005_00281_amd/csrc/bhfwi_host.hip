@@ -533,6 +533,42 @@ void fwd4_tb_launch(bhfwi_ctx* c, hipStream_t st, int n0, int nsteps, const floa
     }
 }
 
+// Fourth-order adjoint steps n_hi, n_hi - 1, ... (nsteps of them) in one time
+// block with the correlation (the plain adjoint only: no extra outputs).
+void adj4_tb_launch(bhfwi_ctx* c, hipStream_t st, int n_hi, int nsteps, const float* lam,
+                    const float* mu, const float* rho, const float* resid, const float* in,
+                    float* out, const float* hist_hi, float* acc)
+{
+    const TileSet& ts = c->f4tiles;
+    const int n_lo = n_hi - nsteps + 1;
+    const int na[2] = {active_tiles(ts, 0, n_lo), active_tiles(ts, 1, n_lo)};
+    if (na[0] + na[1] <= 0) return;
+    EvScope ev(c, st, 2);
+    for (int q = 0; q < 2; ++q) {
+        const int nact = na[q];
+        if (nact <= 0) continue;
+        const int T = c->f4.T, TRE = c->f4.TRE, W = c->f4.W;
+#define BHFWI_A4L(TT, RR, WW)                                                                  \
+        if (T == TT && TRE == RR && W == WW) {                                                 \
+            if (q == 0)                                                                        \
+                hipLaunchKernelGGL((bhfwi::o4::k_adj4_tb<TT, RR, WW, 0>), dim3(nact),          \
+                                   dim3(64 * WW), 0, st, c->d_shots, ts.d[q], nact,            \
+                                   c->tune.tile_map, n_hi, nsteps, lam, mu, rho, c->d_rec,     \
+                                   resid, c->d_pml_r, c->d_pml_z, in, out, hist_hi,            \
+                                   (long long)(2 * c->cells), acc, (long long)c->cells);       \
+            else                                                                               \
+                hipLaunchKernelGGL((bhfwi::o4::k_adj4_tb<TT, RR, WW, 1>), dim3(nact),          \
+                                   dim3(64 * WW), 0, st, c->d_shots, ts.d[q], nact,            \
+                                   c->tune.tile_map, n_hi, nsteps, lam, mu, rho, c->d_rec,     \
+                                   resid, c->d_pml_r, c->d_pml_z, in, out, hist_hi,            \
+                                   (long long)(2 * c->cells), acc, (long long)c->cells);       \
+            continue;                                                                          \
+        }
+        BHFWI_F4(BHFWI_A4L)
+#undef BHFWI_A4L
+    }
+}
+
 bool f4_ok(Shape sh)
 {
 #define BHFWI_F4S(TT, RR, WW) \
@@ -760,9 +796,18 @@ void adj_range(bhfwi_ctx* c, hipStream_t st, int n0, int n1, const float* lam, c
 {
     const int64_t hslot = 2 * c->cells;
     if (c->order == 4) {
-        for (int n = n1 - 1; n >= n0; --n, ++*m)
-            adj4_launch(c, st, n, lam, mu, rho, resid, ab[*m & 1], ab[(*m + 1) & 1],
-                        hist + (int64_t)(n - n0) * hslot, acc, acc_rho, acc_h);
+        // time blocks for the plain adjoint; the extra outputs run one step per launch
+        const int T4 = (c->f4.T >= 2 && !acc_rho && !acc_h) ? c->f4.T : 1;
+        for (int n = n1 - 1; n >= n0; ++*m) {
+            const int nb = std::min(T4, n - n0 + 1);
+            if (T4 >= 2)
+                adj4_tb_launch(c, st, n, nb, lam, mu, rho, resid, ab[*m & 1], ab[(*m + 1) & 1],
+                               hist + (int64_t)(n - n0) * hslot, acc);
+            else
+                adj4_launch(c, st, n, lam, mu, rho, resid, ab[*m & 1], ab[(*m + 1) & 1],
+                            hist + (int64_t)(n - n0) * hslot, acc, acc_rho, acc_h);
+            n -= nb;
+        }
         return;
     }
     const Shape sh = adj_shape(c);
@@ -1253,7 +1298,7 @@ int bhfwi_set_order(bhfwi_ctx* c, int32_t order)
     return BHFWI_OK;
 }
 
-int bhfwi_set_fwd4_shape(bhfwi_ctx* c, int32_t steps, int32_t rows, int32_t waves)
+int bhfwi_set_order4_blocks(bhfwi_ctx* c, int32_t steps, int32_t rows, int32_t waves)
 {
     if (int rc = check_ctx(c)) return rc;
     const Shape sh = steps >= 2 ? Shape{steps, rows, waves} : Shape{0, 0, 0};

@@ -253,14 +253,14 @@ def test_order4_joint_iteration_parity():
 
 
 @pytest.mark.parametrize("nr,nz,p,nt", [(40, 150, 6, 301), (5, 18, 3, 7), (24, 70, 0, 41)])
-def test_order4_blocked_forward_against_one_step_and_oracle(nr, nz, p, nt):
-    """The fourth-order forward in two-step blocks (the default) against the
-    one-step kernels and the oracle: traces and, through the gradient, the
-    stored velocity history, on a ragged grid with PML, a grid smaller than one
-    tile and an odd step count, and a grid without PML."""
+def test_order4_blocks_against_one_step_and_oracle(nr, nz, p, nt):
+    """The fourth-order forward and adjoint in two-step blocks (the default)
+    against the one-step kernels and the oracle: traces, gradients and
+    illumination, on a ragged grid with PML, a grid smaller than one tile with
+    an odd step count, and a grid without PML."""
     w = workloads.tiny(nr=nr, nz=nz, p=p, nt=nt)
     sh = w.shots[0]
-    _say("order 4 blocked forward", sh.NR, sh.NZ, sh.nt)
+    _say("order 4 blocks", sh.NR, sh.NZ, sh.nt)
     lam_o, mu_o, rho_o = oracle_models(w, 0, "start")
     d_o = oracle.forward(geom(sh), lam_o, mu_o, rho_o, sh.wavelet, order=4)
     r = np.random.default_rng(5).standard_normal(d_o.shape)
@@ -268,32 +268,39 @@ def test_order4_blocked_forward_against_one_step_and_oracle(nr, nz, p, nt):
     out = {}
     for steps in (2, 0):
         sv = survey4(w, ckpt=25)
-        sv.set_fwd4_shape(steps)
+        sv.set_order4_blocks(steps)
         wav = sv.pack_wavelets([sh.wavelet])
         tr = sv.fwd_model(lam, mu, rho, wav, store_ckpt=True)
         acc = sv.adjoint_model(lam, mu, rho, wav, f32(r.ravel()))
         out[steps] = (sv.unpack_traces(tr)[0], [t.cpu().numpy() for t in sv.gradient(mu, acc)])
     torch.cuda.synchronize()
     (d2, g2), (d1, g1) = out[2], out[0]
-    print("[case] traces blocked/one-step %.3g, vs oracle %.3g" % (
-        rel_l2(d2, d1), rel_l2(d2, d_o)), flush=True)
+    gl_o, gm_o, il_o = oracle.gradient(geom(sh), lam_o, mu_o, rho_o, sh.wavelet, r, seg=25,
+                                       order=4)
+    print("[case] traces blocked/one-step %.3g, vs oracle %.3g; gradient blocked/one-step %s, "
+          "vs oracle %s" % (rel_l2(d2, d1), rel_l2(d2, d_o),
+                            [float("%.3g" % rel_l2(a, b)) for a, b in zip(g2, g1)],
+                            [float("%.3g" % rel_l2(a, b)) for a, b in zip(g2, (gl_o, gm_o, il_o))]),
+          flush=True)
     assert rel_l2(d2, d_o) <= 1e-4
     assert rel_l2(d2, d1) <= 1e-5
     for a, b in zip(g2, g1):
         assert rel_l2(a, b) <= 1e-5
+    assert rel_l2(g2[0], gl_o) <= 1e-3 and rel_l2(g2[1], gm_o) <= 1e-3
+    assert rel_l2(g2[2], il_o) <= 1e-4
 
 
-def test_order4_forward_shape_rules():
-    """Uncompiled fourth-order forward shapes are refused; one step per launch
+def test_order4_block_shape_rules():
+    """Uncompiled fourth-order block shapes are refused; one step per launch
     and the default two-step blocks are accepted."""
     import paper_2005_00281_amd as P
     from paper_2005_00281_amd._lib import BhfwiError
     w = workloads.tiny(nr=20, nz=60, p=4, nt=50)
-    _say("order 4 forward shape rules")
+    _say("order 4 block shape rules")
     sv = P.Survey(w.shots, (w.NRg, w.NZg), ckpt_every=25, order=4)
     with pytest.raises(BhfwiError):
-        sv.set_fwd4_shape(3, 32, 16)
+        sv.set_order4_blocks(3, 32, 16)
     with pytest.raises(BhfwiError):
-        sv.set_fwd4_shape(2, 48, 16)
-    sv.set_fwd4_shape(0)
-    sv.set_fwd4_shape(2, 32, 16)
+        sv.set_order4_blocks(2, 48, 16)
+    sv.set_order4_blocks(0)
+    sv.set_order4_blocks(2, 32, 16)
