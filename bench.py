@@ -668,8 +668,11 @@ def kernel_roofline(args, inv, surveys, tune, full):
     xm = (1 if args.density else 0) | (2 if args.precond == "pseudo_hessian" else 0)
     ka, kp = (kshapes["adj_x"], kshapes["adj_x_pml"]) if xm else (kshapes["adj"],
                                                                   kshapes["adj_pml"])
-    T = ka[0] if (args.order == 2 and ka[0] >= 2) else 1
-    kname = ("k_adj4<%d>" % xm if args.order == 4
+    b4 = sv.order4_blocks
+    T = (ka[0] if (args.order == 2 and ka[0] >= 2) else
+         b4[0] if (args.order == 4 and xm == 0 and b4[0] >= 2) else 1)
+    kname = (("k_adj4_tb<%d, %d, %d, 0> + k_adj4_tb<%d, %d, %d, 1>" % (b4 + b4)
+              if xm == 0 and b4[0] >= 2 else "k_adj4<%d>" % xm) if args.order == 4
              else "k_adj_tb<%d, %d, %d, 0, %d> + k_adj_tb<%d, %d, %d, 1, %d>" % (
              ka + (xm,) + kp + (xm,))
              if ka[0] >= 2

@@ -372,6 +372,7 @@ class Survey:
         self.sizes = Sizes()
         _check(L.bhfwi_sizes(h, C.byref(self.sizes)), h)
         self._ws = {}
+        self.order4_blocks = (2, 32, 16)  # the library's default fourth-order time blocks
         if order != 2:
             self.set_order(order)
 
@@ -389,6 +390,7 @@ class Survey:
         launch), window rows, waves."""
         _check(load().bhfwi_set_order4_blocks(self._h, int(steps), int(rows), int(waves)),
                self._h)
+        self.order4_blocks = (int(steps), int(rows), int(waves)) if steps >= 2 else (0, 0, 0)
 
     def __del__(self):
         h = getattr(self, "_h", None)
