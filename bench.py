@@ -62,8 +62,8 @@ PMC_SOURCES = ("paper_2005_00281_amd/csrc/bhfwi_tb_adj.hip",
                "paper_2005_00281_amd/csrc/bhfwi_internal.h")
 PMC_TRAFFIC = {
     # (kernel, tile_map, workload, sources sha256[:16]): (read bytes, write bytes)
-    ("k_adj_tb<6, 32, 16, 0, 0> + k_adj_tb<6, 32, 16, 1, 0>", 1, "c3", "2124f23387c3c5a7"):
-        (9441306409, 4475121044),
+    ("k_adj_tb<6, 32, 16, 0, 0> + k_adj_tb<6, 32, 16, 1, 0>", 1, "c3", "1b9ddfade714672a"):
+        (9473552807, 4571637679),
 }
 
 # temporally blocked shapes (T, tile rows incl. halo, waves) of both kernels,
