@@ -92,3 +92,33 @@ def test_full_grid_in_the_benchmark_launch_configuration(full_grid, form):
             rel_l2(gm[form], gm_o[form]), rel_l2(il, il_o))
     print("[case] full grid rel-L2 g_lam %.3g g_mu %.3g (formation %.3g %.3g) illum %.3g" % errs)
     assert max(errs[:4]) <= 1e-3 and errs[4] <= 1e-4
+
+
+@pytest.mark.parametrize("full", [1, 0])
+def test_full_grid_order4_blocks_against_one_step(full_grid, full):
+    """The fourth-order single-shot benchmark's configuration (two-step blocks;
+    full velocity history, and checkpoints every 250 steps) on the full grid:
+    traces, gradients and illumination of the blocked kernels within 1e-5 of the
+    one-step kernels, whose parity with the fourth-order oracle is checked on the
+    smaller grids (the assembled oracle is too slow at this size)."""
+    import paper_2005_00281_amd as P
+    w, r, _ = full_grid
+    sh = w.shots[0]
+    _say("full grid order 4", sh.NR, sh.NZ, NT, "full history", full)
+    lam, mu, rho = gpu_models(w)
+    out = {}
+    for steps in (2, 0):
+        sv = P.Survey(w.shots, (w.NRg, w.NZg), ckpt_every=250, order=4)
+        sv.set_tune(full_history=full)
+        sv.set_order4_blocks(steps)
+        wav = sv.pack_wavelets([sh.wavelet])
+        tr = sv.fwd_model(lam, mu, rho, wav, store_ckpt=True)
+        acc = sv.adjoint_model(lam, mu, rho, wav, f32(r.ravel()))
+        out[steps] = [sv.unpack_traces(tr)[0]] + [t.cpu().numpy() for t in sv.gradient(mu, acc)]
+        del sv
+    torch.cuda.synchronize()
+    errs = [rel_l2(a, b) for a, b in zip(out[2], out[0])]
+    print("[case] full grid order 4 blocked/one-step: traces %.3g g_lam %.3g g_mu %.3g "
+          "illum %.3g" % tuple(errs), flush=True)
+    assert np.abs(out[0][0]).max() > 0
+    assert max(errs) <= 1e-5, errs
