@@ -1,6 +1,7 @@
-// bhfwi_o4_tb.hip -- temporally blocked fourth-order forward step (the Eq. 2
-// step with the four-point staggered differences and 1/r averages of the
-// one-step kernels in bhfwi_o4.hip).
+// bhfwi_o4_tb.hip -- temporally blocked fourth-order steps: the forward (the
+// Eq. 2 step with the four-point staggered differences and 1/r averages of
+// the one-step kernels in bhfwi_o4.hip) and its exact adjoint with the
+// correlation of Eq. 7-8.
 //
 // The tiling is that of the second-order time blocks: a workgroup of W wave64
 // owns TRE - 2H radial by 64 - 2H axial cells and loads them with an H-cell
@@ -14,9 +15,10 @@
 //
 // Across the axis the fields are mirrored (even at half radial positions:
 // normal stresses and v_z; odd and zero on the axis at integer ones: v_r,
-// tau_rz).  A row whose stencil reaches below the axis reads the image row
-// instead, with the field's sign; the rows and signs are per-row constants.
-// Rows below the axis in the window (tiles at the axis) are never read.
+// tau_rz).  In the forward a row whose stencil reaches below the axis reads
+// the image row instead, with the field's sign (per-row constant rows and
+// signs), so the rows below the axis in a window at the axis are never read;
+// the adjoint's treatment is described with its kernel.
 //
 // As in the second-order kernels the step loop has no per-cell branches,
 // rows that have left the correct region are skipped, and tiles that reach a

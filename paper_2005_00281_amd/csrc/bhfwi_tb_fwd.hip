@@ -272,8 +272,9 @@ k_fwd_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
                 const int i = wk.z - T + e;
                 const bool own = kin && lown && e >= T && e < TRE - T && i < NR;
                 if (hist && own) {
-                    *reinterpret_cast<float*>(hvr_t + hoff[j]) = vr[j];
-                    *reinterpret_cast<float*>(hvz_t + hoff[j]) = vz[j];
+                    // streamed out, read back segments later: not kept in L2
+                    __builtin_nontemporal_store(vr[j], reinterpret_cast<float*>(hvr_t + hoff[j]));
+                    __builtin_nontemporal_store(vz[j], reinterpret_cast<float*>(hvz_t + hoff[j]));
                 }
                 if (i == 0 && own && rj >= 0)
                     traces[S.trace_off + (long long)rj * S.nt + n] =
