@@ -44,6 +44,9 @@ ADJ_BYTES_PER_CELL_STEP = 92
 # once (48 + 12 + 24 B), the stored velocities once per step (8 B per step).
 ADJ_BLOCK_BYTES_PER_CELL = 84
 ADJ_BLOCK_BYTES_PER_CELL_STEP = 8
+# each extra output (the density correlation, the pseudo-Hessian) reads and
+# writes two more accumulator planes per cell and launch
+ADJ_BLOCK_BYTES_PER_CELL_X = 16
 
 # HBM traffic of the adjoint time block, from rocprofv3 --pmc runs of
 #   bench.py --workload W --nt 250 --steps 1 --warmup 0 --no-cpu-baseline
@@ -670,9 +673,9 @@ def kernel_roofline(args, inv, surveys, tune, full):
                                                                   kshapes["adj_pml"])
     b4 = sv.order4_blocks
     T = (ka[0] if (args.order == 2 and ka[0] >= 2) else
-         b4[0] if (args.order == 4 and xm == 0 and b4[0] >= 2) else 1)
-    kname = (("k_adj4_tb<%d, %d, %d, 0> + k_adj4_tb<%d, %d, %d, 1>" % (b4 + b4)
-              if xm == 0 and b4[0] >= 2 else "k_adj4<%d>" % xm) if args.order == 4
+         b4[0] if (args.order == 4 and b4[0] >= 2) else 1)
+    kname = (("k_adj4_tb<%d, %d, %d, 0, %d> + k_adj4_tb<%d, %d, %d, 1, %d>" % (
+              b4 + (xm,) + b4 + (xm,)) if b4[0] >= 2 else "k_adj4<%d>" % xm) if args.order == 4
              else "k_adj_tb<%d, %d, %d, 0, %d> + k_adj_tb<%d, %d, %d, 1, %d>" % (
              ka + (xm,) + kp + (xm,))
              if ka[0] >= 2
@@ -681,13 +684,14 @@ def kernel_roofline(args, inv, surveys, tune, full):
     # algorithmic bytes of the blocked adjoint over the timed groups: per cell
     # and launch the state, model and accumulators, per cell and step the
     # stored velocities
+    per_cell = ADJ_BLOCK_BYTES_PER_CELL + ADJ_BLOCK_BYTES_PER_CELL_X * bin(xm).count("1")
     floor = 0
     for x in timed:
         nts = [sh.nt for sh in x.shots]
         seg = max(nts) if full else x.sizes.ckpt_every
         blocks = adjoint_blocks(nts, max(nts), seg, T)
         for sh, nb in zip(x.shots, blocks):
-            floor += sh.cells * (ADJ_BLOCK_BYTES_PER_CELL * nb +
+            floor += sh.cells * (per_cell * nb +
                                  ADJ_BLOCK_BYTES_PER_CELL_STEP * sh.nt)
     floor_per_launch = floor / adj_n
     floor_GBs = floor_per_launch / adj_avg_s / 1e9
@@ -712,7 +716,7 @@ def kernel_roofline(args, inv, surveys, tune, full):
                 "floor_GBs": round(floor_GBs, 1),
                 "floor_frac": round(floor_GBs / HBM_PEAK_GBS, 4),
                 "floor_model": "%d B per cell and launch + %d B per cell and step" % (
-                    ADJ_BLOCK_BYTES_PER_CELL, ADJ_BLOCK_BYTES_PER_CELL_STEP),
+                    per_cell, ADJ_BLOCK_BYTES_PER_CELL_STEP),
                 "effective_GBs": round(eff_GBs, 1),
                 "effective_frac": round(eff_GBs / HBM_PEAK_GBS, 4),
                 "effective_model": "%d B per cell-step, unblocked" % ADJ_BYTES_PER_CELL_STEP}

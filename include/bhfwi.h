@@ -206,9 +206,8 @@ int bhfwi_sizes(const bhfwi_ctx *ctx, bhfwi_sizes_t *out);
  * the device. */
 int bhfwi_set_order(bhfwi_ctx *ctx, int32_t order);
 /* Time blocks of the fourth-order step (bhfwi_set_order(4)): the forward and
- * the plain adjoint (with the Eq. 7-8 correlation; the density and
- * pseudo-Hessian outputs always run one step per launch) advance `steps` steps
- * per launch on workgroups of `waves` wave64 whose window is 64 axial by
+ * the adjoint (with the Eq. 7-8 correlation, the density correlation and the
+ * pseudo-Hessian where they are asked for) advance `steps` steps per launch on workgroups of `waves` wave64 whose window is 64 axial by
  * `rows` radial cells with a 3*steps-cell halo (each step reaches three cells
  * on either side).  steps < 2 runs one step per launch.  The compiled shape is
  * (2, 32, 16), the default; others give BHFWI_EINVAL.  Results equal the

@@ -385,7 +385,7 @@ class Survey:
         self._ws.clear()
 
     def set_order4_blocks(self, steps, rows=32, waves=16):
-        """Time blocks of the fourth-order forward and plain adjoint
+        """Time blocks of the fourth-order forward and adjoint
         (bhfwi_set_order4_blocks): steps per launch (< 2: one step per
         launch), window rows, waves."""
         _check(load().bhfwi_set_order4_blocks(self._h, int(steps), int(rows), int(waves)),

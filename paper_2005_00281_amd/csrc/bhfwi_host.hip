@@ -534,11 +534,13 @@ void fwd4_tb_launch(bhfwi_ctx* c, hipStream_t st, int n0, int nsteps, const floa
 }
 
 // Fourth-order adjoint steps n_hi, n_hi - 1, ... (nsteps of them) in one time
-// block with the correlation (the plain adjoint only: no extra outputs).
+// block with the correlation; acc_rho and acc_h (nullable) select the
+// density correlation and the pseudo-Hessian as in adj4_launch.
 void adj4_tb_launch(bhfwi_ctx* c, hipStream_t st, int n_hi, int nsteps, const float* lam,
                     const float* mu, const float* rho, const float* resid, const float* in,
-                    float* out, const float* hist_hi, float* acc)
+                    float* out, const float* hist_hi, float* acc, float* acc_rho, float* acc_h)
 {
+    const int xm = (acc_rho ? 1 : 0) | (acc_h ? 2 : 0);
     const TileSet& ts = c->f4tiles;
     const int n_lo = n_hi - nsteps + 1;
     const int na[2] = {active_tiles(ts, 0, n_lo), active_tiles(ts, 1, n_lo)};
@@ -548,24 +550,33 @@ void adj4_tb_launch(bhfwi_ctx* c, hipStream_t st, int n_hi, int nsteps, const fl
         const int nact = na[q];
         if (nact <= 0) continue;
         const int T = c->f4.T, TRE = c->f4.TRE, W = c->f4.W;
+#define BHFWI_A4K(TT, RR, WW, PP, XX)                                                          \
+    hipLaunchKernelGGL((bhfwi::o4::k_adj4_tb<TT, RR, WW, PP, XX>), dim3(nact), dim3(64 * WW),    \
+                       0, st, c->d_shots, ts.d[q], nact, c->tune.tile_map, n_hi, nsteps, lam,   \
+                       mu, rho, c->d_rec, resid, c->d_pml_r, c->d_pml_z, in, out, hist_hi,      \
+                       (long long)(2 * c->cells), acc, acc_rho, acc_h, (long long)c->cells)
 #define BHFWI_A4L(TT, RR, WW)                                                                  \
         if (T == TT && TRE == RR && W == WW) {                                                 \
-            if (q == 0)                                                                        \
-                hipLaunchKernelGGL((bhfwi::o4::k_adj4_tb<TT, RR, WW, 0>), dim3(nact),          \
-                                   dim3(64 * WW), 0, st, c->d_shots, ts.d[q], nact,            \
-                                   c->tune.tile_map, n_hi, nsteps, lam, mu, rho, c->d_rec,     \
-                                   resid, c->d_pml_r, c->d_pml_z, in, out, hist_hi,            \
-                                   (long long)(2 * c->cells), acc, (long long)c->cells);       \
-            else                                                                               \
-                hipLaunchKernelGGL((bhfwi::o4::k_adj4_tb<TT, RR, WW, 1>), dim3(nact),          \
-                                   dim3(64 * WW), 0, st, c->d_shots, ts.d[q], nact,            \
-                                   c->tune.tile_map, n_hi, nsteps, lam, mu, rho, c->d_rec,     \
-                                   resid, c->d_pml_r, c->d_pml_z, in, out, hist_hi,            \
-                                   (long long)(2 * c->cells), acc, (long long)c->cells);       \
+            if (q == 0) {                                                                      \
+                switch (xm) {                                                                  \
+                case 1: BHFWI_A4K(TT, RR, WW, 0, 1); break;                                    \
+                case 2: BHFWI_A4K(TT, RR, WW, 0, 2); break;                                    \
+                case 3: BHFWI_A4K(TT, RR, WW, 0, 3); break;                                    \
+                default: BHFWI_A4K(TT, RR, WW, 0, 0); break;                                   \
+                }                                                                              \
+            } else {                                                                           \
+                switch (xm) {                                                                  \
+                case 1: BHFWI_A4K(TT, RR, WW, 1, 1); break;                                    \
+                case 2: BHFWI_A4K(TT, RR, WW, 1, 2); break;                                    \
+                case 3: BHFWI_A4K(TT, RR, WW, 1, 3); break;                                    \
+                default: BHFWI_A4K(TT, RR, WW, 1, 0); break;                                   \
+                }                                                                              \
+            }                                                                                  \
             continue;                                                                          \
         }
         BHFWI_F4(BHFWI_A4L)
 #undef BHFWI_A4L
+#undef BHFWI_A4K
     }
 }
 
@@ -796,13 +807,12 @@ void adj_range(bhfwi_ctx* c, hipStream_t st, int n0, int n1, const float* lam, c
 {
     const int64_t hslot = 2 * c->cells;
     if (c->order == 4) {
-        // time blocks for the plain adjoint; the extra outputs run one step per launch
-        const int T4 = (c->f4.T >= 2 && !acc_rho && !acc_h) ? c->f4.T : 1;
+        const int T4 = c->f4.T >= 2 ? c->f4.T : 1;
         for (int n = n1 - 1; n >= n0; ++*m) {
             const int nb = std::min(T4, n - n0 + 1);
             if (T4 >= 2)
                 adj4_tb_launch(c, st, n, nb, lam, mu, rho, resid, ab[*m & 1], ab[(*m + 1) & 1],
-                               hist + (int64_t)(n - n0) * hslot, acc);
+                               hist + (int64_t)(n - n0) * hslot, acc, acc_rho, acc_h);
             else
                 adj4_launch(c, st, n, lam, mu, rho, resid, ab[*m & 1], ab[(*m + 1) & 1],
                             hist + (int64_t)(n - n0) * hslot, acc, acc_rho, acc_h);

@@ -364,10 +364,13 @@ k_fwd4_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int 
 // A transposed gather reads zero at rows below the axis (their drivers and
 // products vanish: zero coefficients), and the reads the forward stencils
 // made through the mirror are added back to their image rows 0 and 1 with
-// the field's parity: per-row factors f0 = [i = 0], f1 = [i = 1].  Only the
-// plain adjoint (no density, pseudo-Hessian or wavelet outputs).
+// the field's parity: per-row factors f0 = [i = 0], f1 = [i = 1].  X selects
+// the extra outputs of the second-order adjoint: bit 0 the density
+// correlation (the adjoint velocity increments of phase B times the stored
+// v^{n+1/2}, into acc_rho), bit 1 the virtual-source pseudo-Hessian (the
+// plain fourth-order strain rates of v^{n+1/2}, into acc_h).
 // ---------------------------------------------------------------------------
-template <int T, int TRE, int W, int PM>
+template <int T, int TRE, int W, int PM, int X>
 __global__ void __launch_bounds__(64 * W, 1)
 k_adj4_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int nwork, int map,
           int n_hi, int nsteps, const float* __restrict__ lam, const float* __restrict__ mu,
@@ -375,8 +378,10 @@ k_adj4_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int 
           const float* __restrict__ resid, const float* __restrict__ pml_r,
           const float* __restrict__ pml_z, const float* __restrict__ ain,
           float* __restrict__ aout, const float* __restrict__ hist_hi, long long hist_stride,
-          float* __restrict__ acc, long long cells_total)
+          float* __restrict__ acc, float* __restrict__ acc_rho, float* __restrict__ acc_h,
+          long long cells_total)
 {
+    constexpr bool RHO = (X & 1) != 0, HES = (X & 2) != 0;
     constexpr int H = 3 * T;
     constexpr int RPT = TRE / W;
     constexpr int GR = 2;
@@ -438,6 +443,8 @@ k_adj4_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int 
         pH[RPT];
     float a_ri[RPT], b_ri[RPT], a_rh[RPT], b_rh[RPT];
     float gl[RPT], gm[RPT], gs[RPT], ge[RPT];
+    float gR[RPT], gZ[RPT];  // density correlation (X & 1)
+    float hL[RPT], hM[RPT];  // pseudo-Hessian diagonal (X & 2)
     float a_zi = 0.f, b_zi = 1.f, a_zh = 0.f, b_zh = 1.f;
     if (zp) {
         a_zi = pzt[k];
@@ -489,6 +496,7 @@ k_adj4_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int 
         a_ri[j] = a_rh[j] = 0.f;
         b_ri[j] = b_rh[j] = 1.f;
         gl[j] = gm[j] = gs[j] = ge[j] = 0.f;
+        gR[j] = gZ[j] = hL[j] = hM[j] = 0.f;
         if (tile_pml) {
             if (iin && i >= nr) {
                 a_ri[j] = prt[i];
@@ -652,6 +660,11 @@ k_adj4_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int 
                 }
                 const float ur = vr0 + vr_p1, uz = vz_km + vz0;  // twice the C-node means
                 ge[j] = fmaf(ur, ur, fmaf(uz, uz, ge[j]));
+                if constexpr (HES) {  // dt^2 applied at write-back
+                    const float dv = err + ett + ezz, es = mrow[j] * (ez + er);
+                    hL[j] += 3.0f * dv * dv;
+                    hM[j] += 4.0f * (err * err + ett * ett + ezz * ezz) + es * es;
+                }
                 // a_v_r at R(i): the stress update read v_r through e_rr (radial
                 // "hi" stencil), e_tt (I / r) and e_z (axial "hi" stencil)
                 const float E_m1 = at(ERR, p - 1), E_m2 = at(ERR, p - 2), E_p1 = at(ERR, p + 1);
@@ -661,7 +674,8 @@ k_adj4_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int 
                 const float Ez_m1 = from_lane_below(Ez_[j]), Ez_m2 = from_lane_below2(Ez_[j]);
                 const float Ez_p1 = from_lane_above(Ez_[j]);
                 const float dEz = C1 * (Ez_m1 - Ez_[j]) + C2 * (Ez_m2 - Ez_p1);
-                avr[j] += mrow[j] * (dEr * idr + it + dEz * idz);
+                const float dar = mrow[j] * (dEr * idr + it + dEz * idz);
+                avr[j] += dar;
                 // a_v_z at Z(i): read through e_zz (axial "lo") and e_r (radial "lo")
                 const float R_p1 = at(ER, p + 1), R_p2 = at(ER, p + 2), R_m1 = at(ER, p - 1);
                 const float dRr = C1 * (Er_[j] - R_p1) + C2 * (R_m1 - R_p2) -
@@ -669,7 +683,12 @@ k_adj4_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int 
                 const float Zz_p1 = from_lane_above(Ezz_[j]), Zz_p2 = from_lane_above2(Ezz_[j]);
                 const float Zz_m1 = from_lane_below(Ezz_[j]);
                 const float dZz = C1 * (Ezz_[j] - Zz_p1) + C2 * (Zz_m1 - Zz_p2);
-                avz[j] += dZz * idz + dRr * idr;
+                const float daz = dZz * idz + dRr * idr;
+                avz[j] += daz;
+                if constexpr (RHO) {
+                    gR[j] += dar * vr0;
+                    gZ[j] += daz * vz0;
+                }
                 const float W1 = dbR[j] * avr[j];
                 float aDr = W1, aDzR = W1;
                 const float W2 = dbZ[j] * avz[j];
@@ -732,14 +751,21 @@ k_adj4_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int 
             }
         }
     };
-    if (tile_pr && tile_pz)
-        steps(IntC<1>{}, IntC<1>{});
-    else if (tile_pr)
-        steps(IntC<1>{}, IntC<0>{});
-    else if (tile_pz)
-        steps(IntC<0>{}, IntC<1>{});
-    else
-        steps(IntC<0>{}, IntC<0>{});
+    if constexpr (X == 0) {
+        if (tile_pr && tile_pz)
+            steps(IntC<1>{}, IntC<1>{});
+        else if (tile_pr)
+            steps(IntC<1>{}, IntC<0>{});
+        else if (tile_pz)
+            steps(IntC<0>{}, IntC<1>{});
+        else
+            steps(IntC<0>{}, IntC<0>{});
+    } else {  // the extra sums leave registers for two loop forms only
+        if (tile_pml)
+            steps(IntC<1>{}, IntC<1>{});
+        else
+            steps(IntC<0>{}, IntC<0>{});
+    }
 
     // ---- write back the owned tile and add the correlation sums
 #pragma unroll
@@ -780,6 +806,16 @@ k_adj4_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int 
         g[cells_total] += (2.0f * dt) * gm[j];
         if (i >= 1) g[2 * cells_total] += dt * gs[j];
         g[3 * cells_total] += (0.25f * dt) * ge[j];
+        if constexpr (RHO) {
+            float* gr = acc_rho + S.cell_off + c;
+            if (i >= 1) gr[0] += gR[j];
+            gr[cells_total] += gZ[j];
+        }
+        if constexpr (HES) {
+            float* h = acc_h + S.cell_off + c;
+            h[0] += dt * dt * hL[j];
+            h[cells_total] += dt * dt * hM[j];
+        }
     }
 }
 

@@ -255,9 +255,10 @@ def test_order4_joint_iteration_parity():
 @pytest.mark.parametrize("nr,nz,p,nt", [(40, 150, 6, 301), (5, 18, 3, 7), (24, 70, 0, 41)])
 def test_order4_blocks_against_one_step_and_oracle(nr, nz, p, nt):
     """The fourth-order forward and adjoint in two-step blocks (the default)
-    against the one-step kernels and the oracle: traces, gradients and
-    illumination, on a ragged grid with PML, a grid smaller than one tile with
-    an odd step count, and a grid without PML."""
+    against the one-step kernels and the oracle: traces, gradients,
+    illumination, the density correlation and the pseudo-Hessian (each extra
+    output alone and both together), on a ragged grid with PML, a grid
+    smaller than one tile with an odd step count, and a grid without PML."""
     w = workloads.tiny(nr=nr, nz=nz, p=p, nt=nt)
     sh = w.shots[0]
     _say("order 4 blocks", sh.NR, sh.NZ, sh.nt)
@@ -271,12 +272,24 @@ def test_order4_blocks_against_one_step_and_oracle(nr, nz, p, nt):
         sv.set_order4_blocks(steps)
         wav = sv.pack_wavelets([sh.wavelet])
         tr = sv.fwd_model(lam, mu, rho, wav, store_ckpt=True)
-        acc = sv.adjoint_model(lam, mu, rho, wav, f32(r.ravel()))
-        out[steps] = (sv.unpack_traces(tr)[0], [t.cpu().numpy() for t in sv.gradient(mu, acc)])
+        res = f32(r.ravel())
+        acc = sv.adjoint_model(lam, mu, rho, wav, res)
+        x = []
+        for dens, hess in ((True, False), (False, True), (True, True)):
+            acc_x, acc_rho, acc_h = sv.adjoint_model_ex(lam, mu, rho, wav, res, density=dens,
+                                                        hessian=hess)
+            x += [t.cpu().numpy() for t in sv.gradient(mu, acc_x)]
+            if dens:
+                x.append(sv.gradient_density(rho, acc_rho).cpu().numpy())
+            if hess:
+                x += [t.cpu().numpy() for t in sv.gradient_hessian(acc_h)]
+        out[steps] = (sv.unpack_traces(tr)[0], [t.cpu().numpy() for t in sv.gradient(mu, acc)],
+                      x)
     torch.cuda.synchronize()
-    (d2, g2), (d1, g1) = out[2], out[0]
-    gl_o, gm_o, il_o = oracle.gradient(geom(sh), lam_o, mu_o, rho_o, sh.wavelet, r, seg=25,
-                                       order=4)
+    (d2, g2, x2), (d1, g1, x1) = out[2], out[0]
+    gl_o, gm_o, il_o, gr_o, hl_o, hm_o = oracle.gradient(
+        geom(sh), lam_o, mu_o, rho_o, sh.wavelet, r, seg=25, density=True, hessian=True,
+        order=4)
     print("[case] traces blocked/one-step %.3g, vs oracle %.3g; gradient blocked/one-step %s, "
           "vs oracle %s" % (rel_l2(d2, d1), rel_l2(d2, d_o),
                             [float("%.3g" % rel_l2(a, b)) for a, b in zip(g2, g1)],
@@ -288,6 +301,17 @@ def test_order4_blocks_against_one_step_and_oracle(nr, nz, p, nt):
         assert rel_l2(a, b) <= 1e-5
     assert rel_l2(g2[0], gl_o) <= 1e-3 and rel_l2(g2[1], gm_o) <= 1e-3
     assert rel_l2(g2[2], il_o) <= 1e-4
+    # extra outputs: blocked against one step, field by field, then the last
+    # pass (density and pseudo-Hessian together) against the oracle
+    ex = [rel_l2(a, b) for a, b in zip(x2, x1)]
+    print("[case] extra outputs blocked/one-step %s" % [float("%.3g" % e) for e in ex],
+          flush=True)
+    assert len(x2) == len(x1) == 15 and max(ex) <= 1e-5
+    gr2, hl2, hm2 = x2[-3:]
+    for a, b in zip(x2[-6:-3], g2):  # the modulus gradients do not change
+        assert rel_l2(a, b) <= 1e-6
+    assert rel_l2(gr2, gr_o) <= 1e-3
+    assert rel_l2(hl2, hl_o) <= 1e-4 and rel_l2(hm2, hm_o) <= 1e-4
 
 
 def test_order4_block_shape_rules():
