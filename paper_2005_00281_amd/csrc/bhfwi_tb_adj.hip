@@ -66,7 +66,10 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
     static_assert(TRE % W == 0 && TRE > 2 * T && 64 > 2 * T, "tile too small for the halo");
     constexpr bool RHO = (X & 1) != 0, HES = (X & 2) != 0, WAV = (X & 4) != 0;
     constexpr int RPT = TRE / W;
-    constexpr bool LDSE = RPT >= 4;
+    // LDSE: the values this lane wrote to LDS are read back from there rather
+    // than held in registers across the barriers (fewer live registers: no
+    // spills at two rows per thread and 64 VGPRs)
+    constexpr bool LDSE = RPT >= 2;
     constexpr int LDW = (TRE + 2) * 64;
     enum { ERR = 0, ETT, ER, UR, HR, ZR, HVR, HVZ, NPL };
     __shared__ float L[NPL][LDW];
@@ -298,12 +301,13 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
                 Er_[j] = Er;
             }
             __syncthreads();
-            // own stored velocities are in registers; fetch the next step's now
+            // fetch the next step's stored velocities now; this step's own
+            // values are read back from LDS (LDSE) or kept in registers
             float vr0_[RPT], vz0_[RPT];
 #pragma unroll
             for (int j = 0; j < RPT; ++j) {
-                vr0_[j] = hvr[j];
-                vz0_[j] = hvz[j];
+                vr0_[j] = LDSE ? 0.f : hvr[j];
+                vz0_[j] = LDSE ? 0.f : hvz[j];
             }
             if (t + 1 < nsteps) fetch_hist(t + 1);
             // ---- B: correlation, transposed updates of a_v
@@ -312,7 +316,8 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
             for (int j = 0; j < RPT; ++j) {
                 const int x = (wave + W * j + 1) * 64 + lane;
                 // Eq. 7-8 with the strain rates of v^{n+1/2} and dJ/dtau^{n+1}
-                const float vr0 = vr0_[j], vr1 = L[HVR][x + 64], vz0 = vz0_[j];
+                const float vr0 = LDSE ? L[HVR][x] : vr0_[j], vr1 = L[HVR][x + 64];
+                const float vz0 = LDSE ? L[HVZ][x] : vz0_[j];
                 const float vz_km = from_lane_below(vz0), vr_kp = from_lane_above(vr0);
                 const float vz_im = L[HVZ][x - 64];
                 const float err = (vr1 - vr0) * idr;
