@@ -65,8 +65,8 @@ PMC_SOURCES = ("paper_2005_00281_amd/csrc/bhfwi_tb_adj.hip",
                "paper_2005_00281_amd/csrc/bhfwi_internal.h")
 PMC_TRAFFIC = {
     # (kernel, tile_map, workload, sources sha256[:16]): (read bytes, write bytes)
-    ("k_adj_tb<6, 32, 16, 0, 0> + k_adj_tb<6, 32, 16, 1, 0>", 1, "c3", "e4294d8239a027c9"):
-        (8119103573, 3473392355),
+    ("k_adj_tb<6, 32, 16, 0, 0> + k_adj_tb<6, 32, 16, 1, 0>", 1, "c3", "b6b761c8dc442d52"):
+        (8121241232, 3473599305),
 }
 
 # temporally blocked shapes (T, tile rows incl. halo, waves) of both kernels,

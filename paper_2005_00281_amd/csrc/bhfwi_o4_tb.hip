@@ -567,7 +567,9 @@ k_adj4_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int 
     auto steps = [&](auto PRC, auto PZC) {
         constexpr bool PR = decltype(PRC)::value != 0, PZ = decltype(PZC)::value != 0;
         for (int t = t0; t < nsteps; ++t) {
-            float Err_[RPT], Ezz_[RPT], Ez_[RPT], Er_[RPT], Q_[RPT], sa_[RPT];
+            // the values phase A writes to LDS (drivers, stored velocities) are
+            // read back from there in phase B rather than held in registers
+            float Ezz_[RPT], Ez_[RPT];
             // ---- A: residual, drivers, stored velocities -> LDS
 #pragma unroll
             for (int j = 0; j < RPT; ++j) {
@@ -607,20 +609,10 @@ k_adj4_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int 
                 L[ERR][p * 64 + lane] = Err;
                 L[ETQ][p * 64 + lane] = Q;
                 L[ER][p * 64 + lane] = Er;
-                Err_[j] = Err;
-                Q_[j] = Q;
                 Ezz_[j] = Ezz;
                 Ez_[j] = Ez;
-                Er_[j] = Er;
-                sa_[j] = sa;
             }
             __syncthreads();
-            float vr0_[RPT], vz0_[RPT];
-#pragma unroll
-            for (int j = 0; j < RPT; ++j) {
-                vr0_[j] = hvr[j];
-                vz0_[j] = hvz[j];
-            }
             if (t + 1 < nsteps) fetch_hist(t + 1);
             // ---- B: Eq. 7-8, adjoint velocities, products of the transposed velocity update
             float DZR_[RPT], DZZ_[RPT];
@@ -630,7 +622,8 @@ k_adj4_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int 
                 if (!live(e, t)) continue;  // uniform
                 const int p = e + GR;
                 // strain rates of the stored v^{n+1/2} (mirror images as in the forward)
-                const float vr0 = vr0_[j], vz0 = vz0_[j];
+                const float vr0 = at(HVR, p), vz0 = at(HVZ, p);
+                const float sa = trr[j] + ttt[j] + tzz[j];  // phase C has not run yet
                 const float vr_p1 = at(HVR, p + 1), vr_p2 = at(HVR, p + 2);
                 const float vr_m1 = os1[j] * at(HVR, om1[j] + GR);
                 const float vz_p1 = at(HVZ, p + 1), vz_m1 = at(HVZ, em1[j] + GR);
@@ -645,7 +638,7 @@ k_adj4_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int 
                 const float ez = (C1 * (vr_kp - vr0) + C2 * (vr_kp2 - vr_km)) * idz;
                 const float er = (C1 * (vz0 - vz_m1) + C2 * (vz_p1 - vz_m2)) * idr;
                 // the sums leave out dt (g_lambda, g_muS), 2 dt (g_mu), dt/4 (illumination)
-                gl[j] = fmaf(err + ett + ezz, sa_[j], gl[j]);
+                gl[j] = fmaf(err + ett + ezz, sa, gl[j]);
                 gm[j] = fmaf(err, trr[j], fmaf(ett, ttt[j], fmaf(ezz, tzz[j], gm[j])));
                 gs[j] = fmaf(ez + er, trz[j], gs[j]);
                 if constexpr (PR) {
@@ -669,8 +662,9 @@ k_adj4_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int 
                 // "hi" stencil), e_tt (I / r) and e_z (axial "hi" stencil)
                 const float E_m1 = at(ERR, p - 1), E_m2 = at(ERR, p - 2), E_p1 = at(ERR, p + 1);
                 const float Q_m1 = at(ETQ, p - 1), Q_m2 = at(ETQ, p - 2), Q_p1 = at(ETQ, p + 1);
-                const float dEr = C1 * (E_m1 - Err_[j]) + C2 * (E_m2 - E_p1) + f1[j] * C2 * E_m1;
-                const float it = G1 * (Q_m1 + Q_[j]) + G2 * (Q_m2 + Q_p1) - f1[j] * G2 * Q_m1;
+                const float Err0 = at(ERR, p), Q0 = at(ETQ, p);
+                const float dEr = C1 * (E_m1 - Err0) + C2 * (E_m2 - E_p1) + f1[j] * C2 * E_m1;
+                const float it = G1 * (Q_m1 + Q0) + G2 * (Q_m2 + Q_p1) - f1[j] * G2 * Q_m1;
                 const float Ez_m1 = from_lane_below(Ez_[j]), Ez_m2 = from_lane_below2(Ez_[j]);
                 const float Ez_p1 = from_lane_above(Ez_[j]);
                 const float dEz = C1 * (Ez_m1 - Ez_[j]) + C2 * (Ez_m2 - Ez_p1);
@@ -678,8 +672,9 @@ k_adj4_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int 
                 avr[j] += dar;
                 // a_v_z at Z(i): read through e_zz (axial "lo") and e_r (radial "lo")
                 const float R_p1 = at(ER, p + 1), R_p2 = at(ER, p + 2), R_m1 = at(ER, p - 1);
-                const float dRr = C1 * (Er_[j] - R_p1) + C2 * (R_m1 - R_p2) -
-                                  f0[j] * (C1 * Er_[j] + C2 * R_p1) - f1[j] * C2 * R_m1;
+                const float Er0 = at(ER, p);
+                const float dRr = C1 * (Er0 - R_p1) + C2 * (R_m1 - R_p2) -
+                                  f0[j] * (C1 * Er0 + C2 * R_p1) - f1[j] * C2 * R_m1;
                 const float Zz_p1 = from_lane_above(Ezz_[j]), Zz_p2 = from_lane_above2(Ezz_[j]);
                 const float Zz_m1 = from_lane_below(Ezz_[j]);
                 const float dZz = C1 * (Ezz_[j] - Zz_p1) + C2 * (Zz_m1 - Zz_p2);

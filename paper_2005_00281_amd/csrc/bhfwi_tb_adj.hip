@@ -245,6 +245,10 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
     // axial memories, radial only, axial only.  A tile that does not reach a
     // layer has zero coefficients for it everywhere, so leaving that layer's
     // terms out changes nothing; most PML tiles reach the radial layer only.
+    // rows that have left the correct region (the halo shrinks one row per
+    // step) are skipped; what they last left in LDS is read only by rows that
+    // are themselves outside the correct region after this step
+    auto live = [&](int e, int t) { return e >= t && e < TRE - t; };
     auto steps = [&](auto PRC, auto PZC) {
         constexpr bool PR = decltype(PRC)::value != 0, PZ = decltype(PZC)::value != 0;
         for (int t = t0; t < nsteps; ++t) {
@@ -257,6 +261,7 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
                 const int x = (e + 1) * 64 + lane;
                 L[HVR][x] = hvr[j];
                 L[HVZ][x] = hvz[j];
+                if (!live(e, t)) continue;  // uniform
                 if (i == 0) {  // uniform
                     const float v = Lres[t][lane];
                     trr[j] += v;
@@ -314,6 +319,7 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
             float U_[RPT], H_[RPT], DzR_[RPT], DzZ_[RPT], ZS_[RPT];
 #pragma unroll
             for (int j = 0; j < RPT; ++j) {
+                if (!live(wave + W * j, t)) continue;  // uniform
                 const int x = (wave + W * j + 1) * 64 + lane;
                 // Eq. 7-8 with the strain rates of v^{n+1/2} and dJ/dtau^{n+1}
                 const float vr0 = LDSE ? L[HVR][x] : vr0_[j], vr1 = L[HVR][x + 64];
@@ -406,6 +412,7 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
             // ---- C: transposed velocity update gathered into a_tau
 #pragma unroll
             for (int j = 0; j < RPT; ++j) {
+                if (!live(wave + W * j, t)) continue;  // uniform
                 const int x = (wave + W * j + 1) * 64 + lane;
                 const float h0 = LDSE ? L[HR][x] : H_[j], h1 = L[HR][x + 64];
                 trr[j] += (LDSE ? L[UR][x] : U_[j]) + h0 - L[UR][x + 64] + h1;
