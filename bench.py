@@ -30,6 +30,9 @@ sys.path.insert(0, ROOT)
 METRIC = ("Gcell-updates/s fwd+adj+grad and % HBM roofline; "
           "shots·FWI-iters/s batched vs plain")
 HBM_PEAK_GBS = 8000.0
+# vector issue peak without packed FP32: one wave64 VALU instruction per CU
+# and clock, 256 CUs at 2.4 GHz
+VALU_PEAK_GIPS = 256 * 2.4
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 # Algorithmic bytes per cell and step (FP32) of the unblocked step kernels:
 # the forward reads and writes 6 fields and reads lambda, mu, rho; the
@@ -67,6 +70,14 @@ PMC_TRAFFIC = {
     # (kernel, tile_map, workload, sources sha256[:16]): (read bytes, write bytes)
     ("k_adj_tb<6, 32, 16, 0, 0> + k_adj_tb<6, 32, 16, 1, 0>", 1, "c3", "b6b761c8dc442d52"):
         (8121241232, 3473599305),
+}
+
+# Vector instructions of the same adjoint block, from a rocprofv3 --pmc run
+# of the same command with SQ_INSTS_VALU (wave64 instructions, summed over the
+# interior and PML kernels of one block, mean per dispatch); the same keys.
+PMC_VALU = {
+    ("k_adj_tb<6, 32, 16, 0, 0> + k_adj_tb<6, 32, 16, 1, 0>", 1, "c3", "b6b761c8dc442d52"):
+        1202725870,
 }
 
 # temporally blocked shapes (T, tile rows incl. halo, waves) of both kernels,
@@ -696,7 +707,8 @@ def kernel_roofline(args, inv, surveys, tune, full):
     floor_per_launch = floor / adj_n
     floor_GBs = floor_per_launch / adj_avg_s / 1e9
     eff_GBs = ADJ_BYTES_PER_CELL_STEP * cs_timed / adj_n / adj_avg_s / 1e9
-    pmc = PMC_TRAFFIC.get((kname, tune.get("tile_map", 1), args.workload, kernel_sources_sha()))
+    pmc_key = (kname, tune.get("tile_map", 1), args.workload, kernel_sources_sha())
+    pmc = PMC_TRAFFIC.get(pmc_key)
     traffic = None if pmc is None else int(pmc[0] + pmc[1])
     traffic_GBs = None if traffic is None else traffic / adj_avg_s / 1e9
     if traffic is not None:
@@ -720,6 +732,15 @@ def kernel_roofline(args, inv, surveys, tune, full):
                 "effective_GBs": round(eff_GBs, 1),
                 "effective_frac": round(eff_GBs / HBM_PEAK_GBS, 4),
                 "effective_model": "%d B per cell-step, unblocked" % ADJ_BYTES_PER_CELL_STEP}
+    valu = PMC_VALU.get(pmc_key)
+    if valu is not None:  # the resource that bounds these kernels: vector issue
+        gips = valu / adj_avg_s / 1e9
+        roofline["valu"] = {"bound": "alu", "achieved": round(gips, 1),
+                            "peak": VALU_PEAK_GIPS, "unit": "G wave64 VALU instructions/s",
+                            "frac": round(gips / VALU_PEAK_GIPS, 4),
+                            "instructions_per_launch": valu,
+                            "basis": "rocprofv3 SQ_INSTS_VALU per launch (profiles/), over "
+                                     "the HIP-event launch time"}
     return roofline, kernels
 
 
