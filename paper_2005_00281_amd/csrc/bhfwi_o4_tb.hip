@@ -439,8 +439,6 @@ k_adj4_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int 
     float iR[RPT], iZ[RPT], mrow[RPT], f0[RPT], f1[RPT];
     int em1[RPT], em2[RPT], om1[RPT];
     float os1[RPT];
-    float qA[RPT], qB[RPT], qC[RPT], qD[RPT], pTr[RPT], pRr[RPT], pTz[RPT], pZz[RPT], pG[RPT],
-        pH[RPT];
     float a_ri[RPT], b_ri[RPT], a_rh[RPT], b_rh[RPT];
     float gl[RPT], gm[RPT], gs[RPT], ge[RPT];
     float gR[RPT], gZ[RPT];  // density correlation (X & 1)
@@ -491,35 +489,15 @@ k_adj4_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int 
         em2[j] = __builtin_amdgcn_readfirstlane(slot(i - 2 >= 0 ? i - 2 : 1 - i));
         om1[j] = __builtin_amdgcn_readfirstlane(slot(i - 1 >= 0 ? i - 1 : 1 - i));
         os1[j] = wave_uniform(i - 1 >= 0 ? 1.f : -1.f);
-        qA[j] = qB[j] = qC[j] = qD[j] = 0.f;
-        pTr[j] = pRr[j] = pTz[j] = pZz[j] = pG[j] = pH[j] = 0.f;
         a_ri[j] = a_rh[j] = 0.f;
         b_ri[j] = b_rh[j] = 1.f;
         gl[j] = gm[j] = gs[j] = ge[j] = 0.f;
         gR[j] = gZ[j] = hL[j] = hM[j] = 0.f;
-        if (tile_pml) {
-            if (iin && i >= nr) {
-                a_ri[j] = prt[i];
-                b_ri[j] = prt[NR + i];
-                a_rh[j] = prt[2 * NR + i];
-                b_rh[j] = prt[3 * NR + i];
-                if (kin) {
-                    const long long q = oPR + (long long)(i - nr) * NZ + kc;
-                    qA[j] = Ai[q];
-                    qC[j] = Ai[q + LR];
-                    pTr[j] = Ai[q + 2 * LR];
-                    pRr[j] = Ai[q + 3 * LR];
-                    pH[j] = Ai[q + 4 * LR];
-                }
-            }
-            if (in && zp) {
-                const long long q = oPZ + (long long)i * (2 * pz) + kk;
-                qB[j] = Ai[q];
-                qD[j] = Ai[q + LZ];
-                pTz[j] = Ai[q + 2 * LZ];
-                pZz[j] = Ai[q + 3 * LZ];
-                pG[j] = Ai[q + 4 * LZ];
-            }
+        if (tile_pr && iin && i >= nr) {
+            a_ri[j] = prt[i];
+            b_ri[j] = prt[NR + i];
+            a_rh[j] = prt[2 * NR + i];
+            b_rh[j] = prt[3 * NR + i];
         }
         a_ri[j] = wave_uniform(a_ri[j]);
         b_ri[j] = wave_uniform(b_ri[j]);
@@ -564,8 +542,36 @@ k_adj4_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int 
     auto live = [&](int e, int t) { return e >= 3 * t && e < TRE - 3 * t; };
     auto at = [&](int f, int row) { return L[f][row * 64 + lane]; };
 
+    // The PML memories live inside the loop form that updates them: a form
+    // without the axial (radial) layer neither loads nor keeps the axial
+    // (radial) memories, which every cell of such a tile lacks.
     auto steps = [&](auto PRC, auto PZC) {
         constexpr bool PR = decltype(PRC)::value != 0, PZ = decltype(PZC)::value != 0;
+        float qA[RPT], qC[RPT], pTr[RPT], pRr[RPT], pH[RPT];  // radial layer
+        float qB[RPT], qD[RPT], pTz[RPT], pZz[RPT], pG[RPT];  // axial layers
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int i = wk.z - H + wave + W * j;
+            const bool iin = i >= 0 && i < NR;
+            qA[j] = qC[j] = pTr[j] = pRr[j] = pH[j] = 0.f;
+            qB[j] = qD[j] = pTz[j] = pZz[j] = pG[j] = 0.f;
+            if (PR && kin && iin && i >= nr) {
+                const long long q = oPR + (long long)(i - nr) * NZ + kc;
+                qA[j] = Ai[q];
+                qC[j] = Ai[q + LR];
+                pTr[j] = Ai[q + 2 * LR];
+                pRr[j] = Ai[q + 3 * LR];
+                pH[j] = Ai[q + 4 * LR];
+            }
+            if (PZ && kin && iin && zp) {
+                const long long q = oPZ + (long long)i * (2 * pz) + kk;
+                qB[j] = Ai[q];
+                qD[j] = Ai[q + LZ];
+                pTz[j] = Ai[q + 2 * LZ];
+                pZz[j] = Ai[q + 3 * LZ];
+                pG[j] = Ai[q + 4 * LZ];
+            }
+        }
         for (int t = t0; t < nsteps; ++t) {
             // the values phase A writes to LDS (drivers, stored velocities) are
             // read back from there in phase B rather than held in registers
@@ -745,6 +751,31 @@ k_adj4_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int 
                 trz[j] += mrow[j] * (dZ * idz + dZr * idr + zI);
             }
         }
+        // the owned tile's PML memories
+        if constexpr (PR || PZ) {
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) {
+                const int e = wave + W * j;
+                const int i = wk.z - H + e;
+                if (!(kin && i >= 0 && i < NR && lown && e >= H && e < TRE - H)) continue;
+                if (PR && i >= nr) {
+                    const long long q = oPR + (long long)(i - nr) * NZ + k;
+                    Ao[q] = qA[j];
+                    Ao[q + LR] = qC[j];
+                    Ao[q + 2 * LR] = pTr[j];
+                    Ao[q + 3 * LR] = pRr[j];
+                    Ao[q + 4 * LR] = pH[j];
+                }
+                if (PZ && zp) {
+                    const long long q = oPZ + (long long)i * (2 * pz) + kk;
+                    Ao[q] = qB[j];
+                    Ao[q + LZ] = qD[j];
+                    Ao[q + 2 * LZ] = pTz[j];
+                    Ao[q + 3 * LZ] = pZz[j];
+                    Ao[q + 4 * LZ] = pG[j];
+                }
+            }
+        }
     };
     if constexpr (X == 0) {
         if (tile_pr && tile_pz)
@@ -778,24 +809,6 @@ k_adj4_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int 
         Ao[2 * cells + c] = trr[j];
         Ao[3 * cells + c] = ttt[j];
         Ao[4 * cells + c] = tzz[j];
-        if (tile_pml) {
-            if (i >= nr) {
-                const long long q = oPR + (long long)(i - nr) * NZ + k;
-                Ao[q] = qA[j];
-                Ao[q + LR] = qC[j];
-                Ao[q + 2 * LR] = pTr[j];
-                Ao[q + 3 * LR] = pRr[j];
-                Ao[q + 4 * LR] = pH[j];
-            }
-            if (zp) {
-                const long long q = oPZ + (long long)i * (2 * pz) + kk;
-                Ao[q] = qB[j];
-                Ao[q + LZ] = qD[j];
-                Ao[q + 2 * LZ] = pTz[j];
-                Ao[q + 3 * LZ] = pZz[j];
-                Ao[q + 4 * LZ] = pG[j];
-            }
-        }
         float* g = acc + S.cell_off + c;
         g[0] += dt * gl[j];
         g[cells_total] += (2.0f * dt) * gm[j];
