@@ -439,6 +439,59 @@ def test_autograd_end_to_end_and_central_differences():
                 (name, i, k, fd, G[i, k])
 
 
+def test_batched_autograd_central_differences_random_cells():
+    """The batched survey through BoreholeFWI (three shots over overlapping
+    windows of one global model, ragged nt and receiver counts): dJ/dlambda
+    and dJ/dmu of the summed loss against central differences of the GPU
+    loss at 16 random formation cells (seeded draw among the cells where the
+    gradient is at least a quarter of its largest value), <= 1e-2."""
+    import paper_2005_00281_amd as P
+    w = _multi_shot_workload()
+    _say("batched autograd central differences", [(s.NR, s.NZ, s.nt) for s in w.shots])
+    sv = survey(w, ckpt=64)
+    lam, mu, rho = gpu_models(w)
+    wav = sv.pack_wavelets([s.wavelet for s in w.shots])
+    # observed data: the oracle's traces of the true model, packed per shot
+    obs_np = np.zeros(sv.sizes.trace_elems, np.float32)
+    for s, (off, nrec, nt) in enumerate(sv.trace_slices()):
+        lt, mt, rt = oracle_models(w, s, "true")
+        d = oracle.forward(geom(w.shots[s]), lt, mt, rt, w.shots[s].wavelet)
+        obs_np[off:off + nrec * nt] = d.ravel()
+    obs = f32(obs_np)
+    lam.requires_grad_(True)
+    mu.requires_grad_(True)
+    tr = P.BoreholeFWI.apply(lam, mu, sv, rho, wav)
+    loss = 0.5 * ((tr - obs).double() ** 2).sum()
+    loss.backward()
+    gl, gm = lam.grad.cpu().numpy(), mu.grad.cpu().numpy()
+
+    def J(l, m):
+        with torch.no_grad():
+            t = sv.fwd_model(l, m, rho, wav)
+            return 0.5 * ((t - obs).double() ** 2).sum().item()
+
+    form = w.mask.astype(bool)
+    score = np.where(form, np.maximum(np.abs(gl) / np.abs(gl[form]).max(),
+                                      np.abs(gm) / np.abs(gm[form]).max()), 0)
+    pool = np.flatnonzero(score.ravel() >= 0.25)
+    assert pool.size >= 16
+    cells = np.random.default_rng(16).choice(pool, 16, replace=False)
+    L0, M0 = lam.detach(), mu.detach()
+    for c in cells:
+        i, k = np.unravel_index(c, gl.shape)
+        for name, base, G in (("lam", L0, gl), ("mu", M0, gm)):
+            h = 1e-2 * base[i, k].item()
+            p, q = base.clone(), base.clone()
+            p[i, k] += h
+            q[i, k] -= h
+            if name == "lam":
+                fd = (J(p, M0) - J(q, M0)) / (2 * h)
+            else:
+                fd = (J(L0, p) - J(L0, q)) / (2 * h)
+            assert abs(fd - G[i, k]) <= 1e-2 * abs(G[i, k]) + 1e-3 * np.abs(G).max(), \
+                (name, i, k, fd, G[i, k])
+
+
 def test_autotune_picks_a_valid_shape_and_stays_correct(tmp_path):
     """The autotuner times every shape on the survey, installs the fastest,
     records it in the cache, keeps none of its scratch, and the chosen shape
