@@ -12,6 +12,9 @@ third receiver so that the waves reach four receivers inside it (the Ricker
 wavelet alone is delayed by 1.5/f0 = 500 steps); the oracle then finishes in
 under two minutes.  Tolerances as everywhere: traces relative L2 <= 1e-4, gradients
 <= 1e-3, illumination <= 1e-4.
+
+The 64-shot workload is checked the same way at its full size and launch
+shapes, on sampled shots (see its test).
 """
 import copy
 import json
@@ -128,3 +131,79 @@ def test_full_grid_order4_blocks_against_one_step(full_grid, full):
     assert np.abs(out[0][0]).max() > 0
     assert errs[0] <= 1e-5 and errs[3] <= 1e-5, errs
     assert errs[1] <= 1e-4 and errs[2] <= 1e-4, errs
+
+
+def _c3_tune():
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_2005_00281_amd", "tune_cache.json")
+    with open(path) as f:
+        table = json.load(f)
+    key = [k for k in table if k.endswith("|K250|276x4136x8000*64")]
+    assert len(key) == 1, key
+    return table[key[0]]["tune"]
+
+
+def test_64_shot_grids_sampled_shots_against_oracle():
+    """The 64-shot workload at its full size (64 windows of 276 x 4136 padded
+    cells over one global model) batched in the launch shapes of its
+    tune-cache entry (forward 8x48x16, adjoint 6x32x16, XCD-chunked tile
+    order, HIP graphs).  The record is cut to 200 steps with the wavelet
+    started 60 samples before its peak and the source 20 rows from the first
+    receiver, so that the oracle can follow sampled shots one by one: traces
+    of shots 0, 31 and 63 against it (<= 1e-4), and, with a residual on shot
+    63 only, the gradient: zero outside that shot's window and, inside it,
+    the oracle's gradient of that shot (<= 1e-3)."""
+    from concurrent.futures import ThreadPoolExecutor
+    import paper_2005_00281_amd as P
+    w = copy.copy(workloads.make("c3"))
+    nt, sampled, gshot = 200, (0, 31, 63), 63
+    shots = []
+    for s in w.shots:
+        sh = copy.copy(s)
+        peak = int(round(1.5 / sh.f0 / sh.dt))
+        sh.wavelet = np.ascontiguousarray(sh.wavelet[peak - 60: peak - 60 + nt])
+        sh.nt = nt
+        sh.src_k = int(sh.rec_k[0]) - 20
+        shots.append(sh)
+    w.shots = shots
+    _say("64-shot grids, sampled shots", len(shots), shots[0].NR, shots[0].NZ, nt)
+    r_g = np.random.default_rng(64).standard_normal((len(shots[gshot].rec_k), nt))
+
+    def fwd(s):
+        lo, mo, ro = oracle_models(w, s, "start")
+        return oracle.forward(geom(shots[s]), lo, mo, ro, shots[s].wavelet)
+
+    def grad():
+        lo, mo, ro = oracle_models(w, gshot, "start")
+        return oracle.gradient(geom(shots[gshot]), lo, mo, ro, shots[gshot].wavelet, r_g,
+                               seg=100)
+
+    with ThreadPoolExecutor(4) as ex:
+        fs = {s: ex.submit(fwd, s) for s in sampled}
+        fg = ex.submit(grad)
+        d_o = {s: f.result() for s, f in fs.items()}
+        gl_o, gm_o, _ = fg.result()
+
+    sv = P.Survey(shots, (w.NRg, w.NZg), ckpt_every=100)
+    sv.set_tune(**_c3_tune())
+    ks = sv.kernel_shapes()
+    assert tuple(ks["fwd"]) == (8, 48, 16) and tuple(ks["adj"]) == (6, 32, 16)
+    lam, mu, rho = gpu_models(w)
+    wav = sv.pack_wavelets([sh.wavelet for sh in shots])
+    tr = sv.unpack_traces(sv.fwd_model(lam, mu, rho, wav, store_ckpt=True))
+    errs = {s: rel_l2(tr[s], d_o[s]) for s in sampled}
+    print("[case] traces rel-L2 %s" % errs, flush=True)
+    for s in sampled:
+        assert np.abs(d_o[s]).max() > 0 and errs[s] <= 1e-4
+    res = np.zeros(sv.sizes.trace_elems, np.float32)
+    off, nrec, ntt = sv.trace_slices()[gshot]
+    res[off: off + nrec * ntt] = r_g.ravel()
+    acc = sv.adjoint_model(lam, mu, rho, wav, f32(res))
+    gl, gm, _ = (t.cpu().numpy() for t in sv.gradient(mu, acc))
+    sh = shots[gshot]
+    inside = np.zeros(gl.shape, bool)
+    inside[: sh.NR, sh.win_k0: sh.win_k0 + sh.NZ] = True
+    assert not gl[~inside].any() and not gm[~inside].any()
+    e = (rel_l2(w.window(gl, gshot), gl_o), rel_l2(w.window(gm, gshot), gm_o))
+    print("[case] shot %d gradient rel-L2 g_lam %.2e g_mu %.2e" % ((gshot,) + e), flush=True)
+    assert e[0] <= 1e-3 and e[1] <= 1e-3
