@@ -149,7 +149,8 @@ def test_batched_offsets_beyond_int32():
     last shots sit at offsets an int32 cannot address.  Their traces must
     equal those of the same shots run alone, bit for bit (150 steps, the
     wavelet started near its peak, the source 20 rows from the first
-    receiver)."""
+    receiver), and the last shot's traces equal the oracle's (<= 1e-4)."""
+    from concurrent.futures import ThreadPoolExecutor
     import paper_2005_00281_amd as P
     w = workloads.make("c5", nshot=48)
     nt = 150
@@ -163,6 +164,9 @@ def test_batched_offsets_beyond_int32():
         shots.append(sh)
     w.shots = shots
     _say("batched offsets beyond int32", len(shots), shots[0].NR, shots[0].NZ, nt)
+    ex = ThreadPoolExecutor(1)
+    lo, mo, ro = oracle_models(w, 47, "start")
+    f_o = ex.submit(oracle.forward, geom(shots[47]), lo, mo, ro, shots[47].wavelet)
     tune = dict(tb_steps=8, tb_rows=48, tb_waves=16, adj_tb_steps=6, adj_tb_rows=32,
                 adj_tb_waves=16, tile_map=0)
     sv = P.Survey(shots, (w.NRg, w.NZg), ckpt_every=250)
@@ -181,3 +185,6 @@ def test_batched_offsets_beyond_int32():
         assert np.abs(tr1[0]).max() > 0
         assert np.array_equal(tr1[0], tr[s]), s
         del sv1
+    d_o = f_o.result()
+    ex.shutdown()
+    assert rel_l2(tr[47], d_o) <= 1e-4, rel_l2(tr[47], d_o)
