@@ -13,8 +13,8 @@ wavelet alone is delayed by 1.5/f0 = 500 steps); the oracle then finishes in
 under two minutes.  Tolerances as everywhere: traces relative L2 <= 1e-4, gradients
 <= 1e-3, illumination <= 1e-4.
 
-The 64-shot workload is checked the same way at its full size and launch
-shapes, on sampled shots (see its test).
+The 64-shot workload and a planner group of the ragged 96-shot workload are
+checked the same way at their full sizes and launch shapes, on sampled shots.
 """
 import copy
 import json
@@ -206,4 +206,81 @@ def test_64_shot_grids_sampled_shots_against_oracle():
     assert not gl[~inside].any() and not gm[~inside].any()
     e = (rel_l2(w.window(gl, gshot), gl_o), rel_l2(w.window(gm, gshot), gm_o))
     print("[case] shot %d gradient rel-L2 g_lam %.2e g_mu %.2e" % ((gshot,) + e), flush=True)
+    assert e[0] <= 1e-3 and e[1] <= 1e-3
+
+
+def test_ragged_96_shot_group_sampled_shots_against_oracle():
+    """The ragged 96-shot workload at full size: the first group the HBM
+    planner makes of it (48 shots of mixed grids, frequencies, time steps and
+    records over one global model) in the launch shapes of its tune-cache
+    entry.  Records cut to 300 steps (wavelet started 60 samples before its
+    peak, source 20 rows from the first receiver): traces of the group's
+    smallest and largest shot against the oracle (<= 1e-4), and with a
+    residual on the smallest shot only, its gradient in its window (<= 1e-3)
+    and zero outside."""
+    from concurrent.futures import ThreadPoolExecutor
+    import paper_2005_00281_amd as P
+    from paper_2005_00281_amd import plan as planner
+    w = copy.copy(workloads.make("c4"))
+    budget = 0.8 * torch.cuda.get_device_properties(0).total_memory
+    pl = planner.plan(w.shots, budget, ckpt_every=w.meta.get("ckpt"))
+    group = pl.groups[0]
+    sv0 = P.Survey([w.shots[s] for s in group], (w.NRg, w.NZg), ckpt_every=pl.ckpt_every[0])
+    key = sv0.shape_key()
+    del sv0
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_2005_00281_amd", "tune_cache.json")
+    with open(path) as f:
+        tune = json.load(f)[key]["tune"]
+    nt = 300
+    shots = []
+    for s in group:
+        sh = copy.copy(w.shots[s])
+        peak = int(round(1.5 / sh.f0 / sh.dt))
+        sh.wavelet = np.ascontiguousarray(sh.wavelet[peak - 60: peak - 60 + nt])
+        sh.nt = nt
+        sh.src_k = int(sh.rec_k[0]) - 20
+        shots.append(sh)
+    w.shots = shots
+    cells = [sh.NR * sh.NZ for sh in shots]
+    small, large = int(np.argmin(cells)), int(np.argmax(cells))
+    _say("ragged group, sampled shots", len(shots), (shots[small].NR, shots[small].NZ),
+         (shots[large].NR, shots[large].NZ), nt, tune)
+    r_g = np.random.default_rng(96).standard_normal((len(shots[small].rec_k), nt))
+
+    def fwd(s):
+        lo, mo, ro = oracle_models(w, s, "start")
+        return oracle.forward(geom(shots[s]), lo, mo, ro, shots[s].wavelet)
+
+    def grad():
+        lo, mo, ro = oracle_models(w, small, "start")
+        return oracle.gradient(geom(shots[small]), lo, mo, ro, shots[small].wavelet, r_g,
+                               seg=100)
+
+    with ThreadPoolExecutor(3) as ex:
+        fs = {s: ex.submit(fwd, s) for s in (small, large)}
+        fg = ex.submit(grad)
+        d_o = {s: f.result() for s, f in fs.items()}
+        gl_o, gm_o, _ = fg.result()
+
+    sv = P.Survey(shots, (w.NRg, w.NZg), ckpt_every=100)
+    sv.set_tune(**tune)
+    lam, mu, rho = gpu_models(w)
+    wav = sv.pack_wavelets([sh.wavelet for sh in shots])
+    tr = sv.unpack_traces(sv.fwd_model(lam, mu, rho, wav, store_ckpt=True))
+    errs = {s: rel_l2(tr[s], d_o[s]) for s in (small, large)}
+    print("[case] traces rel-L2 %s" % errs, flush=True)
+    for s in (small, large):
+        assert np.abs(d_o[s]).max() > 0 and errs[s] <= 1e-4
+    res = np.zeros(sv.sizes.trace_elems, np.float32)
+    off, nrec, ntt = sv.trace_slices()[small]
+    res[off: off + nrec * ntt] = r_g.ravel()
+    acc = sv.adjoint_model(lam, mu, rho, wav, f32(res))
+    gl, gm, _ = (t.cpu().numpy() for t in sv.gradient(mu, acc))
+    sh = shots[small]
+    inside = np.zeros(gl.shape, bool)
+    inside[: sh.NR, sh.win_k0: sh.win_k0 + sh.NZ] = True
+    assert not gl[~inside].any() and not gm[~inside].any()
+    e = (rel_l2(w.window(gl, small), gl_o), rel_l2(w.window(gm, small), gm_o))
+    print("[case] smallest shot gradient rel-L2 g_lam %.2e g_mu %.2e" % e, flush=True)
     assert e[0] <= 1e-3 and e[1] <= 1e-3
