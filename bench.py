@@ -367,6 +367,8 @@ def parse():
                          "recompute); 0: checkpoints and recompute; -1: full history when the "
                          "plan is one group that fits the budget with it; default: as the "
                          "workload's configuration states")
+    ap.add_argument("--fwd-overlap", type=int, default=-1,
+                    help="tune fwd_tile_overlap (-1: as tuned)")
     ap.add_argument("--rec-overlap", type=int, default=-1,
                     help="1: recompute segment j-1 on a second stream during the adjoint of "
                          "segment j (default: the tune's)")
@@ -528,6 +530,9 @@ def main():
     if args.rec_overlap >= 0:
         for sv in surveys:
             sv.set_tune(rec_overlap=args.rec_overlap)
+    if args.fwd_overlap >= 0:
+        for sv in surveys:
+            sv.set_tune(fwd_tile_overlap=args.fwd_overlap)
     fh = args.full_history
     if fh is None:
         fh = 1 if args.workload in FULL_HISTORY_WORKLOADS else 0

@@ -148,6 +148,18 @@ typedef struct {
                                  in HBM; rec_overlap then has nothing to do.
                                  Gradients equal the checkpointed ones to FP32
                                  regrouping of the correlation sums. */
+    int32_t fwd_tile_overlap; /* 1: the forward's temporally blocked launches add,
+                                 in every column clear of the axial PML, one
+                                 interior tile that ends where the radial PML
+                                 layer's halo begins and overlaps the interior
+                                 tile below it (cells two tiles own get the same
+                                 value from both), so that the PML tiles cover
+                                 fewer rows; pays on launches of many rounds of
+                                 workgroups.  0 (default): interior tiles stop
+                                 at the first one whose halo reaches the layer.
+                                 Traces and gradients differ from 0 only by FP32
+                                 rounding (rows move between the interior and
+                                 the PML kernel). */
 } bhfwi_tune;
 
 /* Memory of one group of shots evaluated together (bhfwi_plan_bytes). */

@@ -50,7 +50,7 @@ class Tune(C.Structure):
                 ("tile_map", C.c_int32), ("adj_tb_steps", C.c_int32),
                 ("adj_tb_rows", C.c_int32), ("adj_tb_waves", C.c_int32),
                 ("pml_overlap", C.c_int32), ("rec_overlap", C.c_int32),
-                ("full_history", C.c_int32)]
+                ("full_history", C.c_int32), ("fwd_tile_overlap", C.c_int32)]
 
 
 class PlanBytes(C.Structure):

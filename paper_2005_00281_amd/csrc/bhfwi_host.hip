@@ -283,7 +283,7 @@ bool touches_pml(const ShotDev& S, Shape sh, int i0, int k0)
 }
 
 void build_tiles(const bhfwi_ctx* c, const std::vector<int>& order, Shape sh, Shape pml,
-                 TileSet* ts)
+                 TileSet* ts, bool overlap = false)
 {
     for (int q = 0; q < 2; ++q) {
         ts->t[q].clear();
@@ -295,7 +295,12 @@ void build_tiles(const bhfwi_ctx* c, const std::vector<int>& order, Shape sh, Sh
     // column clear of the axial PML, interior tiles of TR rows cover the rows
     // whose haloed window stays below the radial PML; the rest of the
     // column, and every column that reaches the axial PML, is covered by PML
-    // tiles of TRp rows.
+    // tiles of TRp rows.  With overlap (tune fwd_tile_overlap; the forward
+    // only: it accumulates nothing, and a cell that two tiles own gets the
+    // same bits from both, as its value depends only on the block's input
+    // state and both run the PML-free kernel) one more interior tile ends
+    // where the radial layer's halo begins, overlapping the one below it, so
+    // that the PML tiles cover only the rows that need them.
     const int TR = sh.TRE - 2 * sh.T, TZ = 64 - 2 * sh.T, TRp = pml.TRE - 2 * pml.T;
     std::vector<int2> tl[2];  // (k0, i0) of one shot's tiles
     for (int s : order) {
@@ -304,9 +309,16 @@ void build_tiles(const bhfwi_ctx* c, const std::vector<int>& order, Shape sh, Sh
         tl[1].clear();
         for (int k0 = 0; k0 < S.NZ; k0 += TZ) {
             int i0 = 0;
-            if (!touches_pml(S, sh, 0, k0))
+            if (!touches_pml(S, sh, 0, k0)) {
                 for (; i0 < S.NR && !touches_pml(S, sh, i0, k0); i0 += TR)
                     tl[0].push_back(make_int2(k0, i0));
+                const int last = S.nr - (sh.TRE - sh.T);  // highest start clear of the layer
+                if (overlap && i0 < S.NR && last > i0 - TR && last < i0 &&
+                    !touches_pml(S, sh, last, k0)) {
+                    tl[0].push_back(make_int2(k0, last));
+                    i0 = last + TR;
+                }
+            }
             for (; i0 < S.NR; i0 += TRp) tl[1].push_back(make_int2(k0, i0));
         }
         for (int q = 0; q < 2; ++q) {
@@ -358,7 +370,7 @@ void rebuild_work(bhfwi_ctx* c)
             }
     }
     const Shape fs = fwd_shape(c), as = adj_shape(c), xs = adj_x_shape(c);
-    build_tiles(c, order, fs, pml_shape(fs, false), &c->ftiles);
+    build_tiles(c, order, fs, pml_shape(fs, false), &c->ftiles, c->tune.fwd_tile_overlap != 0);
     build_tiles(c, order, as, pml_shape(as, true), &c->atiles);
     build_tiles(c, order, xs, pml_shape(xs, true), &c->xtiles);
     // fourth-order forward blocks: a three-cell halo per step, one shape for
@@ -900,6 +912,7 @@ int run_sequence(bhfwi_ctx* c, hipStream_t st, std::vector<uintptr_t> key, F&& r
     key.push_back((uintptr_t)c->tune.pml_overlap);
     key.push_back((uintptr_t)c->tune.rec_overlap);
     key.push_back((uintptr_t)c->tune.full_history);
+    key.push_back((uintptr_t)c->tune.fwd_tile_overlap);
     key.push_back((uintptr_t)c->order);
     key.push_back((uintptr_t)c->f4.T);
     key.push_back((uintptr_t)c->f4.TRE);
@@ -1079,6 +1092,7 @@ int bhfwi_create(bhfwi_ctx** out, int32_t hip_device, const bhfwi_shot* shots, i
     c->tune.tb_waves = 16;
     c->tune.tile_map = 1;
     c->tune.pml_overlap = 0;  // measured: concurrent PML tiles crowd out interior ones
+    c->tune.fwd_tile_overlap = 0;
     rebuild_work(c);
 
     hipError_t e = hipSetDevice(hip_device);
@@ -1256,8 +1270,8 @@ int bhfwi_set_tune(bhfwi_ctx* c, const bhfwi_tune* t)
     if (t->rows_per_wave < 1 || t->use_graph < 0 || t->use_graph > 1 || t->time_kernels < 0 ||
         t->time_kernels > 1 || t->tb_steps < 0 || t->tile_map < 0 || t->tile_map > 1 ||
         t->pml_overlap < 0 || t->pml_overlap > 1 || t->rec_overlap < 0 || t->rec_overlap > 1 ||
-        t->full_history < 0 || t->full_history > 1 ||
-        (t->rec_overlap && t->pml_overlap) ||
+        t->full_history < 0 || t->full_history > 1 || t->fwd_tile_overlap < 0 ||
+        t->fwd_tile_overlap > 1 || (t->rec_overlap && t->pml_overlap) ||
         (t->tb_steps >= 2 && !fwd_supported(t->tb_steps, t->tb_rows, t->tb_waves)) ||
         t->adj_tb_steps < 0 ||
         (t->adj_tb_steps >= 2 && !adj_supported(t->adj_tb_steps, t->adj_tb_rows, t->adj_tb_waves)) ||

@@ -33,7 +33,7 @@ torch = pytest.importorskip("torch")
 # the launch shapes of the 64-shot benchmark workload (its tune-cache entry)
 BENCH_C3 = dict(rows_per_wave=64, waves_per_block=4, use_graph=1, tb_steps=8, tb_rows=48,
                 tb_waves=16, tile_map=1, adj_tb_steps=6, adj_tb_rows=32, adj_tb_waves=16,
-                pml_overlap=0, rec_overlap=0, full_history=0)
+                pml_overlap=0, rec_overlap=0, full_history=0, fwd_tile_overlap=1)
 
 
 def _dev():

@@ -49,11 +49,11 @@ def survey(w, ckpt=250, tune=None):
 
 
 def T(rows=4, wpb=4, graph=1, tb=0, tbr=16, tbw=4, tmap=1, atb=0, atbr=16, atbw=8, ovl=1,
-      rov=0, full=0):
+      rov=0, full=0, fov=0):
     return dict(rows_per_wave=rows, waves_per_block=wpb, use_graph=graph, tb_steps=tb,
                 tb_rows=tbr, tb_waves=tbw, tile_map=tmap, adj_tb_steps=atb, adj_tb_rows=atbr,
                 adj_tb_waves=atbw, pml_overlap=0 if rov else ovl, rec_overlap=rov,
-                full_history=full)
+                full_history=full, fwd_tile_overlap=fov)
 
 
 FWD_TUNES = [T(1, 1, 0), T(2, 4, 1), T(3, 2, 1), T(4, 4, 0), T(16, 4, 1), T(64, 8, 0),
@@ -61,11 +61,14 @@ FWD_TUNES = [T(1, 1, 0), T(2, 4, 1), T(3, 2, 1), T(4, 4, 0), T(16, 4, 1), T(64, 
              T(tb=8, tbr=32, tbw=8), T(tb=3, tbr=24, tbw=8), T(tb=4, tmap=0), T(tb=4, tbw=16),
              T(tb=3, tbw=16, graph=0), T(tb=6, tbr=32, tbw=16), T(tb=6, tbr=48, tbw=16, atb=1),
              T(tb=8, tbr=48, tbw=16, graph=0, atb=1), T(tb=8, tbr=64, tbw=16, atb=1),
-             T(tb=4, tbr=64, tbw=16, atb=1, graph=0), T(tb=8, tbr=64, tbw=16, atb=1, ovl=0)]
+             T(tb=4, tbr=64, tbw=16, atb=1, graph=0), T(tb=8, tbr=64, tbw=16, atb=1, ovl=0),
+             T(tb=4, fov=1), T(tb=8, tbr=48, tbw=16, atb=1, fov=1), T(tb=8, tbr=64, tbw=16, atb=1,
+                                                                      fov=1, graph=0)]
 GRAD_TUNES = [T(1, 1, 1), T(2, 4, 0), T(4, 4, 1), T(5, 4, 1), T(64, 8, 0), T(tb=4),
               T(tb=3, graph=0), T(tb=4, tbw=8), T(tb=6, tbr=24, tbw=8), T(tb=8, tbr=32, tbw=8),
               T(tb=4, tbw=8, tmap=0), T(tb=4, tbw=16), T(tb=2, tbw=16, graph=0),
               T(tb=8, tbr=32, tbw=16), T(tb=6, tbr=48, tbw=16, atb=6, atbr=32, atbw=16),
+              T(tb=8, tbr=48, tbw=16, atb=6, atbr=32, atbw=16, fov=1),
               T(tb=4, tbr=48, tbw=16, atb=3, atbr=16, atbw=8, graph=0),
               T(tb=6, tbr=32, tbw=16, atb=1, rows=2), T(tb=0, rows=2, atb=4, atbr=16, atbw=16),
               T(tb=8, tbr=64, tbw=16, atb=6, atbr=48, atbw=16),
@@ -314,7 +317,8 @@ def _multi_shot_workload():
     return base
 
 
-@pytest.mark.parametrize("tune", [T(4, 4, 1), T(tb=3), T(tb=4, tbr=32, tbw=8, graph=0)])
+@pytest.mark.parametrize("tune", [T(4, 4, 1), T(tb=3), T(tb=4, tbr=32, tbw=8, graph=0),
+                                  T(tb=4, fov=1)])
 def test_batched_equals_single_and_oracle(tune):
     w = _multi_shot_workload()
     _say("batched 3 shots", [(s.NR, s.NZ, s.nt) for s in w.shots], tune)
