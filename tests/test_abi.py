@@ -81,3 +81,35 @@ def test_library_build_id_matches_the_sources(monkeypatch):
             _lib.load()
     finally:
         _lib._lib = saved
+
+
+def _header_struct_fields(name):
+    """Field names and C types of `typedef struct { ... } name;` in the header,
+    in order (comments dropped; `int32_t a, b;` gives both names)."""
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^{}]*)\}\s*%s;" % name, txt).group(1)
+    out = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        ctype, names = decl.split(None, 1)
+        out += [(n.strip(), ctype) for n in names.split(",")]
+    return out
+
+
+@pytest.mark.parametrize("struct,cls", [("bhfwi_shot", "Shot"), ("bhfwi_sizes_t", "Sizes"),
+                                        ("bhfwi_tune", "Tune"),
+                                        ("bhfwi_plan_bytes_t", "PlanBytes"),
+                                        ("bhfwi_plan_info", "PlanInfo"),
+                                        ("bhfwi_kernel_times_t", "KernelTimes"),
+                                        ("bhfwi_bounds", "Bounds")])
+def test_binding_structs_match_the_header(struct, cls):
+    # the ctypes mirrors of the ABI structs: same fields, order and widths
+    from paper_2005_00281_amd import _lib
+    width = {"int32_t": 4, "int64_t": 8, "float": 4, "double": 8}
+    hdr = _header_struct_fields(struct)
+    py = getattr(_lib, cls)._fields_
+    assert [n for n, _ in hdr] == [n for n, _ in py]
+    for (n, ctype), (_, pytype) in zip(hdr, py):
+        assert width[ctype] == ctypes.sizeof(pytype), (struct, n)
