@@ -8,10 +8,6 @@ namespace bhfwi {
 
 constexpr int kOwn = 62;  // axial rows owned by one wave64 (lanes 1..62)
 
-// Workgroup b of a launch is dispatched to XCD b % 8.  With map == 1 the n
-// workgroups are renumbered so that XCD x walks one contiguous chunk of the
-// work table, [x*(n/8) + min(x, n%8), ...), in table order: tiles that are
-// neighbours in the table (and share halo rows) then meet in the same L2.
 // Neighbour exchange along the axial direction inside one wave64 (lane =
 // axial row): DPP wavefront shifts, no LDS.  Lanes without a source read 0.
 __device__ inline float from_lane_below(float v)  // lane l <- lane l - 1
@@ -36,6 +32,10 @@ __device__ inline float wave_uniform(float v)
     return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
 }
 
+// Workgroup b of a launch is dispatched to XCD b % 8.  With map == 1 the n
+// workgroups are renumbered so that XCD x walks one contiguous chunk of the
+// work table, [x*(n/8) + min(x, n%8), ...), in table order: tiles that are
+// neighbours in the table (and share halo rows) then meet in the same L2.
 __device__ inline int xcd_chunk(int b, int n, int map)
 {
     if (map != 1) return b;

@@ -19,10 +19,11 @@
 // The gradient and illumination sums stay in registers for the T steps and
 // are added to the accumulators once per launch (owned cells only).  As in
 // the forward kernel the step loop has no per-cell branches: zero
-// coefficients keep cells outside the grid and the axis nodes inert.  (Unlike
-// the forward kernel it does not skip the rows that have fallen out of the
-// correct region: the branches cost more registers than the adjoint's 64
-// have to spare, and the spills cost more than the skipped rows.)
+// coefficients keep cells outside the grid and the axis nodes inert, and rows
+// that have fallen out of the correct region are skipped (whole-wave
+// branches).  From two rows per thread the values a lane wrote to LDS are
+// read back from there instead of being held across the barriers, which
+// keeps the PML-free kernel within 64 registers without spills.
 //
 // Optional outputs, selected by the bits of X (extensions of the paper, which
 // holds the density fixed and gives the preconditioner only as diagonal):
@@ -241,14 +242,15 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
     fetch_hist(t0);
     __syncthreads();
 
+    // Rows that have left the correct region (the halo shrinks one row per
+    // step) are skipped; what they last left in LDS is read only by rows that
+    // are themselves outside the correct region after this step.
+    auto live = [&](int e, int t) { return e >= t && e < TRE - t; };
+
     // The step loop in three PML forms besides the plain one: radial and
     // axial memories, radial only, axial only.  A tile that does not reach a
     // layer has zero coefficients for it everywhere, so leaving that layer's
     // terms out changes nothing; most PML tiles reach the radial layer only.
-    // rows that have left the correct region (the halo shrinks one row per
-    // step) are skipped; what they last left in LDS is read only by rows that
-    // are themselves outside the correct region after this step
-    auto live = [&](int e, int t) { return e >= t && e < TRE - t; };
     auto steps = [&](auto PRC, auto PZC) {
         constexpr bool PR = decltype(PRC)::value != 0, PZ = decltype(PZC)::value != 0;
         for (int t = t0; t < nsteps; ++t) {
@@ -357,7 +359,7 @@ k_adj_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
                 const float ur = vr0 + vr1, uz = vz_km + vz0;  // twice the C-node means
                 ge[j] = fmaf(ur, ur, fmaf(uz, uz, ge[j]));
                 // transposed stress update into a_v, then the transposed velocity update
-                // with four or more rows per thread the drivers this lane
+                // with two or more rows per thread the drivers this lane
                 // wrote to LDS are read back instead of being held in registers
                 const float Err0 = LDSE ? L[ERR][x] : Err_[j];
                 const float Ett0 = LDSE ? L[ETT][x] : Ett_[j];
