@@ -54,3 +54,27 @@ def test_committed_tune_cache_holds_kernel_choices_only():
     assert table
     for key, entry in table.items():
         assert not set(NOT_CACHED) & set(entry["tune"]), key
+
+
+def test_committed_tune_cache_names_known_fields_with_valid_values():
+    # every cached field is a bhfwi_tune field the binding knows, switches are
+    # 0 or 1, and the shapes are ones the library compiles (by the header's list)
+    from paper_2005_00281_amd._lib import Tune
+    names = {n for n, _ in Tune._fields_}
+    compiled = {(2, 16, 4), (3, 16, 4), (4, 16, 4), (2, 16, 8), (3, 16, 8), (4, 16, 8),
+                (2, 24, 8), (3, 24, 8), (4, 24, 8), (6, 24, 8), (4, 32, 8), (6, 32, 8),
+                (8, 32, 8), (2, 16, 16), (3, 16, 16), (4, 16, 16), (4, 32, 16), (6, 32, 16),
+                (8, 32, 16), (4, 48, 16), (6, 48, 16), (8, 48, 16), (4, 64, 16), (8, 64, 16)}
+    with open(os.path.join(ROOT, "paper_2005_00281_amd", "tune_cache.json")) as f:
+        table = json.load(f)
+    for key, entry in table.items():
+        t = entry["tune"]
+        assert set(t) <= names, (key, set(t) - names)
+        for flag in ("use_graph", "tile_map", "pml_overlap", "rec_overlap", "fwd_tile_overlap"):
+            assert t.get(flag, 0) in (0, 1), (key, flag)
+        assert not (t.get("pml_overlap") and t.get("rec_overlap")), key
+        if t.get("tb_steps", 0) >= 2:
+            assert (t["tb_steps"], t["tb_rows"], t["tb_waves"]) in compiled, key
+        if t.get("adj_tb_steps", 0) >= 2:
+            shape = (t["adj_tb_steps"], t["adj_tb_rows"], t["adj_tb_waves"])
+            assert shape in compiled and shape != (4, 64, 16), key
