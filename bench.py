@@ -68,15 +68,15 @@ PMC_SOURCES = ("paper_2005_00281_amd/csrc/bhfwi_tb_adj.hip",
                "paper_2005_00281_amd/csrc/bhfwi_internal.h")
 PMC_TRAFFIC = {
     # (kernel, tile_map, workload, sources sha256[:16]): (read bytes, write bytes)
-    ("k_adj_tb<6, 32, 16, 0, 0> + k_adj_tb<6, 32, 16, 1, 0>", 1, "c3", "9083023da8c596a7"):
-        (8125567127, 3471202322),
+    ("k_adj_tb<6, 32, 16, 0, 0> + k_adj_tb<6, 32, 16, 1, 0>", 1, "c3", "f361bc00e3e764f0"):
+        (8127040826, 3470398762),
 }
 
 # Vector instructions of the same adjoint block, from a rocprofv3 --pmc run
 # of the same command with SQ_INSTS_VALU (wave64 instructions, summed over the
 # interior and PML kernels of one block, mean per dispatch); the same keys.
 PMC_VALU = {
-    ("k_adj_tb<6, 32, 16, 0, 0> + k_adj_tb<6, 32, 16, 1, 0>", 1, "c3", "9083023da8c596a7"):
+    ("k_adj_tb<6, 32, 16, 0, 0> + k_adj_tb<6, 32, 16, 1, 0>", 1, "c3", "f361bc00e3e764f0"):
         1202725870,
 }
 

@@ -151,10 +151,10 @@ typedef struct {
     int32_t fwd_tile_overlap; /* 1: the forward's temporally blocked launches add,
                                  in every column clear of the axial PML, one
                                  interior tile that ends where the radial PML
-                                 layer's halo begins and overlaps the interior
-                                 tile below it (cells two tiles own get the same
-                                 value from both), so that the PML tiles cover
-                                 fewer rows; pays on launches of many rounds of
+                                 layer's halo begins; its window overlaps the
+                                 interior tile below it and it writes back only
+                                 the rows above that tile, so that the PML tiles
+                                 cover fewer rows; pays on launches of many rounds of
                                  workgroups.  0 (default): interior tiles stop
                                  at the first one whose halo reaches the layer.
                                  Traces and gradients differ from 0 only by FP32

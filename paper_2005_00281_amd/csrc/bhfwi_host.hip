@@ -137,7 +137,8 @@ struct Shape {
     int T, TRE, W;
 };
 
-// Tiles (shot, k0, i0, i1) of one temporally blocked shape in two lists:
+// Tiles (shot, k0, i0, first radial row written back) of one temporally
+// blocked shape in two lists:
 // [0] tiles clear of every PML layer, run by the PML-free kernel of the shape;
 // [1] the tiles that touch a PML layer, cut into sub-tiles of shape `pml`
 // (same T, fewer rows) and run by the kernel that carries the PML memories.
@@ -295,14 +296,14 @@ void build_tiles(const bhfwi_ctx* c, const std::vector<int>& order, Shape sh, Sh
     // column clear of the axial PML, interior tiles of TR rows cover the rows
     // whose haloed window stays below the radial PML; the rest of the
     // column, and every column that reaches the axial PML, is covered by PML
-    // tiles of TRp rows.  With overlap (tune fwd_tile_overlap; the forward
-    // only: it accumulates nothing, and a cell that two tiles own gets the
-    // same bits from both, as its value depends only on the block's input
-    // state and both run the PML-free kernel) one more interior tile ends
-    // where the radial layer's halo begins, overlapping the one below it, so
-    // that the PML tiles cover only the rows that need them.
+    // tiles of TRp rows.  With overlap (tune fwd_tile_overlap, the forward
+    // only) one more interior tile ends where the radial layer's halo begins;
+    // its window overlaps the interior tile below it, but it writes back only
+    // the rows above that tile, so every cell keeps one writer, and the PML
+    // tiles then cover only the rows that need them.  A tile is (shot, first
+    // axial row, first owned radial row, first radial row it writes).
     const int TR = sh.TRE - 2 * sh.T, TZ = 64 - 2 * sh.T, TRp = pml.TRE - 2 * pml.T;
-    std::vector<int2> tl[2];  // (k0, i0) of one shot's tiles
+    std::vector<int4> tl[2];  // (k0, i0, first written row, 0) of one shot's tiles
     for (int s : order) {
         const ShotDev& S = c->sd[s];
         tl[0].clear();
@@ -311,24 +312,23 @@ void build_tiles(const bhfwi_ctx* c, const std::vector<int>& order, Shape sh, Sh
             int i0 = 0;
             if (!touches_pml(S, sh, 0, k0)) {
                 for (; i0 < S.NR && !touches_pml(S, sh, i0, k0); i0 += TR)
-                    tl[0].push_back(make_int2(k0, i0));
+                    tl[0].push_back(make_int4(k0, i0, i0, 0));
                 const int last = S.nr - (sh.TRE - sh.T);  // highest start clear of the layer
                 if (overlap && i0 < S.NR && last > i0 - TR && last < i0 &&
                     !touches_pml(S, sh, last, k0)) {
-                    tl[0].push_back(make_int2(k0, last));
+                    tl[0].push_back(make_int4(k0, last, i0, 0));
                     i0 = last + TR;
                 }
             }
-            for (; i0 < S.NR; i0 += TRp) tl[1].push_back(make_int2(k0, i0));
+            for (; i0 < S.NR; i0 += TRp) tl[1].push_back(make_int4(k0, i0, i0, 0));
         }
         for (int q = 0; q < 2; ++q) {
             if (c->tune.tile_map == 0)  // axial tile fastest
-                std::stable_sort(tl[q].begin(), tl[q].end(), [](int2 a, int2 b) {
+                std::stable_sort(tl[q].begin(), tl[q].end(), [](int4 a, int4 b) {
                     return a.y != b.y ? a.y < b.y : a.x < b.x;
                 });
-            const int rows = q ? TRp : TR;
-            for (const int2 kt : tl[q]) {
-                ts->t[q].push_back(make_int4(s, kt.x, kt.y, std::min(kt.y + rows, S.NR)));
+            for (const int4 kt : tl[q]) {
+                ts->t[q].push_back(make_int4(s, kt.x, kt.y, kt.z));
                 ts->nt[q].push_back(S.nt);
             }
         }

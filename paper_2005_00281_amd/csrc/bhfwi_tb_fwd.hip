@@ -1,7 +1,9 @@
 // bhfwi_tb_fwd.hip -- temporally blocked forward step (Method section, Eq. 2).
 //
 // One workgroup of W wave64 owns a tile of TR = TRE - 2T radial
-// rows by TZ = 64 - 2T axial rows and advances it T time steps per launch.
+// rows by TZ = 64 - 2T axial rows and advances it T time steps per launch
+// (of those rows it writes back the ones from the tile table's fourth entry
+// up: a tile whose window overlaps the one below it leaves their rows to it).
 // It loads the tile plus a T-cell halo on every side (TRE rows x 64 columns,
 // lane = column), keeps each cell's six fields, its precomputed medium
 // coefficients and its PML memories in registers (thread (wave w, lane l)
@@ -270,7 +272,7 @@ k_fwd_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
                 L[TTT][x] = ttt[j];
                 L[TRZ][x] = trz[j];
                 const int i = wk.z - T + e;
-                const bool own = kin && lown && e >= T && e < TRE - T && i < NR;
+                const bool own = kin && lown && e >= T && e < TRE - T && i >= wk.w && i < NR;
                 if (hist && own) {
                     // streamed out, read back segments later: not kept in L2
                     __builtin_nontemporal_store(vr[j], reinterpret_cast<float*>(hvr_t + hoff[j]));
@@ -298,7 +300,7 @@ k_fwd_tb(const ShotDev* __restrict__ shots, const int4* __restrict__ work, int n
         const int e = wave + W * j;
         const int i = wk.z - T + e;
         const bool in = kin && i >= 0 && i < NR;
-        if (!(in && lown && e >= T && e < TRE - T)) continue;
+        if (!(in && lown && e >= T && e < TRE - T && i >= wk.w)) continue;
         const long long c = (long long)i * NZ + k;
         if (i >= 1) {
             Fo[c] = vr[j];
